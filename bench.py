@@ -1,0 +1,273 @@
+#!/usr/bin/env python3
+"""Throughput of the fused DWT pan-sharpening kernels on one MI355X.
+
+Primary line: Daubechies-4, PAN 8192x8192, 3 MS bands (synthetic, seeded),
+inputs resident in HBM; one step = one fused forward launch over all bands.
+Prints exactly one JSON line on stdout; progress goes to stderr.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+    python bench.py --mode copy      # plain copy kernel (counter calibration)
+    python bench.py --mode primary   # primary workload only (for profiling)
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fuse_d4_8192x8192_b3.json")
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def algo_bytes(H, W, B):
+    """PAN read once, MS read once, every output band written once."""
+    return H * W * 4 + B * (H // 2) * (W // 2) * 4 + B * H * W * 4
+
+
+class Prepared:
+    """Pre-marshalled dwt_fuse_run call (keeps Python overhead out of the loop)."""
+
+    def __init__(self, api, pan, ms, wavelet, out, gain=None):
+        from paper_1803_00737_amd._lib import wavelet_id
+
+        self.ctx = api.context(pan.device)
+        self.ctx.bind_stream()
+        H, W = pan.shape
+        B = ms.shape[0]
+        self.args = (self.ctx.handle, wavelet_id(wavelet), H, W, B,
+                     ctypes.c_void_p(pan.data_ptr()), pan.stride(0),
+                     ctypes.c_void_p(ms.data_ptr()), ms.stride(1), ms.stride(0),
+                     ctypes.c_void_p(gain.data_ptr()) if gain is not None else None,
+                     ctypes.c_void_p(out.data_ptr()), out.stride(1), out.stride(0))
+        self.fn = self.ctx.lib.dwt_fuse_run
+        self.keep = (pan, ms, out, gain)
+
+    def __call__(self):
+        st = self.fn(*self.args)
+        if st != 0:
+            self.ctx.check(st, "dwt_fuse_run")
+
+
+def time_loop(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(steps):
+        fn()
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps  # ms per step
+
+
+def read_traffic(bytes_per_launch):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel build."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+        from paper_1803_00737_amd.build import build_id
+
+        if t.get("build_id") != build_id():
+            return None
+        return float(t["traffic_bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def run_copy(torch, steps):
+    n = 1 << 28  # 1 GiB of float32
+    a = torch.ones(n, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    ms = time_loop(torch, lambda: b.copy_(a), steps, 2)
+    gbs = 2 * 4 * n / (ms * 1e-3) / 1e9
+    print(json.dumps({"mode": "copy", "bytes_read": 4 * n, "bytes_written": 4 * n, "ms": ms, "GB/s": gbs}))
+
+
+def cpu_baseline(pan_d, ms_d, wavelet):
+    import oracle
+    import numpy as np
+
+    pan = pan_d.cpu().numpy().astype(np.float64)
+    ms = ms_d.cpu().numpy().astype(np.float64)
+    t0 = time.perf_counter()
+    oracle.fuse(wavelet, pan, ms)
+    dt = time.perf_counter() - t0
+    px = ms.shape[0] * pan.shape[0] * pan.shape[1]
+    return {"value": px / dt / 1e6, "unit": "Mpix/s", "cores": 1, "kind": "oracle",
+            "sample": "the whole workload (same inputs), one pass of the FP64 oracle, 1 thread, %.1f s" % dt}
+
+
+def extras(torch, api, synth, steps, warmup):
+    out = {}
+    dev = torch.device("cuda:0")
+    # Haar 512x512, 1 band: launch-latency bound (fits in cache); Mpix/s only.
+    wl = synth.haar_512()
+    pan, ms = wl.make(device=dev)
+    o = torch.empty((wl.B, wl.H, wl.W), device=dev)
+    ms_t = time_loop(torch, Prepared(api, pan, ms, wl.wavelet, o), steps, warmup)
+    out[wl.name] = {"Mpix/s": wl.B * wl.H * wl.W / ms_t / 1e3, "ms": ms_t}
+    log(wl.name, out[wl.name])
+    # Landsat-shaped scene, both wavelets (PAN detail computed once for 6 bands).
+    for w in ("haar", "d4"):
+        wl = synth.landsat(w)
+        pan, ms = wl.make(device=dev)
+        o = torch.empty((wl.B, wl.H, wl.W), device=dev)
+        ms_t = time_loop(torch, Prepared(api, pan, ms, w, o), max(5, steps // 2), warmup)
+        gbs = algo_bytes(wl.H, wl.W, wl.B) / (ms_t * 1e-3) / 1e9
+        out[wl.name] = {"Mpix/s": wl.B * wl.H * wl.W / ms_t / 1e3, "ms": ms_t, "GB/s": gbs,
+                        "frac": gbs / HBM_PEAK_GBS}
+        log(wl.name, out[wl.name])
+        del pan, ms, o
+        torch.cuda.empty_cache()
+    # Batched: 96 uneven scenes, mixed wavelets, one persistent launch vs 96 launches.
+    layout = synth.uneven_batch()
+    scenes, preps = [], []
+    px = 0
+    nbytes = 0
+    for sc in layout:
+        pan, ms = synth.make_scene(sc.H, sc.W, sc.B, sc.seed, device=dev)
+        o = torch.empty((sc.B, sc.H, sc.W), device=dev)
+        scenes.append(dict(pan=pan, ms=ms, wavelet=sc.wavelet, out=o))
+        preps.append(Prepared(api, pan, ms, sc.wavelet, o))
+        px += sc.B * sc.H * sc.W
+        nbytes += algo_bytes(sc.H, sc.W, sc.B)
+    arr, _, keep = api.make_items(scenes)
+    ctx = api.context(dev)
+    ctx.bind_stream()
+    lib = ctx.lib
+
+    def per_image():
+        for p in preps:
+            p()
+
+    def batched(flags):
+        def f():
+            st = lib.dwt_fuse_run_batched(ctx.handle, arr, len(scenes), flags)
+            if st != 0:
+                ctx.check(st, "dwt_fuse_run_batched")
+        return f
+
+    bsteps = max(5, steps // 2)
+    t_per = time_loop(torch, per_image, bsteps, warmup)
+    t_bat = time_loop(torch, batched(0), bsteps, warmup)
+    t_gra = time_loop(torch, batched(1), bsteps, warmup)
+    out["uneven_96_batched"] = {
+        "scenes": len(layout), "output_Mpix": px / 1e6,
+        "per_image_ms": t_per, "batched_ms": t_bat, "batched_graph_ms": t_gra,
+        "per_image_Mpix/s": px / t_per / 1e3, "batched_graph_Mpix/s": px / t_gra / 1e3,
+        "batched_graph_GB/s": nbytes / (t_gra * 1e-3) / 1e9,
+        "speedup_graph_vs_per_image": t_per / t_gra,
+    }
+    log("uneven_96", out["uneven_96_batched"])
+    del scenes, preps, arr, keep
+    torch.cuda.empty_cache()
+    # Differentiation: 16 x 2048^2, 4 bands, D4: fused forward + adjoint.
+    pans, mss, gys = [], [], []
+    for s in range(16):
+        pan, ms = synth.make_scene(2048, 2048, 4, synth.seed_for(4, s), device=dev)
+        pans.append(pan)
+        mss.append(ms)
+        gys.append(torch.randn((4, 2048, 2048), device=dev) * 1e-3)
+    gain = torch.ones(4, device=dev)
+
+    def fwd_bwd():
+        for pan, ms, gy in zip(pans, mss, gys):
+            api.fuse(pan, ms, "d4", gain)
+            api.fuse_backward(pan, gy, "d4", gain)
+
+    t = time_loop(torch, fwd_bwd, max(3, steps // 5), 1)
+    fb_bytes = 16 * (algo_bytes(2048, 2048, 4) + 2048 * 2048 * (8 + 5 * 4))
+    out["differentiation_16x2048_b4"] = {"fwd_bwd_ms": t, "scenes/s": 16 / (t * 1e-3),
+                                         "GB/s": fb_bytes / (t * 1e-3) / 1e9}
+    log("differentiation", out["differentiation_16x2048_b4"])
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--mode", choices=["full", "primary", "copy"], default="full")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="use the default tile instead of the autotuner")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(requested --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    if args.mode == "copy":
+        run_copy(torch, args.steps)
+        return
+
+    from paper_1803_00737_amd import api, synth
+
+    dev = torch.device("cuda:0")
+    wl = synth.d4_8192()
+    log("generating", wl.name)
+    pan, ms = wl.make(device=dev)
+    out = torch.empty((wl.B, wl.H, wl.W), device=dev)
+    ctx = api.context(dev)
+    if not args.no_tune:
+        ctx.set_tuning(True)
+    torch.cuda.synchronize()
+    call = Prepared(api, pan, ms, wl.wavelet, out)
+    call()  # first call tunes the tile shape for this size class
+    torch.cuda.synchronize()
+    ms_step = time_loop(torch, call, args.steps, args.warmup)
+    nbytes = algo_bytes(wl.H, wl.W, wl.B)
+    achieved = nbytes / (ms_step * 1e-3) / 1e9
+    value = wl.B * wl.H * wl.W / ms_step / 1e3
+    log("primary %.4f ms/step  %.0f Mpix/s  %.0f GB/s" % (ms_step, value, achieved))
+    result = {
+        "metric": "fused output Mpix/s (all bands) + % HBM peak, batched vs per-image, 1 GPU",
+        "value": value,
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded blob/rectangle/noise scenes, uint8-valued float32)",
+        "config": {"workload": wl.name, "wavelet": "d4", "H": wl.H, "W": wl.W, "bands": wl.B,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": read_traffic(nbytes),
+                     "algorithmic_bytes_per_launch": nbytes},
+    }
+    if args.mode == "full":
+        result["workloads"] = extras(torch, api, synth, args.steps, args.warmup)
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        result["cpu_baseline"] = cpu_baseline(pan, ms, wl.wavelet)
+        log("cpu baseline", result["cpu_baseline"])
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

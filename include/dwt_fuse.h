@@ -1,0 +1,177 @@
+/*
+ * dwt_fuse.h -- C ABI of the MI355X (gfx950) DWT pan-sharpening library.
+ *
+ * The operation (Al-Oraiqat et al., "Fusion of multispectral satellite
+ * imagery using a cluster of graphics processing unit", section 2): for a
+ * panchromatic image PAN of H x W pixels and B multispectral bands of
+ * (H/2) x (W/2) pixels each (the 4:1 pixel ratio of section 2), output band b
+ * is
+ *     inverse2D( forward2D(PAN) with its approximation (LL) quadrant
+ *                replaced by MS band b )
+ * where forward2D is the 1D transform over every row and then every column,
+ * and inverse2D is the 1D inverse over every column and then every row.
+ *   - DWT_FUSE_HAAR: Eq. 1-2 (forward, divided by 2) and Eq. 11-12 (inverse).
+ *   - DWT_FUSE_D4:   Daubechies-4 with periodic wrap, Eq. 3-10 (forward) and
+ *                    Eq. 13-16 (inverse), with the high-pass filter read as
+ *                    g_k = (-1)^k h_{3-k} (Eq. 9-10 are garbled in print).
+ * The MS band is inserted unscaled.  An optional per-band gain multiplies the
+ * three detail quadrants of PAN before the inverse (gain 1 = the method as
+ * printed); it is the "injection gain" that the backward pass differentiates.
+ *
+ * Conventions for every entry point:
+ *   - All image pointers are DEVICE pointers to float32, owned by the caller,
+ *     row-major.  "ld" is the row pitch and "band_stride" the distance between
+ *     consecutive bands, both in elements (not bytes).
+ *   - H and W must be even and >= 2.  Any even size is valid for both
+ *     wavelets (a side of 2 makes D4 reduce to orthonormal Haar along it).
+ *   - Pointers and pitches need no particular alignment; 16-byte aligned
+ *     rows take the 128-bit path, others a narrower one, with identical results.
+ *   - Calls are asynchronous and ordered on the context's HIP stream.  The
+ *     returned status covers argument validation (done on the host before any
+ *     HIP call) and launch errors; a fault inside a kernel is reported as
+ *     DWT_FUSE_E_DEVICE by a later call.
+ *   - No call throws or aborts.  A context is not thread-safe; use one per
+ *     host thread / stream.
+ */
+#ifndef DWT_FUSE_H
+#define DWT_FUSE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { DWT_FUSE_HAAR = 0, DWT_FUSE_D4 = 1 } dwt_fuse_wavelet;
+
+typedef enum {
+    DWT_FUSE_OK = 0,
+    DWT_FUSE_E_NULL = 1,    /* a required pointer is NULL */
+    DWT_FUSE_E_SHAPE = 2,   /* H or W odd or < 2, B < 1, n < 0, or a size overflows */
+    DWT_FUSE_E_WAVELET = 3, /* wavelet not in dwt_fuse_wavelet */
+    DWT_FUSE_E_STRIDE = 4,  /* ld < row width, or band_stride < rows * ld */
+    DWT_FUSE_E_ALIAS = 5,   /* an output's byte range overlaps an input's */
+    DWT_FUSE_E_NOMEM = 6,   /* context workspace could not be allocated */
+    DWT_FUSE_E_DEVICE = 7,  /* HIP error (bad device, launch failure, earlier fault) */
+    DWT_FUSE_E_STATE = 8    /* context unusable (e.g. created for another device) */
+} dwt_fuse_status;
+
+typedef struct dwt_fuse_ctx dwt_fuse_ctx; /* opaque */
+
+/* Create a context bound to HIP device `device` and stream `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  The context owns its
+ * workspace (gradient partial sums, batch descriptor tables, captured
+ * graphs, the tuning table).  On failure *ctx is set to NULL. */
+dwt_fuse_status dwt_fuse_create(dwt_fuse_ctx **ctx, int device, void *hip_stream);
+
+/* Release a context and everything it owns.  NULL is ignored.  The caller
+ * must make sure no work issued through the context is still running. */
+void dwt_fuse_destroy(dwt_fuse_ctx *ctx);
+
+/* Make subsequent calls use `hip_stream` (same device). */
+dwt_fuse_status dwt_fuse_set_stream(dwt_fuse_ctx *ctx, void *hip_stream);
+
+/* Fuse one scene (section 2, method steps 1-3, for every band).
+ *   pan   H x W, pitch pan_ld (>= W).
+ *   ms    B bands of (H/2) x (W/2), pitch ms_ld (>= W/2), band_stride
+ *         ms_band_stride (>= (H/2) * ms_ld when B > 1).
+ *   gain  NULL (all ones) or B floats on the device: detail gain per band.
+ *   out   B bands of H x W, pitch out_ld (>= W), band stride
+ *         out_band_stride (>= H * out_ld when B > 1).  Must not overlap pan,
+ *         ms or gain (DWT_FUSE_E_ALIAS).
+ * The PAN detail part is computed once and reused for all bands.  Haar
+ * results on integer-valued inputs are exact (every intermediate is a
+ * multiple of 1/4); D4 results are float32 evaluations of the same map.
+ * Allocates nothing. */
+dwt_fuse_status dwt_fuse_run(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet,
+                             int64_t H, int64_t W, int64_t B,
+                             const float *pan, int64_t pan_ld,
+                             const float *ms, int64_t ms_ld, int64_t ms_band_stride,
+                             const float *gain,
+                             float *out, int64_t out_ld, int64_t out_band_stride);
+
+/* One independent scene of a batch; fields as in dwt_fuse_run. */
+typedef struct {
+    int32_t wavelet; /* dwt_fuse_wavelet */
+    int32_t B;
+    int64_t H, W;
+    const float *pan, *ms, *gain; /* gain may be NULL */
+    float *out;
+    int64_t pan_ld, ms_ld, ms_band_stride, out_ld, out_band_stride;
+} dwt_fuse_item;
+
+enum { DWT_FUSE_GRAPH = 1 /* capture into / replay from a cached hipGraph */ };
+
+/* Fuse n independent scenes of any sizes, band counts and wavelets in ONE
+ * persistent kernel launch whose workgroups take (scene, tile) work units
+ * from a device queue.  `items` is a HOST array of n descriptors (read
+ * during the call only); the pointers inside are device pointers.  Every
+ * item is validated as in dwt_fuse_run (first failure returned, nothing
+ * launched); outputs must not overlap any item's inputs or each other.
+ * With DWT_FUSE_GRAPH the launch is captured once per batch signature
+ * (sizes, bands, wavelets, pitches) and replayed afterwards; scene pointers
+ * live in a device table refreshed before each replay, so new tensors of
+ * the same signature replay safely.  n == 0 is a no-op.  The context grows
+ * its descriptor tables on first use of a larger batch (DWT_FUSE_E_NOMEM on
+ * failure). */
+dwt_fuse_status dwt_fuse_run_batched(dwt_fuse_ctx *ctx, const dwt_fuse_item *items,
+                                     int64_t n, uint32_t flags);
+
+/* Transpose (adjoint) of dwt_fuse_run with respect to PAN, MS and the
+ * per-band gains, for a given upstream gradient grad_out = dL/d(out).
+ *   pan       H x W, pitch pan_ld (needed for dL/dgain).
+ *   gain      NULL (all ones) or B device floats (the forward's gains).
+ *   grad_out  B x H x W, pitch go_ld, band stride go_band_stride.
+ *   grad_pan  NULL or H x W contiguous:      sum_b gain_b (y_b - P y_b)
+ *   grad_ms   NULL or B x H/2 x W/2 contiguous: LL part of forward2D(y_b)
+ *             (Haar: the 2x2 block sum of y_b, the transpose of Eq. 11-12)
+ *   grad_gain NULL or B floats:              < y_b, PAN - P PAN >
+ * where P is the projection of an image onto its LL part.  grad_gain is
+ * reduced in a fixed order (bitwise reproducible).  Outputs must not overlap
+ * inputs.  Uses context workspace (DWT_FUSE_E_NOMEM if it cannot grow). */
+dwt_fuse_status dwt_fuse_backward(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet,
+                                  int64_t H, int64_t W, int64_t B,
+                                  const float *pan, int64_t pan_ld, const float *gain,
+                                  const float *grad_out, int64_t go_ld, int64_t go_band_stride,
+                                  float *grad_pan, float *grad_ms, float *grad_gain);
+
+/* Argument validation only, exactly as the calls above perform it; no HIP
+ * call is made, so these work without a GPU. */
+dwt_fuse_status dwt_fuse_check_run(dwt_fuse_wavelet wavelet, int64_t H, int64_t W, int64_t B,
+                                   const float *pan, int64_t pan_ld,
+                                   const float *ms, int64_t ms_ld, int64_t ms_band_stride,
+                                   const float *gain,
+                                   const float *out, int64_t out_ld, int64_t out_band_stride);
+dwt_fuse_status dwt_fuse_check_batched(const dwt_fuse_item *items, int64_t n);
+dwt_fuse_status dwt_fuse_check_backward(dwt_fuse_wavelet wavelet, int64_t H, int64_t W, int64_t B,
+                                        const float *pan, int64_t pan_ld, const float *gain,
+                                        const float *grad_out, int64_t go_ld, int64_t go_band_stride,
+                                        const float *grad_pan, const float *grad_ms,
+                                        const float *grad_gain);
+
+/* Static description of a status code. */
+const char *dwt_fuse_status_str(dwt_fuse_status s);
+
+/* Human-readable detail of the last failure on this context ("" if none). */
+const char *dwt_fuse_last_error(const dwt_fuse_ctx *ctx);
+
+/* Tuning.  The tile shape of each launch (rows per work unit, waves per
+ * workgroup, columns per lane) comes from a per-context table keyed by
+ * wavelet, size class and band count.  With tuning enabled, the first call
+ * of each key times the candidate shapes on that call's own buffers (each
+ * candidate writes the same output) and keeps the fastest.  The table can be
+ * saved to / loaded from a small text file; a file whose header does not
+ * match this library build and device is ignored. */
+dwt_fuse_status dwt_fuse_set_tuning(dwt_fuse_ctx *ctx, int enable);
+dwt_fuse_status dwt_fuse_tune_save(const dwt_fuse_ctx *ctx, const char *path);
+dwt_fuse_status dwt_fuse_tune_load(dwt_fuse_ctx *ctx, const char *path);
+
+/* Force a tile shape for all later launches on this context (0 = automatic
+ * for that field): rows of coefficients per work unit, waves per workgroup,
+ * coefficient columns per lane (1 or 2). */
+dwt_fuse_status dwt_fuse_force_tile(dwt_fuse_ctx *ctx, int seg_rows, int waves_per_block, int cols_per_lane);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,252 @@
+"""Python surface over the C ABI: ``fuse``, ``fuse_batched``, ``fuse_backward``
+and ``DwtFuseFn`` (torch.autograd.Function).
+
+Every step of the computation runs in the HIP library; this module only
+checks tensor placement/dtype, allocates outputs with torch and passes
+pointers, pitches and the current HIP stream.  Tensors must be float32 on a
+GPU with unit stride along rows; there is no CPU path.
+"""
+from __future__ import annotations
+
+import ctypes
+import threading
+from typing import List, Optional, Sequence
+
+import torch
+
+from . import _lib
+from ._lib import DwtFuseError, Item, wavelet_id
+
+
+class Context:
+    """One dwt_fuse_ctx (device + stream + workspace + tuning table)."""
+
+    def __init__(self, device: int):
+        self.lib = _lib.load()
+        self.device = int(device)
+        h = ctypes.c_void_p()
+        st = self.lib.dwt_fuse_create(ctypes.byref(h), self.device, None)
+        if st != 0:
+            raise DwtFuseError(st, "dwt_fuse_create")
+        self.handle = h
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None):
+                self.lib.dwt_fuse_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+    def check(self, st: int, where: str):
+        if st != 0:
+            detail = self.lib.dwt_fuse_last_error(self.handle) or b""
+            raise DwtFuseError(st, where, detail.decode(errors="replace"))
+
+    def bind_stream(self, stream: Optional[torch.cuda.Stream] = None):
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.check(self.lib.dwt_fuse_set_stream(self.handle, ctypes.c_void_p(stream.cuda_stream)),
+                   "dwt_fuse_set_stream")
+
+    def set_tuning(self, enable: bool = True):
+        self.check(self.lib.dwt_fuse_set_tuning(self.handle, 1 if enable else 0), "dwt_fuse_set_tuning")
+
+    def force_tile(self, seg_rows: int = 0, waves_per_block: int = 0, cols_per_lane: int = 0):
+        self.check(self.lib.dwt_fuse_force_tile(self.handle, seg_rows, waves_per_block, cols_per_lane),
+                   "dwt_fuse_force_tile")
+
+    def tune_save(self, path: str):
+        self.check(self.lib.dwt_fuse_tune_save(self.handle, path.encode()), "dwt_fuse_tune_save")
+
+    def tune_load(self, path: str):
+        self.check(self.lib.dwt_fuse_tune_load(self.handle, path.encode()), "dwt_fuse_tune_load")
+
+
+_ctx_lock = threading.Lock()
+_contexts = {}
+
+
+def context(device=None) -> Context:
+    """The shared context of a device (created on first use)."""
+    if device is None:
+        device = torch.cuda.current_device()
+    if isinstance(device, torch.device):
+        device = device.index if device.index is not None else torch.cuda.current_device()
+    with _ctx_lock:
+        c = _contexts.get(device)
+        if c is None:
+            c = _contexts[device] = Context(device)
+        return c
+
+
+def _require(t: torch.Tensor, name: str, ndim: int):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch.Tensor" % name)
+    if not t.is_cuda:
+        raise ValueError("%s must be on a GPU (there is no CPU path)" % name)
+    if t.dtype != torch.float32:
+        raise TypeError("%s must be float32, got %s" % (name, t.dtype))
+    if t.dim() != ndim:
+        raise ValueError("%s must have %d dimensions, got shape %s" % (name, ndim, tuple(t.shape)))
+
+
+def _rows_unit(t: torch.Tensor) -> torch.Tensor:
+    """Tensor with unit stride along its last dimension (pitches may be anything)."""
+    if t.stride(-1) != 1 or any(s < 0 for s in t.stride()):
+        t = t.contiguous()
+    return t
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _pitch(t: torch.Tensor, dim: int) -> int:
+    # A size-1 dimension may report any stride; use the dense value then.
+    if t.shape[dim] == 1:
+        n = 1
+        for s in t.shape[dim + 1:]:
+            n *= s
+        return max(n, t.stride(dim))
+    return t.stride(dim)
+
+
+def _prep_scene(pan, ms, gain, out):
+    _require(pan, "pan", 2)
+    if ms.dim() == 2:
+        ms = ms.unsqueeze(0)
+    _require(ms, "ms", 3)
+    pan = _rows_unit(pan)
+    ms = _rows_unit(ms)
+    H, W = pan.shape
+    B = ms.shape[0]
+    if tuple(ms.shape[1:]) != (H // 2, W // 2):
+        raise ValueError("ms must be (B, H/2, W/2) = (B, %d, %d), got %s" % (H // 2, W // 2, tuple(ms.shape)))
+    if ms.device != pan.device:
+        raise ValueError("pan and ms must be on the same device")
+    if gain is not None:
+        _require(gain, "gain", 1)
+        gain = gain.contiguous()
+        if gain.shape[0] != B:
+            raise ValueError("gain must have B=%d entries" % B)
+    if out is None:
+        out = torch.empty((B, H, W), dtype=torch.float32, device=pan.device)
+    else:
+        _require(out, "out", 3)
+        if tuple(out.shape) != (B, H, W):
+            raise ValueError("out must be (B, H, W)")
+        if out.stride(-1) != 1:
+            raise ValueError("out must have unit stride along rows")
+    return pan, ms, gain, out, H, W, B
+
+
+def fuse(pan: torch.Tensor, ms: torch.Tensor, wavelet="d4", gain: Optional[torch.Tensor] = None,
+         out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Fused bands (B, H, W) for PAN (H, W) and MS (B, H/2, W/2) (or (H/2, W/2)).
+
+    Section 2 of the paper: forward 2D DWT of PAN, LL quadrant replaced by each
+    MS band, inverse 2D DWT (Haar Eq. 1-2/11-12 or D4 Eq. 3-16 with wrap).
+    ``gain`` (B,) scales the PAN detail quadrants per band (None = 1)."""
+    pan, ms, gain, out, H, W, B = _prep_scene(pan, ms, gain, out)
+    c = context(pan.device)
+    c.bind_stream()
+    st = c.lib.dwt_fuse_run(c.handle, wavelet_id(wavelet), H, W, B,
+                            _ptr(pan), _pitch(pan, 0), _ptr(ms), _pitch(ms, 1), _pitch(ms, 0),
+                            _ptr(gain), _ptr(out), _pitch(out, 1), _pitch(out, 0))
+    c.check(st, "dwt_fuse_run")
+    return out
+
+
+def make_items(scenes: Sequence[dict]):
+    """Prepare dwt_fuse_item descriptors; each scene is a dict with keys pan,
+    ms, wavelet and optionally gain, out.  Returns (items array, outs, keep)."""
+    n = len(scenes)
+    arr = (Item * max(n, 1))()
+    outs, keep = [], []
+    for i, s in enumerate(scenes):
+        pan, ms, gain, out, H, W, B = _prep_scene(s["pan"], s["ms"], s.get("gain"), s.get("out"))
+        keep.extend([pan, ms, gain, out])
+        outs.append(out)
+        it = arr[i]
+        it.wavelet = wavelet_id(s.get("wavelet", "d4"))
+        it.B = B
+        it.H = H
+        it.W = W
+        it.pan = pan.data_ptr()
+        it.ms = ms.data_ptr()
+        it.gain = gain.data_ptr() if gain is not None else None
+        it.out = out.data_ptr()
+        it.pan_ld = _pitch(pan, 0)
+        it.ms_ld = _pitch(ms, 1)
+        it.ms_band_stride = _pitch(ms, 0)
+        it.out_ld = _pitch(out, 1)
+        it.out_band_stride = _pitch(out, 0)
+    return arr, outs, keep
+
+
+def fuse_batched(scenes: Sequence[dict], graph: bool = False, device=None) -> List[torch.Tensor]:
+    """Fuse many independent scenes in one persistent launch (optionally
+    captured/replayed as a hipGraph).  Returns the list of outputs."""
+    if len(scenes) == 0:
+        return []
+    arr, outs, keep = make_items(scenes)
+    c = context(device if device is not None else scenes[0]["pan"].device)
+    c.bind_stream()
+    st = c.lib.dwt_fuse_run_batched(c.handle, arr, len(scenes), _lib.GRAPH if graph else 0)
+    c.check(st, "dwt_fuse_run_batched")
+    return outs
+
+
+def fuse_backward(pan: torch.Tensor, grad_out: torch.Tensor, wavelet="d4", gain: Optional[torch.Tensor] = None,
+                  need_pan: bool = True, need_ms: bool = True, need_gain: bool = True):
+    """Transpose of ``fuse``: (grad_pan (H,W), grad_ms (B,H/2,W/2), grad_gain (B,))
+    for dLoss/d(out) = grad_out (B, H, W).  Entries not requested are None."""
+    _require(pan, "pan", 2)
+    if grad_out.dim() == 2:
+        grad_out = grad_out.unsqueeze(0)
+    _require(grad_out, "grad_out", 3)
+    pan = _rows_unit(pan)
+    grad_out = _rows_unit(grad_out)
+    H, W = pan.shape
+    B = grad_out.shape[0]
+    if tuple(grad_out.shape[1:]) != (H, W):
+        raise ValueError("grad_out must be (B, H, W)")
+    if gain is not None:
+        _require(gain, "gain", 1)
+        gain = gain.contiguous()
+    dev = pan.device
+    gp = torch.empty((H, W), dtype=torch.float32, device=dev) if need_pan else None
+    gm = torch.empty((B, H // 2, W // 2), dtype=torch.float32, device=dev) if need_ms else None
+    gg = torch.empty((B,), dtype=torch.float32, device=dev) if need_gain else None
+    c = context(dev)
+    c.bind_stream()
+    st = c.lib.dwt_fuse_backward(c.handle, wavelet_id(wavelet), H, W, B, _ptr(pan), _pitch(pan, 0), _ptr(gain),
+                                 _ptr(grad_out), _pitch(grad_out, 1), _pitch(grad_out, 0),
+                                 _ptr(gp), _ptr(gm), _ptr(gg))
+    c.check(st, "dwt_fuse_backward")
+    return gp, gm, gg
+
+
+class DwtFuseFn(torch.autograd.Function):
+    """Differentiable fusion: ``DwtFuseFn.apply(pan, ms, gain, wavelet)``.
+
+    Forward runs the fused kernel; backward runs the hand-written adjoint
+    kernel (gradients w.r.t. PAN, MS and the per-band detail gain)."""
+
+    @staticmethod
+    def forward(ctx, pan, ms, gain, wavelet="d4"):
+        ctx.wavelet = wavelet
+        ctx.squeeze = ms.dim() == 2
+        ctx.save_for_backward(pan, gain)
+        return fuse(pan, ms, wavelet, gain)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        pan, gain = ctx.saved_tensors
+        need_pan, need_ms, need_gain = ctx.needs_input_grad[:3]
+        gp, gm, gg = fuse_backward(pan, grad_out, ctx.wavelet, gain, need_pan, need_ms,
+                                   need_gain and gain is not None)
+        if gm is not None and ctx.squeeze:
+            gm = gm[0]
+        return gp, gm, gg, None

@@ -1,0 +1,460 @@
+// Adjoint (transpose) of the fused DWT pan-sharpening map, for gfx950.
+//
+// The forward map is linear in (PAN, MS) for fixed gains and linear in each
+// gain:  out_b = g_b (PAN - P PAN) + S m_b, where P is the projection of an
+// image onto its LL part and S is the synthesis of an LL-only coefficient
+// image.  For D4 (orthonormal, Eq. 3-16 with wrap) S = L^T and P = L^T L;
+// for Haar (Eq. 1-2, 11-12) S repeats each coefficient over its 2x2 block and
+// P replaces each pixel by its block mean.  P is symmetric in both cases, so
+// for an upstream gradient y_b = dLoss/d(out_b):
+//     dLoss/d(m_b)   = S^T y_b            (D4: L y_b;  Haar: 2x2 block sum)
+//     dLoss/d(PAN)   = Y - P Y,  Y = sum_b g_b y_b
+//     dLoss/d(g_b)   = < y_b, PAN - P PAN >.
+// The kernels walk the same work units as the forward kernels (a strip of
+// 64*NC coefficient columns per wavefront, seg_rows coefficient rows) with
+// rolling rows in registers; the per-band gain products are reduced per
+// lane in LDS, per wavefront with cross-lane adds, written per work unit and
+// summed by gain_reduce_kernel in a fixed order (reproducible bit for bit).
+#include "fuse_internal.h"
+
+namespace dwtf {
+
+typedef float f2 __attribute__((ext_vector_type(2)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int kAdjMaxBands = 8;  // bands per launch; the host splits larger B
+
+namespace {
+
+__device__ __forceinline__ int wrap_idx(int q, int n) {
+    q %= n;
+    return q < 0 ? q + n : q;
+}
+
+template <bool AL>
+__device__ __forceinline__ f2 ld2(const float *p) {
+    if constexpr (AL) {
+        return *reinterpret_cast<const f2 *>(p);
+    } else {
+        return f2{p[0], p[1]};
+    }
+}
+
+template <bool AL>
+__device__ __forceinline__ void st2(float *p, f2 v) {
+    if constexpr (AL) {
+        *reinterpret_cast<f2 *>(p) = v;
+    } else {
+        p[0] = v.x;
+        p[1] = v.y;
+    }
+}
+
+__device__ __forceinline__ int xcd_remap(int b, int G) {
+    constexpr int NX = 8;
+    const int x = b % NX, i = b / NX, q = G / NX, rem = G % NX;
+    return x * q + (x < rem ? x : rem) + i;
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+    return v;
+}
+
+// Loads NC+2 column pairs (pc[0..NC+1]) of one row; pairs 1..NC are the
+// lane's own pixels.
+template <int NC, bool AL>
+__device__ __forceinline__ void load_pairs(const float *row, const int (&pc)[NC + 2], int s0, bool full,
+                                           f2 (&x)[NC + 2]) {
+    x[0] = ld2<AL>(row + 2 * pc[0]);
+    if constexpr (NC == 2 && AL) {
+        if (full) {
+            const f4 v = *reinterpret_cast<const f4 *>(row + 2 * s0);
+            x[1] = f2{v.x, v.y};
+            x[2] = f2{v.z, v.w};
+        } else {
+            x[1] = ld2<AL>(row + 2 * pc[1]);
+            x[2] = ld2<AL>(row + 2 * pc[2]);
+        }
+    } else {
+#pragma unroll
+        for (int k = 1; k <= NC; ++k) x[k] = ld2<AL>(row + 2 * pc[k]);
+    }
+    x[NC + 1] = ld2<AL>(row + 2 * pc[NC + 1]);
+}
+
+template <int NC>
+__device__ __forceinline__ void rowfilt(const float (&h)[4], const f2 (&x)[NC + 2], float (&R)[NC + 1]) {
+#pragma unroll
+    for (int j = 0; j <= NC; ++j) R[j] = h[0] * x[j].x + h[1] * x[j].y + h[2] * x[j + 1].x + h[3] * x[j + 1].y;
+}
+
+template <int NC, bool AL>
+__device__ __forceinline__ void store_pairs(float *row, int s0, int W2, bool full, const f2 (&q)[NC]) {
+    if constexpr (NC == 2 && AL) {
+        if (full)
+            *reinterpret_cast<f4 *>(row + 2 * s0) = f4{q[0].x, q[0].y, q[1].x, q[1].y};
+        else
+            st2<AL>(row + 2 * s0, q[0]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < NC; ++i)
+            if (s0 + i < W2) st2<AL>(row + 2 * (s0 + i), q[i]);
+    }
+}
+
+template <int NC, bool AL>
+__device__ __forceinline__ void store_ms(float *row, int s0, int W2, bool full, const float (&v)[NC]) {
+    if constexpr (NC == 2 && AL) {
+        if (full)
+            *reinterpret_cast<f2 *>(row + s0) = f2{v[0], v[1]};
+        else
+            row[s0] = v[0];
+    } else {
+#pragma unroll
+        for (int i = 0; i < NC; ++i)
+            if (s0 + i < W2) row[s0 + i] = v[i];
+    }
+}
+
+// ---- D4 adjoint ----------------------------------------------------------
+
+template <int NC, bool AL>
+__device__ __forceinline__ void d4_adj_unit(const AdjParams &p, const Filters &f, int strip, int seg,
+                                            int lane, float *acc /* this lane's LDS slots */, int acc_stride) {
+    const int W2 = p.W >> 1, H2 = p.H >> 1;
+    const int s0 = (strip * 64 + lane) * NC;
+    if (s0 >= W2) return;
+    const bool full = (s0 + NC) <= W2;
+    bool valid[NC];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) valid[i] = (s0 + i) < W2;
+    int pc[NC + 2];
+#pragma unroll
+    for (int k = 0; k < NC + 2; ++k) pc[k] = wrap_idx(s0 - 1 + k, W2);
+    const float h[4] = {f.h[0], f.h[1], f.h[2], f.h[3]};
+    const int rb = seg * p.seg_rows;
+    const int re = min(rb + p.seg_rows, H2);
+    auto wrow = [&](int y) { return y < 0 ? y + p.H : (y >= p.H ? y - p.H : y); };
+
+    // L PAN at coefficient row rb-1 and L Y at rb-1 (Y = sum_b g_b y_b).
+    f2 xa[NC + 2], xb[NC + 2];
+    float Ra[NC + 1], Rb[NC + 1], Ap[NC + 1], LYp[NC + 1];
+    {
+        f2 xt[NC + 2];
+        float Rt[NC + 1];
+#pragma unroll
+        for (int j = 0; j <= NC; ++j) {
+            Ap[j] = 0.f;
+            LYp[j] = 0.f;
+        }
+        for (int k = 0; k < 2; ++k) {
+            load_pairs<NC, AL>(p.pan + (int64_t)wrow(2 * rb - 2 + k) * p.pan_ld, pc, s0, full, xt);
+            rowfilt<NC>(h, xt, Rt);
+#pragma unroll
+            for (int j = 0; j <= NC; ++j) Ap[j] += h[k] * Rt[j];
+        }
+        load_pairs<NC, AL>(p.pan + (int64_t)(2 * rb) * p.pan_ld, pc, s0, full, xa);
+        load_pairs<NC, AL>(p.pan + (int64_t)(2 * rb + 1) * p.pan_ld, pc, s0, full, xb);
+        rowfilt<NC>(h, xa, Ra);
+        rowfilt<NC>(h, xb, Rb);
+#pragma unroll
+        for (int j = 0; j <= NC; ++j) Ap[j] += h[2] * Ra[j] + h[3] * Rb[j];
+        for (int b = 0; b < p.B; ++b) {
+            const float g = p.gain ? p.gain[b] : 1.0f;
+            const float *yb = p.gy + (int64_t)b * p.gy_bs;
+            float Ly[NC + 1];
+#pragma unroll
+            for (int j = 0; j <= NC; ++j) Ly[j] = 0.f;
+            for (int k = 0; k < 4; ++k) {
+                load_pairs<NC, AL>(yb + (int64_t)wrow(2 * rb - 2 + k) * p.gy_ld, pc, s0, full, xt);
+                rowfilt<NC>(h, xt, Rt);
+#pragma unroll
+                for (int j = 0; j <= NC; ++j) Ly[j] += h[k] * Rt[j];
+            }
+#pragma unroll
+            for (int j = 0; j <= NC; ++j) LYp[j] += g * Ly[j];
+        }
+    }
+
+    for (int r = rb; r < re; ++r) {
+        f2 xc[NC + 2], xd[NC + 2];
+        float Rc[NC + 1], Rd[NC + 1], A[NC + 1];
+        load_pairs<NC, AL>(p.pan + (int64_t)wrow(2 * r + 2) * p.pan_ld, pc, s0, full, xc);
+        load_pairs<NC, AL>(p.pan + (int64_t)wrow(2 * r + 3) * p.pan_ld, pc, s0, full, xd);
+        rowfilt<NC>(h, xc, Rc);
+        rowfilt<NC>(h, xd, Rd);
+#pragma unroll
+        for (int j = 0; j <= NC; ++j) A[j] = h[0] * Ra[j] + h[1] * Rb[j] + h[2] * Rc[j] + h[3] * Rd[j];
+        // D = PAN - P PAN at output rows 2r, 2r+1 (own pixels).
+        f2 Da[NC], Db[NC];
+        {
+            float w0[NC + 1], w1[NC + 1];
+#pragma unroll
+            for (int j = 0; j <= NC; ++j) {
+                w0[j] = h[0] * A[j] + h[2] * Ap[j];
+                w1[j] = h[1] * A[j] + h[3] * Ap[j];
+            }
+#pragma unroll
+            for (int i = 0; i < NC; ++i) {
+                Da[i].x = xa[i + 1].x - (h[0] * w0[i + 1] + h[2] * w0[i]);
+                Da[i].y = xa[i + 1].y - (h[1] * w0[i + 1] + h[3] * w0[i]);
+                Db[i].x = xb[i + 1].x - (h[0] * w1[i + 1] + h[2] * w1[i]);
+                Db[i].y = xb[i + 1].y - (h[1] * w1[i + 1] + h[3] * w1[i]);
+            }
+        }
+        float LY[NC + 1];
+        f2 Ya[NC], Yb[NC];
+#pragma unroll
+        for (int j = 0; j <= NC; ++j) LY[j] = 0.f;
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            Ya[i] = f2{0.f, 0.f};
+            Yb[i] = f2{0.f, 0.f};
+        }
+        for (int b = 0; b < p.B; ++b) {
+            const float g = p.gain ? p.gain[b] : 1.0f;
+            const float *yb = p.gy + (int64_t)b * p.gy_bs;
+            f2 z0[NC + 2], z1[NC + 2], zt[NC + 2];
+            float R0[NC + 1], Rt[NC + 1], Ly[NC + 1];
+            load_pairs<NC, AL>(yb + (int64_t)(2 * r) * p.gy_ld, pc, s0, full, z0);
+            load_pairs<NC, AL>(yb + (int64_t)(2 * r + 1) * p.gy_ld, pc, s0, full, z1);
+            rowfilt<NC>(h, z0, R0);
+#pragma unroll
+            for (int j = 0; j <= NC; ++j) Ly[j] = h[0] * R0[j];
+            rowfilt<NC>(h, z1, Rt);
+#pragma unroll
+            for (int j = 0; j <= NC; ++j) Ly[j] += h[1] * Rt[j];
+            load_pairs<NC, AL>(yb + (int64_t)wrow(2 * r + 2) * p.gy_ld, pc, s0, full, zt);
+            rowfilt<NC>(h, zt, Rt);
+#pragma unroll
+            for (int j = 0; j <= NC; ++j) Ly[j] += h[2] * Rt[j];
+            load_pairs<NC, AL>(yb + (int64_t)wrow(2 * r + 3) * p.gy_ld, pc, s0, full, zt);
+            rowfilt<NC>(h, zt, Rt);
+#pragma unroll
+            for (int j = 0; j <= NC; ++j) Ly[j] += h[3] * Rt[j];
+            if (p.grad_ms) {
+                float v[NC];
+#pragma unroll
+                for (int i = 0; i < NC; ++i) v[i] = Ly[i + 1];
+                store_ms<NC, AL>(p.grad_ms + (int64_t)b * H2 * W2 + (int64_t)r * W2, s0, W2, full, v);
+            }
+#pragma unroll
+            for (int j = 0; j <= NC; ++j) LY[j] += g * Ly[j];
+            float dot = 0.f;
+#pragma unroll
+            for (int i = 0; i < NC; ++i) {
+                if (!valid[i]) continue;
+                Ya[i].x += g * z0[i + 1].x;
+                Ya[i].y += g * z0[i + 1].y;
+                Yb[i].x += g * z1[i + 1].x;
+                Yb[i].y += g * z1[i + 1].y;
+                dot += z0[i + 1].x * Da[i].x + z0[i + 1].y * Da[i].y + z1[i + 1].x * Db[i].x +
+                       z1[i + 1].y * Db[i].y;
+            }
+            acc[b * acc_stride] += dot;
+        }
+        if (p.grad_pan) {
+            float v0[NC + 1], v1[NC + 1];
+#pragma unroll
+            for (int j = 0; j <= NC; ++j) {
+                v0[j] = h[0] * LY[j] + h[2] * LYp[j];
+                v1[j] = h[1] * LY[j] + h[3] * LYp[j];
+            }
+            f2 q0[NC], q1[NC];
+#pragma unroll
+            for (int i = 0; i < NC; ++i) {
+                q0[i].x = Ya[i].x - (h[0] * v0[i + 1] + h[2] * v0[i]);
+                q0[i].y = Ya[i].y - (h[1] * v0[i + 1] + h[3] * v0[i]);
+                q1[i].x = Yb[i].x - (h[0] * v1[i + 1] + h[2] * v1[i]);
+                q1[i].y = Yb[i].y - (h[1] * v1[i + 1] + h[3] * v1[i]);
+            }
+            float *g0 = p.grad_pan + (int64_t)(2 * r) * p.W;
+            float *g1 = g0 + p.W;
+            if (p.accumulate) {
+#pragma unroll
+                for (int i = 0; i < NC; ++i) {
+                    if (!valid[i]) continue;
+                    const f2 e0 = ld2<AL>(g0 + 2 * (s0 + i)), e1 = ld2<AL>(g1 + 2 * (s0 + i));
+                    q0[i] += e0;
+                    q1[i] += e1;
+                }
+            }
+            store_pairs<NC, AL>(g0, s0, W2, full, q0);
+            store_pairs<NC, AL>(g1, s0, W2, full, q1);
+        }
+#pragma unroll
+        for (int j = 0; j <= NC; ++j) {
+            Ap[j] = A[j];
+            Ra[j] = Rc[j];
+            Rb[j] = Rd[j];
+            LYp[j] = LY[j];
+        }
+#pragma unroll
+        for (int k = 0; k < NC + 2; ++k) {
+            xa[k] = xc[k];
+            xb[k] = xd[k];
+        }
+    }
+}
+
+// ---- Haar adjoint --------------------------------------------------------
+
+template <int NC, bool AL>
+__device__ __forceinline__ void haar_adj_unit(const AdjParams &p, int strip, int seg, int lane, float *acc,
+                                              int acc_stride) {
+    const int W2 = p.W >> 1, H2 = p.H >> 1;
+    const int s0 = (strip * 64 + lane) * NC;
+    if (s0 >= W2) return;
+    const bool full = (s0 + NC) <= W2;
+    int pc[NC];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) pc[i] = (s0 + i < W2) ? s0 + i : s0;  // invalid pairs re-read pair s0
+    bool valid[NC];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) valid[i] = (s0 + i) < W2;
+    const int rb = seg * p.seg_rows;
+    const int re = min(rb + p.seg_rows, H2);
+    auto load_own = [&](const float *row, f2(&x)[NC]) {
+        if constexpr (NC == 2 && AL) {
+            if (full) {
+                const f4 v = *reinterpret_cast<const f4 *>(row + 2 * s0);
+                x[0] = f2{v.x, v.y};
+                x[1] = f2{v.z, v.w};
+                return;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < NC; ++i) x[i] = ld2<AL>(row + 2 * pc[i]);
+    };
+    for (int r = rb; r < re; ++r) {
+        f2 a[NC], c[NC];
+        load_own(p.pan + (int64_t)(2 * r) * p.pan_ld, a);
+        load_own(p.pan + (int64_t)(2 * r + 1) * p.pan_ld, c);
+        f2 Da[NC], Dc[NC];
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            const float mean = ((a[i].x + a[i].y) + (c[i].x + c[i].y)) * 0.25f;
+            Da[i] = f2{a[i].x - mean, a[i].y - mean};
+            Dc[i] = f2{c[i].x - mean, c[i].y - mean};
+        }
+        f2 Ya[NC], Yc[NC];
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            Ya[i] = f2{0.f, 0.f};
+            Yc[i] = f2{0.f, 0.f};
+        }
+        for (int b = 0; b < p.B; ++b) {
+            const float g = p.gain ? p.gain[b] : 1.0f;
+            const float *yb = p.gy + (int64_t)b * p.gy_bs;
+            f2 z0[NC], z1[NC];
+            load_own(yb + (int64_t)(2 * r) * p.gy_ld, z0);
+            load_own(yb + (int64_t)(2 * r + 1) * p.gy_ld, z1);
+            float bs[NC];
+            float dot = 0.f;
+#pragma unroll
+            for (int i = 0; i < NC; ++i) {
+                bs[i] = (z0[i].x + z0[i].y) + (z1[i].x + z1[i].y);  // transpose of block repeat
+                if (!valid[i]) continue;
+                Ya[i] += g * z0[i];
+                Yc[i] += g * z1[i];
+                dot += z0[i].x * Da[i].x + z0[i].y * Da[i].y + z1[i].x * Dc[i].x + z1[i].y * Dc[i].y;
+            }
+            if (p.grad_ms) store_ms<NC, AL>(p.grad_ms + (int64_t)b * H2 * W2 + (int64_t)r * W2, s0, W2, full, bs);
+            acc[b * acc_stride] += dot;
+        }
+        if (p.grad_pan) {
+            f2 q0[NC], q1[NC];
+#pragma unroll
+            for (int i = 0; i < NC; ++i) {
+                const float mean = ((Ya[i].x + Ya[i].y) + (Yc[i].x + Yc[i].y)) * 0.25f;
+                q0[i] = f2{Ya[i].x - mean, Ya[i].y - mean};
+                q1[i] = f2{Yc[i].x - mean, Yc[i].y - mean};
+            }
+            float *g0 = p.grad_pan + (int64_t)(2 * r) * p.W;
+            float *g1 = g0 + p.W;
+            if (p.accumulate) {
+#pragma unroll
+                for (int i = 0; i < NC; ++i) {
+                    if (!valid[i]) continue;
+                    q0[i] += ld2<AL>(g0 + 2 * (s0 + i));
+                    q1[i] += ld2<AL>(g1 + 2 * (s0 + i));
+                }
+            }
+            store_pairs<NC, AL>(g0, s0, W2, full, q0);
+            store_pairs<NC, AL>(g1, s0, W2, full, q1);
+        }
+    }
+}
+
+template <int NC, bool AL>
+__global__ __launch_bounds__(256) void adjoint_kernel(AdjParams p, Filters f) {
+    __shared__ float acc_lds[kAdjMaxBands * 256];
+    const int wpb = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int unit = xcd_remap(blockIdx.x, gridDim.x) * wpb + (threadIdx.x >> 6);
+    if (unit >= p.units) return;  // whole wavefront leaves together
+    float *acc = acc_lds + threadIdx.x;
+    for (int b = 0; b < p.B; ++b) acc[b * 256] = 0.f;
+    const int strip = unit / p.nseg;
+    const int seg = unit - strip * p.nseg;
+    if (p.wavelet == 1)
+        d4_adj_unit<NC, AL>(p, f, strip, seg, lane, acc, 256);
+    else
+        haar_adj_unit<NC, AL>(p, strip, seg, lane, acc, 256);
+    if (p.partial) {
+        for (int b = 0; b < p.B; ++b) {
+            const float s = wave_sum(acc[b * 256]);
+            if (lane == 0) p.partial[(int64_t)unit * p.pstride + b] = s;
+        }
+    }
+}
+
+// grad_gain[b] = sum over units of partial[unit * pstride + b], in FP64 with
+// a fixed assignment of units to threads and a fixed reduction tree.
+__global__ __launch_bounds__(256) void gain_reduce_kernel(const float *partial, int units, int pstride,
+                                                          float *grad_gain) {
+    __shared__ double sh[256];
+    const int b = blockIdx.x;
+    double a = 0.0;
+    for (int u = threadIdx.x; u < units; u += 256) a += (double)partial[(int64_t)u * pstride + b];
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) grad_gain[b] = (float)sh[0];
+}
+
+}  // namespace
+
+hipError_t launch_adjoint(const AdjParams &p, const Filters &f, int wpb, hipStream_t s) {
+    if (p.units <= 0) return hipSuccess;
+    if (p.B > kAdjMaxBands || p.B < 1) return hipErrorInvalidValue;
+    const int grid = (p.units + wpb - 1) / wpb;
+    const dim3 block(64 * wpb);
+    switch (p.path) {
+        case PATH_V4:
+            hipLaunchKernelGGL((adjoint_kernel<2, true>), dim3(grid), block, 0, s, p, f);
+            break;
+        case PATH_V2:
+            hipLaunchKernelGGL((adjoint_kernel<1, true>), dim3(grid), block, 0, s, p, f);
+            break;
+        default:
+            hipLaunchKernelGGL((adjoint_kernel<1, false>), dim3(grid), block, 0, s, p, f);
+            break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gain_reduce(const float *partial, int units, int B, float *grad_gain, hipStream_t s) {
+    if (B <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gain_reduce_kernel, dim3(B), dim3(256), 0, s, partial, units, B, grad_gain);
+    return hipGetLastError();
+}
+
+int adjoint_max_bands() { return kAdjMaxBands; }
+
+}  // namespace dwtf

@@ -1,0 +1,920 @@
+// Host side of the C ABI declared in include/dwt_fuse.h: argument
+// validation, the context (stream, workspace, batch tables, captured graphs,
+// tuning table), work decomposition and kernel dispatch.
+#include "dwt_fuse.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "fuse_internal.h"
+
+#ifndef DWT_FUSE_BUILD_ID
+#define DWT_FUSE_BUILD_ID "dev"
+#endif
+
+using namespace dwtf;
+
+namespace {
+
+// ---------------------------------------------------------------- validation
+
+struct Span {
+    uintptr_t lo = 0, hi = 0;  // byte range [lo, hi); empty if lo == hi
+    bool overlaps(const Span &o) const { return lo < o.hi && o.lo < hi && lo != hi && o.lo != o.hi; }
+};
+
+// Elements spanned by nb bands of rows x cols with pitch ld and band stride
+// bs: (nb-1)*bs + (rows-1)*ld + cols.  False on overflow.
+bool extent(int64_t nb, int64_t rows, int64_t cols, int64_t ld, int64_t bs, int64_t *elems) {
+    int64_t a = 0, b = 0, c = 0;
+    if (__builtin_mul_overflow(nb - 1, bs, &a)) return false;
+    if (__builtin_mul_overflow(rows - 1, ld, &b)) return false;
+    if (__builtin_add_overflow(a, b, &c)) return false;
+    if (__builtin_add_overflow(c, cols, &c)) return false;
+    if (c > INT64_MAX / 4) return false;
+    *elems = c;
+    return true;
+}
+
+Span span_of(const void *p, int64_t elems) {
+    Span s;
+    s.lo = reinterpret_cast<uintptr_t>(p);
+    s.hi = s.lo + static_cast<uintptr_t>(elems) * sizeof(float);
+    return s;
+}
+
+constexpr int64_t kMaxSide = int64_t(1) << 30;  // kernels index rows/columns in int32
+constexpr int64_t kMaxBands = int64_t(1) << 20;
+
+dwt_fuse_status check_shape(int64_t H, int64_t W, int64_t B, std::string *err) {
+    if (H < 2 || W < 2 || (H & 1) || (W & 1) || H > kMaxSide || W > kMaxSide) {
+        if (err) *err = "H and W must be even, >= 2 and <= 2^30";
+        return DWT_FUSE_E_SHAPE;
+    }
+    if (B < 1 || B > kMaxBands) {
+        if (err) *err = "B must be in [1, 2^20]";
+        return DWT_FUSE_E_SHAPE;
+    }
+    int64_t hw = 0, hwb = 0;
+    if (__builtin_mul_overflow(H, W, &hw) || __builtin_mul_overflow(hw, B, &hwb) || hwb > INT64_MAX / 4) {
+        if (err) *err = "H*W*B overflows";
+        return DWT_FUSE_E_SHAPE;
+    }
+    return DWT_FUSE_OK;
+}
+
+dwt_fuse_status check_strided(const char *name, int64_t nb, int64_t rows, int64_t cols, int64_t ld, int64_t bs,
+                              const void *ptr, Span *sp, std::string *err) {
+    if (ld < cols || (nb > 1 && (bs < 0 || bs / ld < rows))) {
+        if (err) *err = std::string(name) + ": pitch smaller than the row width, or band stride smaller than rows*pitch";
+        return DWT_FUSE_E_STRIDE;
+    }
+    if (nb > 1) {
+        int64_t rl = 0;
+        if (__builtin_mul_overflow(rows, ld, &rl) || bs < rl) {
+            if (err) *err = std::string(name) + ": band stride smaller than rows*pitch";
+            return DWT_FUSE_E_STRIDE;
+        }
+    }
+    int64_t e = 0;
+    if (!extent(nb, rows, cols, ld, bs, &e)) {
+        if (err) *err = std::string(name) + ": extent overflows";
+        return DWT_FUSE_E_SHAPE;
+    }
+    *sp = span_of(ptr, e);
+    return DWT_FUSE_OK;
+}
+
+struct RunArgs {
+    int wavelet;
+    int64_t H, W, B;
+    const float *pan;
+    int64_t pan_ld;
+    const float *ms;
+    int64_t ms_ld, ms_bs;
+    const float *gain;
+    const float *out;
+    int64_t out_ld, out_bs;
+};
+
+struct RunSpans {
+    Span pan, ms, gain, out;
+};
+
+dwt_fuse_status check_run_args(const RunArgs &a, RunSpans *sp, std::string *err) {
+    if (!a.pan || !a.ms || !a.out) {
+        if (err) *err = "pan, ms and out must not be NULL";
+        return DWT_FUSE_E_NULL;
+    }
+    dwt_fuse_status st = check_shape(a.H, a.W, a.B, err);
+    if (st) return st;
+    if (a.wavelet != DWT_FUSE_HAAR && a.wavelet != DWT_FUSE_D4) {
+        if (err) *err = "unknown wavelet";
+        return DWT_FUSE_E_WAVELET;
+    }
+    RunSpans s;
+    if ((st = check_strided("pan", 1, a.H, a.W, a.pan_ld, 0, a.pan, &s.pan, err))) return st;
+    if ((st = check_strided("ms", a.B, a.H / 2, a.W / 2, a.ms_ld, a.ms_bs, a.ms, &s.ms, err))) return st;
+    if ((st = check_strided("out", a.B, a.H, a.W, a.out_ld, a.out_bs, a.out, &s.out, err))) return st;
+    s.gain = a.gain ? span_of(a.gain, a.B) : Span{};
+    if (s.out.overlaps(s.pan) || s.out.overlaps(s.ms) || s.out.overlaps(s.gain)) {
+        if (err) *err = "out overlaps an input";
+        return DWT_FUSE_E_ALIAS;
+    }
+    if (sp) *sp = s;
+    return DWT_FUSE_OK;
+}
+
+struct BwdArgs {
+    int wavelet;
+    int64_t H, W, B;
+    const float *pan;
+    int64_t pan_ld;
+    const float *gain;
+    const float *gy;
+    int64_t gy_ld, gy_bs;
+    const float *grad_pan, *grad_ms, *grad_gain;
+};
+
+dwt_fuse_status check_bwd_args(const BwdArgs &a, std::string *err) {
+    if (!a.pan || !a.gy) {
+        if (err) *err = "pan and grad_out must not be NULL";
+        return DWT_FUSE_E_NULL;
+    }
+    dwt_fuse_status st = check_shape(a.H, a.W, a.B, err);
+    if (st) return st;
+    if (a.wavelet != DWT_FUSE_HAAR && a.wavelet != DWT_FUSE_D4) {
+        if (err) *err = "unknown wavelet";
+        return DWT_FUSE_E_WAVELET;
+    }
+    Span pan, gy;
+    if ((st = check_strided("pan", 1, a.H, a.W, a.pan_ld, 0, a.pan, &pan, err))) return st;
+    if ((st = check_strided("grad_out", a.B, a.H, a.W, a.gy_ld, a.gy_bs, a.gy, &gy, err))) return st;
+    const Span gain = a.gain ? span_of(a.gain, a.B) : Span{};
+    const Span outs[3] = {a.grad_pan ? span_of(a.grad_pan, a.H * a.W) : Span{},
+                          a.grad_ms ? span_of(a.grad_ms, a.B * (a.H / 2) * (a.W / 2)) : Span{},
+                          a.grad_gain ? span_of(a.grad_gain, a.B) : Span{}};
+    for (int i = 0; i < 3; ++i) {
+        if (outs[i].overlaps(pan) || outs[i].overlaps(gy) || outs[i].overlaps(gain)) {
+            if (err) *err = "a gradient output overlaps an input";
+            return DWT_FUSE_E_ALIAS;
+        }
+        for (int j = i + 1; j < 3; ++j)
+            if (outs[i].overlaps(outs[j])) {
+                if (err) *err = "gradient outputs overlap each other";
+                return DWT_FUSE_E_ALIAS;
+            }
+    }
+    return DWT_FUSE_OK;
+}
+
+RunArgs item_args(const dwt_fuse_item &it) {
+    return RunArgs{it.wavelet, it.H, it.W, it.B, it.pan, it.pan_ld, it.ms, it.ms_ld, it.ms_band_stride,
+                   it.gain, it.out, it.out_ld, it.out_band_stride};
+}
+
+dwt_fuse_status check_batch(const dwt_fuse_item *items, int64_t n, std::string *err) {
+    if (n < 0) {
+        if (err) *err = "n < 0";
+        return DWT_FUSE_E_SHAPE;
+    }
+    if (n == 0) return DWT_FUSE_OK;
+    if (!items) {
+        if (err) *err = "items is NULL";
+        return DWT_FUSE_E_NULL;
+    }
+    if (n > (int64_t(1) << 24)) {
+        if (err) *err = "too many items";
+        return DWT_FUSE_E_SHAPE;
+    }
+    std::vector<Span> outs, ins;
+    outs.reserve(n);
+    ins.reserve(3 * n);
+    for (int64_t i = 0; i < n; ++i) {
+        RunSpans s;
+        std::string e;
+        const dwt_fuse_status st = check_run_args(item_args(items[i]), &s, &e);
+        if (st) {
+            if (err) *err = "item " + std::to_string(i) + ": " + e;
+            return st;
+        }
+        outs.push_back(s.out);
+        ins.push_back(s.pan);
+        ins.push_back(s.ms);
+        if (s.gain.lo != s.gain.hi) ins.push_back(s.gain);
+    }
+    // Outputs pairwise disjoint: sort by start, compare neighbours.
+    std::vector<Span> o = outs;
+    std::sort(o.begin(), o.end(), [](const Span &a, const Span &b) { return a.lo < b.lo; });
+    for (size_t i = 1; i < o.size(); ++i)
+        if (o[i].lo < o[i - 1].hi) {
+            if (err) *err = "outputs of two items overlap";
+            return DWT_FUSE_E_ALIAS;
+        }
+    // No output overlaps any input (inputs may overlap each other).
+    std::sort(ins.begin(), ins.end(), [](const Span &a, const Span &b) { return a.lo < b.lo; });
+    std::vector<uintptr_t> pmax(ins.size());
+    uintptr_t m = 0;
+    for (size_t i = 0; i < ins.size(); ++i) pmax[i] = m = std::max(m, ins[i].hi);
+    for (const Span &s : outs) {
+        // last input starting before s.hi
+        size_t lo = 0, hi = ins.size();
+        while (lo < hi) {
+            const size_t mid = (lo + hi) / 2;
+            if (ins[mid].lo < s.hi)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        if (lo > 0 && pmax[lo - 1] > s.lo) {
+            if (err) *err = "an item's output overlaps an input";
+            return DWT_FUSE_E_ALIAS;
+        }
+    }
+    return DWT_FUSE_OK;
+}
+
+// ---------------------------------------------------------------- tiling
+
+bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+Path choose_path(const RunArgs &a) {
+    const bool b1 = a.B == 1;
+    if (aligned(a.pan, 16) && aligned(a.out, 16) && a.pan_ld % 4 == 0 && a.out_ld % 4 == 0 &&
+        (b1 || a.out_bs % 4 == 0) && aligned(a.ms, 8) && a.ms_ld % 2 == 0 && (b1 || a.ms_bs % 2 == 0))
+        return PATH_V4;
+    if (aligned(a.pan, 8) && aligned(a.out, 8) && a.pan_ld % 2 == 0 && a.out_ld % 2 == 0 &&
+        (b1 || a.out_bs % 2 == 0))
+        return PATH_V2;
+    return PATH_SCALAR;
+}
+
+Path choose_bwd_path(const BwdArgs &a) {
+    const bool b1 = a.B == 1;
+    const bool gp = !a.grad_pan || aligned(a.grad_pan, 16);
+    const bool gm = !a.grad_ms || aligned(a.grad_ms, 8);
+    if (aligned(a.pan, 16) && aligned(a.gy, 16) && gp && gm && a.pan_ld % 4 == 0 && a.gy_ld % 4 == 0 &&
+        (b1 || a.gy_bs % 4 == 0) && a.W % 4 == 0)
+        return PATH_V4;
+    const bool gp2 = !a.grad_pan || aligned(a.grad_pan, 8);
+    if (aligned(a.pan, 8) && aligned(a.gy, 8) && gp2 && a.pan_ld % 2 == 0 && a.gy_ld % 2 == 0 &&
+        (b1 || a.gy_bs % 2 == 0))
+        return PATH_V2;
+    return PATH_SCALAR;
+}
+
+struct Tile {
+    int seg_rows = 0, wpb = 0, nc = 0;
+};
+
+struct Decomp {
+    int32_t nstrips = 0, nseg = 0, units = 0;
+};
+
+bool decompose(int64_t H, int64_t W, int nc, int seg_rows, Decomp *d) {
+    const int64_t W2 = W / 2, H2 = H / 2;
+    const int64_t cols = 64 * nc;
+    const int64_t ns = (W2 + cols - 1) / cols;
+    const int64_t ng = (H2 + seg_rows - 1) / seg_rows;
+    if (ns * ng > INT32_MAX) return false;
+    d->nstrips = (int32_t)ns;
+    d->nseg = (int32_t)ng;
+    d->units = (int32_t)(ns * ng);
+    return true;
+}
+
+// Default: 4 waves per workgroup, 2 coefficient columns per lane where the
+// 128-bit path applies, and units of 32 coefficient rows, shortened until the
+// launch has at least 8192 wavefronts (32 per CU on 256 CUs) or 4 rows.
+Tile default_tile(int64_t H, int64_t W, Path path) {
+    Tile t;
+    t.nc = path_nc(path);
+    t.wpb = 4;
+    t.seg_rows = 32;
+    Decomp d;
+    while (t.seg_rows > 4 && decompose(H, W, t.nc, t.seg_rows, &d) && d.units < 8192) t.seg_rows /= 2;
+    return t;
+}
+
+int ceil_log2(int64_t v) {
+    int k = 0;
+    while ((int64_t(1) << k) < v) ++k;
+    return k;
+}
+
+std::string tune_key(int kind, int wavelet, int64_t H, int64_t W, int64_t B, Path path) {
+    char buf[96];
+    std::snprintf(buf, sizeof(buf), "%c%d_h%d_w%d_b%d_p%d", kind == 0 ? 'f' : 'a', wavelet, ceil_log2(H),
+                  ceil_log2(W), (int)std::min<int64_t>(B, 8), (int)path);
+    return buf;
+}
+
+Filters make_filters() {
+    // Eq. 7-8: h_i = (1 + 2i + sqrt3)/(4 sqrt2), h_{i+2} = (3 - 2i - sqrt3)/(4 sqrt2),
+    // evaluated in double and rounded once to float.
+    const double r3 = std::sqrt(3.0), den = 4.0 * std::sqrt(2.0);
+    Filters f;
+    for (int i = 0; i < 2; ++i) {
+        f.h[i] = (float)((1.0 + 2.0 * i + r3) / den);
+        f.h[i + 2] = (float)((3.0 - 2.0 * i - r3) / den);
+    }
+    return f;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- context
+
+struct dwt_fuse_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string last_error;
+    Filters filt{};
+    int num_cu = 256;
+    std::string device_name;
+    // tiling
+    bool tuning = false;
+    Tile forced;
+    std::map<std::string, Tile> table;
+    // backward workspace
+    float *ws = nullptr;
+    size_t ws_bytes = 0;
+    // batched
+    BatchScene *d_scenes = nullptr;
+    BatchScene *h_scenes = nullptr;  // pinned staging
+    size_t scenes_cap = 0;
+    uint32_t *d_counters = nullptr;
+    hipEvent_t staged = nullptr;     // last upload of h_scenes finished
+    bool staged_pending = false;
+    std::map<std::string, hipGraphExec_t> graphs;
+    hipStream_t cap_stream = nullptr;  // capture only (the null stream cannot be captured)
+    int batched_grid = 0;
+};
+
+namespace {
+
+dwt_fuse_status fail(dwt_fuse_ctx *c, dwt_fuse_status st, const std::string &msg) {
+    if (c) c->last_error = msg;
+    return st;
+}
+
+dwt_fuse_status hip_fail(dwt_fuse_ctx *c, hipError_t e, const char *what) {
+    return fail(c, DWT_FUSE_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+dwt_fuse_status use_device(dwt_fuse_ctx *c) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(c, e, "hipGetDevice");
+    if (cur != c->device) {
+        e = hipSetDevice(c->device);
+        if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+    }
+    return DWT_FUSE_OK;
+}
+
+void clear_graphs(dwt_fuse_ctx *c) {
+    for (auto &kv : c->graphs) hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+}
+
+FuseParams make_params(const RunArgs &a, Path path, const Tile &t, const Decomp &d) {
+    FuseParams p{};
+    p.pan = a.pan;
+    p.ms = a.ms;
+    p.gain = a.gain;
+    p.out = const_cast<float *>(a.out);
+    p.pan_ld = a.pan_ld;
+    p.ms_ld = a.ms_ld;
+    p.ms_bs = a.ms_bs;
+    p.out_ld = a.out_ld;
+    p.out_bs = a.out_bs;
+    p.H = (int32_t)a.H;
+    p.W = (int32_t)a.W;
+    p.B = (int32_t)a.B;
+    p.seg_rows = t.seg_rows;
+    p.nseg = d.nseg;
+    p.units = d.units;
+    p.wavelet = a.wavelet;
+    p.path = path;
+    return p;
+}
+
+Tile apply_forced(const dwt_fuse_ctx *c, Tile t, Path path) {
+    if (c->forced.seg_rows > 0) t.seg_rows = c->forced.seg_rows;
+    if (c->forced.wpb > 0) t.wpb = c->forced.wpb;
+    if (c->forced.nc > 0) t.nc = std::min(c->forced.nc, path_nc(path));
+    return t;
+}
+
+Path path_for_nc(Path path, int nc) { return (path == PATH_V4 && nc == 1) ? PATH_V2 : path; }
+
+// Time one forward launch configuration on the caller's buffers (ms, median of 3).
+float time_fuse(dwt_fuse_ctx *c, const RunArgs &a, Path path, const Tile &t) {
+    Decomp d;
+    if (!decompose(a.H, a.W, t.nc, t.seg_rows, &d)) return 1e30f;
+    const Path pp = path_for_nc(path, t.nc);
+    const FuseParams p = make_params(a, pp, t, d);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return 1e30f;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return 1e30f;
+    }
+    float best[3] = {1e30f, 1e30f, 1e30f};
+    launch_fuse(p, c->filt, t.wpb, c->stream);  // warm-up
+    for (int k = 0; k < 3; ++k) {
+        hipEventRecord(e0, c->stream);
+        launch_fuse(p, c->filt, t.wpb, c->stream);
+        hipEventRecord(e1, c->stream);
+        hipEventSynchronize(e1);
+        float ms = 0;
+        hipEventElapsedTime(&ms, e0, e1);
+        best[k] = ms;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    std::sort(best, best + 3);
+    return best[1];
+}
+
+Tile tune_fuse(dwt_fuse_ctx *c, const RunArgs &a, Path path) {
+    Tile bestt = default_tile(a.H, a.W, path);
+    float bestms = time_fuse(c, a, path, bestt);
+    const int ncs[2] = {2, 1};
+    for (int nc : ncs) {
+        if (nc > path_nc(path)) continue;
+        for (int seg : {4, 8, 16, 32, 64}) {
+            for (int wpb : {1, 2, 4}) {
+                Tile t;
+                t.nc = nc;
+                t.seg_rows = seg;
+                t.wpb = wpb;
+                const float ms = time_fuse(c, a, path, t);
+                if (ms < bestms) {
+                    bestms = ms;
+                    bestt = t;
+                }
+            }
+        }
+    }
+    if (std::getenv("DWT_FUSE_LOG"))
+        std::fprintf(stderr, "[dwt_fuse] tuned %s: seg_rows=%d wpb=%d nc=%d (%.3f ms)\n",
+                     tune_key(0, a.wavelet, a.H, a.W, a.B, path).c_str(), bestt.seg_rows, bestt.wpb, bestt.nc,
+                     bestms);
+    return bestt;
+}
+
+Tile tile_for_run(dwt_fuse_ctx *c, const RunArgs &a, Path path, bool allow_tune) {
+    const std::string key = tune_key(0, a.wavelet, a.H, a.W, a.B, path);
+    auto it = c->table.find(key);
+    Tile t;
+    if (it != c->table.end()) {
+        t = it->second;
+    } else if (c->tuning && allow_tune) {
+        t = tune_fuse(c, a, path);
+        c->table[key] = t;
+    } else {
+        t = default_tile(a.H, a.W, path);
+    }
+    return apply_forced(c, t, path);
+}
+
+dwt_fuse_status ensure_ws(dwt_fuse_ctx *c, size_t bytes) {
+    if (bytes <= c->ws_bytes) return DWT_FUSE_OK;
+    if (c->ws) {
+        hipStreamSynchronize(c->stream);
+        hipFree(c->ws);
+        c->ws = nullptr;
+        c->ws_bytes = 0;
+    }
+    const size_t nb = std::max<size_t>(bytes, 1 << 16);
+    if (hipMalloc(reinterpret_cast<void **>(&c->ws), nb) != hipSuccess) {
+        c->ws = nullptr;
+        return fail(c, DWT_FUSE_E_NOMEM, "workspace allocation failed");
+    }
+    c->ws_bytes = nb;
+    return DWT_FUSE_OK;
+}
+
+dwt_fuse_status ensure_batch_tables(dwt_fuse_ctx *c, size_t n) {
+    if (!c->d_counters) {
+        const size_t bytes = (kQueues + 1) * kQueueStride * sizeof(uint32_t);
+        if (hipMalloc(reinterpret_cast<void **>(&c->d_counters), bytes) != hipSuccess) {
+            c->d_counters = nullptr;
+            return fail(c, DWT_FUSE_E_NOMEM, "counter allocation failed");
+        }
+        hipError_t e = hipMemsetAsync(c->d_counters, 0, bytes, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "hipMemsetAsync");
+    }
+    if (!c->staged) {
+        hipError_t e = hipEventCreateWithFlags(&c->staged, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(c, e, "hipEventCreate");
+    }
+    if (n <= c->scenes_cap) return DWT_FUSE_OK;
+    // Growing moves the device table: captured graphs point at the old one.
+    hipStreamSynchronize(c->stream);
+    clear_graphs(c);
+    if (c->d_scenes) hipFree(c->d_scenes);
+    if (c->h_scenes) hipHostFree(c->h_scenes);
+    c->d_scenes = nullptr;
+    c->h_scenes = nullptr;
+    c->scenes_cap = 0;
+    const size_t cap = std::max<size_t>(n, 128);
+    if (hipMalloc(reinterpret_cast<void **>(&c->d_scenes), cap * sizeof(BatchScene)) != hipSuccess) {
+        c->d_scenes = nullptr;
+        return fail(c, DWT_FUSE_E_NOMEM, "scene table allocation failed");
+    }
+    if (hipHostMalloc(reinterpret_cast<void **>(&c->h_scenes), cap * sizeof(BatchScene), hipHostMallocDefault) !=
+        hipSuccess) {
+        c->h_scenes = nullptr;
+        return fail(c, DWT_FUSE_E_NOMEM, "pinned staging allocation failed");
+    }
+    c->scenes_cap = cap;
+    c->staged_pending = false;
+    return DWT_FUSE_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- C ABI
+
+extern "C" {
+
+const char *dwt_fuse_status_str(dwt_fuse_status s) {
+    switch (s) {
+        case DWT_FUSE_OK: return "ok";
+        case DWT_FUSE_E_NULL: return "null pointer";
+        case DWT_FUSE_E_SHAPE: return "invalid shape";
+        case DWT_FUSE_E_WAVELET: return "unknown wavelet";
+        case DWT_FUSE_E_STRIDE: return "invalid pitch or band stride";
+        case DWT_FUSE_E_ALIAS: return "output overlaps an input";
+        case DWT_FUSE_E_NOMEM: return "out of device memory";
+        case DWT_FUSE_E_DEVICE: return "HIP device error";
+        case DWT_FUSE_E_STATE: return "invalid context state";
+    }
+    return "unknown status";
+}
+
+const char *dwt_fuse_last_error(const dwt_fuse_ctx *ctx) { return ctx ? ctx->last_error.c_str() : ""; }
+
+dwt_fuse_status dwt_fuse_check_run(dwt_fuse_wavelet wavelet, int64_t H, int64_t W, int64_t B, const float *pan,
+                                   int64_t pan_ld, const float *ms, int64_t ms_ld, int64_t ms_band_stride,
+                                   const float *gain, const float *out, int64_t out_ld,
+                                   int64_t out_band_stride) {
+    const RunArgs a{(int)wavelet, H, W, B, pan, pan_ld, ms, ms_ld, ms_band_stride, gain, out, out_ld,
+                    out_band_stride};
+    return check_run_args(a, nullptr, nullptr);
+}
+
+dwt_fuse_status dwt_fuse_check_batched(const dwt_fuse_item *items, int64_t n) {
+    return check_batch(items, n, nullptr);
+}
+
+dwt_fuse_status dwt_fuse_check_backward(dwt_fuse_wavelet wavelet, int64_t H, int64_t W, int64_t B,
+                                        const float *pan, int64_t pan_ld, const float *gain,
+                                        const float *grad_out, int64_t go_ld, int64_t go_band_stride,
+                                        const float *grad_pan, const float *grad_ms, const float *grad_gain) {
+    const BwdArgs a{(int)wavelet, H, W, B, pan, pan_ld, gain, grad_out, go_ld, go_band_stride,
+                    grad_pan, grad_ms, grad_gain};
+    return check_bwd_args(a, nullptr);
+}
+
+dwt_fuse_status dwt_fuse_create(dwt_fuse_ctx **ctx, int device, void *hip_stream) {
+    if (!ctx) return DWT_FUSE_E_NULL;
+    *ctx = nullptr;
+    try {
+        int n = 0;
+        if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return DWT_FUSE_E_DEVICE;
+        if (hipSetDevice(device) != hipSuccess) return DWT_FUSE_E_DEVICE;
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, device) != hipSuccess) return DWT_FUSE_E_DEVICE;
+        dwt_fuse_ctx *c = new dwt_fuse_ctx();
+        c->device = device;
+        c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+        c->filt = make_filters();
+        c->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+        c->device_name = prop.gcnArchName;
+        if (const char *f = std::getenv("DWT_FUSE_FORCE_TILE")) {
+            int a = 0, b = 0, d = 0;
+            if (std::sscanf(f, "%d,%d,%d", &a, &b, &d) >= 1) {
+                c->forced.seg_rows = a;
+                c->forced.wpb = b;
+                c->forced.nc = d;
+            }
+        }
+        if (const char *f = std::getenv("DWT_FUSE_TUNE_CACHE")) dwt_fuse_tune_load(c, f);
+        *ctx = c;
+        return DWT_FUSE_OK;
+    } catch (const std::bad_alloc &) {
+        return DWT_FUSE_E_NOMEM;
+    } catch (...) {
+        return DWT_FUSE_E_STATE;
+    }
+}
+
+void dwt_fuse_destroy(dwt_fuse_ctx *ctx) {
+    if (!ctx) return;
+    try {
+        int cur = -1;
+        hipGetDevice(&cur);
+        hipSetDevice(ctx->device);
+        clear_graphs(ctx);
+        if (ctx->ws) hipFree(ctx->ws);
+        if (ctx->d_scenes) hipFree(ctx->d_scenes);
+        if (ctx->h_scenes) hipHostFree(ctx->h_scenes);
+        if (ctx->d_counters) hipFree(ctx->d_counters);
+        if (ctx->staged) hipEventDestroy(ctx->staged);
+        if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
+        if (cur >= 0) hipSetDevice(cur);
+    } catch (...) {
+    }
+    delete ctx;
+}
+
+dwt_fuse_status dwt_fuse_set_stream(dwt_fuse_ctx *ctx, void *hip_stream) {
+    if (!ctx) return DWT_FUSE_E_NULL;
+    ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    return DWT_FUSE_OK;
+}
+
+dwt_fuse_status dwt_fuse_set_tuning(dwt_fuse_ctx *ctx, int enable) {
+    if (!ctx) return DWT_FUSE_E_NULL;
+    ctx->tuning = enable != 0;
+    return DWT_FUSE_OK;
+}
+
+dwt_fuse_status dwt_fuse_force_tile(dwt_fuse_ctx *ctx, int seg_rows, int wpb, int nc) {
+    if (!ctx) return DWT_FUSE_E_NULL;
+    if (seg_rows < 0 || seg_rows > 4096 || wpb < 0 || wpb > 4 || nc < 0 || nc > 2)
+        return fail(ctx, DWT_FUSE_E_SHAPE, "tile out of range (seg_rows <= 4096, wpb <= 4, nc <= 2)");
+    ctx->forced.seg_rows = seg_rows;
+    ctx->forced.wpb = wpb;
+    ctx->forced.nc = nc;
+    return DWT_FUSE_OK;
+}
+
+dwt_fuse_status dwt_fuse_tune_save(const dwt_fuse_ctx *ctx, const char *path) {
+    if (!ctx || !path) return DWT_FUSE_E_NULL;
+    FILE *f = std::fopen(path, "w");
+    if (!f) return DWT_FUSE_E_STATE;
+    std::fprintf(f, "dwt_fuse_tune 1 %s %s\n", DWT_FUSE_BUILD_ID, ctx->device_name.c_str());
+    for (const auto &kv : ctx->table)
+        std::fprintf(f, "%s %d %d %d\n", kv.first.c_str(), kv.second.seg_rows, kv.second.wpb, kv.second.nc);
+    std::fclose(f);
+    return DWT_FUSE_OK;
+}
+
+dwt_fuse_status dwt_fuse_tune_load(dwt_fuse_ctx *ctx, const char *path) {
+    if (!ctx || !path) return DWT_FUSE_E_NULL;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return fail(ctx, DWT_FUSE_E_STATE, "cannot open tuning file");
+    char magic[32] = {0}, build[128] = {0}, dev[128] = {0};
+    int ver = 0;
+    std::map<std::string, Tile> tab;
+    bool ok = std::fscanf(f, "%31s %d %127s %127s", magic, &ver, build, dev) == 4 &&
+              std::strcmp(magic, "dwt_fuse_tune") == 0 && ver == 1 && std::strcmp(build, DWT_FUSE_BUILD_ID) == 0 &&
+              ctx->device_name == dev;
+    while (ok) {
+        char key[96] = {0};
+        Tile t;
+        const int r = std::fscanf(f, "%95s %d %d %d", key, &t.seg_rows, &t.wpb, &t.nc);
+        if (r == EOF) break;
+        if (r != 4 || t.seg_rows < 1 || t.seg_rows > 4096 || t.wpb < 1 || t.wpb > 4 || t.nc < 1 || t.nc > 2) {
+            ok = false;
+            break;
+        }
+        tab[key] = t;
+    }
+    std::fclose(f);
+    if (!ok) return fail(ctx, DWT_FUSE_E_STATE, "tuning file does not match this build/device or is corrupt; ignored");
+    for (const auto &kv : tab) ctx->table[kv.first] = kv.second;
+    return DWT_FUSE_OK;
+}
+
+dwt_fuse_status dwt_fuse_run(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet, int64_t H, int64_t W, int64_t B,
+                             const float *pan, int64_t pan_ld, const float *ms, int64_t ms_ld,
+                             int64_t ms_band_stride, const float *gain, float *out, int64_t out_ld,
+                             int64_t out_band_stride) {
+    if (!ctx) return DWT_FUSE_E_NULL;
+    try {
+        const RunArgs a{(int)wavelet, H, W, B, pan, pan_ld, ms, ms_ld, ms_band_stride, gain, out, out_ld,
+                        out_band_stride};
+        std::string err;
+        dwt_fuse_status st = check_run_args(a, nullptr, &err);
+        if (st) return fail(ctx, st, err);
+        if ((st = use_device(ctx))) return st;
+        const Path path = choose_path(a);
+        const Tile t = tile_for_run(ctx, a, path, true);
+        Decomp d;
+        if (!decompose(H, W, t.nc, t.seg_rows, &d)) return fail(ctx, DWT_FUSE_E_SHAPE, "too many work units");
+        const FuseParams p = make_params(a, path_for_nc(path, t.nc), t, d);
+        const hipError_t e = launch_fuse(p, ctx->filt, t.wpb, ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "fuse launch");
+        return DWT_FUSE_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(ctx, DWT_FUSE_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(ctx, DWT_FUSE_E_STATE, "unexpected exception");
+    }
+}
+
+dwt_fuse_status dwt_fuse_run_batched(dwt_fuse_ctx *ctx, const dwt_fuse_item *items, int64_t n, uint32_t flags) {
+    if (!ctx) return DWT_FUSE_E_NULL;
+    try {
+        std::string err;
+        dwt_fuse_status st = check_batch(items, n, &err);
+        if (st) return fail(ctx, st, err);
+        if (n == 0) return DWT_FUSE_OK;
+        if ((st = use_device(ctx))) return st;
+        if ((st = ensure_batch_tables(ctx, (size_t)n))) return st;
+
+        // Tuned tiles per size class (timed with the per-image kernel on the
+        // first item of each class), then the work-unit layout.
+        std::vector<BatchScene> sc((size_t)n);
+        std::vector<double> unit_bytes((size_t)n);
+        int64_t total = 0;
+        std::string sig;
+        sig.reserve((size_t)n * 48);
+        for (int64_t i = 0; i < n; ++i) {
+            const RunArgs a = item_args(items[i]);
+            const Path path = choose_path(a);
+            Tile t = tile_for_run(ctx, a, path, true);
+            Decomp d;
+            if (!decompose(a.H, a.W, t.nc, t.seg_rows, &d)) return fail(ctx, DWT_FUSE_E_SHAPE, "too many work units");
+            sc[i].p = make_params(a, path_for_nc(path, t.nc), t, d);
+            sc[i].unit_begin = (int32_t)total;
+            sc[i].pad_ = 0;
+            total += d.units;
+            if (total > INT32_MAX) return fail(ctx, DWT_FUSE_E_SHAPE, "too many work units in batch");
+            unit_bytes[i] = (double)a.H * a.W * (4.0 + 5.0 * a.B) / std::max(1, d.units);
+            char buf[160];
+            std::snprintf(buf, sizeof(buf), "%d.%lld.%lld.%lld.%lld.%lld.%lld.%lld.%lld.%d.%d.%d|", a.wavelet,
+                          (long long)a.H, (long long)a.W, (long long)a.B, (long long)a.pan_ld, (long long)a.ms_ld,
+                          (long long)a.ms_bs, (long long)a.out_ld, (long long)a.out_bs, (int)sc[i].p.path,
+                          t.seg_rows, a.gain ? 1 : 0);
+            sig += buf;
+        }
+        // 8 contiguous queues of about equal bytes.
+        BatchQueues q;
+        {
+            double all = 0;
+            for (int64_t i = 0; i < n; ++i) all += unit_bytes[i] * sc[i].p.units;
+            int qi = 0;
+            double acc = 0;
+            q.begin[0] = 0;
+            for (int64_t i = 0; i < n && qi < kQueues - 1; ++i) {
+                for (int32_t u = 0; u < sc[i].p.units && qi < kQueues - 1; ++u) {
+                    acc += unit_bytes[i];
+                    if (acc >= all * (qi + 1) / kQueues) {
+                        q.end[qi] = sc[i].unit_begin + u + 1;
+                        ++qi;
+                        q.begin[qi] = sc[i].unit_begin + u + 1;
+                    }
+                }
+            }
+            for (; qi < kQueues; ++qi) {
+                q.end[qi] = (int32_t)total;
+                if (qi + 1 < kQueues) q.begin[qi + 1] = (int32_t)total;
+            }
+        }
+        if (ctx->batched_grid == 0) ctx->batched_grid = ctx->num_cu * batched_blocks_per_cu();
+        const int grid = std::max(kQueues, (int)std::min<int64_t>(ctx->batched_grid, (total + 3) / 4 + kQueues));
+
+        // Stage the scene table (wait until the previous upload has left the buffer).
+        if (ctx->staged_pending) {
+            hipError_t e = hipEventSynchronize(ctx->staged);
+            if (e != hipSuccess) return hip_fail(ctx, e, "hipEventSynchronize");
+        }
+        std::memcpy(ctx->h_scenes, sc.data(), sizeof(BatchScene) * (size_t)n);
+        hipError_t e = hipMemcpyAsync(ctx->d_scenes, ctx->h_scenes, sizeof(BatchScene) * (size_t)n,
+                                      hipMemcpyHostToDevice, ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "scene table upload");
+        e = hipEventRecord(ctx->staged, ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipEventRecord");
+        ctx->staged_pending = true;
+
+        if (!(flags & DWT_FUSE_GRAPH)) {
+            e = launch_fuse_batched(ctx->d_scenes, (int)n, q, ctx->d_counters, grid, ctx->filt, ctx->stream);
+            if (e != hipSuccess) return hip_fail(ctx, e, "batched launch");
+            return DWT_FUSE_OK;
+        }
+        char gb[64];
+        std::snprintf(gb, sizeof(gb), "#%d", grid);
+        sig += gb;
+        auto it = ctx->graphs.find(sig);
+        if (it == ctx->graphs.end()) {
+            if (!ctx->cap_stream) {
+                e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking);
+                if (e != hipSuccess) {
+                    ctx->cap_stream = nullptr;
+                    return hip_fail(ctx, e, "hipStreamCreate");
+                }
+            }
+            // Capture records the launch without running it; the graph is
+            // then launched on the caller's stream, after the table upload.
+            hipGraph_t g = nullptr;
+            e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamBeginCapture");
+            const hipError_t le =
+                launch_fuse_batched(ctx->d_scenes, (int)n, q, ctx->d_counters, grid, ctx->filt, ctx->cap_stream);
+            e = hipStreamEndCapture(ctx->cap_stream, &g);
+            if (le != hipSuccess) {
+                if (g) hipGraphDestroy(g);
+                return hip_fail(ctx, le, "batched launch (capture)");
+            }
+            if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamEndCapture");
+            hipGraphExec_t ge = nullptr;
+            e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+            hipGraphDestroy(g);
+            if (e != hipSuccess) return hip_fail(ctx, e, "hipGraphInstantiate");
+            if (ctx->graphs.size() >= 64) clear_graphs(ctx);
+            it = ctx->graphs.emplace(sig, ge).first;
+        }
+        e = hipGraphLaunch(it->second, ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipGraphLaunch");
+        return DWT_FUSE_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(ctx, DWT_FUSE_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(ctx, DWT_FUSE_E_STATE, "unexpected exception");
+    }
+}
+
+dwt_fuse_status dwt_fuse_backward(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet, int64_t H, int64_t W, int64_t B,
+                                  const float *pan, int64_t pan_ld, const float *gain, const float *grad_out,
+                                  int64_t go_ld, int64_t go_band_stride, float *grad_pan, float *grad_ms,
+                                  float *grad_gain) {
+    if (!ctx) return DWT_FUSE_E_NULL;
+    try {
+        const BwdArgs a{(int)wavelet, H, W, B, pan, pan_ld, gain, grad_out, go_ld, go_band_stride,
+                        grad_pan, grad_ms, grad_gain};
+        std::string err;
+        dwt_fuse_status st = check_bwd_args(a, &err);
+        if (st) return fail(ctx, st, err);
+        if (!grad_pan && !grad_ms && !grad_gain) return DWT_FUSE_OK;
+        if ((st = use_device(ctx))) return st;
+        const Path path = choose_bwd_path(a);
+        Tile t = default_tile(H, W, path);
+        {
+            auto it = ctx->table.find(tune_key(1, a.wavelet, H, W, B, path));
+            if (it != ctx->table.end()) t = it->second;
+        }
+        t = apply_forced(ctx, t, path);
+        const Path pp = path_for_nc(path, t.nc);
+        Decomp d;
+        if (!decompose(H, W, t.nc, t.seg_rows, &d)) return fail(ctx, DWT_FUSE_E_SHAPE, "too many work units");
+        float *partial = nullptr;
+        if (grad_gain) {
+            if ((st = ensure_ws(ctx, sizeof(float) * (size_t)d.units * (size_t)B))) return st;
+            partial = ctx->ws;
+        }
+        const int maxb = adjoint_max_bands();
+        for (int64_t b0 = 0; b0 < B; b0 += maxb) {
+            const int64_t nb = std::min<int64_t>(maxb, B - b0);
+            AdjParams p{};
+            p.pan = pan;
+            p.gain = gain ? gain + b0 : nullptr;
+            p.gy = grad_out + b0 * go_band_stride;
+            p.grad_pan = grad_pan;
+            p.grad_ms = grad_ms ? grad_ms + b0 * (H / 2) * (W / 2) : nullptr;
+            p.partial = partial ? partial + b0 : nullptr;
+            p.pan_ld = pan_ld;
+            p.gy_ld = go_ld;
+            p.gy_bs = go_band_stride;
+            p.H = (int32_t)H;
+            p.W = (int32_t)W;
+            p.B = (int32_t)nb;
+            p.seg_rows = t.seg_rows;
+            p.nseg = d.nseg;
+            p.units = d.units;
+            p.wavelet = a.wavelet;
+            p.path = pp;
+            p.pstride = (int32_t)B;
+            p.accumulate = b0 > 0 ? 1 : 0;
+            const hipError_t e = launch_adjoint(p, ctx->filt, t.wpb, ctx->stream);
+            if (e != hipSuccess) return hip_fail(ctx, e, "adjoint launch");
+        }
+        if (grad_gain) {
+            const hipError_t e = launch_gain_reduce(partial, d.units, (int)B, grad_gain, ctx->stream);
+            if (e != hipSuccess) return hip_fail(ctx, e, "gain reduction launch");
+        }
+        return DWT_FUSE_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(ctx, DWT_FUSE_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(ctx, DWT_FUSE_E_STATE, "unexpected exception");
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,89 @@
+// Internal interface between the host library (dwt_fuse_api.cpp) and the
+// gfx950 kernels (fuse_kernels.hip, adjoint_kernels.hip).  Not installed.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dwtf {
+
+// Column layout of one lane: NC coefficient columns = 2*NC output columns.
+//   PATH_V4     NC = 2, 128-bit PAN/out rows, 64-bit MS rows (all aligned)
+//   PATH_V2     NC = 1, 64-bit PAN/out rows, scalar MS
+//   PATH_SCALAR NC = 1, scalar everything (odd pointer offsets or pitches)
+enum Path : int32_t { PATH_V4 = 0, PATH_V2 = 1, PATH_SCALAR = 2 };
+
+inline int path_nc(Path p) { return p == PATH_V4 ? 2 : 1; }
+
+// One scene as the kernels see it.  A work unit is one wavefront (64 lanes)
+// covering a strip of 64*NC coefficient columns and seg_rows coefficient
+// rows (2*seg_rows output rows) of every band.
+struct FuseParams {
+    const float *pan;
+    const float *ms;
+    const float *gain;  // NULL = all ones
+    float *out;
+    int64_t pan_ld, ms_ld, ms_bs, out_ld, out_bs;
+    int32_t H, W, B;
+    int32_t seg_rows;  // coefficient rows per work unit
+    int32_t nseg;      // work units per strip = ceil((H/2) / seg_rows)
+    int32_t units;     // nstrips * nseg
+    int32_t wavelet;   // 0 Haar, 1 D4
+    int32_t path;      // Path
+};
+
+// Daubechies-4 low-pass taps (Eq. 7-8), rounded once from double.
+struct Filters {
+    float h[4];
+};
+
+// Batched (persistent) launch: device table of scenes plus 8 work queues,
+// one per XCD, each a contiguous range of the global unit index.
+struct BatchScene {
+    FuseParams p;
+    int32_t unit_begin;  // first global unit index of this scene
+    int32_t pad_;
+};
+
+constexpr int kQueues = 8;           // = XCDs of an MI355X
+constexpr int kQueueStride = 64;     // uint32 slots between counters (256 B)
+
+struct BatchQueues {
+    int32_t begin[kQueues];
+    int32_t end[kQueues];
+};
+
+// Adjoint.  grad_ms / grad_pan are contiguous; grad-gain partial sums are
+// written per (work unit, band) into `partial` and reduced in a fixed order.
+struct AdjParams {
+    const float *pan;
+    const float *gain;
+    const float *gy;  // dL/d(out)
+    float *grad_pan;  // may be NULL
+    float *grad_ms;   // may be NULL
+    float *partial;   // units * B floats, may be NULL (no grad_gain)
+    int64_t pan_ld, gy_ld, gy_bs;
+    int32_t H, W, B;
+    int32_t seg_rows, nseg, units;
+    int32_t wavelet, path;
+    int32_t pstride;     // floats between consecutive units' partials
+    int32_t accumulate;  // 1: add into grad_pan instead of overwriting
+};
+
+hipError_t launch_fuse(const FuseParams &p, const Filters &f, int waves_per_block, hipStream_t s);
+
+hipError_t launch_fuse_batched(const BatchScene *d_scenes, int nscenes, const BatchQueues &q,
+                               uint32_t *d_counters, int grid, const Filters &f, hipStream_t s);
+
+// Blocks per CU the batched kernel can keep resident (for sizing its grid).
+int batched_blocks_per_cu();
+
+hipError_t launch_adjoint(const AdjParams &p, const Filters &f, int waves_per_block, hipStream_t s);
+
+// grad_gain[b] = sum_u partial[u * B + b], b < B, fixed order.
+hipError_t launch_gain_reduce(const float *partial, int units, int B, float *grad_gain, hipStream_t s);
+
+// Bands one adjoint launch handles (the host splits larger band counts).
+int adjoint_max_bands();
+
+}  // namespace dwtf

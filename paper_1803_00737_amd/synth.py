@@ -2,8 +2,8 @@
 
 The paper fuses Landsat-7 scenes of the Donetsk region (section 4); those are
 not available here, so every workload is synthetic.  This module only draws
-inputs: it contains none of the wavelet arithmetic and is shared by the tests,
-the benchmark and the CPU oracle's callers.
+inputs: it contains none of the wavelet arithmetic and is shared by the tests
+and the benchmark.
 
 Recipe (all counts and noise levels fixed; amplitudes are this project's
 choice):
@@ -28,7 +28,7 @@ this is what large scenes use, since drawing 10^8 normals on the host is slow.
 from __future__ import annotations
 
 import math
-from dataclasses import dataclass, field
+from dataclasses import dataclass
 from typing import List, Optional
 
 import numpy as np

@@ -1,0 +1,163 @@
+"""Adjoint kernel: gradients w.r.t. PAN, MS and the per-band detail gain,
+against the FP64 oracle's transpose, a dot-product test, FP64 central finite
+differences of an MSE loss on 32x32 crops, and autograd end to end.
+
+Tolerances (float32 sums of at most 16 terms per gradient pixel; gain
+gradients are sums over the whole image, accumulated in float32 per lane
+and per wavefront, then in FP64 across work units):
+  grad_pan, grad_ms: max-abs <= 1e-5 * max(1, max|reference|) * 16
+  grad_gain:         |err| <= 1e-5 * sum|y_b * D| + 1e-6
+"""
+import numpy as np
+import pytest
+
+from gpu_helpers import int_scene, require_gpu, say, strided_view, to_dev, torch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return require_gpu()
+
+
+@pytest.fixture(scope="module")
+def fz():
+    from paper_1803_00737_amd import api
+
+    return api
+
+
+def detail_part(oracle, w, pan):
+    """PAN minus its LL-only reconstruction (FP64, via the oracle)."""
+    ms_ll = oracle.dwt2_fwd(w, pan)[: pan.shape[0] // 2, : pan.shape[1] // 2]
+    return pan - oracle.fuse(w, pan, ms_ll[None], [0.0])[0]
+
+
+def check_grads(oracle, w, pan, gy, gain, got):
+    gp, gm, gg = got
+    rp, rm, rg = oracle.fuse_backward(w, pan.astype(np.float64), None if gain is None else gain.astype(np.float64),
+                                      gy.astype(np.float64))
+    tol_p = 16e-5 * max(1.0, np.abs(rp).max())
+    tol_m = 16e-5 * max(1.0, np.abs(rm).max())
+    assert np.abs(gp - rp).max() <= tol_p
+    assert np.abs(gm - rm).max() <= tol_m
+    D = detail_part(oracle, w, pan.astype(np.float64))
+    for b in range(gy.shape[0]):
+        bound = 1e-5 * np.abs(gy[b] * D).sum() + 1e-6
+        assert abs(gg[b] - rg[b]) <= bound, (b, gg[b], rg[b], bound)
+
+
+SHAPES = [(2, 2), (4, 6), (34, 70), (66, 1030), (130, 258), (64, 4070)]
+
+
+@pytest.mark.parametrize("H,W", SHAPES)
+@pytest.mark.parametrize("wavelet", ["haar", "d4"])
+@pytest.mark.parametrize("B", [1, 4, 10])
+def test_adjoint_matches_oracle(dev, fz, oracle, wavelet, H, W, B):
+    rng = np.random.default_rng(H + W + B)
+    pan, _ = int_scene(rng, H, W, 1)
+    gy = rng.normal(size=(B, H, W)).astype(np.float32)
+    gain = rng.uniform(0.5, 1.5, B).astype(np.float32)
+    say("adjoint", wavelet, H, W, B)
+    got = fz.fuse_backward(to_dev(pan, dev), to_dev(gy, dev), wavelet, to_dev(gain, dev))
+    check_grads(oracle, wavelet, pan, gy, gain, [t.cpu().numpy() for t in got])
+
+
+@pytest.mark.parametrize("wavelet", ["haar", "d4"])
+@pytest.mark.parametrize("pad,offset", [(4, 0), (2, 2), (1, 1)])
+def test_adjoint_paths(dev, fz, oracle, wavelet, pad, offset):
+    rng = np.random.default_rng(pad + offset)
+    H, W, B = 34, 134, 3
+    pan, _ = int_scene(rng, H, W, 1)
+    gy = rng.normal(size=(B, H, W)).astype(np.float32)
+    say("adjoint paths", wavelet, pad, offset)
+    got = fz.fuse_backward(strided_view(pan, dev, pad, offset), strided_view(gy, dev, pad, offset), wavelet)
+    check_grads(oracle, wavelet, pan, gy, None, [t.cpu().numpy() for t in got])
+
+
+@pytest.mark.parametrize("wavelet", ["haar", "d4"])
+def test_dot_product(dev, fz, wavelet):
+    """<J x, y> = <x, J^T y> for the map (pan, ms) -> out at fixed gains."""
+    rng = np.random.default_rng(11)
+    H, W, B = 66, 262, 3
+    pan = to_dev(rng.normal(size=(H, W)).astype(np.float32), dev)
+    ms = to_dev(rng.normal(size=(B, H // 2, W // 2)).astype(np.float32), dev)
+    y = to_dev(rng.normal(size=(B, H, W)).astype(np.float32), dev)
+    gain = to_dev(rng.uniform(0.5, 1.5, B).astype(np.float32), dev)
+    say("dot product", wavelet)
+    out = fz.fuse(pan, ms, wavelet, gain)
+    gp, gm, _ = fz.fuse_backward(pan, y, wavelet, gain, need_gain=False)
+    lhs = (out.double() * y.double()).sum().item()
+    rhs = (pan.double() * gp.double()).sum().item() + (ms.double() * gm.double()).sum().item()
+    assert abs(lhs - rhs) <= 1e-5 * (abs(lhs) + abs(rhs)) + 1e-3
+
+
+@pytest.mark.parametrize("wavelet", ["d4", "haar"])
+def test_autograd_vs_fp64_finite_differences(dev, fz, oracle, wavelet):
+    """MSE(fused, target) on a 32x32 crop (4 bands, gain initialised to 1):
+    autograd through the fused kernel and the adjoint kernel vs FP64 central
+    differences through the oracle (exact up to rounding: the loss is
+    quadratic in every input)."""
+    rng = np.random.default_rng(32)
+    H = W = 32
+    B = 4
+    pan, ms = int_scene(rng, H, W, B)
+    tgt_gain = rng.uniform(0.8, 1.2, B)
+    target = (pan[None].astype(np.float64) * tgt_gain[:, None, None])
+    p = to_dev(pan, dev).requires_grad_(True)
+    m = to_dev(ms, dev).requires_grad_(True)
+    g = torch.ones(B, device=dev, requires_grad=True)
+    say("autograd", wavelet)
+    out = fz.DwtFuseFn.apply(p, m, g, wavelet)
+    loss = ((out - to_dev(target.astype(np.float32), dev)) ** 2).mean()
+    loss.backward()
+    count = B * H * W
+
+    def L(pp, mm, gg):
+        return ((oracle.fuse(wavelet, pp, mm, gg) - target) ** 2).sum() / count
+
+    pan64, ms64, g64 = pan.astype(np.float64), ms.astype(np.float64), np.ones(B)
+    eps = 0.5
+    gp, gm, gg = p.grad.cpu().numpy(), m.grad.cpu().numpy(), g.grad.cpu().numpy()
+    for _ in range(8):
+        y, x = rng.integers(0, H, 2)
+        d = np.zeros_like(pan64)
+        d[y, x] = eps
+        fd = (L(pan64 + d, ms64, g64) - L(pan64 - d, ms64, g64)) / (2 * eps)
+        assert abs(fd - gp[y, x]) <= 1e-4 * max(1.0, abs(fd))
+        b, i, j = rng.integers(0, B), rng.integers(0, 16), rng.integers(0, 16)
+        d = np.zeros_like(ms64)
+        d[b, i, j] = eps
+        fd = (L(pan64, ms64 + d, g64) - L(pan64, ms64 - d, g64)) / (2 * eps)
+        assert abs(fd - gm[b, i, j]) <= 1e-4 * max(1.0, abs(fd))
+    for b in range(B):
+        e = np.zeros(B)
+        e[b] = 1e-3
+        fd = (L(pan64, ms64, g64 + e) - L(pan64, ms64, g64 - e)) / 2e-3
+        assert abs(fd - gg[b]) <= 1e-3 * max(1.0, abs(fd))
+
+
+def test_differentiation_workload(dev, fz, oracle):
+    """16 scenes of 2048x2048, 4 bands, D4, gain 1, MSE to PAN x U(0.8, 1.2):
+    forward + adjoint on every scene; the first two scenes are checked in
+    full against the oracle's gradients."""
+    from paper_1803_00737_amd import synth
+
+    for s in range(16):
+        seed = synth.seed_for(4, s)
+        pan, ms = synth.make_scene(2048, 2048, 4, seed, device=dev)
+        tg = torch.tensor(synth.grad_targets(4, seed), dtype=torch.float32, device=dev)
+        p = pan.clone().requires_grad_(True)
+        m = ms.clone().requires_grad_(True)
+        g = torch.ones(4, device=dev, requires_grad=True)
+        say("differentiation scene", s)
+        out = fz.DwtFuseFn.apply(p, m, g, "d4")
+        target = pan[None] * tg[:, None, None]
+        loss = ((out - target) ** 2).mean()
+        loss.backward()
+        assert torch.isfinite(p.grad).all() and torch.isfinite(m.grad).all() and torch.isfinite(g.grad).all()
+        if s < 2:
+            gy = (2.0 / out.numel()) * (out.detach() - target)
+            check_grads(oracle, "d4", pan.cpu().numpy(), gy.cpu().numpy(), np.ones(4, np.float32),
+                        [p.grad.cpu().numpy(), m.grad.cpu().numpy(), g.grad.cpu().numpy()])

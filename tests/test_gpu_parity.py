@@ -1,0 +1,229 @@
+"""GPU parity of the fused forward kernels against the FP64 oracle, through
+the C ABI (via the thin binding).
+
+Bars: Haar bit-exact on integer-valued inputs (the oracle's values are
+multiples of 1/4 and exactly representable in float32); D4 max-abs <= 1e-3 on
+the 0-255 scale.  Sizes span several work units and ragged tails (odd W/2,
+widths not a multiple of the 256/512-column strip), all three load paths
+(128-bit, 64-bit, scalar), pitched views, and the full-size workloads
+(sampled outputs checked one by one with the single-pixel oracle).
+"""
+import numpy as np
+import pytest
+
+from gpu_helpers import D4_TOL, int_scene, require_gpu, say, strided_view, to_dev, torch, ulp_diff
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(2, 2), (2, 6), (4, 10), (6, 2), (34, 70), (130, 258), (64, 4070), (200, 1030), (66, 514),
+          (258, 1026), (512, 512)]
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return require_gpu()
+
+
+@pytest.fixture(scope="module")
+def fz():
+    from paper_1803_00737_amd import api
+
+    return api
+
+
+def oracle_out(oracle, wavelet, pan, ms, gain=None):
+    return oracle.fuse(wavelet, pan.astype(np.float64), ms.astype(np.float64), gain)
+
+
+@pytest.mark.parametrize("H,W", SHAPES)
+@pytest.mark.parametrize("B", [1, 3])
+def test_haar_bit_exact(dev, fz, oracle, H, W, B):
+    rng = np.random.default_rng(H * 1000 + W + B)
+    pan, ms = int_scene(rng, H, W, B)
+    say("haar", H, W, B)
+    out = fz.fuse(to_dev(pan, dev), to_dev(ms, dev), "haar").cpu().numpy()
+    ref = oracle_out(oracle, "haar", pan, ms).astype(np.float32)
+    assert np.array_equal(out, ref)
+
+
+@pytest.mark.parametrize("H,W", SHAPES)
+@pytest.mark.parametrize("B", [1, 3])
+def test_d4_within_tolerance(dev, fz, oracle, H, W, B):
+    rng = np.random.default_rng(H * 1000 + W + B + 7)
+    pan, ms = int_scene(rng, H, W, B)
+    say("d4", H, W, B)
+    out = fz.fuse(to_dev(pan, dev), to_dev(ms, dev), "d4").cpu().numpy()
+    ref = oracle_out(oracle, "d4", pan, ms)
+    assert np.abs(out - ref).max() <= D4_TOL
+
+
+def test_haar_workload_512(dev, fz, oracle):
+    from paper_1803_00737_amd import synth
+
+    wl = synth.haar_512()
+    pan, ms = wl.make()
+    say("haar 512 workload")
+    out = fz.fuse(to_dev(pan, dev), to_dev(ms, dev), "haar").cpu().numpy()
+    assert np.array_equal(out, oracle_out(oracle, "haar", pan, ms).astype(np.float32))
+
+
+@pytest.mark.parametrize("wavelet", ["haar", "d4"])
+def test_gains(dev, fz, oracle, wavelet):
+    rng = np.random.default_rng(21)
+    pan, ms = int_scene(rng, 66, 130, 4)
+    for gain in ([1.0, 0.5, 2.0, 0.0], [0.7, 1.3, 1.05, 0.91]):
+        say(wavelet, "gain", gain)
+        g = torch.tensor(gain, dtype=torch.float32, device=dev)
+        out = fz.fuse(to_dev(pan, dev), to_dev(ms, dev), wavelet, g).cpu().numpy()
+        ref = oracle_out(oracle, wavelet, pan, ms, np.array(gain, np.float32).astype(np.float64))
+        if wavelet == "d4":
+            assert np.abs(out - ref).max() <= D4_TOL
+        elif gain[3] == 0.0:  # powers of two: still exact
+            assert np.array_equal(out, ref.astype(np.float32))
+        else:  # one rounding (fused multiply-add) against the rounded FP64 value
+            assert ulp_diff(out, ref.astype(np.float32)) <= 1
+
+
+@pytest.mark.parametrize("wavelet", ["haar", "d4"])
+@pytest.mark.parametrize("pad,offset", [(0, 0), (6, 0), (4, 2), (1, 1), (3, 3)])
+@pytest.mark.parametrize("H,W", [(34, 70), (66, 1030)])
+def test_paths_and_pitches(dev, fz, oracle, wavelet, pad, offset, H, W):
+    """Pitched and misaligned views take the 64-bit or scalar paths; results
+    must be identical to the contiguous (128-bit) call."""
+    rng = np.random.default_rng(pad * 10 + offset + H)
+    pan, ms = int_scene(rng, H, W, 3)
+    say(wavelet, "pitch", pad, offset, H, W)
+    pv = strided_view(pan, dev, pad, offset)
+    mv = strided_view(ms, dev, pad, offset)
+    ov = strided_view(np.zeros((3, H, W), np.float32), dev, pad, offset)
+    fz.fuse(pv, mv, wavelet, out=ov)
+    got = ov.cpu().numpy()
+    base = fz.fuse(to_dev(pan, dev), to_dev(ms, dev), wavelet).cpu().numpy()
+    assert np.array_equal(got, base)
+    ref = oracle_out(oracle, wavelet, pan, ms)
+    if wavelet == "haar":
+        assert np.array_equal(got, ref.astype(np.float32))
+    else:
+        assert np.abs(got - ref).max() <= D4_TOL
+
+
+@pytest.mark.parametrize("wavelet", ["haar", "d4"])
+def test_tile_shapes_give_identical_results(dev, fz, wavelet):
+    """Every output pixel is evaluated in the same order whatever unit holds
+    it, so forced tile shapes must agree bit for bit."""
+    rng = np.random.default_rng(5)
+    pan, ms = int_scene(rng, 250, 1034, 3)
+    p, m = to_dev(pan, dev), to_dev(ms, dev)
+    ctx = fz.context(dev)
+    outs = []
+    try:
+        for seg, wpb, nc in [(0, 0, 0), (1, 1, 1), (3, 2, 2), (7, 4, 1), (64, 1, 2), (200, 4, 2)]:
+            say(wavelet, "tile", seg, wpb, nc)
+            ctx.force_tile(seg, wpb, nc)
+            outs.append(fz.fuse(p, m, wavelet).cpu().numpy())
+    finally:
+        ctx.force_tile(0, 0, 0)
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+@pytest.mark.parametrize("wavelet", ["haar", "d4"])
+def test_cyclic_shift_equivariance(dev, fz, wavelet):
+    """Shifting PAN by (2r, 2c) and MS by (r, c) shifts the output by (2r, 2c):
+    pins the periodic wrap without the oracle."""
+    rng = np.random.default_rng(77)
+    pan, ms = int_scene(rng, 96, 520, 2)
+    say(wavelet, "shift")
+    out = fz.fuse(to_dev(pan, dev), to_dev(ms, dev), wavelet).cpu().numpy()
+    for r, c in [(1, 0), (0, 1), (5, 131), (47, 259)]:
+        o2 = fz.fuse(to_dev(np.roll(pan, (2 * r, 2 * c), (0, 1)), dev),
+                     to_dev(np.roll(ms, (r, c), (1, 2)), dev), wavelet).cpu().numpy()
+        assert np.array_equal(o2, np.roll(out, (2 * r, 2 * c), (1, 2)))
+
+
+def test_ms_equal_to_ll_reproduces_pan(dev, fz, oracle):
+    rng = np.random.default_rng(3)
+    pan, _ = int_scene(rng, 130, 258, 1)
+    for w in ("haar", "d4"):
+        ll = oracle.dwt2_fwd(w, pan.astype(np.float64))[:65, :129].astype(np.float32)
+        say(w, "ms=LL(pan)")
+        out = fz.fuse(to_dev(pan, dev), to_dev(ll[None], dev), w).cpu().numpy()[0]
+        tol = 0 if w == "haar" else D4_TOL
+        assert np.abs(out - pan).max() <= tol
+
+
+def test_errors_surface_as_exceptions(dev, fz):
+    from paper_1803_00737_amd._lib import DwtFuseError
+
+    pan = torch.zeros(8, 8, device=dev)
+    ms = torch.zeros(1, 4, 4, device=dev)
+    with pytest.raises(DwtFuseError, match="E_ALIAS"):
+        fz.fuse(pan, ms, "d4", out=pan.view(1, 8, 8))
+    with pytest.raises(DwtFuseError, match="E_SHAPE"):
+        fz.fuse(pan, torch.zeros(0, 4, 4, device=dev), "d4")
+    with pytest.raises(ValueError):
+        fz.fuse(torch.zeros(7, 8, device=dev), torch.zeros(1, 3, 4, device=dev), "d4")
+    with pytest.raises(ValueError):
+        fz.fuse(pan, ms, "db8")
+
+
+def test_nan_propagates(dev, fz):
+    pan = torch.full((16, 16), 10.0, device=dev)
+    pan[5, 7] = float("nan")
+    ms = torch.ones(1, 8, 8, device=dev)
+    out = fz.fuse(pan, ms, "d4")
+    assert torch.isnan(out).any() and not torch.isnan(out).all()
+    out = fz.fuse(pan, ms, "haar")
+    assert int(torch.isnan(out).sum()) == 4  # only the 2x2 block holding the NaN
+
+
+# ---- full-size workloads, sampled --------------------------------------
+
+def sample_points(H, W, B, seg_rows_hint, n, rng):
+    ys = [0, 1, 2, H - 1, H - 2, H // 2, H // 2 + 1]
+    xs = [0, 1, 2, 3, W - 1, W - 2, W - 3, W // 2]
+    # unit and strip seams
+    for k in (1, 2, 3):
+        ys += [min(H - 1, 2 * seg_rows_hint * k), min(H - 1, 2 * seg_rows_hint * k - 1)]
+    for k in (1, 2, 5):
+        xs += [min(W - 1, 256 * k), min(W - 1, 256 * k - 1), min(W - 1, 512 * k - 1)]
+    pts = [(b, y, x) for b in range(B) for y in ys for x in xs[:6]]
+    pts += [(int(rng.integers(B)), int(rng.integers(H)), int(rng.integers(W))) for _ in range(n)]
+    return pts
+
+
+def check_full_size(dev, fz, oracle, wl, n=600):
+    say("full size", wl.name, "generate")
+    pan_d, ms_d = wl.make(device=dev)
+    torch.cuda.synchronize()
+    say("full size", wl.name, "fuse")
+    out_d = fz.fuse(pan_d, ms_d, wl.wavelet)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(1)
+    pts = sample_points(wl.H, wl.W, wl.B, 16, n, rng)
+    b, y, x = map(np.array, zip(*pts))
+    got = out_d[torch.from_numpy(b).to(dev), torch.from_numpy(y).to(dev), torch.from_numpy(x).to(dev)].cpu().numpy()
+    pan = pan_d.cpu().numpy().astype(np.float64)
+    ms = ms_d.cpu().numpy().astype(np.float64)
+    ref = oracle.fuse_points(wl.wavelet, pan, ms, None, b, y, x)
+    del out_d, pan_d, ms_d
+    torch.cuda.empty_cache()
+    return got, ref
+
+
+def test_full_size_d4_8192(dev, fz, oracle):
+    from paper_1803_00737_amd import synth
+
+    got, ref = check_full_size(dev, fz, oracle, synth.d4_8192())
+    assert np.abs(got - ref).max() <= D4_TOL
+
+
+@pytest.mark.parametrize("wavelet", ["haar", "d4"])
+def test_full_size_landsat(dev, fz, oracle, wavelet):
+    from paper_1803_00737_amd import synth
+
+    got, ref = check_full_size(dev, fz, oracle, synth.landsat(wavelet), n=400)
+    if wavelet == "haar":
+        assert np.array_equal(got, ref.astype(np.float32))
+    else:
+        assert np.abs(got - ref).max() <= D4_TOL
