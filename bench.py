@@ -207,6 +207,8 @@ def main():
     ap.add_argument("--mode", choices=["full", "primary", "copy"], default="full")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="use the default tile instead of the autotuner")
+    ap.add_argument("--tune-cache", default=None,
+                    help="tuning table file: loaded if it exists (no tuning), else written after tuning")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -230,12 +232,19 @@ def main():
     pan, ms = wl.make(device=dev)
     out = torch.empty((wl.B, wl.H, wl.W), device=dev)
     ctx = api.context(dev)
-    if not args.no_tune:
+    loaded = False
+    if args.tune_cache and os.path.exists(args.tune_cache):
+        ctx.tune_load(args.tune_cache)
+        loaded = True
+        log("tuning table loaded from", args.tune_cache)
+    elif not args.no_tune:
         ctx.set_tuning(True)
     torch.cuda.synchronize()
     call = Prepared(api, pan, ms, wl.wavelet, out)
-    call()  # first call tunes the tile shape for this size class
+    call()  # first call tunes the launch shape for this size class
     torch.cuda.synchronize()
+    if args.tune_cache and not loaded and not args.no_tune:
+        ctx.tune_save(args.tune_cache)
     ms_step = time_loop(torch, call, args.steps, args.warmup)
     nbytes = algo_bytes(wl.H, wl.W, wl.B)
     achieved = nbytes / (ms_step * 1e-3) / 1e9

@@ -155,21 +155,29 @@ const char *dwt_fuse_status_str(dwt_fuse_status s);
 /* Human-readable detail of the last failure on this context ("" if none). */
 const char *dwt_fuse_last_error(const dwt_fuse_ctx *ctx);
 
-/* Tuning.  The tile shape of each launch (rows per work unit, waves per
- * workgroup, columns per lane) comes from a per-context table keyed by
- * wavelet, size class and band count.  With tuning enabled, the first call
- * of each key times the candidate shapes on that call's own buffers (each
- * candidate writes the same output) and keeps the fastest.  The table can be
- * saved to / loaded from a small text file; a file whose header does not
- * match this library build and device is ignored. */
+/* Tuning.  The launch shape of each call (kernel variant, rows per work
+ * unit, waves per workgroup, columns per lane, unit order) comes from a
+ * per-context table keyed by wavelet, size class and band count.  With tuning
+ * enabled, the first call of each key times the candidate shapes on that
+ * call's own buffers (each candidate writes the same output) and keeps the
+ * fastest; the first batched call of each batch signature likewise times the
+ * kernel variants on the batch.  The table can be saved to / loaded from a
+ * small text file; a file whose header does not match this library build and
+ * device is ignored. */
 dwt_fuse_status dwt_fuse_set_tuning(dwt_fuse_ctx *ctx, int enable);
 dwt_fuse_status dwt_fuse_tune_save(const dwt_fuse_ctx *ctx, const char *path);
 dwt_fuse_status dwt_fuse_tune_load(dwt_fuse_ctx *ctx, const char *path);
 
-/* Force a tile shape for all later launches on this context (0 = automatic
- * for that field): rows of coefficients per work unit, waves per workgroup,
- * coefficient columns per lane (1 or 2). */
-dwt_fuse_status dwt_fuse_force_tile(dwt_fuse_ctx *ctx, int seg_rows, int waves_per_block, int cols_per_lane);
+/* Force a launch shape for all later launches on this context (0 = automatic
+ * for that field): coefficient rows per work unit, waves per workgroup,
+ * coefficient columns per lane (1 or 2), and the kernel variant (1 = rolling
+ * wavefronts that walk seg_rows rows; 2 = one-shot wavefronts of 1 or 2 rows
+ * that issue all their loads up front; 3 = LDS-staged workgroups whose
+ * wavefronts take seg_rows = 1, 2 or 4 rows each, D4 with 16-byte aligned rows
+ * only, otherwise 2 is used).  Every shape gives bit-identical results.
+ * DWT_FUSE_E_SHAPE if a field is out of range. */
+dwt_fuse_status dwt_fuse_force_tile(dwt_fuse_ctx *ctx, int seg_rows, int waves_per_block, int cols_per_lane,
+                                    int variant);
 
 #ifdef __cplusplus
 }

@@ -99,7 +99,7 @@ def load(require_torch: bool = True):
         lib.dwt_fuse_tune_save.restype = st
         lib.dwt_fuse_tune_load.argtypes = [vp, ctypes.c_char_p]
         lib.dwt_fuse_tune_load.restype = st
-        lib.dwt_fuse_force_tile.argtypes = [vp, i32, i32, i32]
+        lib.dwt_fuse_force_tile.argtypes = [vp, i32, i32, i32, i32]
         lib.dwt_fuse_force_tile.restype = st
         _lib = lib
         return lib

@@ -52,8 +52,9 @@ class Context:
     def set_tuning(self, enable: bool = True):
         self.check(self.lib.dwt_fuse_set_tuning(self.handle, 1 if enable else 0), "dwt_fuse_set_tuning")
 
-    def force_tile(self, seg_rows: int = 0, waves_per_block: int = 0, cols_per_lane: int = 0):
-        self.check(self.lib.dwt_fuse_force_tile(self.handle, seg_rows, waves_per_block, cols_per_lane),
+    def force_tile(self, seg_rows: int = 0, waves_per_block: int = 0, cols_per_lane: int = 0, variant: int = 0):
+        """Force the launch shape (0 = automatic); variant 1 = rolling, 2 = one-shot."""
+        self.check(self.lib.dwt_fuse_force_tile(self.handle, seg_rows, waves_per_block, cols_per_lane, variant),
                    "dwt_fuse_force_tile")
 
     def tune_save(self, path: str):

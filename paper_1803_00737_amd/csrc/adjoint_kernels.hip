@@ -397,8 +397,14 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjParams p, Filters f) {
     if (unit >= p.units) return;  // whole wavefront leaves together
     float *acc = acc_lds + threadIdx.x;
     for (int b = 0; b < p.B; ++b) acc[b * 256] = 0.f;
-    const int strip = unit / p.nseg;
-    const int seg = unit - strip * p.nseg;
+    int strip, seg;
+    if (p.order) {
+        seg = unit / p.nstrips;
+        strip = unit - seg * p.nstrips;
+    } else {
+        strip = unit / p.nseg;
+        seg = unit - strip * p.nseg;
+    }
     if (p.wavelet == 1)
         d4_adj_unit<NC, AL>(p, f, strip, seg, lane, acc, 256);
     else

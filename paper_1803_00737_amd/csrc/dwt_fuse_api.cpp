@@ -273,17 +273,32 @@ Path choose_bwd_path(const BwdArgs &a) {
     return PATH_SCALAR;
 }
 
+// Launch shape of one scene.  mode 0: rolling wavefronts over seg_rows
+// coefficient rows; mode 1 or 2: one-shot wavefronts of `mode` rows; mode
+// 2 + KR (KR = 1, 2, 4): LDS-staged workgroups of wpb wavefronts with KR rows
+// each (D4, 128-bit path only).  seg_rows is ignored unless mode == 0.
 struct Tile {
     int seg_rows = 0, wpb = 0, nc = 0;
+    int order = 1;  // 1 row-band-major, 0 strip-major
+    int mode = 0;
+    int rows() const { return mode >= 3 ? wpb * (mode - 2) : (mode > 0 ? mode : seg_rows); }
+};
+
+// Forced launch shape (0 = automatic for each field); variant 1 = rolling,
+// 2 = one-shot, 3 = LDS-staged (where it applies).
+struct Forced {
+    int seg_rows = 0, wpb = 0, nc = 0, variant = 0;
 };
 
 struct Decomp {
     int32_t nstrips = 0, nseg = 0, units = 0;
 };
 
-bool decompose(int64_t H, int64_t W, int nc, int seg_rows, Decomp *d) {
+bool decompose(int64_t H, int64_t W, const Tile &t, Decomp *d) {
     const int64_t W2 = W / 2, H2 = H / 2;
-    const int64_t cols = 64 * nc;
+    const int64_t cols = 64 * t.nc;
+    const int seg_rows = t.rows();
+    if (seg_rows < 1) return false;
     const int64_t ns = (W2 + cols - 1) / cols;
     const int64_t ng = (H2 + seg_rows - 1) / seg_rows;
     if (ns * ng > INT32_MAX) return false;
@@ -302,7 +317,7 @@ Tile default_tile(int64_t H, int64_t W, Path path) {
     t.wpb = 4;
     t.seg_rows = 32;
     Decomp d;
-    while (t.seg_rows > 4 && decompose(H, W, t.nc, t.seg_rows, &d) && d.units < 8192) t.seg_rows /= 2;
+    while (t.seg_rows > 4 && decompose(H, W, t, &d) && d.units < 8192) t.seg_rows /= 2;
     return t;
 }
 
@@ -314,7 +329,7 @@ int ceil_log2(int64_t v) {
 
 std::string tune_key(int kind, int wavelet, int64_t H, int64_t W, int64_t B, Path path) {
     char buf[96];
-    std::snprintf(buf, sizeof(buf), "%c%d_h%d_w%d_b%d_p%d", kind == 0 ? 'f' : 'a', wavelet, ceil_log2(H),
+    std::snprintf(buf, sizeof(buf), "%c%d_h%d_w%d_b%d_p%d", kind == 0 ? 'f' : 'b', wavelet, ceil_log2(H),
                   ceil_log2(W), (int)std::min<int64_t>(B, 8), (int)path);
     return buf;
 }
@@ -344,8 +359,9 @@ struct dwt_fuse_ctx {
     std::string device_name;
     // tiling
     bool tuning = false;
-    Tile forced;
+    Forced forced;
     std::map<std::string, Tile> table;
+    std::map<std::string, int> batch_modes;  // tuned variant per batch signature
     // backward workspace
     float *ws = nullptr;
     size_t ws_bytes = 0;
@@ -358,7 +374,6 @@ struct dwt_fuse_ctx {
     bool staged_pending = false;
     std::map<std::string, hipGraphExec_t> graphs;
     hipStream_t cap_stream = nullptr;  // capture only (the null stream cannot be captured)
-    int batched_grid = 0;
 };
 
 namespace {
@@ -402,18 +417,34 @@ FuseParams make_params(const RunArgs &a, Path path, const Tile &t, const Decomp 
     p.H = (int32_t)a.H;
     p.W = (int32_t)a.W;
     p.B = (int32_t)a.B;
-    p.seg_rows = t.seg_rows;
+    p.seg_rows = t.rows();
     p.nseg = d.nseg;
     p.units = d.units;
     p.wavelet = a.wavelet;
     p.path = path;
+    p.nstrips = d.nstrips;
+    p.order = t.order;
+    p.mode = t.mode;
     return p;
 }
 
-Tile apply_forced(const dwt_fuse_ctx *c, Tile t, Path path) {
-    if (c->forced.seg_rows > 0) t.seg_rows = c->forced.seg_rows;
-    if (c->forced.wpb > 0) t.wpb = c->forced.wpb;
-    if (c->forced.nc > 0) t.nc = std::min(c->forced.nc, path_nc(path));
+bool staged_allowed(int wavelet, Path path, int nc) { return wavelet == DWT_FUSE_D4 && path == PATH_V4 && nc == 2; }
+
+Tile apply_forced(const dwt_fuse_ctx *c, Tile t, Path path, int wavelet) {
+    const Forced &fo = c->forced;
+    if (fo.seg_rows > 0) t.seg_rows = fo.seg_rows;
+    if (fo.wpb > 0) t.wpb = fo.wpb;
+    if (fo.nc > 0) t.nc = std::min(fo.nc, path_nc(path));
+    int variant = fo.variant;
+    if (variant == 3 && !staged_allowed(wavelet, path, t.nc)) variant = 2;
+    if (variant == 0 && t.mode >= 3 && !staged_allowed(wavelet, path, t.nc)) variant = 2;
+    if (variant == 1) t.mode = 0;
+    if (variant == 2) t.mode = std::min(2, std::max(1, fo.seg_rows > 0 ? fo.seg_rows : 2));
+    if (variant == 3) {
+        const int kr = fo.seg_rows >= 4 ? 4 : (fo.seg_rows >= 2 ? 2 : (fo.seg_rows == 1 ? 1 : 2));
+        t.mode = 2 + kr;
+    }
+    if (t.mode == 0 && t.seg_rows < 1) t.seg_rows = 1;
     return t;
 }
 
@@ -422,7 +453,7 @@ Path path_for_nc(Path path, int nc) { return (path == PATH_V4 && nc == 1) ? PATH
 // Time one forward launch configuration on the caller's buffers (ms, median of 3).
 float time_fuse(dwt_fuse_ctx *c, const RunArgs &a, Path path, const Tile &t) {
     Decomp d;
-    if (!decompose(a.H, a.W, t.nc, t.seg_rows, &d)) return 1e30f;
+    if (!decompose(a.H, a.W, t, &d)) return 1e30f;
     const Path pp = path_for_nc(path, t.nc);
     const FuseParams p = make_params(a, pp, t, d);
     hipEvent_t e0, e1;
@@ -451,27 +482,55 @@ float time_fuse(dwt_fuse_ctx *c, const RunArgs &a, Path path, const Tile &t) {
 Tile tune_fuse(dwt_fuse_ctx *c, const RunArgs &a, Path path) {
     Tile bestt = default_tile(a.H, a.W, path);
     float bestms = time_fuse(c, a, path, bestt);
+    // Candidates: rolling units of 2..64 rows and one-shot units of 1 or 2
+    // rows, each with 1, 2 or 4 waves per workgroup, both unit orders and
+    // (on the 128-bit path) 1 or 2 coefficient columns per lane.
     const int ncs[2] = {2, 1};
+    const int rows_cand[8] = {-1, -2, 2, 4, 8, 16, 32, 64};  // negative: one-shot of that many rows
     for (int nc : ncs) {
         if (nc > path_nc(path)) continue;
-        for (int seg : {4, 8, 16, 32, 64}) {
+        for (int rc : rows_cand) {
             for (int wpb : {1, 2, 4}) {
-                Tile t;
-                t.nc = nc;
-                t.seg_rows = seg;
-                t.wpb = wpb;
-                const float ms = time_fuse(c, a, path, t);
-                if (ms < bestms) {
-                    bestms = ms;
-                    bestt = t;
+                for (int order : {1, 0}) {
+                    Tile t;
+                    t.nc = nc;
+                    t.mode = rc < 0 ? -rc : 0;
+                    t.seg_rows = rc < 0 ? -rc : rc;
+                    t.wpb = wpb;
+                    t.order = order;
+                    const float ms = time_fuse(c, a, path, t);
+                    if (ms < bestms) {
+                        bestms = ms;
+                        bestt = t;
+                    }
+                }
+            }
+        }
+    }
+    // LDS-staged workgroups (D4 on the 128-bit path): KR rows per wavefront.
+    if (staged_allowed(a.wavelet, path, 2)) {
+        for (int kr : {1, 2, 4}) {
+            for (int wpb : {1, 2, 4}) {
+                for (int order : {1, 0}) {
+                    Tile t;
+                    t.nc = 2;
+                    t.mode = 2 + kr;
+                    t.seg_rows = kr;
+                    t.wpb = wpb;
+                    t.order = order;
+                    const float ms = time_fuse(c, a, path, t);
+                    if (ms < bestms) {
+                        bestms = ms;
+                        bestt = t;
+                    }
                 }
             }
         }
     }
     if (std::getenv("DWT_FUSE_LOG"))
-        std::fprintf(stderr, "[dwt_fuse] tuned %s: seg_rows=%d wpb=%d nc=%d (%.3f ms)\n",
-                     tune_key(0, a.wavelet, a.H, a.W, a.B, path).c_str(), bestt.seg_rows, bestt.wpb, bestt.nc,
-                     bestms);
+        std::fprintf(stderr, "[dwt_fuse] tuned %s: mode=%d seg_rows=%d wpb=%d nc=%d order=%d (%.3f ms)\n",
+                     tune_key(0, a.wavelet, a.H, a.W, a.B, path).c_str(), bestt.mode, bestt.seg_rows, bestt.wpb,
+                     bestt.nc, bestt.order, bestms);
     return bestt;
 }
 
@@ -487,7 +546,7 @@ Tile tile_for_run(dwt_fuse_ctx *c, const RunArgs &a, Path path, bool allow_tune)
     } else {
         t = default_tile(a.H, a.W, path);
     }
-    return apply_forced(c, t, path);
+    return apply_forced(c, t, path, a.wavelet);
 }
 
 dwt_fuse_status ensure_ws(dwt_fuse_ctx *c, size_t bytes) {
@@ -543,6 +602,127 @@ dwt_fuse_status ensure_batch_tables(dwt_fuse_ctx *c, size_t n) {
     c->scenes_cap = cap;
     c->staged_pending = false;
     return DWT_FUSE_OK;
+}
+
+
+// ---- batched launch planning ----
+
+constexpr int kDefaultBatchMode = 0;
+
+struct BatchPlan {
+    std::vector<BatchScene> sc;
+    BatchQueues q;
+    int grid = 0;
+    int mode = 0;
+    std::string sig;  // batch signature (graph cache key), includes the variant and grid
+};
+
+// Per-scene tiles (tuned per size class with the per-image kernel when tuning
+// is on), forced to the batch's variant `mode`, then 8 contiguous queues of
+// about equal bytes.
+dwt_fuse_status plan_batch(dwt_fuse_ctx *ctx, const dwt_fuse_item *items, int64_t n, int mode, BatchPlan *pl) {
+    pl->sc.assign((size_t)n, BatchScene{});
+    pl->mode = mode;
+    pl->sig.clear();
+    pl->sig.reserve((size_t)n * 48);
+    std::vector<double> unit_bytes((size_t)n);
+    int64_t total = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const RunArgs a = item_args(items[i]);
+        const Path path = choose_path(a);
+        Tile t = tile_for_run(ctx, a, path, true);
+        if (mode > 0) {
+            t.mode = mode;
+        } else if (t.mode > 0) {  // one-shot or staged per-image tiles: rolling here
+            t.mode = 0;
+            t.seg_rows = default_tile(a.H, a.W, path).seg_rows;
+        }
+        Decomp d;
+        if (!decompose(a.H, a.W, t, &d)) return fail(ctx, DWT_FUSE_E_SHAPE, "too many work units");
+        BatchScene &b = pl->sc[(size_t)i];
+        b.p = make_params(a, path_for_nc(path, t.nc), t, d);
+        b.unit_begin = (int32_t)total;
+        b.pad_ = 0;
+        total += d.units;
+        if (total > INT32_MAX) return fail(ctx, DWT_FUSE_E_SHAPE, "too many work units in batch");
+        unit_bytes[(size_t)i] = (double)a.H * a.W * (4.0 + 5.0 * a.B) / std::max(1, d.units);
+        char buf[200];
+        std::snprintf(buf, sizeof(buf), "%d.%lld.%lld.%lld.%lld.%lld.%lld.%lld.%lld.%d.%d.%d.%d.%d|", a.wavelet,
+                      (long long)a.H, (long long)a.W, (long long)a.B, (long long)a.pan_ld, (long long)a.ms_ld,
+                      (long long)a.ms_bs, (long long)a.out_ld, (long long)a.out_bs, (int)b.p.path, t.rows(),
+                      t.order, t.mode, a.gain ? 1 : 0);
+        pl->sig += buf;
+    }
+    BatchQueues &q = pl->q;
+    double all = 0;
+    for (int64_t i = 0; i < n; ++i) all += unit_bytes[(size_t)i] * pl->sc[(size_t)i].p.units;
+    int qi = 0;
+    double acc = 0;
+    q.begin[0] = 0;
+    for (int64_t i = 0; i < n && qi < kQueues - 1; ++i) {
+        const BatchScene &b = pl->sc[(size_t)i];
+        for (int32_t u = 0; u < b.p.units && qi < kQueues - 1; ++u) {
+            acc += unit_bytes[(size_t)i];
+            if (acc >= all * (qi + 1) / kQueues) {
+                q.end[qi] = b.unit_begin + u + 1;
+                ++qi;
+                q.begin[qi] = b.unit_begin + u + 1;
+            }
+        }
+    }
+    for (; qi < kQueues; ++qi) {
+        q.end[qi] = (int32_t)total;
+        if (qi + 1 < kQueues) q.begin[qi + 1] = (int32_t)total;
+    }
+    const int resident = ctx->num_cu * batched_blocks_per_cu(mode);
+    pl->grid = std::max(kQueues, (int)std::min<int64_t>(resident, (total + 3) / 4 + kQueues));
+    char gb[64];
+    std::snprintf(gb, sizeof(gb), "#m%d#g%d", mode, pl->grid);
+    pl->sig += gb;
+    return DWT_FUSE_OK;
+}
+
+// Upload the scene table (after the previous upload has left the staging buffer).
+dwt_fuse_status stage_batch(dwt_fuse_ctx *ctx, const BatchPlan &pl) {
+    const size_t n = pl.sc.size();
+    if (ctx->staged_pending) {
+        hipError_t e = hipEventSynchronize(ctx->staged);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipEventSynchronize");
+    }
+    std::memcpy(ctx->h_scenes, pl.sc.data(), sizeof(BatchScene) * n);
+    hipError_t e = hipMemcpyAsync(ctx->d_scenes, ctx->h_scenes, sizeof(BatchScene) * n, hipMemcpyHostToDevice,
+                                  ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "scene table upload");
+    e = hipEventRecord(ctx->staged, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipEventRecord");
+    ctx->staged_pending = true;
+    return DWT_FUSE_OK;
+}
+
+// Median of 3 timed launches of a planned batch (ms), after one warm-up.
+float time_batch(dwt_fuse_ctx *ctx, const BatchPlan &pl) {
+    if (stage_batch(ctx, pl) != DWT_FUSE_OK) return 1e30f;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return 1e30f;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return 1e30f;
+    }
+    const int n = (int)pl.sc.size();
+    launch_fuse_batched(ctx->d_scenes, n, pl.q, ctx->d_counters, pl.grid, pl.mode, ctx->filt, ctx->stream);
+    float t[3];
+    for (int k = 0; k < 3; ++k) {
+        hipEventRecord(e0, ctx->stream);
+        launch_fuse_batched(ctx->d_scenes, n, pl.q, ctx->d_counters, pl.grid, pl.mode, ctx->filt, ctx->stream);
+        hipEventRecord(e1, ctx->stream);
+        hipEventSynchronize(e1);
+        t[k] = 1e30f;
+        hipEventElapsedTime(&t[k], e0, e1);
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    std::sort(t, t + 3);
+    return t[1];
 }
 
 }  // namespace
@@ -606,11 +786,13 @@ dwt_fuse_status dwt_fuse_create(dwt_fuse_ctx **ctx, int device, void *hip_stream
         c->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
         c->device_name = prop.gcnArchName;
         if (const char *f = std::getenv("DWT_FUSE_FORCE_TILE")) {
-            int a = 0, b = 0, d = 0;
-            if (std::sscanf(f, "%d,%d,%d", &a, &b, &d) >= 1) {
+            int a = 0, b = 0, d = 0, v = 0;
+            if (std::sscanf(f, "%d,%d,%d,%d", &a, &b, &d, &v) >= 1 && a >= 0 && a <= 4096 && b >= 0 && b <= 4 &&
+                d >= 0 && d <= 2 && v >= 0 && v <= 3) {
                 c->forced.seg_rows = a;
                 c->forced.wpb = b;
                 c->forced.nc = d;
+                c->forced.variant = v;
             }
         }
         if (const char *f = std::getenv("DWT_FUSE_TUNE_CACHE")) dwt_fuse_tune_load(c, f);
@@ -654,13 +836,15 @@ dwt_fuse_status dwt_fuse_set_tuning(dwt_fuse_ctx *ctx, int enable) {
     return DWT_FUSE_OK;
 }
 
-dwt_fuse_status dwt_fuse_force_tile(dwt_fuse_ctx *ctx, int seg_rows, int wpb, int nc) {
+dwt_fuse_status dwt_fuse_force_tile(dwt_fuse_ctx *ctx, int seg_rows, int wpb, int nc, int variant) {
     if (!ctx) return DWT_FUSE_E_NULL;
-    if (seg_rows < 0 || seg_rows > 4096 || wpb < 0 || wpb > 4 || nc < 0 || nc > 2)
-        return fail(ctx, DWT_FUSE_E_SHAPE, "tile out of range (seg_rows <= 4096, wpb <= 4, nc <= 2)");
+    if (seg_rows < 0 || seg_rows > 4096 || wpb < 0 || wpb > 4 || nc < 0 || nc > 2 || variant < 0 || variant > 3)
+        return fail(ctx, DWT_FUSE_E_SHAPE,
+                    "tile out of range (seg_rows <= 4096, wpb <= 4, nc <= 2, variant <= 3)");
     ctx->forced.seg_rows = seg_rows;
     ctx->forced.wpb = wpb;
     ctx->forced.nc = nc;
+    ctx->forced.variant = variant;
     return DWT_FUSE_OK;
 }
 
@@ -668,9 +852,10 @@ dwt_fuse_status dwt_fuse_tune_save(const dwt_fuse_ctx *ctx, const char *path) {
     if (!ctx || !path) return DWT_FUSE_E_NULL;
     FILE *f = std::fopen(path, "w");
     if (!f) return DWT_FUSE_E_STATE;
-    std::fprintf(f, "dwt_fuse_tune 1 %s %s\n", DWT_FUSE_BUILD_ID, ctx->device_name.c_str());
+    std::fprintf(f, "dwt_fuse_tune 3 %s %s\n", DWT_FUSE_BUILD_ID, ctx->device_name.c_str());
     for (const auto &kv : ctx->table)
-        std::fprintf(f, "%s %d %d %d\n", kv.first.c_str(), kv.second.seg_rows, kv.second.wpb, kv.second.nc);
+        std::fprintf(f, "%s %d %d %d %d %d\n", kv.first.c_str(), kv.second.seg_rows, kv.second.wpb, kv.second.nc,
+                     kv.second.order, kv.second.mode);
     std::fclose(f);
     return DWT_FUSE_OK;
 }
@@ -683,14 +868,15 @@ dwt_fuse_status dwt_fuse_tune_load(dwt_fuse_ctx *ctx, const char *path) {
     int ver = 0;
     std::map<std::string, Tile> tab;
     bool ok = std::fscanf(f, "%31s %d %127s %127s", magic, &ver, build, dev) == 4 &&
-              std::strcmp(magic, "dwt_fuse_tune") == 0 && ver == 1 && std::strcmp(build, DWT_FUSE_BUILD_ID) == 0 &&
+              std::strcmp(magic, "dwt_fuse_tune") == 0 && ver == 3 && std::strcmp(build, DWT_FUSE_BUILD_ID) == 0 &&
               ctx->device_name == dev;
     while (ok) {
         char key[96] = {0};
         Tile t;
-        const int r = std::fscanf(f, "%95s %d %d %d", key, &t.seg_rows, &t.wpb, &t.nc);
+        const int r = std::fscanf(f, "%95s %d %d %d %d %d", key, &t.seg_rows, &t.wpb, &t.nc, &t.order, &t.mode);
         if (r == EOF) break;
-        if (r != 4 || t.seg_rows < 1 || t.seg_rows > 4096 || t.wpb < 1 || t.wpb > 4 || t.nc < 1 || t.nc > 2) {
+        if (r != 6 || t.seg_rows < 1 || t.seg_rows > 4096 || t.wpb < 1 || t.wpb > 4 || t.nc < 1 || t.nc > 2 ||
+            t.order < 0 || t.order > 1 || t.mode < 0 || t.mode > 6 || t.mode == 5) {
             ok = false;
             break;
         }
@@ -717,7 +903,7 @@ dwt_fuse_status dwt_fuse_run(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet, int64_
         const Path path = choose_path(a);
         const Tile t = tile_for_run(ctx, a, path, true);
         Decomp d;
-        if (!decompose(H, W, t.nc, t.seg_rows, &d)) return fail(ctx, DWT_FUSE_E_SHAPE, "too many work units");
+        if (!decompose(H, W, t, &d)) return fail(ctx, DWT_FUSE_E_SHAPE, "too many work units");
         const FuseParams p = make_params(a, path_for_nc(path, t.nc), t, d);
         const hipError_t e = launch_fuse(p, ctx->filt, t.wpb, ctx->stream);
         if (e != hipSuccess) return hip_fail(ctx, e, "fuse launch");
@@ -739,80 +925,49 @@ dwt_fuse_status dwt_fuse_run_batched(dwt_fuse_ctx *ctx, const dwt_fuse_item *ite
         if ((st = use_device(ctx))) return st;
         if ((st = ensure_batch_tables(ctx, (size_t)n))) return st;
 
-        // Tuned tiles per size class (timed with the per-image kernel on the
-        // first item of each class), then the work-unit layout.
-        std::vector<BatchScene> sc((size_t)n);
-        std::vector<double> unit_bytes((size_t)n);
-        int64_t total = 0;
-        std::string sig;
-        sig.reserve((size_t)n * 48);
-        for (int64_t i = 0; i < n; ++i) {
-            const RunArgs a = item_args(items[i]);
-            const Path path = choose_path(a);
-            Tile t = tile_for_run(ctx, a, path, true);
-            Decomp d;
-            if (!decompose(a.H, a.W, t.nc, t.seg_rows, &d)) return fail(ctx, DWT_FUSE_E_SHAPE, "too many work units");
-            sc[i].p = make_params(a, path_for_nc(path, t.nc), t, d);
-            sc[i].unit_begin = (int32_t)total;
-            sc[i].pad_ = 0;
-            total += d.units;
-            if (total > INT32_MAX) return fail(ctx, DWT_FUSE_E_SHAPE, "too many work units in batch");
-            unit_bytes[i] = (double)a.H * a.W * (4.0 + 5.0 * a.B) / std::max(1, d.units);
-            char buf[160];
-            std::snprintf(buf, sizeof(buf), "%d.%lld.%lld.%lld.%lld.%lld.%lld.%lld.%lld.%d.%d.%d|", a.wavelet,
-                          (long long)a.H, (long long)a.W, (long long)a.B, (long long)a.pan_ld, (long long)a.ms_ld,
-                          (long long)a.ms_bs, (long long)a.out_ld, (long long)a.out_bs, (int)sc[i].p.path,
-                          t.seg_rows, a.gain ? 1 : 0);
-            sig += buf;
-        }
-        // 8 contiguous queues of about equal bytes.
-        BatchQueues q;
-        {
-            double all = 0;
-            for (int64_t i = 0; i < n; ++i) all += unit_bytes[i] * sc[i].p.units;
-            int qi = 0;
-            double acc = 0;
-            q.begin[0] = 0;
-            for (int64_t i = 0; i < n && qi < kQueues - 1; ++i) {
-                for (int32_t u = 0; u < sc[i].p.units && qi < kQueues - 1; ++u) {
-                    acc += unit_bytes[i];
-                    if (acc >= all * (qi + 1) / kQueues) {
-                        q.end[qi] = sc[i].unit_begin + u + 1;
-                        ++qi;
-                        q.begin[qi] = sc[i].unit_begin + u + 1;
+        BatchPlan plan;
+        int mode = 0;
+        if (ctx->forced.variant == 1) {
+            mode = 0;
+        } else if (ctx->forced.variant == 2) {
+            mode = std::min(2, std::max(1, ctx->forced.seg_rows > 0 ? ctx->forced.seg_rows : 2));
+        } else {
+            // The variant is chosen per batch signature (sizes, bands, wavelets,
+            // pitches); with tuning on, each variant is timed once on the batch.
+            if ((st = plan_batch(ctx, items, n, kDefaultBatchMode, &plan))) return st;
+            auto it = ctx->batch_modes.find(plan.sig);
+            if (it != ctx->batch_modes.end()) {
+                mode = it->second;
+            } else if (ctx->tuning) {
+                float best = 1e30f;
+                for (int m : {0, 1, 2}) {
+                    BatchPlan pm;
+                    if ((st = plan_batch(ctx, items, n, m, &pm))) return st;
+                    const float ms = time_batch(ctx, pm);
+                    if (ms < best) {
+                        best = ms;
+                        mode = m;
                     }
                 }
-            }
-            for (; qi < kQueues; ++qi) {
-                q.end[qi] = (int32_t)total;
-                if (qi + 1 < kQueues) q.begin[qi + 1] = (int32_t)total;
+                ctx->batch_modes[plan.sig] = mode;
+                if (std::getenv("DWT_FUSE_LOG"))
+                    std::fprintf(stderr, "[dwt_fuse] tuned batch of %lld scenes: mode=%d (%.3f ms)\n", (long long)n,
+                                 mode, best);
+            } else {
+                mode = kDefaultBatchMode;
             }
         }
-        if (ctx->batched_grid == 0) ctx->batched_grid = ctx->num_cu * batched_blocks_per_cu();
-        const int grid = std::max(kQueues, (int)std::min<int64_t>(ctx->batched_grid, (total + 3) / 4 + kQueues));
+        if ((st = plan_batch(ctx, items, n, mode, &plan))) return st;
+        if ((st = stage_batch(ctx, plan))) return st;
 
-        // Stage the scene table (wait until the previous upload has left the buffer).
-        if (ctx->staged_pending) {
-            hipError_t e = hipEventSynchronize(ctx->staged);
-            if (e != hipSuccess) return hip_fail(ctx, e, "hipEventSynchronize");
-        }
-        std::memcpy(ctx->h_scenes, sc.data(), sizeof(BatchScene) * (size_t)n);
-        hipError_t e = hipMemcpyAsync(ctx->d_scenes, ctx->h_scenes, sizeof(BatchScene) * (size_t)n,
-                                      hipMemcpyHostToDevice, ctx->stream);
-        if (e != hipSuccess) return hip_fail(ctx, e, "scene table upload");
-        e = hipEventRecord(ctx->staged, ctx->stream);
-        if (e != hipSuccess) return hip_fail(ctx, e, "hipEventRecord");
-        ctx->staged_pending = true;
-
+        hipError_t e;
         if (!(flags & DWT_FUSE_GRAPH)) {
-            e = launch_fuse_batched(ctx->d_scenes, (int)n, q, ctx->d_counters, grid, ctx->filt, ctx->stream);
+            e = launch_fuse_batched(ctx->d_scenes, (int)n, plan.q, ctx->d_counters, plan.grid, plan.mode, ctx->filt,
+                                    ctx->stream);
             if (e != hipSuccess) return hip_fail(ctx, e, "batched launch");
             return DWT_FUSE_OK;
         }
-        char gb[64];
-        std::snprintf(gb, sizeof(gb), "#%d", grid);
-        sig += gb;
-        auto it = ctx->graphs.find(sig);
+        auto it = ctx->graphs.find(plan.sig);
         if (it == ctx->graphs.end()) {
             if (!ctx->cap_stream) {
                 e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking);
@@ -826,8 +981,8 @@ dwt_fuse_status dwt_fuse_run_batched(dwt_fuse_ctx *ctx, const dwt_fuse_item *ite
             hipGraph_t g = nullptr;
             e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamBeginCapture");
-            const hipError_t le =
-                launch_fuse_batched(ctx->d_scenes, (int)n, q, ctx->d_counters, grid, ctx->filt, ctx->cap_stream);
+            const hipError_t le = launch_fuse_batched(ctx->d_scenes, (int)n, plan.q, ctx->d_counters, plan.grid,
+                                                      plan.mode, ctx->filt, ctx->cap_stream);
             e = hipStreamEndCapture(ctx->cap_stream, &g);
             if (le != hipSuccess) {
                 if (g) hipGraphDestroy(g);
@@ -839,7 +994,7 @@ dwt_fuse_status dwt_fuse_run_batched(dwt_fuse_ctx *ctx, const dwt_fuse_item *ite
             hipGraphDestroy(g);
             if (e != hipSuccess) return hip_fail(ctx, e, "hipGraphInstantiate");
             if (ctx->graphs.size() >= 64) clear_graphs(ctx);
-            it = ctx->graphs.emplace(sig, ge).first;
+            it = ctx->graphs.emplace(plan.sig, ge).first;
         }
         e = hipGraphLaunch(it->second, ctx->stream);
         if (e != hipSuccess) return hip_fail(ctx, e, "hipGraphLaunch");
@@ -870,10 +1025,12 @@ dwt_fuse_status dwt_fuse_backward(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet, i
             auto it = ctx->table.find(tune_key(1, a.wavelet, H, W, B, path));
             if (it != ctx->table.end()) t = it->second;
         }
-        t = apply_forced(ctx, t, path);
+        t = apply_forced(ctx, t, path, a.wavelet);
+        t.mode = 0;  // the adjoint kernels are rolling only
+        if (t.seg_rows < 1) t.seg_rows = 1;
         const Path pp = path_for_nc(path, t.nc);
         Decomp d;
-        if (!decompose(H, W, t.nc, t.seg_rows, &d)) return fail(ctx, DWT_FUSE_E_SHAPE, "too many work units");
+        if (!decompose(H, W, t, &d)) return fail(ctx, DWT_FUSE_E_SHAPE, "too many work units");
         float *partial = nullptr;
         if (grad_gain) {
             if ((st = ensure_ws(ctx, sizeof(float) * (size_t)d.units * (size_t)B))) return st;
@@ -900,6 +1057,8 @@ dwt_fuse_status dwt_fuse_backward(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet, i
             p.units = d.units;
             p.wavelet = a.wavelet;
             p.path = pp;
+            p.nstrips = d.nstrips;
+            p.order = t.order;
             p.pstride = (int32_t)B;
             p.accumulate = b0 > 0 ? 1 : 0;
             const hipError_t e = launch_adjoint(p, ctx->filt, t.wpb, ctx->stream);

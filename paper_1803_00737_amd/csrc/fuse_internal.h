@@ -30,6 +30,10 @@ struct FuseParams {
     int32_t units;     // nstrips * nseg
     int32_t wavelet;   // 0 Haar, 1 D4
     int32_t path;      // Path
+    int32_t nstrips;   // ceil((W/2) / (64*NC))
+    int32_t order;     // unit numbering: 0 strip-major, 1 row-band-major
+    int32_t mode;      // 0 rolling over seg_rows rows; 1, 2 one-shot tile of that many rows
+    int32_t pad_;
 };
 
 // Daubechies-4 low-pass taps (Eq. 7-8), rounded once from double.
@@ -66,17 +70,19 @@ struct AdjParams {
     int32_t H, W, B;
     int32_t seg_rows, nseg, units;
     int32_t wavelet, path;
+    int32_t nstrips, order;  // as in FuseParams
     int32_t pstride;     // floats between consecutive units' partials
     int32_t accumulate;  // 1: add into grad_pan instead of overwriting
 };
 
 hipError_t launch_fuse(const FuseParams &p, const Filters &f, int waves_per_block, hipStream_t s);
 
+// All scenes of one batched launch use the same variant `mode` (see FuseParams).
 hipError_t launch_fuse_batched(const BatchScene *d_scenes, int nscenes, const BatchQueues &q,
-                               uint32_t *d_counters, int grid, const Filters &f, hipStream_t s);
+                               uint32_t *d_counters, int grid, int mode, const Filters &f, hipStream_t s);
 
-// Blocks per CU the batched kernel can keep resident (for sizing its grid).
-int batched_blocks_per_cu();
+// Blocks per CU the batched kernel of a variant can keep resident (grid sizing).
+int batched_blocks_per_cu(int mode);
 
 hipError_t launch_adjoint(const AdjParams &p, const Filters &f, int waves_per_block, hipStream_t s);
 

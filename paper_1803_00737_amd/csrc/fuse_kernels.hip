@@ -25,15 +25,21 @@
 //
 // Work decomposition: one wavefront handles a strip of 64*NC coefficient
 // columns (each lane NC columns = 2*NC output columns, 128-bit rows for
-// NC = 2) and walks down seg_rows coefficient rows.  D4 keeps a rolling
-// window of two row-filtered PAN rows and one row of L PAN in registers, so
-// every PAN row is read once per strip plus a 2-row halo at the top of each
-// unit; the 1-column horizontal halos are neighbouring lanes' data and hit
-// L1.  The PAN-dependent part (L PAN and the PAN pixels) is computed once
-// per row pair and reused for all B bands.  Outputs go out with
-// non-temporal stores.  Workgroups are remapped so that each XCD (one L2)
-// takes a contiguous run of units, i.e. vertically adjacent units of a
-// strip, whose halo rows then hit that L2.
+// NC = 2) and a run of coefficient rows of every band.  Two variants:
+//   * rolling (KR = 0): the wavefront walks seg_rows coefficient rows,
+//     keeping two row-filtered PAN rows and one row of L PAN in registers,
+//     so each PAN row is read once per strip plus a 2-row halo per unit;
+//   * one-shot (KR = 1 or 2): the wavefront covers KR coefficient rows, issues
+//     all its PAN rows (with the 2-row halos) and band 0's MS rows at once,
+//     and loads band b+1's MS rows while computing and storing band b.  Many
+//     short-lived wavefronts keep far more bytes in flight per CU; the halo
+//     rows are re-read from L2.
+// Both evaluate every output pixel with the same fixed fma chains, so they
+// agree bit for bit whatever the tiling.  The PAN-dependent part (L PAN and
+// the PAN pixels) is computed once and reused for all B bands.  Outputs go out
+// with non-temporal stores.  Workgroups are remapped so that each XCD (one
+// L2) takes a contiguous run of units (by default a band of rows across the
+// whole width), whose halo rows and columns then hit that L2.
 #include "fuse_internal.h"
 
 namespace dwtf {
@@ -77,26 +83,25 @@ __device__ __forceinline__ int xcd_remap(int b, int G) {
     return x * q + (x < rem ? x : rem) + i;
 }
 
-// ---- Daubechies-4 ------------------------------------------------------
-
+// The columns one lane owns: coefficient columns s0 .. s0+NC-1 (output
+// columns 2*s0 .. 2*s0+2*NC-1), plus the wrapped neighbours s0-1 and s0+NC
+// that D4 needs (Eq. 5-6).  pc[k] = (s0 - 1 + k) mod W/2.
 template <int NC, bool AL>
-__device__ __forceinline__ void d4_unit(const FuseParams &p, const Filters &f, int strip, int seg,
-                                        int lane) {
-    const int W2 = p.W >> 1, H2 = p.H >> 1;
-    const int s0 = (strip * 64 + lane) * NC;  // first own coefficient column
-    if (s0 >= W2) return;
-    const bool full = (s0 + NC) <= W2;
-    // Column pairs (= coefficient columns) s0-1 .. s0+NC, wrapped (Eq. 5-6).
+struct LaneCols {
+    int s0, W2;
+    bool full;  // all NC own columns inside the image (vector access allowed)
     int pc[NC + 2];
-#pragma unroll
-    for (int k = 0; k < NC + 2; ++k) pc[k] = wrap_idx(s0 - 1 + k, W2);
-    const float h0 = f.h[0], h1 = f.h[1], h2 = f.h[2], h3 = f.h[3];
-    const int rb = seg * p.seg_rows;
-    const int re = min(rb + p.seg_rows, H2);
 
-    // PAN row y at pairs pc[0..NC+1] (x[1..NC] are this lane's own pixels).
-    auto load_row = [&](int y, f2(&x)[NC + 2]) {
-        const float *row = p.pan + (int64_t)y * p.pan_ld;
+    __device__ __forceinline__ LaneCols(int strip, int lane, int W2_) : W2(W2_) {
+        s0 = (strip * 64 + lane) * NC;
+        full = (s0 + NC) <= W2;
+#pragma unroll
+        for (int k = 0; k < NC + 2; ++k) pc[k] = wrap_idx(s0 - 1 + k, W2);
+    }
+    __device__ __forceinline__ bool active() const { return s0 < W2; }
+
+    // Row pairs at pc[0..NC+1] (x[1..NC] are the lane's own pixels).
+    __device__ __forceinline__ void load_row(const float *row, f2 (&x)[NC + 2]) const {
         x[0] = ld2<AL>(row + 2 * pc[0]);
         if constexpr (NC == 2 && AL) {
             if (full) {
@@ -112,37 +117,48 @@ __device__ __forceinline__ void d4_unit(const FuseParams &p, const Filters &f, i
             for (int k = 1; k <= NC; ++k) x[k] = ld2<AL>(row + 2 * pc[k]);
         }
         x[NC + 1] = ld2<AL>(row + 2 * pc[NC + 1]);
-    };
-    // Row low-pass at coefficient columns pc[0..NC]: sum_l h_l PAN(y, 2s+l).
-    auto rowfilt = [&](const f2(&x)[NC + 2], float(&R)[NC + 1]) {
+    }
+    // Only the lane's own pairs (Haar).
+    __device__ __forceinline__ void load_own(const float *row, f2 (&x)[NC]) const {
+        if constexpr (NC == 2 && AL) {
+            if (full) {
+                const f4 v = *reinterpret_cast<const f4 *>(row + 2 * s0);
+                x[0] = f2{v.x, v.y};
+                x[1] = f2{v.z, v.w};
+                return;
+            }
+        }
 #pragma unroll
-        for (int j = 0; j <= NC; ++j)
-            R[j] = fmaf(h3, x[j + 1].y, fmaf(h2, x[j + 1].x, fmaf(h1, x[j].y, h0 * x[j].x)));
-    };
-    // Column low-pass of four row-filtered rows: one fixed evaluation order,
-    // so every output is computed the same way whatever unit it falls in.
-    auto colfilt = [&](const float(&R0)[NC + 1], const float(&R1)[NC + 1], const float(&R2)[NC + 1],
-                       const float(&R3)[NC + 1], float(&A)[NC + 1]) {
-#pragma unroll
-        for (int j = 0; j <= NC; ++j) A[j] = fmaf(h3, R3[j], fmaf(h2, R2[j], fmaf(h1, R1[j], h0 * R0[j])));
-    };
-    auto load_ms = [&](const float *mrow, float(&m)[NC + 1]) {
+        for (int i = 0; i < NC; ++i) x[i] = ld2<AL>(row + 2 * pc[i + 1]);
+    }
+    // MS coefficients at pc[0..NC].
+    __device__ __forceinline__ void load_ms(const float *mrow, float (&m)[NC + 1]) const {
         m[0] = mrow[pc[0]];
         if constexpr (NC == 2 && AL) {
             if (full) {
                 const f2 v = *reinterpret_cast<const f2 *>(mrow + s0);
                 m[1] = v.x;
                 m[2] = v.y;
-            } else {
-                m[1] = mrow[pc[1]];
-                m[2] = mrow[pc[2]];
+                return;
             }
-        } else {
-#pragma unroll
-            for (int k = 1; k <= NC; ++k) m[k] = mrow[pc[k]];
         }
-    };
-    auto store_row = [&](float *orow, const f2(&q)[NC]) {
+#pragma unroll
+        for (int k = 1; k <= NC; ++k) m[k] = mrow[pc[k]];
+    }
+    // MS coefficients at the lane's own columns only (Haar).
+    __device__ __forceinline__ void load_ms_own(const float *mrow, float (&m)[NC]) const {
+        if constexpr (NC == 2 && AL) {
+            if (full) {
+                const f2 v = *reinterpret_cast<const f2 *>(mrow + s0);
+                m[0] = v.x;
+                m[1] = v.y;
+                return;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < NC; ++i) m[i] = mrow[pc[i + 1]];
+    }
+    __device__ __forceinline__ void store_row(float *orow, const f2 (&q)[NC]) const {
         if constexpr (NC == 2 && AL) {
             if (full)
                 st4(orow + 2 * s0, f4{q[0].x, q[0].y, q[1].x, q[1].y});
@@ -153,67 +169,103 @@ __device__ __forceinline__ void d4_unit(const FuseParams &p, const Filters &f, i
             for (int i = 0; i < NC; ++i)
                 if (s0 + i < W2) st2<AL>(orow + 2 * (s0 + i), q[i]);
         }
-    };
+    }
+};
+
+// Row low-pass at coefficient columns pc[0..NC]: sum_l h_l PAN(y, 2s+l).
+template <int NC>
+__device__ __forceinline__ void rowfilt(const Filters &f, const f2 (&x)[NC + 2], float (&R)[NC + 1]) {
+#pragma unroll
+    for (int j = 0; j <= NC; ++j)
+        R[j] = fmaf(f.h[3], x[j + 1].y, fmaf(f.h[2], x[j + 1].x, fmaf(f.h[1], x[j].y, f.h[0] * x[j].x)));
+}
+
+// Column low-pass of four consecutive row-filtered rows (one coefficient row
+// of L PAN).  One fixed evaluation order, so every output is computed the
+// same way whatever unit it falls in.
+template <int NC>
+__device__ __forceinline__ void colfilt(const Filters &f, const float (&R0)[NC + 1], const float (&R1)[NC + 1],
+                                        const float (&R2)[NC + 1], const float (&R3)[NC + 1],
+                                        float (&A)[NC + 1]) {
+#pragma unroll
+    for (int j = 0; j <= NC; ++j)
+        A[j] = fmaf(f.h[3], R3[j], fmaf(f.h[2], R2[j], fmaf(f.h[1], R1[j], f.h[0] * R0[j])));
+}
+
+// Output rows 2r (q0) and 2r+1 (q1) of one band from the coefficient rows
+// c(r-1) = cp, c(r) = cc of (m - g L PAN) and the lane's PAN pixels of rows
+// 2r (xa) and 2r+1 (xb).
+template <int NC>
+__device__ __forceinline__ void d4_out_rows(const Filters &f, float g, const float (&mc)[NC + 1],
+                                            const float (&mp)[NC + 1], const float (&A)[NC + 1],
+                                            const float (&Ap)[NC + 1], const f2 (&xa)[NC + 2],
+                                            const f2 (&xb)[NC + 2], f2 (&q0)[NC], f2 (&q1)[NC]) {
+    const float h0 = f.h[0], h1 = f.h[1], h2 = f.h[2], h3 = f.h[3];
+    float v0[NC + 1], v1[NC + 1];
+#pragma unroll
+    for (int j = 0; j <= NC; ++j) {
+        const float cc = fmaf(-g, A[j], mc[j]);   // coefficient row r
+        const float cp = fmaf(-g, Ap[j], mp[j]);  // coefficient row r-1
+        v0[j] = fmaf(h2, cp, h0 * cc);             // output row 2r
+        v1[j] = fmaf(h3, cp, h1 * cc);             // output row 2r+1
+    }
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+        q0[i].x = fmaf(g, xa[i + 1].x, fmaf(h2, v0[i], h0 * v0[i + 1]));
+        q0[i].y = fmaf(g, xa[i + 1].y, fmaf(h3, v0[i], h1 * v0[i + 1]));
+        q1[i].x = fmaf(g, xb[i + 1].x, fmaf(h2, v1[i], h0 * v1[i + 1]));
+        q1[i].y = fmaf(g, xb[i + 1].y, fmaf(h3, v1[i], h1 * v1[i + 1]));
+    }
+}
+
+// ---- Daubechies-4, rolling ----------------------------------------------
+
+template <int NC, bool AL>
+__device__ __forceinline__ void d4_rolling(const FuseParams &p, const Filters &f, int strip, int seg, int lane) {
+    const LaneCols<NC, AL> L(strip, lane, p.W >> 1);
+    if (!L.active()) return;
+    const int H2 = p.H >> 1;
+    const int rb = seg * p.seg_rows;
+    const int re = min(rb + p.seg_rows, H2);
+    auto row = [&](int y) { return p.pan + (int64_t)y * p.pan_ld; };
 
     // Prologue: rows 2rb-2 .. 2rb+1 give L PAN at coefficient row rb-1.
     f2 xa[NC + 2], xb[NC + 2];
     float Ra[NC + 1], Rb[NC + 1], Ap[NC + 1];
     {
-        f2 xt[NC + 2];
+        f2 xs[NC + 2], xt[NC + 2];
         float Rs[NC + 1], Rt[NC + 1];
-        int y = 2 * rb - 2;
-        if (y < 0) y += p.H;
-        load_row(y, xt);
-        rowfilt(xt, Rs);
-        y = 2 * rb - 1;
-        if (y < 0) y += p.H;
-        load_row(y, xt);
-        rowfilt(xt, Rt);
-        load_row(2 * rb, xa);
-        load_row(2 * rb + 1, xb);
-        rowfilt(xa, Ra);
-        rowfilt(xb, Rb);
-        colfilt(Rs, Rt, Ra, Rb, Ap);
+        L.load_row(row(wrap_idx(2 * rb - 2, p.H)), xs);
+        L.load_row(row(wrap_idx(2 * rb - 1, p.H)), xt);
+        L.load_row(row(2 * rb), xa);
+        L.load_row(row(2 * rb + 1), xb);
+        rowfilt<NC>(f, xs, Rs);
+        rowfilt<NC>(f, xt, Rt);
+        rowfilt<NC>(f, xa, Ra);
+        rowfilt<NC>(f, xb, Rb);
+        colfilt<NC>(f, Rs, Rt, Ra, Rb, Ap);
     }
 
     for (int r = rb; r < re; ++r) {
-        int y2 = 2 * r + 2;
-        if (y2 >= p.H) y2 -= p.H;
-        int y3 = 2 * r + 3;
-        if (y3 >= p.H) y3 -= p.H;
         f2 xc[NC + 2], xd[NC + 2];
-        load_row(y2, xc);
-        load_row(y3, xd);
+        L.load_row(row(wrap_idx(2 * r + 2, p.H)), xc);
+        L.load_row(row(wrap_idx(2 * r + 3, p.H)), xd);
         float Rc[NC + 1], Rd[NC + 1], A[NC + 1];
-        rowfilt(xc, Rc);
-        rowfilt(xd, Rd);
-        colfilt(Ra, Rb, Rc, Rd, A);
+        rowfilt<NC>(f, xc, Rc);
+        rowfilt<NC>(f, xd, Rd);
+        colfilt<NC>(f, Ra, Rb, Rc, Rd, A);
         const int rp = (r == 0) ? H2 - 1 : r - 1;
         for (int b = 0; b < p.B; ++b) {
             const float g = p.gain ? p.gain[b] : 1.0f;
             const float *mb = p.ms + (int64_t)b * p.ms_bs;
             float mc[NC + 1], mp[NC + 1];
-            load_ms(mb + (int64_t)r * p.ms_ld, mc);
-            load_ms(mb + (int64_t)rp * p.ms_ld, mp);
-            float v0[NC + 1], v1[NC + 1];
-#pragma unroll
-            for (int j = 0; j <= NC; ++j) {
-                const float cc = fmaf(-g, A[j], mc[j]);   // coefficient row r
-                const float cp = fmaf(-g, Ap[j], mp[j]);  // coefficient row r-1
-                v0[j] = fmaf(h2, cp, h0 * cc);             // output row 2r
-                v1[j] = fmaf(h3, cp, h1 * cc);             // output row 2r+1
-            }
+            L.load_ms(mb + (int64_t)r * p.ms_ld, mc);
+            L.load_ms(mb + (int64_t)rp * p.ms_ld, mp);
             f2 q0[NC], q1[NC];
-#pragma unroll
-            for (int i = 0; i < NC; ++i) {
-                q0[i].x = fmaf(g, xa[i + 1].x, fmaf(h2, v0[i], h0 * v0[i + 1]));
-                q0[i].y = fmaf(g, xa[i + 1].y, fmaf(h3, v0[i], h1 * v0[i + 1]));
-                q1[i].x = fmaf(g, xb[i + 1].x, fmaf(h2, v1[i], h0 * v1[i + 1]));
-                q1[i].y = fmaf(g, xb[i + 1].y, fmaf(h3, v1[i], h1 * v1[i + 1]));
-            }
+            d4_out_rows<NC>(f, g, mc, mp, A, Ap, xa, xb, q0, q1);
             float *o0 = p.out + (int64_t)b * p.out_bs + (int64_t)(2 * r) * p.out_ld;
-            store_row(o0, q0);
-            store_row(o0 + p.out_ld, q1);
+            L.store_row(o0, q0);
+            L.store_row(o0 + p.out_ld, q1);
         }
 #pragma unroll
         for (int j = 0; j <= NC; ++j) {
@@ -229,129 +281,378 @@ __device__ __forceinline__ void d4_unit(const FuseParams &p, const Filters &f, i
     }
 }
 
-// ---- Haar ---------------------------------------------------------------
+// ---- Daubechies-4, one-shot tile of KR coefficient rows --------------------
+
+template <int NC, bool AL, int KR>
+__device__ __forceinline__ void d4_tile(const FuseParams &p, const Filters &f, int strip, int seg, int lane) {
+    const LaneCols<NC, AL> L(strip, lane, p.W >> 1);
+    if (!L.active()) return;
+    const int H2 = p.H >> 1;
+    const int rb = seg * KR;
+    const int nr = min(KR, H2 - rb);  // coefficient rows in this tile
+    constexpr int NR = 2 * KR + 4;     // PAN rows 2rb-2 .. 2rb+2KR+1
+    // Every load of the tile is issued before any arithmetic.
+    f2 x[NR][NC + 2];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) L.load_row(p.pan + (int64_t)wrap_idx(2 * rb - 2 + k, p.H) * p.pan_ld, x[k]);
+    // MS coefficient rows rb-1 .. rb+KR-1 of one band.
+    auto load_band = [&](int b, float(&m)[KR + 1][NC + 1]) {
+        const float *mb = p.ms + (int64_t)b * p.ms_bs;
+#pragma unroll
+        for (int i = 0; i <= KR; ++i) L.load_ms(mb + (int64_t)wrap_idx(rb - 1 + i, H2) * p.ms_ld, m[i]);
+    };
+    float m[KR + 1][NC + 1];
+    load_band(0, m);
+    // L PAN at coefficient rows rb-1 .. rb+KR-1.
+    float R[NR][NC + 1];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) rowfilt<NC>(f, x[k], R[k]);
+    float A[KR + 1][NC + 1];
+#pragma unroll
+    for (int i = 0; i <= KR; ++i) colfilt<NC>(f, R[2 * i], R[2 * i + 1], R[2 * i + 2], R[2 * i + 3], A[i]);
+
+    for (int b = 0; b < p.B; ++b) {
+        float mn[KR + 1][NC + 1];
+        if (b + 1 < p.B) load_band(b + 1, mn);  // in flight while band b is computed and stored
+        const float g = p.gain ? p.gain[b] : 1.0f;
+        float *ob = p.out + (int64_t)b * p.out_bs;
+#pragma unroll
+        for (int i = 0; i < KR; ++i) {
+            if (i >= nr) break;
+            // Coefficient row rb+i: output rows 2(rb+i), 2(rb+i)+1 are PAN rows x[2i+2], x[2i+3].
+            f2 q0[NC], q1[NC];
+            d4_out_rows<NC>(f, g, m[i + 1], m[i], A[i + 1], A[i], x[2 * i + 2], x[2 * i + 3], q0, q1);
+            float *o0 = ob + (int64_t)(2 * (rb + i)) * p.out_ld;
+            L.store_row(o0, q0);
+            L.store_row(o0 + p.out_ld, q1);
+        }
+        if (b + 1 < p.B) {
+#pragma unroll
+            for (int i = 0; i <= KR; ++i)
+#pragma unroll
+                for (int j = 0; j <= NC; ++j) m[i][j] = mn[i][j];
+        }
+    }
+}
+
+// ---- Haar -----------------------------------------------------------------
+
+// Detail part of PAN: pixel minus the mean of its 2x2 block (the block mean is
+// the LL coefficient of Eq. 1-2 applied to rows and columns).
+template <int NC>
+__device__ __forceinline__ void haar_details(const f2 (&a)[NC], const f2 (&c)[NC], f2 (&da)[NC], f2 (&dc)[NC]) {
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+        const float mean = ((a[i].x + a[i].y) + (c[i].x + c[i].y)) * 0.25f;
+        da[i] = f2{a[i].x - mean, a[i].y - mean};
+        dc[i] = f2{c[i].x - mean, c[i].y - mean};
+    }
+}
+
+// Output rows 2r, 2r+1 of one band: m + g * detail.
+template <int NC>
+__device__ __forceinline__ void haar_out_rows(float g, const float (&m)[NC], const f2 (&da)[NC], const f2 (&dc)[NC],
+                                              f2 (&q0)[NC], f2 (&q1)[NC]) {
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+        q0[i] = f2{fmaf(g, da[i].x, m[i]), fmaf(g, da[i].y, m[i])};
+        q1[i] = f2{fmaf(g, dc[i].x, m[i]), fmaf(g, dc[i].y, m[i])};
+    }
+}
 
 template <int NC, bool AL>
-__device__ __forceinline__ void haar_unit(const FuseParams &p, int strip, int seg, int lane) {
-    const int W2 = p.W >> 1, H2 = p.H >> 1;
-    const int s0 = (strip * 64 + lane) * NC;
-    if (s0 >= W2) return;
-    const bool full = (s0 + NC) <= W2;
+__device__ __forceinline__ void haar_rolling(const FuseParams &p, int strip, int seg, int lane) {
+    const LaneCols<NC, AL> L(strip, lane, p.W >> 1);
+    if (!L.active()) return;
+    const int H2 = p.H >> 1;
     const int rb = seg * p.seg_rows;
     const int re = min(rb + p.seg_rows, H2);
     for (int r = rb; r < re; ++r) {
         const float *p0 = p.pan + (int64_t)(2 * r) * p.pan_ld;
-        const float *p1 = p0 + p.pan_ld;
-        f2 a[NC], c[NC];
-        if constexpr (NC == 2 && AL) {
-            if (full) {
-                const f4 u = *reinterpret_cast<const f4 *>(p0 + 2 * s0);
-                const f4 v = *reinterpret_cast<const f4 *>(p1 + 2 * s0);
-                a[0] = f2{u.x, u.y};
-                a[1] = f2{u.z, u.w};
-                c[0] = f2{v.x, v.y};
-                c[1] = f2{v.z, v.w};
-            } else {
-                a[0] = ld2<AL>(p0 + 2 * s0);
-                c[0] = ld2<AL>(p1 + 2 * s0);
-                a[1] = f2{0.f, 0.f};
-                c[1] = f2{0.f, 0.f};
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i < NC; ++i) {
-                a[i] = ld2<AL>(p0 + 2 * (s0 + i));
-                c[i] = ld2<AL>(p1 + 2 * (s0 + i));
-            }
-        }
-        // Detail part of PAN: pixel minus the mean of its 2x2 block (the
-        // block mean is the LL coefficient of Eq. 1-2 applied to rows and
-        // columns).
-        f2 da[NC], dc[NC];
-#pragma unroll
-        for (int i = 0; i < NC; ++i) {
-            const float mean = ((a[i].x + a[i].y) + (c[i].x + c[i].y)) * 0.25f;
-            da[i] = f2{a[i].x - mean, a[i].y - mean};
-            dc[i] = f2{c[i].x - mean, c[i].y - mean};
-        }
+        f2 a[NC], c[NC], da[NC], dc[NC];
+        L.load_own(p0, a);
+        L.load_own(p0 + p.pan_ld, c);
+        haar_details<NC>(a, c, da, dc);
         for (int b = 0; b < p.B; ++b) {
             const float g = p.gain ? p.gain[b] : 1.0f;
-            const float *mrow = p.ms + (int64_t)b * p.ms_bs + (int64_t)r * p.ms_ld;
             float m[NC];
-            if constexpr (NC == 2 && AL) {
-                if (full) {
-                    const f2 v = *reinterpret_cast<const f2 *>(mrow + s0);
-                    m[0] = v.x;
-                    m[1] = v.y;
-                } else {
-                    m[0] = mrow[s0];
-                    m[1] = 0.f;
-                }
-            } else {
-#pragma unroll
-                for (int i = 0; i < NC; ++i) m[i] = mrow[s0 + i];
-            }
-            float *o0 = p.out + (int64_t)b * p.out_bs + (int64_t)(2 * r) * p.out_ld;
-            float *o1 = o0 + p.out_ld;
+            L.load_ms_own(p.ms + (int64_t)b * p.ms_bs + (int64_t)r * p.ms_ld, m);
             f2 q0[NC], q1[NC];
+            haar_out_rows<NC>(g, m, da, dc, q0, q1);
+            float *o0 = p.out + (int64_t)b * p.out_bs + (int64_t)(2 * r) * p.out_ld;
+            L.store_row(o0, q0);
+            L.store_row(o0 + p.out_ld, q1);
+        }
+    }
+}
+
+template <int NC, bool AL, int KR>
+__device__ __forceinline__ void haar_tile(const FuseParams &p, int strip, int seg, int lane) {
+    const LaneCols<NC, AL> L(strip, lane, p.W >> 1);
+    if (!L.active()) return;
+    const int H2 = p.H >> 1;
+    const int rb = seg * KR;
+    const int nr = min(KR, H2 - rb);
+    f2 a[KR][NC], c[KR][NC];
 #pragma unroll
-            for (int i = 0; i < NC; ++i) {
-                q0[i] = f2{fmaf(g, da[i].x, m[i]), fmaf(g, da[i].y, m[i])};
-                q1[i] = f2{fmaf(g, dc[i].x, m[i]), fmaf(g, dc[i].y, m[i])};
+    for (int i = 0; i < KR; ++i) {
+        const int r = rb + (i < nr ? i : 0);  // rows past the image re-read row rb (unused)
+        const float *p0 = p.pan + (int64_t)(2 * r) * p.pan_ld;
+        L.load_own(p0, a[i]);
+        L.load_own(p0 + p.pan_ld, c[i]);
+    }
+    auto load_band = [&](int b, float(&m)[KR][NC]) {
+        const float *mb = p.ms + (int64_t)b * p.ms_bs;
+#pragma unroll
+        for (int i = 0; i < KR; ++i) L.load_ms_own(mb + (int64_t)(rb + (i < nr ? i : 0)) * p.ms_ld, m[i]);
+    };
+    float m[KR][NC];
+    load_band(0, m);
+    f2 da[KR][NC], dc[KR][NC];
+#pragma unroll
+    for (int i = 0; i < KR; ++i) haar_details<NC>(a[i], c[i], da[i], dc[i]);
+    for (int b = 0; b < p.B; ++b) {
+        float mn[KR][NC];
+        if (b + 1 < p.B) load_band(b + 1, mn);
+        const float g = p.gain ? p.gain[b] : 1.0f;
+        float *ob = p.out + (int64_t)b * p.out_bs;
+#pragma unroll
+        for (int i = 0; i < KR; ++i) {
+            if (i >= nr) break;
+            f2 q0[NC], q1[NC];
+            haar_out_rows<NC>(g, m[i], da[i], dc[i], q0, q1);
+            float *o0 = ob + (int64_t)(2 * (rb + i)) * p.out_ld;
+            L.store_row(o0, q0);
+            L.store_row(o0 + p.out_ld, q1);
+        }
+        if (b + 1 < p.B) {
+#pragma unroll
+            for (int i = 0; i < KR; ++i)
+#pragma unroll
+                for (int j = 0; j < NC; ++j) m[i][j] = mn[i][j];
+        }
+    }
+}
+
+// Unit numbering.  Row-band-major (order 1) puts horizontally adjacent
+// strips of the same rows next to each other, so with the XCD remap one
+// XCD works on a band of rows across the whole width at a time and the
+// 1-column halos of neighbouring strips are read while still in its L2.
+__device__ __forceinline__ void unit_coords(int unit, int nstrips, int nseg, int order, int &strip, int &seg) {
+    if (order) {
+        seg = unit / nstrips;
+        strip = unit - seg * nstrips;
+    } else {
+        strip = unit / nseg;
+        seg = unit - strip * nseg;
+    }
+}
+
+// ---- Daubechies-4, LDS-staged workgroup tile (128-bit path) ----------------
+//
+// A workgroup of wpb wavefronts covers one strip of 128 coefficient columns
+// (256 output columns) and T = wpb * KR coefficient rows.  It stages, with
+// direct global-to-LDS loads (no registers held), the T*2 + 4 PAN rows it
+// needs (2-row halos above and below, 2-column halos left and right, all
+// wrapped) and the T + 1 MS rows of a group of bands, waits once, and then
+// each wavefront computes its KR coefficient rows from LDS and streams the
+// outputs.  Halos are read once per workgroup instead of once per wavefront.
+
+constexpr int kStagedPanRow = 264;  // floats: [2,4) left halo, [4,260) own, [260,262) right halo
+constexpr int kStagedMsRow = 132;   // floats: [3] left halo, [4,132) own
+
+__device__ __forceinline__ void lds_load4(const float *g, float *l) {
+    __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void *)l, 4, 0, 0);
+}
+__device__ __forceinline__ void lds_load16(const float *g, float *l) {
+    __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void *)l, 16, 0, 0);
+}
+
+// LDS floats for a tile of T coefficient rows and bg bands.
+__host__ __device__ constexpr int staged_lds_floats(int T, int bg) {
+    return (2 * T + 4) * kStagedPanRow + bg * (T + 1) * kStagedMsRow;
+}
+
+template <int KR>
+__global__ __launch_bounds__(256) void d4_staged_kernel(FuseParams p, Filters f, int bg_max) {
+    extern __shared__ float lds[];
+    const int wpb = blockDim.x >> 6;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int T = wpb * KR;
+    const int unit = xcd_remap(blockIdx.x, gridDim.x);
+    if (unit >= p.units) return;  // whole workgroup
+    int strip, trow;
+    unit_coords(unit, p.nstrips, p.nseg, p.order, strip, trow);
+    const int W2 = p.W >> 1, H2 = p.H >> 1;
+    const int sb = strip * 128;  // first coefficient column of the strip
+    const int r0 = trow * T;
+    float *Pl = lds;
+    float *Ml = lds + (2 * T + 4) * kStagedPanRow;
+
+    // PAN rows 2r0-2 .. 2r0+2T+1.  Column groups of 4 start at multiples of 4
+    // and W % 4 == 0 on this path, so a group never straddles the wrap.
+    for (int k = w; k < 2 * T + 4; k += wpb) {
+        const float *row = p.pan + (int64_t)wrap_idx(2 * r0 - 2 + k, p.H) * p.pan_ld;
+        float *dst = Pl + k * kStagedPanRow;
+        lds_load16(row + wrap_idx(2 * sb + 4 * lane, p.W), dst + 4);
+        if (lane < 2) {
+            lds_load4(row + wrap_idx(2 * sb - 2 + lane, p.W), dst + 2);
+            lds_load4(row + wrap_idx(2 * sb + 256 + lane, p.W), dst + 260);
+        }
+    }
+    // MS rows r0-1 .. r0+T-1 of bands g0 .. g0+bg-1.
+    auto stage_ms = [&](int g0, int bg) {
+        for (int k = w; k < bg * (T + 1); k += wpb) {
+            const int b = g0 + k / (T + 1), i = k - (k / (T + 1)) * (T + 1);
+            const float *row = p.ms + (int64_t)b * p.ms_bs + (int64_t)wrap_idx(r0 - 1 + i, H2) * p.ms_ld;
+            float *dst = Ml + k * kStagedMsRow;
+            lds_load4(row + wrap_idx(sb + lane, W2), dst + 4);
+            lds_load4(row + wrap_idx(sb + 64 + lane, W2), dst + 68);
+            if (lane == 0) lds_load4(row + wrap_idx(sb - 1, W2), dst + 3);
+        }
+    };
+    const int bg0 = min(p.B, bg_max);
+    stage_ms(0, bg0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+
+    // This wavefront: coefficient rows rb .. rb+KR-1; its lane owns
+    // coefficient columns s0, s0+1.
+    const int rb = r0 + KR * w;
+    const int nr = max(0, min(KR, H2 - rb));
+    const int s0 = sb + 2 * lane;
+    const bool active = s0 < W2;
+    const bool full = s0 + 2 <= W2;
+    constexpr int NR = 2 * KR + 4;  // PAN rows 2rb-2 .. 2rb+2KR+1 = LDS rows 2KR*w + t
+    f2 x[NR][4];
+    float R[NR][3];
+#pragma unroll
+    for (int t = 0; t < NR; ++t) {
+        const float *src = Pl + (2 * KR * w + t) * kStagedPanRow + 4 * lane;
+        x[t][0] = *reinterpret_cast<const f2 *>(src + 2);
+        const f4 v = *reinterpret_cast<const f4 *>(src + 4);
+        x[t][1] = f2{v.x, v.y};
+        x[t][2] = f2{v.z, v.w};
+        x[t][3] = *reinterpret_cast<const f2 *>(src + 8);
+        rowfilt<2>(f, x[t], R[t]);
+    }
+    float A[KR + 1][3];
+#pragma unroll
+    for (int i = 0; i <= KR; ++i) colfilt<2>(f, R[2 * i], R[2 * i + 1], R[2 * i + 2], R[2 * i + 3], A[i]);
+
+    for (int g0 = 0; g0 < p.B; g0 += bg_max) {
+        const int bg = min(bg_max, p.B - g0);
+        if (g0 > 0) {  // next band group: every wavefront is done with the previous one
+            __syncthreads();
+            stage_ms(g0, bg);
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+        }
+        for (int bi = 0; bi < bg; ++bi) {
+            const int b = g0 + bi;
+            float m[KR + 1][3];
+#pragma unroll
+            for (int i = 0; i <= KR; ++i) {
+                const float *src = Ml + (bi * (T + 1) + KR * w + i) * kStagedMsRow + 2 * lane;
+                m[i][0] = src[3];
+                const f2 v = *reinterpret_cast<const f2 *>(src + 4);
+                m[i][1] = v.x;
+                m[i][2] = v.y;
             }
-            if constexpr (NC == 2 && AL) {
-                if (full) {
-                    st4(o0 + 2 * s0, f4{q0[0].x, q0[0].y, q0[1].x, q0[1].y});
-                    st4(o1 + 2 * s0, f4{q1[0].x, q1[0].y, q1[1].x, q1[1].y});
-                } else {
-                    st2<AL>(o0 + 2 * s0, q0[0]);
-                    st2<AL>(o1 + 2 * s0, q1[0]);
-                }
-            } else {
+            const float g = p.gain ? p.gain[b] : 1.0f;
+            float *ob = p.out + (int64_t)b * p.out_bs;
 #pragma unroll
-                for (int i = 0; i < NC; ++i) {
-                    st2<AL>(o0 + 2 * (s0 + i), q0[i]);
-                    st2<AL>(o1 + 2 * (s0 + i), q1[i]);
+            for (int i = 0; i < KR; ++i) {
+                if (i >= nr || !active) break;
+                f2 q0[2], q1[2];
+                d4_out_rows<2>(f, g, m[i + 1], m[i], A[i + 1], A[i], x[2 * i + 2], x[2 * i + 3], q0, q1);
+                float *o0 = ob + (int64_t)(2 * (rb + i)) * p.out_ld + 2 * s0;
+                if (full) {
+                    st4(o0, f4{q0[0].x, q0[0].y, q0[1].x, q0[1].y});
+                    st4(o0 + p.out_ld, f4{q1[0].x, q1[0].y, q1[1].x, q1[1].y});
+                } else {
+                    st2<true>(o0, q0[0]);
+                    st2<true>(o0 + p.out_ld, q1[0]);
                 }
             }
         }
     }
 }
 
-template <int NC, bool AL>
+// KR = 0: rolling over p.seg_rows rows; KR = 1, 2: one-shot tile (seg_rows == KR).
+template <int NC, bool AL, int KR>
 __device__ __forceinline__ void run_unit(const FuseParams &p, const Filters &f, int unit, int lane) {
-    const int strip = unit / p.nseg;
-    const int seg = unit - strip * p.nseg;
-    if (p.wavelet == 1)
-        d4_unit<NC, AL>(p, f, strip, seg, lane);
-    else
-        haar_unit<NC, AL>(p, strip, seg, lane);
+    int strip, seg;
+    unit_coords(unit, p.nstrips, p.nseg, p.order, strip, seg);
+    if constexpr (KR == 0) {
+        if (p.wavelet == 1)
+            d4_rolling<NC, AL>(p, f, strip, seg, lane);
+        else
+            haar_rolling<NC, AL>(p, strip, seg, lane);
+    } else {
+        if (p.wavelet == 1)
+            d4_tile<NC, AL, KR>(p, f, strip, seg, lane);
+        else
+            haar_tile<NC, AL, KR>(p, strip, seg, lane);
+    }
 }
 
 // One scene: one wavefront per work unit.
-template <int NC, bool AL>
+template <int NC, bool AL, int KR>
 __global__ __launch_bounds__(256) void fuse_kernel(FuseParams p, Filters f) {
     const int wpb = blockDim.x >> 6;
     const int lane = threadIdx.x & 63;
     const int unit = xcd_remap(blockIdx.x, gridDim.x) * wpb + (threadIdx.x >> 6);
     if (unit >= p.units) return;
-    run_unit<NC, AL>(p, f, unit, lane);
+    run_unit<NC, AL, KR>(p, f, unit, lane);
+}
+
+template <int KR>
+static void launch_path(const FuseParams &p, const Filters &f, int grid, dim3 block, hipStream_t s) {
+    switch (p.path) {
+        case PATH_V4:
+            hipLaunchKernelGGL((fuse_kernel<2, true, KR>), dim3(grid), block, 0, s, p, f);
+            break;
+        case PATH_V2:
+            hipLaunchKernelGGL((fuse_kernel<1, true, KR>), dim3(grid), block, 0, s, p, f);
+            break;
+        default:
+            hipLaunchKernelGGL((fuse_kernel<1, false, KR>), dim3(grid), block, 0, s, p, f);
+            break;
+    }
+}
+
+// Largest band group whose MS rows fit next to the PAN rows in 64 KB of LDS.
+int staged_bg_max(int T) {
+    const int pan = (2 * T + 4) * kStagedPanRow;
+    const int per_band = (T + 1) * kStagedMsRow;
+    const int bg = (16384 - pan) / per_band;
+    return bg < 1 ? 0 : (bg > 8 ? 8 : bg);
 }
 
 hipError_t launch_fuse(const FuseParams &p, const Filters &f, int wpb, hipStream_t s) {
     if (p.units <= 0) return hipSuccess;
+    if (p.mode >= 3) {  // LDS-staged: one workgroup per unit, KR = mode - 2 rows per wavefront
+        const int kr = p.mode - 2;
+        if (p.path != PATH_V4 || p.seg_rows != wpb * kr) return hipErrorInvalidValue;
+        const int bgm = staged_bg_max(p.seg_rows);
+        if (bgm < 1) return hipErrorInvalidValue;
+        const size_t lds = sizeof(float) * staged_lds_floats(p.seg_rows, p.B < bgm ? p.B : bgm);
+        switch (kr) {
+            case 1: hipLaunchKernelGGL(d4_staged_kernel<1>, dim3(p.units), dim3(64 * wpb), lds, s, p, f, bgm); break;
+            case 2: hipLaunchKernelGGL(d4_staged_kernel<2>, dim3(p.units), dim3(64 * wpb), lds, s, p, f, bgm); break;
+            case 4: hipLaunchKernelGGL(d4_staged_kernel<4>, dim3(p.units), dim3(64 * wpb), lds, s, p, f, bgm); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     const int grid = (p.units + wpb - 1) / wpb;
     const dim3 block(64 * wpb);
-    switch (p.path) {
-        case PATH_V4:
-            hipLaunchKernelGGL((fuse_kernel<2, true>), dim3(grid), block, 0, s, p, f);
-            break;
-        case PATH_V2:
-            hipLaunchKernelGGL((fuse_kernel<1, true>), dim3(grid), block, 0, s, p, f);
-            break;
-        default:
-            hipLaunchKernelGGL((fuse_kernel<1, false>), dim3(grid), block, 0, s, p, f);
-            break;
+    switch (p.mode) {
+        case 0: launch_path<0>(p, f, grid, block, s); break;
+        case 1: launch_path<1>(p, f, grid, block, s); break;
+        case 2: launch_path<2>(p, f, grid, block, s); break;
+        default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
@@ -363,7 +664,8 @@ hipError_t launch_fuse(const FuseParams &p, const Filters &f, int wpb, hipStream
 // one per XCD; a wavefront takes units from its own XCD's queue (so a
 // scene's neighbouring units share that XCD's L2) and, when that queue is
 // empty, from the others in turn.  The last wavefront to finish resets the
-// counters, so the same launch can be replayed from a graph.
+// counters, so the same launch can be replayed from a graph.  All scenes of
+// one launch use the same variant KR (the host sets seg_rows accordingly).
 
 __device__ __forceinline__ int find_scene(const BatchScene *sc, int n, int u) {
     int lo = 0, hi = n - 1;
@@ -377,9 +679,9 @@ __device__ __forceinline__ int find_scene(const BatchScene *sc, int n, int u) {
     return lo;
 }
 
-__global__ __launch_bounds__(256) void fuse_batched_kernel(const BatchScene *__restrict__ scenes,
-                                                           int nscenes, BatchQueues q,
-                                                           uint32_t *counters, Filters f) {
+template <int KR>
+__global__ __launch_bounds__(256) void fuse_batched_kernel(const BatchScene *__restrict__ scenes, int nscenes,
+                                                           BatchQueues q, uint32_t *counters, Filters f) {
     const int lane = threadIdx.x & 63;
     const int home = blockIdx.x % kQueues;  // the XCD this block runs on
     for (int k = 0; k < kQueues; ++k) {
@@ -396,13 +698,13 @@ __global__ __launch_bounds__(256) void fuse_batched_kernel(const BatchScene *__r
             const int unit = u - scenes[si].unit_begin;
             switch (p.path) {
                 case PATH_V4:
-                    run_unit<2, true>(p, f, unit, lane);
+                    run_unit<2, true, KR>(p, f, unit, lane);
                     break;
                 case PATH_V2:
-                    run_unit<1, true>(p, f, unit, lane);
+                    run_unit<1, true, KR>(p, f, unit, lane);
                     break;
                 default:
-                    run_unit<1, false>(p, f, unit, lane);
+                    run_unit<1, false, KR>(p, f, unit, lane);
                     break;
             }
         }
@@ -419,18 +721,32 @@ __global__ __launch_bounds__(256) void fuse_batched_kernel(const BatchScene *__r
     }
 }
 
-int batched_blocks_per_cu() {
+int batched_blocks_per_cu(int mode) {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fuse_batched_kernel, 256, 0) != hipSuccess)
-        return 4;
+    hipError_t e;
+    switch (mode) {
+        case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fuse_batched_kernel<1>, 256, 0); break;
+        case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fuse_batched_kernel<2>, 256, 0); break;
+        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fuse_batched_kernel<0>, 256, 0); break;
+    }
+    if (e != hipSuccess) return 4;
     return n > 0 ? n : 1;
 }
 
-hipError_t launch_fuse_batched(const BatchScene *d_scenes, int nscenes, const BatchQueues &q,
-                               uint32_t *d_counters, int grid, const Filters &f, hipStream_t s) {
+hipError_t launch_fuse_batched(const BatchScene *d_scenes, int nscenes, const BatchQueues &q, uint32_t *d_counters,
+                               int grid, int mode, const Filters &f, hipStream_t s) {
     if (nscenes <= 0 || grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL(fuse_batched_kernel, dim3(grid), dim3(256), 0, s, d_scenes, nscenes, q,
-                       d_counters, f);
+    switch (mode) {
+        case 1:
+            hipLaunchKernelGGL(fuse_batched_kernel<1>, dim3(grid), dim3(256), 0, s, d_scenes, nscenes, q, d_counters, f);
+            break;
+        case 2:
+            hipLaunchKernelGGL(fuse_batched_kernel<2>, dim3(grid), dim3(256), 0, s, d_scenes, nscenes, q, d_counters, f);
+            break;
+        default:
+            hipLaunchKernelGGL(fuse_batched_kernel<0>, dim3(grid), dim3(256), 0, s, d_scenes, nscenes, q, d_counters, f);
+            break;
+    }
     return hipGetLastError();
 }
 

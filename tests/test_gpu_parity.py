@@ -108,21 +108,26 @@ def test_paths_and_pitches(dev, fz, oracle, wavelet, pad, offset, H, W):
 
 
 @pytest.mark.parametrize("wavelet", ["haar", "d4"])
-def test_tile_shapes_give_identical_results(dev, fz, wavelet):
+@pytest.mark.parametrize("H,W", [(250, 1034), (250, 1288), (18, 8)])
+def test_tile_shapes_give_identical_results(dev, fz, wavelet, H, W):
     """Every output pixel is evaluated in the same order whatever unit holds
-    it, so forced tile shapes must agree bit for bit."""
+    it, so forced launch shapes (rolling, one-shot and LDS-staged variants)
+    must agree bit for bit.  1288 = 5 full 256-column strips + a partial one
+    on the 128-bit path; H/2 = 125 leaves partial tiles."""
     rng = np.random.default_rng(5)
-    pan, ms = int_scene(rng, 250, 1034, 3)
+    pan, ms = int_scene(rng, H, W, 3)
     p, m = to_dev(pan, dev), to_dev(ms, dev)
     ctx = fz.context(dev)
     outs = []
     try:
-        for seg, wpb, nc in [(0, 0, 0), (1, 1, 1), (3, 2, 2), (7, 4, 1), (64, 1, 2), (200, 4, 2)]:
-            say(wavelet, "tile", seg, wpb, nc)
-            ctx.force_tile(seg, wpb, nc)
+        for seg, wpb, nc, var in [(0, 0, 0, 0), (1, 1, 1, 1), (3, 2, 2, 1), (7, 4, 1, 1), (64, 1, 2, 1),
+                                  (200, 4, 2, 1), (1, 1, 2, 2), (2, 4, 2, 2), (1, 2, 1, 2), (2, 1, 1, 2),
+                                  (1, 4, 2, 3), (2, 2, 2, 3), (4, 1, 2, 3), (2, 4, 2, 3), (4, 4, 2, 3)]:
+            say(wavelet, "tile", seg, wpb, nc, var)
+            ctx.force_tile(seg, wpb, nc, var)
             outs.append(fz.fuse(p, m, wavelet).cpu().numpy())
     finally:
-        ctx.force_tile(0, 0, 0)
+        ctx.force_tile(0, 0, 0, 0)
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
 
@@ -159,10 +164,14 @@ def test_errors_surface_as_exceptions(dev, fz):
     ms = torch.zeros(1, 4, 4, device=dev)
     with pytest.raises(DwtFuseError, match="E_ALIAS"):
         fz.fuse(pan, ms, "d4", out=pan.view(1, 8, 8))
-    with pytest.raises(DwtFuseError, match="E_SHAPE"):
+    # zero bands: an empty tensor has a NULL data pointer, which the library
+    # reports first (E_NULL); either way nothing is launched
+    with pytest.raises(DwtFuseError, match="E_NULL|E_SHAPE"):
         fz.fuse(pan, torch.zeros(0, 4, 4, device=dev), "d4")
-    with pytest.raises(ValueError):
+    with pytest.raises(DwtFuseError, match="E_SHAPE"):  # odd H: rejected by the library
         fz.fuse(torch.zeros(7, 8, device=dev), torch.zeros(1, 3, 4, device=dev), "d4")
+    with pytest.raises(ValueError):  # MS shape does not match PAN: rejected by the binding
+        fz.fuse(torch.zeros(8, 8, device=dev), torch.zeros(1, 3, 4, device=dev), "d4")
     with pytest.raises(ValueError):
         fz.fuse(pan, ms, "db8")
 
@@ -193,11 +202,18 @@ def sample_points(H, W, B, seg_rows_hint, n, rng):
 
 
 def check_full_size(dev, fz, oracle, wl, n=600):
+    """Sampled parity at a full workload size, in the launch configuration the
+    benchmark times (tuner on: the shape it picks for this size class)."""
     say("full size", wl.name, "generate")
     pan_d, ms_d = wl.make(device=dev)
     torch.cuda.synchronize()
-    say("full size", wl.name, "fuse")
-    out_d = fz.fuse(pan_d, ms_d, wl.wavelet)
+    say("full size", wl.name, "fuse (tuned)")
+    ctx = fz.context(dev)
+    ctx.set_tuning(True)
+    try:
+        out_d = fz.fuse(pan_d, ms_d, wl.wavelet)
+    finally:
+        ctx.set_tuning(False)
     torch.cuda.synchronize()
     rng = np.random.default_rng(1)
     pts = sample_points(wl.H, wl.W, wl.B, 16, n, rng)
