@@ -177,6 +177,17 @@ def extras(torch, api, synth, steps, warmup):
     log("uneven_96", out["uneven_96_batched"])
     del scenes, preps, arr, keep
     torch.cuda.empty_cache()
+    # The paper's own multi-pass pipeline (section 3) on the primary workload, as a comparator.
+    wl = synth.d4_8192()
+    pan, ms = wl.make(device=dev)
+    o = torch.empty((wl.B, wl.H, wl.W), device=dev)
+    t_mp = time_loop(torch, lambda: api.fuse_multipass(pan, ms, wl.wavelet, out=o), max(3, steps // 10), 1)
+    t_fu = time_loop(torch, Prepared(api, pan, ms, wl.wavelet, o), steps, warmup)
+    out["paper_multipass_" + wl.name] = {"multipass_ms": t_mp, "fused_ms": t_fu, "fused_speedup": t_mp / t_fu,
+                                         "multipass_Mpix/s": wl.B * wl.H * wl.W / t_mp / 1e3}
+    log("multipass", out["paper_multipass_" + wl.name])
+    del pan, ms, o
+    torch.cuda.empty_cache()
     # Differentiation: 16 x 2048^2, 4 bands, D4: fused forward + adjoint.
     pans, mss, gys = [], [], []
     for s in range(16):

@@ -135,6 +135,22 @@ dwt_fuse_status dwt_fuse_backward(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet,
                                   const float *grad_out, int64_t go_ld, int64_t go_band_stride,
                                   float *grad_pan, float *grad_ms, float *grad_gain);
 
+/* The paper's own GPU pipeline, kept as a comparator for dwt_fuse_run
+ * (section 3, the per-channel step list): for each band, PAN is copied into a
+ * working array, then full-image passes run one after another -- forward 1D
+ * over rows, copy, forward 1D over columns, LL replaced by the band, copy,
+ * inverse 1D over columns, copy, inverse 1D over rows into the output band --
+ * one thread per output element.  Same arguments and results as
+ * dwt_fuse_run without gains (Haar bit-identical; D4 within float32
+ * rounding).  Uses two H x W float work arrays owned by the context,
+ * allocated on first use of a larger size (DWT_FUSE_E_NOMEM on failure).
+ * H must be <= 65535. */
+dwt_fuse_status dwt_fuse_run_multipass(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet,
+                                       int64_t H, int64_t W, int64_t B,
+                                       const float *pan, int64_t pan_ld,
+                                       const float *ms, int64_t ms_ld, int64_t ms_band_stride,
+                                       float *out, int64_t out_ld, int64_t out_band_stride);
+
 /* Argument validation only, exactly as the calls above perform it; no HIP
  * call is made, so these work without a GPU. */
 dwt_fuse_status dwt_fuse_check_run(dwt_fuse_wavelet wavelet, int64_t H, int64_t W, int64_t B,

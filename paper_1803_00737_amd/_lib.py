@@ -20,7 +20,7 @@ EXPORTS = (
     "dwt_fuse_create", "dwt_fuse_destroy", "dwt_fuse_set_stream", "dwt_fuse_run",
     "dwt_fuse_run_batched", "dwt_fuse_backward", "dwt_fuse_check_run", "dwt_fuse_check_batched",
     "dwt_fuse_check_backward", "dwt_fuse_status_str", "dwt_fuse_last_error", "dwt_fuse_set_tuning",
-    "dwt_fuse_tune_save", "dwt_fuse_tune_load", "dwt_fuse_force_tile",
+    "dwt_fuse_tune_save", "dwt_fuse_tune_load", "dwt_fuse_force_tile", "dwt_fuse_run_multipass",
 )
 
 HAAR = 0
@@ -101,6 +101,8 @@ def load(require_torch: bool = True):
         lib.dwt_fuse_tune_load.restype = st
         lib.dwt_fuse_force_tile.argtypes = [vp, i32, i32, i32, i32]
         lib.dwt_fuse_force_tile.restype = st
+        lib.dwt_fuse_run_multipass.argtypes = [vp, i32, i64, i64, i64, vp, i64, vp, i64, i64, vp, i64, i64]
+        lib.dwt_fuse_run_multipass.restype = st
         _lib = lib
         return lib
 

@@ -159,6 +159,19 @@ def fuse(pan: torch.Tensor, ms: torch.Tensor, wavelet="d4", gain: Optional[torch
     return out
 
 
+def fuse_multipass(pan: torch.Tensor, ms: torch.Tensor, wavelet="d4", out: Optional[torch.Tensor] = None):
+    """The paper's per-channel multi-pass GPU pipeline (section 3), as a
+    comparator for ``fuse``: same result, one full-image pass per step."""
+    pan, ms, _, out, H, W, B = _prep_scene(pan, ms, None, out)
+    c = context(pan.device)
+    c.bind_stream()
+    st = c.lib.dwt_fuse_run_multipass(c.handle, wavelet_id(wavelet), H, W, B, _ptr(pan), _pitch(pan, 0),
+                                      _ptr(ms), _pitch(ms, 1), _pitch(ms, 0), _ptr(out), _pitch(out, 1),
+                                      _pitch(out, 0))
+    c.check(st, "dwt_fuse_run_multipass")
+    return out
+
+
 def make_items(scenes: Sequence[dict]):
     """Prepare dwt_fuse_item descriptors; each scene is a dict with keys pan,
     ms, wavelet and optionally gain, out.  Returns (items array, outs, keep)."""

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(PKG, "libdwtfuse.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-SOURCES = ["dwt_fuse_api.cpp", "fuse_kernels.hip", "adjoint_kernels.hip"]
+SOURCES = ["dwt_fuse_api.cpp", "fuse_kernels.hip", "adjoint_kernels.hip", "multipass_kernels.hip"]
 HEADERS = [os.path.join(CSRC, "fuse_internal.h"), os.path.join(INCLUDE, "dwt_fuse.h")]
 
 # -packed-fp32-ops: keep the compiler from forming packed FP32 arithmetic.

@@ -434,7 +434,247 @@ __global__ __launch_bounds__(256) void gain_reduce_kernel(const float *partial, 
     if (threadIdx.x == 0) grad_gain[b] = (float)sh[0];
 }
 
+// ---- D4 adjoint, LDS-staged workgroup tile (16-byte rows) -------------------
+//
+// A workgroup of wpb wavefronts covers a strip of 128 coefficient columns and
+// T = wpb * KR coefficient rows.  PAN rows 2r0-2 .. 2r0+2T+1 (with 2-column
+// halos) are staged into LDS once; the same rows of each band's upstream
+// gradient y_b are staged band after band into two alternating LDS buffers
+// (band b+1 is in flight while band b is computed).  Each wavefront keeps
+// Y = sum_b g_b y_b and L Y for its KR rows in registers and writes grad_pan
+// once at the end, so any band count runs in one launch.  The per-band
+// products <y_b, D> are reduced per wavefront, combined over the workgroup's
+// wavefronts in LDS in a fixed order, and written once per work unit.
+
+constexpr int kAdjRow = 264;  // floats per staged row: [2,4) left halo, [4,260) own, [260,262) right halo
+
+__device__ __forceinline__ void lds_load4(const float *g, float *l) {
+    __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void *)l, 4, 0, 0);
+}
+__device__ __forceinline__ void lds_load16(const float *g, float *l) {
+    __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void *)l, 16, 0, 0);
+}
+
+// Stage rows 2r0-2+k (k < 2T+4) of an H x W image (pitch ld) for strip sb.
+__device__ __forceinline__ void adj_stage_rows(const float *img, int64_t ld, int H, int W, int r0, int T, int sb,
+                                               float *dst, int w, int wpb, int lane) {
+    for (int k = w; k < 2 * T + 4; k += wpb) {
+        const float *row = img + (int64_t)wrap_idx(2 * r0 - 2 + k, H) * ld;
+        float *d = dst + k * kAdjRow;
+        lds_load16(row + wrap_idx(2 * sb + 4 * lane, W), d + 4);
+        if (lane < 2) {
+            lds_load4(row + wrap_idx(2 * sb - 2 + lane, W), d + 2);
+            lds_load4(row + wrap_idx(2 * sb + 256 + lane, W), d + 260);
+        }
+    }
+}
+
+template <int KR>
+__global__ __launch_bounds__(256) void d4_adjoint_staged_kernel(AdjParams p, Filters f) {
+    extern __shared__ float lds[];
+    const int wpb = blockDim.x >> 6;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int T = wpb * KR;
+    const int unit = xcd_remap(blockIdx.x, gridDim.x);
+    if (unit >= p.units) return;  // whole workgroup
+    int strip, trow;
+    if (p.order) {
+        trow = unit / p.nstrips;
+        strip = unit - trow * p.nstrips;
+    } else {
+        strip = unit / p.nseg;
+        trow = unit - strip * p.nseg;
+    }
+    const int W2 = p.W >> 1, H2 = p.H >> 1;
+    const int sb = strip * 128, r0 = trow * T;
+    const int rows = 2 * T + 4;
+    float *Pl = lds;
+    float *Yl[2] = {lds + rows * kAdjRow, lds + 2 * rows * kAdjRow};
+    float *red = lds + 3 * rows * kAdjRow;  // [band][wavefront] partial products
+
+    adj_stage_rows(p.pan, p.pan_ld, p.H, p.W, r0, T, sb, Pl, w, wpb, lane);
+    adj_stage_rows(p.gy, p.gy_ld, p.H, p.W, r0, T, sb, Yl[0], w, wpb, lane);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+
+    const int rb = r0 + KR * w;
+    const int nr = max(0, min(KR, H2 - rb));
+    const int s0 = sb + 2 * lane;
+    const bool active = s0 < W2, full = s0 + 2 <= W2;
+    const float h[4] = {f.h[0], f.h[1], f.h[2], f.h[3]};
+    constexpr int NR = 2 * KR + 4;
+    auto read_row = [&](const float *base, int t, f2 (&x)[4]) {
+        const float *src = base + (2 * KR * w + t) * kAdjRow + 4 * lane;
+        x[0] = *reinterpret_cast<const f2 *>(src + 2);
+        const f4 v = *reinterpret_cast<const f4 *>(src + 4);
+        x[1] = f2{v.x, v.y};
+        x[2] = f2{v.z, v.w};
+        x[3] = *reinterpret_cast<const f2 *>(src + 8);
+    };
+    // L PAN at rows rb-1 .. rb+KR-1, then D = PAN - P PAN at the lane's pixels.
+    f2 D[2 * KR][2];
+    {
+        float R[NR][3];
+        f2 own[2 * KR][2];
+#pragma unroll
+        for (int t = 0; t < NR; ++t) {
+            f2 x[4];
+            read_row(Pl, t, x);
+            rowfilt<2>(h, x, R[t]);
+            if (t >= 2 && t < 2 + 2 * KR) {
+                own[t - 2][0] = x[1];
+                own[t - 2][1] = x[2];
+            }
+        }
+        float A[KR + 1][3];
+#pragma unroll
+        for (int i = 0; i <= KR; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                A[i][j] = h[0] * R[2 * i][j] + h[1] * R[2 * i + 1][j] + h[2] * R[2 * i + 2][j] + h[3] * R[2 * i + 3][j];
+#pragma unroll
+        for (int i = 0; i < KR; ++i) {
+            float w0[3], w1[3];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                w0[j] = h[0] * A[i + 1][j] + h[2] * A[i][j];
+                w1[j] = h[1] * A[i + 1][j] + h[3] * A[i][j];
+            }
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                D[2 * i][c].x = own[2 * i][c].x - (h[0] * w0[c + 1] + h[2] * w0[c]);
+                D[2 * i][c].y = own[2 * i][c].y - (h[1] * w0[c + 1] + h[3] * w0[c]);
+                D[2 * i + 1][c].x = own[2 * i + 1][c].x - (h[0] * w1[c + 1] + h[2] * w1[c]);
+                D[2 * i + 1][c].y = own[2 * i + 1][c].y - (h[1] * w1[c + 1] + h[3] * w1[c]);
+            }
+        }
+    }
+    float LY[KR + 1][3];
+    f2 Y[2 * KR][2];
+#pragma unroll
+    for (int i = 0; i <= KR; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) LY[i][j] = 0.f;
+#pragma unroll
+    for (int t = 0; t < 2 * KR; ++t) Y[t][0] = Y[t][1] = f2{0.f, 0.f};
+
+    for (int b = 0; b < p.B; ++b) {
+        const float *Yb = Yl[b & 1];
+        if (b + 1 < p.B)  // next band into the other buffer, in flight during this band
+            adj_stage_rows(p.gy + (int64_t)(b + 1) * p.gy_bs, p.gy_ld, p.H, p.W, r0, T, sb, Yl[(b + 1) & 1], w, wpb,
+                           lane);
+        const float g = p.gain ? p.gain[b] : 1.0f;
+        float R[NR][3];
+        f2 yo[2 * KR][2];
+#pragma unroll
+        for (int t = 0; t < NR; ++t) {
+            f2 x[4];
+            read_row(Yb, t, x);
+            rowfilt<2>(h, x, R[t]);
+            if (t >= 2 && t < 2 + 2 * KR) {
+                yo[t - 2][0] = x[1];
+                yo[t - 2][1] = x[2];
+            }
+        }
+        float Ly[KR + 1][3];
+#pragma unroll
+        for (int i = 0; i <= KR; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                Ly[i][j] = h[0] * R[2 * i][j] + h[1] * R[2 * i + 1][j] + h[2] * R[2 * i + 2][j] + h[3] * R[2 * i + 3][j];
+        float dot = 0.f;
+        if (active) {
+#pragma unroll
+            for (int i = 0; i < KR; ++i) {
+                if (i >= nr) break;
+                if (p.grad_ms) {
+                    float *gm = p.grad_ms + (int64_t)b * H2 * W2 + (int64_t)(rb + i) * W2 + s0;
+                    if (full)
+                        *reinterpret_cast<f2 *>(gm) = f2{Ly[i + 1][1], Ly[i + 1][2]};
+                    else
+                        gm[0] = Ly[i + 1][1];
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < 2 * KR; ++t) {
+                if (t >= 2 * nr) break;
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    if (c == 1 && !full) break;
+                    Y[t][c] += g * yo[t][c];
+                    dot += yo[t][c].x * D[t][c].x + yo[t][c].y * D[t][c].y;
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i <= KR; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) LY[i][j] += g * Ly[i][j];
+        if (p.partial) {
+            const float sd = wave_sum(dot);
+            if (lane == 0) red[b * wpb + w] = sd;
+        }
+        __builtin_amdgcn_s_waitcnt(0);  // band b+1 has landed
+        __syncthreads();                // and every wavefront is done with band b
+    }
+    // grad_pan = Y - L^T L Y at the lane's pixels.
+    if (p.grad_pan && active) {
+#pragma unroll
+        for (int i = 0; i < KR; ++i) {
+            if (i >= nr) break;
+            float v0[3], v1[3];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                v0[j] = h[0] * LY[i + 1][j] + h[2] * LY[i][j];
+                v1[j] = h[1] * LY[i + 1][j] + h[3] * LY[i][j];
+            }
+            f2 q0[2], q1[2];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                q0[c].x = Y[2 * i][c].x - (h[0] * v0[c + 1] + h[2] * v0[c]);
+                q0[c].y = Y[2 * i][c].y - (h[1] * v0[c + 1] + h[3] * v0[c]);
+                q1[c].x = Y[2 * i + 1][c].x - (h[0] * v1[c + 1] + h[2] * v1[c]);
+                q1[c].y = Y[2 * i + 1][c].y - (h[1] * v1[c + 1] + h[3] * v1[c]);
+            }
+            float *g0 = p.grad_pan + (int64_t)(2 * (rb + i)) * p.W + 2 * s0;
+            if (full) {
+                *reinterpret_cast<f4 *>(g0) = f4{q0[0].x, q0[0].y, q0[1].x, q0[1].y};
+                *reinterpret_cast<f4 *>(g0 + p.W) = f4{q1[0].x, q1[0].y, q1[1].x, q1[1].y};
+            } else {
+                *reinterpret_cast<f2 *>(g0) = q0[0];
+                *reinterpret_cast<f2 *>(g0 + p.W) = q1[0];
+            }
+        }
+    }
+    if (p.partial) {  // fixed-order sum over the wavefronts
+        for (int bb = threadIdx.x; bb < p.B; bb += blockDim.x) {
+            float t = 0.f;
+            for (int k = 0; k < wpb; ++k) t += red[bb * wpb + k];
+            p.partial[(int64_t)unit * p.pstride + bb] = t;
+        }
+    }
+}
+
 }  // namespace
+
+// LDS bytes of the staged adjoint for T coefficient rows and B bands.
+size_t adjoint_staged_lds(int T, int B) {
+    return sizeof(float) * ((size_t)3 * (2 * T + 4) * kAdjRow + (size_t)B * 4);  // red: B x (wpb <= 4)
+}
+
+hipError_t launch_adjoint_staged(const AdjParams &p, const Filters &f, int kr, int wpb, hipStream_t s) {
+    if (p.units <= 0) return hipSuccess;
+    if (p.wavelet != 1 || p.path != PATH_V4 || p.seg_rows != kr * wpb || p.nstrips != (p.W / 2 + 127) / 128)
+        return hipErrorInvalidValue;
+    const size_t lds = adjoint_staged_lds(p.seg_rows, p.B);
+    if (lds > 65536) return hipErrorInvalidValue;
+    switch (kr) {
+        case 1: hipLaunchKernelGGL(d4_adjoint_staged_kernel<1>, dim3(p.units), dim3(64 * wpb), lds, s, p, f); break;
+        case 2: hipLaunchKernelGGL(d4_adjoint_staged_kernel<2>, dim3(p.units), dim3(64 * wpb), lds, s, p, f); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_adjoint(const AdjParams &p, const Filters &f, int wpb, hipStream_t s) {
     if (p.units <= 0) return hipSuccess;

@@ -308,16 +308,41 @@ bool decompose(int64_t H, int64_t W, const Tile &t, Decomp *d) {
     return true;
 }
 
-// Default: 4 waves per workgroup, 2 coefficient columns per lane where the
-// 128-bit path applies, and units of 32 coefficient rows, shortened until the
-// launch has at least 8192 wavefronts (32 per CU on 256 CUs) or 4 rows.
-Tile default_tile(int64_t H, int64_t W, Path path) {
+// Rolling shape (the adjoint kernels and the persistent batch kernel's
+// rolling variant): 4 waves per workgroup, 2 coefficient columns per lane
+// where the 128-bit path applies, units of 32 coefficient rows shortened
+// until the launch has at least 8192 wavefronts (32 per CU) or 4 rows.
+Tile rolling_tile(int64_t H, int64_t W, Path path) {
     Tile t;
     t.nc = path_nc(path);
     t.wpb = 4;
     t.seg_rows = 32;
+    t.mode = 0;
     Decomp d;
     while (t.seg_rows > 4 && decompose(H, W, t, &d) && d.units < 8192) t.seg_rows /= 2;
+    return t;
+}
+
+// Default forward shape (what the tuner picks on the large workloads):
+// D4 -> LDS-staged workgroups of 4 wavefronts x 2 coefficient rows, strip-major
+// units; Haar -> one-shot single-row wavefronts, row-band-major units.
+Tile default_tile(int wavelet, int64_t H, int64_t W, Path path) {
+    Tile t;
+    if (wavelet == DWT_FUSE_D4) {
+        t.nc = 2;
+        t.mode = 4;
+        t.seg_rows = 2;
+        t.wpb = 4;
+        t.order = 0;
+    } else {
+        t.nc = path_nc(path);
+        t.mode = 1;
+        t.seg_rows = 1;
+        t.wpb = 1;
+        t.order = 1;
+    }
+    (void)H;
+    (void)W;
     return t;
 }
 
@@ -365,6 +390,9 @@ struct dwt_fuse_ctx {
     // backward workspace
     float *ws = nullptr;
     size_t ws_bytes = 0;
+    // multi-pass comparator work arrays (2 x H x W floats)
+    float *mp = nullptr;
+    size_t mp_bytes = 0;
     // batched
     BatchScene *d_scenes = nullptr;
     BatchScene *h_scenes = nullptr;  // pinned staging
@@ -428,7 +456,9 @@ FuseParams make_params(const RunArgs &a, Path path, const Tile &t, const Decomp 
     return p;
 }
 
-bool staged_allowed(int wavelet, Path path, int nc) { return wavelet == DWT_FUSE_D4 && path == PATH_V4 && nc == 2; }
+// LDS-staged tiles exist for D4 on every path (their strips are always 128
+// coefficient columns wide, i.e. nc = 2 in the decomposition).
+bool staged_allowed(int wavelet, Path, int) { return wavelet == DWT_FUSE_D4; }
 
 Tile apply_forced(const dwt_fuse_ctx *c, Tile t, Path path, int wavelet) {
     const Forced &fo = c->forced;
@@ -444,6 +474,13 @@ Tile apply_forced(const dwt_fuse_ctx *c, Tile t, Path path, int wavelet) {
         const int kr = fo.seg_rows >= 4 ? 4 : (fo.seg_rows >= 2 ? 2 : (fo.seg_rows == 1 ? 1 : 2));
         t.mode = 2 + kr;
     }
+    if (t.mode >= 3) {
+        t.nc = 2;  // staged strips are 128 coefficient columns on every path
+        if (t.wpb < 1) t.wpb = 4;
+    } else if (t.mode > 0 || variant == 1) {
+        if (t.nc > path_nc(path) || t.nc < 1) t.nc = path_nc(path);
+    }
+    if (t.wpb < 1) t.wpb = 4;
     if (t.mode == 0 && t.seg_rows < 1) t.seg_rows = 1;
     return t;
 }
@@ -480,7 +517,7 @@ float time_fuse(dwt_fuse_ctx *c, const RunArgs &a, Path path, const Tile &t) {
 }
 
 Tile tune_fuse(dwt_fuse_ctx *c, const RunArgs &a, Path path) {
-    Tile bestt = default_tile(a.H, a.W, path);
+    Tile bestt = default_tile(a.wavelet, a.H, a.W, path);
     float bestms = time_fuse(c, a, path, bestt);
     // Candidates: rolling units of 2..64 rows and one-shot units of 1 or 2
     // rows, each with 1, 2 or 4 waves per workgroup, both unit orders and
@@ -507,7 +544,7 @@ Tile tune_fuse(dwt_fuse_ctx *c, const RunArgs &a, Path path) {
             }
         }
     }
-    // LDS-staged workgroups (D4 on the 128-bit path): KR rows per wavefront.
+    // LDS-staged workgroups (D4): KR rows per wavefront.
     if (staged_allowed(a.wavelet, path, 2)) {
         for (int kr : {1, 2, 4}) {
             for (int wpb : {1, 2, 4}) {
@@ -544,7 +581,7 @@ Tile tile_for_run(dwt_fuse_ctx *c, const RunArgs &a, Path path, bool allow_tune)
         t = tune_fuse(c, a, path);
         c->table[key] = t;
     } else {
-        t = default_tile(a.H, a.W, path);
+        t = default_tile(a.wavelet, a.H, a.W, path);
     }
     return apply_forced(c, t, path, a.wavelet);
 }
@@ -607,13 +644,19 @@ dwt_fuse_status ensure_batch_tables(dwt_fuse_ctx *c, size_t n) {
 
 // ---- batched launch planning ----
 
-constexpr int kDefaultBatchMode = 0;
+// Batch variants: 0, 1, 2 = persistent work-queue kernel with rolling or
+// one-shot (1 or 2 rows) wavefront units; 3 = flat grid, one workgroup per
+// work item (LDS-staged D4 tiles, one-shot wavefronts otherwise).
+constexpr int kFlatBatch = 3;
+constexpr int kDefaultBatchMode = kFlatBatch;
 
 struct BatchPlan {
     std::vector<BatchScene> sc;
     BatchQueues q;
     int grid = 0;
     int mode = 0;
+    int total = 0;          // work items (flat) or wavefront units (persistent)
+    int staged_bands = 0;   // flat: largest band count among staged scenes
     std::string sig;  // batch signature (graph cache key), includes the variant and grid
 };
 
@@ -623,6 +666,7 @@ struct BatchPlan {
 dwt_fuse_status plan_batch(dwt_fuse_ctx *ctx, const dwt_fuse_item *items, int64_t n, int mode, BatchPlan *pl) {
     pl->sc.assign((size_t)n, BatchScene{});
     pl->mode = mode;
+    pl->staged_bands = 0;
     pl->sig.clear();
     pl->sig.reserve((size_t)n * 48);
     std::vector<double> unit_bytes((size_t)n);
@@ -630,28 +674,55 @@ dwt_fuse_status plan_batch(dwt_fuse_ctx *ctx, const dwt_fuse_item *items, int64_
     for (int64_t i = 0; i < n; ++i) {
         const RunArgs a = item_args(items[i]);
         const Path path = choose_path(a);
-        Tile t = tile_for_run(ctx, a, path, true);
-        if (mode > 0) {
-            t.mode = mode;
-        } else if (t.mode > 0) {  // one-shot or staged per-image tiles: rolling here
-            t.mode = 0;
-            t.seg_rows = default_tile(a.H, a.W, path).seg_rows;
-        }
+        Tile t;
+        int items_of_scene = 0;
         Decomp d;
-        if (!decompose(a.H, a.W, t, &d)) return fail(ctx, DWT_FUSE_E_SHAPE, "too many work units");
+        if (mode == kFlatBatch) {
+            t.order = 1;
+            t.wpb = 4;
+            if (staged_allowed(a.wavelet, path, 2)) {
+                t.nc = 2;
+                t.mode = 4;  // staged, 2 rows per wavefront, 4 wavefronts
+                t.seg_rows = 2;
+                pl->staged_bands = std::max<int>(pl->staged_bands, (int)a.B);
+            } else {
+                t.nc = path_nc(path);
+                t.mode = 1;
+                t.seg_rows = 1;
+            }
+            if (!decompose(a.H, a.W, t, &d)) return fail(ctx, DWT_FUSE_E_SHAPE, "too many work units");
+            items_of_scene = t.mode >= 3 ? d.units : (d.units + 3) / 4;
+        } else {
+            t = tile_for_run(ctx, a, path, true);
+            if (mode > 0) {
+                t.mode = mode;
+            } else if (t.mode > 0) {  // one-shot or staged per-image tiles: rolling here
+                t = rolling_tile(a.H, a.W, path);
+            }
+            if (!decompose(a.H, a.W, t, &d)) return fail(ctx, DWT_FUSE_E_SHAPE, "too many work units");
+            items_of_scene = d.units;
+        }
         BatchScene &b = pl->sc[(size_t)i];
         b.p = make_params(a, path_for_nc(path, t.nc), t, d);
         b.unit_begin = (int32_t)total;
         b.pad_ = 0;
-        total += d.units;
+        total += items_of_scene;
         if (total > INT32_MAX) return fail(ctx, DWT_FUSE_E_SHAPE, "too many work units in batch");
-        unit_bytes[(size_t)i] = (double)a.H * a.W * (4.0 + 5.0 * a.B) / std::max(1, d.units);
+        unit_bytes[(size_t)i] = (double)a.H * a.W * (4.0 + 5.0 * a.B) / std::max(1, items_of_scene);
         char buf[200];
         std::snprintf(buf, sizeof(buf), "%d.%lld.%lld.%lld.%lld.%lld.%lld.%lld.%lld.%d.%d.%d.%d.%d|", a.wavelet,
                       (long long)a.H, (long long)a.W, (long long)a.B, (long long)a.pan_ld, (long long)a.ms_ld,
                       (long long)a.ms_bs, (long long)a.out_ld, (long long)a.out_bs, (int)b.p.path, t.rows(),
                       t.order, t.mode, a.gain ? 1 : 0);
         pl->sig += buf;
+    }
+    pl->total = (int)total;
+    if (mode == kFlatBatch) {
+        pl->grid = (int)total;
+        char gb[64];
+        std::snprintf(gb, sizeof(gb), "#flat#%d", pl->staged_bands);
+        pl->sig += gb;
+        return DWT_FUSE_OK;
     }
     BatchQueues &q = pl->q;
     double all = 0;
@@ -699,6 +770,12 @@ dwt_fuse_status stage_batch(dwt_fuse_ctx *ctx, const BatchPlan &pl) {
     return DWT_FUSE_OK;
 }
 
+hipError_t launch_plan(dwt_fuse_ctx *ctx, const BatchPlan &pl, hipStream_t s) {
+    const int n = (int)pl.sc.size();
+    if (pl.mode == kFlatBatch) return launch_fuse_batched_flat(ctx->d_scenes, n, pl.total, pl.staged_bands, ctx->filt, s);
+    return launch_fuse_batched(ctx->d_scenes, n, pl.q, ctx->d_counters, pl.grid, pl.mode, ctx->filt, s);
+}
+
 // Median of 3 timed launches of a planned batch (ms), after one warm-up.
 float time_batch(dwt_fuse_ctx *ctx, const BatchPlan &pl) {
     if (stage_batch(ctx, pl) != DWT_FUSE_OK) return 1e30f;
@@ -708,12 +785,11 @@ float time_batch(dwt_fuse_ctx *ctx, const BatchPlan &pl) {
         hipEventDestroy(e0);
         return 1e30f;
     }
-    const int n = (int)pl.sc.size();
-    launch_fuse_batched(ctx->d_scenes, n, pl.q, ctx->d_counters, pl.grid, pl.mode, ctx->filt, ctx->stream);
+    launch_plan(ctx, pl, ctx->stream);
     float t[3];
     for (int k = 0; k < 3; ++k) {
         hipEventRecord(e0, ctx->stream);
-        launch_fuse_batched(ctx->d_scenes, n, pl.q, ctx->d_counters, pl.grid, pl.mode, ctx->filt, ctx->stream);
+        launch_plan(ctx, pl, ctx->stream);
         hipEventRecord(e1, ctx->stream);
         hipEventSynchronize(e1);
         t[k] = 1e30f;
@@ -813,6 +889,7 @@ void dwt_fuse_destroy(dwt_fuse_ctx *ctx) {
         hipSetDevice(ctx->device);
         clear_graphs(ctx);
         if (ctx->ws) hipFree(ctx->ws);
+        if (ctx->mp) hipFree(ctx->mp);
         if (ctx->d_scenes) hipFree(ctx->d_scenes);
         if (ctx->h_scenes) hipHostFree(ctx->h_scenes);
         if (ctx->d_counters) hipFree(ctx->d_counters);
@@ -931,6 +1008,8 @@ dwt_fuse_status dwt_fuse_run_batched(dwt_fuse_ctx *ctx, const dwt_fuse_item *ite
             mode = 0;
         } else if (ctx->forced.variant == 2) {
             mode = std::min(2, std::max(1, ctx->forced.seg_rows > 0 ? ctx->forced.seg_rows : 2));
+        } else if (ctx->forced.variant == 3) {
+            mode = kFlatBatch;
         } else {
             // The variant is chosen per batch signature (sizes, bands, wavelets,
             // pitches); with tuning on, each variant is timed once on the batch.
@@ -940,7 +1019,7 @@ dwt_fuse_status dwt_fuse_run_batched(dwt_fuse_ctx *ctx, const dwt_fuse_item *ite
                 mode = it->second;
             } else if (ctx->tuning) {
                 float best = 1e30f;
-                for (int m : {0, 1, 2}) {
+                for (int m : {kFlatBatch, 0, 1, 2}) {
                     BatchPlan pm;
                     if ((st = plan_batch(ctx, items, n, m, &pm))) return st;
                     const float ms = time_batch(ctx, pm);
@@ -962,8 +1041,7 @@ dwt_fuse_status dwt_fuse_run_batched(dwt_fuse_ctx *ctx, const dwt_fuse_item *ite
 
         hipError_t e;
         if (!(flags & DWT_FUSE_GRAPH)) {
-            e = launch_fuse_batched(ctx->d_scenes, (int)n, plan.q, ctx->d_counters, plan.grid, plan.mode, ctx->filt,
-                                    ctx->stream);
+            e = launch_plan(ctx, plan, ctx->stream);
             if (e != hipSuccess) return hip_fail(ctx, e, "batched launch");
             return DWT_FUSE_OK;
         }
@@ -981,8 +1059,7 @@ dwt_fuse_status dwt_fuse_run_batched(dwt_fuse_ctx *ctx, const dwt_fuse_item *ite
             hipGraph_t g = nullptr;
             e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamBeginCapture");
-            const hipError_t le = launch_fuse_batched(ctx->d_scenes, (int)n, plan.q, ctx->d_counters, plan.grid,
-                                                      plan.mode, ctx->filt, ctx->cap_stream);
+            const hipError_t le = launch_plan(ctx, plan, ctx->cap_stream);
             e = hipStreamEndCapture(ctx->cap_stream, &g);
             if (le != hipSuccess) {
                 if (g) hipGraphDestroy(g);
@@ -1006,6 +1083,44 @@ dwt_fuse_status dwt_fuse_run_batched(dwt_fuse_ctx *ctx, const dwt_fuse_item *ite
     }
 }
 
+dwt_fuse_status dwt_fuse_run_multipass(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet, int64_t H, int64_t W, int64_t B,
+                                       const float *pan, int64_t pan_ld, const float *ms, int64_t ms_ld,
+                                       int64_t ms_band_stride, float *out, int64_t out_ld, int64_t out_band_stride) {
+    if (!ctx) return DWT_FUSE_E_NULL;
+    try {
+        const RunArgs a{(int)wavelet, H, W, B, pan, pan_ld, ms, ms_ld, ms_band_stride, nullptr, out, out_ld,
+                        out_band_stride};
+        std::string err;
+        dwt_fuse_status st = check_run_args(a, nullptr, &err);
+        if (st) return fail(ctx, st, err);
+        if (H > 65535) return fail(ctx, DWT_FUSE_E_SHAPE, "the multi-pass pipeline needs H <= 65535");
+        if ((st = use_device(ctx))) return st;
+        const size_t need = sizeof(float) * 2 * (size_t)H * (size_t)W;
+        if (need > ctx->mp_bytes) {
+            if (ctx->mp) {
+                hipStreamSynchronize(ctx->stream);
+                hipFree(ctx->mp);
+                ctx->mp = nullptr;
+                ctx->mp_bytes = 0;
+            }
+            if (hipMalloc(reinterpret_cast<void **>(&ctx->mp), need) != hipSuccess) {
+                ctx->mp = nullptr;
+                return fail(ctx, DWT_FUSE_E_NOMEM, "multi-pass work arrays could not be allocated");
+            }
+            ctx->mp_bytes = need;
+        }
+        const hipError_t e = launch_multipass((int)wavelet, (int)H, (int)W, (int)B, pan, pan_ld, ms, ms_ld,
+                                              ms_band_stride, out, out_ld, out_band_stride, ctx->mp,
+                                              ctx->mp + (size_t)H * (size_t)W, ctx->filt, ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "multi-pass launch");
+        return DWT_FUSE_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(ctx, DWT_FUSE_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(ctx, DWT_FUSE_E_STATE, "unexpected exception");
+    }
+}
+
 dwt_fuse_status dwt_fuse_backward(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet, int64_t H, int64_t W, int64_t B,
                                   const float *pan, int64_t pan_ld, const float *gain, const float *grad_out,
                                   int64_t go_ld, int64_t go_band_stride, float *grad_pan, float *grad_ms,
@@ -1020,13 +1135,62 @@ dwt_fuse_status dwt_fuse_backward(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet, i
         if (!grad_pan && !grad_ms && !grad_gain) return DWT_FUSE_OK;
         if ((st = use_device(ctx))) return st;
         const Path path = choose_bwd_path(a);
-        Tile t = default_tile(H, W, path);
+        // D4 on 16-byte rows: LDS-staged adjoint (4 wavefronts x 1 row, all bands in one launch).
+        const bool staged = a.wavelet == DWT_FUSE_D4 && path == PATH_V4 && ctx->forced.variant != 1 &&
+                            ctx->forced.variant != 2 && adjoint_staged_lds(4, (int)B) <= 65536;
+        if (staged) {
+            const int kr = 1, wpb = 4, T = kr * wpb;
+            const int64_t ns = (W / 2 + 127) / 128, ng = (H / 2 + T - 1) / T;
+            if (ns * ng > INT32_MAX) return fail(ctx, DWT_FUSE_E_SHAPE, "too many work units");
+            const int units = (int)(ns * ng);
+            float *partial = nullptr;
+            if (grad_gain) {
+                if ((st = ensure_ws(ctx, sizeof(float) * (size_t)units * (size_t)B))) return st;
+                partial = ctx->ws;
+            }
+            AdjParams p{};
+            p.pan = pan;
+            p.gain = gain;
+            p.gy = grad_out;
+            p.grad_pan = grad_pan;
+            p.grad_ms = grad_ms;
+            p.partial = partial;
+            p.pan_ld = pan_ld;
+            p.gy_ld = go_ld;
+            p.gy_bs = go_band_stride;
+            p.H = (int32_t)H;
+            p.W = (int32_t)W;
+            p.B = (int32_t)B;
+            p.seg_rows = T;
+            p.nseg = (int32_t)ng;
+            p.units = units;
+            p.wavelet = a.wavelet;
+            p.path = path;
+            p.nstrips = (int32_t)ns;
+            p.order = 0;
+            p.pstride = (int32_t)B;
+            p.accumulate = 0;
+            hipError_t e = launch_adjoint_staged(p, ctx->filt, kr, wpb, ctx->stream);
+            if (e != hipSuccess) return hip_fail(ctx, e, "staged adjoint launch");
+            if (grad_gain) {
+                e = launch_gain_reduce(partial, units, (int)B, grad_gain, ctx->stream);
+                if (e != hipSuccess) return hip_fail(ctx, e, "gain reduction launch");
+            }
+            return DWT_FUSE_OK;
+        }
+        Tile t = rolling_tile(H, W, path);
         {
             auto it = ctx->table.find(tune_key(1, a.wavelet, H, W, B, path));
             if (it != ctx->table.end()) t = it->second;
         }
         t = apply_forced(ctx, t, path, a.wavelet);
-        t.mode = 0;  // the adjoint kernels are rolling only
+        if (t.mode != 0) {  // the adjoint kernels are rolling only
+            const Tile r = rolling_tile(H, W, path);
+            t.mode = 0;
+            t.seg_rows = r.seg_rows;
+            t.nc = std::min(t.nc, path_nc(path));
+            if (t.nc < 1) t.nc = r.nc;
+        }
         if (t.seg_rows < 1) t.seg_rows = 1;
         const Path pp = path_for_nc(path, t.nc);
         Decomp d;

@@ -84,12 +84,33 @@ hipError_t launch_fuse_batched(const BatchScene *d_scenes, int nscenes, const Ba
 // Blocks per CU the batched kernel of a variant can keep resident (grid sizing).
 int batched_blocks_per_cu(int mode);
 
+// Flat batched launch: `total` workgroups of 256 threads, one work item each
+// (scene unit_begin counts items).  Scenes with mode >= 3 are LDS-staged D4
+// tiles of 8 coefficient rows (4 wavefronts x 2 rows, band groups of at most
+// `staged_bands`); all others are one-shot single-row wavefront units, 4 per
+// item.
+hipError_t launch_fuse_batched_flat(const BatchScene *d_scenes, int nscenes, int total, int staged_bands,
+                                    const Filters &f, hipStream_t s);
+
+// Largest band group a staged tile of T coefficient rows can hold in 64 KB of LDS.
+int staged_bg_max(int T);
+
 hipError_t launch_adjoint(const AdjParams &p, const Filters &f, int waves_per_block, hipStream_t s);
 
 // grad_gain[b] = sum_u partial[u * B + b], b < B, fixed order.
 hipError_t launch_gain_reduce(const float *partial, int units, int B, float *grad_gain, hipStream_t s);
 
-// Bands one adjoint launch handles (the host splits larger band counts).
+// Bands one rolling adjoint launch handles (the host splits larger band counts).
 int adjoint_max_bands();
+
+// LDS-staged D4 adjoint (16-byte rows): units are strips of 128 coefficient
+// columns x (kr * wpb) coefficient rows, one workgroup each; any band count.
+hipError_t launch_adjoint_staged(const AdjParams &p, const Filters &f, int kr, int wpb, hipStream_t s);
+size_t adjoint_staged_lds(int T, int B);
+
+// The paper's multi-pass pipeline (comparator); work and scratch are H x W.
+hipError_t launch_multipass(int wavelet, int H, int W, int B, const float *pan, int64_t pan_ld, const float *ms,
+                            int64_t ms_ld, int64_t ms_bs, float *out, int64_t out_ld, int64_t out_bs, float *work,
+                            float *scratch, const Filters &f, hipStream_t s);
 
 }  // namespace dwtf

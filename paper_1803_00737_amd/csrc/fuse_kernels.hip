@@ -406,9 +406,36 @@ __device__ __forceinline__ void haar_tile(const FuseParams &p, int strip, int se
 #pragma unroll
         for (int i = 0; i < KR; ++i) L.load_ms_own(mb + (int64_t)(rb + (i < nr ? i : 0)) * p.ms_ld, m[i]);
     };
+    f2 da[KR][NC], dc[KR][NC];
+    constexpr int MB = 8;
+    if (p.B <= MB) {
+        // Up to 8 bands: every MS row of the tile is in flight together with
+        // the PAN rows; the wavefront then only computes and stores.
+        float mall[MB][KR][NC];
+#pragma unroll
+        for (int b = 0; b < MB; ++b)
+            if (b < p.B) load_band(b, mall[b]);
+#pragma unroll
+        for (int i = 0; i < KR; ++i) haar_details<NC>(a[i], c[i], da[i], dc[i]);
+#pragma unroll
+        for (int b = 0; b < MB; ++b) {
+            if (b >= p.B) break;
+            const float g = p.gain ? p.gain[b] : 1.0f;
+            float *ob = p.out + (int64_t)b * p.out_bs;
+#pragma unroll
+            for (int i = 0; i < KR; ++i) {
+                if (i >= nr) break;
+                f2 q0[NC], q1[NC];
+                haar_out_rows<NC>(g, mall[b][i], da[i], dc[i], q0, q1);
+                float *o0 = ob + (int64_t)(2 * (rb + i)) * p.out_ld;
+                L.store_row(o0, q0);
+                L.store_row(o0 + p.out_ld, q1);
+            }
+        }
+        return;
+    }
     float m[KR][NC];
     load_band(0, m);
-    f2 da[KR][NC], dc[KR][NC];
 #pragma unroll
     for (int i = 0; i < KR; ++i) haar_details<NC>(a[i], c[i], da[i], dc[i]);
     for (int b = 0; b < p.B; ++b) {
@@ -448,7 +475,7 @@ __device__ __forceinline__ void unit_coords(int unit, int nstrips, int nseg, int
     }
 }
 
-// ---- Daubechies-4, LDS-staged workgroup tile (128-bit path) ----------------
+// ---- Daubechies-4, LDS-staged workgroup tile --------------------------------
 //
 // A workgroup of wpb wavefronts covers one strip of 128 coefficient columns
 // (256 output columns) and T = wpb * KR coefficient rows.  It stages, with
@@ -473,14 +500,18 @@ __host__ __device__ constexpr int staged_lds_floats(int T, int bg) {
     return (2 * T + 4) * kStagedPanRow + bg * (T + 1) * kStagedMsRow;
 }
 
-template <int KR>
-__global__ __launch_bounds__(256) void d4_staged_kernel(FuseParams p, Filters f, int bg_max) {
-    extern __shared__ float lds[];
-    const int wpb = blockDim.x >> 6;
+// One staged tile (`unit` of p) by the whole workgroup; every wavefront must
+// call it (it contains barriers).  LAY follows the row alignment: 0 = 16-byte
+// rows (PAN staged with 16-byte loads; a lane owns 2 adjacent coefficient
+// columns and stores 16 bytes), 1 = 8-byte rows and 2 = 4-byte rows (PAN
+// staged with 4-byte loads; a lane owns coefficient columns sb+l and sb+64+l
+// and stores 8 bytes (1) or 4 bytes (2) per column, so each store
+// instruction of the wavefront covers one contiguous 512-byte run).
+template <int KR, int LAY>
+__device__ __forceinline__ void d4_staged_tile(const FuseParams &p, const Filters &f, int bg_max, int unit,
+                                               float *lds, int wpb) {
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int T = wpb * KR;
-    const int unit = xcd_remap(blockIdx.x, gridDim.x);
-    if (unit >= p.units) return;  // whole workgroup
     int strip, trow;
     unit_coords(unit, p.nstrips, p.nseg, p.order, strip, trow);
     const int W2 = p.W >> 1, H2 = p.H >> 1;
@@ -489,12 +520,18 @@ __global__ __launch_bounds__(256) void d4_staged_kernel(FuseParams p, Filters f,
     float *Pl = lds;
     float *Ml = lds + (2 * T + 4) * kStagedPanRow;
 
-    // PAN rows 2r0-2 .. 2r0+2T+1.  Column groups of 4 start at multiples of 4
-    // and W % 4 == 0 on this path, so a group never straddles the wrap.
+    // PAN rows 2r0-2 .. 2r0+2T+1.  On the 16-byte path column groups of 4
+    // start at multiples of 4 and W % 4 == 0, so a group never straddles the
+    // wrap; the other paths stage single floats.
     for (int k = w; k < 2 * T + 4; k += wpb) {
         const float *row = p.pan + (int64_t)wrap_idx(2 * r0 - 2 + k, p.H) * p.pan_ld;
         float *dst = Pl + k * kStagedPanRow;
-        lds_load16(row + wrap_idx(2 * sb + 4 * lane, p.W), dst + 4);
+        if constexpr (LAY == 0) {
+            lds_load16(row + wrap_idx(2 * sb + 4 * lane, p.W), dst + 4);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) lds_load4(row + wrap_idx(2 * sb + 64 * q + lane, p.W), dst + 4 + 64 * q);
+        }
         if (lane < 2) {
             lds_load4(row + wrap_idx(2 * sb - 2 + lane, p.W), dst + 2);
             lds_load4(row + wrap_idx(2 * sb + 256 + lane, p.W), dst + 260);
@@ -516,29 +553,44 @@ __global__ __launch_bounds__(256) void d4_staged_kernel(FuseParams p, Filters f,
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
 
-    // This wavefront: coefficient rows rb .. rb+KR-1; its lane owns
-    // coefficient columns s0, s0+1.
+    // This wavefront: coefficient rows rb .. rb+KR-1.
     const int rb = r0 + KR * w;
     const int nr = max(0, min(KR, H2 - rb));
-    const int s0 = sb + 2 * lane;
-    const bool active = s0 < W2;
-    const bool full = s0 + 2 <= W2;
     constexpr int NR = 2 * KR + 4;  // PAN rows 2rb-2 .. 2rb+2KR+1 = LDS rows 2KR*w + t
-    f2 x[NR][4];
-    float R[NR][3];
+    constexpr int NC = LAY == 0 ? 2 : 1;   // coefficient columns per lane and half
+    constexpr int NH = LAY == 0 ? 1 : 2;   // column halves per lane
+    // Column layout of half h: first own coefficient column s0[h]; its PAN
+    // pairs s0-1 .. s0+NC sit at LDS row positions pos[h] + 2k, MS columns
+    // s0-1 .. s0+NC-1 at mpos[h] + k.
+    int s0[NH], pos[NH], mpos[NH];
 #pragma unroll
-    for (int t = 0; t < NR; ++t) {
-        const float *src = Pl + (2 * KR * w + t) * kStagedPanRow + 4 * lane;
-        x[t][0] = *reinterpret_cast<const f2 *>(src + 2);
-        const f4 v = *reinterpret_cast<const f4 *>(src + 4);
-        x[t][1] = f2{v.x, v.y};
-        x[t][2] = f2{v.z, v.w};
-        x[t][3] = *reinterpret_cast<const f2 *>(src + 8);
-        rowfilt<2>(f, x[t], R[t]);
+    for (int h = 0; h < NH; ++h) {
+        const int c = LAY == 0 ? 2 * lane : 64 * h + lane;  // offset of s0 within the strip
+        s0[h] = sb + c;
+        pos[h] = 2 + 2 * c;
+        mpos[h] = 3 + c;
     }
-    float A[KR + 1][3];
+    f2 xo[NH][2 * KR][NC];  // the lane's PAN pixels of its output rows
+    float A[NH][KR + 1][NC + 1];
 #pragma unroll
-    for (int i = 0; i <= KR; ++i) colfilt<2>(f, R[2 * i], R[2 * i + 1], R[2 * i + 2], R[2 * i + 3], A[i]);
+    for (int h = 0; h < NH; ++h) {
+        float R[NR][NC + 1];
+#pragma unroll
+        for (int t = 0; t < NR; ++t) {
+            const float *src = Pl + (2 * KR * w + t) * kStagedPanRow + pos[h];
+            f2 x[NC + 2];
+#pragma unroll
+            for (int k = 0; k < NC + 2; ++k) x[k] = *reinterpret_cast<const f2 *>(src + 2 * k);
+            rowfilt<NC>(f, x, R[t]);
+            if (t >= 2 && t < 2 + 2 * KR) {
+#pragma unroll
+                for (int i = 0; i < NC; ++i) xo[h][t - 2][i] = x[i + 1];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i <= KR; ++i)
+            colfilt<NC>(f, R[2 * i], R[2 * i + 1], R[2 * i + 2], R[2 * i + 3], A[h][i]);
+    }
 
     for (int g0 = 0; g0 < p.B; g0 += bg_max) {
         const int bg = min(bg_max, p.B - g0);
@@ -550,76 +602,126 @@ __global__ __launch_bounds__(256) void d4_staged_kernel(FuseParams p, Filters f,
         }
         for (int bi = 0; bi < bg; ++bi) {
             const int b = g0 + bi;
-            float m[KR + 1][3];
-#pragma unroll
-            for (int i = 0; i <= KR; ++i) {
-                const float *src = Ml + (bi * (T + 1) + KR * w + i) * kStagedMsRow + 2 * lane;
-                m[i][0] = src[3];
-                const f2 v = *reinterpret_cast<const f2 *>(src + 4);
-                m[i][1] = v.x;
-                m[i][2] = v.y;
-            }
             const float g = p.gain ? p.gain[b] : 1.0f;
             float *ob = p.out + (int64_t)b * p.out_bs;
 #pragma unroll
-            for (int i = 0; i < KR; ++i) {
-                if (i >= nr || !active) break;
-                f2 q0[2], q1[2];
-                d4_out_rows<2>(f, g, m[i + 1], m[i], A[i + 1], A[i], x[2 * i + 2], x[2 * i + 3], q0, q1);
-                float *o0 = ob + (int64_t)(2 * (rb + i)) * p.out_ld + 2 * s0;
-                if (full) {
-                    st4(o0, f4{q0[0].x, q0[0].y, q0[1].x, q0[1].y});
-                    st4(o0 + p.out_ld, f4{q1[0].x, q1[0].y, q1[1].x, q1[1].y});
-                } else {
-                    st2<true>(o0, q0[0]);
-                    st2<true>(o0 + p.out_ld, q1[0]);
+            for (int h = 0; h < NH; ++h) {
+                if (s0[h] >= W2) continue;
+                float m[KR + 1][NC + 1];
+#pragma unroll
+                for (int i = 0; i <= KR; ++i) {
+                    const float *src = Ml + (bi * (T + 1) + KR * w + i) * kStagedMsRow + mpos[h];
+#pragma unroll
+                    for (int j = 0; j <= NC; ++j) m[i][j] = src[j];
+                }
+#pragma unroll
+                for (int i = 0; i < KR; ++i) {
+                    if (i >= nr) break;
+                    // d4_out_rows reads the PAN pixels as pairs 1..NC of a chunk row
+                    f2 xa[NC + 2], xb[NC + 2];
+#pragma unroll
+                    for (int k = 0; k < NC; ++k) {
+                        xa[k + 1] = xo[h][2 * i][k];
+                        xb[k + 1] = xo[h][2 * i + 1][k];
+                    }
+                    f2 q0[NC], q1[NC];
+                    d4_out_rows<NC>(f, g, m[i + 1], m[i], A[h][i + 1], A[h][i], xa, xb, q0, q1);
+                    float *o0 = ob + (int64_t)(2 * (rb + i)) * p.out_ld + 2 * s0[h];
+                    if constexpr (LAY == 0) {
+                        if (s0[h] + 2 <= W2) {
+                            st4(o0, f4{q0[0].x, q0[0].y, q0[1].x, q0[1].y});
+                            st4(o0 + p.out_ld, f4{q1[0].x, q1[0].y, q1[1].x, q1[1].y});
+                        } else {
+                            st2<true>(o0, q0[0]);
+                            st2<true>(o0 + p.out_ld, q1[0]);
+                        }
+                    } else {
+                        st2<LAY == 1>(o0, q0[0]);
+                        st2<LAY == 1>(o0 + p.out_ld, q1[0]);
+                    }
                 }
             }
         }
     }
 }
 
-// KR = 0: rolling over p.seg_rows rows; KR = 1, 2: one-shot tile (seg_rows == KR).
-template <int NC, bool AL, int KR>
-__device__ __forceinline__ void run_unit(const FuseParams &p, const Filters &f, int unit, int lane) {
-    int strip, seg;
-    unit_coords(unit, p.nstrips, p.nseg, p.order, strip, seg);
-    if constexpr (KR == 0) {
-        if (p.wavelet == 1)
-            d4_rolling<NC, AL>(p, f, strip, seg, lane);
-        else
-            haar_rolling<NC, AL>(p, strip, seg, lane);
-    } else {
-        if (p.wavelet == 1)
-            d4_tile<NC, AL, KR>(p, f, strip, seg, lane);
-        else
-            haar_tile<NC, AL, KR>(p, strip, seg, lane);
+template <int KR, int LAY>
+__global__ __launch_bounds__(256) void d4_staged_kernel(FuseParams p, Filters f, int bg_max) {
+    extern __shared__ float lds[];
+    const int unit = xcd_remap(blockIdx.x, gridDim.x);
+    if (unit >= p.units) return;  // whole workgroup
+    d4_staged_tile<KR, LAY>(p, f, bg_max, unit, lds, blockDim.x >> 6);
+}
+
+template <int KR>
+static void launch_staged(const FuseParams &p, const Filters &f, int wpb, size_t lds, int bgm, hipStream_t s) {
+    switch (p.path) {
+        case PATH_V4:
+            hipLaunchKernelGGL((d4_staged_kernel<KR, 0>), dim3(p.units), dim3(64 * wpb), lds, s, p, f, bgm);
+            break;
+        case PATH_V2:
+            hipLaunchKernelGGL((d4_staged_kernel<KR, 1>), dim3(p.units), dim3(64 * wpb), lds, s, p, f, bgm);
+            break;
+        default:
+            hipLaunchKernelGGL((d4_staged_kernel<KR, 2>), dim3(p.units), dim3(64 * wpb), lds, s, p, f, bgm);
+            break;
     }
 }
 
-// One scene: one wavefront per work unit.
-template <int NC, bool AL, int KR>
+// KR = 0: rolling over p.seg_rows rows; KR = 1, 2: one-shot tile (seg_rows == KR).
+// WAV = 0 Haar, 1 D4, -1 read from p.wavelet (batched launches mix wavelets).
+template <int NC, bool AL, int KR, int WAV = -1>
+__device__ __forceinline__ void run_unit(const FuseParams &p, const Filters &f, int unit, int lane) {
+    int strip, seg;
+    unit_coords(unit, p.nstrips, p.nseg, p.order, strip, seg);
+    const bool d4 = WAV < 0 ? p.wavelet == 1 : WAV == 1;
+    if constexpr (KR == 0) {
+        if (d4) {
+            if constexpr (WAV != 0) d4_rolling<NC, AL>(p, f, strip, seg, lane);
+        } else {
+            if constexpr (WAV != 1) haar_rolling<NC, AL>(p, strip, seg, lane);
+        }
+    } else {
+        if (d4) {
+            if constexpr (WAV != 0) d4_tile<NC, AL, KR>(p, f, strip, seg, lane);
+        } else {
+            if constexpr (WAV != 1) haar_tile<NC, AL, KR>(p, strip, seg, lane);
+        }
+    }
+}
+
+// One scene: one wavefront per work unit.  Specialised per wavelet so each
+// gets its own register allocation.
+template <int WAV, int NC, bool AL, int KR>
 __global__ __launch_bounds__(256) void fuse_kernel(FuseParams p, Filters f) {
     const int wpb = blockDim.x >> 6;
     const int lane = threadIdx.x & 63;
     const int unit = xcd_remap(blockIdx.x, gridDim.x) * wpb + (threadIdx.x >> 6);
     if (unit >= p.units) return;
-    run_unit<NC, AL, KR>(p, f, unit, lane);
+    run_unit<NC, AL, KR, WAV>(p, f, unit, lane);
+}
+
+template <int WAV, int KR>
+static void launch_path_w(const FuseParams &p, const Filters &f, int grid, dim3 block, hipStream_t s) {
+    switch (p.path) {
+        case PATH_V4:
+            hipLaunchKernelGGL((fuse_kernel<WAV, 2, true, KR>), dim3(grid), block, 0, s, p, f);
+            break;
+        case PATH_V2:
+            hipLaunchKernelGGL((fuse_kernel<WAV, 1, true, KR>), dim3(grid), block, 0, s, p, f);
+            break;
+        default:
+            hipLaunchKernelGGL((fuse_kernel<WAV, 1, false, KR>), dim3(grid), block, 0, s, p, f);
+            break;
+    }
 }
 
 template <int KR>
 static void launch_path(const FuseParams &p, const Filters &f, int grid, dim3 block, hipStream_t s) {
-    switch (p.path) {
-        case PATH_V4:
-            hipLaunchKernelGGL((fuse_kernel<2, true, KR>), dim3(grid), block, 0, s, p, f);
-            break;
-        case PATH_V2:
-            hipLaunchKernelGGL((fuse_kernel<1, true, KR>), dim3(grid), block, 0, s, p, f);
-            break;
-        default:
-            hipLaunchKernelGGL((fuse_kernel<1, false, KR>), dim3(grid), block, 0, s, p, f);
-            break;
-    }
+    if (p.wavelet == 1)
+        launch_path_w<1, KR>(p, f, grid, block, s);
+    else
+        launch_path_w<0, KR>(p, f, grid, block, s);
 }
 
 // Largest band group whose MS rows fit next to the PAN rows in 64 KB of LDS.
@@ -634,14 +736,15 @@ hipError_t launch_fuse(const FuseParams &p, const Filters &f, int wpb, hipStream
     if (p.units <= 0) return hipSuccess;
     if (p.mode >= 3) {  // LDS-staged: one workgroup per unit, KR = mode - 2 rows per wavefront
         const int kr = p.mode - 2;
-        if (p.path != PATH_V4 || p.seg_rows != wpb * kr) return hipErrorInvalidValue;
+        if (p.wavelet != 1 || p.seg_rows != wpb * kr || p.nstrips != (p.W / 2 + 127) / 128)
+            return hipErrorInvalidValue;
         const int bgm = staged_bg_max(p.seg_rows);
         if (bgm < 1) return hipErrorInvalidValue;
         const size_t lds = sizeof(float) * staged_lds_floats(p.seg_rows, p.B < bgm ? p.B : bgm);
         switch (kr) {
-            case 1: hipLaunchKernelGGL(d4_staged_kernel<1>, dim3(p.units), dim3(64 * wpb), lds, s, p, f, bgm); break;
-            case 2: hipLaunchKernelGGL(d4_staged_kernel<2>, dim3(p.units), dim3(64 * wpb), lds, s, p, f, bgm); break;
-            case 4: hipLaunchKernelGGL(d4_staged_kernel<4>, dim3(p.units), dim3(64 * wpb), lds, s, p, f, bgm); break;
+            case 1: launch_staged<1>(p, f, wpb, lds, bgm, s); break;
+            case 2: launch_staged<2>(p, f, wpb, lds, bgm, s); break;
+            case 4: launch_staged<4>(p, f, wpb, lds, bgm, s); break;
             default: return hipErrorInvalidValue;
         }
         return hipGetLastError();
@@ -747,6 +850,60 @@ hipError_t launch_fuse_batched(const BatchScene *d_scenes, int nscenes, const Ba
             hipLaunchKernelGGL(fuse_batched_kernel<0>, dim3(grid), dim3(256), 0, s, d_scenes, nscenes, q, d_counters, f);
             break;
     }
+    return hipGetLastError();
+}
+
+// ---- flat batched kernel ------------------------------------------------
+//
+// One launch, one workgroup of 4 wavefronts per work item: the item is a
+// staged LDS tile (mode >= 3 scenes) or 4 consecutive one-shot wavefront units
+// (other scenes).  Items of all scenes are numbered consecutively (scene by
+// scene, row bands across the width inside a scene) and remapped so that each
+// XCD takes a contiguous run; a workgroup finds its scene by binary search.
+// Short-lived workgroups keep the memory system busier than a persistent
+// queue on this GPU.
+
+__global__ __launch_bounds__(256) void fuse_batched_flat_kernel(const BatchScene *__restrict__ scenes, int nscenes,
+                                                                int total, int bg_max, Filters f) {
+    extern __shared__ float lds[];
+    const int u = xcd_remap(blockIdx.x, gridDim.x);
+    if (u >= total) return;
+    const int si = find_scene(scenes, nscenes, u);
+    const FuseParams p = scenes[si].p;
+    const int item = u - scenes[si].unit_begin;
+    if (p.mode >= 3) {
+        if (p.path == PATH_V4)
+            d4_staged_tile<2, 0>(p, f, bg_max, item, lds, 4);
+        else if (p.path == PATH_V2)
+            d4_staged_tile<2, 1>(p, f, bg_max, item, lds, 4);
+        else
+            d4_staged_tile<2, 2>(p, f, bg_max, item, lds, 4);
+        return;
+    }
+    const int unit = item * 4 + (threadIdx.x >> 6);
+    if (unit >= p.units) return;
+    const int lane = threadIdx.x & 63;
+    switch (p.path) {
+        case PATH_V4:
+            run_unit<2, true, 1>(p, f, unit, lane);
+            break;
+        case PATH_V2:
+            run_unit<1, true, 1>(p, f, unit, lane);
+            break;
+        default:
+            run_unit<1, false, 1>(p, f, unit, lane);
+            break;
+    }
+}
+
+hipError_t launch_fuse_batched_flat(const BatchScene *d_scenes, int nscenes, int total, int staged_bands,
+                                    const Filters &f, hipStream_t s) {
+    if (nscenes <= 0 || total <= 0) return hipSuccess;
+    const int bgm = staged_bg_max(8);
+    const int bg = staged_bands < bgm ? staged_bands : bgm;
+    const size_t lds = bg > 0 ? sizeof(float) * staged_lds_floats(8, bg) : 0;
+    hipLaunchKernelGGL(fuse_batched_flat_kernel, dim3(total), dim3(256), lds, s, d_scenes, nscenes, total,
+                       bg > 0 ? bg : 1, f);
     return hipGetLastError();
 }
 

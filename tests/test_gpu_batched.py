@@ -54,6 +54,34 @@ def test_small_batch_matches_per_image_and_oracle(dev, fz, oracle, graph):
             assert np.abs(got - ref).max() <= D4_TOL
 
 
+@pytest.mark.parametrize("variant", [1, 2, 3])
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_variants_match_per_image(dev, fz, variant, graph):
+    """Persistent rolling (1), persistent one-shot (2) and flat (3) batched
+    launches give the per-image outputs bit for bit, including D4 scenes on
+    the 128-bit path (LDS-staged tiles in the flat variant), ragged widths
+    and band counts above one staged band group."""
+    rng = np.random.default_rng(600 + variant)
+    shapes = [(64, 1288, 3, "d4"), (34, 136, 9, "d4"), (2, 8, 2, "d4"), (130, 516, 5, "haar"), (66, 262, 4, "d4"),
+              (18, 4070, 2, "d4"), (256, 256, 6, "haar")]
+    scenes = []
+    for H, W, B, w in shapes:
+        pan, ms = int_scene(rng, H, W, B)
+        scenes.append(dict(pan=to_dev(pan, dev), ms=to_dev(ms, dev), wavelet=w))
+    ctx = fz.context(dev)
+    say("batched variant", variant, "graph", graph)
+    try:
+        ctx.force_tile(0, 0, 0, variant)
+        outs = fz.fuse_batched(scenes, graph=graph)
+        outs2 = fz.fuse_batched(scenes, graph=graph)  # replay / relaunch
+    finally:
+        ctx.force_tile(0, 0, 0, 0)
+    for s, o, o2 in zip(scenes, outs, outs2):
+        ref = fz.fuse(s["pan"], s["ms"], s["wavelet"])
+        assert torch.equal(o, ref)
+        assert torch.equal(o2, ref)
+
+
 def test_batch_with_pitches_and_misalignment(dev, fz):
     rng = np.random.default_rng(9)
     scenes = []

@@ -48,7 +48,10 @@ def check_grads(oracle, w, pan, gy, gain, got):
         assert abs(gg[b] - rg[b]) <= bound, (b, gg[b], rg[b], bound)
 
 
-SHAPES = [(2, 2), (4, 6), (34, 70), (66, 1030), (130, 258), (64, 4070)]
+# widths = 2 mod 4 take the 64-bit (rolling) adjoint; multiples of 4 the
+# LDS-staged one (1288 = 5 full strips + a partial one; odd H/2 = partial tiles)
+SHAPES = [(2, 2), (4, 6), (34, 70), (66, 1030), (130, 258), (64, 4070), (8, 8), (34, 136), (130, 1288),
+          (66, 516), (2, 4)]
 
 
 @pytest.mark.parametrize("H,W", SHAPES)
@@ -80,7 +83,7 @@ def test_adjoint_paths(dev, fz, oracle, wavelet, pad, offset):
 def test_dot_product(dev, fz, wavelet):
     """<J x, y> = <x, J^T y> for the map (pan, ms) -> out at fixed gains."""
     rng = np.random.default_rng(11)
-    H, W, B = 66, 262, 3
+    H, W, B = 66, 264, 3
     pan = to_dev(rng.normal(size=(H, W)).astype(np.float32), dev)
     ms = to_dev(rng.normal(size=(B, H // 2, W // 2)).astype(np.float32), dev)
     y = to_dev(rng.normal(size=(B, H, W)).astype(np.float32), dev)
