@@ -191,7 +191,10 @@ dwt_fuse_status dwt_fuse_tune_load(dwt_fuse_ctx *ctx, const char *path);
  * that issue all their loads up front; 3 = LDS-staged workgroups whose
  * wavefronts take seg_rows = 1, 2 or 4 rows each, D4 with 16-byte aligned rows
  * only, otherwise 2 is used).  Every shape gives bit-identical results.
- * DWT_FUSE_E_SHAPE if a field is out of range. */
+ * dwt_fuse_backward follows the rows, waves and columns fields with its
+ * rolling adjoint; variant 3 selects its LDS-staged D4 adjoint (16-byte
+ * aligned rows, 1 or 2 rows per wavefront, up to 4 waves), which is otherwise
+ * never used.  DWT_FUSE_E_SHAPE if a field is out of range. */
 dwt_fuse_status dwt_fuse_force_tile(dwt_fuse_ctx *ctx, int seg_rows, int waves_per_block, int cols_per_lane,
                                     int variant);
 

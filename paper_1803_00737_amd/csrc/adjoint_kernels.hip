@@ -585,17 +585,6 @@ __global__ __launch_bounds__(256) void d4_adjoint_staged_kernel(AdjParams p, Fil
         float dot = 0.f;
         if (active) {
 #pragma unroll
-            for (int i = 0; i < KR; ++i) {
-                if (i >= nr) break;
-                if (p.grad_ms) {
-                    float *gm = p.grad_ms + (int64_t)b * H2 * W2 + (int64_t)(rb + i) * W2 + s0;
-                    if (full)
-                        *reinterpret_cast<f2 *>(gm) = f2{Ly[i + 1][1], Ly[i + 1][2]};
-                    else
-                        gm[0] = Ly[i + 1][1];
-                }
-            }
-#pragma unroll
             for (int t = 0; t < 2 * KR; ++t) {
                 if (t >= 2 * nr) break;
 #pragma unroll
@@ -614,8 +603,21 @@ __global__ __launch_bounds__(256) void d4_adjoint_staged_kernel(AdjParams p, Fil
             const float sd = wave_sum(dot);
             if (lane == 0) red[b * wpb + w] = sd;
         }
-        __builtin_amdgcn_s_waitcnt(0);  // band b+1 has landed
-        __syncthreads();                // and every wavefront is done with band b
+        // Wait for band b+1's rows before this band's stores are issued, so
+        // the wait does not include them (the counter also covers stores).
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();  // every wavefront is done with band b's buffer
+        if (active && p.grad_ms) {
+#pragma unroll
+            for (int i = 0; i < KR; ++i) {
+                if (i >= nr) break;
+                float *gm = p.grad_ms + (int64_t)b * H2 * W2 + (int64_t)(rb + i) * W2 + s0;
+                if (full)
+                    *reinterpret_cast<f2 *>(gm) = f2{Ly[i + 1][1], Ly[i + 1][2]};
+                else
+                    gm[0] = Ly[i + 1][1];
+            }
+        }
     }
     // grad_pan = Y - L^T L Y at the lane's pixels.
     if (p.grad_pan && active) {

@@ -1135,11 +1135,16 @@ dwt_fuse_status dwt_fuse_backward(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet, i
         if (!grad_pan && !grad_ms && !grad_gain) return DWT_FUSE_OK;
         if ((st = use_device(ctx))) return st;
         const Path path = choose_bwd_path(a);
-        // D4 on 16-byte rows: LDS-staged adjoint (4 wavefronts x 1 row, all bands in one launch).
-        const bool staged = a.wavelet == DWT_FUSE_D4 && path == PATH_V4 && ctx->forced.variant != 1 &&
-                            ctx->forced.variant != 2 && adjoint_staged_lds(4, (int)B) <= 65536;
+        // D4 on 16-byte rows, on request only (forced variant 3): the LDS-staged
+        // adjoint (wpb wavefronts x kr rows, all bands in one launch).  The
+        // rolling adjoint below is faster on every shape measured, so it is the
+        // default.
+        const int skr = ctx->forced.seg_rows == 2 ? 2 : 1;
+        const int swpb = ctx->forced.wpb >= 1 && ctx->forced.wpb <= 4 ? ctx->forced.wpb : 4;
+        const bool staged = a.wavelet == DWT_FUSE_D4 && path == PATH_V4 && ctx->forced.variant == 3 &&
+                            adjoint_staged_lds(skr * swpb, (int)B) <= 65536;
         if (staged) {
-            const int kr = 1, wpb = 4, T = kr * wpb;
+            const int kr = skr, wpb = swpb, T = kr * wpb;
             const int64_t ns = (W / 2 + 127) / 128, ng = (H / 2 + T - 1) / T;
             if (ns * ng > INT32_MAX) return fail(ctx, DWT_FUSE_E_SHAPE, "too many work units");
             const int units = (int)(ns * ng);

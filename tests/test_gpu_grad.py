@@ -48,8 +48,8 @@ def check_grads(oracle, w, pan, gy, gain, got):
         assert abs(gg[b] - rg[b]) <= bound, (b, gg[b], rg[b], bound)
 
 
-# widths = 2 mod 4 take the 64-bit (rolling) adjoint; multiples of 4 the
-# LDS-staged one (1288 = 5 full strips + a partial one; odd H/2 = partial tiles)
+# widths = 2 mod 4 take the 64-bit path, multiples of 4 the 128-bit one
+# (1288 = 5 full 256-column strips + a partial one; odd H/2 = partial units)
 SHAPES = [(2, 2), (4, 6), (34, 70), (66, 1030), (130, 258), (64, 4070), (8, 8), (34, 136), (130, 1288),
           (66, 516), (2, 4)]
 
@@ -65,6 +65,37 @@ def test_adjoint_matches_oracle(dev, fz, oracle, wavelet, H, W, B):
     say("adjoint", wavelet, H, W, B)
     got = fz.fuse_backward(to_dev(pan, dev), to_dev(gy, dev), wavelet, to_dev(gain, dev))
     check_grads(oracle, wavelet, pan, gy, gain, [t.cpu().numpy() for t in got])
+
+
+@pytest.mark.parametrize("H,W", [(8, 8), (34, 136), (130, 1288), (66, 516), (2, 4), (66, 1030)])
+@pytest.mark.parametrize("B", [1, 4, 10])
+def test_forced_adjoint_shapes(dev, fz, oracle, H, W, B):
+    """Forced launch shapes of the adjoint: rolling wavefronts with several
+    rows per unit / waves per workgroup / columns per lane, and the LDS-staged
+    D4 adjoint (variant 3, 1 or 2 rows per wavefront).  Every shape must meet
+    the oracle's tolerance; the rolling shapes evaluate every per-pixel
+    gradient with the same operations in the same order, so they also agree
+    bit for bit."""
+    rng = np.random.default_rng(7 * H + W + B)
+    pan, _ = int_scene(rng, H, W, 1)
+    gy = rng.normal(size=(B, H, W)).astype(np.float32)
+    gain = rng.uniform(0.5, 1.5, B).astype(np.float32)
+    p, y, g = to_dev(pan, dev), to_dev(gy, dev), to_dev(gain, dev)
+    ctx = fz.context(dev)
+    outs = []
+    try:
+        for seg, wpb, nc, var in [(0, 0, 0, 0), (1, 1, 1, 1), (3, 2, 2, 1), (16, 4, 2, 1), (200, 1, 1, 1),
+                                  (1, 4, 2, 3), (2, 2, 2, 3), (1, 1, 2, 3), (2, 4, 2, 3)]:
+            say("adjoint forced", H, W, B, seg, wpb, nc, var)
+            ctx.force_tile(seg, wpb, nc, var)
+            got = [t.cpu().numpy() for t in fz.fuse_backward(p, y, "d4", g)]
+            check_grads(oracle, "d4", pan, gy, gain, got)
+            if var != 3:
+                outs.append(got)
+    finally:
+        ctx.force_tile(0, 0, 0, 0)
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
 
 
 @pytest.mark.parametrize("wavelet", ["haar", "d4"])
