@@ -68,6 +68,10 @@ def _load():
             getattr(lib, name).restype = ci
         lib.oracle_fuse.argtypes = [ci, i64, i64, i64, dp, dp, dp, dp]
         lib.oracle_fuse.restype = ci
+        lib.oracle_fuse_kappa.argtypes = [ci, i64, i64, i64, dp, dp, dp, ctypes.c_double, dp]
+        lib.oracle_fuse_kappa.restype = ci
+        lib.oracle_quantize_u8.argtypes = [i64, dp, ctypes.POINTER(ctypes.c_uint8)]
+        lib.oracle_quantize_u8.restype = ci
         lib.oracle_fuse_point.argtypes = [ci, i64, i64, dp, dp, ctypes.c_double, i64, i64]
         lib.oracle_fuse_point.restype = ctypes.c_double
         lib.oracle_fuse_backward.argtypes = [ci, i64, i64, i64, dp, dp, dp, dp, dp, dp]
@@ -161,8 +165,9 @@ def _gain(gain, B):
     return g
 
 
-def fuse(w, pan, ms, gain=None):
-    """Fused images (B, H, W) float64 for PAN (H, W) and MS (B, H/2, W/2)."""
+def fuse(w, pan, ms, gain=None, kappa=1.0):
+    """Fused images (B, H, W) float64 for PAN (H, W) and MS (B, H/2, W/2);
+    the MS band replaces LL multiplied by ``kappa`` (1 = as printed)."""
     lib = _load()
     pan = _f64(pan)
     ms = _f64(ms)
@@ -174,7 +179,29 @@ def fuse(w, pan, ms, gain=None):
         raise ValueError("ms must be (B, H/2, W/2)")
     g = _gain(gain, B)
     out = np.empty((B, H, W), dtype=np.float64)
-    _check(lib.oracle_fuse(_wav(w), H, W, B, _ptr(pan), _ptr(ms), _ptr(g), _ptr(out)), "fuse")
+    if kappa == 1.0:
+        _check(lib.oracle_fuse(_wav(w), H, W, B, _ptr(pan), _ptr(ms), _ptr(g), _ptr(out)), "fuse")
+    else:
+        _check(lib.oracle_fuse_kappa(_wav(w), H, W, B, _ptr(pan), _ptr(ms), _ptr(g), float(kappa), _ptr(out)),
+               "fuse_kappa")
+    return out
+
+
+def dc_kappa(w) -> float:
+    """kappa that matches the DC gain of the analysis LL, (sum of the
+    low-pass taps)^2: 2 for D4 (the taps of Eq. 7-8 sum to sqrt 2), 1 for the
+    divided-by-2 Haar of Eq. 1-2."""
+    return 2.0 if _wav(w) == D4 else 1.0
+
+
+def quantize_u8(v):
+    """8-bit code of each value: nearest integer, ties to even, clamped to
+    [0, 255], NaN -> 0 (section 3's 8-bit image representation)."""
+    lib = _load()
+    v = _f64(v)
+    out = np.empty(v.shape, dtype=np.uint8)
+    _check(lib.oracle_quantize_u8(v.size, _ptr(v), out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))),
+           "quantize_u8")
     return out
 
 

@@ -261,9 +261,9 @@ int oracle_dwt2_inv(int w, int64_t H, int64_t W, const double *X, double *x)
 }
 
 /* Section 2, method steps 1-3, for each band: forward 2D of PAN, LL replaced
- * by the band, details scaled by the band's gain, inverse 2D. */
-int oracle_fuse(int w, int64_t H, int64_t W, int64_t B, const double *pan,
-                const double *ms, const double *gain, double *out)
+ * by the band (times kappa), details scaled by the band's gain, inverse 2D. */
+int oracle_fuse_kappa(int w, int64_t H, int64_t W, int64_t B, const double *pan,
+                      const double *ms, const double *gain, double kappa, double *out)
 {
     if (!valid_wavelet(w) || !valid_len(H) || !valid_len(W) || B < 0) return -1;
     const int64_t H2 = H / 2, W2 = W / 2, n = H * W;
@@ -280,11 +280,39 @@ int oracle_fuse(int w, int64_t H, int64_t W, int64_t B, const double *pan,
         const double *m = ms + b * H2 * W2;
         for (int64_t i = 0; i < H; ++i)
             for (int64_t j = 0; j < W; ++j)
-                Xb[i * W + j] = (i < H2 && j < W2) ? m[i * W2 + j] : gb * X[i * W + j];
+                Xb[i * W + j] = (i < H2 && j < W2) ? kappa * m[i * W2 + j] : gb * X[i * W + j];
         oracle_dwt2_inv(w, H, W, Xb, out + b * n);
     }
     free(X);
     free(Xb);
+    return 0;
+}
+
+int oracle_fuse(int w, int64_t H, int64_t W, int64_t B, const double *pan,
+                const double *ms, const double *gain, double *out)
+{
+    return oracle_fuse_kappa(w, H, W, B, pan, ms, gain, 1.0, out);
+}
+
+/* Section 3 keeps images at 8 bits per pixel.  A fused value v becomes the
+ * integer nearest to v (a value exactly halfway between two integers goes to
+ * the even one), limited to [0, 255]. */
+int oracle_quantize_u8(int64_t n, const double *v, uint8_t *out)
+{
+    if (n < 0) return -1;
+    for (int64_t i = 0; i < n; ++i) {
+        const double x = v[i];
+        if (x != x) {  /* NaN */
+            out[i] = 0;
+            continue;
+        }
+        double r = floor(x);
+        const double frac = x - r;  /* exact for |x| < 2^52 */
+        if (frac > 0.5 || (frac == 0.5 && fmod(r, 2.0) != 0.0)) r += 1.0;
+        if (r < 0.0) r = 0.0;
+        if (r > 255.0) r = 255.0;
+        out[i] = (uint8_t)r;
+    }
     return 0;
 }
 

@@ -64,6 +64,19 @@ int oracle_fuse(int wavelet, int64_t H, int64_t W, int64_t B,
                 const double *pan, const double *ms, const double *gain,
                 double *out);
 
+/* The same fusion with the MS band scaled by kappa before it replaces LL
+ * (kappa = 1 is the method as printed; kappa = (sum of the low-pass taps)^2
+ * matches the DC gain of the analysis LL, i.e. 2 for D4 and 1 for the
+ * divided-by-2 Haar of Eq. 1-2). */
+int oracle_fuse_kappa(int wavelet, int64_t H, int64_t W, int64_t B,
+                      const double *pan, const double *ms, const double *gain,
+                      double kappa, double *out);
+
+/* Eight-bit code of n values (the 8-bit-per-pixel image representation of
+ * section 3): nearest integer with ties to the even neighbour, clamped to
+ * [0, 255]; NaN becomes 0. */
+int oracle_quantize_u8(int64_t n, const double *v, uint8_t *out);
+
 /* One output pixel (y, x) of the fusion with one MS band, evaluated from
  * the same 1D equations restricted to the coefficients that pixel needs. */
 double oracle_fuse_point(int wavelet, int64_t H, int64_t W,
