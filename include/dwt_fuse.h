@@ -53,7 +53,8 @@ typedef enum {
     DWT_FUSE_E_ALIAS = 5,   /* an output's byte range overlaps an input's */
     DWT_FUSE_E_NOMEM = 6,   /* context workspace could not be allocated */
     DWT_FUSE_E_DEVICE = 7,  /* HIP error (bad device, launch failure, earlier fault) */
-    DWT_FUSE_E_STATE = 8    /* context unusable (e.g. created for another device) */
+    DWT_FUSE_E_STATE = 8,   /* context unusable (e.g. created for another device) */
+    DWT_FUSE_E_FORMAT = 9   /* element format not in dwt_fuse_format */
 } dwt_fuse_status;
 
 typedef struct dwt_fuse_ctx dwt_fuse_ctx; /* opaque */
@@ -89,6 +90,58 @@ dwt_fuse_status dwt_fuse_run(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet,
                              const float *ms, int64_t ms_ld, int64_t ms_band_stride,
                              const float *gain,
                              float *out, int64_t out_ld, int64_t out_band_stride);
+
+/* Element formats of dwt_fuse_run_ex. */
+typedef enum { DWT_FUSE_F32 = 0, DWT_FUSE_U8 = 1 } dwt_fuse_format;
+
+typedef struct {
+    int32_t in_format;  /* dwt_fuse_format of pan and ms */
+    int32_t out_format; /* dwt_fuse_format of out */
+    float kappa;        /* LL <- kappa * MS band (1 = as printed) */
+} dwt_fuse_opts;
+
+/* dwt_fuse_run with a choice of element formats and of the scale of the
+ * inserted MS band.
+ *   - in_format DWT_FUSE_U8: pan and ms hold 8-bit pixels (uint8_t), the
+ *     8-bit-per-pixel representation the paper moves images in (section 3).
+ *   - out_format DWT_FUSE_U8: each output pixel is the float32 value that
+ *     out_format DWT_FUSE_F32 gives, rounded to the nearest integer (ties to
+ *     the even one), clamped to [0, 255], NaN -> 0.
+ *   - kappa scales the MS band where it replaces LL (section 2, step 2).  1 is
+ *     the method as printed; 2 = (sum of the D4 low-pass taps of Eq. 7-8)^2
+ *     matches the DC gain of the D4 analysis LL, so that a band at MS
+ *     radiometry keeps its mean level (with 1, D4 output has half the MS mean).
+ * Pitches and band strides are in elements of each buffer's own format.
+ * opts NULL = {F32, F32, 1}.  With opts {F32, F32, 1} this is dwt_fuse_run.
+ * For every format the float32 values equal dwt_fuse_run's on the same
+ * (converted) inputs and gains times kappa on the MS band, bit for bit.
+ * DWT_FUSE_E_FORMAT for a format outside the enum; other errors as in
+ * dwt_fuse_run, with byte ranges computed from each format's element size.
+ * Allocates nothing. */
+dwt_fuse_status dwt_fuse_run_ex(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet,
+                                int64_t H, int64_t W, int64_t B,
+                                const void *pan, int64_t pan_ld,
+                                const void *ms, int64_t ms_ld, int64_t ms_band_stride,
+                                const float *gain,
+                                void *out, int64_t out_ld, int64_t out_band_stride,
+                                const dwt_fuse_opts *opts);
+
+/* Quality diagnostics of B fused bands against B reference bands (e.g. the
+ * full-resolution truth of a synthetic scene), both H x W float32 on the
+ * device with their own pitches and band strides:
+ *     out[b]     = sum over pixels of (fused_b - ref_b)^2
+ *     out[B + b] = sum over pixels of ref_b
+ * accumulated in FP64 in a fixed order (reproducible bit for bit); out is a
+ * device array of 2*B doubles.  From these, RMSE_b = sqrt(out[b] / (H*W)),
+ * mean_b = out[B+b] / (H*W), and an ERGAS-style score
+ * 100 * (1/2) * sqrt(mean over b of (RMSE_b / mean_b)^2) for the 1:2 PAN:MS
+ * pixel-size ratio of section 2 (the paper names ERGAS in section 4 without
+ * defining it).  H, W >= 1; 1 <= B <= 65535.  Uses context workspace
+ * (DWT_FUSE_E_NOMEM if it cannot grow); out must not overlap the inputs. */
+dwt_fuse_status dwt_fuse_quality(dwt_fuse_ctx *ctx, int64_t H, int64_t W, int64_t B,
+                                 const float *fused, int64_t fused_ld, int64_t fused_band_stride,
+                                 const float *ref, int64_t ref_ld, int64_t ref_band_stride,
+                                 double *out);
 
 /* One independent scene of a batch; fields as in dwt_fuse_run. */
 typedef struct {
@@ -158,6 +211,16 @@ dwt_fuse_status dwt_fuse_check_run(dwt_fuse_wavelet wavelet, int64_t H, int64_t 
                                    const float *ms, int64_t ms_ld, int64_t ms_band_stride,
                                    const float *gain,
                                    const float *out, int64_t out_ld, int64_t out_band_stride);
+dwt_fuse_status dwt_fuse_check_run_ex(dwt_fuse_wavelet wavelet, int64_t H, int64_t W, int64_t B,
+                                      const void *pan, int64_t pan_ld,
+                                      const void *ms, int64_t ms_ld, int64_t ms_band_stride,
+                                      const float *gain,
+                                      const void *out, int64_t out_ld, int64_t out_band_stride,
+                                      const dwt_fuse_opts *opts);
+dwt_fuse_status dwt_fuse_check_quality(int64_t H, int64_t W, int64_t B,
+                                       const float *fused, int64_t fused_ld, int64_t fused_band_stride,
+                                       const float *ref, int64_t ref_ld, int64_t ref_band_stride,
+                                       const double *out);
 dwt_fuse_status dwt_fuse_check_batched(const dwt_fuse_item *items, int64_t n);
 dwt_fuse_status dwt_fuse_check_backward(dwt_fuse_wavelet wavelet, int64_t H, int64_t W, int64_t B,
                                         const float *pan, int64_t pan_ld, const float *gain,

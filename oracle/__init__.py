@@ -72,6 +72,8 @@ def _load():
         lib.oracle_fuse_kappa.restype = ci
         lib.oracle_quantize_u8.argtypes = [i64, dp, ctypes.POINTER(ctypes.c_uint8)]
         lib.oracle_quantize_u8.restype = ci
+        lib.oracle_quality.argtypes = [i64, i64, i64, dp, dp, dp, dp]
+        lib.oracle_quality.restype = ci
         lib.oracle_fuse_point.argtypes = [ci, i64, i64, dp, dp, ctypes.c_double, i64, i64]
         lib.oracle_fuse_point.restype = ctypes.c_double
         lib.oracle_fuse_backward.argtypes = [ci, i64, i64, i64, dp, dp, dp, dp, dp, dp]
@@ -192,6 +194,29 @@ def dc_kappa(w) -> float:
     low-pass taps)^2: 2 for D4 (the taps of Eq. 7-8 sum to sqrt 2), 1 for the
     divided-by-2 Haar of Eq. 1-2."""
     return 2.0 if _wav(w) == D4 else 1.0
+
+
+def quality(fused, ref):
+    """Per-band quality of fused (B, H, W) against ref (B, H, W): dict with
+    sse, sum_ref (arrays of B), rmse, mean and the ERGAS-style score
+    100 * (1/2) * sqrt(mean_b (rmse_b / mean_b)^2) (PAN pixels half the MS
+    pixel size, section 2)."""
+    lib = _load()
+    f = _f64(fused)
+    r = _f64(ref)
+    if f.ndim == 2:
+        f, r = f[None], r[None]
+    if f.shape != r.shape:
+        raise ValueError("fused and ref must have the same shape")
+    B, H, W = f.shape
+    sse = np.empty(B)
+    sr = np.empty(B)
+    _check(lib.oracle_quality(H, W, B, _ptr(f), _ptr(r), _ptr(sse), _ptr(sr)), "quality")
+    n = float(H * W)
+    rmse = np.sqrt(sse / n)
+    mean = sr / n
+    return {"sse": sse, "sum_ref": sr, "rmse": rmse, "mean": mean,
+            "ergas": 100.0 * 0.5 * float(np.sqrt(np.mean((rmse / mean) ** 2)))}
 
 
 def quantize_u8(v):

@@ -294,6 +294,25 @@ int oracle_fuse(int w, int64_t H, int64_t W, int64_t B, const double *pan,
     return oracle_fuse_kappa(w, H, W, B, pan, ms, gain, 1.0, out);
 }
 
+/* Squared-error and reference sums per band, the inputs of RMSE and of an
+ * ERGAS-style score (section 4 names ERGAS without a formula). */
+int oracle_quality(int64_t H, int64_t W, int64_t B, const double *fused,
+                   const double *ref, double *sse, double *sum_ref)
+{
+    if (H < 1 || W < 1 || B < 1) return -1;
+    for (int64_t b = 0; b < B; ++b) {
+        double e = 0.0, s = 0.0;
+        for (int64_t i = 0; i < H * W; ++i) {
+            const double d = fused[b * H * W + i] - ref[b * H * W + i];
+            e += d * d;
+            s += ref[b * H * W + i];
+        }
+        sse[b] = e;
+        sum_ref[b] = s;
+    }
+    return 0;
+}
+
 /* Section 3 keeps images at 8 bits per pixel.  A fused value v becomes the
  * integer nearest to v (a value exactly halfway between two integers goes to
  * the even one), limited to [0, 255]. */

@@ -77,6 +77,11 @@ int oracle_fuse_kappa(int wavelet, int64_t H, int64_t W, int64_t B,
  * [0, 255]; NaN becomes 0. */
 int oracle_quantize_u8(int64_t n, const double *v, uint8_t *out);
 
+/* Quality sums of B fused bands against B reference bands (H x W each):
+ * sse[b] = sum of (fused - ref)^2, sum_ref[b] = sum of ref. */
+int oracle_quality(int64_t H, int64_t W, int64_t B, const double *fused,
+                   const double *ref, double *sse, double *sum_ref);
+
 /* One output pixel (y, x) of the fusion with one MS band, evaluated from
  * the same 1D equations restricted to the coefficients that pixel needs. */
 double oracle_fuse_point(int wavelet, int64_t H, int64_t W,

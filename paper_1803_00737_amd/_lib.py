@@ -21,16 +21,25 @@ EXPORTS = (
     "dwt_fuse_run_batched", "dwt_fuse_backward", "dwt_fuse_check_run", "dwt_fuse_check_batched",
     "dwt_fuse_check_backward", "dwt_fuse_status_str", "dwt_fuse_last_error", "dwt_fuse_set_tuning",
     "dwt_fuse_tune_save", "dwt_fuse_tune_load", "dwt_fuse_force_tile", "dwt_fuse_run_multipass",
+    "dwt_fuse_run_ex", "dwt_fuse_check_run_ex", "dwt_fuse_quality", "dwt_fuse_check_quality",
 )
 
 HAAR = 0
 D4 = 1
 WAVELETS = {"haar": HAAR, "d4": D4}
 
-OK, E_NULL, E_SHAPE, E_WAVELET, E_STRIDE, E_ALIAS, E_NOMEM, E_DEVICE, E_STATE = range(9)
+OK, E_NULL, E_SHAPE, E_WAVELET, E_STRIDE, E_ALIAS, E_NOMEM, E_DEVICE, E_STATE, E_FORMAT = range(10)
 STATUS_NAMES = {0: "OK", 1: "E_NULL", 2: "E_SHAPE", 3: "E_WAVELET", 4: "E_STRIDE", 5: "E_ALIAS",
-                6: "E_NOMEM", 7: "E_DEVICE", 8: "E_STATE"}
+                6: "E_NOMEM", 7: "E_DEVICE", 8: "E_STATE", 9: "E_FORMAT"}
 GRAPH = 1
+F32 = 0
+U8 = 1
+
+
+class Opts(ctypes.Structure):
+    """dwt_fuse_opts."""
+
+    _fields_ = [("in_format", ctypes.c_int32), ("out_format", ctypes.c_int32), ("kappa", ctypes.c_float)]
 
 
 class Item(ctypes.Structure):
@@ -103,6 +112,16 @@ def load(require_torch: bool = True):
         lib.dwt_fuse_force_tile.restype = st
         lib.dwt_fuse_run_multipass.argtypes = [vp, i32, i64, i64, i64, vp, i64, vp, i64, i64, vp, i64, i64]
         lib.dwt_fuse_run_multipass.restype = st
+        ex_args = run_args + [ctypes.POINTER(Opts)]
+        lib.dwt_fuse_run_ex.argtypes = [vp] + ex_args
+        lib.dwt_fuse_run_ex.restype = st
+        lib.dwt_fuse_check_run_ex.argtypes = ex_args
+        lib.dwt_fuse_check_run_ex.restype = st
+        q_args = [i64, i64, i64, vp, i64, i64, vp, i64, i64, vp]
+        lib.dwt_fuse_quality.argtypes = [vp] + q_args
+        lib.dwt_fuse_quality.restype = st
+        lib.dwt_fuse_check_quality.argtypes = q_args
+        lib.dwt_fuse_check_quality.restype = st
         _lib = lib
         return lib
 

@@ -81,13 +81,16 @@ def context(device=None) -> Context:
         return c
 
 
-def _require(t: torch.Tensor, name: str, ndim: int):
+_FORMATS = {torch.float32: _lib.F32, torch.uint8: _lib.U8}
+
+
+def _require(t: torch.Tensor, name: str, ndim: int, dtype=torch.float32):
     if not isinstance(t, torch.Tensor):
         raise TypeError("%s must be a torch.Tensor" % name)
     if not t.is_cuda:
         raise ValueError("%s must be on a GPU (there is no CPU path)" % name)
-    if t.dtype != torch.float32:
-        raise TypeError("%s must be float32, got %s" % (name, t.dtype))
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
     if t.dim() != ndim:
         raise ValueError("%s must have %d dimensions, got shape %s" % (name, ndim, tuple(t.shape)))
 
@@ -113,11 +116,13 @@ def _pitch(t: torch.Tensor, dim: int) -> int:
     return t.stride(dim)
 
 
-def _prep_scene(pan, ms, gain, out):
-    _require(pan, "pan", 2)
+def _prep_scene(pan, ms, gain, out, out_dtype=torch.float32, allow_u8=False):
+    u8 = allow_u8 and isinstance(pan, torch.Tensor) and pan.dtype == torch.uint8
+    in_dtype = torch.uint8 if u8 else torch.float32
+    _require(pan, "pan", 2, in_dtype)
     if ms.dim() == 2:
         ms = ms.unsqueeze(0)
-    _require(ms, "ms", 3)
+    _require(ms, "ms", 3, in_dtype)
     pan = _rows_unit(pan)
     ms = _rows_unit(ms)
     H, W = pan.shape
@@ -132,9 +137,9 @@ def _prep_scene(pan, ms, gain, out):
         if gain.shape[0] != B:
             raise ValueError("gain must have B=%d entries" % B)
     if out is None:
-        out = torch.empty((B, H, W), dtype=torch.float32, device=pan.device)
+        out = torch.empty((B, H, W), dtype=out_dtype, device=pan.device)
     else:
-        _require(out, "out", 3)
+        _require(out, "out", 3, out_dtype)
         if tuple(out.shape) != (B, H, W):
             raise ValueError("out must be (B, H, W)")
         if out.stride(-1) != 1:
@@ -143,20 +148,71 @@ def _prep_scene(pan, ms, gain, out):
 
 
 def fuse(pan: torch.Tensor, ms: torch.Tensor, wavelet="d4", gain: Optional[torch.Tensor] = None,
-         out: Optional[torch.Tensor] = None) -> torch.Tensor:
+         out: Optional[torch.Tensor] = None, out_dtype=None, kappa: float = 1.0) -> torch.Tensor:
     """Fused bands (B, H, W) for PAN (H, W) and MS (B, H/2, W/2) (or (H/2, W/2)).
 
     Section 2 of the paper: forward 2D DWT of PAN, LL quadrant replaced by each
     MS band, inverse 2D DWT (Haar Eq. 1-2/11-12 or D4 Eq. 3-16 with wrap).
-    ``gain`` (B,) scales the PAN detail quadrants per band (None = 1)."""
-    pan, ms, gain, out, H, W, B = _prep_scene(pan, ms, gain, out)
+    ``gain`` (B,) scales the PAN detail quadrants per band (None = 1).
+
+    pan/ms may be float32 or uint8 (8-bit pixels); ``out_dtype`` float32 or
+    uint8 (nearest integer, ties to even, clamped to [0, 255]; default: the
+    dtype of ``out`` if given, else float32).  ``kappa`` scales the MS band where
+    it replaces LL (1 = as printed, 2 = DC-matched D4)."""
+    if out_dtype is None:
+        out_dtype = out.dtype if isinstance(out, torch.Tensor) else torch.float32
+    if out_dtype not in _FORMATS:
+        raise TypeError("out_dtype must be float32 or uint8, got %s" % (out_dtype,))
+    pan, ms, gain, out, H, W, B = _prep_scene(pan, ms, gain, out, out_dtype, allow_u8=True)
     c = context(pan.device)
     c.bind_stream()
-    st = c.lib.dwt_fuse_run(c.handle, wavelet_id(wavelet), H, W, B,
-                            _ptr(pan), _pitch(pan, 0), _ptr(ms), _pitch(ms, 1), _pitch(ms, 0),
-                            _ptr(gain), _ptr(out), _pitch(out, 1), _pitch(out, 0))
-    c.check(st, "dwt_fuse_run")
+    if pan.dtype == torch.float32 and out_dtype == torch.float32 and float(kappa) == 1.0:
+        st = c.lib.dwt_fuse_run(c.handle, wavelet_id(wavelet), H, W, B,
+                                _ptr(pan), _pitch(pan, 0), _ptr(ms), _pitch(ms, 1), _pitch(ms, 0),
+                                _ptr(gain), _ptr(out), _pitch(out, 1), _pitch(out, 0))
+        c.check(st, "dwt_fuse_run")
+        return out
+    opts = _lib.Opts(_FORMATS[pan.dtype], _FORMATS[out_dtype], float(kappa))
+    st = c.lib.dwt_fuse_run_ex(c.handle, wavelet_id(wavelet), H, W, B,
+                               _ptr(pan), _pitch(pan, 0), _ptr(ms), _pitch(ms, 1), _pitch(ms, 0),
+                               _ptr(gain), _ptr(out), _pitch(out, 1), _pitch(out, 0), ctypes.byref(opts))
+    c.check(st, "dwt_fuse_run_ex")
     return out
+
+
+def quality(fused: torch.Tensor, ref: torch.Tensor) -> dict:
+    """Quality of fused bands (B, H, W) against reference bands of the same
+    shape (e.g. a synthetic full-resolution truth), float32 on the GPU.
+
+    The per-band sums (squared error, reference) are reduced on the GPU in
+    FP64; returns dict with ``sse``, ``sum_ref`` (float64 tensors of B, on the
+    device), ``rmse`` and ``mean`` (lists), and ``ergas`` =
+    100 * (1/2) * sqrt(mean_b (rmse_b / mean_b)^2) for the 1:2 PAN:MS pixel
+    size of section 2."""
+    if fused.dim() == 2:
+        fused = fused.unsqueeze(0)
+    if ref.dim() == 2:
+        ref = ref.unsqueeze(0)
+    _require(fused, "fused", 3)
+    _require(ref, "ref", 3)
+    if fused.shape != ref.shape:
+        raise ValueError("fused and ref must have the same shape, got %s and %s"
+                         % (tuple(fused.shape), tuple(ref.shape)))
+    fused, ref = _rows_unit(fused), _rows_unit(ref)
+    B, H, W = fused.shape
+    out = torch.empty(2 * B, dtype=torch.float64, device=fused.device)
+    c = context(fused.device)
+    c.bind_stream()
+    st = c.lib.dwt_fuse_quality(c.handle, H, W, B, _ptr(fused), _pitch(fused, 1), _pitch(fused, 0),
+                                _ptr(ref), _pitch(ref, 1), _pitch(ref, 0), _ptr(out))
+    c.check(st, "dwt_fuse_quality")
+    host = out.cpu().tolist()
+    n = float(H * W)
+    rmse = [(host[b] / n) ** 0.5 for b in range(B)]
+    mean = [host[B + b] / n for b in range(B)]
+    rel = [(r / m) ** 2 if m != 0 else float("inf") for r, m in zip(rmse, mean)]
+    return {"sse": out[:B], "sum_ref": out[B:], "rmse": rmse, "mean": mean,
+            "ergas": 100.0 * 0.5 * (sum(rel) / B) ** 0.5}
 
 
 def fuse_multipass(pan: torch.Tensor, ms: torch.Tensor, wavelet="d4", out: Optional[torch.Tensor] = None):

@@ -1,0 +1,384 @@
+// Format variants of the fused kernels for gfx950: 8-bit or float32 PAN/MS,
+// 8-bit or float32 output, and a scale kappa on the MS band where it replaces
+// the LL quadrant (kappa = 1 is the method as printed).
+//
+// The paper moves images at 8 bits per pixel (section 3).  With 8-bit input
+// and output a fused pixel costs 1/B + 1/4 + 1 bytes of HBM traffic instead
+// of 4/B + 1 + 4, so the same bandwidth carries about four times the pixels.
+// Every pixel is computed with the float32 arithmetic of the float kernels
+// (fuse_math.h): 8-bit inputs are converted exactly, so the float32 output of
+// this path equals dwt_fuse_run's on the same values bit for bit, and the
+// 8-bit output is that float32 value rounded to the nearest integer (ties to
+// even) and clamped to [0, 255] (NaN -> 0).
+//
+// Work decomposition: one-shot wavefront tiles.  A wavefront covers a strip
+// of 64*NC coefficient columns (each lane NC coefficient columns = 2*NC
+// pixels per row: 8 or 16 bytes of 8-bit PAN, 16 bytes of float PAN) and KR
+// coefficient rows of every band; it issues all its PAN rows (with the D4
+// halo rows and columns, Eq. 5-6 wrap) and the first band's MS rows before
+// computing, and loads band b+1 while band b is computed and stored.
+#include "fuse_internal.h"
+#include "fuse_math.h"
+
+namespace dwtf {
+namespace {
+
+typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float byte_at(uint32_t w, int i) { return (float)((w >> (8 * i)) & 0xffu); }
+
+// 8-bit code of a fused value: nearest integer, ties to even (the default
+// rounding of rint), clamped to [0, 255]; NaN fails both comparisons -> 0.
+__device__ __forceinline__ uint32_t q8(float v) {
+    float r = __builtin_rintf(v);
+    r = (r >= 0.f) ? r : 0.f;
+    r = (r <= 255.f) ? r : 255.f;
+    return (uint32_t)r;
+}
+
+__device__ __forceinline__ uint32_t pack4(float a, float b, float c, float d) {
+    return q8(a) | (q8(b) << 8) | (q8(c) << 16) | (q8(d) << 24);
+}
+
+// One pair of pixels (2 elements) starting at p.
+template <typename T, bool AL>
+__device__ __forceinline__ f2 ld_pair(const T *p) {
+    if constexpr (sizeof(T) == 1) {
+        if constexpr (AL) {
+            const uint32_t v = *reinterpret_cast<const uint16_t *>(p);
+            return f2{(float)(v & 0xffu), (float)(v >> 8)};
+        } else {
+            return f2{(float)p[0], (float)p[1]};
+        }
+    } else {
+        if constexpr (AL) {
+            return *reinterpret_cast<const f2 *>(p);
+        } else {
+            return f2{p[0], p[1]};
+        }
+    }
+}
+
+// The 2*NC pixels a lane owns in one row, as NC pairs (vector load).
+template <typename T, int NC>
+__device__ __forceinline__ void ld_own_vec(const T *p, f2 *x) {
+    if constexpr (sizeof(T) == 1) {
+        static_assert(NC == 4 || NC == 8, "8-bit rows: 8 or 16 bytes per lane");
+        uint32_t w[NC / 2];
+        if constexpr (NC == 4) {
+            const u2 v = *reinterpret_cast<const u2 *>(p);
+            w[0] = v.x;
+            w[1] = v.y;
+        } else {
+            const u4 v = *reinterpret_cast<const u4 *>(p);
+            w[0] = v.x;
+            w[1] = v.y;
+            w[2] = v.z;
+            w[3] = v.w;
+        }
+#pragma unroll
+        for (int k = 0; k < NC; ++k) x[k] = f2{byte_at(w[k >> 1], 2 * (k & 1)), byte_at(w[k >> 1], 2 * (k & 1) + 1)};
+    } else {
+        static_assert(NC == 2, "float rows: 16 bytes per lane");
+        const f4 v = *reinterpret_cast<const f4 *>(p);
+        x[0] = f2{v.x, v.y};
+        x[1] = f2{v.z, v.w};
+    }
+}
+
+// The NC MS coefficients a lane owns in one row (vector load).
+template <typename T, int NC>
+__device__ __forceinline__ void ld_ms_vec(const T *p, float *m) {
+    if constexpr (sizeof(T) == 1) {
+        if constexpr (NC == 4) {
+            const uint32_t v = *reinterpret_cast<const uint32_t *>(p);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) m[k] = byte_at(v, k);
+        } else {
+            const u2 v = *reinterpret_cast<const u2 *>(p);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                m[k] = byte_at(v.x, k);
+                m[4 + k] = byte_at(v.y, k);
+            }
+        }
+    } else {
+        const f2 v = *reinterpret_cast<const f2 *>(p);
+        m[0] = v.x;
+        m[1] = v.y;
+    }
+}
+
+// Columns of one lane: coefficient columns s0 .. s0+NC-1 and the wrapped
+// neighbours s0-1, s0+NC (pc[k] = (s0 - 1 + k) mod W/2).
+template <typename TI, int NC, bool AL>
+struct CodecCols {
+    int s0, W2;
+    bool full;
+    int pc[NC + 2];
+
+    __device__ __forceinline__ CodecCols(int strip, int lane, int W2_) : W2(W2_) {
+        s0 = (strip * 64 + lane) * NC;
+        full = (s0 + NC) <= W2;
+#pragma unroll
+        for (int k = 0; k < NC + 2; ++k) pc[k] = wrap_idx(s0 - 1 + k, W2);
+    }
+    __device__ __forceinline__ bool active() const { return s0 < W2; }
+
+    __device__ __forceinline__ void load_row(const TI *row, f2 (&x)[NC + 2]) const {
+        x[0] = ld_pair<TI, AL>(row + 2 * pc[0]);
+        if (AL && full) {
+            ld_own_vec<TI, NC>(row + 2 * s0, &x[1]);
+        } else {
+#pragma unroll
+            for (int k = 1; k <= NC; ++k) x[k] = ld_pair<TI, AL>(row + 2 * pc[k]);
+        }
+        x[NC + 1] = ld_pair<TI, AL>(row + 2 * pc[NC + 1]);
+    }
+    __device__ __forceinline__ void load_own(const TI *row, f2 (&x)[NC]) const {
+        if (AL && full) {
+            ld_own_vec<TI, NC>(row + 2 * s0, &x[0]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < NC; ++i) x[i] = ld_pair<TI, AL>(row + 2 * pc[i + 1]);
+        }
+    }
+    // MS coefficients at pc[0..NC], times kappa.
+    __device__ __forceinline__ void load_ms(const TI *mrow, float kappa, float (&m)[NC + 1]) const {
+        m[0] = (float)mrow[pc[0]];
+        if (AL && full) {
+            ld_ms_vec<TI, NC>(mrow + s0, &m[1]);
+        } else {
+#pragma unroll
+            for (int k = 1; k <= NC; ++k) m[k] = (float)mrow[pc[k]];
+        }
+#pragma unroll
+        for (int k = 0; k <= NC; ++k) m[k] *= kappa;
+    }
+    __device__ __forceinline__ void load_ms_own(const TI *mrow, float kappa, float (&m)[NC]) const {
+        if (AL && full) {
+            ld_ms_vec<TI, NC>(mrow + s0, &m[0]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < NC; ++i) m[i] = (float)mrow[pc[i + 1]];
+        }
+#pragma unroll
+        for (int i = 0; i < NC; ++i) m[i] *= kappa;
+    }
+};
+
+// Store the lane's 2*NC pixels of one output row.
+template <typename TO, int NC, bool AL>
+__device__ __forceinline__ void store_out(TO *orow, int s0, int W2, bool full, const f2 (&q)[NC]) {
+    if constexpr (sizeof(TO) == 1) {
+        if (AL && full) {
+            uint32_t w[NC / 2];
+#pragma unroll
+            for (int k = 0; k < NC / 2; ++k) w[k] = pack4(q[2 * k].x, q[2 * k].y, q[2 * k + 1].x, q[2 * k + 1].y);
+            if constexpr (NC == 2) {
+                __builtin_nontemporal_store(w[0], reinterpret_cast<uint32_t *>(orow + 2 * s0));
+            } else if constexpr (NC == 4) {
+                __builtin_nontemporal_store(u2{w[0], w[1]}, reinterpret_cast<u2 *>(orow + 2 * s0));
+            } else {
+                __builtin_nontemporal_store(u4{w[0], w[1], w[2], w[3]}, reinterpret_cast<u4 *>(orow + 2 * s0));
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < NC; ++i) {
+                if (s0 + i < W2) {
+                    orow[2 * (s0 + i)] = (uint8_t)q8(q[i].x);
+                    orow[2 * (s0 + i) + 1] = (uint8_t)q8(q[i].y);
+                }
+            }
+        }
+    } else {
+        if (AL && full) {
+#pragma unroll
+            for (int k = 0; k < NC / 2; ++k)
+                __builtin_nontemporal_store(f4{q[2 * k].x, q[2 * k].y, q[2 * k + 1].x, q[2 * k + 1].y},
+                                            reinterpret_cast<f4 *>(orow + 2 * (s0 + 2 * k)));
+        } else {
+#pragma unroll
+            for (int i = 0; i < NC; ++i) {
+                if (s0 + i < W2) {
+                    orow[2 * (s0 + i)] = q[i].x;
+                    orow[2 * (s0 + i) + 1] = q[i].y;
+                }
+            }
+        }
+    }
+}
+
+template <typename TI, typename TO, int NC, int KR, bool AL>
+__device__ __forceinline__ void d4_codec_tile(const CodecParams &p, const Filters &f, int strip, int seg, int lane) {
+    const CodecCols<TI, NC, AL> L(strip, lane, p.W >> 1);
+    if (!L.active()) return;
+    const TI *pan = static_cast<const TI *>(p.pan);
+    const TI *ms = static_cast<const TI *>(p.ms);
+    TO *out = static_cast<TO *>(p.out);
+    const int H2 = p.H >> 1;
+    const int rb = seg * KR;
+    const int nr = min(KR, H2 - rb);
+    constexpr int NR = 2 * KR + 4;  // PAN rows 2rb-2 .. 2rb+2KR+1
+    f2 x[NR][NC + 2];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) L.load_row(pan + (int64_t)wrap_idx(2 * rb - 2 + k, p.H) * p.pan_ld, x[k]);
+    auto load_band = [&](int b, float(&m)[KR + 1][NC + 1]) {
+        const TI *mb = ms + (int64_t)b * p.ms_bs;
+#pragma unroll
+        for (int i = 0; i <= KR; ++i) L.load_ms(mb + (int64_t)wrap_idx(rb - 1 + i, H2) * p.ms_ld, p.kappa, m[i]);
+    };
+    float m[KR + 1][NC + 1];
+    load_band(0, m);
+    float A[KR + 1][NC + 1];
+    {
+        float R[NR][NC + 1];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) rowfilt<NC>(f, x[k], R[k]);
+#pragma unroll
+        for (int i = 0; i <= KR; ++i) colfilt<NC>(f, R[2 * i], R[2 * i + 1], R[2 * i + 2], R[2 * i + 3], A[i]);
+    }
+    for (int b = 0; b < p.B; ++b) {
+        float mn[KR + 1][NC + 1];
+        if (b + 1 < p.B) load_band(b + 1, mn);
+        const float g = p.gain ? p.gain[b] : 1.0f;
+        TO *ob = out + (int64_t)b * p.out_bs;
+#pragma unroll
+        for (int i = 0; i < KR; ++i) {
+            if (i >= nr) break;
+            f2 q0[NC], q1[NC];
+            d4_out_rows<NC>(f, g, m[i + 1], m[i], A[i + 1], A[i], x[2 * i + 2], x[2 * i + 3], q0, q1);
+            TO *o0 = ob + (int64_t)(2 * (rb + i)) * p.out_ld;
+            store_out<TO, NC, AL>(o0, L.s0, L.W2, L.full, q0);
+            store_out<TO, NC, AL>(o0 + p.out_ld, L.s0, L.W2, L.full, q1);
+        }
+        if (b + 1 < p.B) {
+#pragma unroll
+            for (int i = 0; i <= KR; ++i)
+#pragma unroll
+                for (int j = 0; j <= NC; ++j) m[i][j] = mn[i][j];
+        }
+    }
+}
+
+template <typename TI, typename TO, int NC, int KR, bool AL>
+__device__ __forceinline__ void haar_codec_tile(const CodecParams &p, int strip, int seg, int lane) {
+    const CodecCols<TI, NC, AL> L(strip, lane, p.W >> 1);
+    if (!L.active()) return;
+    const TI *pan = static_cast<const TI *>(p.pan);
+    const TI *ms = static_cast<const TI *>(p.ms);
+    TO *out = static_cast<TO *>(p.out);
+    const int H2 = p.H >> 1;
+    const int rb = seg * KR;
+    const int nr = min(KR, H2 - rb);
+    f2 da[KR][NC], dc[KR][NC];
+    {
+        f2 a[KR][NC], c[KR][NC];
+#pragma unroll
+        for (int i = 0; i < KR; ++i) {
+            const int r = rb + (i < nr ? i : 0);  // rows past the image re-read row rb (unused)
+            const TI *p0 = pan + (int64_t)(2 * r) * p.pan_ld;
+            L.load_own(p0, a[i]);
+            L.load_own(p0 + p.pan_ld, c[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < KR; ++i) haar_details<NC>(a[i], c[i], da[i], dc[i]);
+    }
+    auto load_band = [&](int b, float(&m)[KR][NC]) {
+        const TI *mb = ms + (int64_t)b * p.ms_bs;
+#pragma unroll
+        for (int i = 0; i < KR; ++i) L.load_ms_own(mb + (int64_t)(rb + (i < nr ? i : 0)) * p.ms_ld, p.kappa, m[i]);
+    };
+    float m[KR][NC];
+    load_band(0, m);
+    for (int b = 0; b < p.B; ++b) {
+        float mn[KR][NC];
+        if (b + 1 < p.B) load_band(b + 1, mn);
+        const float g = p.gain ? p.gain[b] : 1.0f;
+        TO *ob = out + (int64_t)b * p.out_bs;
+#pragma unroll
+        for (int i = 0; i < KR; ++i) {
+            if (i >= nr) break;
+            f2 q0[NC], q1[NC];
+            haar_out_rows<NC>(g, m[i], da[i], dc[i], q0, q1);
+            TO *o0 = ob + (int64_t)(2 * (rb + i)) * p.out_ld;
+            store_out<TO, NC, AL>(o0, L.s0, L.W2, L.full, q0);
+            store_out<TO, NC, AL>(o0 + p.out_ld, L.s0, L.W2, L.full, q1);
+        }
+        if (b + 1 < p.B) {
+#pragma unroll
+            for (int i = 0; i < KR; ++i)
+#pragma unroll
+                for (int j = 0; j < NC; ++j) m[i][j] = mn[i][j];
+        }
+    }
+}
+
+template <typename TI, typename TO, int NC, int KR, bool AL, int WAV>
+__global__ __launch_bounds__(256) void codec_kernel(CodecParams p, Filters f) {
+    const int wpb = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int unit = xcd_remap(blockIdx.x, gridDim.x) * wpb + (threadIdx.x >> 6);
+    if (unit >= p.units) return;  // whole wavefront; no barriers in this kernel
+    int strip, seg;
+    if (p.order) {
+        seg = unit / p.nstrips;
+        strip = unit - seg * p.nstrips;
+    } else {
+        strip = unit / p.nseg;
+        seg = unit - strip * p.nseg;
+    }
+    if constexpr (WAV == 1)
+        d4_codec_tile<TI, TO, NC, KR, AL>(p, f, strip, seg, lane);
+    else
+        haar_codec_tile<TI, TO, NC, KR, AL>(p, strip, seg, lane);
+}
+
+template <typename TI, typename TO, int NC, int KR, bool AL>
+hipError_t launch_t(const CodecParams &p, const Filters &f, int wpb, hipStream_t s) {
+    const int grid = (p.units + wpb - 1) / wpb;
+    if (p.wavelet == 1)
+        hipLaunchKernelGGL((codec_kernel<TI, TO, NC, KR, AL, 1>), dim3(grid), dim3(64 * wpb), 0, s, p, f);
+    else
+        hipLaunchKernelGGL((codec_kernel<TI, TO, NC, KR, AL, 0>), dim3(grid), dim3(64 * wpb), 0, s, p, f);
+    return hipGetLastError();
+}
+
+template <typename TI, typename TO>
+hipError_t launch_io(const CodecParams &p, const Filters &f, int nc, int kr, bool al, int wpb, hipStream_t s) {
+    if constexpr (sizeof(TI) == 1) {
+        if (!al) return (nc == 4 && kr == 1) ? launch_t<TI, TO, 4, 1, false>(p, f, wpb, s) : hipErrorInvalidValue;
+        if (nc == 4 && kr == 1) return launch_t<TI, TO, 4, 1, true>(p, f, wpb, s);
+        if (nc == 4 && kr == 2) return launch_t<TI, TO, 4, 2, true>(p, f, wpb, s);
+        if (nc == 8 && kr == 1) return launch_t<TI, TO, 8, 1, true>(p, f, wpb, s);
+        if (nc == 8 && kr == 2) return launch_t<TI, TO, 8, 2, true>(p, f, wpb, s);
+    } else {
+        if (!al) return (nc == 2 && kr == 1) ? launch_t<TI, TO, 2, 1, false>(p, f, wpb, s) : hipErrorInvalidValue;
+        if (nc == 2 && kr == 1) return launch_t<TI, TO, 2, 1, true>(p, f, wpb, s);
+        if (nc == 2 && kr == 2) return launch_t<TI, TO, 2, 2, true>(p, f, wpb, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+bool codec_shape_ok(int in_u8, int nc, int kr, bool al) {
+    if (in_u8) return al ? ((nc == 4 || nc == 8) && (kr == 1 || kr == 2)) : (nc == 4 && kr == 1);
+    return al ? (nc == 2 && (kr == 1 || kr == 2)) : (nc == 2 && kr == 1);
+}
+
+hipError_t launch_codec(const CodecParams &p, const Filters &f, int in_u8, int out_u8, int nc, int kr, bool al,
+                        int wpb, hipStream_t s) {
+    if (p.units <= 0) return hipSuccess;
+    if (wpb < 1 || wpb > 4 || !codec_shape_ok(in_u8, nc, kr, al)) return hipErrorInvalidValue;
+    if (p.nstrips != (p.W / 2 + 64 * nc - 1) / (64 * nc) || p.nseg != (p.H / 2 + kr - 1) / kr) return hipErrorInvalidValue;
+    if (in_u8) {
+        return out_u8 ? launch_io<uint8_t, uint8_t>(p, f, nc, kr, al, wpb, s)
+                      : launch_io<uint8_t, float>(p, f, nc, kr, al, wpb, s);
+    }
+    return out_u8 ? launch_io<float, uint8_t>(p, f, nc, kr, al, wpb, s)
+                  : launch_io<float, float>(p, f, nc, kr, al, wpb, s);
+}
+
+}  // namespace dwtf

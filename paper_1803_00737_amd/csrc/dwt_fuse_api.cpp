@@ -46,10 +46,10 @@ bool extent(int64_t nb, int64_t rows, int64_t cols, int64_t ld, int64_t bs, int6
     return true;
 }
 
-Span span_of(const void *p, int64_t elems) {
+Span span_of(const void *p, int64_t elems, int64_t esize = sizeof(float)) {
     Span s;
     s.lo = reinterpret_cast<uintptr_t>(p);
-    s.hi = s.lo + static_cast<uintptr_t>(elems) * sizeof(float);
+    s.hi = s.lo + static_cast<uintptr_t>(elems) * static_cast<uintptr_t>(esize);
     return s;
 }
 
@@ -74,7 +74,7 @@ dwt_fuse_status check_shape(int64_t H, int64_t W, int64_t B, std::string *err) {
 }
 
 dwt_fuse_status check_strided(const char *name, int64_t nb, int64_t rows, int64_t cols, int64_t ld, int64_t bs,
-                              const void *ptr, Span *sp, std::string *err) {
+                              const void *ptr, Span *sp, std::string *err, int64_t esize = sizeof(float)) {
     if (ld < cols || (nb > 1 && (bs < 0 || bs / ld < rows))) {
         if (err) *err = std::string(name) + ": pitch smaller than the row width, or band stride smaller than rows*pitch";
         return DWT_FUSE_E_STRIDE;
@@ -91,7 +91,7 @@ dwt_fuse_status check_strided(const char *name, int64_t nb, int64_t rows, int64_
         if (err) *err = std::string(name) + ": extent overflows";
         return DWT_FUSE_E_SHAPE;
     }
-    *sp = span_of(ptr, e);
+    *sp = span_of(ptr, e, esize);
     return DWT_FUSE_OK;
 }
 
@@ -132,6 +132,52 @@ dwt_fuse_status check_run_args(const RunArgs &a, RunSpans *sp, std::string *err)
         return DWT_FUSE_E_ALIAS;
     }
     if (sp) *sp = s;
+    return DWT_FUSE_OK;
+}
+
+// dwt_fuse_run_ex: formats and kappa on top of RunArgs' geometry.
+struct ExArgs {
+    int wavelet;
+    int64_t H, W, B;
+    const void *pan;
+    int64_t pan_ld;
+    const void *ms;
+    int64_t ms_ld, ms_bs;
+    const float *gain;
+    const void *out;
+    int64_t out_ld, out_bs;
+    int in_format, out_format;
+    float kappa;
+};
+
+int64_t format_size(int fmt) { return fmt == DWT_FUSE_U8 ? 1 : (int64_t)sizeof(float); }
+
+dwt_fuse_status check_ex_args(const ExArgs &a, std::string *err) {
+    if (!a.pan || !a.ms || !a.out) {
+        if (err) *err = "pan, ms and out must not be NULL";
+        return DWT_FUSE_E_NULL;
+    }
+    dwt_fuse_status st = check_shape(a.H, a.W, a.B, err);
+    if (st) return st;
+    if (a.wavelet != DWT_FUSE_HAAR && a.wavelet != DWT_FUSE_D4) {
+        if (err) *err = "unknown wavelet";
+        return DWT_FUSE_E_WAVELET;
+    }
+    const auto known = [](int f) { return f == DWT_FUSE_F32 || f == DWT_FUSE_U8; };
+    if (!known(a.in_format) || !known(a.out_format)) {
+        if (err) *err = "unknown element format";
+        return DWT_FUSE_E_FORMAT;
+    }
+    const int64_t ei = format_size(a.in_format), eo = format_size(a.out_format);
+    Span pan, ms, out;
+    if ((st = check_strided("pan", 1, a.H, a.W, a.pan_ld, 0, a.pan, &pan, err, ei))) return st;
+    if ((st = check_strided("ms", a.B, a.H / 2, a.W / 2, a.ms_ld, a.ms_bs, a.ms, &ms, err, ei))) return st;
+    if ((st = check_strided("out", a.B, a.H, a.W, a.out_ld, a.out_bs, a.out, &out, err, eo))) return st;
+    const Span gain = a.gain ? span_of(a.gain, a.B) : Span{};
+    if (out.overlaps(pan) || out.overlaps(ms) || out.overlaps(gain)) {
+        if (err) *err = "out overlaps an input";
+        return DWT_FUSE_E_ALIAS;
+    }
     return DWT_FUSE_OK;
 }
 
@@ -818,6 +864,7 @@ const char *dwt_fuse_status_str(dwt_fuse_status s) {
         case DWT_FUSE_E_NOMEM: return "out of device memory";
         case DWT_FUSE_E_DEVICE: return "HIP device error";
         case DWT_FUSE_E_STATE: return "invalid context state";
+        case DWT_FUSE_E_FORMAT: return "unknown element format";
     }
     return "unknown status";
 }
@@ -990,6 +1037,274 @@ dwt_fuse_status dwt_fuse_run(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet, int64_
     } catch (...) {
         return fail(ctx, DWT_FUSE_E_STATE, "unexpected exception");
     }
+}
+
+namespace {
+
+// ------------------------------------------------------------ format variants
+
+struct CodecShape {
+    int nc = 4, kr = 1, wpb = 4, order = 1;
+    bool aligned = false;
+};
+
+bool is_aligned(const void *p, int64_t ld, int64_t bs, int64_t nb, int64_t esize, int64_t a) {
+    if (reinterpret_cast<uintptr_t>(p) % (uintptr_t)a) return false;
+    if ((ld * esize) % a) return false;
+    return nb <= 1 || (bs * esize) % a == 0;
+}
+
+// Vector access for nc coefficient columns per lane: own PAN pixels (2*nc
+// elements), own MS coefficients (nc elements) and output pixels (2*nc
+// elements, at most 16 bytes per store) in one access each.
+bool codec_aligned(const ExArgs &a, int nc) {
+    const int64_t ei = format_size(a.in_format), eo = format_size(a.out_format);
+    return is_aligned(a.pan, a.pan_ld, 0, 1, ei, 2 * nc * ei) &&
+           is_aligned(a.ms, a.ms_ld, a.ms_bs, a.B, ei, nc * ei) &&
+           is_aligned(a.out, a.out_ld, a.out_bs, a.B, eo, std::min<int64_t>(2 * nc * eo, 16));
+}
+
+std::string codec_key(const ExArgs &a, bool aligned) {
+    char buf[96];
+    std::snprintf(buf, sizeof(buf), "c%d%d%d_h%d_w%d_b%d_a%d", a.in_format, a.out_format, a.wavelet, ceil_log2(a.H),
+                  ceil_log2(a.W), (int)std::min<int64_t>(a.B, 8), aligned ? 1 : 0);
+    return buf;
+}
+
+// Untuned shape: one coefficient row per wavefront (D4 keeps 6 PAN rows in
+// registers), 16-byte 8-bit rows for Haar, 8-byte ones for D4.
+CodecShape codec_default(const ExArgs &a) {
+    CodecShape t;
+    const bool u8 = a.in_format == DWT_FUSE_U8;
+    t.nc = u8 ? (a.wavelet == DWT_FUSE_D4 ? 4 : 8) : 2;
+    t.kr = 1;
+    if (!codec_aligned(a, t.nc) && u8) t.nc = 4;
+    t.aligned = codec_aligned(a, t.nc);
+    if (!t.aligned) {
+        t.nc = u8 ? 4 : 2;
+        t.kr = 1;
+    }
+    return t;
+}
+
+bool codec_params(const ExArgs &a, const CodecShape &t, CodecParams *p) {
+    const int64_t W2 = a.W / 2, H2 = a.H / 2;
+    const int64_t ns = (W2 + 64 * t.nc - 1) / (64 * t.nc), ng = (H2 + t.kr - 1) / t.kr;
+    if (ns * ng > INT32_MAX - 4) return false;
+    CodecParams q{};
+    q.pan = a.pan;
+    q.ms = a.ms;
+    q.gain = a.gain;
+    q.out = const_cast<void *>(a.out);
+    q.pan_ld = a.pan_ld;
+    q.ms_ld = a.ms_ld;
+    q.ms_bs = a.ms_bs;
+    q.out_ld = a.out_ld;
+    q.out_bs = a.out_bs;
+    q.kappa = a.kappa;
+    q.H = (int32_t)a.H;
+    q.W = (int32_t)a.W;
+    q.B = (int32_t)a.B;
+    q.nstrips = (int32_t)ns;
+    q.nseg = (int32_t)ng;
+    q.units = (int32_t)(ns * ng);
+    q.order = t.order;
+    q.wavelet = a.wavelet;
+    *p = q;
+    return true;
+}
+
+hipError_t launch_codec_shape(dwt_fuse_ctx *c, const ExArgs &a, const CodecShape &t) {
+    CodecParams p;
+    if (!codec_params(a, t, &p)) return hipErrorInvalidValue;
+    return launch_codec(p, c->filt, a.in_format == DWT_FUSE_U8, a.out_format == DWT_FUSE_U8, t.nc, t.kr, t.aligned,
+                        t.wpb, c->stream);
+}
+
+float time_codec(dwt_fuse_ctx *c, const ExArgs &a, const CodecShape &t) {
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return 1e30f;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return 1e30f;
+    }
+    float best[3] = {1e30f, 1e30f, 1e30f};
+    if (launch_codec_shape(c, a, t) == hipSuccess) {
+        for (int k = 0; k < 3; ++k) {
+            hipEventRecord(e0, c->stream);
+            launch_codec_shape(c, a, t);
+            hipEventRecord(e1, c->stream);
+            hipEventSynchronize(e1);
+            hipEventElapsedTime(&best[k], e0, e1);
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    std::sort(best, best + 3);
+    return best[1];
+}
+
+CodecShape codec_shape(dwt_fuse_ctx *c, const ExArgs &a) {
+    CodecShape t = codec_default(a);
+    const bool u8 = a.in_format == DWT_FUSE_U8;
+    const std::string key = codec_key(a, t.aligned);
+    auto it = c->table.find(key);
+    if (it != c->table.end()) {
+        t.nc = it->second.nc;
+        t.kr = it->second.seg_rows;
+        t.wpb = it->second.wpb;
+        t.order = it->second.order;
+    } else if (c->tuning && t.aligned) {
+        float bestms = time_codec(c, a, t);
+        for (int nc : {2, 4, 8}) {
+            if (!codec_shape_ok(u8, nc, 1, true) || !codec_aligned(a, nc)) continue;
+            for (int kr : {1, 2})
+                for (int wpb : {1, 2, 4})
+                    for (int order : {1, 0}) {
+                        CodecShape s = t;
+                        s.nc = nc;
+                        s.kr = kr;
+                        s.wpb = wpb;
+                        s.order = order;
+                        const float ms = time_codec(c, a, s);
+                        if (ms < bestms) {
+                            bestms = ms;
+                            t = s;
+                        }
+                    }
+        }
+        Tile rec;
+        rec.nc = t.nc;
+        rec.seg_rows = t.kr;
+        rec.wpb = t.wpb;
+        rec.order = t.order;
+        rec.mode = 1;
+        c->table[key] = rec;
+        if (std::getenv("DWT_FUSE_LOG"))
+            std::fprintf(stderr, "[dwt_fuse] tuned %s: nc=%d kr=%d wpb=%d order=%d (%.3f ms)\n", key.c_str(), t.nc,
+                         t.kr, t.wpb, t.order, bestms);
+    }
+    // Forced fields: rows -> kr, waves, columns 1/2 -> nc 4/8 for 8-bit input.
+    const Forced &fo = c->forced;
+    if (fo.seg_rows > 0) t.kr = fo.seg_rows >= 2 ? 2 : 1;
+    if (fo.wpb > 0) t.wpb = fo.wpb;
+    if (fo.nc > 0 && u8) t.nc = fo.nc == 1 ? 4 : 8;
+    if (t.aligned && !codec_aligned(a, t.nc)) t.nc = 4;
+    t.aligned = codec_aligned(a, t.nc);
+    if (!codec_shape_ok(u8, t.nc, t.kr, t.aligned)) {
+        t.nc = u8 ? 4 : 2;
+        t.kr = 1;
+        t.aligned = codec_aligned(a, t.nc);
+    }
+    return t;
+}
+
+}  // namespace
+
+dwt_fuse_status dwt_fuse_run_ex(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet, int64_t H, int64_t W, int64_t B,
+                                const void *pan, int64_t pan_ld, const void *ms, int64_t ms_ld, int64_t ms_band_stride,
+                                const float *gain, void *out, int64_t out_ld, int64_t out_band_stride,
+                                const dwt_fuse_opts *opts) {
+    if (!ctx) return DWT_FUSE_E_NULL;
+    const dwt_fuse_opts o = opts ? *opts : dwt_fuse_opts{DWT_FUSE_F32, DWT_FUSE_F32, 1.0f};
+    if (o.in_format == DWT_FUSE_F32 && o.out_format == DWT_FUSE_F32 && o.kappa == 1.0f)
+        return dwt_fuse_run(ctx, wavelet, H, W, B, static_cast<const float *>(pan), pan_ld,
+                            static_cast<const float *>(ms), ms_ld, ms_band_stride, gain, static_cast<float *>(out),
+                            out_ld, out_band_stride);
+    try {
+        const ExArgs a{(int)wavelet, H, W, B, pan, pan_ld, ms, ms_ld, ms_band_stride, gain, out, out_ld,
+                       out_band_stride, o.in_format, o.out_format, o.kappa};
+        std::string err;
+        dwt_fuse_status st = check_ex_args(a, &err);
+        if (st) return fail(ctx, st, err);
+        if ((st = use_device(ctx))) return st;
+        const CodecShape t = codec_shape(ctx, a);
+        CodecParams p;
+        if (!codec_params(a, t, &p)) return fail(ctx, DWT_FUSE_E_SHAPE, "too many work units");
+        const hipError_t e = launch_codec(p, ctx->filt, a.in_format == DWT_FUSE_U8, a.out_format == DWT_FUSE_U8,
+                                          t.nc, t.kr, t.aligned, t.wpb, ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "format-variant launch");
+        return DWT_FUSE_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(ctx, DWT_FUSE_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(ctx, DWT_FUSE_E_STATE, "unexpected exception");
+    }
+}
+
+dwt_fuse_status dwt_fuse_check_run_ex(dwt_fuse_wavelet wavelet, int64_t H, int64_t W, int64_t B, const void *pan,
+                                      int64_t pan_ld, const void *ms, int64_t ms_ld, int64_t ms_band_stride,
+                                      const float *gain, const void *out, int64_t out_ld, int64_t out_band_stride,
+                                      const dwt_fuse_opts *opts) {
+    const dwt_fuse_opts o = opts ? *opts : dwt_fuse_opts{DWT_FUSE_F32, DWT_FUSE_F32, 1.0f};
+    const ExArgs a{(int)wavelet, H, W, B, pan, pan_ld, ms, ms_ld, ms_band_stride, gain, out, out_ld,
+                   out_band_stride, o.in_format, o.out_format, o.kappa};
+    return check_ex_args(a, nullptr);
+}
+
+namespace {
+
+dwt_fuse_status check_quality_args(int64_t H, int64_t W, int64_t B, const float *fused, int64_t f_ld, int64_t f_bs,
+                                   const float *ref, int64_t r_ld, int64_t r_bs, const double *out,
+                                   std::string *err) {
+    if (!fused || !ref || !out) {
+        if (err) *err = "fused, ref and out must not be NULL";
+        return DWT_FUSE_E_NULL;
+    }
+    if (H < 1 || W < 1 || H > kMaxSide || W > kMaxSide || B < 1 || B > kQualityMaxBands) {
+        if (err) *err = "H, W must be in [1, 2^30] and B in [1, 65535]";
+        return DWT_FUSE_E_SHAPE;
+    }
+    Span fs, rs;
+    dwt_fuse_status st;
+    if ((st = check_strided("fused", B, H, W, f_ld, f_bs, fused, &fs, err))) return st;
+    if ((st = check_strided("ref", B, H, W, r_ld, r_bs, ref, &rs, err))) return st;
+    const Span os = span_of(out, 2 * B, sizeof(double));
+    if (os.overlaps(fs) || os.overlaps(rs)) {
+        if (err) *err = "out overlaps an input";
+        return DWT_FUSE_E_ALIAS;
+    }
+    return DWT_FUSE_OK;
+}
+
+}  // namespace
+
+dwt_fuse_status dwt_fuse_quality(dwt_fuse_ctx *ctx, int64_t H, int64_t W, int64_t B, const float *fused,
+                                 int64_t fused_ld, int64_t fused_band_stride, const float *ref, int64_t ref_ld,
+                                 int64_t ref_band_stride, double *out) {
+    if (!ctx) return DWT_FUSE_E_NULL;
+    try {
+        std::string err;
+        dwt_fuse_status st = check_quality_args(H, W, B, fused, fused_ld, fused_band_stride, ref, ref_ld,
+                                                ref_band_stride, out, &err);
+        if (st) return fail(ctx, st, err);
+        if ((st = use_device(ctx))) return st;
+        if ((st = ensure_ws(ctx, sizeof(double) * 2 * (size_t)kQualityBlocks * (size_t)B))) return st;
+        QualityParams p{};
+        p.fused = fused;
+        p.ref = ref;
+        p.f_ld = fused_ld;
+        p.f_bs = fused_band_stride;
+        p.r_ld = ref_ld;
+        p.r_bs = ref_band_stride;
+        p.H = (int32_t)H;
+        p.W = (int32_t)W;
+        p.B = (int32_t)B;
+        const hipError_t e = launch_quality(p, reinterpret_cast<double *>(ctx->ws), out, ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "quality launch");
+        return DWT_FUSE_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(ctx, DWT_FUSE_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(ctx, DWT_FUSE_E_STATE, "unexpected exception");
+    }
+}
+
+dwt_fuse_status dwt_fuse_check_quality(int64_t H, int64_t W, int64_t B, const float *fused, int64_t fused_ld,
+                                       int64_t fused_band_stride, const float *ref, int64_t ref_ld,
+                                       int64_t ref_band_stride, const double *out) {
+    return check_quality_args(H, W, B, fused, fused_ld, fused_band_stride, ref, ref_ld, ref_band_stride, out,
+                              nullptr);
 }
 
 dwt_fuse_status dwt_fuse_run_batched(dwt_fuse_ctx *ctx, const dwt_fuse_item *items, int64_t n, uint32_t flags) {

@@ -1,5 +1,6 @@
 // Internal interface between the host library (dwt_fuse_api.cpp) and the
-// gfx950 kernels (fuse_kernels.hip, adjoint_kernels.hip).  Not installed.
+// gfx950 kernels (fuse_kernels.hip, adjoint_kernels.hip, codec_kernels.hip,
+// multipass_kernels.hip).  Not installed.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -107,6 +108,44 @@ int adjoint_max_bands();
 // columns x (kr * wpb) coefficient rows, one workgroup each; any band count.
 hipError_t launch_adjoint_staged(const AdjParams &p, const Filters &f, int kr, int wpb, hipStream_t s);
 size_t adjoint_staged_lds(int T, int B);
+
+// Format variants (codec_kernels.hip): pan/ms float32 or 8-bit, out float32
+// or 8-bit, MS scaled by kappa.  Units are one-shot wavefronts over a strip of
+// 64*nc coefficient columns and kr coefficient rows; pitches and band
+// strides in elements of each buffer's format.
+struct CodecParams {
+    const void *pan;
+    const void *ms;
+    const float *gain;  // NULL = all ones
+    void *out;
+    int64_t pan_ld, ms_ld, ms_bs, out_ld, out_bs;
+    float kappa;
+    int32_t H, W, B;
+    int32_t nstrips;  // ceil((W/2) / (64*nc))
+    int32_t nseg;     // ceil((H/2) / kr)
+    int32_t units;    // nstrips * nseg
+    int32_t order;    // 0 strip-major, 1 row-band-major
+    int32_t wavelet;  // 0 Haar, 1 D4
+};
+
+// Shapes that exist: 8-bit input nc 4 or 8 (kr 1, 2) on aligned buffers, nc 4
+// kr 1 otherwise; float input nc 2 (kr 1, 2 aligned; kr 1 otherwise).
+bool codec_shape_ok(int in_u8, int nc, int kr, bool aligned);
+hipError_t launch_codec(const CodecParams &p, const Filters &f, int in_u8, int out_u8, int nc, int kr, bool aligned,
+                        int waves_per_block, hipStream_t s);
+
+// Quality diagnostics (quality_kernels.hip): per band, sum of squared
+// differences fused - ref and sum of ref, FP64, fixed order.
+struct QualityParams {
+    const float *fused;
+    const float *ref;
+    int64_t f_ld, f_bs, r_ld, r_bs;
+    int32_t H, W, B;
+};
+constexpr int kQualityBlocks = 256;       // blocks per band
+constexpr int kQualityMaxBands = 65535;  // grid y limit
+// partial: B * kQualityBlocks * 2 doubles of workspace; out: 2 * B doubles.
+hipError_t launch_quality(const QualityParams &p, double *partial, double *out, hipStream_t s);
 
 // The paper's multi-pass pipeline (comparator); work and scratch are H x W.
 hipError_t launch_multipass(int wavelet, int H, int W, int B, const float *pan, int64_t pan_ld, const float *ms,

@@ -41,16 +41,9 @@
 // L2) takes a contiguous run of units (by default a band of rows across the
 // whole width), whose halo rows and columns then hit that L2.
 #include "fuse_internal.h"
+#include "fuse_math.h"
 
 namespace dwtf {
-
-typedef float f2 __attribute__((ext_vector_type(2)));
-typedef float f4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ int wrap_idx(int q, int n) {
-    q %= n;
-    return q < 0 ? q + n : q;
-}
 
 template <bool AL>
 __device__ __forceinline__ f2 ld2(const float *p) {
@@ -73,14 +66,6 @@ __device__ __forceinline__ void st2(float *p, f2 v) {
 
 __device__ __forceinline__ void st4(float *p, f4 v) {
     __builtin_nontemporal_store(v, reinterpret_cast<f4 *>(p));
-}
-
-// Workgroups are dispatched round-robin over the 8 XCDs.  Map hardware
-// block b to a logical block so that XCD x gets a contiguous logical range.
-__device__ __forceinline__ int xcd_remap(int b, int G) {
-    constexpr int NX = 8;
-    const int x = b % NX, i = b / NX, q = G / NX, rem = G % NX;
-    return x * q + (x < rem ? x : rem) + i;
 }
 
 // The columns one lane owns: coefficient columns s0 .. s0+NC-1 (output
@@ -171,52 +156,6 @@ struct LaneCols {
         }
     }
 };
-
-// Row low-pass at coefficient columns pc[0..NC]: sum_l h_l PAN(y, 2s+l).
-template <int NC>
-__device__ __forceinline__ void rowfilt(const Filters &f, const f2 (&x)[NC + 2], float (&R)[NC + 1]) {
-#pragma unroll
-    for (int j = 0; j <= NC; ++j)
-        R[j] = fmaf(f.h[3], x[j + 1].y, fmaf(f.h[2], x[j + 1].x, fmaf(f.h[1], x[j].y, f.h[0] * x[j].x)));
-}
-
-// Column low-pass of four consecutive row-filtered rows (one coefficient row
-// of L PAN).  One fixed evaluation order, so every output is computed the
-// same way whatever unit it falls in.
-template <int NC>
-__device__ __forceinline__ void colfilt(const Filters &f, const float (&R0)[NC + 1], const float (&R1)[NC + 1],
-                                        const float (&R2)[NC + 1], const float (&R3)[NC + 1],
-                                        float (&A)[NC + 1]) {
-#pragma unroll
-    for (int j = 0; j <= NC; ++j)
-        A[j] = fmaf(f.h[3], R3[j], fmaf(f.h[2], R2[j], fmaf(f.h[1], R1[j], f.h[0] * R0[j])));
-}
-
-// Output rows 2r (q0) and 2r+1 (q1) of one band from the coefficient rows
-// c(r-1) = cp, c(r) = cc of (m - g L PAN) and the lane's PAN pixels of rows
-// 2r (xa) and 2r+1 (xb).
-template <int NC>
-__device__ __forceinline__ void d4_out_rows(const Filters &f, float g, const float (&mc)[NC + 1],
-                                            const float (&mp)[NC + 1], const float (&A)[NC + 1],
-                                            const float (&Ap)[NC + 1], const f2 (&xa)[NC + 2],
-                                            const f2 (&xb)[NC + 2], f2 (&q0)[NC], f2 (&q1)[NC]) {
-    const float h0 = f.h[0], h1 = f.h[1], h2 = f.h[2], h3 = f.h[3];
-    float v0[NC + 1], v1[NC + 1];
-#pragma unroll
-    for (int j = 0; j <= NC; ++j) {
-        const float cc = fmaf(-g, A[j], mc[j]);   // coefficient row r
-        const float cp = fmaf(-g, Ap[j], mp[j]);  // coefficient row r-1
-        v0[j] = fmaf(h2, cp, h0 * cc);             // output row 2r
-        v1[j] = fmaf(h3, cp, h1 * cc);             // output row 2r+1
-    }
-#pragma unroll
-    for (int i = 0; i < NC; ++i) {
-        q0[i].x = fmaf(g, xa[i + 1].x, fmaf(h2, v0[i], h0 * v0[i + 1]));
-        q0[i].y = fmaf(g, xa[i + 1].y, fmaf(h3, v0[i], h1 * v0[i + 1]));
-        q1[i].x = fmaf(g, xb[i + 1].x, fmaf(h2, v1[i], h0 * v1[i + 1]));
-        q1[i].y = fmaf(g, xb[i + 1].y, fmaf(h3, v1[i], h1 * v1[i + 1]));
-    }
-}
 
 // ---- Daubechies-4, rolling ----------------------------------------------
 
@@ -336,29 +275,6 @@ __device__ __forceinline__ void d4_tile(const FuseParams &p, const Filters &f, i
 }
 
 // ---- Haar -----------------------------------------------------------------
-
-// Detail part of PAN: pixel minus the mean of its 2x2 block (the block mean is
-// the LL coefficient of Eq. 1-2 applied to rows and columns).
-template <int NC>
-__device__ __forceinline__ void haar_details(const f2 (&a)[NC], const f2 (&c)[NC], f2 (&da)[NC], f2 (&dc)[NC]) {
-#pragma unroll
-    for (int i = 0; i < NC; ++i) {
-        const float mean = ((a[i].x + a[i].y) + (c[i].x + c[i].y)) * 0.25f;
-        da[i] = f2{a[i].x - mean, a[i].y - mean};
-        dc[i] = f2{c[i].x - mean, c[i].y - mean};
-    }
-}
-
-// Output rows 2r, 2r+1 of one band: m + g * detail.
-template <int NC>
-__device__ __forceinline__ void haar_out_rows(float g, const float (&m)[NC], const f2 (&da)[NC], const f2 (&dc)[NC],
-                                              f2 (&q0)[NC], f2 (&q1)[NC]) {
-#pragma unroll
-    for (int i = 0; i < NC; ++i) {
-        q0[i] = f2{fmaf(g, da[i].x, m[i]), fmaf(g, da[i].y, m[i])};
-        q1[i] = f2{fmaf(g, dc[i].x, m[i]), fmaf(g, dc[i].y, m[i])};
-    }
-}
 
 template <int NC, bool AL>
 __device__ __forceinline__ void haar_rolling(const FuseParams &p, int strip, int seg, int lane) {

@@ -140,6 +140,32 @@ def make_scene(H: int, W: int, B: int, seed: int, gain=(0.6, 1.4), offset=(-10.0
     return _scene_torch(p, device)
 
 
+def make_truth(pan, H: int, W: int, B: int, seed: int, gain=(0.6, 1.4), offset=(-10.0, 10.0)):
+    """Full-resolution reference of each MS band of the scene drawn with the
+    same arguments: clip(rint(PAN * a_b + o_b), 0, 255), what a sensor with
+    that band's response would record at PAN resolution (noise-free).  The
+    MS band itself is this reference box-averaged 2x2 plus noise, so it is the
+    target a fused band should reproduce.  ``pan`` is the scene's PAN (numpy
+    or torch); the result has the same type and device, float32."""
+    p = draw_params(H, W, B, seed, gain, offset)
+    if isinstance(pan, np.ndarray):
+        t = np.empty((B, H, W), dtype=np.float32)
+        for b in range(B):
+            t[b] = np.clip(np.rint(pan.astype(np.float64) * p.band_gain[b] + p.band_offset[b]), 0, 255)
+        return t
+    import torch
+
+    t = torch.empty((B, H, W), dtype=torch.float32, device=pan.device)
+    for b in range(B):
+        t[b] = torch.clamp(torch.round(pan * float(p.band_gain[b]) + float(p.band_offset[b])), 0, 255)
+    return t
+
+
+def band_gains(H: int, W: int, B: int, seed: int, gain=(0.6, 1.4), offset=(-10.0, 10.0)) -> np.ndarray:
+    """The per-band response a_b the scene's MS bands were drawn with."""
+    return draw_params(H, W, B, seed, gain, offset).band_gain.copy()
+
+
 # ---- the five workloads -------------------------------------------------
 
 @dataclass
@@ -155,6 +181,12 @@ class Workload:
 
     def make(self, device=None):
         return make_scene(self.H, self.W, self.B, self.seed, self.gain, self.offset, device)
+
+    def truth(self, pan):
+        return make_truth(pan, self.H, self.W, self.B, self.seed, self.gain, self.offset)
+
+    def band_gains(self):
+        return band_gains(self.H, self.W, self.B, self.seed, self.gain, self.offset)
 
 
 def haar_512() -> Workload:

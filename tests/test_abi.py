@@ -196,3 +196,38 @@ def test_no_oracle_in_product():
             if f.endswith((".py", ".cpp", ".hip", ".h")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in text.lower(), os.path.join(dirpath, f)
+
+
+def ex_check(lib, fin=1, fout=1, kappa=1.0, w=1, H=8, W=8, B=2, pan=P, pan_ld=None, ms=P + 10**6, ms_ld=None,
+             ms_bs=None, gain=None, out=P + 2 * 10**6, out_ld=None, out_bs=None, opts=True):
+    pan_ld = W if pan_ld is None else pan_ld
+    ms_ld = W // 2 if ms_ld is None else ms_ld
+    ms_bs = (H // 2) * ms_ld if ms_bs is None else ms_bs
+    out_ld = W if out_ld is None else out_ld
+    out_bs = H * out_ld if out_bs is None else out_bs
+    o = ctypes.byref(_lib.Opts(fin, fout, kappa)) if opts else None
+    return lib.dwt_fuse_check_run_ex(w, H, W, B, pan, pan_ld, ms, ms_ld, ms_bs, gain, out, out_ld, out_bs, o)
+
+
+def test_run_ex_validation(lib):
+    E_FORMAT = 9
+    assert ex_check(lib) == OK
+    assert ex_check(lib, opts=False) == OK  # NULL opts = float32 in and out, kappa 1
+    assert ex_check(lib, fin=0, fout=1, kappa=2.0) == OK
+    assert ex_check(lib, fin=2) == E_FORMAT
+    assert ex_check(lib, fout=-1) == E_FORMAT
+    assert ex_check(lib, pan=None) == E_NULL
+    assert ex_check(lib, w=5) == E_WAVELET
+    assert ex_check(lib, H=7) == E_SHAPE
+    assert ex_check(lib, pan_ld=7) == E_STRIDE
+    assert ex_check(lib, pan=P + 1, pan_ld=9) == OK  # byte pitches need no alignment
+    # byte ranges follow each buffer's element size: 8-bit PAN of 8 x 8 ends
+    # 64 bytes after its start, a float one 256 bytes after
+    assert ex_check(lib, out=P + 64, B=1) == OK
+    assert ex_check(lib, out=P + 63, B=1) == E_ALIAS
+    assert ex_check(lib, fin=0, fout=0, out=P + 64, B=1) == E_ALIAS
+    assert ex_check(lib, fin=0, fout=0, out=P + 256, B=1) == OK
+    # 8-bit out of 2 bands x 8 x 8 spans 128 bytes
+    assert ex_check(lib, out=P - 128, B=2) == OK
+    assert ex_check(lib, out=P - 127, B=2) == E_ALIAS
+    assert lib.dwt_fuse_status_str(E_FORMAT) == b"unknown element format"

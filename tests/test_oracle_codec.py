@@ -93,3 +93,26 @@ def test_dc_matched_d4_reproduces_smooth_pan(oracle):
     assert abs(e1.mean() + pan.mean() / 2) < 1.0
     eh = np.sqrt(((oracle.fuse("haar", pan, ms)[0] - pan) ** 2).mean())
     assert eh < 1e-9 * pan.max() + 1e-9  # Haar's LL is the block mean itself
+
+
+def test_quality_closed_forms(oracle):
+    """sse and sums against hand-derived values and numpy's own sums; the
+    ERGAS-style score of a constant error c on a flat reference mu is
+    100 * (1/2) * c / mu."""
+    H, W = 6, 10
+    ref = np.full((2, H, W), 80.0)
+    fused = ref.copy()
+    fused[0] += 4.0
+    fused[1, 2, 3] -= 5.0
+    q = oracle.quality(fused, ref)
+    assert np.array_equal(q["sse"], [16.0 * H * W, 25.0])
+    assert np.array_equal(q["sum_ref"], [80.0 * H * W] * 2)
+    assert np.allclose(q["rmse"], [4.0, 5.0 / np.sqrt(H * W)])
+    one = oracle.quality(fused[:1], ref[:1])
+    assert abs(one["ergas"] - 100 * 0.5 * 4.0 / 80.0) < 1e-12
+    rng = np.random.default_rng(5)
+    a, b = rng.normal(100, 30, (3, 17, 9)), rng.normal(100, 30, (3, 17, 9))
+    q = oracle.quality(a, b)
+    assert np.allclose(q["sse"], ((a - b) ** 2).sum(axis=(1, 2)), rtol=1e-13)
+    assert np.allclose(q["sum_ref"], b.sum(axis=(1, 2)), rtol=1e-13)
+    assert np.all(oracle.quality(b, b)["sse"] == 0)
