@@ -84,10 +84,42 @@ __device__ __forceinline__ void load_pairs(const float *row, const int (&pc)[NC 
     x[NC + 1] = ld2<AL>(row + 2 * pc[NC + 1]);
 }
 
+// Per-pixel arithmetic of the D4 adjoint, written as explicit fma chains so
+// that every kernel variant (rolling, one-shot, LDS-staged) forms each value
+// with the same operations in the same order and they agree bit for bit
+// (the compiler contracts free-standing a*b + c differently per kernel).
+
+// Row low-pass at coefficient columns pc[0..NC]: sum_l h_l x(2s+l).
 template <int NC>
 __device__ __forceinline__ void rowfilt(const float (&h)[4], const f2 (&x)[NC + 2], float (&R)[NC + 1]) {
 #pragma unroll
-    for (int j = 0; j <= NC; ++j) R[j] = h[0] * x[j].x + h[1] * x[j].y + h[2] * x[j + 1].x + h[3] * x[j + 1].y;
+    for (int j = 0; j <= NC; ++j) R[j] = fmaf(h[3], x[j + 1].y, fmaf(h[2], x[j + 1].x, fmaf(h[1], x[j].y, h[0] * x[j].x)));
+}
+
+// Column low-pass of four row-filtered rows 2r .. 2r+3: coefficient row r of L.
+__device__ __forceinline__ float col4(const float (&h)[4], float r0, float r1, float r2, float r3) {
+    return fmaf(h[3], r3, fmaf(h[2], r2, fmaf(h[1], r1, h[0] * r0)));
+}
+
+// L^T of an LL-only coefficient image at the lane's pixels of rows 2r (s0)
+// and 2r+1 (s1), from coefficient rows r (c) and r-1 (cp) at columns
+// pc[0..NC]: pixel (2r+p, 2s+q) = sum_{a,b} h_{p+2a} h_{q+2b} c(r-a, s-b).
+template <int NC>
+__device__ __forceinline__ void synth_rows(const float (&h)[4], const float (&c)[NC + 1], const float (&cp)[NC + 1],
+                                           f2 (&s0)[NC], f2 (&s1)[NC]) {
+    float v0[NC + 1], v1[NC + 1];
+#pragma unroll
+    for (int j = 0; j <= NC; ++j) {
+        v0[j] = fmaf(h[2], cp[j], h[0] * c[j]);
+        v1[j] = fmaf(h[3], cp[j], h[1] * c[j]);
+    }
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+        s0[i].x = fmaf(h[2], v0[i], h[0] * v0[i + 1]);
+        s0[i].y = fmaf(h[3], v0[i], h[1] * v0[i + 1]);
+        s1[i].x = fmaf(h[2], v1[i], h[0] * v1[i + 1]);
+        s1[i].y = fmaf(h[3], v1[i], h[1] * v1[i + 1]);
+    }
 }
 
 template <int NC, bool AL>
@@ -138,43 +170,37 @@ __device__ __forceinline__ void d4_adj_unit(const AdjParams &p, const Filters &f
     const int re = min(rb + p.seg_rows, H2);
     auto wrow = [&](int y) { return y < 0 ? y + p.H : (y >= p.H ? y - p.H : y); };
 
-    // L PAN at coefficient row rb-1 and L Y at rb-1 (Y = sum_b g_b y_b).
+    // Row-filtered PAN rows 2r, 2r+1 (Ra, Rb), their pixels (xa, xb), and
+    // L PAN / L Y at coefficient row r-1 (Ap, LYp), Y = sum_b g_b y_b.
     f2 xa[NC + 2], xb[NC + 2];
     float Ra[NC + 1], Rb[NC + 1], Ap[NC + 1], LYp[NC + 1];
     {
         f2 xt[NC + 2];
-        float Rt[NC + 1];
-#pragma unroll
-        for (int j = 0; j <= NC; ++j) {
-            Ap[j] = 0.f;
-            LYp[j] = 0.f;
-        }
-        for (int k = 0; k < 2; ++k) {
-            load_pairs<NC, AL>(p.pan + (int64_t)wrow(2 * rb - 2 + k) * p.pan_ld, pc, s0, full, xt);
-            rowfilt<NC>(h, xt, Rt);
-#pragma unroll
-            for (int j = 0; j <= NC; ++j) Ap[j] += h[k] * Rt[j];
-        }
+        float Rs[NC + 1], Rt[NC + 1];
+        load_pairs<NC, AL>(p.pan + (int64_t)wrow(2 * rb - 2) * p.pan_ld, pc, s0, full, xt);
+        rowfilt<NC>(h, xt, Rs);
+        load_pairs<NC, AL>(p.pan + (int64_t)wrow(2 * rb - 1) * p.pan_ld, pc, s0, full, xt);
+        rowfilt<NC>(h, xt, Rt);
         load_pairs<NC, AL>(p.pan + (int64_t)(2 * rb) * p.pan_ld, pc, s0, full, xa);
         load_pairs<NC, AL>(p.pan + (int64_t)(2 * rb + 1) * p.pan_ld, pc, s0, full, xb);
         rowfilt<NC>(h, xa, Ra);
         rowfilt<NC>(h, xb, Rb);
 #pragma unroll
-        for (int j = 0; j <= NC; ++j) Ap[j] += h[2] * Ra[j] + h[3] * Rb[j];
+        for (int j = 0; j <= NC; ++j) {
+            Ap[j] = col4(h, Rs[j], Rt[j], Ra[j], Rb[j]);
+            LYp[j] = 0.f;
+        }
         for (int b = 0; b < p.B; ++b) {
             const float g = p.gain ? p.gain[b] : 1.0f;
             const float *yb = p.gy + (int64_t)b * p.gy_bs;
-            float Ly[NC + 1];
+            float R4[4][NC + 1];
 #pragma unroll
-            for (int j = 0; j <= NC; ++j) Ly[j] = 0.f;
             for (int k = 0; k < 4; ++k) {
                 load_pairs<NC, AL>(yb + (int64_t)wrow(2 * rb - 2 + k) * p.gy_ld, pc, s0, full, xt);
-                rowfilt<NC>(h, xt, Rt);
-#pragma unroll
-                for (int j = 0; j <= NC; ++j) Ly[j] += h[k] * Rt[j];
+                rowfilt<NC>(h, xt, R4[k]);
             }
 #pragma unroll
-            for (int j = 0; j <= NC; ++j) LYp[j] += g * Ly[j];
+            for (int j = 0; j <= NC; ++j) LYp[j] = fmaf(g, col4(h, R4[0][j], R4[1][j], R4[2][j], R4[3][j]), LYp[j]);
         }
     }
 
@@ -186,22 +212,16 @@ __device__ __forceinline__ void d4_adj_unit(const AdjParams &p, const Filters &f
         rowfilt<NC>(h, xc, Rc);
         rowfilt<NC>(h, xd, Rd);
 #pragma unroll
-        for (int j = 0; j <= NC; ++j) A[j] = h[0] * Ra[j] + h[1] * Rb[j] + h[2] * Rc[j] + h[3] * Rd[j];
+        for (int j = 0; j <= NC; ++j) A[j] = col4(h, Ra[j], Rb[j], Rc[j], Rd[j]);
         // D = PAN - P PAN at output rows 2r, 2r+1 (own pixels).
         f2 Da[NC], Db[NC];
         {
-            float w0[NC + 1], w1[NC + 1];
-#pragma unroll
-            for (int j = 0; j <= NC; ++j) {
-                w0[j] = h[0] * A[j] + h[2] * Ap[j];
-                w1[j] = h[1] * A[j] + h[3] * Ap[j];
-            }
+            f2 sa[NC], sb[NC];
+            synth_rows<NC>(h, A, Ap, sa, sb);
 #pragma unroll
             for (int i = 0; i < NC; ++i) {
-                Da[i].x = xa[i + 1].x - (h[0] * w0[i + 1] + h[2] * w0[i]);
-                Da[i].y = xa[i + 1].y - (h[1] * w0[i + 1] + h[3] * w0[i]);
-                Db[i].x = xb[i + 1].x - (h[0] * w1[i + 1] + h[2] * w1[i]);
-                Db[i].y = xb[i + 1].y - (h[1] * w1[i + 1] + h[3] * w1[i]);
+                Da[i] = xa[i + 1] - sa[i];
+                Db[i] = xb[i + 1] - sb[i];
             }
         }
         float LY[NC + 1];
@@ -217,23 +237,17 @@ __device__ __forceinline__ void d4_adj_unit(const AdjParams &p, const Filters &f
             const float g = p.gain ? p.gain[b] : 1.0f;
             const float *yb = p.gy + (int64_t)b * p.gy_bs;
             f2 z0[NC + 2], z1[NC + 2], zt[NC + 2];
-            float R0[NC + 1], Rt[NC + 1], Ly[NC + 1];
+            float R0[NC + 1], R1[NC + 1], R2[NC + 1], R3[NC + 1], Ly[NC + 1];
             load_pairs<NC, AL>(yb + (int64_t)(2 * r) * p.gy_ld, pc, s0, full, z0);
             load_pairs<NC, AL>(yb + (int64_t)(2 * r + 1) * p.gy_ld, pc, s0, full, z1);
             rowfilt<NC>(h, z0, R0);
-#pragma unroll
-            for (int j = 0; j <= NC; ++j) Ly[j] = h[0] * R0[j];
-            rowfilt<NC>(h, z1, Rt);
-#pragma unroll
-            for (int j = 0; j <= NC; ++j) Ly[j] += h[1] * Rt[j];
+            rowfilt<NC>(h, z1, R1);
             load_pairs<NC, AL>(yb + (int64_t)wrow(2 * r + 2) * p.gy_ld, pc, s0, full, zt);
-            rowfilt<NC>(h, zt, Rt);
-#pragma unroll
-            for (int j = 0; j <= NC; ++j) Ly[j] += h[2] * Rt[j];
+            rowfilt<NC>(h, zt, R2);
             load_pairs<NC, AL>(yb + (int64_t)wrow(2 * r + 3) * p.gy_ld, pc, s0, full, zt);
-            rowfilt<NC>(h, zt, Rt);
+            rowfilt<NC>(h, zt, R3);
 #pragma unroll
-            for (int j = 0; j <= NC; ++j) Ly[j] += h[3] * Rt[j];
+            for (int j = 0; j <= NC; ++j) Ly[j] = col4(h, R0[j], R1[j], R2[j], R3[j]);
             if (p.grad_ms) {
                 float v[NC];
 #pragma unroll
@@ -241,34 +255,29 @@ __device__ __forceinline__ void d4_adj_unit(const AdjParams &p, const Filters &f
                 store_ms<NC, AL>(p.grad_ms + (int64_t)b * H2 * W2 + (int64_t)r * W2, s0, W2, full, v);
             }
 #pragma unroll
-            for (int j = 0; j <= NC; ++j) LY[j] += g * Ly[j];
+            for (int j = 0; j <= NC; ++j) LY[j] = fmaf(g, Ly[j], LY[j]);
             float dot = 0.f;
 #pragma unroll
             for (int i = 0; i < NC; ++i) {
                 if (!valid[i]) continue;
-                Ya[i].x += g * z0[i + 1].x;
-                Ya[i].y += g * z0[i + 1].y;
-                Yb[i].x += g * z1[i + 1].x;
-                Yb[i].y += g * z1[i + 1].y;
-                dot += z0[i + 1].x * Da[i].x + z0[i + 1].y * Da[i].y + z1[i + 1].x * Db[i].x +
-                       z1[i + 1].y * Db[i].y;
+                Ya[i].x = fmaf(g, z0[i + 1].x, Ya[i].x);
+                Ya[i].y = fmaf(g, z0[i + 1].y, Ya[i].y);
+                Yb[i].x = fmaf(g, z1[i + 1].x, Yb[i].x);
+                Yb[i].y = fmaf(g, z1[i + 1].y, Yb[i].y);
+                dot = fmaf(z0[i + 1].x, Da[i].x, dot);
+                dot = fmaf(z0[i + 1].y, Da[i].y, dot);
+                dot = fmaf(z1[i + 1].x, Db[i].x, dot);
+                dot = fmaf(z1[i + 1].y, Db[i].y, dot);
             }
             acc[b * acc_stride] += dot;
         }
         if (p.grad_pan) {
-            float v0[NC + 1], v1[NC + 1];
-#pragma unroll
-            for (int j = 0; j <= NC; ++j) {
-                v0[j] = h[0] * LY[j] + h[2] * LYp[j];
-                v1[j] = h[1] * LY[j] + h[3] * LYp[j];
-            }
-            f2 q0[NC], q1[NC];
+            f2 sa[NC], sb[NC], q0[NC], q1[NC];
+            synth_rows<NC>(h, LY, LYp, sa, sb);
 #pragma unroll
             for (int i = 0; i < NC; ++i) {
-                q0[i].x = Ya[i].x - (h[0] * v0[i + 1] + h[2] * v0[i]);
-                q0[i].y = Ya[i].y - (h[1] * v0[i + 1] + h[3] * v0[i]);
-                q1[i].x = Yb[i].x - (h[0] * v1[i + 1] + h[2] * v1[i]);
-                q1[i].y = Yb[i].y - (h[1] * v1[i + 1] + h[3] * v1[i]);
+                q0[i] = Ya[i] - sa[i];
+                q1[i] = Yb[i] - sb[i];
             }
             float *g0 = p.grad_pan + (int64_t)(2 * r) * p.W;
             float *g1 = g0 + p.W;
@@ -295,6 +304,139 @@ __device__ __forceinline__ void d4_adj_unit(const AdjParams &p, const Filters &f
         for (int k = 0; k < NC + 2; ++k) {
             xa[k] = xc[k];
             xb[k] = xd[k];
+        }
+    }
+}
+
+// ---- D4 adjoint, one-shot tile of KR coefficient rows ----------------------
+//
+// One wavefront covers KR coefficient rows of a strip: it issues all PAN rows
+// 2rb-2 .. 2rb+2KR+1 at once, then, band after band, all of that band's
+// upstream-gradient rows at once (the halo rows are re-read from L2).  The
+// per-pixel values use the shared fma chains above, so grad_pan and grad_ms
+// agree with the rolling units bit for bit; only the gain partial sums
+// differ in rounding (their per-unit split).
+
+template <int NC, bool AL, int KR>
+__device__ __forceinline__ void d4_adj_tile(const AdjParams &p, const Filters &f, int strip, int seg, int lane,
+                                            float *acc, int acc_stride) {
+    const int W2 = p.W >> 1, H2 = p.H >> 1;
+    const int s0 = (strip * 64 + lane) * NC;
+    if (s0 >= W2) return;
+    const bool full = (s0 + NC) <= W2;
+    bool valid[NC];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) valid[i] = (s0 + i) < W2;
+    int pc[NC + 2];
+#pragma unroll
+    for (int k = 0; k < NC + 2; ++k) pc[k] = wrap_idx(s0 - 1 + k, W2);
+    const float h[4] = {f.h[0], f.h[1], f.h[2], f.h[3]};
+    const int rb = seg * KR;
+    const int nr = min(KR, H2 - rb);
+    constexpr int NR = 2 * KR + 4;  // image rows 2rb-2 .. 2rb+2KR+1
+    auto wrow = [&](int y) { return wrap_idx(y, p.H); };
+
+    // D = PAN - P PAN at the lane's pixels of the tile's 2*nr rows.
+    f2 D[2 * KR][NC];
+    {
+        f2 x[NR][NC + 2];
+#pragma unroll
+        for (int k = 0; k < NR; ++k)
+            load_pairs<NC, AL>(p.pan + (int64_t)wrow(2 * rb - 2 + k) * p.pan_ld, pc, s0, full, x[k]);
+        float R[NR][NC + 1];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) rowfilt<NC>(h, x[k], R[k]);
+        float A[KR + 1][NC + 1];  // L PAN at coefficient rows rb-1 .. rb+KR-1
+#pragma unroll
+        for (int i = 0; i <= KR; ++i)
+#pragma unroll
+            for (int j = 0; j <= NC; ++j) A[i][j] = col4(h, R[2 * i][j], R[2 * i + 1][j], R[2 * i + 2][j], R[2 * i + 3][j]);
+#pragma unroll
+        for (int i = 0; i < KR; ++i) {
+            f2 sa[NC], sb[NC];
+            synth_rows<NC>(h, A[i + 1], A[i], sa, sb);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                D[2 * i][c] = x[2 * i + 2][c + 1] - sa[c];
+                D[2 * i + 1][c] = x[2 * i + 3][c + 1] - sb[c];
+            }
+        }
+    }
+    float LY[KR + 1][NC + 1];
+    f2 Y[2 * KR][NC];
+#pragma unroll
+    for (int i = 0; i <= KR; ++i)
+#pragma unroll
+        for (int j = 0; j <= NC; ++j) LY[i][j] = 0.f;
+#pragma unroll
+    for (int t = 0; t < 2 * KR; ++t)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) Y[t][c] = f2{0.f, 0.f};
+
+    for (int b = 0; b < p.B; ++b) {
+        const float *yb = p.gy + (int64_t)b * p.gy_bs;
+        f2 z[NR][NC + 2];
+#pragma unroll
+        for (int k = 0; k < NR; ++k)
+            load_pairs<NC, AL>(yb + (int64_t)wrow(2 * rb - 2 + k) * p.gy_ld, pc, s0, full, z[k]);
+        const float g = p.gain ? p.gain[b] : 1.0f;
+        float R[NR][NC + 1];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) rowfilt<NC>(h, z[k], R[k]);
+#pragma unroll
+        for (int i = 0; i <= KR; ++i) {
+            // L y_b at coefficient row rb-1+i; rows rb .. rb+nr-1 are this tile's grad_ms.
+            float Ly[NC + 1];
+#pragma unroll
+            for (int j = 0; j <= NC; ++j) Ly[j] = col4(h, R[2 * i][j], R[2 * i + 1][j], R[2 * i + 2][j], R[2 * i + 3][j]);
+            if (i >= 1 && i - 1 < nr && p.grad_ms) {
+                float v[NC];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) v[c] = Ly[c + 1];
+                store_ms<NC, AL>(p.grad_ms + (int64_t)b * H2 * W2 + (int64_t)(rb + i - 1) * W2, s0, W2, full, v);
+            }
+#pragma unroll
+            for (int j = 0; j <= NC; ++j) LY[i][j] = fmaf(g, Ly[j], LY[i][j]);
+        }
+        float dot = 0.f;
+#pragma unroll
+        for (int t = 0; t < 2 * KR; ++t) {
+            if (t >= 2 * nr) break;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                if (!valid[c]) continue;
+                const f2 zz = z[t + 2][c + 1];
+                Y[t][c].x = fmaf(g, zz.x, Y[t][c].x);
+                Y[t][c].y = fmaf(g, zz.y, Y[t][c].y);
+                dot = fmaf(zz.x, D[t][c].x, dot);
+                dot = fmaf(zz.y, D[t][c].y, dot);
+            }
+        }
+        acc[b * acc_stride] += dot;
+    }
+    if (p.grad_pan) {
+#pragma unroll
+        for (int i = 0; i < KR; ++i) {
+            if (i >= nr) break;
+            f2 sa[NC], sb[NC], q0[NC], q1[NC];
+            synth_rows<NC>(h, LY[i + 1], LY[i], sa, sb);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                q0[c] = Y[2 * i][c] - sa[c];
+                q1[c] = Y[2 * i + 1][c] - sb[c];
+            }
+            float *g0 = p.grad_pan + (int64_t)(2 * (rb + i)) * p.W;
+            float *g1 = g0 + p.W;
+            if (p.accumulate) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    if (!valid[c]) continue;
+                    q0[c] += ld2<AL>(g0 + 2 * (s0 + c));
+                    q1[c] += ld2<AL>(g1 + 2 * (s0 + c));
+                }
+            }
+            store_pairs<NC, AL>(g0, s0, W2, full, q0);
+            store_pairs<NC, AL>(g1, s0, W2, full, q1);
         }
     }
 }
@@ -417,6 +559,33 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjParams p, Filters f) {
     }
 }
 
+// One-shot D4 adjoint tiles of KR coefficient rows (p.seg_rows == KR).
+template <int NC, bool AL, int KR>
+__global__ __launch_bounds__(256) void adjoint_tile_kernel(AdjParams p, Filters f) {
+    __shared__ float acc_lds[kAdjMaxBands * 256];
+    const int wpb = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int unit = xcd_remap(blockIdx.x, gridDim.x) * wpb + (threadIdx.x >> 6);
+    if (unit >= p.units) return;  // whole wavefront leaves together
+    float *acc = acc_lds + threadIdx.x;
+    for (int b = 0; b < p.B; ++b) acc[b * 256] = 0.f;
+    int strip, seg;
+    if (p.order) {
+        seg = unit / p.nstrips;
+        strip = unit - seg * p.nstrips;
+    } else {
+        strip = unit / p.nseg;
+        seg = unit - strip * p.nseg;
+    }
+    d4_adj_tile<NC, AL, KR>(p, f, strip, seg, lane, acc, 256);
+    if (p.partial) {
+        for (int b = 0; b < p.B; ++b) {
+            const float s = wave_sum(acc[b * 256]);
+            if (lane == 0) p.partial[(int64_t)unit * p.pstride + b] = s;
+        }
+    }
+}
+
 // grad_gain[b] = sum over units of partial[unit * pstride + b], in FP64 with
 // a fixed assignment of units to threads and a fixed reduction tree.
 __global__ __launch_bounds__(256) void gain_reduce_kernel(const float *partial, int units, int pstride,
@@ -530,22 +699,15 @@ __global__ __launch_bounds__(256) void d4_adjoint_staged_kernel(AdjParams p, Fil
 #pragma unroll
         for (int i = 0; i <= KR; ++i)
 #pragma unroll
-            for (int j = 0; j < 3; ++j)
-                A[i][j] = h[0] * R[2 * i][j] + h[1] * R[2 * i + 1][j] + h[2] * R[2 * i + 2][j] + h[3] * R[2 * i + 3][j];
+            for (int j = 0; j < 3; ++j) A[i][j] = col4(h, R[2 * i][j], R[2 * i + 1][j], R[2 * i + 2][j], R[2 * i + 3][j]);
 #pragma unroll
         for (int i = 0; i < KR; ++i) {
-            float w0[3], w1[3];
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                w0[j] = h[0] * A[i + 1][j] + h[2] * A[i][j];
-                w1[j] = h[1] * A[i + 1][j] + h[3] * A[i][j];
-            }
+            f2 sa[2], sb[2];
+            synth_rows<2>(h, A[i + 1], A[i], sa, sb);
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
-                D[2 * i][c].x = own[2 * i][c].x - (h[0] * w0[c + 1] + h[2] * w0[c]);
-                D[2 * i][c].y = own[2 * i][c].y - (h[1] * w0[c + 1] + h[3] * w0[c]);
-                D[2 * i + 1][c].x = own[2 * i + 1][c].x - (h[0] * w1[c + 1] + h[2] * w1[c]);
-                D[2 * i + 1][c].y = own[2 * i + 1][c].y - (h[1] * w1[c + 1] + h[3] * w1[c]);
+                D[2 * i][c] = own[2 * i][c] - sa[c];
+                D[2 * i + 1][c] = own[2 * i + 1][c] - sb[c];
             }
         }
     }
@@ -580,8 +742,7 @@ __global__ __launch_bounds__(256) void d4_adjoint_staged_kernel(AdjParams p, Fil
 #pragma unroll
         for (int i = 0; i <= KR; ++i)
 #pragma unroll
-            for (int j = 0; j < 3; ++j)
-                Ly[i][j] = h[0] * R[2 * i][j] + h[1] * R[2 * i + 1][j] + h[2] * R[2 * i + 2][j] + h[3] * R[2 * i + 3][j];
+            for (int j = 0; j < 3; ++j) Ly[i][j] = col4(h, R[2 * i][j], R[2 * i + 1][j], R[2 * i + 2][j], R[2 * i + 3][j]);
         float dot = 0.f;
         if (active) {
 #pragma unroll
@@ -590,15 +751,17 @@ __global__ __launch_bounds__(256) void d4_adjoint_staged_kernel(AdjParams p, Fil
 #pragma unroll
                 for (int c = 0; c < 2; ++c) {
                     if (c == 1 && !full) break;
-                    Y[t][c] += g * yo[t][c];
-                    dot += yo[t][c].x * D[t][c].x + yo[t][c].y * D[t][c].y;
+                    Y[t][c].x = fmaf(g, yo[t][c].x, Y[t][c].x);
+                    Y[t][c].y = fmaf(g, yo[t][c].y, Y[t][c].y);
+                    dot = fmaf(yo[t][c].x, D[t][c].x, dot);
+                    dot = fmaf(yo[t][c].y, D[t][c].y, dot);
                 }
             }
         }
 #pragma unroll
         for (int i = 0; i <= KR; ++i)
 #pragma unroll
-            for (int j = 0; j < 3; ++j) LY[i][j] += g * Ly[i][j];
+            for (int j = 0; j < 3; ++j) LY[i][j] = fmaf(g, Ly[i][j], LY[i][j]);
         if (p.partial) {
             const float sd = wave_sum(dot);
             if (lane == 0) red[b * wpb + w] = sd;
@@ -624,19 +787,12 @@ __global__ __launch_bounds__(256) void d4_adjoint_staged_kernel(AdjParams p, Fil
 #pragma unroll
         for (int i = 0; i < KR; ++i) {
             if (i >= nr) break;
-            float v0[3], v1[3];
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                v0[j] = h[0] * LY[i + 1][j] + h[2] * LY[i][j];
-                v1[j] = h[1] * LY[i + 1][j] + h[3] * LY[i][j];
-            }
-            f2 q0[2], q1[2];
+            f2 sa[2], sb[2], q0[2], q1[2];
+            synth_rows<2>(h, LY[i + 1], LY[i], sa, sb);
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
-                q0[c].x = Y[2 * i][c].x - (h[0] * v0[c + 1] + h[2] * v0[c]);
-                q0[c].y = Y[2 * i][c].y - (h[1] * v0[c + 1] + h[3] * v0[c]);
-                q1[c].x = Y[2 * i + 1][c].x - (h[0] * v1[c + 1] + h[2] * v1[c]);
-                q1[c].y = Y[2 * i + 1][c].y - (h[1] * v1[c + 1] + h[3] * v1[c]);
+                q0[c] = Y[2 * i][c] - sa[c];
+                q1[c] = Y[2 * i + 1][c] - sb[c];
             }
             float *g0 = p.grad_pan + (int64_t)(2 * (rb + i)) * p.W + 2 * s0;
             if (full) {
@@ -694,6 +850,28 @@ hipError_t launch_adjoint(const AdjParams &p, const Filters &f, int wpb, hipStre
             hipLaunchKernelGGL((adjoint_kernel<1, false>), dim3(grid), block, 0, s, p, f);
             break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_tile(const AdjParams &p, const Filters &f, int kr, int wpb, hipStream_t s) {
+    if (p.units <= 0) return hipSuccess;
+    if (p.B > kAdjMaxBands || p.B < 1 || p.wavelet != 1 || p.seg_rows != kr || wpb < 1 || wpb > 4)
+        return hipErrorInvalidValue;
+    const int grid = (p.units + wpb - 1) / wpb;
+    const dim3 block(64 * wpb);
+#define ADJ_TILE(NC, AL, KR) hipLaunchKernelGGL((adjoint_tile_kernel<NC, AL, KR>), dim3(grid), block, 0, s, p, f)
+    if (kr == 1) {
+        if (p.path == PATH_V4) ADJ_TILE(2, true, 1);
+        else if (p.path == PATH_V2) ADJ_TILE(1, true, 1);
+        else ADJ_TILE(1, false, 1);
+    } else if (kr == 2) {
+        if (p.path == PATH_V4) ADJ_TILE(2, true, 2);
+        else if (p.path == PATH_V2) ADJ_TILE(1, true, 2);
+        else ADJ_TILE(1, false, 2);
+    } else {
+        return hipErrorInvalidValue;
+    }
+#undef ADJ_TILE
     return hipGetLastError();
 }
 

@@ -1504,13 +1504,16 @@ dwt_fuse_status dwt_fuse_backward(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet, i
             if (it != ctx->table.end()) t = it->second;
         }
         t = apply_forced(ctx, t, path, a.wavelet);
-        if (t.mode != 0) {  // the adjoint kernels are rolling only
+        // Adjoint kernels: rolling units (mode 0) and, for D4, one-shot tiles of
+        // 1 or 2 rows (mode 1, 2); no LDS-staged form here.
+        if (t.mode != 0 && !(a.wavelet == DWT_FUSE_D4 && (t.mode == 1 || t.mode == 2))) {
             const Tile r = rolling_tile(H, W, path);
             t.mode = 0;
             t.seg_rows = r.seg_rows;
             t.nc = std::min(t.nc, path_nc(path));
             if (t.nc < 1) t.nc = r.nc;
         }
+        if (t.mode == 1 || t.mode == 2) t.seg_rows = t.mode;
         if (t.seg_rows < 1) t.seg_rows = 1;
         const Path pp = path_for_nc(path, t.nc);
         Decomp d;
@@ -1545,7 +1548,8 @@ dwt_fuse_status dwt_fuse_backward(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet, i
             p.order = t.order;
             p.pstride = (int32_t)B;
             p.accumulate = b0 > 0 ? 1 : 0;
-            const hipError_t e = launch_adjoint(p, ctx->filt, t.wpb, ctx->stream);
+            const hipError_t e = t.mode == 0 ? launch_adjoint(p, ctx->filt, t.wpb, ctx->stream)
+                                             : launch_adjoint_tile(p, ctx->filt, t.mode, t.wpb, ctx->stream);
             if (e != hipSuccess) return hip_fail(ctx, e, "adjoint launch");
         }
         if (grad_gain) {

@@ -71,11 +71,11 @@ def test_adjoint_matches_oracle(dev, fz, oracle, wavelet, H, W, B):
 @pytest.mark.parametrize("B", [1, 4, 10])
 def test_forced_adjoint_shapes(dev, fz, oracle, H, W, B):
     """Forced launch shapes of the adjoint: rolling wavefronts with several
-    rows per unit / waves per workgroup / columns per lane, and the LDS-staged
-    D4 adjoint (variant 3, 1 or 2 rows per wavefront).  Every shape must meet
-    the oracle's tolerance; the rolling shapes evaluate every per-pixel
-    gradient with the same operations in the same order, so they also agree
-    bit for bit."""
+    rows per unit / waves per workgroup / columns per lane, one-shot tiles of
+    1 or 2 rows (variant 2), and the LDS-staged D4 adjoint (variant 3, 1 or 2
+    rows per wavefront).  Every shape must meet the oracle's tolerance; all
+    of them form every per-pixel gradient with the same fma chains in the same
+    order, so grad_pan and grad_ms also agree bit for bit."""
     rng = np.random.default_rng(7 * H + W + B)
     pan, _ = int_scene(rng, H, W, 1)
     gy = rng.normal(size=(B, H, W)).astype(np.float32)
@@ -85,17 +85,22 @@ def test_forced_adjoint_shapes(dev, fz, oracle, H, W, B):
     outs = []
     try:
         for seg, wpb, nc, var in [(0, 0, 0, 0), (1, 1, 1, 1), (3, 2, 2, 1), (16, 4, 2, 1), (200, 1, 1, 1),
+                                  (1, 4, 2, 2), (2, 2, 2, 2), (2, 1, 1, 2), (1, 2, 1, 2),
                                   (1, 4, 2, 3), (2, 2, 2, 3), (1, 1, 2, 3), (2, 4, 2, 3)]:
             say("adjoint forced", H, W, B, seg, wpb, nc, var)
             ctx.force_tile(seg, wpb, nc, var)
             got = [t.cpu().numpy() for t in fz.fuse_backward(p, y, "d4", g)]
             check_grads(oracle, "d4", pan, gy, gain, got)
-            if var != 3:
-                outs.append(got)
+            outs.append((seg, wpb, nc, var, got))
     finally:
         ctx.force_tile(0, 0, 0, 0)
-    for o in outs[1:]:
-        assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
+    for seg, wpb, nc, var, o in outs[1:]:
+        # Above 8 bands the rolling and one-shot kernels sum grad_pan over
+        # groups of 8 bands and add the groups; the staged kernel sums all
+        # bands in one pass, so only grad_ms is comparable bit for bit there.
+        if not (var == 3 and B > 8):
+            assert np.array_equal(o[0], outs[0][4][0]), ("grad_pan differs", seg, wpb, nc, var)
+        assert np.array_equal(o[1], outs[0][4][1]), ("grad_ms differs", seg, wpb, nc, var)
 
 
 @pytest.mark.parametrize("wavelet", ["haar", "d4"])
