@@ -32,7 +32,7 @@ __device__ __forceinline__ float byte_at(uint32_t w, int i) { return (float)((w 
 // [0, 255], NaN -> 0.  The gfx950 float-to-packed-byte conversion does
 // exactly this in one instruction per pixel (rounding in the default
 // nearest-even mode, saturating, NaN to 0); the parity tests check every
-// code against the oracle's definition.
+// code against that definition.
 __device__ __forceinline__ uint32_t q8(float v) { return __builtin_amdgcn_cvt_pk_u8_f32(v, 0, 0u); }
 
 __device__ __forceinline__ uint32_t pack4(float a, float b, float c, float d) {
