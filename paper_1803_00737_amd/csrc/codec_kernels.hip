@@ -1,6 +1,7 @@
-// Format variants of the fused kernels for gfx950: 8-bit or float32 PAN/MS,
-// 8-bit or float32 output, and a scale kappa on the MS band where it replaces
-// the LL quadrant (kappa = 1 is the method as printed).
+// Format variants of the fused kernels for gfx950: 8-bit PAN/MS with 8-bit
+// or float32 output, and float32 PAN/MS with 8-bit output, with the scale
+// kappa on the MS band where it replaces the LL quadrant (kappa = 1 is the
+// method as printed).  Float in and out runs on the float kernels.
 //
 // The paper moves images at 8 bits per pixel (section 3).  With 8-bit input
 // and output a fused pixel costs 1/B + 1/4 + 1 bytes of HBM traffic instead
@@ -145,8 +146,8 @@ struct CodecCols {
             for (int i = 0; i < NC; ++i) x[i] = ld_pair<TI, AL>(row + 2 * pc[i + 1]);
         }
     }
-    // MS coefficients at pc[0..NC], times kappa.
-    __device__ __forceinline__ void load_ms(const TI *mrow, float kappa, float (&m)[NC + 1]) const {
+    // MS coefficients at pc[0..NC].
+    __device__ __forceinline__ void load_ms(const TI *mrow, float (&m)[NC + 1]) const {
         m[0] = (float)mrow[pc[0]];
         if (AL && full) {
             ld_ms_vec<TI, NC>(mrow + s0, &m[1]);
@@ -154,18 +155,14 @@ struct CodecCols {
 #pragma unroll
             for (int k = 1; k <= NC; ++k) m[k] = (float)mrow[pc[k]];
         }
-#pragma unroll
-        for (int k = 0; k <= NC; ++k) m[k] *= kappa;
     }
-    __device__ __forceinline__ void load_ms_own(const TI *mrow, float kappa, float (&m)[NC]) const {
+    __device__ __forceinline__ void load_ms_own(const TI *mrow, float (&m)[NC]) const {
         if (AL && full) {
             ld_ms_vec<TI, NC>(mrow + s0, &m[0]);
         } else {
 #pragma unroll
             for (int i = 0; i < NC; ++i) m[i] = (float)mrow[pc[i + 1]];
         }
-#pragma unroll
-        for (int i = 0; i < NC; ++i) m[i] *= kappa;
     }
 };
 
@@ -228,7 +225,7 @@ __device__ __forceinline__ void d4_codec_tile(const CodecParams &p, const Filter
     auto load_band = [&](int b, float(&m)[KR + 1][NC + 1]) {
         const TI *mb = ms + (int64_t)b * p.ms_bs;
 #pragma unroll
-        for (int i = 0; i <= KR; ++i) L.load_ms(mb + (int64_t)wrap_idx(rb - 1 + i, H2) * p.ms_ld, p.kappa, m[i]);
+        for (int i = 0; i <= KR; ++i) L.load_ms(mb + (int64_t)wrap_idx(rb - 1 + i, H2) * p.ms_ld, m[i]);
     };
     float m[KR + 1][NC + 1];
     load_band(0, m);
@@ -249,7 +246,7 @@ __device__ __forceinline__ void d4_codec_tile(const CodecParams &p, const Filter
         for (int i = 0; i < KR; ++i) {
             if (i >= nr) break;
             f2 q0[NC], q1[NC];
-            d4_out_rows<NC>(f, g, m[i + 1], m[i], A[i + 1], A[i], x[2 * i + 2], x[2 * i + 3], q0, q1);
+            d4_out_rows<NC>(f, g, p.kappa, m[i + 1], m[i], A[i + 1], A[i], x[2 * i + 2], x[2 * i + 3], q0, q1);
             TO *o0 = ob + (int64_t)(2 * (rb + i)) * p.out_ld;
             store_out<TO, NC, AL>(o0, L.s0, L.W2, L.full, q0);
             store_out<TO, NC, AL>(o0 + p.out_ld, L.s0, L.W2, L.full, q1);
@@ -289,7 +286,7 @@ __device__ __forceinline__ void haar_codec_tile(const CodecParams &p, int strip,
     auto load_band = [&](int b, float(&m)[KR][NC]) {
         const TI *mb = ms + (int64_t)b * p.ms_bs;
 #pragma unroll
-        for (int i = 0; i < KR; ++i) L.load_ms_own(mb + (int64_t)(rb + (i < nr ? i : 0)) * p.ms_ld, p.kappa, m[i]);
+        for (int i = 0; i < KR; ++i) L.load_ms_own(mb + (int64_t)(rb + (i < nr ? i : 0)) * p.ms_ld, m[i]);
     };
     float m[KR][NC];
     load_band(0, m);
@@ -302,7 +299,7 @@ __device__ __forceinline__ void haar_codec_tile(const CodecParams &p, int strip,
         for (int i = 0; i < KR; ++i) {
             if (i >= nr) break;
             f2 q0[NC], q1[NC];
-            haar_out_rows<NC>(g, m[i], da[i], dc[i], q0, q1);
+            haar_out_rows<NC>(g, p.kappa, m[i], da[i], dc[i], q0, q1);
             TO *o0 = ob + (int64_t)(2 * (rb + i)) * p.out_ld;
             store_out<TO, NC, AL>(o0, L.s0, L.W2, L.full, q0);
             store_out<TO, NC, AL>(o0 + p.out_ld, L.s0, L.W2, L.full, q1);
@@ -378,8 +375,8 @@ hipError_t launch_codec(const CodecParams &p, const Filters &f, int in_u8, int o
         return out_u8 ? launch_io<uint8_t, uint8_t>(p, f, nc, kr, al, wpb, s)
                       : launch_io<uint8_t, float>(p, f, nc, kr, al, wpb, s);
     }
-    return out_u8 ? launch_io<float, uint8_t>(p, f, nc, kr, al, wpb, s)
-                  : launch_io<float, float>(p, f, nc, kr, al, wpb, s);
+    // float in and out is the tuned float path (fuse_kernels.hip)
+    return out_u8 ? launch_io<float, uint8_t>(p, f, nc, kr, al, wpb, s) : hipErrorInvalidValue;
 }
 
 }  // namespace dwtf

@@ -499,6 +499,7 @@ FuseParams make_params(const RunArgs &a, Path path, const Tile &t, const Decomp 
     p.nstrips = d.nstrips;
     p.order = t.order;
     p.mode = t.mode;
+    p.kappa = 1.0f;
     return p;
 }
 
@@ -1012,14 +1013,11 @@ dwt_fuse_status dwt_fuse_tune_load(dwt_fuse_ctx *ctx, const char *path) {
     return DWT_FUSE_OK;
 }
 
-dwt_fuse_status dwt_fuse_run(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet, int64_t H, int64_t W, int64_t B,
-                             const float *pan, int64_t pan_ld, const float *ms, int64_t ms_ld,
-                             int64_t ms_band_stride, const float *gain, float *out, int64_t out_ld,
-                             int64_t out_band_stride) {
-    if (!ctx) return DWT_FUSE_E_NULL;
+namespace {
+
+// Float PAN/MS/out: the tuned fused kernels, LL <- kappa * MS.
+dwt_fuse_status run_float(dwt_fuse_ctx *ctx, const RunArgs &a, float kappa) {
     try {
-        const RunArgs a{(int)wavelet, H, W, B, pan, pan_ld, ms, ms_ld, ms_band_stride, gain, out, out_ld,
-                        out_band_stride};
         std::string err;
         dwt_fuse_status st = check_run_args(a, nullptr, &err);
         if (st) return fail(ctx, st, err);
@@ -1027,8 +1025,9 @@ dwt_fuse_status dwt_fuse_run(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet, int64_
         const Path path = choose_path(a);
         const Tile t = tile_for_run(ctx, a, path, true);
         Decomp d;
-        if (!decompose(H, W, t, &d)) return fail(ctx, DWT_FUSE_E_SHAPE, "too many work units");
-        const FuseParams p = make_params(a, path_for_nc(path, t.nc), t, d);
+        if (!decompose(a.H, a.W, t, &d)) return fail(ctx, DWT_FUSE_E_SHAPE, "too many work units");
+        FuseParams p = make_params(a, path_for_nc(path, t.nc), t, d);
+        p.kappa = kappa;
         const hipError_t e = launch_fuse(p, ctx->filt, t.wpb, ctx->stream);
         if (e != hipSuccess) return hip_fail(ctx, e, "fuse launch");
         return DWT_FUSE_OK;
@@ -1037,6 +1036,18 @@ dwt_fuse_status dwt_fuse_run(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet, int64_
     } catch (...) {
         return fail(ctx, DWT_FUSE_E_STATE, "unexpected exception");
     }
+}
+
+}  // namespace
+
+dwt_fuse_status dwt_fuse_run(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet, int64_t H, int64_t W, int64_t B,
+                             const float *pan, int64_t pan_ld, const float *ms, int64_t ms_ld,
+                             int64_t ms_band_stride, const float *gain, float *out, int64_t out_ld,
+                             int64_t out_band_stride) {
+    if (!ctx) return DWT_FUSE_E_NULL;
+    const RunArgs a{(int)wavelet, H, W, B, pan, pan_ld, ms, ms_ld, ms_band_stride, gain, out, out_ld,
+                    out_band_stride};
+    return run_float(ctx, a, 1.0f);
 }
 
 namespace {
@@ -1207,10 +1218,12 @@ dwt_fuse_status dwt_fuse_run_ex(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet, int
                                 const dwt_fuse_opts *opts) {
     if (!ctx) return DWT_FUSE_E_NULL;
     const dwt_fuse_opts o = opts ? *opts : dwt_fuse_opts{DWT_FUSE_F32, DWT_FUSE_F32, 1.0f};
-    if (o.in_format == DWT_FUSE_F32 && o.out_format == DWT_FUSE_F32 && o.kappa == 1.0f)
-        return dwt_fuse_run(ctx, wavelet, H, W, B, static_cast<const float *>(pan), pan_ld,
-                            static_cast<const float *>(ms), ms_ld, ms_band_stride, gain, static_cast<float *>(out),
-                            out_ld, out_band_stride);
+    if (o.in_format == DWT_FUSE_F32 && o.out_format == DWT_FUSE_F32) {
+        const RunArgs a{(int)wavelet, H, W, B, static_cast<const float *>(pan), pan_ld,
+                        static_cast<const float *>(ms), ms_ld, ms_band_stride, gain,
+                        static_cast<const float *>(out), out_ld, out_band_stride};
+        return run_float(ctx, a, o.kappa);
+    }
     try {
         const ExArgs a{(int)wavelet, H, W, B, pan, pan_ld, ms, ms_ld, ms_band_stride, gain, out, out_ld,
                        out_band_stride, o.in_format, o.out_format, o.kappa};

@@ -34,7 +34,7 @@ struct FuseParams {
     int32_t nstrips;   // ceil((W/2) / (64*NC))
     int32_t order;     // unit numbering: 0 strip-major, 1 row-band-major
     int32_t mode;      // 0 rolling over seg_rows rows; 1, 2 one-shot tile of that many rows
-    int32_t pad_;
+    float kappa;       // LL <- kappa * MS band (1 = as printed)
 };
 
 // Daubechies-4 low-pass taps (Eq. 7-8), rounded once from double.
@@ -113,8 +113,8 @@ int adjoint_max_bands();
 hipError_t launch_adjoint_staged(const AdjParams &p, const Filters &f, int kr, int wpb, hipStream_t s);
 size_t adjoint_staged_lds(int T, int B);
 
-// Format variants (codec_kernels.hip): pan/ms float32 or 8-bit, out float32
-// or 8-bit, MS scaled by kappa.  Units are one-shot wavefronts over a strip of
+// Format variants (codec_kernels.hip): pan/ms 8-bit with out float32 or 8-bit,
+// or pan/ms float32 with out 8-bit; MS scaled by kappa.  Units are one-shot wavefronts over a strip of
 // 64*nc coefficient columns and kr coefficient rows; pitches and band
 // strides in elements of each buffer's format.
 struct CodecParams {

@@ -201,7 +201,7 @@ __device__ __forceinline__ void d4_rolling(const FuseParams &p, const Filters &f
             L.load_ms(mb + (int64_t)r * p.ms_ld, mc);
             L.load_ms(mb + (int64_t)rp * p.ms_ld, mp);
             f2 q0[NC], q1[NC];
-            d4_out_rows<NC>(f, g, mc, mp, A, Ap, xa, xb, q0, q1);
+            d4_out_rows<NC>(f, g, p.kappa, mc, mp, A, Ap, xa, xb, q0, q1);
             float *o0 = p.out + (int64_t)b * p.out_bs + (int64_t)(2 * r) * p.out_ld;
             L.store_row(o0, q0);
             L.store_row(o0 + p.out_ld, q1);
@@ -260,7 +260,7 @@ __device__ __forceinline__ void d4_tile(const FuseParams &p, const Filters &f, i
             if (i >= nr) break;
             // Coefficient row rb+i: output rows 2(rb+i), 2(rb+i)+1 are PAN rows x[2i+2], x[2i+3].
             f2 q0[NC], q1[NC];
-            d4_out_rows<NC>(f, g, m[i + 1], m[i], A[i + 1], A[i], x[2 * i + 2], x[2 * i + 3], q0, q1);
+            d4_out_rows<NC>(f, g, p.kappa, m[i + 1], m[i], A[i + 1], A[i], x[2 * i + 2], x[2 * i + 3], q0, q1);
             float *o0 = ob + (int64_t)(2 * (rb + i)) * p.out_ld;
             L.store_row(o0, q0);
             L.store_row(o0 + p.out_ld, q1);
@@ -294,7 +294,7 @@ __device__ __forceinline__ void haar_rolling(const FuseParams &p, int strip, int
             float m[NC];
             L.load_ms_own(p.ms + (int64_t)b * p.ms_bs + (int64_t)r * p.ms_ld, m);
             f2 q0[NC], q1[NC];
-            haar_out_rows<NC>(g, m, da, dc, q0, q1);
+            haar_out_rows<NC>(g, p.kappa, m, da, dc, q0, q1);
             float *o0 = p.out + (int64_t)b * p.out_bs + (int64_t)(2 * r) * p.out_ld;
             L.store_row(o0, q0);
             L.store_row(o0 + p.out_ld, q1);
@@ -342,7 +342,7 @@ __device__ __forceinline__ void haar_tile(const FuseParams &p, int strip, int se
             for (int i = 0; i < KR; ++i) {
                 if (i >= nr) break;
                 f2 q0[NC], q1[NC];
-                haar_out_rows<NC>(g, mall[b][i], da[i], dc[i], q0, q1);
+                haar_out_rows<NC>(g, p.kappa, mall[b][i], da[i], dc[i], q0, q1);
                 float *o0 = ob + (int64_t)(2 * (rb + i)) * p.out_ld;
                 L.store_row(o0, q0);
                 L.store_row(o0 + p.out_ld, q1);
@@ -363,7 +363,7 @@ __device__ __forceinline__ void haar_tile(const FuseParams &p, int strip, int se
         for (int i = 0; i < KR; ++i) {
             if (i >= nr) break;
             f2 q0[NC], q1[NC];
-            haar_out_rows<NC>(g, m[i], da[i], dc[i], q0, q1);
+            haar_out_rows<NC>(g, p.kappa, m[i], da[i], dc[i], q0, q1);
             float *o0 = ob + (int64_t)(2 * (rb + i)) * p.out_ld;
             L.store_row(o0, q0);
             L.store_row(o0 + p.out_ld, q1);
@@ -541,7 +541,7 @@ __device__ __forceinline__ void d4_staged_tile(const FuseParams &p, const Filter
                         xb[k + 1] = xo[h][2 * i + 1][k];
                     }
                     f2 q0[NC], q1[NC];
-                    d4_out_rows<NC>(f, g, m[i + 1], m[i], A[h][i + 1], A[h][i], xa, xb, q0, q1);
+                    d4_out_rows<NC>(f, g, p.kappa, m[i + 1], m[i], A[h][i + 1], A[h][i], xa, xb, q0, q1);
                     float *o0 = ob + (int64_t)(2 * (rb + i)) * p.out_ld + 2 * s0[h];
                     if constexpr (LAY == 0) {
                         if (s0[h] + 2 <= W2) {

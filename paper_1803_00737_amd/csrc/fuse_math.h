@@ -47,10 +47,10 @@ __device__ __forceinline__ void colfilt(const Filters &f, const float (&R0)[NC +
 }
 
 // Output rows 2r (q0) and 2r+1 (q1) of one band from the coefficient rows
-// c(r-1) = cp, c(r) = cc of (m - g L PAN) and the lane's PAN pixels of rows
-// 2r (xa) and 2r+1 (xb).
+// c(r-1) = cp, c(r) = cc of (kappa m - g L PAN) and the lane's PAN pixels of
+// rows 2r (xa) and 2r+1 (xb).  kappa = 1 multiplies exactly.
 template <int NC>
-__device__ __forceinline__ void d4_out_rows(const Filters &f, float g, const float (&mc)[NC + 1],
+__device__ __forceinline__ void d4_out_rows(const Filters &f, float g, float kappa, const float (&mc)[NC + 1],
                                             const float (&mp)[NC + 1], const float (&A)[NC + 1],
                                             const float (&Ap)[NC + 1], const f2 (&xa)[NC + 2],
                                             const f2 (&xb)[NC + 2], f2 (&q0)[NC], f2 (&q1)[NC]) {
@@ -58,8 +58,8 @@ __device__ __forceinline__ void d4_out_rows(const Filters &f, float g, const flo
     float v0[NC + 1], v1[NC + 1];
 #pragma unroll
     for (int j = 0; j <= NC; ++j) {
-        const float cc = fmaf(-g, A[j], mc[j]);   // coefficient row r
-        const float cp = fmaf(-g, Ap[j], mp[j]);  // coefficient row r-1
+        const float cc = fmaf(-g, A[j], kappa * mc[j]);   // coefficient row r
+        const float cp = fmaf(-g, Ap[j], kappa * mp[j]);  // coefficient row r-1
         v0[j] = fmaf(h2, cp, h0 * cc);             // output row 2r
         v1[j] = fmaf(h3, cp, h1 * cc);             // output row 2r+1
     }
@@ -84,14 +84,15 @@ __device__ __forceinline__ void haar_details(const f2 (&a)[NC], const f2 (&c)[NC
     }
 }
 
-// Output rows 2r, 2r+1 of one band: m + g * detail.
+// Output rows 2r, 2r+1 of one band: kappa m + g * detail.
 template <int NC>
-__device__ __forceinline__ void haar_out_rows(float g, const float (&m)[NC], const f2 (&da)[NC], const f2 (&dc)[NC],
+__device__ __forceinline__ void haar_out_rows(float g, float kappa, const float (&m)[NC], const f2 (&da)[NC], const f2 (&dc)[NC],
                                               f2 (&q0)[NC], f2 (&q1)[NC]) {
 #pragma unroll
     for (int i = 0; i < NC; ++i) {
-        q0[i] = f2{fmaf(g, da[i].x, m[i]), fmaf(g, da[i].y, m[i])};
-        q1[i] = f2{fmaf(g, dc[i].x, m[i]), fmaf(g, dc[i].y, m[i])};
+        const float mk = kappa * m[i];
+        q0[i] = f2{fmaf(g, da[i].x, mk), fmaf(g, da[i].y, mk)};
+        q1[i] = f2{fmaf(g, dc[i].x, mk), fmaf(g, dc[i].y, mk)};
     }
 }
 
