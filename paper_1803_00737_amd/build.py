@@ -49,7 +49,9 @@ def build(verbose: bool = False, arch: str = "gfx950") -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
     cc = hipcc()
     bid = build_id()
-    common = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I", INCLUDE, "-I", CSRC,
+    # Only the C ABI of include/dwt_fuse.h is exported (dwt_fuse_api.cpp
+    # includes the header with default visibility); everything else is hidden.
+    common = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-fvisibility=hidden", "-I", INCLUDE, "-I", CSRC,
               '-DDWT_FUSE_BUILD_ID="%s"' % bid]
 
     def compile_one(src):

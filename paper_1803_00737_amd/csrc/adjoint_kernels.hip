@@ -308,6 +308,187 @@ __device__ __forceinline__ void d4_adj_unit(const AdjParams &p, const Filters &f
     }
 }
 
+// ---- D4 adjoint, rolling with a compile-time band group ------------------------
+//
+// As d4_adj_unit for BG (<= 4) bands, with the band loop unrolled so that the
+// loads of all bands' rows are independent and issued together, and with each
+// band's last two row-filtered upstream-gradient rows (and their own pixels)
+// kept in registers: rows 2r+2, 2r+3 of one step are rows 2r, 2r+1 of the
+// next, so every row of y_b is loaded once per unit.  Same fma chains as the
+// other D4 adjoints (bit-identical grad_pan / grad_ms).
+
+template <int NC, bool AL, int BG>
+__device__ __forceinline__ void d4_adj_unit_bg(const AdjParams &p, const Filters &f, int strip, int seg, int lane,
+                                               float *acc, int acc_stride) {
+    const int W2 = p.W >> 1, H2 = p.H >> 1;
+    const int s0 = (strip * 64 + lane) * NC;
+    if (s0 >= W2) return;
+    const bool full = (s0 + NC) <= W2;
+    bool valid[NC];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) valid[i] = (s0 + i) < W2;
+    int pc[NC + 2];
+#pragma unroll
+    for (int k = 0; k < NC + 2; ++k) pc[k] = wrap_idx(s0 - 1 + k, W2);
+    const float h[4] = {f.h[0], f.h[1], f.h[2], f.h[3]};
+    const int rb = seg * p.seg_rows;
+    const int re = min(rb + p.seg_rows, H2);
+    auto wrow = [&](int y) { return y < 0 ? y + p.H : (y >= p.H ? y - p.H : y); };
+    float g[BG];
+    const float *yb[BG];
+#pragma unroll
+    for (int j = 0; j < BG; ++j) {
+        g[j] = p.gain ? p.gain[j] : 1.0f;
+        yb[j] = p.gy + (int64_t)j * p.gy_bs;
+    }
+
+    f2 xa[NC + 2], xb[NC + 2];
+    float Ra[NC + 1], Rb[NC + 1], Ap[NC + 1], LYp[NC + 1];
+    // Per band: row-filtered y rows 2r, 2r+1 and their own pixels.
+    float Y0[BG][NC + 1], Y1[BG][NC + 1];
+    f2 o0[BG][NC], o1[BG][NC];
+    {
+        f2 xt[NC + 2];
+        float Rs[NC + 1], Rt[NC + 1];
+        load_pairs<NC, AL>(p.pan + (int64_t)wrow(2 * rb - 2) * p.pan_ld, pc, s0, full, xt);
+        rowfilt<NC>(h, xt, Rs);
+        load_pairs<NC, AL>(p.pan + (int64_t)wrow(2 * rb - 1) * p.pan_ld, pc, s0, full, xt);
+        rowfilt<NC>(h, xt, Rt);
+        load_pairs<NC, AL>(p.pan + (int64_t)(2 * rb) * p.pan_ld, pc, s0, full, xa);
+        load_pairs<NC, AL>(p.pan + (int64_t)(2 * rb + 1) * p.pan_ld, pc, s0, full, xb);
+        rowfilt<NC>(h, xa, Ra);
+        rowfilt<NC>(h, xb, Rb);
+#pragma unroll
+        for (int j = 0; j <= NC; ++j) {
+            Ap[j] = col4(h, Rs[j], Rt[j], Ra[j], Rb[j]);
+            LYp[j] = 0.f;
+        }
+#pragma unroll
+        for (int bb = 0; bb < BG; ++bb) {
+            f2 z[4][NC + 2];
+            float R4[4][NC + 1];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                load_pairs<NC, AL>(yb[bb] + (int64_t)wrow(2 * rb - 2 + k) * p.gy_ld, pc, s0, full, z[k]);
+                rowfilt<NC>(h, z[k], R4[k]);
+            }
+#pragma unroll
+            for (int j = 0; j <= NC; ++j) {
+                LYp[j] = fmaf(g[bb], col4(h, R4[0][j], R4[1][j], R4[2][j], R4[3][j]), LYp[j]);
+                Y0[bb][j] = R4[2][j];
+                Y1[bb][j] = R4[3][j];
+            }
+#pragma unroll
+            for (int i = 0; i < NC; ++i) {
+                o0[bb][i] = z[2][i + 1];
+                o1[bb][i] = z[3][i + 1];
+            }
+        }
+    }
+
+    for (int r = rb; r < re; ++r) {
+        // Loads of this step: PAN rows 2r+2, 2r+3 and y rows 2r+2, 2r+3 of every band.
+        f2 xc[NC + 2], xd[NC + 2];
+        f2 zc[BG][NC + 2], zd[BG][NC + 2];
+        load_pairs<NC, AL>(p.pan + (int64_t)wrow(2 * r + 2) * p.pan_ld, pc, s0, full, xc);
+        load_pairs<NC, AL>(p.pan + (int64_t)wrow(2 * r + 3) * p.pan_ld, pc, s0, full, xd);
+#pragma unroll
+        for (int bb = 0; bb < BG; ++bb) {
+            load_pairs<NC, AL>(yb[bb] + (int64_t)wrow(2 * r + 2) * p.gy_ld, pc, s0, full, zc[bb]);
+            load_pairs<NC, AL>(yb[bb] + (int64_t)wrow(2 * r + 3) * p.gy_ld, pc, s0, full, zd[bb]);
+        }
+        float Rc[NC + 1], Rd[NC + 1], A[NC + 1];
+        rowfilt<NC>(h, xc, Rc);
+        rowfilt<NC>(h, xd, Rd);
+#pragma unroll
+        for (int j = 0; j <= NC; ++j) A[j] = col4(h, Ra[j], Rb[j], Rc[j], Rd[j]);
+        f2 Da[NC], Db[NC];
+        {
+            f2 sa[NC], sb[NC];
+            synth_rows<NC>(h, A, Ap, sa, sb);
+#pragma unroll
+            for (int i = 0; i < NC; ++i) {
+                Da[i] = xa[i + 1] - sa[i];
+                Db[i] = xb[i + 1] - sb[i];
+            }
+        }
+        float LY[NC + 1];
+        f2 Ya[NC], Yb[NC];
+#pragma unroll
+        for (int j = 0; j <= NC; ++j) LY[j] = 0.f;
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            Ya[i] = f2{0.f, 0.f};
+            Yb[i] = f2{0.f, 0.f};
+        }
+#pragma unroll
+        for (int bb = 0; bb < BG; ++bb) {
+            float R2[NC + 1], R3[NC + 1], Ly[NC + 1];
+            rowfilt<NC>(h, zc[bb], R2);
+            rowfilt<NC>(h, zd[bb], R3);
+#pragma unroll
+            for (int j = 0; j <= NC; ++j) Ly[j] = col4(h, Y0[bb][j], Y1[bb][j], R2[j], R3[j]);
+            if (p.grad_ms) {
+                float v[NC];
+#pragma unroll
+                for (int i = 0; i < NC; ++i) v[i] = Ly[i + 1];
+                store_ms<NC, AL>(p.grad_ms + (int64_t)bb * H2 * W2 + (int64_t)r * W2, s0, W2, full, v);
+            }
+#pragma unroll
+            for (int j = 0; j <= NC; ++j) LY[j] = fmaf(g[bb], Ly[j], LY[j]);
+            float dot = 0.f;
+#pragma unroll
+            for (int i = 0; i < NC; ++i) {
+                if (!valid[i]) continue;
+                Ya[i].x = fmaf(g[bb], o0[bb][i].x, Ya[i].x);
+                Ya[i].y = fmaf(g[bb], o0[bb][i].y, Ya[i].y);
+                Yb[i].x = fmaf(g[bb], o1[bb][i].x, Yb[i].x);
+                Yb[i].y = fmaf(g[bb], o1[bb][i].y, Yb[i].y);
+                dot = fmaf(o0[bb][i].x, Da[i].x, dot);
+                dot = fmaf(o0[bb][i].y, Da[i].y, dot);
+                dot = fmaf(o1[bb][i].x, Db[i].x, dot);
+                dot = fmaf(o1[bb][i].y, Db[i].y, dot);
+            }
+            acc[bb * acc_stride] += dot;
+#pragma unroll
+            for (int j = 0; j <= NC; ++j) {
+                Y0[bb][j] = R2[j];
+                Y1[bb][j] = R3[j];
+            }
+#pragma unroll
+            for (int i = 0; i < NC; ++i) {
+                o0[bb][i] = zc[bb][i + 1];
+                o1[bb][i] = zd[bb][i + 1];
+            }
+        }
+        if (p.grad_pan) {
+            f2 sa[NC], sb[NC], q0[NC], q1[NC];
+            synth_rows<NC>(h, LY, LYp, sa, sb);
+#pragma unroll
+            for (int i = 0; i < NC; ++i) {
+                q0[i] = Ya[i] - sa[i];
+                q1[i] = Yb[i] - sb[i];
+            }
+            float *g0 = p.grad_pan + (int64_t)(2 * r) * p.W;
+            float *g1 = g0 + p.W;
+            store_pairs<NC, AL>(g0, s0, W2, full, q0);
+            store_pairs<NC, AL>(g1, s0, W2, full, q1);
+        }
+#pragma unroll
+        for (int j = 0; j <= NC; ++j) {
+            Ap[j] = A[j];
+            Ra[j] = Rc[j];
+            Rb[j] = Rd[j];
+            LYp[j] = LY[j];
+        }
+#pragma unroll
+        for (int k = 0; k < NC + 2; ++k) {
+            xa[k] = xc[k];
+            xb[k] = xd[k];
+        }
+    }
+}
+
 // ---- D4 adjoint, one-shot tile of KR coefficient rows ----------------------
 //
 // One wavefront covers KR coefficient rows of a strip: it issues all PAN rows
@@ -553,6 +734,36 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjParams p, Filters f) {
         haar_adj_unit<NC, AL>(p, strip, seg, lane, acc, 256);
     if (p.partial) {
         for (int b = 0; b < p.B; ++b) {
+            const float s = wave_sum(acc[b * 256]);
+            if (lane == 0) p.partial[(int64_t)unit * p.pstride + b] = s;
+        }
+    }
+}
+
+// Rolling D4 adjoint for a band group of BG = p.B <= 4 bands (one launch,
+// no accumulation into grad_pan).
+template <int NC, bool AL, int BG>
+__global__ __launch_bounds__(256) void adjoint_bg_kernel(AdjParams p, Filters f) {
+    __shared__ float acc_lds[4 * 256];
+    const int wpb = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int unit = xcd_remap(blockIdx.x, gridDim.x) * wpb + (threadIdx.x >> 6);
+    if (unit >= p.units) return;  // whole wavefront leaves together
+    float *acc = acc_lds + threadIdx.x;
+#pragma unroll
+    for (int b = 0; b < BG; ++b) acc[b * 256] = 0.f;
+    int strip, seg;
+    if (p.order) {
+        seg = unit / p.nstrips;
+        strip = unit - seg * p.nstrips;
+    } else {
+        strip = unit / p.nseg;
+        seg = unit - strip * p.nseg;
+    }
+    d4_adj_unit_bg<NC, AL, BG>(p, f, strip, seg, lane, acc, 256);
+    if (p.partial) {
+#pragma unroll
+        for (int b = 0; b < BG; ++b) {
             const float s = wave_sum(acc[b * 256]);
             if (lane == 0) p.partial[(int64_t)unit * p.pstride + b] = s;
         }
@@ -850,6 +1061,29 @@ hipError_t launch_adjoint(const AdjParams &p, const Filters &f, int wpb, hipStre
             hipLaunchKernelGGL((adjoint_kernel<1, false>), dim3(grid), block, 0, s, p, f);
             break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_bg(const AdjParams &p, const Filters &f, int wpb, hipStream_t s) {
+    if (p.units <= 0) return hipSuccess;
+    if (p.B < 1 || p.B > 4 || p.wavelet != 1 || p.accumulate || wpb < 1 || wpb > 4) return hipErrorInvalidValue;
+    const int grid = (p.units + wpb - 1) / wpb;
+    const dim3 block(64 * wpb);
+#define ADJ_BG(NC, AL, BG) hipLaunchKernelGGL((adjoint_bg_kernel<NC, AL, BG>), dim3(grid), block, 0, s, p, f)
+#define ADJ_BG_PATH(BG)                                   \
+    do {                                                  \
+        if (p.path == PATH_V4) ADJ_BG(2, true, BG);       \
+        else if (p.path == PATH_V2) ADJ_BG(1, true, BG);  \
+        else ADJ_BG(1, false, BG);                        \
+    } while (0)
+    switch (p.B) {
+        case 1: ADJ_BG_PATH(1); break;
+        case 2: ADJ_BG_PATH(2); break;
+        case 3: ADJ_BG_PATH(3); break;
+        default: ADJ_BG_PATH(4); break;
+    }
+#undef ADJ_BG_PATH
+#undef ADJ_BG
     return hipGetLastError();
 }
 

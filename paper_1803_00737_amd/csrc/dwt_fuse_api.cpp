@@ -1,7 +1,9 @@
 // Host side of the C ABI declared in include/dwt_fuse.h: argument
 // validation, the context (stream, workspace, batch tables, captured graphs,
 // tuning table), work decomposition and kernel dispatch.
+#pragma GCC visibility push(default)
 #include "dwt_fuse.h"
+#pragma GCC visibility pop
 
 #include <hip/hip_runtime.h>
 
@@ -1449,6 +1451,12 @@ dwt_fuse_status dwt_fuse_run_multipass(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavel
     }
 }
 
+// True when the backward shape of this call comes from the defaults (no
+// tuned or loaded table entry).
+static bool it_bwd_default(const dwt_fuse_ctx *ctx, const BwdArgs &a, Path path) {
+    return ctx->table.find(tune_key(1, a.wavelet, a.H, a.W, a.B, path)) == ctx->table.end();
+}
+
 dwt_fuse_status dwt_fuse_backward(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet, int64_t H, int64_t W, int64_t B,
                                   const float *pan, int64_t pan_ld, const float *gain, const float *grad_out,
                                   int64_t go_ld, int64_t go_band_stride, float *grad_pan, float *grad_ms,
@@ -1516,6 +1524,13 @@ dwt_fuse_status dwt_fuse_backward(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet, i
             auto it = ctx->table.find(tune_key(1, a.wavelet, H, W, B, path));
             if (it != ctx->table.end()) t = it->second;
         }
+        if (a.wavelet == DWT_FUSE_D4 && B <= 4 && ctx->forced.seg_rows == 0 && it_bwd_default(ctx, a, path)) {
+            // band-unrolled D4 adjoint: longest units (<= 32 rows) that still
+            // give >= 2048 units (measured best at 2048^2 .. 8192^2)
+            t.seg_rows = 32;
+            Decomp d0;
+            while (t.seg_rows > 4 && decompose(H, W, t, &d0) && d0.units < 2048) t.seg_rows /= 2;
+        }
         t = apply_forced(ctx, t, path, a.wavelet);
         // Adjoint kernels: rolling units (mode 0) and, for D4, one-shot tiles of
         // 1 or 2 rows (mode 1, 2); no LDS-staged form here.
@@ -1561,8 +1576,12 @@ dwt_fuse_status dwt_fuse_backward(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet, i
             p.order = t.order;
             p.pstride = (int32_t)B;
             p.accumulate = b0 > 0 ? 1 : 0;
-            const hipError_t e = t.mode == 0 ? launch_adjoint(p, ctx->filt, t.wpb, ctx->stream)
-                                             : launch_adjoint_tile(p, ctx->filt, t.mode, t.wpb, ctx->stream);
+            // D4 with at most 4 bands: the rolling kernel with the band loop
+            // unrolled (unless the dynamic-band rolling kernel is forced).
+            const bool bg = t.mode == 0 && a.wavelet == DWT_FUSE_D4 && B <= 4 && ctx->forced.variant != 1;
+            const hipError_t e = t.mode != 0 ? launch_adjoint_tile(p, ctx->filt, t.mode, t.wpb, ctx->stream)
+                                 : bg        ? launch_adjoint_bg(p, ctx->filt, t.wpb, ctx->stream)
+                                             : launch_adjoint(p, ctx->filt, t.wpb, ctx->stream);
             if (e != hipSuccess) return hip_fail(ctx, e, "adjoint launch");
         }
         if (grad_gain) {

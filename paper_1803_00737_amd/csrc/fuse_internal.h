@@ -98,6 +98,10 @@ int staged_bg_max(int T);
 
 hipError_t launch_adjoint(const AdjParams &p, const Filters &f, int waves_per_block, hipStream_t s);
 
+// Rolling D4 adjoint with the band loop unrolled for p.B <= 4 bands (whole
+// band set in one launch, no accumulate); same units as launch_adjoint.
+hipError_t launch_adjoint_bg(const AdjParams &p, const Filters &f, int waves_per_block, hipStream_t s);
+
 // One-shot D4 adjoint: units of kr (1 or 2) coefficient rows (p.seg_rows == kr),
 // same decomposition and band-group rules as launch_adjoint.
 hipError_t launch_adjoint_tile(const AdjParams &p, const Filters &f, int kr, int waves_per_block, hipStream_t s);

@@ -231,3 +231,17 @@ def test_run_ex_validation(lib):
     assert ex_check(lib, out=P - 128, B=2) == OK
     assert ex_check(lib, out=P - 127, B=2) == E_ALIAS
     assert lib.dwt_fuse_status_str(E_FORMAT) == b"unknown element format"
+
+
+def test_only_the_header_is_exported(lib):
+    """The library exports exactly the C ABI the header declares (internal
+    C++ symbols have hidden visibility)."""
+    import shutil
+    import subprocess
+
+    nm = shutil.which("nm")
+    if not nm:
+        pytest.skip("nm not available")
+    out = subprocess.run([nm, "-D", "--defined-only", _lib.LIB_PATH], capture_output=True, text=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if line.split()[1:2] == ["T"]}
+    assert exported == declared_symbols()

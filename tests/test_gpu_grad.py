@@ -71,7 +71,9 @@ def test_adjoint_matches_oracle(dev, fz, oracle, wavelet, H, W, B):
 @pytest.mark.parametrize("B", [1, 4, 10])
 def test_forced_adjoint_shapes(dev, fz, oracle, H, W, B):
     """Forced launch shapes of the adjoint: rolling wavefronts with several
-    rows per unit / waves per workgroup / columns per lane, one-shot tiles of
+    rows per unit / waves per workgroup / columns per lane (variant 0: the
+    band loop unrolled for up to 4 bands; variant 1: a dynamic band loop),
+    one-shot tiles of
     1 or 2 rows (variant 2), and the LDS-staged D4 adjoint (variant 3, 1 or 2
     rows per wavefront).  Every shape must meet the oracle's tolerance; all
     of them form every per-pixel gradient with the same fma chains in the same
@@ -85,6 +87,7 @@ def test_forced_adjoint_shapes(dev, fz, oracle, H, W, B):
     outs = []
     try:
         for seg, wpb, nc, var in [(0, 0, 0, 0), (1, 1, 1, 1), (3, 2, 2, 1), (16, 4, 2, 1), (200, 1, 1, 1),
+                                  (1, 1, 1, 0), (3, 2, 2, 0), (16, 4, 2, 0), (200, 1, 1, 0),
                                   (1, 4, 2, 2), (2, 2, 2, 2), (2, 1, 1, 2), (1, 2, 1, 2),
                                   (1, 4, 2, 3), (2, 2, 2, 3), (1, 1, 2, 3), (2, 4, 2, 3)]:
             say("adjoint forced", H, W, B, seg, wpb, nc, var)
