@@ -12,12 +12,13 @@
 // 8-bit output is that float32 value rounded to the nearest integer (ties to
 // even) and clamped to [0, 255] (NaN -> 0).
 //
-// Work decomposition: one-shot wavefront tiles.  A wavefront covers a strip
-// of 64*NC coefficient columns (each lane NC coefficient columns = 2*NC
-// pixels per row: 8 or 16 bytes of 8-bit PAN, 16 bytes of float PAN) and KR
-// coefficient rows of every band; it issues all its PAN rows (with the D4
-// halo rows and columns, Eq. 5-6 wrap) and the first band's MS rows before
-// computing, and loads band b+1 while band b is computed and stored.
+// Work decomposition: a wavefront covers a strip of 64*NC coefficient columns
+// (each lane NC coefficient columns = 2*NC pixels per row: 8 or 16 bytes of
+// 8-bit PAN, 16 bytes of float PAN) and a run of coefficient rows of every
+// band.  One-shot tiles (KR = 1, 2 rows) issue all their PAN rows (with the
+// D4 halo rows and columns, Eq. 5-6 wrap) and the first band's MS rows before
+// computing, and load band b+1 while band b is computed and stored; D4 also
+// has rolling units (KR = 0: seg_rows rows, each PAN row filtered once).
 #include "fuse_internal.h"
 #include "fuse_math.h"
 
@@ -260,6 +261,76 @@ __device__ __forceinline__ void d4_codec_tile(const CodecParams &p, const Filter
     }
 }
 
+// D4, rolling: the wavefront walks p.seg_rows coefficient rows of its strip,
+// keeping two row-filtered PAN rows, the PAN pixels of the current row pair
+// and one row of L PAN in registers, so each PAN row is unpacked and
+// filtered once per unit (the one-shot tiles filter the halo rows again in
+// every tile).  Same per-pixel arithmetic as the tiles.
+template <typename TI, typename TO, int NC, bool AL>
+__device__ __forceinline__ void d4_codec_rolling(const CodecParams &p, const Filters &f, int strip, int seg, int lane) {
+    const CodecCols<TI, NC, AL> L(strip, lane, p.W >> 1);
+    if (!L.active()) return;
+    const TI *pan = static_cast<const TI *>(p.pan);
+    const TI *ms = static_cast<const TI *>(p.ms);
+    TO *out = static_cast<TO *>(p.out);
+    const int H2 = p.H >> 1;
+    const int rb = seg * p.seg_rows;
+    const int re = min(rb + p.seg_rows, H2);
+    // rows needed lie in [-2, H+1]: one conditional wrap (Eq. 5-6) suffices
+    auto row = [&](int y) {
+        y = y < 0 ? y + p.H : (y >= p.H ? y - p.H : y);
+        return pan + (int64_t)y * p.pan_ld;
+    };
+    f2 xa[NC + 2], xb[NC + 2];
+    float Ra[NC + 1], Rb[NC + 1], Ap[NC + 1];
+    {
+        f2 xs[NC + 2], xt[NC + 2];
+        float Rs[NC + 1], Rt[NC + 1];
+        L.load_row(row(2 * rb - 2), xs);
+        L.load_row(row(2 * rb - 1), xt);
+        L.load_row(row(2 * rb), xa);
+        L.load_row(row(2 * rb + 1), xb);
+        rowfilt<NC>(f, xs, Rs);
+        rowfilt<NC>(f, xt, Rt);
+        rowfilt<NC>(f, xa, Ra);
+        rowfilt<NC>(f, xb, Rb);
+        colfilt<NC>(f, Rs, Rt, Ra, Rb, Ap);
+    }
+    for (int r = rb; r < re; ++r) {
+        f2 xc[NC + 2], xd[NC + 2];
+        L.load_row(row(2 * r + 2), xc);
+        L.load_row(row(2 * r + 3), xd);
+        float Rc[NC + 1], Rd[NC + 1], A[NC + 1];
+        rowfilt<NC>(f, xc, Rc);
+        rowfilt<NC>(f, xd, Rd);
+        colfilt<NC>(f, Ra, Rb, Rc, Rd, A);
+        const int rp = (r == 0) ? H2 - 1 : r - 1;
+        for (int b = 0; b < p.B; ++b) {
+            const float g = p.gain ? p.gain[b] : 1.0f;
+            const TI *mb = ms + (int64_t)b * p.ms_bs;
+            float mc[NC + 1], mp[NC + 1];
+            L.load_ms(mb + (int64_t)r * p.ms_ld, mc);
+            L.load_ms(mb + (int64_t)rp * p.ms_ld, mp);
+            f2 q0[NC], q1[NC];
+            d4_out_rows<NC>(f, g, p.kappa, mc, mp, A, Ap, xa, xb, q0, q1);
+            TO *o0 = out + (int64_t)b * p.out_bs + (int64_t)(2 * r) * p.out_ld;
+            store_out<TO, NC, AL>(o0, L.s0, L.W2, L.full, q0);
+            store_out<TO, NC, AL>(o0 + p.out_ld, L.s0, L.W2, L.full, q1);
+        }
+#pragma unroll
+        for (int j = 0; j <= NC; ++j) {
+            Ap[j] = A[j];
+            Ra[j] = Rc[j];
+            Rb[j] = Rd[j];
+        }
+#pragma unroll
+        for (int k = 0; k < NC + 2; ++k) {
+            xa[k] = xc[k];
+            xb[k] = xd[k];
+        }
+    }
+}
+
 template <typename TI, typename TO, int NC, int KR, bool AL>
 __device__ __forceinline__ void haar_codec_tile(const CodecParams &p, int strip, int seg, int lane) {
     const CodecCols<TI, NC, AL> L(strip, lane, p.W >> 1);
@@ -327,19 +398,28 @@ __global__ __launch_bounds__(256) void codec_kernel(CodecParams p, Filters f) {
         strip = unit / p.nseg;
         seg = unit - strip * p.nseg;
     }
-    if constexpr (WAV == 1)
-        d4_codec_tile<TI, TO, NC, KR, AL>(p, f, strip, seg, lane);
-    else
+    if constexpr (WAV == 1) {
+        if constexpr (KR == 0)
+            d4_codec_rolling<TI, TO, NC, AL>(p, f, strip, seg, lane);
+        else
+            d4_codec_tile<TI, TO, NC, KR, AL>(p, f, strip, seg, lane);
+    } else {
         haar_codec_tile<TI, TO, NC, KR, AL>(p, strip, seg, lane);
+    }
 }
 
 template <typename TI, typename TO, int NC, int KR, bool AL>
 hipError_t launch_t(const CodecParams &p, const Filters &f, int wpb, hipStream_t s) {
     const int grid = (p.units + wpb - 1) / wpb;
-    if (p.wavelet == 1)
-        hipLaunchKernelGGL((codec_kernel<TI, TO, NC, KR, AL, 1>), dim3(grid), dim3(64 * wpb), 0, s, p, f);
-    else
-        hipLaunchKernelGGL((codec_kernel<TI, TO, NC, KR, AL, 0>), dim3(grid), dim3(64 * wpb), 0, s, p, f);
+    if constexpr (KR == 0) {  // rolling exists for D4 only
+        if (p.wavelet != 1) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((codec_kernel<TI, TO, NC, 0, AL, 1>), dim3(grid), dim3(64 * wpb), 0, s, p, f);
+    } else {
+        if (p.wavelet == 1)
+            hipLaunchKernelGGL((codec_kernel<TI, TO, NC, KR, AL, 1>), dim3(grid), dim3(64 * wpb), 0, s, p, f);
+        else
+            hipLaunchKernelGGL((codec_kernel<TI, TO, NC, KR, AL, 0>), dim3(grid), dim3(64 * wpb), 0, s, p, f);
+    }
     return hipGetLastError();
 }
 
@@ -351,26 +431,32 @@ hipError_t launch_io(const CodecParams &p, const Filters &f, int nc, int kr, boo
         if (nc == 4 && kr == 2) return launch_t<TI, TO, 4, 2, true>(p, f, wpb, s);
         if (nc == 8 && kr == 1) return launch_t<TI, TO, 8, 1, true>(p, f, wpb, s);
         if (nc == 8 && kr == 2) return launch_t<TI, TO, 8, 2, true>(p, f, wpb, s);
+        if (nc == 4 && kr == 0) return launch_t<TI, TO, 4, 0, true>(p, f, wpb, s);
+        if (nc == 8 && kr == 0) return launch_t<TI, TO, 8, 0, true>(p, f, wpb, s);
     } else {
         if (!al) return (nc == 2 && kr == 1) ? launch_t<TI, TO, 2, 1, false>(p, f, wpb, s) : hipErrorInvalidValue;
         if (nc == 2 && kr == 1) return launch_t<TI, TO, 2, 1, true>(p, f, wpb, s);
         if (nc == 2 && kr == 2) return launch_t<TI, TO, 2, 2, true>(p, f, wpb, s);
+        if (nc == 2 && kr == 0) return launch_t<TI, TO, 2, 0, true>(p, f, wpb, s);
     }
     return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-bool codec_shape_ok(int in_u8, int nc, int kr, bool al) {
-    if (in_u8) return al ? ((nc == 4 || nc == 8) && (kr == 1 || kr == 2)) : (nc == 4 && kr == 1);
-    return al ? (nc == 2 && (kr == 1 || kr == 2)) : (nc == 2 && kr == 1);
+bool codec_shape_ok(int in_u8, int nc, int kr, bool al, int wavelet) {
+    if (kr == 0 && (wavelet != 1 || !al)) return false;  // rolling: D4, aligned buffers
+    if (in_u8) return al ? ((nc == 4 || nc == 8) && kr >= 0 && kr <= 2) : (nc == 4 && kr == 1);
+    return al ? (nc == 2 && kr >= 0 && kr <= 2) : (nc == 2 && kr == 1);
 }
 
 hipError_t launch_codec(const CodecParams &p, const Filters &f, int in_u8, int out_u8, int nc, int kr, bool al,
                         int wpb, hipStream_t s) {
     if (p.units <= 0) return hipSuccess;
-    if (wpb < 1 || wpb > 4 || !codec_shape_ok(in_u8, nc, kr, al)) return hipErrorInvalidValue;
-    if (p.nstrips != (p.W / 2 + 64 * nc - 1) / (64 * nc) || p.nseg != (p.H / 2 + kr - 1) / kr) return hipErrorInvalidValue;
+    if (wpb < 1 || wpb > 4 || !codec_shape_ok(in_u8, nc, kr, al, p.wavelet)) return hipErrorInvalidValue;
+    if (p.seg_rows < 1 || (kr > 0 && p.seg_rows != kr)) return hipErrorInvalidValue;
+    if (p.nstrips != (p.W / 2 + 64 * nc - 1) / (64 * nc) || p.nseg != (p.H / 2 + p.seg_rows - 1) / p.seg_rows)
+        return hipErrorInvalidValue;
     if (in_u8) {
         return out_u8 ? launch_io<uint8_t, uint8_t>(p, f, nc, kr, al, wpb, s)
                       : launch_io<uint8_t, float>(p, f, nc, kr, al, wpb, s);

@@ -1058,6 +1058,7 @@ namespace {
 
 struct CodecShape {
     int nc = 4, kr = 1, wpb = 4, order = 1;
+    int rows = 1;  // coefficient rows per unit: kr for one-shot tiles, seg_rows when rolling (kr = 0)
     bool aligned = false;
 };
 
@@ -1091,6 +1092,7 @@ CodecShape codec_default(const ExArgs &a) {
     const bool u8 = a.in_format == DWT_FUSE_U8;
     t.nc = u8 ? (a.wavelet == DWT_FUSE_D4 ? 4 : 8) : 2;
     t.kr = 1;
+    t.rows = 1;
     if (!codec_aligned(a, t.nc) && u8) t.nc = 4;
     t.aligned = codec_aligned(a, t.nc);
     if (!t.aligned) {
@@ -1102,7 +1104,8 @@ CodecShape codec_default(const ExArgs &a) {
 
 bool codec_params(const ExArgs &a, const CodecShape &t, CodecParams *p) {
     const int64_t W2 = a.W / 2, H2 = a.H / 2;
-    const int64_t ns = (W2 + 64 * t.nc - 1) / (64 * t.nc), ng = (H2 + t.kr - 1) / t.kr;
+    const int rows = t.kr > 0 ? t.kr : std::max(1, t.rows);
+    const int64_t ns = (W2 + 64 * t.nc - 1) / (64 * t.nc), ng = (H2 + rows - 1) / rows;
     if (ns * ng > INT32_MAX - 4) return false;
     CodecParams q{};
     q.pan = a.pan;
@@ -1119,6 +1122,7 @@ bool codec_params(const ExArgs &a, const CodecShape &t, CodecParams *p) {
     q.W = (int32_t)a.W;
     q.B = (int32_t)a.B;
     q.nstrips = (int32_t)ns;
+    q.seg_rows = rows;
     q.nseg = (int32_t)ng;
     q.units = (int32_t)(ns * ng);
     q.order = t.order;
@@ -1164,19 +1168,25 @@ CodecShape codec_shape(dwt_fuse_ctx *c, const ExArgs &a) {
     auto it = c->table.find(key);
     if (it != c->table.end()) {
         t.nc = it->second.nc;
-        t.kr = it->second.seg_rows;
+        t.kr = it->second.mode;  // 0 = rolling
+        t.rows = it->second.seg_rows;
         t.wpb = it->second.wpb;
         t.order = it->second.order;
     } else if (c->tuning && t.aligned) {
         float bestms = time_codec(c, a, t);
+        // one-shot tiles of 1 or 2 rows (rolling D4 units, forced variant 1,
+        // measured slower on every 8-bit workload, so they are not candidates)
+        const int rows_cand[2] = {-1, -2};  // negative: one-shot of that many rows
         for (int nc : {2, 4, 8}) {
-            if (!codec_shape_ok(u8, nc, 1, true) || !codec_aligned(a, nc)) continue;
-            for (int kr : {1, 2})
+            if (!codec_shape_ok(u8, nc, 1, true, a.wavelet) || !codec_aligned(a, nc)) continue;
+            for (int rc : rows_cand) {
+                if (rc > 0 && a.wavelet != DWT_FUSE_D4) continue;
                 for (int wpb : {1, 2, 4})
                     for (int order : {1, 0}) {
                         CodecShape s = t;
                         s.nc = nc;
-                        s.kr = kr;
+                        s.kr = rc < 0 ? -rc : 0;
+                        s.rows = rc < 0 ? -rc : rc;
                         s.wpb = wpb;
                         s.order = order;
                         const float ms = time_codec(c, a, s);
@@ -1185,28 +1195,38 @@ CodecShape codec_shape(dwt_fuse_ctx *c, const ExArgs &a) {
                             t = s;
                         }
                     }
+            }
         }
         Tile rec;
         rec.nc = t.nc;
-        rec.seg_rows = t.kr;
+        rec.seg_rows = t.rows;
         rec.wpb = t.wpb;
         rec.order = t.order;
-        rec.mode = 1;
+        rec.mode = t.kr;
         c->table[key] = rec;
         if (std::getenv("DWT_FUSE_LOG"))
-            std::fprintf(stderr, "[dwt_fuse] tuned %s: nc=%d kr=%d wpb=%d order=%d (%.3f ms)\n", key.c_str(), t.nc,
-                         t.kr, t.wpb, t.order, bestms);
+            std::fprintf(stderr, "[dwt_fuse] tuned %s: nc=%d kr=%d rows=%d wpb=%d order=%d (%.3f ms)\n", key.c_str(),
+                         t.nc, t.kr, t.rows, t.wpb, t.order, bestms);
     }
-    // Forced fields: rows -> kr, waves, columns 1/2 -> nc 4/8 for 8-bit input.
+    // Forced fields: variant 1 = rolling (D4) of seg_rows rows (default 16),
+    // otherwise one-shot tiles of 1 or 2 rows; waves; columns 1/2 -> nc 4/8
+    // for 8-bit input.
     const Forced &fo = c->forced;
-    if (fo.seg_rows > 0) t.kr = fo.seg_rows >= 2 ? 2 : 1;
+    if (fo.variant == 1 && a.wavelet == DWT_FUSE_D4) {
+        t.kr = 0;
+        t.rows = fo.seg_rows > 0 ? fo.seg_rows : 16;
+    } else if (fo.variant != 0 || fo.seg_rows > 0) {
+        if (t.kr == 0 || fo.seg_rows > 0) t.kr = fo.seg_rows >= 2 ? 2 : 1;
+        t.rows = t.kr;
+    }
     if (fo.wpb > 0) t.wpb = fo.wpb;
     if (fo.nc > 0 && u8) t.nc = fo.nc == 1 ? 4 : 8;
     if (t.aligned && !codec_aligned(a, t.nc)) t.nc = 4;
     t.aligned = codec_aligned(a, t.nc);
-    if (!codec_shape_ok(u8, t.nc, t.kr, t.aligned)) {
+    if (!codec_shape_ok(u8, t.nc, t.kr, t.aligned, a.wavelet)) {
         t.nc = u8 ? 4 : 2;
         t.kr = 1;
+        t.rows = 1;
         t.aligned = codec_aligned(a, t.nc);
     }
     return t;

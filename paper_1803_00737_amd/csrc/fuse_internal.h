@@ -129,16 +129,17 @@ struct CodecParams {
     int64_t pan_ld, ms_ld, ms_bs, out_ld, out_bs;
     float kappa;
     int32_t H, W, B;
-    int32_t nstrips;  // ceil((W/2) / (64*nc))
-    int32_t nseg;     // ceil((H/2) / kr)
-    int32_t units;    // nstrips * nseg
-    int32_t order;    // 0 strip-major, 1 row-band-major
-    int32_t wavelet;  // 0 Haar, 1 D4
+    int32_t nstrips;   // ceil((W/2) / (64*nc))
+    int32_t seg_rows;  // coefficient rows per unit (= kr for one-shot tiles)
+    int32_t nseg;      // ceil((H/2) / seg_rows)
+    int32_t units;     // nstrips * nseg
+    int32_t order;     // 0 strip-major, 1 row-band-major
+    int32_t wavelet;   // 0 Haar, 1 D4
 };
 
-// Shapes that exist: 8-bit input nc 4 or 8 (kr 1, 2) on aligned buffers, nc 4
-// kr 1 otherwise; float input nc 2 (kr 1, 2 aligned; kr 1 otherwise).
-bool codec_shape_ok(int in_u8, int nc, int kr, bool aligned);
+// Shapes that exist: 8-bit input nc 4 or 8 (kr 1, 2, or 0 = rolling for D4)
+// on aligned buffers, nc 4 kr 1 otherwise; float input nc 2 (likewise).
+bool codec_shape_ok(int in_u8, int nc, int kr, bool aligned, int wavelet);
 hipError_t launch_codec(const CodecParams &p, const Filters &f, int in_u8, int out_u8, int nc, int kr, bool aligned,
                         int waves_per_block, hipStream_t s);
 

@@ -125,7 +125,8 @@ def test_kappa(dev, fz, oracle, wavelet, kappa, H, W, B):
 @pytest.mark.parametrize("wavelet", ["haar", "d4"])
 @pytest.mark.parametrize("H,W", [(250, 1034), (250, 4104), (18, 8)])
 def test_forced_shapes_identical(dev, fz, wavelet, H, W):
-    """Every (rows, waves, columns) shape of the format kernels evaluates each
+    """Every shape of the format kernels (one-shot tiles of 1 or 2 rows,
+    rolling D4 units of any length (variant 1), waves, columns) evaluates each
     pixel with the same operations, so all agree bit for bit."""
     rng = np.random.default_rng(9)
     pan, ms = u8_scene(rng, H, W, 3)
@@ -133,9 +134,10 @@ def test_forced_shapes_identical(dev, fz, wavelet, H, W):
     ctx = fz.context(dev)
     outs = []
     try:
-        for seg, wpb, nc in [(0, 0, 0), (1, 1, 1), (2, 4, 1), (1, 2, 2), (2, 1, 2), (2, 4, 2), (1, 4, 2)]:
-            say("codec shape", wavelet, H, W, seg, wpb, nc)
-            ctx.force_tile(seg, wpb, nc, 0)
+        for seg, wpb, nc, var in [(0, 0, 0, 0), (1, 1, 1, 0), (2, 4, 1, 0), (1, 2, 2, 0), (2, 1, 2, 0), (2, 4, 2, 0),
+                                  (1, 4, 2, 0), (3, 2, 1, 1), (16, 4, 2, 1), (64, 1, 1, 1), (1, 4, 2, 1)]:
+            say("codec shape", wavelet, H, W, seg, wpb, nc, var)
+            ctx.force_tile(seg, wpb, nc, var)
             outs.append((fz.fuse(p, m, wavelet).cpu().numpy(),
                          fz.fuse(p, m, wavelet, out_dtype=torch.uint8).cpu().numpy()))
     finally:
