@@ -7,9 +7,10 @@
 // an ERGAS-style score need, and the host turns them into those numbers.
 //
 // Every pixel goes to a fixed thread of a fixed block (rows round-robin over
-// the blocks of a band, columns strided over the threads), and blocks and
-// bands are combined by fixed reduction trees, so the sums are reproducible
-// bit for bit.  Memory-bound: 8 bytes read per pixel per band.
+// the blocks of a band, columns strided over the threads, 4 adjacent pixels
+// per thread on 16-byte aligned rows), and blocks and bands are combined by
+// fixed reduction trees, so the sums are reproducible bit for bit.
+// Memory-bound: 8 bytes read per pixel per band.
 #include "fuse_internal.h"
 
 namespace dwtf {
@@ -31,6 +32,17 @@ __device__ __forceinline__ void block_sum2(double &a, double &b, double *sh) {
     b = sh[256];
 }
 
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void acc1(float fv, float rv, double &sse, double &sr) {
+    const double r = (double)rv;
+    const double d = (double)fv - r;
+    sse = fma(d, d, sse);
+    sr += r;
+}
+
+// VEC: rows 16-byte aligned with W a multiple of 4 -> 16-byte loads.
+template <bool VEC>
 __global__ __launch_bounds__(256) void quality_partial_kernel(QualityParams p, double *__restrict__ partial) {
     __shared__ double sh[512];
     const int b = blockIdx.y;
@@ -40,11 +52,17 @@ __global__ __launch_bounds__(256) void quality_partial_kernel(QualityParams p, d
     for (int y = blockIdx.x; y < p.H; y += gridDim.x) {
         const float *fr = f + (int64_t)y * p.f_ld;
         const float *rr = r + (int64_t)y * p.r_ld;
-        for (int x = threadIdx.x; x < p.W; x += 256) {
-            const double rv = (double)rr[x];
-            const double d = (double)fr[x] - rv;
-            sse = fma(d, d, sse);
-            sr += rv;
+        if constexpr (VEC) {
+            for (int x = 4 * threadIdx.x; x < p.W; x += 1024) {
+                const f4 a = *reinterpret_cast<const f4 *>(fr + x);
+                const f4 c = *reinterpret_cast<const f4 *>(rr + x);
+                acc1(a.x, c.x, sse, sr);
+                acc1(a.y, c.y, sse, sr);
+                acc1(a.z, c.z, sse, sr);
+                acc1(a.w, c.w, sse, sr);
+            }
+        } else {
+            for (int x = threadIdx.x; x < p.W; x += 256) acc1(fr[x], rr[x], sse, sr);
         }
     }
     block_sum2(sse, sr, sh);
@@ -75,7 +93,13 @@ __global__ __launch_bounds__(256) void quality_final_kernel(const double *__rest
 
 hipError_t launch_quality(const QualityParams &p, double *partial, double *out, hipStream_t s) {
     if (p.B < 1 || p.B > kQualityMaxBands || p.H < 1 || p.W < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(quality_partial_kernel, dim3(kQualityBlocks, p.B), dim3(256), 0, s, p, partial);
+    const auto al16 = [](const float *q, int64_t ld, int64_t bs, int B) {
+        return reinterpret_cast<uintptr_t>(q) % 16 == 0 && ld % 4 == 0 && (B == 1 || bs % 4 == 0);
+    };
+    if (p.W % 4 == 0 && al16(p.fused, p.f_ld, p.f_bs, p.B) && al16(p.ref, p.r_ld, p.r_bs, p.B))
+        hipLaunchKernelGGL(quality_partial_kernel<true>, dim3(kQualityBlocks, p.B), dim3(256), 0, s, p, partial);
+    else
+        hipLaunchKernelGGL(quality_partial_kernel<false>, dim3(kQualityBlocks, p.B), dim3(256), 0, s, p, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(quality_final_kernel, dim3(p.B), dim3(256), 0, s, partial, kQualityBlocks, p.B, out);

@@ -45,15 +45,20 @@ def test_sums_match_oracle(dev, fz, oracle, B, H, W):
     assert torch.equal(q["sse"], q2["sse"]) and torch.equal(q["sum_ref"], q2["sum_ref"])
 
 
-def test_pitched_inputs(dev, fz, oracle):
+@pytest.mark.parametrize("cols", [(5, 55, 1, 51), (4, 68, 8, 72)])
+def test_pitched_inputs(dev, fz, oracle, cols):
+    """Pitched views: odd offsets take the scalar loop, 16-byte aligned rows
+    of a width divisible by 4 the vector loop."""
     rng = np.random.default_rng(3)
-    big_f = to_dev(rng.normal(0, 1, (3, 40, 70)).astype(np.float32), dev)
-    big_r = to_dev(rng.normal(0, 1, (3, 40, 70)).astype(np.float32), dev)
-    f, r = big_f[:, 3:33, 5:55], big_r[:, 2:32, 1:51]
-    say("quality pitched")
+    big_f = to_dev(rng.normal(0, 1, (3, 40, 80)).astype(np.float32), dev)
+    big_r = to_dev(rng.normal(0, 1, (3, 40, 80)).astype(np.float32), dev)
+    f0, f1, r0, r1 = cols
+    f, r = big_f[:, 4:34, f0:f1], big_r[:, 8:38, r0:r1]
+    say("quality pitched", cols)
     q = fz.quality(f, r)
     ref = oracle.quality(f.cpu().numpy().astype(np.float64), r.cpu().numpy().astype(np.float64))
     assert np.allclose(q["sse"].cpu().numpy(), ref["sse"], rtol=1e-12)
+    assert np.allclose(q["sum_ref"].cpu().numpy(), ref["sum_ref"], rtol=1e-12, atol=1e-9)
 
 
 def test_dc_matched_d4(dev, fz, oracle):
