@@ -243,3 +243,42 @@ def test_full_size_landsat(dev, fz, oracle, wavelet):
         assert np.array_equal(got, ref.astype(np.float32))
     else:
         assert np.abs(got - ref).max() <= D4_TOL
+
+
+@pytest.mark.parametrize("wavelet", ["haar", "d4"])
+def test_output_beyond_2_pow_31_elements(dev, fz, oracle, wavelet):
+    """PAN 8192 x 8192 with 33 bands: the output holds 2.2e9 float32 elements
+    (8.9 GB), more than a 32-bit index can address, so every band offset must
+    be formed in 64-bit arithmetic.  Sampled pixels of the first and last
+    bands against the single-pixel oracle, in the tuned launch shape."""
+    H = W = 8192
+    B = 33
+    rng = np.random.default_rng(33)
+    say("beyond 2^31", wavelet, "generate")
+    pan_d = torch.randint(0, 256, (H, W), device=dev).float()
+    ms1 = torch.randint(0, 256, (1, H // 2, W // 2), device=dev).float()
+    ms_d = ms1.expand(B, H // 2, W // 2).contiguous()
+    ms_d[B - 1] = torch.flip(ms1[0], dims=[0])  # a last band that differs from the others
+    ctx = fz.context(dev)
+    ctx.set_tuning(True)
+    try:
+        say("beyond 2^31", wavelet, "fuse")
+        out = fz.fuse(pan_d, ms_d, wavelet)
+    finally:
+        ctx.set_tuning(False)
+    torch.cuda.synchronize()
+    assert out.numel() > 2 ** 31
+    pts = [(b, int(y), int(x)) for b in (0, 1, B - 2, B - 1) for y, x in
+           zip(rng.integers(0, H, 24), rng.integers(0, W, 24))] + [(B - 1, H - 1, W - 1), (B - 1, 0, 0)]
+    b, y, x = map(np.array, zip(*pts))
+    got = out[torch.from_numpy(b).to(dev), torch.from_numpy(y).to(dev), torch.from_numpy(x).to(dev)].cpu().numpy()
+    pan = pan_d.cpu().numpy().astype(np.float64)
+    ms_small = np.stack([ms_d[k].cpu().numpy() for k in (0, B - 1)]).astype(np.float64)
+    del out, ms_d, pan_d
+    torch.cuda.empty_cache()
+    bi = np.where(b == B - 1, 1, 0)
+    ref = oracle.fuse_points(wavelet, pan, ms_small, None, bi, y, x)
+    if wavelet == "haar":
+        assert np.array_equal(got, ref.astype(np.float32))
+    else:
+        assert np.abs(got - ref).max() <= D4_TOL
