@@ -419,10 +419,13 @@ __host__ __device__ constexpr int staged_lds_floats(int T, int bg) {
 // One staged tile (`unit` of p) by the whole workgroup; every wavefront must
 // call it (it contains barriers).  LAY follows the row alignment: 0 = 16-byte
 // rows (PAN staged with 16-byte loads; a lane owns 2 adjacent coefficient
-// columns and stores 16 bytes), 1 = 8-byte rows and 2 = 4-byte rows (PAN
-// staged with 4-byte loads; a lane owns coefficient columns sb+l and sb+64+l
-// and stores 8 bytes (1) or 4 bytes (2) per column, so each store
-// instruction of the wavefront covers one contiguous 512-byte run).
+// columns and stores 16 bytes); 3 = 8-byte rows (PAN staged in 16-byte groups
+// aligned per row in strips clear of the wrap, 4-byte loads elsewhere; a lane
+// owns 2 adjacent columns and stores 16 bytes on rows 16-byte aligned there,
+// 2 x 8 bytes on the others); 1 = 8-byte rows and 2 = 4-byte rows with 4-byte
+// staging (a lane owns coefficient columns sb+l and sb+64+l and stores 8 or
+// 4 bytes per column, so each store instruction of the wavefront covers one
+// contiguous 512-byte run).
 template <int KR, int LAY>
 __device__ __forceinline__ void d4_staged_tile(const FuseParams &p, const Filters &f, int bg_max, int unit,
                                                float *lds, int wpb) {
@@ -438,12 +441,25 @@ __device__ __forceinline__ void d4_staged_tile(const FuseParams &p, const Filter
 
     // PAN rows 2r0-2 .. 2r0+2T+1.  On the 16-byte path column groups of 4
     // start at multiples of 4 and W % 4 == 0, so a group never straddles the
-    // wrap; the other paths stage single floats.
+    // wrap; the other paths stage single floats, except that on 8-byte rows
+    // (LAY 3) strips clear of the wrap stage 16-byte groups starting at pixel
+    // 2sb (rows 16-byte aligned there) or 2sb-2 (rows 8 bytes off), the
+    // latter placed 2 floats further right in LDS (row shift, see pan_shift).
+    // 8-byte rows: a strip whose groups of 4 pixels from 2sb-2 to 2sb+257 all
+    // lie inside the row.
+    const bool fast = LAY == 3 && sb >= 128 && 2 * sb + 258 <= p.W;
     for (int k = w; k < 2 * T + 4; k += wpb) {
         const float *row = p.pan + (int64_t)wrap_idx(2 * r0 - 2 + k, p.H) * p.pan_ld;
         float *dst = Pl + k * kStagedPanRow;
         if constexpr (LAY == 0) {
             lds_load16(row + wrap_idx(2 * sb + 4 * lane, p.W), dst + 4);
+        } else if (LAY == 3 && fast && (reinterpret_cast<uintptr_t>(row) & 15) != 0) {
+            // groups from pixel 2sb-2: LDS 4 + 4l holds pixels 2sb-2+4l .. +3
+            lds_load16(row + 2 * sb - 2 + 4 * lane, dst + 4);
+            if (lane == 0) lds_load16(row + 2 * sb + 254, dst + 260);
+            continue;  // both halos are inside the groups
+        } else if (LAY == 3 && fast) {
+            lds_load16(row + 2 * sb + 4 * lane, dst + 4);
         } else {
 #pragma unroll
             for (int q = 0; q < 4; ++q) lds_load4(row + wrap_idx(2 * sb + 64 * q + lane, p.W), dst + 4 + 64 * q);
@@ -473,15 +489,26 @@ __device__ __forceinline__ void d4_staged_tile(const FuseParams &p, const Filter
     const int rb = r0 + KR * w;
     const int nr = max(0, min(KR, H2 - rb));
     constexpr int NR = 2 * KR + 4;  // PAN rows 2rb-2 .. 2rb+2KR+1 = LDS rows 2KR*w + t
-    constexpr int NC = LAY == 0 ? 2 : 1;   // coefficient columns per lane and half
-    constexpr int NH = LAY == 0 ? 1 : 2;   // column halves per lane
+    constexpr int NC = (LAY == 0 || LAY == 3) ? 2 : 1;  // coefficient columns per lane and half
+    constexpr int NH = (LAY == 0 || LAY == 3) ? 1 : 2;  // column halves per lane
+    // LAY 3: staged row t sits 2 floats right when its row is 8 bytes off a
+    // 16-byte boundary in a clear-of-the-wrap strip (the same test as staging).
+    auto pan_shift = [&](int t) {
+        if constexpr (LAY != 3) {
+            return 0;
+        } else {
+            if (!fast) return 0;
+            const float *row = p.pan + (int64_t)wrap_idx(2 * r0 - 2 + 2 * KR * w + t, p.H) * p.pan_ld;
+            return (reinterpret_cast<uintptr_t>(row) & 15) != 0 ? 2 : 0;
+        }
+    };
     // Column layout of half h: first own coefficient column s0[h]; its PAN
     // pairs s0-1 .. s0+NC sit at LDS row positions pos[h] + 2k, MS columns
     // s0-1 .. s0+NC-1 at mpos[h] + k.
     int s0[NH], pos[NH], mpos[NH];
 #pragma unroll
     for (int h = 0; h < NH; ++h) {
-        const int c = LAY == 0 ? 2 * lane : 64 * h + lane;  // offset of s0 within the strip
+        const int c = (LAY == 0 || LAY == 3) ? 2 * lane : 64 * h + lane;  // offset of s0 within the strip
         s0[h] = sb + c;
         pos[h] = 2 + 2 * c;
         mpos[h] = 3 + c;
@@ -493,7 +520,7 @@ __device__ __forceinline__ void d4_staged_tile(const FuseParams &p, const Filter
         float R[NR][NC + 1];
 #pragma unroll
         for (int t = 0; t < NR; ++t) {
-            const float *src = Pl + (2 * KR * w + t) * kStagedPanRow + pos[h];
+            const float *src = Pl + (2 * KR * w + t) * kStagedPanRow + pos[h] + pan_shift(t);
             f2 x[NC + 2];
 #pragma unroll
             for (int k = 0; k < NC + 2; ++k) x[k] = *reinterpret_cast<const f2 *>(src + 2 * k);
@@ -551,6 +578,26 @@ __device__ __forceinline__ void d4_staged_tile(const FuseParams &p, const Filter
                             st2<true>(o0, q0[0]);
                             st2<true>(o0 + p.out_ld, q1[0]);
                         }
+                    } else if constexpr (LAY == 3) {
+                        // 8-byte rows: 16-byte stores on rows that are 16-byte aligned here
+                        float *o1 = o0 + p.out_ld;
+                        if (s0[h] + 2 <= W2) {
+                            if ((reinterpret_cast<uintptr_t>(o0) & 15) == 0) {
+                                st4(o0, f4{q0[0].x, q0[0].y, q0[1].x, q0[1].y});
+                            } else {
+                                st2<true>(o0, q0[0]);
+                                st2<true>(o0 + 2, q0[1]);
+                            }
+                            if ((reinterpret_cast<uintptr_t>(o1) & 15) == 0) {
+                                st4(o1, f4{q1[0].x, q1[0].y, q1[1].x, q1[1].y});
+                            } else {
+                                st2<true>(o1, q1[0]);
+                                st2<true>(o1 + 2, q1[1]);
+                            }
+                        } else {
+                            st2<true>(o0, q0[0]);
+                            st2<true>(o1, q1[0]);
+                        }
                     } else {
                         st2<LAY == 1>(o0, q0[0]);
                         st2<LAY == 1>(o0 + p.out_ld, q1[0]);
@@ -576,7 +623,7 @@ static void launch_staged(const FuseParams &p, const Filters &f, int wpb, size_t
             hipLaunchKernelGGL((d4_staged_kernel<KR, 0>), dim3(p.units), dim3(64 * wpb), lds, s, p, f, bgm);
             break;
         case PATH_V2:
-            hipLaunchKernelGGL((d4_staged_kernel<KR, 1>), dim3(p.units), dim3(64 * wpb), lds, s, p, f, bgm);
+            hipLaunchKernelGGL((d4_staged_kernel<KR, 3>), dim3(p.units), dim3(64 * wpb), lds, s, p, f, bgm);
             break;
         default:
             hipLaunchKernelGGL((d4_staged_kernel<KR, 2>), dim3(p.units), dim3(64 * wpb), lds, s, p, f, bgm);
@@ -791,7 +838,7 @@ __global__ __launch_bounds__(256) void fuse_batched_flat_kernel(const BatchScene
         if (p.path == PATH_V4)
             d4_staged_tile<2, 0>(p, f, bg_max, item, lds, 4);
         else if (p.path == PATH_V2)
-            d4_staged_tile<2, 1>(p, f, bg_max, item, lds, 4);
+            d4_staged_tile<2, 3>(p, f, bg_max, item, lds, 4);
         else
             d4_staged_tile<2, 2>(p, f, bg_max, item, lds, 4);
         return;
