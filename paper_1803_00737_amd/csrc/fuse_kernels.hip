@@ -422,13 +422,14 @@ __host__ __device__ constexpr int staged_lds_floats(int T, int bg) {
 // columns and stores 16 bytes); 3 = 8-byte rows (PAN staged in 16-byte groups
 // aligned per row in strips clear of the wrap, 4-byte loads elsewhere; a lane
 // owns 2 adjacent columns and stores 16 bytes on rows 16-byte aligned there,
-// 2 x 8 bytes on the others); 1 = 8-byte rows and 2 = 4-byte rows with 4-byte
-// staging (a lane owns coefficient columns sb+l and sb+64+l and stores 8 or
-// 4 bytes per column, so each store instruction of the wavefront covers one
-// contiguous 512-byte run).
+// 2 x 8 bytes on the others); 2 = 4-byte rows (4-byte staging; a lane owns
+// coefficient columns sb+l and sb+64+l and stores their two pixels with two
+// 4-byte stores, so each pair of store instructions of the wavefront covers
+// one contiguous 512-byte run).
 template <int KR, int LAY>
 __device__ __forceinline__ void d4_staged_tile(const FuseParams &p, const Filters &f, int bg_max, int unit,
                                                float *lds, int wpb) {
+    static_assert(LAY == 0 || LAY == 2 || LAY == 3, "row layouts: 16-, 4- or 8-byte rows");
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int T = wpb * KR;
     int strip, trow;
@@ -599,8 +600,8 @@ __device__ __forceinline__ void d4_staged_tile(const FuseParams &p, const Filter
                             st2<true>(o1, q1[0]);
                         }
                     } else {
-                        st2<LAY == 1>(o0, q0[0]);
-                        st2<LAY == 1>(o0 + p.out_ld, q1[0]);
+                        st2<false>(o0, q0[0]);  // 4-byte rows
+                        st2<false>(o0 + p.out_ld, q1[0]);
                     }
                 }
             }
