@@ -48,6 +48,13 @@ bool extent(int64_t nb, int64_t rows, int64_t cols, int64_t ld, int64_t bs, int6
     return true;
 }
 
+// The byte range [p, p + elems * esize) does not wrap past the end of the
+// address space.
+bool fits_address_space(const void *p, int64_t elems, int64_t esize = sizeof(float)) {
+    const uintptr_t lo = reinterpret_cast<uintptr_t>(p);
+    return elems >= 0 && (uintptr_t)elems <= (UINTPTR_MAX - lo) / (uintptr_t)esize;
+}
+
 Span span_of(const void *p, int64_t elems, int64_t esize = sizeof(float)) {
     Span s;
     s.lo = reinterpret_cast<uintptr_t>(p);
@@ -89,7 +96,7 @@ dwt_fuse_status check_strided(const char *name, int64_t nb, int64_t rows, int64_
         }
     }
     int64_t e = 0;
-    if (!extent(nb, rows, cols, ld, bs, &e)) {
+    if (!extent(nb, rows, cols, ld, bs, &e) || !fits_address_space(ptr, e, esize)) {
         if (err) *err = std::string(name) + ": extent overflows";
         return DWT_FUSE_E_SHAPE;
     }
@@ -128,6 +135,10 @@ dwt_fuse_status check_run_args(const RunArgs &a, RunSpans *sp, std::string *err)
     if ((st = check_strided("pan", 1, a.H, a.W, a.pan_ld, 0, a.pan, &s.pan, err))) return st;
     if ((st = check_strided("ms", a.B, a.H / 2, a.W / 2, a.ms_ld, a.ms_bs, a.ms, &s.ms, err))) return st;
     if ((st = check_strided("out", a.B, a.H, a.W, a.out_ld, a.out_bs, a.out, &s.out, err))) return st;
+    if (a.gain && !fits_address_space(a.gain, a.B)) {
+        if (err) *err = "gain: extent overflows";
+        return DWT_FUSE_E_SHAPE;
+    }
     s.gain = a.gain ? span_of(a.gain, a.B) : Span{};
     if (s.out.overlaps(s.pan) || s.out.overlaps(s.ms) || s.out.overlaps(s.gain)) {
         if (err) *err = "out overlaps an input";
@@ -175,6 +186,10 @@ dwt_fuse_status check_ex_args(const ExArgs &a, std::string *err) {
     if ((st = check_strided("pan", 1, a.H, a.W, a.pan_ld, 0, a.pan, &pan, err, ei))) return st;
     if ((st = check_strided("ms", a.B, a.H / 2, a.W / 2, a.ms_ld, a.ms_bs, a.ms, &ms, err, ei))) return st;
     if ((st = check_strided("out", a.B, a.H, a.W, a.out_ld, a.out_bs, a.out, &out, err, eo))) return st;
+    if (a.gain && !fits_address_space(a.gain, a.B)) {
+        if (err) *err = "gain: extent overflows";
+        return DWT_FUSE_E_SHAPE;
+    }
     const Span gain = a.gain ? span_of(a.gain, a.B) : Span{};
     if (out.overlaps(pan) || out.overlaps(ms) || out.overlaps(gain)) {
         if (err) *err = "out overlaps an input";
@@ -208,6 +223,12 @@ dwt_fuse_status check_bwd_args(const BwdArgs &a, std::string *err) {
     Span pan, gy;
     if ((st = check_strided("pan", 1, a.H, a.W, a.pan_ld, 0, a.pan, &pan, err))) return st;
     if ((st = check_strided("grad_out", a.B, a.H, a.W, a.gy_ld, a.gy_bs, a.gy, &gy, err))) return st;
+    if ((a.gain && !fits_address_space(a.gain, a.B)) || (a.grad_pan && !fits_address_space(a.grad_pan, a.H * a.W)) ||
+        (a.grad_ms && !fits_address_space(a.grad_ms, a.B * (a.H / 2) * (a.W / 2))) ||
+        (a.grad_gain && !fits_address_space(a.grad_gain, a.B))) {
+        if (err) *err = "a gain or gradient extent overflows";
+        return DWT_FUSE_E_SHAPE;
+    }
     const Span gain = a.gain ? span_of(a.gain, a.B) : Span{};
     const Span outs[3] = {a.grad_pan ? span_of(a.grad_pan, a.H * a.W) : Span{},
                           a.grad_ms ? span_of(a.grad_ms, a.B * (a.H / 2) * (a.W / 2)) : Span{},
@@ -1294,6 +1315,10 @@ dwt_fuse_status check_quality_args(int64_t H, int64_t W, int64_t B, const float 
     dwt_fuse_status st;
     if ((st = check_strided("fused", B, H, W, f_ld, f_bs, fused, &fs, err))) return st;
     if ((st = check_strided("ref", B, H, W, r_ld, r_bs, ref, &rs, err))) return st;
+    if (!fits_address_space(out, 2 * B, sizeof(double))) {
+        if (err) *err = "out: extent overflows";
+        return DWT_FUSE_E_SHAPE;
+    }
     const Span os = span_of(out, 2 * B, sizeof(double));
     if (os.overlaps(fs) || os.overlaps(rs)) {
         if (err) *err = "out overlaps an input";
