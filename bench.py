@@ -129,18 +129,25 @@ def run_copy(torch, steps):
     print(json.dumps({"mode": "copy", "bytes_read": 4 * n, "bytes_written": 4 * n, "ms": ms, "GB/s": gbs}))
 
 
-def cpu_baseline(pan_d, ms_d, wavelet):
+def cpu_baseline(pan_d, ms_d, wavelet, budget_s=8.0, max_passes=6):
+    """The FP64 oracle as it stands (plain C, one thread) on the benchmark's own
+    inputs: whole passes over the workload until about budget_s seconds have
+    run; the rate is total output pixels over total time."""
     import oracle
     import numpy as np
 
     pan = pan_d.cpu().numpy().astype(np.float64)
     ms = ms_d.cpu().numpy().astype(np.float64)
-    t0 = time.perf_counter()
-    oracle.fuse(wavelet, pan, ms)
-    dt = time.perf_counter() - t0
     px = ms.shape[0] * pan.shape[0] * pan.shape[1]
-    return {"value": px / dt / 1e6, "unit": "Mpix/s", "cores": 1, "kind": "oracle",
-            "sample": "the whole workload (same inputs), one pass of the FP64 oracle, 1 thread, %.1f s" % dt}
+    total, passes = 0.0, 0
+    while passes < max_passes and (passes == 0 or total < budget_s):
+        t0 = time.perf_counter()
+        oracle.fuse(wavelet, pan, ms)
+        total += time.perf_counter() - t0
+        passes += 1
+    return {"value": passes * px / total / 1e6, "unit": "Mpix/s", "cores": 1, "kind": "oracle",
+            "sample": "%d whole passes over the workload (same inputs) of the FP64 oracle, 1 thread, %.1f s"
+                      % (passes, total)}
 
 
 def extras(torch, api, synth, steps, warmup):
