@@ -241,8 +241,9 @@ const char *dwt_fuse_last_error(const dwt_fuse_ctx *ctx);
  * call's own buffers (each candidate writes the same output) and keeps the
  * fastest; the first batched call of each batch signature likewise times the
  * kernel variants on the batch.  The table can be saved to / loaded from a
- * small text file; a file whose header does not match this library build and
- * device is ignored. */
+ * small text file (a header line, then one line per key); a file whose
+ * header does not match this library build and device, or with a malformed
+ * line, is refused as a whole (DWT_FUSE_E_STATE) and the table is unchanged. */
 dwt_fuse_status dwt_fuse_set_tuning(dwt_fuse_ctx *ctx, int enable);
 dwt_fuse_status dwt_fuse_tune_save(const dwt_fuse_ctx *ctx, const char *path);
 dwt_fuse_status dwt_fuse_tune_load(dwt_fuse_ctx *ctx, const char *path);
@@ -260,6 +261,15 @@ dwt_fuse_status dwt_fuse_tune_load(dwt_fuse_ctx *ctx, const char *path);
  * never used.  DWT_FUSE_E_SHAPE if a field is out of range. */
 dwt_fuse_status dwt_fuse_force_tile(dwt_fuse_ctx *ctx, int seg_rows, int waves_per_block, int cols_per_lane,
                                     int variant);
+
+/* Force LDS-staged D4 launches (dwt_fuse_run, dwt_fuse_run_ex with float
+ * formats) to split each tile's bands into work units of bands_per_unit
+ * bands (1 .. 8; 0 = automatic: the tuned or default choice, which keeps all
+ * bands of a tile in one unit unless tuning found a split faster).  The
+ * units of one tile are adjacent, so the PAN rows they share are re-read
+ * from L2.  Results are bit-identical for every split.  DWT_FUSE_E_SHAPE if
+ * out of range. */
+dwt_fuse_status dwt_fuse_force_band_split(dwt_fuse_ctx *ctx, int bands_per_unit);
 
 #ifdef __cplusplus
 }

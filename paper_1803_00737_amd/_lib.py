@@ -22,6 +22,7 @@ EXPORTS = (
     "dwt_fuse_check_backward", "dwt_fuse_status_str", "dwt_fuse_last_error", "dwt_fuse_set_tuning",
     "dwt_fuse_tune_save", "dwt_fuse_tune_load", "dwt_fuse_force_tile", "dwt_fuse_run_multipass",
     "dwt_fuse_run_ex", "dwt_fuse_check_run_ex", "dwt_fuse_quality", "dwt_fuse_check_quality",
+    "dwt_fuse_force_band_split",
 )
 
 HAAR = 0
@@ -110,6 +111,8 @@ def load(require_torch: bool = True):
         lib.dwt_fuse_tune_load.restype = st
         lib.dwt_fuse_force_tile.argtypes = [vp, i32, i32, i32, i32]
         lib.dwt_fuse_force_tile.restype = st
+        lib.dwt_fuse_force_band_split.argtypes = [vp, i32]
+        lib.dwt_fuse_force_band_split.restype = st
         lib.dwt_fuse_run_multipass.argtypes = [vp, i32, i64, i64, i64, vp, i64, vp, i64, i64, vp, i64, i64]
         lib.dwt_fuse_run_multipass.restype = st
         ex_args = run_args + [ctypes.POINTER(Opts)]

@@ -57,6 +57,10 @@ class Context:
         self.check(self.lib.dwt_fuse_force_tile(self.handle, seg_rows, waves_per_block, cols_per_lane, variant),
                    "dwt_fuse_force_tile")
 
+    def force_band_split(self, bands_per_unit: int = 0):
+        """LDS-staged D4: bands per work unit (0 = automatic)."""
+        self.check(self.lib.dwt_fuse_force_band_split(self.handle, bands_per_unit), "dwt_fuse_force_band_split")
+
     def tune_save(self, path: str):
         self.check(self.lib.dwt_fuse_tune_save(self.handle, path.encode()), "dwt_fuse_tune_save")
 

@@ -350,13 +350,15 @@ struct Tile {
     int seg_rows = 0, wpb = 0, nc = 0;
     int order = 1;  // 1 row-band-major, 0 strip-major
     int mode = 0;
+    int split = 0;  // LDS-staged: bands per unit (0 = all)
     int rows() const { return mode >= 3 ? wpb * (mode - 2) : (mode > 0 ? mode : seg_rows); }
 };
 
 // Forced launch shape (0 = automatic for each field); variant 1 = rolling,
-// 2 = one-shot, 3 = LDS-staged (where it applies).
+// 2 = one-shot, 3 = LDS-staged (where it applies); split = bands per
+// LDS-staged unit.
 struct Forced {
-    int seg_rows = 0, wpb = 0, nc = 0, variant = 0;
+    int seg_rows = 0, wpb = 0, nc = 0, variant = 0, split = 0;
 };
 
 struct Decomp {
@@ -523,7 +525,17 @@ FuseParams make_params(const RunArgs &a, Path path, const Tile &t, const Decomp 
     p.order = t.order;
     p.mode = t.mode;
     p.kappa = 1.0f;
+    if (t.mode >= 3 && t.split > 0 && t.split < a.B) {  // (tile, band group) units
+        p.bsplit = t.split;
+        p.units = d.units * (int32_t)((a.B + t.split - 1) / t.split);  // bounded by split_fits
+    }
     return p;
+}
+
+// The (tile, band group) unit count of a band-split staged launch fits int32.
+bool split_fits(const Tile &t, const Decomp &d, int64_t B) {
+    if (!(t.mode >= 3 && t.split > 0 && t.split < B)) return true;
+    return (int64_t)d.units * ((B + t.split - 1) / t.split) <= INT32_MAX;
 }
 
 // LDS-staged tiles exist for D4 on every path (their strips are always 128
@@ -552,6 +564,8 @@ Tile apply_forced(const dwt_fuse_ctx *c, Tile t, Path path, int wavelet) {
     }
     if (t.wpb < 1) t.wpb = 4;
     if (t.mode == 0 && t.seg_rows < 1) t.seg_rows = 1;
+    if (fo.split > 0) t.split = fo.split;
+    if (t.mode < 3) t.split = 0;
     return t;
 }
 
@@ -560,7 +574,7 @@ Path path_for_nc(Path path, int nc) { return (path == PATH_V4 && nc == 1) ? PATH
 // Time one forward launch configuration on the caller's buffers (ms, median of 3).
 float time_fuse(dwt_fuse_ctx *c, const RunArgs &a, Path path, const Tile &t) {
     Decomp d;
-    if (!decompose(a.H, a.W, t, &d)) return 1e30f;
+    if (!decompose(a.H, a.W, t, &d) || !split_fits(t, d, a.B)) return 1e30f;
     const Path pp = path_for_nc(path, t.nc);
     const FuseParams p = make_params(a, pp, t, d);
     hipEvent_t e0, e1;
@@ -614,30 +628,35 @@ Tile tune_fuse(dwt_fuse_ctx *c, const RunArgs &a, Path path) {
             }
         }
     }
-    // LDS-staged workgroups (D4): KR rows per wavefront.
+    // LDS-staged workgroups (D4): KR rows per wavefront, all bands of a tile
+    // per unit (units split into band groups, dwt_fuse_force_band_split,
+    // measured slower on every workload, so they are not candidates).
     if (staged_allowed(a.wavelet, path, 2)) {
         for (int kr : {1, 2, 4}) {
             for (int wpb : {1, 2, 4}) {
                 for (int order : {1, 0}) {
-                    Tile t;
-                    t.nc = 2;
-                    t.mode = 2 + kr;
-                    t.seg_rows = kr;
-                    t.wpb = wpb;
-                    t.order = order;
-                    const float ms = time_fuse(c, a, path, t);
-                    if (ms < bestms) {
-                        bestms = ms;
-                        bestt = t;
+                    for (int split : {0}) {
+                        Tile t;
+                        t.nc = 2;
+                        t.mode = 2 + kr;
+                        t.seg_rows = kr;
+                        t.wpb = wpb;
+                        t.order = order;
+                        t.split = split;
+                        const float ms = time_fuse(c, a, path, t);
+                        if (ms < bestms) {
+                            bestms = ms;
+                            bestt = t;
+                        }
                     }
                 }
             }
         }
     }
     if (std::getenv("DWT_FUSE_LOG"))
-        std::fprintf(stderr, "[dwt_fuse] tuned %s: mode=%d seg_rows=%d wpb=%d nc=%d order=%d (%.3f ms)\n",
+        std::fprintf(stderr, "[dwt_fuse] tuned %s: mode=%d seg_rows=%d wpb=%d nc=%d order=%d split=%d (%.3f ms)\n",
                      tune_key(0, a.wavelet, a.H, a.W, a.B, path).c_str(), bestt.mode, bestt.seg_rows, bestt.wpb,
-                     bestt.nc, bestt.order, bestms);
+                     bestt.nc, bestt.order, bestt.split, bestms);
     return bestt;
 }
 
@@ -773,6 +792,7 @@ dwt_fuse_status plan_batch(dwt_fuse_ctx *ctx, const dwt_fuse_item *items, int64_
             items_of_scene = d.units;
         }
         BatchScene &b = pl->sc[(size_t)i];
+        t.split = 0;  // batched launches keep every band of a tile in one work item
         b.p = make_params(a, path_for_nc(path, t.nc), t, d);
         b.unit_begin = (int32_t)total;
         b.pad_ = 0;
@@ -996,14 +1016,22 @@ dwt_fuse_status dwt_fuse_force_tile(dwt_fuse_ctx *ctx, int seg_rows, int wpb, in
     return DWT_FUSE_OK;
 }
 
+dwt_fuse_status dwt_fuse_force_band_split(dwt_fuse_ctx *ctx, int bands_per_unit) {
+    if (!ctx) return DWT_FUSE_E_NULL;
+    if (bands_per_unit < 0 || bands_per_unit > 8)
+        return fail(ctx, DWT_FUSE_E_SHAPE, "bands per unit out of range (0 .. 8)");
+    ctx->forced.split = bands_per_unit;
+    return DWT_FUSE_OK;
+}
+
 dwt_fuse_status dwt_fuse_tune_save(const dwt_fuse_ctx *ctx, const char *path) {
     if (!ctx || !path) return DWT_FUSE_E_NULL;
     FILE *f = std::fopen(path, "w");
     if (!f) return DWT_FUSE_E_STATE;
-    std::fprintf(f, "dwt_fuse_tune 3 %s %s\n", DWT_FUSE_BUILD_ID, ctx->device_name.c_str());
+    std::fprintf(f, "dwt_fuse_tune 4 %s %s\n", DWT_FUSE_BUILD_ID, ctx->device_name.c_str());
     for (const auto &kv : ctx->table)
-        std::fprintf(f, "%s %d %d %d %d %d\n", kv.first.c_str(), kv.second.seg_rows, kv.second.wpb, kv.second.nc,
-                     kv.second.order, kv.second.mode);
+        std::fprintf(f, "%s %d %d %d %d %d %d\n", kv.first.c_str(), kv.second.seg_rows, kv.second.wpb, kv.second.nc,
+                     kv.second.order, kv.second.mode, kv.second.split);
     std::fclose(f);
     return DWT_FUSE_OK;
 }
@@ -1016,15 +1044,22 @@ dwt_fuse_status dwt_fuse_tune_load(dwt_fuse_ctx *ctx, const char *path) {
     int ver = 0;
     std::map<std::string, Tile> tab;
     bool ok = std::fscanf(f, "%31s %d %127s %127s", magic, &ver, build, dev) == 4 &&
-              std::strcmp(magic, "dwt_fuse_tune") == 0 && ver == 3 && std::strcmp(build, DWT_FUSE_BUILD_ID) == 0 &&
+              std::strcmp(magic, "dwt_fuse_tune") == 0 && ver == 4 && std::strcmp(build, DWT_FUSE_BUILD_ID) == 0 &&
               ctx->device_name == dev;
     while (ok) {
         char key[96] = {0};
         Tile t;
-        const int r = std::fscanf(f, "%95s %d %d %d %d %d", key, &t.seg_rows, &t.wpb, &t.nc, &t.order, &t.mode);
+        const int r = std::fscanf(f, "%95s %d %d %d %d %d %d", key, &t.seg_rows, &t.wpb, &t.nc, &t.order, &t.mode,
+                                  &t.split);
         if (r == EOF) break;
-        if (r != 6 || t.seg_rows < 1 || t.seg_rows > 4096 || t.wpb < 1 || t.wpb > 4 || t.nc < 1 || t.nc > 2 ||
-            t.order < 0 || t.order > 1 || t.mode < 0 || t.mode > 6 || t.mode == 5) {
+        // 'f' / 'b': float-path tiles (mode 0 rolling, 1-2 one-shot, 3/4/6
+        // LDS-staged); 'c': format-variant shapes (nc 2/4/8, mode = rows of a
+        // one-shot tile, 0 = rolling).
+        const bool codec = key[0] == 'c';
+        const bool shape_ok = codec ? ((t.nc == 2 || t.nc == 4 || t.nc == 8) && t.mode >= 0 && t.mode <= 2)
+                                    : (t.nc >= 1 && t.nc <= 2 && t.mode >= 0 && t.mode <= 6 && t.mode != 5);
+        if (r != 7 || t.split < 0 || t.split > 8 || (key[0] != 'f' && key[0] != 'b' && !codec) || t.seg_rows < 1 || t.seg_rows > 4096 ||
+            t.wpb < 1 || t.wpb > 4 || t.order < 0 || t.order > 1 || !shape_ok) {
             ok = false;
             break;
         }
@@ -1048,7 +1083,8 @@ dwt_fuse_status run_float(dwt_fuse_ctx *ctx, const RunArgs &a, float kappa) {
         const Path path = choose_path(a);
         const Tile t = tile_for_run(ctx, a, path, true);
         Decomp d;
-        if (!decompose(a.H, a.W, t, &d)) return fail(ctx, DWT_FUSE_E_SHAPE, "too many work units");
+        if (!decompose(a.H, a.W, t, &d) || !split_fits(t, d, a.B))
+            return fail(ctx, DWT_FUSE_E_SHAPE, "too many work units");
         FuseParams p = make_params(a, path_for_nc(path, t.nc), t, d);
         p.kappa = kappa;
         const hipError_t e = launch_fuse(p, ctx->filt, t.wpb, ctx->stream);

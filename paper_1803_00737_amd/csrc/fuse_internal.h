@@ -35,6 +35,9 @@ struct FuseParams {
     int32_t order;     // unit numbering: 0 strip-major, 1 row-band-major
     int32_t mode;      // 0 rolling over seg_rows rows; 1, 2 one-shot tile of that many rows
     float kappa;       // LL <- kappa * MS band (1 = as printed)
+    int32_t bsplit;    // LDS-staged D4: bands per unit (0 = every band in one unit); units
+                       // are then (tile, band group) with the groups of a tile adjacent
+    int32_t pad_;
 };
 
 // Daubechies-4 low-pass taps (Eq. 7-8), rounded once from double.

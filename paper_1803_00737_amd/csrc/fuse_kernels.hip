@@ -428,7 +428,7 @@ __host__ __device__ constexpr int staged_lds_floats(int T, int bg) {
 // one contiguous 512-byte run).
 template <int KR, int LAY>
 __device__ __forceinline__ void d4_staged_tile(const FuseParams &p, const Filters &f, int bg_max, int unit,
-                                               float *lds, int wpb) {
+                                               float *lds, int wpb, int b_lo, int b_hi) {
     static_assert(LAY == 0 || LAY == 2 || LAY == 3, "row layouts: 16-, 4- or 8-byte rows");
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int T = wpb * KR;
@@ -470,7 +470,7 @@ __device__ __forceinline__ void d4_staged_tile(const FuseParams &p, const Filter
             lds_load4(row + wrap_idx(2 * sb + 256 + lane, p.W), dst + 260);
         }
     }
-    // MS rows r0-1 .. r0+T-1 of bands g0 .. g0+bg-1.
+    // MS rows r0-1 .. r0+T-1 of bands g0 .. g0+bg-1 (b_lo <= g0 < b_hi).
     auto stage_ms = [&](int g0, int bg) {
         for (int k = w; k < bg * (T + 1); k += wpb) {
             const int b = g0 + k / (T + 1), i = k - (k / (T + 1)) * (T + 1);
@@ -481,8 +481,8 @@ __device__ __forceinline__ void d4_staged_tile(const FuseParams &p, const Filter
             if (lane == 0) lds_load4(row + wrap_idx(sb - 1, W2), dst + 3);
         }
     };
-    const int bg0 = min(p.B, bg_max);
-    stage_ms(0, bg0);
+    const int bg0 = min(b_hi - b_lo, bg_max);
+    stage_ms(b_lo, bg0);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
 
@@ -536,9 +536,9 @@ __device__ __forceinline__ void d4_staged_tile(const FuseParams &p, const Filter
             colfilt<NC>(f, R[2 * i], R[2 * i + 1], R[2 * i + 2], R[2 * i + 3], A[h][i]);
     }
 
-    for (int g0 = 0; g0 < p.B; g0 += bg_max) {
-        const int bg = min(bg_max, p.B - g0);
-        if (g0 > 0) {  // next band group: every wavefront is done with the previous one
+    for (int g0 = b_lo; g0 < b_hi; g0 += bg_max) {
+        const int bg = min(bg_max, b_hi - g0);
+        if (g0 > b_lo) {  // next band group: every wavefront is done with the previous one
             __syncthreads();
             stage_ms(g0, bg);
             __builtin_amdgcn_s_waitcnt(0);
@@ -614,7 +614,14 @@ __global__ __launch_bounds__(256) void d4_staged_kernel(FuseParams p, Filters f,
     extern __shared__ float lds[];
     const int unit = xcd_remap(blockIdx.x, gridDim.x);
     if (unit >= p.units) return;  // whole workgroup
-    d4_staged_tile<KR, LAY>(p, f, bg_max, unit, lds, blockDim.x >> 6);
+    if (p.bsplit > 0) {  // unit = tile * ngroups + group
+        const int ng = (p.B + p.bsplit - 1) / p.bsplit;
+        const int tile = unit / ng, g = unit - tile * ng;
+        const int b_lo = g * p.bsplit;
+        d4_staged_tile<KR, LAY>(p, f, bg_max, tile, lds, blockDim.x >> 6, b_lo, min(p.B, b_lo + p.bsplit));
+    } else {
+        d4_staged_tile<KR, LAY>(p, f, bg_max, unit, lds, blockDim.x >> 6, 0, p.B);
+    }
 }
 
 template <int KR>
@@ -703,8 +710,9 @@ hipError_t launch_fuse(const FuseParams &p, const Filters &f, int wpb, hipStream
         if (p.wavelet != 1 || p.seg_rows != wpb * kr || p.nstrips != (p.W / 2 + 127) / 128)
             return hipErrorInvalidValue;
         const int bgm = staged_bg_max(p.seg_rows);
-        if (bgm < 1) return hipErrorInvalidValue;
-        const size_t lds = sizeof(float) * staged_lds_floats(p.seg_rows, p.B < bgm ? p.B : bgm);
+        if (bgm < 1 || p.bsplit < 0) return hipErrorInvalidValue;
+        const int per_unit = p.bsplit > 0 && p.bsplit < p.B ? p.bsplit : p.B;  // bands one unit handles
+        const size_t lds = sizeof(float) * staged_lds_floats(p.seg_rows, per_unit < bgm ? per_unit : bgm);
         switch (kr) {
             case 1: launch_staged<1>(p, f, wpb, lds, bgm, s); break;
             case 2: launch_staged<2>(p, f, wpb, lds, bgm, s); break;
@@ -837,11 +845,11 @@ __global__ __launch_bounds__(256) void fuse_batched_flat_kernel(const BatchScene
     const int item = u - scenes[si].unit_begin;
     if (p.mode >= 3) {
         if (p.path == PATH_V4)
-            d4_staged_tile<2, 0>(p, f, bg_max, item, lds, 4);
+            d4_staged_tile<2, 0>(p, f, bg_max, item, lds, 4, 0, p.B);
         else if (p.path == PATH_V2)
-            d4_staged_tile<2, 3>(p, f, bg_max, item, lds, 4);
+            d4_staged_tile<2, 3>(p, f, bg_max, item, lds, 4, 0, p.B);
         else
-            d4_staged_tile<2, 2>(p, f, bg_max, item, lds, 4);
+            d4_staged_tile<2, 2>(p, f, bg_max, item, lds, 4, 0, p.B);
         return;
     }
     const int unit = item * 4 + (threadIdx.x >> 6);

@@ -173,6 +173,7 @@ def test_null_context_entry_points(lib):
     assert lib.dwt_fuse_set_stream(None, None) == E_NULL
     assert lib.dwt_fuse_set_tuning(None, 1) == E_NULL
     assert lib.dwt_fuse_force_tile(None, 1, 1, 1, 0) == E_NULL
+    assert lib.dwt_fuse_force_band_split(None, 1) == E_NULL
     assert lib.dwt_fuse_run_multipass(None, 1, 8, 8, 1, P, 8, P + 10**6, 4, 16, P + 2 * 10**6, 8, 64) == E_NULL
     lib.dwt_fuse_destroy(None)  # NULL-safe
     assert lib.dwt_fuse_create(None, 0, None) == E_NULL

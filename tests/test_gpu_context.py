@@ -1,0 +1,101 @@
+"""Context-level behaviour on the GPU: the tuning table survives a save/load
+round trip (float and 8-bit entries), a mismatching or corrupt table is
+refused without changing results, and calls follow the stream a context is
+bound to."""
+import os
+
+import numpy as np
+import pytest
+
+from gpu_helpers import int_scene, require_gpu, say, to_dev, torch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return require_gpu()
+
+
+@pytest.fixture(scope="module")
+def fz():
+    from paper_1803_00737_amd import api
+
+    return api
+
+
+def test_tuning_table_round_trip(dev, fz, tmp_path):
+    from paper_1803_00737_amd import _lib
+
+    rng = np.random.default_rng(12)
+    pan, ms = int_scene(rng, 514, 1032, 3)
+    p, m = to_dev(pan, dev), to_dev(ms, dev)
+    p8, m8 = p.to(torch.uint8), m.to(torch.uint8)
+    a = fz.Context(dev.index or 0)
+    a.bind_stream()
+    a.set_tuning(True)
+
+    def run(ctx):
+        o = torch.empty((3, 514, 1032), device=dev)
+        q = torch.empty((3, 514, 1032), dtype=torch.uint8, device=dev)
+        from paper_1803_00737_amd.api import _ptr, _pitch
+        import ctypes
+        ctx.check(ctx.lib.dwt_fuse_run(ctx.handle, 1, 514, 1032, 3, _ptr(p), 1032, _ptr(m), 516, 257 * 516, None,
+                                       _ptr(o), 1032, 514 * 1032), "run")
+        opts = _lib.Opts(_lib.U8, _lib.U8, 1.0)
+        ctx.check(ctx.lib.dwt_fuse_run_ex(ctx.handle, 1, 514, 1032, 3, _ptr(p8), 1032, _ptr(m8), 516, 257 * 516, None,
+                                          _ptr(q), 1032, 514 * 1032, ctypes.byref(opts)), "run_ex")
+        torch.cuda.synchronize()
+        return o.cpu().numpy(), q.cpu().numpy()
+
+    say("tuning round trip: tune")
+    ref = run(a)
+    path = str(tmp_path / "tune.txt")
+    a.tune_save(path)
+    text = open(path).read().splitlines()
+    assert text[0].startswith("dwt_fuse_tune 4 ")
+    keys = [line.split()[0] for line in text[1:]]
+    assert any(k.startswith("f1_") for k in keys) and any(k.startswith("c111_") for k in keys)
+    b = fz.Context(dev.index or 0)
+    b.bind_stream()
+    b.tune_load(path)
+    say("tuning round trip: loaded")
+    got = run(b)
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+    # a table from another build (or a corrupt one) is refused as a whole
+    bad = str(tmp_path / "bad.txt")
+    with open(bad, "w") as f:
+        f.write(text[0].replace("dwt_fuse_tune 4 ", "dwt_fuse_tune 4 x") + "\n" + "\n".join(text[1:]) + "\n")
+    c = fz.Context(dev.index or 0)
+    c.bind_stream()
+    with pytest.raises(_lib.DwtFuseError) as e:
+        c.tune_load(bad)
+    assert e.value.status == _lib.E_STATE
+    with open(bad, "w") as f:
+        f.write(text[0] + "\nf1_h10 1 2\n")
+    with pytest.raises(_lib.DwtFuseError):
+        c.tune_load(bad)
+    with pytest.raises(_lib.DwtFuseError):
+        c.tune_load(str(tmp_path / "missing.txt"))
+    got = run(c)
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+
+
+def test_calls_follow_the_bound_stream(dev, fz):
+    """A context bound to a side stream issues there: results appear only
+    after that stream's work, and equal the default-stream results."""
+    rng = np.random.default_rng(13)
+    pan, ms = int_scene(rng, 258, 1030, 4)
+    p, m = to_dev(pan, dev), to_dev(ms, dev)
+    ref = fz.fuse(p, m, "d4").cpu().numpy()
+    side = torch.cuda.Stream()
+    ctx = fz.Context(dev.index or 0)
+    ctx.bind_stream(side)
+    out = torch.zeros((4, 258, 1030), device=dev)
+    side.wait_stream(torch.cuda.current_stream())
+    from paper_1803_00737_amd.api import _ptr
+    say("side stream")
+    ctx.check(ctx.lib.dwt_fuse_run(ctx.handle, 1, 258, 1030, 4, _ptr(p), 1030, _ptr(m), 515, 129 * 515, None,
+                                   _ptr(out), 1030, 258 * 1030), "run")
+    side.synchronize()
+    assert np.array_equal(out.cpu().numpy(), ref)

@@ -111,8 +111,9 @@ def test_paths_and_pitches(dev, fz, oracle, wavelet, pad, offset, H, W):
 @pytest.mark.parametrize("H,W", [(250, 1034), (250, 1288), (18, 8)])
 def test_tile_shapes_give_identical_results(dev, fz, wavelet, H, W):
     """Every output pixel is evaluated in the same order whatever unit holds
-    it, so forced launch shapes (rolling, one-shot and LDS-staged variants)
-    must agree bit for bit.  1288 = 5 full 256-column strips + a partial one
+    it, so forced launch shapes (rolling, one-shot and LDS-staged variants,
+    staged units split into band groups of 1 or 2 bands) must agree bit for
+    bit.  1288 = 5 full 256-column strips + a partial one
     on the 128-bit path; H/2 = 125 leaves partial tiles."""
     rng = np.random.default_rng(5)
     pan, ms = int_scene(rng, H, W, 3)
@@ -120,14 +121,18 @@ def test_tile_shapes_give_identical_results(dev, fz, wavelet, H, W):
     ctx = fz.context(dev)
     outs = []
     try:
-        for seg, wpb, nc, var in [(0, 0, 0, 0), (1, 1, 1, 1), (3, 2, 2, 1), (7, 4, 1, 1), (64, 1, 2, 1),
-                                  (200, 4, 2, 1), (1, 1, 2, 2), (2, 4, 2, 2), (1, 2, 1, 2), (2, 1, 1, 2),
-                                  (1, 4, 2, 3), (2, 2, 2, 3), (4, 1, 2, 3), (2, 4, 2, 3), (4, 4, 2, 3)]:
-            say(wavelet, "tile", seg, wpb, nc, var)
+        for seg, wpb, nc, var, split in [(0, 0, 0, 0, 0), (1, 1, 1, 1, 0), (3, 2, 2, 1, 0), (7, 4, 1, 1, 0),
+                                         (64, 1, 2, 1, 0), (200, 4, 2, 1, 0), (1, 1, 2, 2, 0), (2, 4, 2, 2, 0),
+                                         (1, 2, 1, 2, 0), (2, 1, 1, 2, 0), (1, 4, 2, 3, 0), (2, 2, 2, 3, 0),
+                                         (4, 1, 2, 3, 0), (2, 4, 2, 3, 0), (4, 4, 2, 3, 0), (2, 4, 2, 3, 1),
+                                         (1, 2, 2, 3, 2), (4, 1, 2, 3, 1)]:
+            say(wavelet, "tile", seg, wpb, nc, var, "split", split)
             ctx.force_tile(seg, wpb, nc, var)
+            ctx.force_band_split(split)
             outs.append(fz.fuse(p, m, wavelet).cpu().numpy())
     finally:
         ctx.force_tile(0, 0, 0, 0)
+        ctx.force_band_split(0)
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
 
