@@ -635,19 +635,16 @@ Tile tune_fuse(dwt_fuse_ctx *c, const RunArgs &a, Path path) {
         for (int kr : {1, 2, 4}) {
             for (int wpb : {1, 2, 4}) {
                 for (int order : {1, 0}) {
-                    for (int split : {0}) {
-                        Tile t;
-                        t.nc = 2;
-                        t.mode = 2 + kr;
-                        t.seg_rows = kr;
-                        t.wpb = wpb;
-                        t.order = order;
-                        t.split = split;
-                        const float ms = time_fuse(c, a, path, t);
-                        if (ms < bestms) {
-                            bestms = ms;
-                            bestt = t;
-                        }
+                    Tile t;
+                    t.nc = 2;
+                    t.mode = 2 + kr;
+                    t.seg_rows = kr;
+                    t.wpb = wpb;
+                    t.order = order;
+                    const float ms = time_fuse(c, a, path, t);
+                    if (ms < bestms) {
+                        bestms = ms;
+                        bestt = t;
                     }
                 }
             }
