@@ -30,6 +30,12 @@ typedef uint32_t u4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ float byte_at(uint32_t w, int i) { return (float)((w >> (8 * i)) & 0xffu); }
 
+// q mod n for q in [-n, 2n) (two compare/selects instead of an integer divide).
+__device__ __forceinline__ int wrap_near(int q, int n) {
+    q = q < 0 ? q + n : q;
+    return q >= n ? q - n : q;
+}
+
 // 8-bit code of a fused value: nearest integer, ties to even, clamped to
 // [0, 255], NaN -> 0.  The gfx950 float-to-packed-byte conversion does
 // exactly this in one instruction per pixel (rounding in the default
@@ -124,8 +130,13 @@ struct CodecCols {
     __device__ __forceinline__ CodecCols(int strip, int lane, int W2_) : W2(W2_) {
         s0 = (strip * 64 + lane) * NC;
         full = (s0 + NC) <= W2;
+        if (W2 > NC + 1) {  // s0 - 1 + k lies in [-1, W2 + NC] within [-W2, 2 W2)
 #pragma unroll
-        for (int k = 0; k < NC + 2; ++k) pc[k] = wrap_idx(s0 - 1 + k, W2);
+            for (int k = 0; k < NC + 2; ++k) pc[k] = wrap_near(s0 - 1 + k, W2);
+        } else {
+#pragma unroll
+            for (int k = 0; k < NC + 2; ++k) pc[k] = wrap_idx(s0 - 1 + k, W2);
+        }
     }
     __device__ __forceinline__ bool active() const { return s0 < W2; }
 
@@ -220,14 +231,22 @@ __device__ __forceinline__ void d4_codec_tile(const CodecParams &p, const Filter
     const int rb = seg * KR;
     const int nr = min(KR, H2 - rb);
     constexpr int NR = 2 * KR + 4;  // PAN rows 2rb-2 .. 2rb+2KR+1
+    // Rows lie in [-2, H + 2KR - 1] and [-1, H2 + KR - 1]: a compare/select
+    // wrap suffices unless the image is only a few rows high.
+    const bool near = p.H > 2 * KR + 4;
+    auto wrow = [&](int y, int n) { return near ? wrap_near(y, n) : wrap_idx(y, n); };
     f2 x[NR][NC + 2];
 #pragma unroll
-    for (int k = 0; k < NR; ++k) L.load_row(pan + (int64_t)wrap_idx(2 * rb - 2 + k, p.H) * p.pan_ld, x[k]);
+    for (int k = 0; k < NR; ++k) L.load_row(pan + (int64_t)wrow(2 * rb - 2 + k, p.H) * p.pan_ld, x[k]);
+    int64_t mrow[KR + 1];  // MS row offsets, the same for every band
+#pragma unroll
+    for (int i = 0; i <= KR; ++i) mrow[i] = (int64_t)wrow(rb - 1 + i, H2) * p.ms_ld;
     auto load_band = [&](int b, float(&m)[KR + 1][NC + 1]) {
         const TI *mb = ms + (int64_t)b * p.ms_bs;
 #pragma unroll
-        for (int i = 0; i <= KR; ++i) L.load_ms(mb + (int64_t)wrap_idx(rb - 1 + i, H2) * p.ms_ld, m[i]);
+        for (int i = 0; i <= KR; ++i) L.load_ms(mb + mrow[i], m[i]);
     };
+    const bool unit_kappa = p.kappa == 1.0f;  // kappa * m == m exactly: skip the multiply
     float m[KR + 1][NC + 1];
     load_band(0, m);
     float A[KR + 1][NC + 1];
@@ -238,16 +257,38 @@ __device__ __forceinline__ void d4_codec_tile(const CodecParams &p, const Filter
 #pragma unroll
         for (int i = 0; i <= KR; ++i) colfilt<NC>(f, R[2 * i], R[2 * i + 1], R[2 * i + 2], R[2 * i + 3], A[i]);
     }
+    const float h0 = f.h[0], h1 = f.h[1], h2 = f.h[2], h3 = f.h[3];
     for (int b = 0; b < p.B; ++b) {
         float mn[KR + 1][NC + 1];
         if (b + 1 < p.B) load_band(b + 1, mn);
         const float g = p.gain ? p.gain[b] : 1.0f;
         TO *ob = out + (int64_t)b * p.out_bs;
+        // Coefficient rows rb-1 .. rb+KR-1 of (kappa m - g L PAN), each formed
+        // once; then the synthesis of d4_out_rows, operation for operation.
+        float c[KR + 1][NC + 1];
+#pragma unroll
+        for (int i = 0; i <= KR; ++i)
+#pragma unroll
+            for (int j = 0; j <= NC; ++j) c[i][j] = fmaf(-g, A[i][j], unit_kappa ? m[i][j] : p.kappa * m[i][j]);
 #pragma unroll
         for (int i = 0; i < KR; ++i) {
             if (i >= nr) break;
+            float v0[NC + 1], v1[NC + 1];
+#pragma unroll
+            for (int j = 0; j <= NC; ++j) {
+                v0[j] = fmaf(h2, c[i][j], h0 * c[i + 1][j]);
+                v1[j] = fmaf(h3, c[i][j], h1 * c[i + 1][j]);
+            }
+            const f2(&xa)[NC + 2] = x[2 * i + 2];
+            const f2(&xb)[NC + 2] = x[2 * i + 3];
             f2 q0[NC], q1[NC];
-            d4_out_rows<NC>(f, g, p.kappa, m[i + 1], m[i], A[i + 1], A[i], x[2 * i + 2], x[2 * i + 3], q0, q1);
+#pragma unroll
+            for (int k = 0; k < NC; ++k) {
+                q0[k].x = fmaf(g, xa[k + 1].x, fmaf(h2, v0[k], h0 * v0[k + 1]));
+                q0[k].y = fmaf(g, xa[k + 1].y, fmaf(h3, v0[k], h1 * v0[k + 1]));
+                q1[k].x = fmaf(g, xb[k + 1].x, fmaf(h2, v1[k], h0 * v1[k + 1]));
+                q1[k].y = fmaf(g, xb[k + 1].y, fmaf(h3, v1[k], h1 * v1[k + 1]));
+            }
             TO *o0 = ob + (int64_t)(2 * (rb + i)) * p.out_ld;
             store_out<TO, NC, AL>(o0, L.s0, L.W2, L.full, q0);
             store_out<TO, NC, AL>(o0 + p.out_ld, L.s0, L.W2, L.full, q1);
