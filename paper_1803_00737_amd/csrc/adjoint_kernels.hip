@@ -808,7 +808,7 @@ __global__ __launch_bounds__(256) void gain_reduce_kernel(const float *partial, 
     sh[threadIdx.x] = a;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
         __syncthreads();
     }
     if (threadIdx.x == 0) grad_gain[b] = (float)sh[0];

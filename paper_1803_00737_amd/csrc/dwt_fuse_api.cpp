@@ -498,7 +498,7 @@ dwt_fuse_status use_device(dwt_fuse_ctx *c) {
 }
 
 void clear_graphs(dwt_fuse_ctx *c) {
-    for (auto &kv : c->graphs) hipGraphExecDestroy(kv.second);
+    for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     c->graphs.clear();
 }
 
@@ -572,32 +572,34 @@ Tile apply_forced(const dwt_fuse_ctx *c, Tile t, Path path, int wavelet) {
 Path path_for_nc(Path path, int nc) { return (path == PATH_V4 && nc == 1) ? PATH_V2 : path; }
 
 // Time one forward launch configuration on the caller's buffers (ms, median of 3).
-float time_fuse(dwt_fuse_ctx *c, const RunArgs &a, Path path, const Tile &t) {
-    Decomp d;
-    if (!decompose(a.H, a.W, t, &d) || !split_fits(t, d, a.B)) return 1e30f;
-    const Path pp = path_for_nc(path, t.nc);
-    const FuseParams p = make_params(a, pp, t, d);
+// Median of 3 timed runs of `launch` on stream s (ms), after one warm-up;
+// 1e30 if any launch or event call fails, so a failing candidate is never
+// chosen.
+template <class F>
+float time_median3(hipStream_t s, F launch) {
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return 1e30f;
     if (hipEventCreate(&e1) != hipSuccess) {
-        hipEventDestroy(e0);
+        (void)hipEventDestroy(e0);
         return 1e30f;
     }
-    float best[3] = {1e30f, 1e30f, 1e30f};
-    launch_fuse(p, c->filt, t.wpb, c->stream);  // warm-up
-    for (int k = 0; k < 3; ++k) {
-        hipEventRecord(e0, c->stream);
-        launch_fuse(p, c->filt, t.wpb, c->stream);
-        hipEventRecord(e1, c->stream);
-        hipEventSynchronize(e1);
-        float ms = 0;
-        hipEventElapsedTime(&ms, e0, e1);
-        best[k] = ms;
-    }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    std::sort(best, best + 3);
-    return best[1];
+    float t[3] = {1e30f, 1e30f, 1e30f};
+    bool ok = launch() == hipSuccess;
+    for (int k = 0; ok && k < 3; ++k)
+        ok = hipEventRecord(e0, s) == hipSuccess && launch() == hipSuccess && hipEventRecord(e1, s) == hipSuccess &&
+             hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&t[k], e0, e1) == hipSuccess;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (!ok) return 1e30f;
+    std::sort(t, t + 3);
+    return t[1];
+}
+
+float time_fuse(dwt_fuse_ctx *c, const RunArgs &a, Path path, const Tile &t) {
+    Decomp d;
+    if (!decompose(a.H, a.W, t, &d) || !split_fits(t, d, a.B)) return 1e30f;
+    const FuseParams p = make_params(a, path_for_nc(path, t.nc), t, d);
+    return time_median3(c->stream, [&] { return launch_fuse(p, c->filt, t.wpb, c->stream); });
 }
 
 Tile tune_fuse(dwt_fuse_ctx *c, const RunArgs &a, Path path) {
@@ -675,8 +677,8 @@ Tile tile_for_run(dwt_fuse_ctx *c, const RunArgs &a, Path path, bool allow_tune)
 dwt_fuse_status ensure_ws(dwt_fuse_ctx *c, size_t bytes) {
     if (bytes <= c->ws_bytes) return DWT_FUSE_OK;
     if (c->ws) {
-        hipStreamSynchronize(c->stream);
-        hipFree(c->ws);
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipFree(c->ws);
         c->ws = nullptr;
         c->ws_bytes = 0;
     }
@@ -705,10 +707,10 @@ dwt_fuse_status ensure_batch_tables(dwt_fuse_ctx *c, size_t n) {
     }
     if (n <= c->scenes_cap) return DWT_FUSE_OK;
     // Growing moves the device table: captured graphs point at the old one.
-    hipStreamSynchronize(c->stream);
+    (void)hipStreamSynchronize(c->stream);
     clear_graphs(c);
-    if (c->d_scenes) hipFree(c->d_scenes);
-    if (c->h_scenes) hipHostFree(c->h_scenes);
+    if (c->d_scenes) (void)hipFree(c->d_scenes);
+    if (c->h_scenes) (void)hipHostFree(c->h_scenes);
     c->d_scenes = nullptr;
     c->h_scenes = nullptr;
     c->scenes_cap = 0;
@@ -866,33 +868,15 @@ hipError_t launch_plan(dwt_fuse_ctx *ctx, const BatchPlan &pl, hipStream_t s) {
 // Median of 3 timed launches of a planned batch (ms), after one warm-up.
 float time_batch(dwt_fuse_ctx *ctx, const BatchPlan &pl) {
     if (stage_batch(ctx, pl) != DWT_FUSE_OK) return 1e30f;
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess) return 1e30f;
-    if (hipEventCreate(&e1) != hipSuccess) {
-        hipEventDestroy(e0);
-        return 1e30f;
-    }
-    launch_plan(ctx, pl, ctx->stream);
-    float t[3];
-    for (int k = 0; k < 3; ++k) {
-        hipEventRecord(e0, ctx->stream);
-        launch_plan(ctx, pl, ctx->stream);
-        hipEventRecord(e1, ctx->stream);
-        hipEventSynchronize(e1);
-        t[k] = 1e30f;
-        hipEventElapsedTime(&t[k], e0, e1);
-    }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    std::sort(t, t + 3);
-    return t[1];
+    return time_median3(ctx->stream, [&] { return launch_plan(ctx, pl, ctx->stream); });
 }
 
 }  // namespace
 
 // ---------------------------------------------------------------- C ABI
 
-extern "C" {
+// The public entry points below take C linkage from their declarations in
+// dwt_fuse.h; the helpers between them are internal C++.
 
 const char *dwt_fuse_status_str(dwt_fuse_status s) {
     switch (s) {
@@ -973,17 +957,17 @@ void dwt_fuse_destroy(dwt_fuse_ctx *ctx) {
     if (!ctx) return;
     try {
         int cur = -1;
-        hipGetDevice(&cur);
-        hipSetDevice(ctx->device);
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(ctx->device);
         clear_graphs(ctx);
-        if (ctx->ws) hipFree(ctx->ws);
-        if (ctx->mp) hipFree(ctx->mp);
-        if (ctx->d_scenes) hipFree(ctx->d_scenes);
-        if (ctx->h_scenes) hipHostFree(ctx->h_scenes);
-        if (ctx->d_counters) hipFree(ctx->d_counters);
-        if (ctx->staged) hipEventDestroy(ctx->staged);
-        if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
-        if (cur >= 0) hipSetDevice(cur);
+        if (ctx->ws) (void)hipFree(ctx->ws);
+        if (ctx->mp) (void)hipFree(ctx->mp);
+        if (ctx->d_scenes) (void)hipFree(ctx->d_scenes);
+        if (ctx->h_scenes) (void)hipHostFree(ctx->h_scenes);
+        if (ctx->d_counters) (void)hipFree(ctx->d_counters);
+        if (ctx->staged) (void)hipEventDestroy(ctx->staged);
+        if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+        if (cur >= 0) (void)hipSetDevice(cur);
     } catch (...) {
     }
     delete ctx;
@@ -1193,26 +1177,7 @@ hipError_t launch_codec_shape(dwt_fuse_ctx *c, const ExArgs &a, const CodecShape
 }
 
 float time_codec(dwt_fuse_ctx *c, const ExArgs &a, const CodecShape &t) {
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess) return 1e30f;
-    if (hipEventCreate(&e1) != hipSuccess) {
-        hipEventDestroy(e0);
-        return 1e30f;
-    }
-    float best[3] = {1e30f, 1e30f, 1e30f};
-    if (launch_codec_shape(c, a, t) == hipSuccess) {
-        for (int k = 0; k < 3; ++k) {
-            hipEventRecord(e0, c->stream);
-            launch_codec_shape(c, a, t);
-            hipEventRecord(e1, c->stream);
-            hipEventSynchronize(e1);
-            hipEventElapsedTime(&best[k], e0, e1);
-        }
-    }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    std::sort(best, best + 3);
-    return best[1];
+    return time_median3(c->stream, [&] { return launch_codec_shape(c, a, t); });
 }
 
 CodecShape codec_shape(dwt_fuse_ctx *c, const ExArgs &a) {
@@ -1470,13 +1435,13 @@ dwt_fuse_status dwt_fuse_run_batched(dwt_fuse_ctx *ctx, const dwt_fuse_item *ite
             const hipError_t le = launch_plan(ctx, plan, ctx->cap_stream);
             e = hipStreamEndCapture(ctx->cap_stream, &g);
             if (le != hipSuccess) {
-                if (g) hipGraphDestroy(g);
+                if (g) (void)hipGraphDestroy(g);
                 return hip_fail(ctx, le, "batched launch (capture)");
             }
             if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamEndCapture");
             hipGraphExec_t ge = nullptr;
             e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-            hipGraphDestroy(g);
+            (void)hipGraphDestroy(g);
             if (e != hipSuccess) return hip_fail(ctx, e, "hipGraphInstantiate");
             if (ctx->graphs.size() >= 64) clear_graphs(ctx);
             it = ctx->graphs.emplace(plan.sig, ge).first;
@@ -1506,8 +1471,8 @@ dwt_fuse_status dwt_fuse_run_multipass(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavel
         const size_t need = sizeof(float) * 2 * (size_t)H * (size_t)W;
         if (need > ctx->mp_bytes) {
             if (ctx->mp) {
-                hipStreamSynchronize(ctx->stream);
-                hipFree(ctx->mp);
+                (void)hipStreamSynchronize(ctx->stream);
+                (void)hipFree(ctx->mp);
                 ctx->mp = nullptr;
                 ctx->mp_bytes = 0;
             }
@@ -1674,4 +1639,4 @@ dwt_fuse_status dwt_fuse_backward(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet, i
     }
 }
 
-}  // extern "C"
+
