@@ -260,8 +260,9 @@ def make_items(scenes: Sequence[dict]):
 
 
 def fuse_batched(scenes: Sequence[dict], graph: bool = False, device=None) -> List[torch.Tensor]:
-    """Fuse many independent scenes in one persistent launch (optionally
-    captured/replayed as a hipGraph).  Returns the list of outputs."""
+    """Fuse many independent scenes of any sizes, band counts and wavelets in
+    one kernel launch (optionally captured into / replayed from a hipGraph).
+    Returns the list of outputs."""
     if len(scenes) == 0:
         return []
     arr, outs, keep = make_items(scenes)
@@ -289,6 +290,10 @@ def fuse_backward(pan: torch.Tensor, grad_out: torch.Tensor, wavelet="d4", gain:
     if gain is not None:
         _require(gain, "gain", 1)
         gain = gain.contiguous()
+        if gain.shape[0] != B:
+            raise ValueError("gain must have B=%d entries" % B)
+    if grad_out.device != pan.device:
+        raise ValueError("pan and grad_out must be on the same device")
     dev = pan.device
     gp = torch.empty((H, W), dtype=torch.float32, device=dev) if need_pan else None
     gm = torch.empty((B, H // 2, W // 2), dtype=torch.float32, device=dev) if need_ms else None

@@ -179,6 +179,15 @@ def test_errors_surface_as_exceptions(dev, fz):
         fz.fuse(torch.zeros(8, 8, device=dev), torch.zeros(1, 3, 4, device=dev), "d4")
     with pytest.raises(ValueError):
         fz.fuse(pan, ms, "db8")
+    # backward: gain of the wrong length is rejected by the binding
+    with pytest.raises(ValueError):
+        fz.fuse_backward(pan, torch.zeros(2, 8, 8, device=dev), "d4", torch.ones(3, device=dev))
+    with pytest.raises(DwtFuseError, match="E_ALIAS"):  # gradient output aliasing an input
+        from paper_1803_00737_amd.api import context, _ptr
+        c = context(dev)
+        gy = torch.zeros(1, 8, 8, device=dev)
+        c.check(c.lib.dwt_fuse_backward(c.handle, 1, 8, 8, 1, _ptr(pan), 8, None, _ptr(gy), 8, 64, _ptr(gy), None,
+                                        None), "dwt_fuse_backward")
 
 
 def test_nan_propagates(dev, fz):
