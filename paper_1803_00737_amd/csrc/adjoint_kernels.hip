@@ -1047,7 +1047,7 @@ hipError_t launch_adjoint_staged(const AdjParams &p, const Filters &f, int kr, i
 
 hipError_t launch_adjoint(const AdjParams &p, const Filters &f, int wpb, hipStream_t s) {
     if (p.units <= 0) return hipSuccess;
-    if (p.B > kAdjMaxBands || p.B < 1) return hipErrorInvalidValue;
+    if (p.B > kAdjMaxBands || p.B < 1 || p.path == PATH_V2W) return hipErrorInvalidValue;
     const int grid = (p.units + wpb - 1) / wpb;
     const dim3 block(64 * wpb);
     switch (p.path) {
@@ -1066,7 +1066,8 @@ hipError_t launch_adjoint(const AdjParams &p, const Filters &f, int wpb, hipStre
 
 hipError_t launch_adjoint_bg(const AdjParams &p, const Filters &f, int wpb, hipStream_t s) {
     if (p.units <= 0) return hipSuccess;
-    if (p.B < 1 || p.B > 4 || p.wavelet != 1 || p.accumulate || wpb < 1 || wpb > 4) return hipErrorInvalidValue;
+    if (p.B < 1 || p.B > 4 || p.wavelet != 1 || p.accumulate || wpb < 1 || wpb > 4 || p.path == PATH_V2W)
+        return hipErrorInvalidValue;
     const int grid = (p.units + wpb - 1) / wpb;
     const dim3 block(64 * wpb);
 #define ADJ_BG(NC, AL, BG) hipLaunchKernelGGL((adjoint_bg_kernel<NC, AL, BG>), dim3(grid), block, 0, s, p, f)
@@ -1089,7 +1090,8 @@ hipError_t launch_adjoint_bg(const AdjParams &p, const Filters &f, int wpb, hipS
 
 hipError_t launch_adjoint_tile(const AdjParams &p, const Filters &f, int kr, int wpb, hipStream_t s) {
     if (p.units <= 0) return hipSuccess;
-    if (p.B > kAdjMaxBands || p.B < 1 || p.wavelet != 1 || p.seg_rows != kr || wpb < 1 || wpb > 4)
+    if (p.B > kAdjMaxBands || p.B < 1 || p.wavelet != 1 || p.seg_rows != kr || wpb < 1 || wpb > 4 ||
+        p.path == PATH_V2W)
         return hipErrorInvalidValue;
     const int grid = (p.units + wpb - 1) / wpb;
     const dim3 block(64 * wpb);

@@ -380,12 +380,13 @@ bool decompose(int64_t H, int64_t W, const Tile &t, Decomp *d) {
 }
 
 // Rolling shape (the adjoint kernels and the persistent batch kernel's
-// rolling variant): 4 waves per workgroup, 2 coefficient columns per lane
-// where the 128-bit path applies, units of 32 coefficient rows shortened
-// until the launch has at least 8192 wavefronts (32 per CU) or 4 rows.
-Tile rolling_tile(int64_t H, int64_t W, Path path) {
+// rolling variant): 4 waves per workgroup, nc coefficient columns per lane
+// (the widest the caller's kernels have on the path), units of 32
+// coefficient rows shortened until the launch has at least 8192 wavefronts
+// (32 per CU) or 4 rows.
+Tile rolling_tile(int64_t H, int64_t W, int nc) {
     Tile t;
-    t.nc = path_nc(path);
+    t.nc = nc;
     t.wpb = 4;
     t.seg_rows = 32;
     t.mode = 0;
@@ -396,24 +397,25 @@ Tile rolling_tile(int64_t H, int64_t W, Path path) {
 
 // Default forward shape (what the tuner picks on the large workloads):
 // D4 -> LDS-staged workgroups of 4 wavefronts x 2 coefficient rows, strip-major
-// units; Haar -> one-shot single-row wavefronts, row-band-major units.
+// units, except on 8-byte rows below 2^25 pixels, where one-shot single-row
+// wavefronts with 2 coefficient columns per lane measured faster (the staged
+// tile then stages half of its rows in 16-byte groups shifted by 2 floats);
+// Haar -> one-shot single-row wavefronts, row-band-major units.
 Tile default_tile(int wavelet, int64_t H, int64_t W, Path path) {
     Tile t;
-    if (wavelet == DWT_FUSE_D4) {
+    if (wavelet == DWT_FUSE_D4 && !(path == PATH_V2 && H * W < ((int64_t)1 << 25))) {
         t.nc = 2;
         t.mode = 4;
         t.seg_rows = 2;
         t.wpb = 4;
         t.order = 0;
     } else {
-        t.nc = path_nc(path);
+        t.nc = fwd_path_nc(path);
         t.mode = 1;
         t.seg_rows = 1;
-        t.wpb = 1;
+        t.wpb = wavelet == DWT_FUSE_D4 ? 4 : 1;
         t.order = 1;
     }
-    (void)H;
-    (void)W;
     return t;
 }
 
@@ -542,11 +544,12 @@ bool split_fits(const Tile &t, const Decomp &d, int64_t B) {
 // coefficient columns wide, i.e. nc = 2 in the decomposition).
 bool staged_allowed(int wavelet, Path, int) { return wavelet == DWT_FUSE_D4; }
 
-Tile apply_forced(const dwt_fuse_ctx *c, Tile t, Path path, int wavelet) {
+// max_nc: the widest lane layout the caller's kernels have on this path.
+Tile apply_forced(const dwt_fuse_ctx *c, Tile t, Path path, int wavelet, int max_nc) {
     const Forced &fo = c->forced;
     if (fo.seg_rows > 0) t.seg_rows = fo.seg_rows;
     if (fo.wpb > 0) t.wpb = fo.wpb;
-    if (fo.nc > 0) t.nc = std::min(fo.nc, path_nc(path));
+    if (fo.nc > 0) t.nc = std::min(fo.nc, max_nc);
     int variant = fo.variant;
     if (variant == 3 && !staged_allowed(wavelet, path, t.nc)) variant = 2;
     if (variant == 0 && t.mode >= 3 && !staged_allowed(wavelet, path, t.nc)) variant = 2;
@@ -560,7 +563,7 @@ Tile apply_forced(const dwt_fuse_ctx *c, Tile t, Path path, int wavelet) {
         t.nc = 2;  // staged strips are 128 coefficient columns on every path
         if (t.wpb < 1) t.wpb = 4;
     } else if (t.mode > 0 || variant == 1) {
-        if (t.nc > path_nc(path) || t.nc < 1) t.nc = path_nc(path);
+        if (t.nc > max_nc || t.nc < 1) t.nc = max_nc;
     }
     if (t.wpb < 1) t.wpb = 4;
     if (t.mode == 0 && t.seg_rows < 1) t.seg_rows = 1;
@@ -569,7 +572,13 @@ Tile apply_forced(const dwt_fuse_ctx *c, Tile t, Path path, int wavelet) {
     return t;
 }
 
-Path path_for_nc(Path path, int nc) { return (path == PATH_V4 && nc == 1) ? PATH_V2 : path; }
+// The path a launch runs: NC = 1 on 128-bit rows takes the 64-bit kernels,
+// NC = 2 on 64-bit rows the mixed 64/128-bit ones.
+Path path_for_nc(Path path, int nc) {
+    if (path == PATH_V4 && nc == 1) return PATH_V2;
+    if (path == PATH_V2 && nc == 2) return PATH_V2W;
+    return path;
+}
 
 // Time one forward launch configuration on the caller's buffers (ms, median of 3).
 // Median of 3 timed runs of `launch` on stream s (ms), after one warm-up;
@@ -607,11 +616,11 @@ Tile tune_fuse(dwt_fuse_ctx *c, const RunArgs &a, Path path) {
     float bestms = time_fuse(c, a, path, bestt);
     // Candidates: rolling units of 2..64 rows and one-shot units of 1 or 2
     // rows, each with 1, 2 or 4 waves per workgroup, both unit orders and
-    // (on the 128-bit path) 1 or 2 coefficient columns per lane.
+    // (on 128- and 64-bit rows) 1 or 2 coefficient columns per lane.
     const int ncs[2] = {2, 1};
     const int rows_cand[8] = {-1, -2, 2, 4, 8, 16, 32, 64};  // negative: one-shot of that many rows
     for (int nc : ncs) {
-        if (nc > path_nc(path)) continue;
+        if (nc > fwd_path_nc(path)) continue;
         for (int rc : rows_cand) {
             for (int wpb : {1, 2, 4}) {
                 for (int order : {1, 0}) {
@@ -671,7 +680,7 @@ Tile tile_for_run(dwt_fuse_ctx *c, const RunArgs &a, Path path, bool allow_tune)
     } else {
         t = default_tile(a.wavelet, a.H, a.W, path);
     }
-    return apply_forced(c, t, path, a.wavelet);
+    return apply_forced(c, t, path, a.wavelet, fwd_path_nc(path));
 }
 
 dwt_fuse_status ensure_ws(dwt_fuse_ctx *c, size_t bytes) {
@@ -768,13 +777,17 @@ dwt_fuse_status plan_batch(dwt_fuse_ctx *ctx, const dwt_fuse_item *items, int64_
         if (mode == kFlatBatch) {
             t.order = 1;
             t.wpb = 4;
+            // Every D4 scene staged, also on 8-byte rows where one-shot
+            // wavefronts win per image: the launch reserves the staged
+            // tiles' LDS for every workgroup, and one-shot items at that
+            // occupancy measured slower than staged ones.
             if (staged_allowed(a.wavelet, path, 2)) {
                 t.nc = 2;
                 t.mode = 4;  // staged, 2 rows per wavefront, 4 wavefronts
                 t.seg_rows = 2;
                 pl->staged_bands = std::max<int>(pl->staged_bands, (int)a.B);
             } else {
-                t.nc = path_nc(path);
+                t.nc = fwd_path_nc(path);
                 t.mode = 1;
                 t.seg_rows = 1;
             }
@@ -785,7 +798,7 @@ dwt_fuse_status plan_batch(dwt_fuse_ctx *ctx, const dwt_fuse_item *items, int64_
             if (mode > 0) {
                 t.mode = mode;
             } else if (t.mode > 0) {  // one-shot or staged per-image tiles: rolling here
-                t = rolling_tile(a.H, a.W, path);
+                t = rolling_tile(a.H, a.W, fwd_path_nc(path));
             }
             if (!decompose(a.H, a.W, t, &d)) return fail(ctx, DWT_FUSE_E_SHAPE, "too many work units");
             items_of_scene = d.units;
@@ -1562,7 +1575,7 @@ dwt_fuse_status dwt_fuse_backward(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet, i
             }
             return DWT_FUSE_OK;
         }
-        Tile t = rolling_tile(H, W, path);
+        Tile t = rolling_tile(H, W, path_nc(path));
         {
             auto it = ctx->table.find(tune_key(1, a.wavelet, H, W, B, path));
             if (it != ctx->table.end()) t = it->second;
@@ -1574,11 +1587,11 @@ dwt_fuse_status dwt_fuse_backward(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet, i
             Decomp d0;
             while (t.seg_rows > 4 && decompose(H, W, t, &d0) && d0.units < 2048) t.seg_rows /= 2;
         }
-        t = apply_forced(ctx, t, path, a.wavelet);
+        t = apply_forced(ctx, t, path, a.wavelet, path_nc(path));
         // Adjoint kernels: rolling units (mode 0) and, for D4, one-shot tiles of
         // 1 or 2 rows (mode 1, 2); no LDS-staged form here.
         if (t.mode != 0 && !(a.wavelet == DWT_FUSE_D4 && (t.mode == 1 || t.mode == 2))) {
-            const Tile r = rolling_tile(H, W, path);
+            const Tile r = rolling_tile(H, W, path_nc(path));
             t.mode = 0;
             t.seg_rows = r.seg_rows;
             t.nc = std::min(t.nc, path_nc(path));
@@ -1586,6 +1599,7 @@ dwt_fuse_status dwt_fuse_backward(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet, i
         }
         if (t.mode == 1 || t.mode == 2) t.seg_rows = t.mode;
         if (t.seg_rows < 1) t.seg_rows = 1;
+        if (t.nc > path_nc(path)) t.nc = path_nc(path);  // the adjoint has no mixed 64/128-bit form
         const Path pp = path_for_nc(path, t.nc);
         Decomp d;
         if (!decompose(H, W, t, &d)) return fail(ctx, DWT_FUSE_E_SHAPE, "too many work units");

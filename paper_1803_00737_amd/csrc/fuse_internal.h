@@ -12,9 +12,18 @@ namespace dwtf {
 //   PATH_V4     NC = 2, 128-bit PAN/out rows, 64-bit MS rows (all aligned)
 //   PATH_V2     NC = 1, 64-bit PAN/out rows, scalar MS
 //   PATH_SCALAR NC = 1, scalar everything (odd pointer offsets or pitches)
-enum Path : int32_t { PATH_V4 = 0, PATH_V2 = 1, PATH_SCALAR = 2 };
+//   PATH_V2W    NC = 2 on 64-bit rows (forward only): 128-bit accesses on the
+//               rows that happen to be 16-byte aligned, 64-bit on the others;
+//               64-bit MS on 8-byte aligned MS rows, scalar otherwise
+// The LDS-staged D4 kernels read only the row alignment from the path
+// (PATH_V2 and PATH_V2W both mean 8-byte rows).
+enum Path : int32_t { PATH_V4 = 0, PATH_V2 = 1, PATH_SCALAR = 2, PATH_V2W = 3 };
 
+// Widest lane layout of a path chosen from the alignment of the arguments
+// (the adjoint kernels: NC = 2 needs the 128-bit path).
 inline int path_nc(Path p) { return p == PATH_V4 ? 2 : 1; }
+// The same for the forward kernels, which also run NC = 2 on 64-bit rows.
+inline int fwd_path_nc(Path p) { return p == PATH_SCALAR ? 1 : 2; }
 
 // One scene as the kernels see it.  A work unit is one wavefront (64 lanes)
 // covering a strip of 64*NC coefficient columns and seg_rows coefficient

@@ -45,7 +45,7 @@
 
 namespace dwtf {
 
-template <bool AL>
+template <int AL>
 __device__ __forceinline__ f2 ld2(const float *p) {
     if constexpr (AL) {
         return *reinterpret_cast<const f2 *>(p);
@@ -54,7 +54,7 @@ __device__ __forceinline__ f2 ld2(const float *p) {
     }
 }
 
-template <bool AL>
+template <int AL>
 __device__ __forceinline__ void st2(float *p, f2 v) {
     if constexpr (AL) {
         __builtin_nontemporal_store(v, reinterpret_cast<f2 *>(p));
@@ -71,7 +71,13 @@ __device__ __forceinline__ void st4(float *p, f4 v) {
 // The columns one lane owns: coefficient columns s0 .. s0+NC-1 (output
 // columns 2*s0 .. 2*s0+2*NC-1), plus the wrapped neighbours s0-1 and s0+NC
 // that D4 needs (Eq. 5-6).  pc[k] = (s0 - 1 + k) mod W/2.
-template <int NC, bool AL>
+// AL: 0 = 4-byte rows; 1 = aligned rows (8-byte pairs, and with NC = 2
+// 16-byte own groups and 8-byte MS pairs); 2 = NC = 2 on 8-byte rows, with
+// 16-byte own groups on the rows that are 16-byte aligned and 8-byte MS pairs
+// on the MS rows that are 8-byte aligned.  2*s0 is a multiple of 4 when
+// NC = 2, so the alignment of a lane's group is that of its row (the same
+// for the whole wavefront).
+template <int NC, int AL>
 struct LaneCols {
     int s0, W2;
     bool full;  // all NC own columns inside the image (vector access allowed)
@@ -85,11 +91,18 @@ struct LaneCols {
     }
     __device__ __forceinline__ bool active() const { return s0 < W2; }
 
+    static __device__ __forceinline__ bool wide(const float *row) {
+        return AL == 1 || (AL == 2 && (reinterpret_cast<uintptr_t>(row) & 15) == 0);
+    }
+    static __device__ __forceinline__ bool wide_ms(const float *mrow) {
+        return AL == 1 || (AL == 2 && (reinterpret_cast<uintptr_t>(mrow) & 7) == 0);
+    }
+
     // Row pairs at pc[0..NC+1] (x[1..NC] are the lane's own pixels).
     __device__ __forceinline__ void load_row(const float *row, f2 (&x)[NC + 2]) const {
         x[0] = ld2<AL>(row + 2 * pc[0]);
         if constexpr (NC == 2 && AL) {
-            if (full) {
+            if (full && wide(row)) {
                 const f4 v = *reinterpret_cast<const f4 *>(row + 2 * s0);
                 x[1] = f2{v.x, v.y};
                 x[2] = f2{v.z, v.w};
@@ -106,7 +119,7 @@ struct LaneCols {
     // Only the lane's own pairs (Haar).
     __device__ __forceinline__ void load_own(const float *row, f2 (&x)[NC]) const {
         if constexpr (NC == 2 && AL) {
-            if (full) {
+            if (full && wide(row)) {
                 const f4 v = *reinterpret_cast<const f4 *>(row + 2 * s0);
                 x[0] = f2{v.x, v.y};
                 x[1] = f2{v.z, v.w};
@@ -120,7 +133,7 @@ struct LaneCols {
     __device__ __forceinline__ void load_ms(const float *mrow, float (&m)[NC + 1]) const {
         m[0] = mrow[pc[0]];
         if constexpr (NC == 2 && AL) {
-            if (full) {
+            if (full && wide_ms(mrow)) {
                 const f2 v = *reinterpret_cast<const f2 *>(mrow + s0);
                 m[1] = v.x;
                 m[2] = v.y;
@@ -133,7 +146,7 @@ struct LaneCols {
     // MS coefficients at the lane's own columns only (Haar).
     __device__ __forceinline__ void load_ms_own(const float *mrow, float (&m)[NC]) const {
         if constexpr (NC == 2 && AL) {
-            if (full) {
+            if (full && wide_ms(mrow)) {
                 const f2 v = *reinterpret_cast<const f2 *>(mrow + s0);
                 m[0] = v.x;
                 m[1] = v.y;
@@ -145,10 +158,14 @@ struct LaneCols {
     }
     __device__ __forceinline__ void store_row(float *orow, const f2 (&q)[NC]) const {
         if constexpr (NC == 2 && AL) {
-            if (full)
-                st4(orow + 2 * s0, f4{q[0].x, q[0].y, q[1].x, q[1].y});
-            else
+            if (!full) {
                 st2<AL>(orow + 2 * s0, q[0]);  // s0 + 1 == W2: one pair left
+            } else if (wide(orow)) {
+                st4(orow + 2 * s0, f4{q[0].x, q[0].y, q[1].x, q[1].y});
+            } else {
+                st2<AL>(orow + 2 * s0, q[0]);
+                st2<AL>(orow + 2 * s0 + 2, q[1]);
+            }
         } else {
 #pragma unroll
             for (int i = 0; i < NC; ++i)
@@ -159,7 +176,7 @@ struct LaneCols {
 
 // ---- Daubechies-4, rolling ----------------------------------------------
 
-template <int NC, bool AL>
+template <int NC, int AL>
 __device__ __forceinline__ void d4_rolling(const FuseParams &p, const Filters &f, int strip, int seg, int lane) {
     const LaneCols<NC, AL> L(strip, lane, p.W >> 1);
     if (!L.active()) return;
@@ -222,7 +239,7 @@ __device__ __forceinline__ void d4_rolling(const FuseParams &p, const Filters &f
 
 // ---- Daubechies-4, one-shot tile of KR coefficient rows --------------------
 
-template <int NC, bool AL, int KR>
+template <int NC, int AL, int KR>
 __device__ __forceinline__ void d4_tile(const FuseParams &p, const Filters &f, int strip, int seg, int lane) {
     const LaneCols<NC, AL> L(strip, lane, p.W >> 1);
     if (!L.active()) return;
@@ -276,7 +293,7 @@ __device__ __forceinline__ void d4_tile(const FuseParams &p, const Filters &f, i
 
 // ---- Haar -----------------------------------------------------------------
 
-template <int NC, bool AL>
+template <int NC, int AL>
 __device__ __forceinline__ void haar_rolling(const FuseParams &p, int strip, int seg, int lane) {
     const LaneCols<NC, AL> L(strip, lane, p.W >> 1);
     if (!L.active()) return;
@@ -302,7 +319,7 @@ __device__ __forceinline__ void haar_rolling(const FuseParams &p, int strip, int
     }
 }
 
-template <int NC, bool AL, int KR>
+template <int NC, int AL, int KR>
 __device__ __forceinline__ void haar_tile(const FuseParams &p, int strip, int seg, int lane) {
     const LaneCols<NC, AL> L(strip, lane, p.W >> 1);
     if (!L.active()) return;
@@ -631,6 +648,7 @@ static void launch_staged(const FuseParams &p, const Filters &f, int wpb, size_t
             hipLaunchKernelGGL((d4_staged_kernel<KR, 0>), dim3(p.units), dim3(64 * wpb), lds, s, p, f, bgm);
             break;
         case PATH_V2:
+        case PATH_V2W:
             hipLaunchKernelGGL((d4_staged_kernel<KR, 3>), dim3(p.units), dim3(64 * wpb), lds, s, p, f, bgm);
             break;
         default:
@@ -641,7 +659,7 @@ static void launch_staged(const FuseParams &p, const Filters &f, int wpb, size_t
 
 // KR = 0: rolling over p.seg_rows rows; KR = 1, 2: one-shot tile (seg_rows == KR).
 // WAV = 0 Haar, 1 D4, -1 read from p.wavelet (batched launches mix wavelets).
-template <int NC, bool AL, int KR, int WAV = -1>
+template <int NC, int AL, int KR, int WAV = -1>
 __device__ __forceinline__ void run_unit(const FuseParams &p, const Filters &f, int unit, int lane) {
     int strip, seg;
     unit_coords(unit, p.nstrips, p.nseg, p.order, strip, seg);
@@ -663,7 +681,7 @@ __device__ __forceinline__ void run_unit(const FuseParams &p, const Filters &f, 
 
 // One scene: one wavefront per work unit.  Specialised per wavelet so each
 // gets its own register allocation.
-template <int WAV, int NC, bool AL, int KR>
+template <int WAV, int NC, int AL, int KR>
 __global__ __launch_bounds__(256) void fuse_kernel(FuseParams p, Filters f) {
     const int wpb = blockDim.x >> 6;
     const int lane = threadIdx.x & 63;
@@ -680,6 +698,9 @@ static void launch_path_w(const FuseParams &p, const Filters &f, int grid, dim3 
             break;
         case PATH_V2:
             hipLaunchKernelGGL((fuse_kernel<WAV, 1, true, KR>), dim3(grid), block, 0, s, p, f);
+            break;
+        case PATH_V2W:
+            hipLaunchKernelGGL((fuse_kernel<WAV, 2, 2, KR>), dim3(grid), block, 0, s, p, f);
             break;
         default:
             hipLaunchKernelGGL((fuse_kernel<WAV, 1, false, KR>), dim3(grid), block, 0, s, p, f);
@@ -778,6 +799,9 @@ __global__ __launch_bounds__(256) void fuse_batched_kernel(const BatchScene *__r
                 case PATH_V2:
                     run_unit<1, true, KR>(p, f, unit, lane);
                     break;
+                case PATH_V2W:
+                    run_unit<2, 2, KR>(p, f, unit, lane);
+                    break;
                 default:
                     run_unit<1, false, KR>(p, f, unit, lane);
                     break;
@@ -846,7 +870,7 @@ __global__ __launch_bounds__(256) void fuse_batched_flat_kernel(const BatchScene
     if (p.mode >= 3) {
         if (p.path == PATH_V4)
             d4_staged_tile<2, 0>(p, f, bg_max, item, lds, 4, 0, p.B);
-        else if (p.path == PATH_V2)
+        else if (p.path == PATH_V2 || p.path == PATH_V2W)
             d4_staged_tile<2, 3>(p, f, bg_max, item, lds, 4, 0, p.B);
         else
             d4_staged_tile<2, 2>(p, f, bg_max, item, lds, 4, 0, p.B);
@@ -861,6 +885,9 @@ __global__ __launch_bounds__(256) void fuse_batched_flat_kernel(const BatchScene
             break;
         case PATH_V2:
             run_unit<1, true, 1>(p, f, unit, lane);
+            break;
+        case PATH_V2W:
+            run_unit<2, 2, 1>(p, f, unit, lane);
             break;
         default:
             run_unit<1, false, 1>(p, f, unit, lane);

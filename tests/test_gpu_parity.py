@@ -138,6 +138,39 @@ def test_tile_shapes_give_identical_results(dev, fz, wavelet, H, W):
 
 
 @pytest.mark.parametrize("wavelet", ["haar", "d4"])
+@pytest.mark.parametrize("H,W", [(66, 1032), (34, 70), (10, 516)])
+@pytest.mark.parametrize("ms_pad,ms_off", [(0, 0), (1, 1), (2, 2)])
+def test_tile_shapes_on_8_byte_rows(dev, fz, oracle, wavelet, H, W, ms_pad, ms_off):
+    """PAN/out rows with an even pitch that is not a multiple of 4 floats are
+    8-byte aligned, every other one also 16-byte aligned; the first row here
+    starts 8 bytes past a 16-byte boundary.  Two coefficient columns per lane
+    then take 16-byte accesses on the aligned rows and 8-byte ones on the
+    others, and MS rows 8-byte pairs where their alignment allows.  Every
+    forced shape must equal the contiguous call bit for bit."""
+    rng = np.random.default_rng(H + W + ms_pad)
+    pan, ms = int_scene(rng, H, W, 3)
+    base = fz.fuse(to_dev(pan, dev), to_dev(ms, dev), wavelet).cpu().numpy()
+    pad = 2 if W % 4 == 0 else 0  # pitch = 2 (mod 4)
+    pv = strided_view(pan, dev, pad, 2)
+    mv = strided_view(ms, dev, ms_pad, ms_off)
+    ctx = fz.context(dev)
+    try:
+        for seg, wpb, nc, var in [(0, 0, 0, 0), (1, 1, 2, 1), (3, 2, 2, 1), (5, 4, 1, 1), (1, 1, 2, 2),
+                                  (2, 4, 2, 2), (2, 4, 1, 2), (2, 4, 2, 3)]:
+            say(wavelet, "8-byte rows", H, W, "ms", ms_pad, ms_off, "tile", seg, wpb, nc, var)
+            ctx.force_tile(seg, wpb, nc, var)
+            ov = strided_view(np.zeros((3, H, W), np.float32), dev, pad, 2)
+            fz.fuse(pv, mv, wavelet, out=ov)
+            assert np.array_equal(ov.cpu().numpy(), base)
+    finally:
+        ctx.force_tile(0, 0, 0, 0)
+    if wavelet == "haar":
+        assert np.array_equal(base, oracle_out(oracle, "haar", pan, ms).astype(np.float32))
+    else:
+        assert np.abs(base - oracle_out(oracle, "d4", pan, ms)).max() <= D4_TOL
+
+
+@pytest.mark.parametrize("wavelet", ["haar", "d4"])
 def test_cyclic_shift_equivariance(dev, fz, wavelet):
     """Shifting PAN by (2r, 2c) and MS by (r, c) shifts the output by (2r, 2c):
     pins the periodic wrap without the oracle."""
