@@ -147,12 +147,58 @@ def cpu_baseline(pan_d, ms_d, wavelet, budget_s=8.0, max_passes=6):
         passes += 1
     return {"value": passes * px / total / 1e6, "unit": "Mpix/s", "cores": 1, "kind": "oracle",
             "sample": "%d whole passes over the workload (same inputs) of the FP64 oracle, 1 thread, %.1f s"
-                      % (passes, total)}
+                      % (passes, total),
+            "host": {"cpu": cpu_model(), "logical_cpus": os.cpu_count()}}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def launch_stats(torch, fn, n, flush=None):
+    """Per-launch kernel times (ms) from an event pair around each launch on
+    the current stream.  With `flush` (a device buffer larger than the L2 and
+    the Infinity Cache together), the buffer is read before each launch, so
+    that no input is left in a cache and no dirty line of the previous launch
+    is left to be written back during the timed one (a write would leave its
+    own dirty lines behind instead)."""
+    s = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+    fn()
+    for e0, e1 in ev:
+        if flush is not None:
+            flush.sum()
+        e0.record(s)
+        fn()
+        e1.record(s)
+    torch.cuda.synchronize()
+    t = sorted(e0.elapsed_time(e1) for e0, e1 in ev)
+    return {"median_ms": t[len(t) // 2], "min_ms": t[0], "max_ms": t[-1], "launches": n}
 
 
 def extras(torch, api, synth, steps, warmup):
     out = {}
     dev = torch.device("cuda:0")
+    # Primary workload launch by launch: back to back, and with every input
+    # and output evicted from the caches before each launch.
+    wl = synth.d4_8192()
+    pan, ms = wl.make(device=dev)
+    o = torch.empty((wl.B, wl.H, wl.W), device=dev)
+    call = Prepared(api, pan, ms, wl.wavelet, o)
+    flush = torch.ones(1 << 27, device=dev)  # 512 MiB
+    n = max(10, steps // 2)
+    out["primary_per_launch"] = {"back_to_back": launch_stats(torch, call, n),
+                                 "cache_flushed": launch_stats(torch, call, n, flush)}
+    log("primary per launch", out["primary_per_launch"])
+    del pan, ms, o, call, flush
+    torch.cuda.empty_cache()
     # Haar 512x512, 1 band: launch-latency bound (fits in cache); Mpix/s only.
     wl = synth.haar_512()
     pan, ms = wl.make(device=dev)
@@ -317,6 +363,12 @@ def extras(torch, api, synth, steps, warmup):
     return out
 
 
+def device_info(torch):
+    p = torch.cuda.get_device_properties(0)
+    return {"name": p.name, "arch": getattr(p, "gcnArchName", None), "compute_units": p.multi_processor_count,
+            "hbm_GiB": round(p.total_memory / 2**30, 1), "hip": torch.version.hip}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -383,6 +435,7 @@ def main():
         "data": "synthetic (seeded blob/rectangle/noise scenes, uint8-valued float32)",
         "config": {"workload": wl.name, "wavelet": "d4", "H": wl.H, "W": wl.W, "bands": wl.B,
                    "parallelism": "single GPU"},
+        "device": device_info(torch),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": read_traffic(nbytes),
                      "algorithmic_bytes_per_launch": nbytes},
