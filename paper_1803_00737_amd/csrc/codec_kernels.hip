@@ -36,6 +36,15 @@ __device__ __forceinline__ int wrap_near(int q, int n) {
     return q >= n ? q - n : q;
 }
 
+// q mod n for a row index that is the same on every lane of the wavefront
+// and lies within a few n of [0, n) (n >= 1): a short scalar loop, no
+// integer divide.
+__device__ __forceinline__ int wrap_row(int q, int n) {
+    while (q < 0) q += n;
+    while (q >= n) q -= n;
+    return q;
+}
+
 // 8-bit code of a fused value: nearest integer, ties to even, clamped to
 // [0, 255], NaN -> 0.  The gfx950 float-to-packed-byte conversion does
 // exactly this in one instruction per pixel (rounding in the default
@@ -231,10 +240,8 @@ __device__ __forceinline__ void d4_codec_tile(const CodecParams &p, const Filter
     const int rb = seg * KR;
     const int nr = min(KR, H2 - rb);
     constexpr int NR = 2 * KR + 4;  // PAN rows 2rb-2 .. 2rb+2KR+1
-    // Rows lie in [-2, H + 2KR - 1] and [-1, H2 + KR - 1]: a compare/select
-    // wrap suffices unless the image is only a few rows high.
-    const bool near = p.H > 2 * KR + 4;
-    auto wrow = [&](int y, int n) { return near ? wrap_near(y, n) : wrap_idx(y, n); };
+    // Rows lie in [-2, H + 2KR - 1] and [-1, H2 + KR - 1].
+    auto wrow = [](int y, int n) { return wrap_row(y, n); };
     f2 x[NR][NC + 2];
 #pragma unroll
     for (int k = 0; k < NR; ++k) L.load_row(pan + (int64_t)wrow(2 * rb - 2 + k, p.H) * p.pan_ld, x[k]);
@@ -429,7 +436,10 @@ template <typename TI, typename TO, int NC, int KR, bool AL, int WAV>
 __global__ __launch_bounds__(256) void codec_kernel(CodecParams p, Filters f) {
     const int wpb = blockDim.x >> 6;
     const int lane = threadIdx.x & 63;
-    const int unit = xcd_remap(blockIdx.x, gridDim.x) * wpb + (threadIdx.x >> 6);
+    // The wavefront's index is the same on all its lanes; saying so keeps the
+    // unit's row and column bookkeeping in scalar registers.
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int unit = xcd_remap(blockIdx.x, gridDim.x) * wpb + wave;
     if (unit >= p.units) return;  // whole wavefront; no barriers in this kernel
     int strip, seg;
     if (p.order) {
