@@ -188,6 +188,35 @@ dwt_fuse_status dwt_fuse_backward(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet,
                                   const float *grad_out, int64_t go_ld, int64_t go_band_stride,
                                   float *grad_pan, float *grad_ms, float *grad_gain);
 
+/* One scene of a batched backward; fields as in dwt_fuse_backward (grad_pan
+ * H x W and grad_ms B x H/2 x W/2 contiguous; each output may be NULL). */
+typedef struct {
+    int32_t wavelet; /* dwt_fuse_wavelet */
+    int32_t B;
+    int64_t H, W;
+    const float *pan;
+    const float *gain; /* NULL = all ones */
+    const float *grad_out;
+    float *grad_pan, *grad_ms, *grad_gain;
+    int64_t pan_ld, go_ld, go_band_stride;
+} dwt_fuse_bwd_item;
+
+/* dwt_fuse_backward of n independent scenes (any sizes, band counts and
+ * wavelets; the adjoint of a dwt_fuse_run_batched call, for instance) with
+ * one adjoint launch per kernel variant present in the batch (scenes of the
+ * same variant share a launch, so small scenes fill the GPU together) and
+ * one launch for every grad_gain reduction.  Each scene gets the work units
+ * dwt_fuse_backward would give it on this context, so its results are
+ * bit-identical to that call (the LDS-staged adjoint of forced variant 3 is
+ * not used here).  `items` is a HOST array of n descriptors (read during the
+ * call only); the pointers inside are device pointers.  Every item is
+ * validated as in dwt_fuse_backward (first failure returned, nothing
+ * launched); no output of any item may overlap any input or another output
+ * of any item.  n == 0 is a no-op.  Uses context workspace for the per-unit
+ * gain partials of all scenes and a context-owned scene table, grown on
+ * first use of a larger batch (DWT_FUSE_E_NOMEM on failure). */
+dwt_fuse_status dwt_fuse_backward_batched(dwt_fuse_ctx *ctx, const dwt_fuse_bwd_item *items, int64_t n);
+
 /* The paper's own GPU pipeline, kept as a comparator for dwt_fuse_run
  * (section 3, the per-channel step list): for each band, PAN is copied into a
  * working array, then full-image passes run one after another -- forward 1D
@@ -222,6 +251,7 @@ dwt_fuse_status dwt_fuse_check_quality(int64_t H, int64_t W, int64_t B,
                                        const float *ref, int64_t ref_ld, int64_t ref_band_stride,
                                        const double *out);
 dwt_fuse_status dwt_fuse_check_batched(const dwt_fuse_item *items, int64_t n);
+dwt_fuse_status dwt_fuse_check_backward_batched(const dwt_fuse_bwd_item *items, int64_t n);
 dwt_fuse_status dwt_fuse_check_backward(dwt_fuse_wavelet wavelet, int64_t H, int64_t W, int64_t B,
                                         const float *pan, int64_t pan_ld, const float *gain,
                                         const float *grad_out, int64_t go_ld, int64_t go_band_stride,

@@ -22,7 +22,7 @@ EXPORTS = (
     "dwt_fuse_check_backward", "dwt_fuse_status_str", "dwt_fuse_last_error", "dwt_fuse_set_tuning",
     "dwt_fuse_tune_save", "dwt_fuse_tune_load", "dwt_fuse_force_tile", "dwt_fuse_run_multipass",
     "dwt_fuse_run_ex", "dwt_fuse_check_run_ex", "dwt_fuse_quality", "dwt_fuse_check_quality",
-    "dwt_fuse_force_band_split",
+    "dwt_fuse_force_band_split", "dwt_fuse_backward_batched", "dwt_fuse_check_backward_batched",
 )
 
 HAAR = 0
@@ -52,6 +52,18 @@ class Item(ctypes.Structure):
         ("pan", ctypes.c_void_p), ("ms", ctypes.c_void_p), ("gain", ctypes.c_void_p), ("out", ctypes.c_void_p),
         ("pan_ld", ctypes.c_int64), ("ms_ld", ctypes.c_int64), ("ms_band_stride", ctypes.c_int64),
         ("out_ld", ctypes.c_int64), ("out_band_stride", ctypes.c_int64),
+    ]
+
+
+class BwdItem(ctypes.Structure):
+    """dwt_fuse_bwd_item."""
+
+    _fields_ = [
+        ("wavelet", ctypes.c_int32), ("B", ctypes.c_int32),
+        ("H", ctypes.c_int64), ("W", ctypes.c_int64),
+        ("pan", ctypes.c_void_p), ("gain", ctypes.c_void_p), ("grad_out", ctypes.c_void_p),
+        ("grad_pan", ctypes.c_void_p), ("grad_ms", ctypes.c_void_p), ("grad_gain", ctypes.c_void_p),
+        ("pan_ld", ctypes.c_int64), ("go_ld", ctypes.c_int64), ("go_band_stride", ctypes.c_int64),
     ]
 
 
@@ -99,6 +111,10 @@ def load(require_torch: bool = True):
         lib.dwt_fuse_backward.restype = st
         lib.dwt_fuse_check_backward.argtypes = bwd_args
         lib.dwt_fuse_check_backward.restype = st
+        lib.dwt_fuse_backward_batched.argtypes = [vp, ctypes.POINTER(BwdItem), i64]
+        lib.dwt_fuse_backward_batched.restype = st
+        lib.dwt_fuse_check_backward_batched.argtypes = [ctypes.POINTER(BwdItem), i64]
+        lib.dwt_fuse_check_backward_batched.restype = st
         lib.dwt_fuse_status_str.argtypes = [st]
         lib.dwt_fuse_status_str.restype = ctypes.c_char_p
         lib.dwt_fuse_last_error.argtypes = [vp]

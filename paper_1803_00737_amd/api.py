@@ -15,7 +15,7 @@ from typing import List, Optional, Sequence
 import torch
 
 from . import _lib
-from ._lib import DwtFuseError, Item, wavelet_id
+from ._lib import BwdItem, DwtFuseError, Item, wavelet_id
 
 
 class Context:
@@ -273,10 +273,7 @@ def fuse_batched(scenes: Sequence[dict], graph: bool = False, device=None) -> Li
     return outs
 
 
-def fuse_backward(pan: torch.Tensor, grad_out: torch.Tensor, wavelet="d4", gain: Optional[torch.Tensor] = None,
-                  need_pan: bool = True, need_ms: bool = True, need_gain: bool = True):
-    """Transpose of ``fuse``: (grad_pan (H,W), grad_ms (B,H/2,W/2), grad_gain (B,))
-    for dLoss/d(out) = grad_out (B, H, W).  Entries not requested are None."""
+def _prep_backward(pan, grad_out, gain, need_pan, need_ms, need_gain):
     _require(pan, "pan", 2)
     if grad_out.dim() == 2:
         grad_out = grad_out.unsqueeze(0)
@@ -292,19 +289,74 @@ def fuse_backward(pan: torch.Tensor, grad_out: torch.Tensor, wavelet="d4", gain:
         gain = gain.contiguous()
         if gain.shape[0] != B:
             raise ValueError("gain must have B=%d entries" % B)
+        if gain.device != pan.device:
+            raise ValueError("gain must be on the device of pan")
     if grad_out.device != pan.device:
         raise ValueError("pan and grad_out must be on the same device")
     dev = pan.device
     gp = torch.empty((H, W), dtype=torch.float32, device=dev) if need_pan else None
     gm = torch.empty((B, H // 2, W // 2), dtype=torch.float32, device=dev) if need_ms else None
     gg = torch.empty((B,), dtype=torch.float32, device=dev) if need_gain else None
-    c = context(dev)
+    return pan, grad_out, gain, gp, gm, gg, H, W, B
+
+
+def fuse_backward(pan: torch.Tensor, grad_out: torch.Tensor, wavelet="d4", gain: Optional[torch.Tensor] = None,
+                  need_pan: bool = True, need_ms: bool = True, need_gain: bool = True):
+    """Transpose of ``fuse``: (grad_pan (H,W), grad_ms (B,H/2,W/2), grad_gain (B,))
+    for dLoss/d(out) = grad_out (B, H, W).  Entries not requested are None."""
+    pan, grad_out, gain, gp, gm, gg, H, W, B = _prep_backward(pan, grad_out, gain, need_pan, need_ms, need_gain)
+    c = context(pan.device)
     c.bind_stream()
     st = c.lib.dwt_fuse_backward(c.handle, wavelet_id(wavelet), H, W, B, _ptr(pan), _pitch(pan, 0), _ptr(gain),
                                  _ptr(grad_out), _pitch(grad_out, 1), _pitch(grad_out, 0),
                                  _ptr(gp), _ptr(gm), _ptr(gg))
     c.check(st, "dwt_fuse_backward")
     return gp, gm, gg
+
+
+def make_bwd_items(scenes: Sequence[dict]):
+    """Prepare dwt_fuse_bwd_item descriptors; each scene is a dict with keys
+    pan, grad_out, wavelet and optionally gain, need_pan, need_ms, need_gain
+    (default True).  Returns (items array, [(grad_pan, grad_ms, grad_gain)],
+    keep)."""
+    n = len(scenes)
+    arr = (BwdItem * max(n, 1))()
+    outs, keep = [], []
+    for i, s in enumerate(scenes):
+        pan, go, gain, gp, gm, gg, H, W, B = _prep_backward(s["pan"], s["grad_out"], s.get("gain"),
+                                                           s.get("need_pan", True), s.get("need_ms", True),
+                                                           s.get("need_gain", True))
+        keep.extend([pan, go, gain])
+        outs.append((gp, gm, gg))
+        it = arr[i]
+        it.wavelet = wavelet_id(s.get("wavelet", "d4"))
+        it.B = B
+        it.H = H
+        it.W = W
+        it.pan = pan.data_ptr()
+        it.gain = gain.data_ptr() if gain is not None else None
+        it.grad_out = go.data_ptr()
+        it.grad_pan = gp.data_ptr() if gp is not None else None
+        it.grad_ms = gm.data_ptr() if gm is not None else None
+        it.grad_gain = gg.data_ptr() if gg is not None else None
+        it.pan_ld = _pitch(pan, 0)
+        it.go_ld = _pitch(go, 1)
+        it.go_band_stride = _pitch(go, 0)
+    return arr, outs, keep
+
+
+def fuse_backward_batched(scenes: Sequence[dict], device=None):
+    """``fuse_backward`` of many independent scenes (dicts as in
+    ``make_bwd_items``) with one launch per adjoint kernel variant.  Returns
+    [(grad_pan, grad_ms, grad_gain)] per scene; entries not requested are
+    None."""
+    if len(scenes) == 0:
+        return []
+    arr, outs, keep = make_bwd_items(scenes)
+    c = context(device if device is not None else scenes[0]["pan"].device)
+    c.bind_stream()
+    c.check(c.lib.dwt_fuse_backward_batched(c.handle, arr, len(scenes)), "dwt_fuse_backward_batched")
+    return outs
 
 
 class DwtFuseFn(torch.autograd.Function):

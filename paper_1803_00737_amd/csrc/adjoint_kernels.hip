@@ -711,90 +711,86 @@ __device__ __forceinline__ void haar_adj_unit(const AdjParams &p, int strip, int
     }
 }
 
-template <int NC, bool AL>
+__device__ __forceinline__ void unit_strip_seg(const AdjParams &p, int unit, int &strip, int &seg) {
+    if (p.order) {
+        seg = unit / p.nstrips;
+        strip = unit - seg * p.nstrips;
+    } else {
+        strip = unit / p.nseg;
+        seg = unit - strip * p.nseg;
+    }
+}
+
+// One work unit of each adjoint variant, by one wavefront; `acc` is the
+// lane's slot in a block-wide LDS array of nb * 256 floats.  The unit's
+// per-band gain products go to p.partial[unit * p.pstride + b].
+//   KIND 0: rolling, any wavelet, p.B <= kAdjMaxBands (X unused)
+//   KIND 1: rolling D4 with the band loop unrolled, p.B == X <= 4
+//   KIND 2: one-shot D4 tile of X = p.seg_rows coefficient rows
+template <int KIND, int NC, bool AL, int X>
+__device__ __forceinline__ void adj_unit(const AdjParams &p, const Filters &f, int unit, int lane, float *acc) {
+    const int nb = KIND == 1 ? X : p.B;
+    for (int b = 0; b < nb; ++b) acc[b * 256] = 0.f;
+    int strip, seg;
+    unit_strip_seg(p, unit, strip, seg);
+    if constexpr (KIND == 0) {
+        if (p.wavelet == 1)
+            d4_adj_unit<NC, AL>(p, f, strip, seg, lane, acc, 256);
+        else
+            haar_adj_unit<NC, AL>(p, strip, seg, lane, acc, 256);
+    } else if constexpr (KIND == 1) {
+        d4_adj_unit_bg<NC, AL, X>(p, f, strip, seg, lane, acc, 256);
+    } else {
+        d4_adj_tile<NC, AL, X>(p, f, strip, seg, lane, acc, 256);
+    }
+    if (p.partial) {
+        for (int b = 0; b < nb; ++b) {
+            const float s = wave_sum(acc[b * 256]);
+            if (lane == 0) p.partial[(int64_t)unit * p.pstride + b] = s;
+        }
+    }
+}
+
+template <int KIND>
+constexpr int adj_lds_bands() {
+    return KIND == 1 ? 4 : kAdjMaxBands;
+}
+
+// One scene: one wavefront per work unit.
+template <int KIND, int NC, bool AL, int X>
 __global__ __launch_bounds__(256) void adjoint_kernel(AdjParams p, Filters f) {
-    __shared__ float acc_lds[kAdjMaxBands * 256];
+    __shared__ float acc_lds[adj_lds_bands<KIND>() * 256];
     const int wpb = blockDim.x >> 6;
     const int lane = threadIdx.x & 63;
     const int unit = xcd_remap(blockIdx.x, gridDim.x) * wpb + (threadIdx.x >> 6);
     if (unit >= p.units) return;  // whole wavefront leaves together
-    float *acc = acc_lds + threadIdx.x;
-    for (int b = 0; b < p.B; ++b) acc[b * 256] = 0.f;
-    int strip, seg;
-    if (p.order) {
-        seg = unit / p.nstrips;
-        strip = unit - seg * p.nstrips;
-    } else {
-        strip = unit / p.nseg;
-        seg = unit - strip * p.nseg;
-    }
-    if (p.wavelet == 1)
-        d4_adj_unit<NC, AL>(p, f, strip, seg, lane, acc, 256);
-    else
-        haar_adj_unit<NC, AL>(p, strip, seg, lane, acc, 256);
-    if (p.partial) {
-        for (int b = 0; b < p.B; ++b) {
-            const float s = wave_sum(acc[b * 256]);
-            if (lane == 0) p.partial[(int64_t)unit * p.pstride + b] = s;
-        }
-    }
+    adj_unit<KIND, NC, AL, X>(p, f, unit, lane, acc_lds + threadIdx.x);
 }
 
-// Rolling D4 adjoint for a band group of BG = p.B <= 4 bands (one launch,
-// no accumulation into grad_pan).
-template <int NC, bool AL, int BG>
-__global__ __launch_bounds__(256) void adjoint_bg_kernel(AdjParams p, Filters f) {
-    __shared__ float acc_lds[4 * 256];
-    const int wpb = blockDim.x >> 6;
-    const int lane = threadIdx.x & 63;
-    const int unit = xcd_remap(blockIdx.x, gridDim.x) * wpb + (threadIdx.x >> 6);
-    if (unit >= p.units) return;  // whole wavefront leaves together
-    float *acc = acc_lds + threadIdx.x;
-#pragma unroll
-    for (int b = 0; b < BG; ++b) acc[b * 256] = 0.f;
-    int strip, seg;
-    if (p.order) {
-        seg = unit / p.nstrips;
-        strip = unit - seg * p.nstrips;
-    } else {
-        strip = unit / p.nseg;
-        seg = unit - strip * p.nseg;
+// Many scenes of one variant: workgroups of 4 wavefronts, wavefront u of the
+// launch takes unit u - unit_begin of the scene whose range holds u.
+__device__ __forceinline__ int find_adj_scene(const AdjScene *sc, int n, int u) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (sc[mid].unit_begin <= u)
+            lo = mid;
+        else
+            hi = mid - 1;
     }
-    d4_adj_unit_bg<NC, AL, BG>(p, f, strip, seg, lane, acc, 256);
-    if (p.partial) {
-#pragma unroll
-        for (int b = 0; b < BG; ++b) {
-            const float s = wave_sum(acc[b * 256]);
-            if (lane == 0) p.partial[(int64_t)unit * p.pstride + b] = s;
-        }
-    }
+    return lo;
 }
 
-// One-shot D4 adjoint tiles of KR coefficient rows (p.seg_rows == KR).
-template <int NC, bool AL, int KR>
-__global__ __launch_bounds__(256) void adjoint_tile_kernel(AdjParams p, Filters f) {
-    __shared__ float acc_lds[kAdjMaxBands * 256];
-    const int wpb = blockDim.x >> 6;
+template <int KIND, int NC, bool AL, int X>
+__global__ __launch_bounds__(256) void adjoint_batched_kernel(const AdjScene *__restrict__ scenes, int nscenes,
+                                                              int total, Filters f) {
+    __shared__ float acc_lds[adj_lds_bands<KIND>() * 256];
     const int lane = threadIdx.x & 63;
-    const int unit = xcd_remap(blockIdx.x, gridDim.x) * wpb + (threadIdx.x >> 6);
-    if (unit >= p.units) return;  // whole wavefront leaves together
-    float *acc = acc_lds + threadIdx.x;
-    for (int b = 0; b < p.B; ++b) acc[b * 256] = 0.f;
-    int strip, seg;
-    if (p.order) {
-        seg = unit / p.nstrips;
-        strip = unit - seg * p.nstrips;
-    } else {
-        strip = unit / p.nseg;
-        seg = unit - strip * p.nseg;
-    }
-    d4_adj_tile<NC, AL, KR>(p, f, strip, seg, lane, acc, 256);
-    if (p.partial) {
-        for (int b = 0; b < p.B; ++b) {
-            const float s = wave_sum(acc[b * 256]);
-            if (lane == 0) p.partial[(int64_t)unit * p.pstride + b] = s;
-        }
-    }
+    const int u = xcd_remap(blockIdx.x, gridDim.x) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (u >= total) return;  // whole wavefront leaves together
+    const int si = find_adj_scene(scenes, nscenes, u);
+    const AdjParams p = scenes[si].p;
+    adj_unit<KIND, NC, AL, X>(p, f, u - scenes[si].unit_begin, lane, acc_lds + threadIdx.x);
 }
 
 // grad_gain[b] = sum over units of partial[unit * pstride + b], in FP64 with
@@ -812,6 +808,22 @@ __global__ __launch_bounds__(256) void gain_reduce_kernel(const float *partial, 
         __syncthreads();
     }
     if (threadIdx.x == 0) grad_gain[b] = (float)sh[0];
+}
+
+// One workgroup per (scene, band) job: the same sum, order and rounding as
+// gain_reduce_kernel on that scene alone.
+__global__ __launch_bounds__(256) void gain_reduce_batched_kernel(const GainJob *__restrict__ jobs) {
+    __shared__ double sh[256];
+    const GainJob j = jobs[blockIdx.x];
+    double a = 0.0;
+    for (int u = threadIdx.x; u < j.units; u += 256) a += (double)j.partial[(int64_t)u * j.pstride + j.band];
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) j.grad_gain[j.band] = (float)sh[0];
 }
 
 // ---- D4 adjoint, LDS-staged workgroup tile (16-byte rows) -------------------
@@ -1052,13 +1064,13 @@ hipError_t launch_adjoint(const AdjParams &p, const Filters &f, int wpb, hipStre
     const dim3 block(64 * wpb);
     switch (p.path) {
         case PATH_V4:
-            hipLaunchKernelGGL((adjoint_kernel<2, true>), dim3(grid), block, 0, s, p, f);
+            hipLaunchKernelGGL((adjoint_kernel<0, 2, true, 0>), dim3(grid), block, 0, s, p, f);
             break;
         case PATH_V2:
-            hipLaunchKernelGGL((adjoint_kernel<1, true>), dim3(grid), block, 0, s, p, f);
+            hipLaunchKernelGGL((adjoint_kernel<0, 1, true, 0>), dim3(grid), block, 0, s, p, f);
             break;
         default:
-            hipLaunchKernelGGL((adjoint_kernel<1, false>), dim3(grid), block, 0, s, p, f);
+            hipLaunchKernelGGL((adjoint_kernel<0, 1, false, 0>), dim3(grid), block, 0, s, p, f);
             break;
     }
     return hipGetLastError();
@@ -1070,7 +1082,7 @@ hipError_t launch_adjoint_bg(const AdjParams &p, const Filters &f, int wpb, hipS
         return hipErrorInvalidValue;
     const int grid = (p.units + wpb - 1) / wpb;
     const dim3 block(64 * wpb);
-#define ADJ_BG(NC, AL, BG) hipLaunchKernelGGL((adjoint_bg_kernel<NC, AL, BG>), dim3(grid), block, 0, s, p, f)
+#define ADJ_BG(NC, AL, BG) hipLaunchKernelGGL((adjoint_kernel<1, NC, AL, BG>), dim3(grid), block, 0, s, p, f)
 #define ADJ_BG_PATH(BG)                                   \
     do {                                                  \
         if (p.path == PATH_V4) ADJ_BG(2, true, BG);       \
@@ -1095,7 +1107,7 @@ hipError_t launch_adjoint_tile(const AdjParams &p, const Filters &f, int kr, int
         return hipErrorInvalidValue;
     const int grid = (p.units + wpb - 1) / wpb;
     const dim3 block(64 * wpb);
-#define ADJ_TILE(NC, AL, KR) hipLaunchKernelGGL((adjoint_tile_kernel<NC, AL, KR>), dim3(grid), block, 0, s, p, f)
+#define ADJ_TILE(NC, AL, KR) hipLaunchKernelGGL((adjoint_kernel<2, NC, AL, KR>), dim3(grid), block, 0, s, p, f)
     if (kr == 1) {
         if (p.path == PATH_V4) ADJ_TILE(2, true, 1);
         else if (p.path == PATH_V2) ADJ_TILE(1, true, 1);
@@ -1108,6 +1120,44 @@ hipError_t launch_adjoint_tile(const AdjParams &p, const Filters &f, int kr, int
         return hipErrorInvalidValue;
     }
 #undef ADJ_TILE
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_batched(const AdjScene *d_scenes, int nscenes, int total, int kind, int path, int x,
+                                  const Filters &f, hipStream_t s) {
+    if (nscenes <= 0 || total <= 0) return hipSuccess;
+    if (path == PATH_V2W || kind < 0 || kind > 2) return hipErrorInvalidValue;
+    if ((kind == 1 && (x < 1 || x > 4)) || (kind == 2 && x != 1 && x != 2)) return hipErrorInvalidValue;
+    const dim3 grid((total + 3) / 4), block(256);
+#define ADJ_B(K, NC, AL, X) \
+    hipLaunchKernelGGL((adjoint_batched_kernel<K, NC, AL, X>), grid, block, 0, s, d_scenes, nscenes, total, f)
+#define ADJ_B_PATH(K, X)                                  \
+    do {                                                  \
+        if (path == PATH_V4) ADJ_B(K, 2, true, X);        \
+        else if (path == PATH_V2) ADJ_B(K, 1, true, X);   \
+        else ADJ_B(K, 1, false, X);                       \
+    } while (0)
+    if (kind == 0) {
+        ADJ_B_PATH(0, 0);
+    } else if (kind == 1) {
+        switch (x) {
+            case 1: ADJ_B_PATH(1, 1); break;
+            case 2: ADJ_B_PATH(1, 2); break;
+            case 3: ADJ_B_PATH(1, 3); break;
+            default: ADJ_B_PATH(1, 4); break;
+        }
+    } else {
+        if (x == 1) ADJ_B_PATH(2, 1);
+        else ADJ_B_PATH(2, 2);
+    }
+#undef ADJ_B_PATH
+#undef ADJ_B
+    return hipGetLastError();
+}
+
+hipError_t launch_gain_reduce_batched(const GainJob *d_jobs, int njobs, hipStream_t s) {
+    if (njobs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gain_reduce_batched_kernel, dim3(njobs), dim3(256), 0, s, d_jobs);
     return hipGetLastError();
 }
 

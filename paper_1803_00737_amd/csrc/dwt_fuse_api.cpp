@@ -16,6 +16,7 @@
 #include <map>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "fuse_internal.h"
@@ -209,7 +210,13 @@ struct BwdArgs {
     const float *grad_pan, *grad_ms, *grad_gain;
 };
 
-dwt_fuse_status check_bwd_args(const BwdArgs &a, std::string *err) {
+// Byte ranges of a backward call's inputs and (possibly empty) outputs.
+struct BwdSpans {
+    Span pan, gy, gain;
+    Span outs[3];  // grad_pan, grad_ms, grad_gain
+};
+
+dwt_fuse_status check_bwd_args(const BwdArgs &a, std::string *err, BwdSpans *sp = nullptr) {
     if (!a.pan || !a.gy) {
         if (err) *err = "pan and grad_out must not be NULL";
         return DWT_FUSE_E_NULL;
@@ -243,6 +250,79 @@ dwt_fuse_status check_bwd_args(const BwdArgs &a, std::string *err) {
                 if (err) *err = "gradient outputs overlap each other";
                 return DWT_FUSE_E_ALIAS;
             }
+    }
+    if (sp) {
+        sp->pan = pan;
+        sp->gy = gy;
+        sp->gain = gain;
+        for (int i = 0; i < 3; ++i) sp->outs[i] = outs[i];
+    }
+    return DWT_FUSE_OK;
+}
+
+BwdArgs bwd_item_args(const dwt_fuse_bwd_item &it) {
+    return BwdArgs{it.wavelet, it.H,       it.W,        it.B,       it.pan,      it.pan_ld,   it.gain,
+                   it.grad_out, it.go_ld, it.go_band_stride, it.grad_pan, it.grad_ms, it.grad_gain};
+}
+
+// True if any two spans of `v` overlap (empty spans never do).
+bool any_overlap(std::vector<Span> v) {
+    v.erase(std::remove_if(v.begin(), v.end(), [](const Span &x) { return x.lo == x.hi; }), v.end());
+    std::sort(v.begin(), v.end(), [](const Span &a, const Span &b) { return a.lo < b.lo; });
+    for (size_t i = 1; i < v.size(); ++i)
+        if (v[i].lo < v[i - 1].hi) return true;
+    return false;
+}
+
+dwt_fuse_status check_bwd_batch(const dwt_fuse_bwd_item *items, int64_t n, std::string *err) {
+    if (n < 0) {
+        if (err) *err = "n < 0";
+        return DWT_FUSE_E_SHAPE;
+    }
+    if (n == 0) return DWT_FUSE_OK;
+    if (!items) {
+        if (err) *err = "items is NULL";
+        return DWT_FUSE_E_NULL;
+    }
+    if (n > (int64_t(1) << 24)) {
+        if (err) *err = "too many items";
+        return DWT_FUSE_E_SHAPE;
+    }
+    std::vector<Span> outs, ins;
+    outs.reserve(3 * n);
+    ins.reserve(3 * n);
+    for (int64_t i = 0; i < n; ++i) {
+        BwdSpans sp;
+        std::string e;
+        const dwt_fuse_status st = check_bwd_args(bwd_item_args(items[i]), &e, &sp);
+        if (st) {
+            if (err) *err = "item " + std::to_string(i) + ": " + e;
+            return st;
+        }
+        for (const Span &o : sp.outs)
+            if (o.lo != o.hi) outs.push_back(o);
+        ins.push_back(sp.pan);
+        ins.push_back(sp.gy);
+        if (sp.gain.lo != sp.gain.hi) ins.push_back(sp.gain);
+    }
+    if (any_overlap(outs)) {
+        if (err) *err = "gradient outputs of two items overlap";
+        return DWT_FUSE_E_ALIAS;
+    }
+    // No output overlaps any input (inputs may overlap each other).
+    std::sort(ins.begin(), ins.end(), [](const Span &a, const Span &b) { return a.lo < b.lo; });
+    std::vector<uintptr_t> pmax(ins.size());
+    uintptr_t m = 0;
+    for (size_t i = 0; i < ins.size(); ++i) pmax[i] = m = std::max(m, ins[i].hi);
+    for (const Span &o : outs) {
+        // inputs starting before o.hi; the furthest-reaching of them must end at or before o.lo
+        const size_t k = std::lower_bound(ins.begin(), ins.end(), o.hi,
+                                          [](const Span &a, uintptr_t v) { return a.lo < v; }) -
+                         ins.begin();
+        if (k > 0 && pmax[k - 1] > o.lo) {
+            if (err) *err = "a gradient output overlaps an input of another item";
+            return DWT_FUSE_E_ALIAS;
+        }
     }
     return DWT_FUSE_OK;
 }
@@ -475,6 +555,12 @@ struct dwt_fuse_ctx {
     bool staged_pending = false;
     std::map<std::string, hipGraphExec_t> graphs;
     hipStream_t cap_stream = nullptr;  // capture only (the null stream cannot be captured)
+    // batched backward: adjoint scene table and gain jobs (device + pinned staging)
+    void *d_bwd = nullptr;
+    void *h_bwd = nullptr;
+    size_t bwd_bytes = 0;
+    hipEvent_t bwd_staged = nullptr;  // last upload of h_bwd finished
+    bool bwd_pending = false;
 };
 
 namespace {
@@ -979,6 +1065,9 @@ void dwt_fuse_destroy(dwt_fuse_ctx *ctx) {
         if (ctx->h_scenes) (void)hipHostFree(ctx->h_scenes);
         if (ctx->d_counters) (void)hipFree(ctx->d_counters);
         if (ctx->staged) (void)hipEventDestroy(ctx->staged);
+        if (ctx->d_bwd) (void)hipFree(ctx->d_bwd);
+        if (ctx->h_bwd) (void)hipHostFree(ctx->h_bwd);
+        if (ctx->bwd_staged) (void)hipEventDestroy(ctx->bwd_staged);
         if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
         if (cur >= 0) (void)hipSetDevice(cur);
     } catch (...) {
@@ -1513,6 +1602,91 @@ static bool it_bwd_default(const dwt_fuse_ctx *ctx, const BwdArgs &a, Path path)
     return ctx->table.find(tune_key(1, a.wavelet, a.H, a.W, a.B, path)) == ctx->table.end();
 }
 
+// Work units of the rolling / one-shot adjoint of one scene (everything but
+// the LDS-staged form): tile, launch path, decomposition and kernel variant
+// (kind 0 rolling, 1 rolling D4 with x = B <= 4 bands unrolled, 2 one-shot
+// D4 tiles of x rows).
+struct BwdTile {
+    Tile t;
+    Path pp = PATH_SCALAR;
+    Decomp d;
+    int kind = 0, x = 0;
+};
+
+static bool plan_bwd(const dwt_fuse_ctx *ctx, const BwdArgs &a, Path path, BwdTile *out) {
+    const int64_t H = a.H, W = a.W, B = a.B;
+    Tile t = rolling_tile(H, W, path_nc(path));
+    {
+        auto it = ctx->table.find(tune_key(1, a.wavelet, H, W, B, path));
+        if (it != ctx->table.end()) t = it->second;
+    }
+    if (a.wavelet == DWT_FUSE_D4 && B <= 4 && ctx->forced.seg_rows == 0 && it_bwd_default(ctx, a, path)) {
+        // band-unrolled D4 adjoint: longest units (<= 32 rows) that still
+        // give >= 2048 units (measured best at 2048^2 .. 8192^2)
+        t.seg_rows = 32;
+        Decomp d0;
+        while (t.seg_rows > 4 && decompose(H, W, t, &d0) && d0.units < 2048) t.seg_rows /= 2;
+    }
+    t = apply_forced(ctx, t, path, a.wavelet, path_nc(path));
+    // Adjoint kernels: rolling units (mode 0) and, for D4, one-shot tiles of
+    // 1 or 2 rows (mode 1, 2); no LDS-staged form here.
+    if (t.mode != 0 && !(a.wavelet == DWT_FUSE_D4 && (t.mode == 1 || t.mode == 2))) {
+        const Tile r = rolling_tile(H, W, path_nc(path));
+        t.mode = 0;
+        t.seg_rows = r.seg_rows;
+        t.nc = std::min(t.nc, path_nc(path));
+        if (t.nc < 1) t.nc = r.nc;
+    }
+    if (t.mode == 1 || t.mode == 2) t.seg_rows = t.mode;
+    if (t.seg_rows < 1) t.seg_rows = 1;
+    if (t.nc > path_nc(path)) t.nc = path_nc(path);  // the adjoint has no mixed 64/128-bit form
+    out->t = t;
+    out->pp = path_for_nc(path, t.nc);
+    if (!decompose(H, W, t, &out->d)) return false;
+    // D4 with at most 4 bands: the rolling kernel with the band loop
+    // unrolled (unless the dynamic-band rolling kernel is forced).
+    if (t.mode != 0) {
+        out->kind = 2;
+        out->x = t.mode;
+    } else if (a.wavelet == DWT_FUSE_D4 && B <= 4 && ctx->forced.variant != 1) {
+        out->kind = 1;
+        out->x = (int)B;
+    } else {
+        out->kind = 0;
+        out->x = 0;
+    }
+    return true;
+}
+
+// Parameters of the adjoint launch over bands b0 .. b0 + min(maxb, B - b0) - 1
+// (later band groups add into grad_pan).
+static AdjParams bwd_params(const BwdArgs &a, const BwdTile &bt, float *partial, int64_t b0) {
+    const int64_t nb = std::min<int64_t>(adjoint_max_bands(), a.B - b0);
+    AdjParams p{};
+    p.pan = a.pan;
+    p.gain = a.gain ? a.gain + b0 : nullptr;
+    p.gy = a.gy + b0 * a.gy_bs;
+    p.grad_pan = const_cast<float *>(a.grad_pan);
+    p.grad_ms = a.grad_ms ? const_cast<float *>(a.grad_ms) + b0 * (a.H / 2) * (a.W / 2) : nullptr;
+    p.partial = partial ? partial + b0 : nullptr;
+    p.pan_ld = a.pan_ld;
+    p.gy_ld = a.gy_ld;
+    p.gy_bs = a.gy_bs;
+    p.H = (int32_t)a.H;
+    p.W = (int32_t)a.W;
+    p.B = (int32_t)nb;
+    p.seg_rows = bt.t.seg_rows;
+    p.nseg = bt.d.nseg;
+    p.units = bt.d.units;
+    p.wavelet = a.wavelet;
+    p.path = bt.pp;
+    p.nstrips = bt.d.nstrips;
+    p.order = bt.t.order;
+    p.pstride = (int32_t)a.B;
+    p.accumulate = b0 > 0 ? 1 : 0;
+    return p;
+}
+
 dwt_fuse_status dwt_fuse_backward(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet, int64_t H, int64_t W, int64_t B,
                                   const float *pan, int64_t pan_ld, const float *gain, const float *grad_out,
                                   int64_t go_ld, int64_t go_band_stride, float *grad_pan, float *grad_ms,
@@ -1575,75 +1749,168 @@ dwt_fuse_status dwt_fuse_backward(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet, i
             }
             return DWT_FUSE_OK;
         }
-        Tile t = rolling_tile(H, W, path_nc(path));
-        {
-            auto it = ctx->table.find(tune_key(1, a.wavelet, H, W, B, path));
-            if (it != ctx->table.end()) t = it->second;
-        }
-        if (a.wavelet == DWT_FUSE_D4 && B <= 4 && ctx->forced.seg_rows == 0 && it_bwd_default(ctx, a, path)) {
-            // band-unrolled D4 adjoint: longest units (<= 32 rows) that still
-            // give >= 2048 units (measured best at 2048^2 .. 8192^2)
-            t.seg_rows = 32;
-            Decomp d0;
-            while (t.seg_rows > 4 && decompose(H, W, t, &d0) && d0.units < 2048) t.seg_rows /= 2;
-        }
-        t = apply_forced(ctx, t, path, a.wavelet, path_nc(path));
-        // Adjoint kernels: rolling units (mode 0) and, for D4, one-shot tiles of
-        // 1 or 2 rows (mode 1, 2); no LDS-staged form here.
-        if (t.mode != 0 && !(a.wavelet == DWT_FUSE_D4 && (t.mode == 1 || t.mode == 2))) {
-            const Tile r = rolling_tile(H, W, path_nc(path));
-            t.mode = 0;
-            t.seg_rows = r.seg_rows;
-            t.nc = std::min(t.nc, path_nc(path));
-            if (t.nc < 1) t.nc = r.nc;
-        }
-        if (t.mode == 1 || t.mode == 2) t.seg_rows = t.mode;
-        if (t.seg_rows < 1) t.seg_rows = 1;
-        if (t.nc > path_nc(path)) t.nc = path_nc(path);  // the adjoint has no mixed 64/128-bit form
-        const Path pp = path_for_nc(path, t.nc);
-        Decomp d;
-        if (!decompose(H, W, t, &d)) return fail(ctx, DWT_FUSE_E_SHAPE, "too many work units");
+        BwdTile bt;
+        if (!plan_bwd(ctx, a, path, &bt)) return fail(ctx, DWT_FUSE_E_SHAPE, "too many work units");
         float *partial = nullptr;
         if (grad_gain) {
-            if ((st = ensure_ws(ctx, sizeof(float) * (size_t)d.units * (size_t)B))) return st;
+            if ((st = ensure_ws(ctx, sizeof(float) * (size_t)bt.d.units * (size_t)B))) return st;
             partial = ctx->ws;
         }
         const int maxb = adjoint_max_bands();
         for (int64_t b0 = 0; b0 < B; b0 += maxb) {
-            const int64_t nb = std::min<int64_t>(maxb, B - b0);
-            AdjParams p{};
-            p.pan = pan;
-            p.gain = gain ? gain + b0 : nullptr;
-            p.gy = grad_out + b0 * go_band_stride;
-            p.grad_pan = grad_pan;
-            p.grad_ms = grad_ms ? grad_ms + b0 * (H / 2) * (W / 2) : nullptr;
-            p.partial = partial ? partial + b0 : nullptr;
-            p.pan_ld = pan_ld;
-            p.gy_ld = go_ld;
-            p.gy_bs = go_band_stride;
-            p.H = (int32_t)H;
-            p.W = (int32_t)W;
-            p.B = (int32_t)nb;
-            p.seg_rows = t.seg_rows;
-            p.nseg = d.nseg;
-            p.units = d.units;
-            p.wavelet = a.wavelet;
-            p.path = pp;
-            p.nstrips = d.nstrips;
-            p.order = t.order;
-            p.pstride = (int32_t)B;
-            p.accumulate = b0 > 0 ? 1 : 0;
-            // D4 with at most 4 bands: the rolling kernel with the band loop
-            // unrolled (unless the dynamic-band rolling kernel is forced).
-            const bool bg = t.mode == 0 && a.wavelet == DWT_FUSE_D4 && B <= 4 && ctx->forced.variant != 1;
-            const hipError_t e = t.mode != 0 ? launch_adjoint_tile(p, ctx->filt, t.mode, t.wpb, ctx->stream)
-                                 : bg        ? launch_adjoint_bg(p, ctx->filt, t.wpb, ctx->stream)
-                                             : launch_adjoint(p, ctx->filt, t.wpb, ctx->stream);
+            const AdjParams p = bwd_params(a, bt, partial, b0);
+            const hipError_t e = bt.kind == 2   ? launch_adjoint_tile(p, ctx->filt, bt.x, bt.t.wpb, ctx->stream)
+                                 : bt.kind == 1 ? launch_adjoint_bg(p, ctx->filt, bt.t.wpb, ctx->stream)
+                                                : launch_adjoint(p, ctx->filt, bt.t.wpb, ctx->stream);
             if (e != hipSuccess) return hip_fail(ctx, e, "adjoint launch");
         }
         if (grad_gain) {
-            const hipError_t e = launch_gain_reduce(partial, d.units, (int)B, grad_gain, ctx->stream);
+            const hipError_t e = launch_gain_reduce(partial, bt.d.units, (int)B, grad_gain, ctx->stream);
             if (e != hipSuccess) return hip_fail(ctx, e, "gain reduction launch");
+        }
+        return DWT_FUSE_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(ctx, DWT_FUSE_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(ctx, DWT_FUSE_E_STATE, "unexpected exception");
+    }
+}
+
+dwt_fuse_status dwt_fuse_check_backward_batched(const dwt_fuse_bwd_item *items, int64_t n) {
+    return check_bwd_batch(items, n, nullptr);
+}
+
+namespace {
+
+// Grow the batched-backward tables to `bytes` (device and pinned staging).
+dwt_fuse_status ensure_bwd_tables(dwt_fuse_ctx *c, size_t bytes) {
+    if (!c->bwd_staged) {
+        const hipError_t e = hipEventCreateWithFlags(&c->bwd_staged, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            c->bwd_staged = nullptr;
+            return hip_fail(c, e, "hipEventCreate");
+        }
+    }
+    if (bytes <= c->bwd_bytes) return DWT_FUSE_OK;
+    (void)hipStreamSynchronize(c->stream);
+    if (c->d_bwd) (void)hipFree(c->d_bwd);
+    if (c->h_bwd) (void)hipHostFree(c->h_bwd);
+    c->d_bwd = nullptr;
+    c->h_bwd = nullptr;
+    c->bwd_bytes = 0;
+    c->bwd_pending = false;
+    const size_t cap = std::max<size_t>(bytes, 16384);
+    if (hipMalloc(&c->d_bwd, cap) != hipSuccess) {
+        c->d_bwd = nullptr;
+        return fail(c, DWT_FUSE_E_NOMEM, "backward scene table allocation failed");
+    }
+    if (hipHostMalloc(&c->h_bwd, cap, hipHostMallocDefault) != hipSuccess) {
+        c->h_bwd = nullptr;
+        return fail(c, DWT_FUSE_E_NOMEM, "pinned staging allocation failed");
+    }
+    c->bwd_bytes = cap;
+    return DWT_FUSE_OK;
+}
+
+// Adjoint launches of one kernel variant and band group.
+struct BwdGroup {
+    int kind, path, x, chunk;
+    std::vector<AdjScene> sc;
+    int64_t total = 0;
+};
+
+}  // namespace
+
+dwt_fuse_status dwt_fuse_backward_batched(dwt_fuse_ctx *ctx, const dwt_fuse_bwd_item *items, int64_t n) {
+    if (!ctx) return DWT_FUSE_E_NULL;
+    try {
+        std::string err;
+        dwt_fuse_status st = check_bwd_batch(items, n, &err);
+        if (st) return fail(ctx, st, err);
+        if (n == 0) return DWT_FUSE_OK;
+        if ((st = use_device(ctx))) return st;
+        // Plan every scene as dwt_fuse_backward would (without the staged form),
+        // then group the launches by kernel variant and band group.
+        std::vector<BwdTile> tiles((size_t)n);
+        std::vector<int64_t> poff((size_t)n, -1);  // float offset of a scene's partials in ws
+        int64_t pfloats = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            const BwdArgs a = bwd_item_args(items[i]);
+            if (!a.grad_pan && !a.grad_ms && !a.grad_gain) continue;
+            if (!plan_bwd(ctx, a, choose_bwd_path(a), &tiles[(size_t)i]))
+                return fail(ctx, DWT_FUSE_E_SHAPE, "item " + std::to_string(i) + ": too many work units");
+            if (a.grad_gain) {
+                poff[(size_t)i] = pfloats;
+                pfloats += (int64_t)tiles[(size_t)i].d.units * a.B;
+            }
+        }
+        if (pfloats > 0 && (st = ensure_ws(ctx, sizeof(float) * (size_t)pfloats))) return st;
+        const int maxb = adjoint_max_bands();
+        std::map<std::tuple<int, int, int, int>, BwdGroup> groups;  // (chunk, kind, path, x): chunk first
+        std::vector<GainJob> jobs;
+        for (int64_t i = 0; i < n; ++i) {
+            const BwdArgs a = bwd_item_args(items[i]);
+            if (!a.grad_pan && !a.grad_ms && !a.grad_gain) continue;
+            const BwdTile &bt = tiles[(size_t)i];
+            float *partial = poff[(size_t)i] >= 0 ? ctx->ws + poff[(size_t)i] : nullptr;
+            for (int64_t b0 = 0; b0 < a.B; b0 += maxb) {
+                const int chunk = (int)(b0 / maxb);
+                BwdGroup &g = groups[std::make_tuple(chunk, bt.kind, (int)bt.pp, bt.x)];
+                g.kind = bt.kind;
+                g.path = bt.pp;
+                g.x = bt.x;
+                g.chunk = chunk;
+                AdjScene sc{};
+                sc.p = bwd_params(a, bt, partial, b0);
+                sc.unit_begin = (int32_t)g.total;
+                g.total += bt.d.units;
+                if (g.total > INT32_MAX) return fail(ctx, DWT_FUSE_E_SHAPE, "too many work units in batch");
+                g.sc.push_back(sc);
+            }
+            if (partial)
+                for (int64_t b = 0; b < a.B; ++b)
+                    jobs.push_back(GainJob{partial, const_cast<float *>(a.grad_gain), bt.d.units, (int32_t)a.B,
+                                           (int32_t)b, 0});
+        }
+        if (groups.empty()) return DWT_FUSE_OK;
+        if (jobs.size() > (size_t)INT32_MAX) return fail(ctx, DWT_FUSE_E_SHAPE, "too many gain reductions in batch");
+        size_t nsc = 0;
+        for (const auto &kv : groups) nsc += kv.second.sc.size();
+        const size_t sc_bytes = nsc * sizeof(AdjScene);
+        const size_t job_off = (sc_bytes + 255) / 256 * 256;
+        const size_t bytes = job_off + jobs.size() * sizeof(GainJob);
+        if ((st = ensure_bwd_tables(ctx, bytes))) return st;
+        if (ctx->bwd_pending) {  // the previous upload has left the pinned buffer
+            const hipError_t e = hipEventSynchronize(ctx->bwd_staged);
+            if (e != hipSuccess) return hip_fail(ctx, e, "hipEventSynchronize");
+        }
+        char *h = static_cast<char *>(ctx->h_bwd);
+        size_t off = 0;
+        for (const auto &kv : groups) {
+            std::memcpy(h + off, kv.second.sc.data(), kv.second.sc.size() * sizeof(AdjScene));
+            off += kv.second.sc.size() * sizeof(AdjScene);
+        }
+        if (!jobs.empty()) std::memcpy(h + job_off, jobs.data(), jobs.size() * sizeof(GainJob));
+        hipError_t e = hipMemcpyAsync(ctx->d_bwd, ctx->h_bwd, bytes, hipMemcpyHostToDevice, ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "backward table upload");
+        e = hipEventRecord(ctx->bwd_staged, ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipEventRecord");
+        ctx->bwd_pending = true;
+        // Band group 0 of every scene first (the map is ordered by chunk), so
+        // later groups, which add into grad_pan, run after it on the stream.
+        const AdjScene *d_sc = static_cast<const AdjScene *>(ctx->d_bwd);
+        for (const auto &kv : groups) {
+            const BwdGroup &g = kv.second;
+            e = launch_adjoint_batched(d_sc, (int)g.sc.size(), (int)g.total, g.kind, g.path, g.x, ctx->filt,
+                                       ctx->stream);
+            if (e != hipSuccess) return hip_fail(ctx, e, "batched adjoint launch");
+            d_sc += g.sc.size();
+        }
+        if (!jobs.empty()) {
+            e = launch_gain_reduce_batched(
+                reinterpret_cast<const GainJob *>(static_cast<const char *>(ctx->d_bwd) + job_off), (int)jobs.size(),
+                ctx->stream);
+            if (e != hipSuccess) return hip_fail(ctx, e, "batched gain reduction launch");
         }
         return DWT_FUSE_OK;
     } catch (const std::bad_alloc &) {

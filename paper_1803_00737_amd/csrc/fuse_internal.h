@@ -121,6 +121,33 @@ hipError_t launch_adjoint_tile(const AdjParams &p, const Filters &f, int kr, int
 // grad_gain[b] = sum_u partial[u * B + b], b < B, fixed order.
 hipError_t launch_gain_reduce(const float *partial, int units, int B, float *grad_gain, hipStream_t s);
 
+// One scene of a batched adjoint launch: its parameters (as for the
+// single-scene launchers) and the first launch-wide unit it owns.
+struct AdjScene {
+    AdjParams p;
+    int32_t unit_begin;
+    int32_t pad_;
+};
+
+// Adjoint units of many scenes that share one kernel variant, in one launch
+// of 4-wavefront workgroups (scenes sorted by unit_begin, units of scene i
+// are unit_begin[i] .. unit_begin[i] + p.units - 1, total in all).  kind 0:
+// rolling, any wavelet, B <= adjoint_max_bands(); kind 1: rolling D4 with
+// x = B <= 4 bands unrolled (no accumulate); kind 2: one-shot D4 tiles of
+// x = seg_rows (1 or 2) rows.  path: PATH_V4, PATH_V2 or PATH_SCALAR, the
+// same for every scene.  Results per scene equal the single-scene launch.
+hipError_t launch_adjoint_batched(const AdjScene *d_scenes, int nscenes, int total, int kind, int path, int x,
+                                  const Filters &f, hipStream_t s);
+
+// One band of one scene's gain reduction: grad_gain[band] = sum over the
+// scene's units u of partial[u * pstride + band], as launch_gain_reduce.
+struct GainJob {
+    const float *partial;
+    float *grad_gain;
+    int32_t units, pstride, band, pad_;
+};
+hipError_t launch_gain_reduce_batched(const GainJob *d_jobs, int njobs, hipStream_t s);
+
 // Bands one rolling adjoint launch handles (the host splits larger band counts).
 int adjoint_max_bands();
 

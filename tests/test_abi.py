@@ -159,6 +159,62 @@ def test_backward_validation(lib):
     assert bwd_check(lib, gg=P + 4) == E_ALIAS  # grad_gain over pan
 
 
+def bwd_item(w=1, H=8, W=8, B=2, base=P, gain=False, outs=(True, True, True)):
+    it = _lib.BwdItem()
+    it.wavelet, it.B, it.H, it.W = w, B, H, W
+    it.pan = base
+    it.grad_out = base + 10**6
+    it.gain = base + 5 * 10**6 if gain else None
+    it.grad_pan = base + 2 * 10**6 if outs[0] else None
+    it.grad_ms = base + 3 * 10**6 if outs[1] else None
+    it.grad_gain = base + 4 * 10**6 if outs[2] else None
+    it.pan_ld, it.go_ld, it.go_band_stride = W, W, H * W
+    return it
+
+
+def bwd_batch(*items):
+    arr = (_lib.BwdItem * len(items))()
+    for i, it in enumerate(items):
+        arr[i] = it
+    return arr
+
+
+def test_backward_batched_validation(lib):
+    chk = lib.dwt_fuse_check_backward_batched
+    assert chk(None, 0) == OK
+    assert chk(None, 2) == E_NULL
+    assert chk(bwd_batch(bwd_item()), -1) == E_SHAPE
+    a = bwd_item()
+    assert chk(bwd_batch(a, bwd_item(base=P + 10**7, gain=True)), 2) == OK
+    # per-item rules, reported for the first failing item
+    assert chk(bwd_batch(a, bwd_item(H=6, W=5, base=P + 10**7)), 2) == E_SHAPE
+    assert chk(bwd_batch(a, bwd_item(w=4, base=P + 10**7)), 2) == E_WAVELET
+    b = bwd_item(base=P + 10**7)
+    b.pan = None
+    assert chk(bwd_batch(a, b), 2) == E_NULL
+    b = bwd_item(base=P + 10**7)
+    b.go_ld = 4
+    assert chk(bwd_batch(a, b), 2) == E_STRIDE
+    # item 1's grad_ms over item 0's grad_pan
+    b = bwd_item(base=P + 10**7)
+    b.grad_ms = a.grad_pan + 8
+    assert chk(bwd_batch(a, b), 2) == E_ALIAS
+    # item 1's grad_gain over item 0's grad_out
+    b = bwd_item(base=P + 10**7)
+    b.grad_gain = a.grad_out + 4
+    assert chk(bwd_batch(a, b), 2) == E_ALIAS
+    # item 0's grad_pan over item 1's gain
+    b = bwd_item(base=P + 10**7, gain=True)
+    b.gain = a.grad_pan + 16
+    assert chk(bwd_batch(a, b), 2) == E_ALIAS
+    # inputs may be shared (one PAN, several upstream gradients); absent outputs never alias
+    b = bwd_item(base=P + 10**7, outs=(False, True, False))
+    b.pan = a.pan
+    assert chk(bwd_batch(a, b), 2) == OK
+    assert chk(bwd_batch(bwd_item(outs=(False, False, False)), bwd_item(outs=(False, False, False))), 2) == OK
+    assert lib.dwt_fuse_backward_batched(None, None, 0) == E_NULL
+
+
 def test_status_strings(lib):
     for s in range(9):
         assert lib.dwt_fuse_status_str(s)

@@ -203,3 +203,136 @@ def test_differentiation_workload(dev, fz, oracle):
             gy = (2.0 / out.numel()) * (out.detach() - target)
             check_grads(oracle, "d4", pan.cpu().numpy(), gy.cpu().numpy(), np.ones(4, np.float32),
                         [p.grad.cpu().numpy(), m.grad.cpu().numpy(), g.grad.cpu().numpy()])
+
+
+def _bwd_scene(rng, dev, wavelet, H, W, B, pad=0, offset=0, gain=True, need=(True, True, True)):
+    pan, _ = int_scene(rng, H, W, 1)
+    gy = rng.normal(size=(B, H, W)).astype(np.float32)
+    g = rng.uniform(0.5, 1.5, B).astype(np.float32) if gain else None
+    p = strided_view(pan, dev, pad, offset) if pad or offset else to_dev(pan, dev)
+    y = strided_view(gy, dev, pad, offset) if pad or offset else to_dev(gy, dev)
+    return dict(pan=p, grad_out=y, wavelet=wavelet, gain=None if g is None else to_dev(g, dev),
+                need_pan=need[0], need_ms=need[1], need_gain=need[2] and gain,
+                host=(pan, gy, g))
+
+
+def _single(fz, s):
+    return fz.fuse_backward(s["pan"], s["grad_out"], s["wavelet"], s["gain"], s["need_pan"], s["need_ms"],
+                            s["need_gain"])
+
+
+def _same(a, b):
+    for x, y in zip(a, b):
+        assert (x is None) == (y is None)
+        if x is not None:
+            assert torch.equal(x, y)
+
+
+# (wavelet, H, W, B, pad, offset, gain, need): every adjoint variant and load
+# path -- D4 with <= 4 bands (band loop unrolled), D4 and Haar with 9 bands
+# (two band groups, the second adding into grad_pan), 16-byte, 8-byte and
+# 4-byte rows, scenes without grad_gain or without any output.
+BWD_BATCH = [("d4", 66, 516, 4, 0, 0, True, (True, True, True)),
+             ("d4", 34, 70, 3, 0, 0, True, (True, True, True)),
+             ("haar", 130, 258, 2, 0, 0, True, (True, True, True)),
+             ("d4", 130, 1288, 9, 0, 0, True, (True, True, True)),
+             ("haar", 34, 136, 9, 0, 0, False, (True, True, False)),
+             ("d4", 34, 134, 3, 2, 2, True, (True, False, True)),
+             ("d4", 34, 134, 1, 1, 1, True, (False, True, True)),
+             ("haar", 34, 134, 5, 1, 1, True, (True, True, True)),
+             ("d4", 8, 8, 2, 0, 0, True, (False, False, False)),
+             ("d4", 2, 4, 1, 0, 0, True, (True, True, True)),
+             ("d4", 66, 516, 4, 0, 0, False, (True, True, False))]
+
+
+def test_backward_batched_matches_single_calls(dev, fz, oracle):
+    """One batched call equals a dwt_fuse_backward call per scene bit for bit
+    (same work units per scene, same fma chains, same fixed-order gain sums),
+    and meets the oracle's tolerance."""
+    rng = np.random.default_rng(99)
+    scenes = [_bwd_scene(rng, dev, *c) for c in BWD_BATCH]
+    say("backward batched", len(scenes), "scenes")
+    got = fz.fuse_backward_batched(scenes)
+    for i, (s, g) in enumerate(zip(scenes, got)):
+        say("backward batched scene", i, BWD_BATCH[i])
+        _same(g, _single(fz, s))
+        pan, gy, gain = s["host"]
+        if g[0] is not None and g[1] is not None and g[2] is not None:
+            check_grads(oracle, s["wavelet"], pan, gy, gain, [t.cpu().numpy() for t in g])
+
+
+@pytest.mark.parametrize("seg,wpb,nc,var", [(1, 1, 1, 1), (16, 4, 2, 1), (1, 4, 2, 2), (2, 2, 1, 2), (3, 2, 2, 0)])
+def test_backward_batched_forced_shapes(dev, fz, seg, wpb, nc, var):
+    """Forced adjoint shapes (rolling with a dynamic band loop, one-shot tiles,
+    other unit lengths) apply to every scene of a batch as to a single call."""
+    rng = np.random.default_rng(seg * 10 + var)
+    scenes = [_bwd_scene(rng, dev, *c) for c in BWD_BATCH[:6]]
+    ctx = fz.context(dev)
+    try:
+        ctx.force_tile(seg, wpb, nc, var)
+        say("backward batched forced", seg, wpb, nc, var)
+        got = fz.fuse_backward_batched(scenes)
+        for s, g in zip(scenes, got):
+            _same(g, _single(fz, s))
+    finally:
+        ctx.force_tile(0, 0, 0, 0)
+
+
+def test_backward_batched_twice_and_empty(dev, fz):
+    """Consecutive batched calls reuse the context's tables (the second call,
+    with a smaller batch, must not see the first one's scenes); n = 0 is a
+    no-op."""
+    rng = np.random.default_rng(5)
+    big = [_bwd_scene(rng, dev, *c) for c in BWD_BATCH]
+    small = [_bwd_scene(rng, dev, *c) for c in BWD_BATCH[2:4]]
+    say("backward batched twice")
+    g1 = fz.fuse_backward_batched(big)
+    g2 = fz.fuse_backward_batched(small)
+    for s, g in zip(big, g1):
+        _same(g, _single(fz, s))
+    for s, g in zip(small, g2):
+        _same(g, _single(fz, s))
+    assert fz.fuse_backward_batched([]) == []
+
+
+def test_backward_batched_rejects_aliasing(dev, fz):
+    rng = np.random.default_rng(6)
+    a = _bwd_scene(rng, dev, "d4", 34, 70, 2)
+    b = _bwd_scene(rng, dev, "d4", 34, 70, 2)
+    arr, outs, keep = fz.make_bwd_items([a, b])
+    arr[1].grad_pan = arr[0].grad_pan  # two scenes writing one grad_pan
+    ctx = fz.context(dev)
+    ctx.bind_stream()
+    from paper_1803_00737_amd import _lib
+
+    assert ctx.lib.dwt_fuse_backward_batched(ctx.handle, arr, 2) == _lib.E_ALIAS
+    arr, outs, keep = fz.make_bwd_items([a, b])
+    arr[1].grad_ms = arr[0].grad_out  # a gradient over another scene's upstream gradient
+    assert ctx.lib.dwt_fuse_backward_batched(ctx.handle, arr, 2) == _lib.E_ALIAS
+
+
+def test_differentiation_workload_batched(dev, fz, oracle):
+    """The 16 x 2048^2, 4-band D4 step as two batched calls (forward of all
+    scenes, then the adjoint of all scenes): gradients equal the per-scene
+    calls bit for bit; scene 0 is checked against the oracle."""
+    from paper_1803_00737_amd import synth
+
+    scenes, bwd = [], []
+    for s in range(16):
+        seed = synth.seed_for(4, s)
+        pan, ms = synth.make_scene(2048, 2048, 4, seed, device=dev)
+        tg = torch.tensor(synth.grad_targets(4, seed), dtype=torch.float32, device=dev)
+        scenes.append(dict(pan=pan, ms=ms, wavelet="d4", gain=torch.ones(4, device=dev), tg=tg))
+    say("differentiation batched: forward")
+    outs = fz.fuse_batched([{k: v for k, v in s.items() if k != "tg"} for s in scenes])
+    for s, out in zip(scenes, outs):
+        target = s["pan"][None] * s["tg"][:, None, None]
+        gy = (2.0 / (16 * out.numel())) * (out - target)
+        bwd.append(dict(pan=s["pan"], grad_out=gy, wavelet="d4", gain=s["gain"]))
+    say("differentiation batched: adjoint")
+    got = fz.fuse_backward_batched(bwd)
+    for i, (b, g) in enumerate(zip(bwd, got)):
+        _same(g, fz.fuse_backward(b["pan"], b["grad_out"], "d4", b["gain"]))
+        if i == 0:
+            check_grads(oracle, "d4", b["pan"].cpu().numpy(), b["grad_out"].cpu().numpy(), np.ones(4, np.float32),
+                        [t.cpu().numpy() for t in g])
