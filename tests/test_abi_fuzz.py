@@ -106,3 +106,50 @@ def test_check_batched_never_crashes(lib, n, H, W, B, stride):
     assert st_ in STATUSES
     if n < 0:
         assert st_ != 0
+
+
+@settings(max_examples=300, deadline=None)
+@given(n=st.integers(-2, 5), H=st.integers(-2, 300), W=st.integers(-2, 300), B=st.integers(-1, 10),
+       stride=st.integers(0, 1 << 24), shift=st.integers(-(1 << 22), 1 << 22), which=st.integers(0, 5),
+       outs=st.integers(0, 7))
+def test_check_backward_batched_never_crashes(lib, n, H, W, B, stride, shift, which, outs):
+    """Random batches of backward descriptors, one field of the last item
+    moved by `shift` bytes: OK only when every item is valid on its own, no
+    output overlaps another output and no output overlaps any input."""
+    k = max(n, 0)
+    items = (_lib.BwdItem * max(k, 1))()
+    for i in range(k):
+        it = items[i]
+        it.wavelet, it.B, it.H, it.W = i % 2, B, H, W
+        base = (1 << 40) + i * stride
+        it.pan, it.grad_out, it.gain = base, base + (1 << 30), base + (3 << 30)
+        it.grad_pan = base + (1 << 31) if outs & 1 else None
+        it.grad_ms = base + (5 << 29) if outs & 2 else None
+        it.grad_gain = base + (7 << 29) if outs & 4 else None
+        it.pan_ld, it.go_ld, it.go_band_stride = W, W, H * W
+    if k > 0:
+        f = ["pan", "grad_out", "gain", "grad_pan", "grad_ms", "grad_gain"][which]
+        if getattr(items[k - 1], f) is not None:
+            setattr(items[k - 1], f, max(1, getattr(items[k - 1], f) + shift))
+    st_ = lib.dwt_fuse_check_backward_batched(items, n)
+    assert st_ in STATUSES
+    if n < 0:
+        assert st_ != 0
+    if st_ != 0 or k == 0:
+        return
+    assert H >= 2 and W >= 2 and H % 2 == 0 and W % 2 == 0 and B >= 1
+    ins, outs_ = [], []
+    for i in range(k):
+        it = items[i]
+        ins.append(span(it.pan, 1, H, W, W, 0, 4))
+        ins.append(span(it.grad_out, B, H, W, W, H * W, 4))
+        ins.append(span(it.gain, 1, 1, B, B, 0, 4))
+        for ptr, nb, rows, cols in ((it.grad_pan, 1, H, W), (it.grad_ms, B, H // 2, W // 2), (it.grad_gain, 1, 1, B)):
+            if ptr is not None:
+                outs_.append(span(ptr, nb, rows, cols, cols, rows * cols, 4))
+    assert all(s is not None for s in ins + outs_)
+    for a in range(len(outs_)):
+        for b in range(a + 1, len(outs_)):
+            assert not overlap(outs_[a], outs_[b])
+        for s in ins:
+            assert not overlap(outs_[a], s)
