@@ -393,7 +393,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="use the default tile instead of the autotuner")
     ap.add_argument("--tune-cache", default=None,
-                    help="tuning table file: loaded if it exists (no tuning), else written after tuning")
+                    help="tuning table file: loaded if it exists (no tuning), else written after tuning "
+                         "(after the primary workload, and again at the end with every workload's shapes)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -457,6 +458,8 @@ def main():
     }
     if args.mode == "full":
         result["workloads"] = extras(torch, api, synth, args.steps, args.warmup)
+        if args.tune_cache and not loaded and not args.no_tune:
+            ctx.tune_save(args.tune_cache)  # now with the shapes of every workload
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         result["cpu_baseline"] = cpu_baseline(pan, ms, wl.wavelet)
