@@ -69,7 +69,12 @@ dwt_fuse_status dwt_fuse_create(dwt_fuse_ctx **ctx, int device, void *hip_stream
  * must make sure no work issued through the context is still running. */
 void dwt_fuse_destroy(dwt_fuse_ctx *ctx);
 
-/* Make subsequent calls use `hip_stream` (same device). */
+/* Make subsequent calls use `hip_stream` (same device).  When the stream
+ * changes, the new stream is made to wait (hipStreamWaitEvent, no host
+ * wait) for everything already issued through the context on the old one,
+ * so the context's workspace and tables are never rewritten while earlier
+ * work still reads them.  DWT_FUSE_E_DEVICE if that ordering cannot be
+ * set up. */
 dwt_fuse_status dwt_fuse_set_stream(dwt_fuse_ctx *ctx, void *hip_stream);
 
 /* Fuse one scene (section 2, method steps 1-3, for every band).

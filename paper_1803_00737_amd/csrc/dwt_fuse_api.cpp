@@ -561,6 +561,7 @@ struct dwt_fuse_ctx {
     size_t bwd_bytes = 0;
     hipEvent_t bwd_staged = nullptr;  // last upload of h_bwd finished
     bool bwd_pending = false;
+    hipEvent_t switched = nullptr;  // recorded on the old stream by dwt_fuse_set_stream
 };
 
 namespace {
@@ -1068,6 +1069,7 @@ void dwt_fuse_destroy(dwt_fuse_ctx *ctx) {
         if (ctx->d_bwd) (void)hipFree(ctx->d_bwd);
         if (ctx->h_bwd) (void)hipHostFree(ctx->h_bwd);
         if (ctx->bwd_staged) (void)hipEventDestroy(ctx->bwd_staged);
+        if (ctx->switched) (void)hipEventDestroy(ctx->switched);
         if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
         if (cur >= 0) (void)hipSetDevice(cur);
     } catch (...) {
@@ -1077,8 +1079,29 @@ void dwt_fuse_destroy(dwt_fuse_ctx *ctx) {
 
 dwt_fuse_status dwt_fuse_set_stream(dwt_fuse_ctx *ctx, void *hip_stream) {
     if (!ctx) return DWT_FUSE_E_NULL;
-    ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
-    return DWT_FUSE_OK;
+    const hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    if (s == ctx->stream) return DWT_FUSE_OK;
+    try {
+        dwt_fuse_status st = use_device(ctx);
+        if (st) return st;
+        if (!ctx->switched) {
+            const hipError_t e = hipEventCreateWithFlags(&ctx->switched, hipEventDisableTiming);
+            if (e != hipSuccess) {
+                ctx->switched = nullptr;
+                return hip_fail(ctx, e, "hipEventCreate");
+            }
+        }
+        // Work issued later on the new stream runs after the context's work
+        // on the old one (workspace, descriptor tables and graphs are shared).
+        hipError_t e = hipEventRecord(ctx->switched, ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipEventRecord");
+        e = hipStreamWaitEvent(s, ctx->switched, 0);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamWaitEvent");
+        ctx->stream = s;
+        return DWT_FUSE_OK;
+    } catch (...) {
+        return fail(ctx, DWT_FUSE_E_STATE, "unexpected exception");
+    }
 }
 
 dwt_fuse_status dwt_fuse_set_tuning(dwt_fuse_ctx *ctx, int enable) {

@@ -99,3 +99,46 @@ def test_calls_follow_the_bound_stream(dev, fz):
                                    _ptr(out), 1030, 258 * 1030), "run")
     side.synchronize()
     assert np.array_equal(out.cpu().numpy(), ref)
+
+
+def test_stream_switch_orders_shared_tables(dev, fz):
+    """One context, two streams, no host wait between them: a batched adjoint
+    issued on stream A, then (after switching the context to stream B) a
+    second batched adjoint and a batched forward that rewrite the context's
+    workspace and descriptor tables.  Switching makes B wait for A's work, so
+    every result equals the per-scene calls."""
+    rng = np.random.default_rng(21)
+    H, W, B = 514, 1030, 3
+
+    def scene():
+        pan, ms = int_scene(rng, H, W, B)
+        gy = rng.normal(size=(B, H, W)).astype(np.float32)
+        return to_dev(pan, dev), to_dev(ms, dev), to_dev(gy, dev)
+
+    first = [scene() for _ in range(6)]
+    second = [scene() for _ in range(2)]
+    ref1 = [fz.fuse_backward(p, y, "d4") for p, _, y in first]
+    ref2 = [fz.fuse_backward(p, y, "haar") for p, _, y in second]
+    reff = [fz.fuse(p, m, "haar") for p, m, _ in second]
+    torch.cuda.synchronize()
+    ctx = fz.Context(dev.index or 0)
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    from paper_1803_00737_amd import _lib
+
+    a1, o1, k1 = fz.make_bwd_items([dict(pan=p, grad_out=y, wavelet="d4") for p, _, y in first])
+    a2, o2, k2 = fz.make_bwd_items([dict(pan=p, grad_out=y, wavelet="haar") for p, _, y in second])
+    outs = [torch.empty((B, H, W), device=dev) for _ in second]
+    af, _, kf = fz.make_items([dict(pan=p, ms=m, wavelet="haar", out=o) for (p, m, _), o in zip(second, outs)])
+    torch.cuda.synchronize()
+    say("stream switch")
+    ctx.bind_stream(sa)
+    ctx.check(ctx.lib.dwt_fuse_backward_batched(ctx.handle, a1, len(first)), "batched adjoint on A")
+    ctx.bind_stream(sb)
+    ctx.check(ctx.lib.dwt_fuse_backward_batched(ctx.handle, a2, len(second)), "batched adjoint on B")
+    ctx.check(ctx.lib.dwt_fuse_run_batched(ctx.handle, af, len(second), _lib.GRAPH), "batched forward on B")
+    torch.cuda.synchronize()
+    for got, ref in zip(o1 + o2, ref1 + ref2):
+        for x, y in zip(got, ref):
+            assert torch.equal(x, y)
+    for o, r in zip(outs, reff):
+        assert torch.equal(o, r)
