@@ -459,6 +459,174 @@ __global__ __launch_bounds__(256) void codec_kernel(CodecParams p, Filters f) {
     }
 }
 
+// ---- D4, 8-bit input, LDS-staged workgroup tiles -----------------------------
+//
+// As the float LDS-staged kernel: a workgroup of wpb wavefronts covers a strip
+// of 128 coefficient columns and T = wpb * KR coefficient rows.  Its PAN rows
+// 2r0-2 .. 2r0+2T+1 (2-column halos, all wrapped) and the MS rows r0-1 ..
+// r0+T-1 of a group of bands are read once, converted to float32 and written
+// to LDS; after one barrier each wavefront computes its KR rows from LDS
+// (two coefficient columns per lane) with the same fma chains as every other
+// kernel, so its results equal theirs bit for bit.  Only the rows a
+// wavefront is computing sit in its registers, so many more wavefronts fit
+// on a CU than with the one-shot 8-bit tiles, which hold every PAN row of
+// their unit as floats.
+constexpr int kCPanRow = 264;  // floats: [2,4) left halo, [4,260) own 256 pixels, [260,262) right halo
+constexpr int kCMsRow = 132;   // floats: [3] left halo, [4,132) own 128 coefficients
+
+template <typename TO, int KR, bool AL>
+__global__ __launch_bounds__(256) void d4_codec_staged_kernel(CodecParams p, Filters f, int bg_max) {
+    extern __shared__ float lds[];
+    const int wpb = blockDim.x >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int unit = xcd_remap(blockIdx.x, gridDim.x);
+    if (unit >= p.units) return;  // whole workgroup
+    const int T = wpb * KR;
+    int strip, trow;
+    if (p.order) {
+        trow = unit / p.nstrips;
+        strip = unit - trow * p.nstrips;
+    } else {
+        strip = unit / p.nseg;
+        trow = unit - strip * p.nseg;
+    }
+    const int W2 = p.W >> 1, H2 = p.H >> 1;
+    const int sb = strip * 128, r0 = trow * T;
+    const uint8_t *pan = static_cast<const uint8_t *>(p.pan);
+    const uint8_t *ms = static_cast<const uint8_t *>(p.ms);
+    TO *out = static_cast<TO *>(p.out);
+    float *Pl = lds;
+    float *Ml = lds + (2 * T + 4) * kCPanRow;
+    // The strip's 256 pixels lie inside every row (no wrap within them).
+    const bool clear = 2 * sb + 256 <= p.W;
+
+    for (int k = w; k < 2 * T + 4; k += wpb) {
+        const uint8_t *row = pan + (int64_t)wrap_row(2 * r0 - 2 + k, p.H) * p.pan_ld;
+        float *dst = Pl + k * kCPanRow;
+        if (clear && (reinterpret_cast<uintptr_t>(row) & 3) == 0) {
+            const uint32_t v = *reinterpret_cast<const uint32_t *>(row + 2 * sb + 4 * lane);
+            *reinterpret_cast<f4 *>(dst + 4 + 4 * lane) = f4{byte_at(v, 0), byte_at(v, 1), byte_at(v, 2), byte_at(v, 3)};
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) dst[4 + 4 * lane + q] = (float)row[wrap_idx(2 * sb + 4 * lane + q, p.W)];
+        }
+        if (lane < 2) {
+            dst[2 + lane] = (float)row[wrap_idx(2 * sb - 2 + lane, p.W)];
+            dst[260 + lane] = (float)row[wrap_idx(2 * sb + 256 + lane, p.W)];
+        }
+    }
+    const bool mclear = sb + 128 <= W2;
+    auto stage_ms = [&](int g0, int bg) {
+        for (int k = w; k < bg * (T + 1); k += wpb) {
+            const int b = g0 + k / (T + 1), i = k - (k / (T + 1)) * (T + 1);
+            const uint8_t *row = ms + (int64_t)b * p.ms_bs + (int64_t)wrap_row(r0 - 1 + i, H2) * p.ms_ld;
+            float *dst = Ml + k * kCMsRow;
+            if (mclear && (reinterpret_cast<uintptr_t>(row) & 1) == 0) {
+                const uint32_t v = *reinterpret_cast<const uint16_t *>(row + sb + 2 * lane);
+                *reinterpret_cast<f2 *>(dst + 4 + 2 * lane) = f2{byte_at(v, 0), byte_at(v, 1)};
+            } else {
+                dst[4 + 2 * lane] = (float)row[wrap_idx(sb + 2 * lane, W2)];
+                dst[5 + 2 * lane] = (float)row[wrap_idx(sb + 2 * lane + 1, W2)];
+            }
+            if (lane == 0) dst[3] = (float)row[wrap_idx(sb - 1, W2)];
+        }
+    };
+    const int bg0 = min(p.B, bg_max);
+    stage_ms(0, bg0);
+    __syncthreads();
+
+    // This wavefront: coefficient rows rb .. rb+KR-1, coefficient columns
+    // s0 = sb + 2*lane and s0 + 1; its PAN pairs s0-1 .. s0+2 start at LDS
+    // float 2 + 4*lane of a staged row, its MS columns s0-1 .. s0+1 at 3 + 2*lane.
+    const int rb = r0 + KR * w;
+    const int nr = max(0, min(KR, H2 - rb));
+    constexpr int NR = 2 * KR + 4;  // PAN rows 2rb-2 .. 2rb+2KR+1 = staged rows 2KR*w + t
+    const int s0 = sb + 2 * lane;
+    const bool full = s0 + 2 <= W2;
+    f2 xo[2 * KR][2];  // the lane's PAN pixels of its output rows
+    float A[KR + 1][3];
+    {
+        float R[NR][3];
+#pragma unroll
+        for (int t = 0; t < NR; ++t) {
+            const float *src = Pl + (2 * KR * w + t) * kCPanRow + 2 + 4 * lane;
+            f2 x[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) x[k] = *reinterpret_cast<const f2 *>(src + 2 * k);
+            rowfilt<2>(f, x, R[t]);
+            if (t >= 2 && t < 2 + 2 * KR) {
+                xo[t - 2][0] = x[1];
+                xo[t - 2][1] = x[2];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i <= KR; ++i) colfilt<2>(f, R[2 * i], R[2 * i + 1], R[2 * i + 2], R[2 * i + 3], A[i]);
+    }
+
+    for (int g0 = 0; g0 < p.B; g0 += bg_max) {
+        const int bg = min(bg_max, p.B - g0);
+        if (g0 > 0) {  // next band group: every wavefront is done with the previous one
+            __syncthreads();
+            stage_ms(g0, bg);
+            __syncthreads();
+        }
+        for (int bi = 0; bi < bg && s0 < W2; ++bi) {
+            const int b = g0 + bi;
+            const float g = p.gain ? p.gain[b] : 1.0f;
+            TO *ob = out + (int64_t)b * p.out_bs;
+            float m[KR + 1][3];
+#pragma unroll
+            for (int i = 0; i <= KR; ++i) {
+                const float *src = Ml + (bi * (T + 1) + KR * w + i) * kCMsRow + 3 + 2 * lane;
+#pragma unroll
+                for (int j = 0; j < 3; ++j) m[i][j] = src[j];
+            }
+#pragma unroll
+            for (int i = 0; i < KR; ++i) {
+                if (i >= nr) break;
+                f2 xa[4], xb[4];
+                xa[1] = xo[2 * i][0];
+                xa[2] = xo[2 * i][1];
+                xb[1] = xo[2 * i + 1][0];
+                xb[2] = xo[2 * i + 1][1];
+                f2 q0[2], q1[2];
+                d4_out_rows<2>(f, g, p.kappa, m[i + 1], m[i], A[i + 1], A[i], xa, xb, q0, q1);
+                TO *o0 = ob + (int64_t)(2 * (rb + i)) * p.out_ld;
+                store_out<TO, 2, AL>(o0, s0, W2, full, q0);
+                store_out<TO, 2, AL>(o0 + p.out_ld, s0, W2, full, q1);
+            }
+        }
+    }
+}
+
+// Largest band group a staged 8-bit tile of T rows holds in 64 KB of LDS (<= 8).
+int codec_staged_bg_max(int T) {
+    const int pan = (2 * T + 4) * kCPanRow, per_band = (T + 1) * kCMsRow;
+    const int bg = (16384 - pan) / per_band;
+    return bg < 1 ? 0 : (bg > 8 ? 8 : bg);
+}
+
+template <typename TO>
+hipError_t launch_staged_io(const CodecParams &p, const Filters &f, int kr, bool al, int wpb, hipStream_t s) {
+    const int T = kr * wpb;
+    const int bgm = codec_staged_bg_max(T);
+    if (bgm < 1) return hipErrorInvalidValue;
+    const int bg = p.B < bgm ? p.B : bgm;
+    const size_t lds = sizeof(float) * ((size_t)(2 * T + 4) * kCPanRow + (size_t)bg * (T + 1) * kCMsRow);
+    const dim3 grid(p.units), block(64 * wpb);
+#define CODEC_STAGED(KR, AL) \
+    hipLaunchKernelGGL((d4_codec_staged_kernel<TO, KR, AL>), grid, block, lds, s, p, f, bgm)
+    if (kr == 1) {
+        if (al) CODEC_STAGED(1, true);
+        else CODEC_STAGED(1, false);
+    } else {
+        if (al) CODEC_STAGED(2, true);
+        else CODEC_STAGED(2, false);
+    }
+#undef CODEC_STAGED
+    return hipGetLastError();
+}
+
 template <typename TI, typename TO, int NC, int KR, bool AL>
 hipError_t launch_t(const CodecParams &p, const Filters &f, int wpb, hipStream_t s) {
     const int grid = (p.units + wpb - 1) / wpb;
@@ -496,6 +664,7 @@ hipError_t launch_io(const CodecParams &p, const Filters &f, int nc, int kr, boo
 }  // namespace
 
 bool codec_shape_ok(int in_u8, int nc, int kr, bool al, int wavelet) {
+    if (kr >= 3) return in_u8 && wavelet == 1 && nc == 2 && kr <= 4;  // LDS-staged (al: output stores)
     if (kr == 0 && (wavelet != 1 || !al)) return false;  // rolling: D4, aligned buffers
     if (in_u8) return al ? ((nc == 4 || nc == 8) && kr >= 0 && kr <= 2) : (nc == 4 && kr == 1);
     return al ? (nc == 2 && kr >= 0 && kr <= 2) : (nc == 2 && kr == 1);
@@ -505,6 +674,13 @@ hipError_t launch_codec(const CodecParams &p, const Filters &f, int in_u8, int o
                         int wpb, hipStream_t s) {
     if (p.units <= 0) return hipSuccess;
     if (wpb < 1 || wpb > 4 || !codec_shape_ok(in_u8, nc, kr, al, p.wavelet)) return hipErrorInvalidValue;
+    if (kr >= 3) {  // LDS-staged D4 tiles of (kr - 2) * wpb rows, 8-bit input
+        if (p.seg_rows != (kr - 2) * wpb || p.nstrips != (p.W / 2 + 127) / 128 ||
+            p.nseg != (p.H / 2 + p.seg_rows - 1) / p.seg_rows)
+            return hipErrorInvalidValue;
+        return out_u8 ? launch_staged_io<uint8_t>(p, f, kr - 2, al, wpb, s)
+                      : launch_staged_io<float>(p, f, kr - 2, al, wpb, s);
+    }
     if (p.seg_rows < 1 || (kr > 0 && p.seg_rows != kr)) return hipErrorInvalidValue;
     if (p.nstrips != (p.W / 2 + 64 * nc - 1) / (64 * nc) || p.nseg != (p.H / 2 + p.seg_rows - 1) / p.seg_rows)
         return hipErrorInvalidValue;

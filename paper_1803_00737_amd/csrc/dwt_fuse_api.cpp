@@ -1162,7 +1162,8 @@ dwt_fuse_status dwt_fuse_tune_load(dwt_fuse_ctx *ctx, const char *path) {
         // LDS-staged); 'c': format-variant shapes (nc 2/4/8, mode = rows of a
         // one-shot tile, 0 = rolling).
         const bool codec = key[0] == 'c';
-        const bool shape_ok = codec ? ((t.nc == 2 || t.nc == 4 || t.nc == 8) && t.mode >= 0 && t.mode <= 2)
+        const bool shape_ok = codec ? ((t.nc == 2 || t.nc == 4 || t.nc == 8) && t.mode >= 0 && t.mode <= 4 &&
+                                              (t.mode < 3 || t.nc == 2))
                                     : (t.nc >= 1 && t.nc <= 2 && t.mode >= 0 && t.mode <= 6 && t.mode != 5);
         if (r != 7 || t.split < 0 || t.split > 8 || (key[0] != 'f' && key[0] != 'b' && !codec) || t.seg_rows < 1 || t.seg_rows > 4096 ||
             t.wpb < 1 || t.wpb > 4 || t.order < 0 || t.order > 1 || !shape_ok) {
@@ -1221,8 +1222,11 @@ namespace {
 
 struct CodecShape {
     int nc = 4, kr = 1, wpb = 4, order = 1;
-    int rows = 1;  // coefficient rows per unit: kr for one-shot tiles, seg_rows when rolling (kr = 0)
-    bool aligned = false;
+    // coefficient rows per unit: kr for one-shot tiles (kr 1, 2), seg_rows when
+    // rolling (kr 0), (kr - 2) * wpb for LDS-staged tiles (kr 3, 4: D4, 8-bit
+    // input, nc 2)
+    int rows = 1;
+    bool aligned = false;  // vector access (LDS-staged: output stores only)
 };
 
 bool is_aligned(const void *p, int64_t ld, int64_t bs, int64_t nb, int64_t esize, int64_t a) {
@@ -1239,6 +1243,17 @@ bool codec_aligned(const ExArgs &a, int nc) {
     return is_aligned(a.pan, a.pan_ld, 0, 1, ei, 2 * nc * ei) &&
            is_aligned(a.ms, a.ms_ld, a.ms_bs, a.B, ei, nc * ei) &&
            is_aligned(a.out, a.out_ld, a.out_bs, a.B, eo, std::min<int64_t>(2 * nc * eo, 16));
+}
+
+// LDS-staged 8-bit tiles: 4-byte (8-bit) or 16-byte (float) output stores.
+bool codec_staged_aligned(const ExArgs &a) {
+    const int64_t eo = format_size(a.out_format);
+    return is_aligned(a.out, a.out_ld, a.out_bs, a.B, eo, 4 * eo);
+}
+
+// Recompute the alignment flag of a shape for these buffers.
+void codec_set_aligned(const ExArgs &a, CodecShape *t) {
+    t->aligned = t->kr >= 3 ? codec_staged_aligned(a) : codec_aligned(a, t->nc);
 }
 
 std::string codec_key(const ExArgs &a, bool aligned) {
@@ -1267,7 +1282,7 @@ CodecShape codec_default(const ExArgs &a) {
 
 bool codec_params(const ExArgs &a, const CodecShape &t, CodecParams *p) {
     const int64_t W2 = a.W / 2, H2 = a.H / 2;
-    const int rows = t.kr > 0 ? t.kr : std::max(1, t.rows);
+    const int rows = t.kr >= 3 ? (t.kr - 2) * t.wpb : (t.kr > 0 ? t.kr : std::max(1, t.rows));
     const int64_t ns = (W2 + 64 * t.nc - 1) / (64 * t.nc), ng = (H2 + rows - 1) / rows;
     if (ns * ng > INT32_MAX - 4) return false;
     CodecParams q{};
@@ -1341,6 +1356,25 @@ CodecShape codec_shape(dwt_fuse_ctx *c, const ExArgs &a) {
                     }
             }
         }
+        // LDS-staged D4 tiles (8-bit input): 1 or 2 rows per wavefront
+        if (u8 && a.wavelet == DWT_FUSE_D4) {
+            for (int kr : {3, 4})
+                for (int wpb : {2, 4})
+                    for (int order : {0, 1}) {
+                        CodecShape s = t;
+                        s.nc = 2;
+                        s.kr = kr;
+                        s.wpb = wpb;
+                        s.rows = (kr - 2) * wpb;
+                        s.order = order;
+                        codec_set_aligned(a, &s);
+                        const float ms = time_codec(c, a, s);
+                        if (ms < bestms) {
+                            bestms = ms;
+                            t = s;
+                        }
+                    }
+        }
         Tile rec;
         rec.nc = t.nc;
         rec.seg_rows = t.rows;
@@ -1355,16 +1389,33 @@ CodecShape codec_shape(dwt_fuse_ctx *c, const ExArgs &a) {
     // Forced fields: variant 1 = rolling (D4) of seg_rows rows (default 16),
     // otherwise one-shot tiles of 1 or 2 rows; waves; columns 1/2 -> nc 4/8
     // for 8-bit input.
+    // Forced variant 3: LDS-staged D4 tiles (8-bit input) of seg_rows (1 or 2,
+    // default 2) rows per wavefront.
     const Forced &fo = c->forced;
+    if (fo.variant == 3 && u8 && a.wavelet == DWT_FUSE_D4) {
+        t.kr = 2 + (fo.seg_rows == 1 ? 1 : 2);
+        t.nc = 2;
+        if (fo.wpb > 0) t.wpb = fo.wpb;
+        t.rows = (t.kr - 2) * t.wpb;
+        codec_set_aligned(a, &t);
+        return t;
+    }
     if (fo.variant == 1 && a.wavelet == DWT_FUSE_D4) {
         t.kr = 0;
         t.rows = fo.seg_rows > 0 ? fo.seg_rows : 16;
     } else if (fo.variant != 0 || fo.seg_rows > 0) {
-        if (t.kr == 0 || fo.seg_rows > 0) t.kr = fo.seg_rows >= 2 ? 2 : 1;
+        if (t.kr == 0 || t.kr >= 3 || fo.seg_rows > 0) t.kr = fo.seg_rows >= 2 ? 2 : 1;
         t.rows = t.kr;
     }
     if (fo.wpb > 0) t.wpb = fo.wpb;
-    if (fo.nc > 0 && u8) t.nc = fo.nc == 1 ? 4 : 8;
+    if (t.kr >= 3) {  // a staged shape from the table
+        t.rows = (t.kr - 2) * t.wpb;
+        codec_set_aligned(a, &t);
+        if (codec_shape_ok(u8, t.nc, t.kr, t.aligned, a.wavelet)) return t;
+        t.kr = 1;
+        t.rows = 1;
+    }
+    if ((t.nc == 2 && u8) || (fo.nc > 0 && u8)) t.nc = fo.nc == 2 ? 8 : 4;
     if (t.aligned && !codec_aligned(a, t.nc)) t.nc = 4;
     t.aligned = codec_aligned(a, t.nc);
     if (!codec_shape_ok(u8, t.nc, t.kr, t.aligned, a.wavelet)) {

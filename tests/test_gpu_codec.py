@@ -126,8 +126,9 @@ def test_kappa(dev, fz, oracle, wavelet, kappa, H, W, B):
 @pytest.mark.parametrize("H,W", [(250, 1034), (250, 4104), (18, 8)])
 def test_forced_shapes_identical(dev, fz, wavelet, H, W):
     """Every shape of the format kernels (one-shot tiles of 1 or 2 rows,
-    rolling D4 units of any length (variant 1), waves, columns) evaluates each
-    pixel with the same operations, so all agree bit for bit."""
+    rolling D4 units of any length (variant 1), LDS-staged D4 workgroups
+    (variant 3), waves, columns) evaluates each pixel with the same
+    operations, so all agree bit for bit."""
     rng = np.random.default_rng(9)
     pan, ms = u8_scene(rng, H, W, 3)
     p, m = to_dev(pan, dev), to_dev(ms, dev)
@@ -135,7 +136,8 @@ def test_forced_shapes_identical(dev, fz, wavelet, H, W):
     outs = []
     try:
         for seg, wpb, nc, var in [(0, 0, 0, 0), (1, 1, 1, 0), (2, 4, 1, 0), (1, 2, 2, 0), (2, 1, 2, 0), (2, 4, 2, 0),
-                                  (1, 4, 2, 0), (3, 2, 1, 1), (16, 4, 2, 1), (64, 1, 1, 1), (1, 4, 2, 1)]:
+                                  (1, 4, 2, 0), (3, 2, 1, 1), (16, 4, 2, 1), (64, 1, 1, 1), (1, 4, 2, 1),
+                                  (1, 4, 0, 3), (2, 4, 0, 3), (2, 2, 0, 3), (1, 1, 0, 3), (2, 1, 0, 3)]:
             say("codec shape", wavelet, H, W, seg, wpb, nc, var)
             ctx.force_tile(seg, wpb, nc, var)
             outs.append((fz.fuse(p, m, wavelet).cpu().numpy(),
@@ -171,6 +173,31 @@ def test_pitches_and_offsets(dev, fz, wavelet, pad, offset):
     fz.fuse(p, m, wavelet, out=out)
     assert np.array_equal(out.cpu().numpy(), ref)
     assert np.array_equal(fz.fuse(p, m, wavelet).cpu().numpy(), reff)
+
+
+@pytest.mark.parametrize("pad,offset", [(16, 0), (1, 0), (0, 3), (5, 7), (2, 2)])
+@pytest.mark.parametrize("B", [1, 3, 9])
+def test_staged_u8_pitches_offsets_bands(dev, fz, pad, offset, B):
+    """LDS-staged 8-bit D4 workgroups on pitched and offset views (rows not
+    4-byte aligned take byte loads and stores) and with more bands than one
+    LDS band group holds: identical to the contiguous call."""
+    rng = np.random.default_rng(pad * 7 + offset + B)
+    H, W = 66, 1290
+    pan, ms = u8_scene(rng, H, W, B)
+    ref = fz.fuse(to_dev(pan, dev), to_dev(ms, dev), "d4", out_dtype=torch.uint8).cpu().numpy()
+    reff = fz.fuse(to_dev(pan, dev), to_dev(ms, dev), "d4").cpu().numpy()
+    p, m = strided_u8(pan, dev, pad, offset), strided_u8(ms, dev, pad, offset)
+    out = strided_u8(np.zeros((B, H, W), np.uint8), dev, pad, offset)
+    ctx = fz.context(dev)
+    try:
+        for seg, wpb in ((2, 4), (1, 2)):
+            say("codec staged pitches", pad, offset, B, seg, wpb)
+            ctx.force_tile(seg, wpb, 0, 3)
+            fz.fuse(p, m, "d4", out=out)
+            assert np.array_equal(out.cpu().numpy(), ref)
+            assert np.array_equal(fz.fuse(p, m, "d4").cpu().numpy(), reff)
+    finally:
+        ctx.force_tile(0, 0, 0, 0)
 
 
 def test_nan_gain_gives_zero_code(dev, fz):
