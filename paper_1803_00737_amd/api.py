@@ -140,12 +140,16 @@ def _prep_scene(pan, ms, gain, out, out_dtype=torch.float32, allow_u8=False):
         gain = gain.contiguous()
         if gain.shape[0] != B:
             raise ValueError("gain must have B=%d entries" % B)
+        if gain.device != pan.device:
+            raise ValueError("gain must be on the device of pan")
     if out is None:
         out = torch.empty((B, H, W), dtype=out_dtype, device=pan.device)
     else:
         _require(out, "out", 3, out_dtype)
         if tuple(out.shape) != (B, H, W):
             raise ValueError("out must be (B, H, W)")
+        if out.device != pan.device:
+            raise ValueError("out must be on the device of pan")
         if out.stride(-1) != 1:
             raise ValueError("out must have unit stride along rows")
     return pan, ms, gain, out, H, W, B
@@ -232,6 +236,21 @@ def fuse_multipass(pan: torch.Tensor, ms: torch.Tensor, wavelet="d4", out: Optio
     return out
 
 
+def _check_batch_device(device, scene_device):
+    """A batch runs on its scenes' device; an explicit `device` must be it."""
+    if device is None:
+        return
+    if isinstance(device, int):
+        idx = device
+    else:
+        d = torch.device(device)
+        if d.type != "cuda":
+            raise ValueError("device %s is not a GPU" % (device,))
+        idx = d.index if d.index is not None else torch.cuda.current_device()
+    if idx != scene_device.index:
+        raise ValueError("device %s differs from the scenes' device %s" % (device, scene_device))
+
+
 def make_items(scenes: Sequence[dict]):
     """Prepare dwt_fuse_item descriptors; each scene is a dict with keys pan,
     ms, wavelet and optionally gain, out.  Returns (items array, outs, keep)."""
@@ -239,6 +258,9 @@ def make_items(scenes: Sequence[dict]):
     arr = (Item * max(n, 1))()
     outs, keep = [], []
     for i, s in enumerate(scenes):
+        if s["pan"].device != scenes[0]["pan"].device:
+            raise ValueError("scene %d is on %s, scene 0 on %s: one batch runs on one device"
+                             % (i, s["pan"].device, scenes[0]["pan"].device))
         pan, ms, gain, out, H, W, B = _prep_scene(s["pan"], s["ms"], s.get("gain"), s.get("out"))
         keep.extend([pan, ms, gain, out])
         outs.append(out)
@@ -266,7 +288,8 @@ def fuse_batched(scenes: Sequence[dict], graph: bool = False, device=None) -> Li
     if len(scenes) == 0:
         return []
     arr, outs, keep = make_items(scenes)
-    c = context(device if device is not None else scenes[0]["pan"].device)
+    _check_batch_device(device, scenes[0]["pan"].device)
+    c = context(scenes[0]["pan"].device)
     c.bind_stream()
     st = c.lib.dwt_fuse_run_batched(c.handle, arr, len(scenes), _lib.GRAPH if graph else 0)
     c.check(st, "dwt_fuse_run_batched")
@@ -323,6 +346,9 @@ def make_bwd_items(scenes: Sequence[dict]):
     arr = (BwdItem * max(n, 1))()
     outs, keep = [], []
     for i, s in enumerate(scenes):
+        if s["pan"].device != scenes[0]["pan"].device:
+            raise ValueError("scene %d is on %s, scene 0 on %s: one batch runs on one device"
+                             % (i, s["pan"].device, scenes[0]["pan"].device))
         pan, go, gain, gp, gm, gg, H, W, B = _prep_backward(s["pan"], s["grad_out"], s.get("gain"),
                                                            s.get("need_pan", True), s.get("need_ms", True),
                                                            s.get("need_gain", True))
@@ -353,7 +379,8 @@ def fuse_backward_batched(scenes: Sequence[dict], device=None):
     if len(scenes) == 0:
         return []
     arr, outs, keep = make_bwd_items(scenes)
-    c = context(device if device is not None else scenes[0]["pan"].device)
+    _check_batch_device(device, scenes[0]["pan"].device)
+    c = context(scenes[0]["pan"].device)
     c.bind_stream()
     c.check(c.lib.dwt_fuse_backward_batched(c.handle, arr, len(scenes)), "dwt_fuse_backward_batched")
     return outs

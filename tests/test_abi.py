@@ -243,6 +243,24 @@ def test_cpu_tensors_rejected_by_binding():
         api.fuse(torch.zeros(8, 8), torch.zeros(1, 4, 4), "haar")
     with pytest.raises(ValueError, match="GPU"):
         api.fuse_backward(torch.zeros(8, 8), torch.zeros(1, 8, 8), "d4")
+    with pytest.raises(ValueError, match="GPU"):
+        api.fuse_backward_batched([dict(pan=torch.zeros(8, 8), grad_out=torch.zeros(1, 8, 8))])
+    with pytest.raises(ValueError, match="GPU"):
+        api.fuse_batched([dict(pan=torch.zeros(8, 8), ms=torch.zeros(1, 4, 4))])
+
+
+def test_batch_device_argument_checked():
+    torch = pytest.importorskip("torch")
+    from paper_1803_00737_amd import api
+
+    cuda0 = torch.device("cuda", 0)
+    api._check_batch_device(None, cuda0)
+    api._check_batch_device(0, cuda0)
+    api._check_batch_device("cuda:0", cuda0)
+    with pytest.raises(ValueError, match="differs"):
+        api._check_batch_device(1, cuda0)
+    with pytest.raises(ValueError, match="not a GPU"):
+        api._check_batch_device("cpu", cuda0)
 
 
 def test_no_oracle_in_product():
