@@ -285,15 +285,20 @@ dwt_fuse_status dwt_fuse_tune_load(dwt_fuse_ctx *ctx, const char *path);
 
 /* Force a launch shape for all later launches on this context (0 = automatic
  * for that field): coefficient rows per work unit, waves per workgroup,
- * coefficient columns per lane (1 or 2), and the kernel variant (1 = rolling
- * wavefronts that walk seg_rows rows; 2 = one-shot wavefronts of 1 or 2 rows
- * that issue all their loads up front; 3 = LDS-staged workgroups whose
- * wavefronts take seg_rows = 1, 2 or 4 rows each, D4 with 16-byte aligned rows
- * only, otherwise 2 is used).  Every shape gives bit-identical results.
- * dwt_fuse_backward follows the rows, waves and columns fields with its
- * rolling adjoint; variant 3 selects its LDS-staged D4 adjoint (16-byte
- * aligned rows, 1 or 2 rows per wavefront, up to 4 waves), which is otherwise
- * never used.  DWT_FUSE_E_SHAPE if a field is out of range. */
+ * coefficient columns per lane (1 or 2; 4-byte rows always use 1), and the
+ * kernel variant (1 = rolling wavefronts that walk seg_rows rows; 2 = one-shot
+ * wavefronts of 1 or 2 rows that issue all their loads up front; 3 =
+ * LDS-staged workgroups whose wavefronts take seg_rows = 1, 2 or 4 rows each,
+ * D4 only, otherwise 2 is used).  Every shape gives bit-identical results.
+ * dwt_fuse_run_ex with 8-bit input follows the rows and waves fields (columns
+ * 1 / 2 select 4 / 8 per lane), variant 1 (rolling D4) and variant 3
+ * (LDS-staged D4, 1 or 2 rows per wavefront); other format combinations use
+ * one-shot tiles.  dwt_fuse_backward and dwt_fuse_backward_batched follow the
+ * rows, waves and columns fields with the rolling adjoint and variant 2 with
+ * one-shot D4 adjoint tiles; variant 3 selects the LDS-staged D4 adjoint
+ * (dwt_fuse_backward only, 16-byte aligned rows, 1 or 2 rows per wavefront,
+ * up to 4 waves), which is otherwise never used.  DWT_FUSE_E_SHAPE if a field
+ * is out of range. */
 dwt_fuse_status dwt_fuse_force_tile(dwt_fuse_ctx *ctx, int seg_rows, int waves_per_block, int cols_per_lane,
                                     int variant);
 
