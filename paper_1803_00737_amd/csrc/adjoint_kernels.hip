@@ -1036,22 +1036,231 @@ __global__ __launch_bounds__(256) void d4_adjoint_staged_kernel(AdjParams p, Fil
     }
 }
 
+// The same tile with the upstream gradients of a group of up to bg_all bands
+// staged together: PAN and the group's y rows go to LDS at once, one barrier,
+// then every band of the group is computed from LDS without further waits
+// (per-pixel values as in the kernel above, so results are bit-identical).
+template <int KR>
+__global__ __launch_bounds__(256) void d4_adjoint_staged_all_kernel(AdjParams p, Filters f, int bg_all) {
+    extern __shared__ float lds[];
+    const int wpb = blockDim.x >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int T = wpb * KR;
+    const int unit = xcd_remap(blockIdx.x, gridDim.x);
+    if (unit >= p.units) return;  // whole workgroup
+    int strip, trow;
+    if (p.order) {
+        trow = unit / p.nstrips;
+        strip = unit - trow * p.nstrips;
+    } else {
+        strip = unit / p.nseg;
+        trow = unit - strip * p.nseg;
+    }
+    const int W2 = p.W >> 1, H2 = p.H >> 1;
+    const int sb = strip * 128, r0 = trow * T;
+    const int rows = 2 * T + 4;
+    float *Pl = lds;
+    float *Yl = lds + rows * kAdjRow;                  // bg_all images of `rows` rows
+    float *red = lds + (1 + bg_all) * rows * kAdjRow;  // [band][wavefront] partial products
+
+    auto stage_group = [&](int g0, int bg) {
+        for (int bi = 0; bi < bg; ++bi)
+            adj_stage_rows(p.gy + (int64_t)(g0 + bi) * p.gy_bs, p.gy_ld, p.H, p.W, r0, T, sb, Yl + bi * rows * kAdjRow,
+                           w, wpb, lane);
+    };
+    adj_stage_rows(p.pan, p.pan_ld, p.H, p.W, r0, T, sb, Pl, w, wpb, lane);
+    stage_group(0, min(bg_all, p.B));
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+
+    const int rb = r0 + KR * w;
+    const int nr = max(0, min(KR, H2 - rb));
+    const int s0 = sb + 2 * lane;
+    const bool active = s0 < W2, full = s0 + 2 <= W2;
+    const float h[4] = {f.h[0], f.h[1], f.h[2], f.h[3]};
+    constexpr int NR = 2 * KR + 4;
+    auto read_row = [&](const float *base, int t, f2 (&x)[4]) {
+        const float *src = base + (2 * KR * w + t) * kAdjRow + 4 * lane;
+        x[0] = *reinterpret_cast<const f2 *>(src + 2);
+        const f4 v = *reinterpret_cast<const f4 *>(src + 4);
+        x[1] = f2{v.x, v.y};
+        x[2] = f2{v.z, v.w};
+        x[3] = *reinterpret_cast<const f2 *>(src + 8);
+    };
+    f2 D[2 * KR][2];
+    {
+        float R[NR][3];
+        f2 own[2 * KR][2];
+#pragma unroll
+        for (int t = 0; t < NR; ++t) {
+            f2 x[4];
+            read_row(Pl, t, x);
+            rowfilt<2>(h, x, R[t]);
+            if (t >= 2 && t < 2 + 2 * KR) {
+                own[t - 2][0] = x[1];
+                own[t - 2][1] = x[2];
+            }
+        }
+        float A[KR + 1][3];
+#pragma unroll
+        for (int i = 0; i <= KR; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) A[i][j] = col4(h, R[2 * i][j], R[2 * i + 1][j], R[2 * i + 2][j], R[2 * i + 3][j]);
+#pragma unroll
+        for (int i = 0; i < KR; ++i) {
+            f2 sa[2], sb2[2];
+            synth_rows<2>(h, A[i + 1], A[i], sa, sb2);
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                D[2 * i][c] = own[2 * i][c] - sa[c];
+                D[2 * i + 1][c] = own[2 * i + 1][c] - sb2[c];
+            }
+        }
+    }
+    float LY[KR + 1][3];
+    f2 Y[2 * KR][2];
+#pragma unroll
+    for (int i = 0; i <= KR; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) LY[i][j] = 0.f;
+#pragma unroll
+    for (int t = 0; t < 2 * KR; ++t) Y[t][0] = Y[t][1] = f2{0.f, 0.f};
+
+    for (int g0 = 0; g0 < p.B; g0 += bg_all) {
+        const int bg = min(bg_all, p.B - g0);
+        if (g0 > 0) {  // every wavefront is done with the previous group's rows
+            __syncthreads();
+            stage_group(g0, bg);
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+        }
+        for (int bi = 0; bi < bg; ++bi) {
+            const int b = g0 + bi;
+            const float *Yb = Yl + bi * rows * kAdjRow;
+            const float g = p.gain ? p.gain[b] : 1.0f;
+            float R[NR][3];
+            f2 yo[2 * KR][2];
+#pragma unroll
+            for (int t = 0; t < NR; ++t) {
+                f2 x[4];
+                read_row(Yb, t, x);
+                rowfilt<2>(h, x, R[t]);
+                if (t >= 2 && t < 2 + 2 * KR) {
+                    yo[t - 2][0] = x[1];
+                    yo[t - 2][1] = x[2];
+                }
+            }
+            float Ly[KR + 1][3];
+#pragma unroll
+            for (int i = 0; i <= KR; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+                    Ly[i][j] = col4(h, R[2 * i][j], R[2 * i + 1][j], R[2 * i + 2][j], R[2 * i + 3][j]);
+            float dot = 0.f;
+            if (active) {
+#pragma unroll
+                for (int t = 0; t < 2 * KR; ++t) {
+                    if (t >= 2 * nr) break;
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        if (c == 1 && !full) break;
+                        Y[t][c].x = fmaf(g, yo[t][c].x, Y[t][c].x);
+                        Y[t][c].y = fmaf(g, yo[t][c].y, Y[t][c].y);
+                        dot = fmaf(yo[t][c].x, D[t][c].x, dot);
+                        dot = fmaf(yo[t][c].y, D[t][c].y, dot);
+                    }
+                }
+            }
+#pragma unroll
+            for (int i = 0; i <= KR; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) LY[i][j] = fmaf(g, Ly[i][j], LY[i][j]);
+            if (p.partial) {
+                const float sd = wave_sum(dot);
+                if (lane == 0) red[b * wpb + w] = sd;
+            }
+            if (active && p.grad_ms) {
+#pragma unroll
+                for (int i = 0; i < KR; ++i) {
+                    if (i >= nr) break;
+                    float *gm = p.grad_ms + (int64_t)b * H2 * W2 + (int64_t)(rb + i) * W2 + s0;
+                    if (full)
+                        *reinterpret_cast<f2 *>(gm) = f2{Ly[i + 1][1], Ly[i + 1][2]};
+                    else
+                        gm[0] = Ly[i + 1][1];
+                }
+            }
+        }
+    }
+    if (p.grad_pan && active) {
+#pragma unroll
+        for (int i = 0; i < KR; ++i) {
+            if (i >= nr) break;
+            f2 sa[2], sb2[2], q0[2], q1[2];
+            synth_rows<2>(h, LY[i + 1], LY[i], sa, sb2);
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                q0[c] = Y[2 * i][c] - sa[c];
+                q1[c] = Y[2 * i + 1][c] - sb2[c];
+            }
+            float *g0p = p.grad_pan + (int64_t)(2 * (rb + i)) * p.W + 2 * s0;
+            if (full) {
+                *reinterpret_cast<f4 *>(g0p) = f4{q0[0].x, q0[0].y, q0[1].x, q0[1].y};
+                *reinterpret_cast<f4 *>(g0p + p.W) = f4{q1[0].x, q1[0].y, q1[1].x, q1[1].y};
+            } else {
+                *reinterpret_cast<f2 *>(g0p) = q0[0];
+                *reinterpret_cast<f2 *>(g0p + p.W) = q1[0];
+            }
+        }
+    }
+    if (p.partial) {  // fixed-order sum over the wavefronts
+        __syncthreads();
+        for (int bb = threadIdx.x; bb < p.B; bb += blockDim.x) {
+            float t = 0.f;
+            for (int k = 0; k < wpb; ++k) t += red[bb * wpb + k];
+            p.partial[(int64_t)unit * p.pstride + bb] = t;
+        }
+    }
+}
+
 }  // namespace
 
 // LDS bytes of the staged adjoint for T coefficient rows and B bands.
-size_t adjoint_staged_lds(int T, int B) {
-    return sizeof(float) * ((size_t)3 * (2 * T + 4) * kAdjRow + (size_t)B * 4);  // red: B x (wpb <= 4)
+// Bands whose upstream-gradient rows a staged tile of T rows holds at once
+// next to its PAN rows in 64 KB of LDS (all-bands form), at most B.
+static int adjoint_staged_group(int T, int B) {
+    const int img = (2 * T + 4) * kAdjRow;
+    const int g = (16384 - img - 4 * B) / img;
+    return g < B ? g : B;
 }
 
-hipError_t launch_adjoint_staged(const AdjParams &p, const Filters &f, int kr, int wpb, hipStream_t s) {
+size_t adjoint_staged_lds(int T, int B, bool all) {
+    const size_t img = (size_t)(2 * T + 4) * kAdjRow;
+    const size_t red = (size_t)B * 4;  // [band][wavefront <= 4]
+    if (!all) return sizeof(float) * (3 * img + red);
+    const int g = adjoint_staged_group(T, B);
+    return g < 1 ? (size_t)1 << 30 : sizeof(float) * ((1 + (size_t)g) * img + red);
+}
+
+hipError_t launch_adjoint_staged(const AdjParams &p, const Filters &f, int kr, int wpb, bool all, hipStream_t s) {
     if (p.units <= 0) return hipSuccess;
     if (p.wavelet != 1 || p.path != PATH_V4 || p.seg_rows != kr * wpb || p.nstrips != (p.W / 2 + 127) / 128)
         return hipErrorInvalidValue;
-    const size_t lds = adjoint_staged_lds(p.seg_rows, p.B);
+    const size_t lds = adjoint_staged_lds(p.seg_rows, p.B, all);
     if (lds > 65536) return hipErrorInvalidValue;
+    const dim3 grid(p.units), block(64 * wpb);
+    if (all) {
+        const int g = adjoint_staged_group(p.seg_rows, p.B);
+        switch (kr) {
+            case 1: hipLaunchKernelGGL(d4_adjoint_staged_all_kernel<1>, grid, block, lds, s, p, f, g); break;
+            case 2: hipLaunchKernelGGL(d4_adjoint_staged_all_kernel<2>, grid, block, lds, s, p, f, g); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     switch (kr) {
-        case 1: hipLaunchKernelGGL(d4_adjoint_staged_kernel<1>, dim3(p.units), dim3(64 * wpb), lds, s, p, f); break;
-        case 2: hipLaunchKernelGGL(d4_adjoint_staged_kernel<2>, dim3(p.units), dim3(64 * wpb), lds, s, p, f); break;
+        case 1: hipLaunchKernelGGL(d4_adjoint_staged_kernel<1>, grid, block, lds, s, p, f); break;
+        case 2: hipLaunchKernelGGL(d4_adjoint_staged_kernel<2>, grid, block, lds, s, p, f); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

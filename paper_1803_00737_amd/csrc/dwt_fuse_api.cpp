@@ -1782,7 +1782,7 @@ dwt_fuse_status dwt_fuse_backward(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet, i
         const int skr = ctx->forced.seg_rows == 2 ? 2 : 1;
         const int swpb = ctx->forced.wpb >= 1 && ctx->forced.wpb <= 4 ? ctx->forced.wpb : 4;
         const bool staged = a.wavelet == DWT_FUSE_D4 && path == PATH_V4 && ctx->forced.variant == 3 &&
-                            adjoint_staged_lds(skr * swpb, (int)B) <= 65536;
+                            adjoint_staged_lds(skr * swpb, (int)B, ctx->forced.nc != 1) <= 65536;
         if (staged) {
             const int kr = skr, wpb = swpb, T = kr * wpb;
             const int64_t ns = (W / 2 + 127) / 128, ng = (H / 2 + T - 1) / T;
@@ -1815,7 +1815,7 @@ dwt_fuse_status dwt_fuse_backward(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet, i
             p.order = 0;
             p.pstride = (int32_t)B;
             p.accumulate = 0;
-            hipError_t e = launch_adjoint_staged(p, ctx->filt, kr, wpb, ctx->stream);
+            hipError_t e = launch_adjoint_staged(p, ctx->filt, kr, wpb, ctx->forced.nc != 1, ctx->stream);
             if (e != hipSuccess) return hip_fail(ctx, e, "staged adjoint launch");
             if (grad_gain) {
                 e = launch_gain_reduce(partial, units, (int)B, grad_gain, ctx->stream);

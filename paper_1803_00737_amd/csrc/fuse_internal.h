@@ -153,8 +153,10 @@ int adjoint_max_bands();
 
 // LDS-staged D4 adjoint (16-byte rows): units are strips of 128 coefficient
 // columns x (kr * wpb) coefficient rows, one workgroup each; any band count.
-hipError_t launch_adjoint_staged(const AdjParams &p, const Filters &f, int kr, int wpb, hipStream_t s);
-size_t adjoint_staged_lds(int T, int B);
+// all: the upstream gradients of a group of bands are staged together (one
+// barrier per group) instead of band after band into two alternating buffers.
+hipError_t launch_adjoint_staged(const AdjParams &p, const Filters &f, int kr, int wpb, bool all, hipStream_t s);
+size_t adjoint_staged_lds(int T, int B, bool all);
 
 // Format variants (codec_kernels.hip): pan/ms 8-bit with out float32 or 8-bit,
 // or pan/ms float32 with out 8-bit; MS scaled by kappa.  Units are one-shot wavefronts over a strip of

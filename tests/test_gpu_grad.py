@@ -75,7 +75,8 @@ def test_forced_adjoint_shapes(dev, fz, oracle, H, W, B):
     band loop unrolled for up to 4 bands; variant 1: a dynamic band loop),
     one-shot tiles of
     1 or 2 rows (variant 2), and the LDS-staged D4 adjoint (variant 3, 1 or 2
-    rows per wavefront).  Every shape must meet the oracle's tolerance; all
+    rows per wavefront; upstream gradients staged a group of bands at a time,
+    or with 1 column per lane requested, band after band in two buffers).  Every shape must meet the oracle's tolerance; all
     of them form every per-pixel gradient with the same fma chains in the same
     order, so grad_pan and grad_ms also agree bit for bit."""
     rng = np.random.default_rng(7 * H + W + B)
@@ -89,7 +90,8 @@ def test_forced_adjoint_shapes(dev, fz, oracle, H, W, B):
         for seg, wpb, nc, var in [(0, 0, 0, 0), (1, 1, 1, 1), (3, 2, 2, 1), (16, 4, 2, 1), (200, 1, 1, 1),
                                   (1, 1, 1, 0), (3, 2, 2, 0), (16, 4, 2, 0), (200, 1, 1, 0),
                                   (1, 4, 2, 2), (2, 2, 2, 2), (2, 1, 1, 2), (1, 2, 1, 2),
-                                  (1, 4, 2, 3), (2, 2, 2, 3), (1, 1, 2, 3), (2, 4, 2, 3)]:
+                                  (1, 4, 2, 3), (2, 2, 2, 3), (1, 1, 2, 3), (2, 4, 2, 3), (1, 4, 1, 3),
+                                  (2, 2, 1, 3)]:
             say("adjoint forced", H, W, B, seg, wpb, nc, var)
             ctx.force_tile(seg, wpb, nc, var)
             got = [t.cpu().numpy() for t in fz.fuse_backward(p, y, "d4", g)]
