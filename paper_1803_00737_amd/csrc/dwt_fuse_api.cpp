@@ -1173,7 +1173,7 @@ dwt_fuse_status dwt_fuse_tune_load(dwt_fuse_ctx *ctx, const char *path) {
         tab[key] = t;
     }
     std::fclose(f);
-    if (!ok) return fail(ctx, DWT_FUSE_E_STATE, "tuning file does not match this build/device or is corrupt; ignored");
+    if (!ok) return fail(ctx, DWT_FUSE_E_STATE, "tuning file does not match this library version/device or is corrupt; ignored");
     for (const auto &kv : tab) ctx->table[kv.first] = kv.second;
     return DWT_FUSE_OK;
 }
