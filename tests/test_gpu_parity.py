@@ -57,6 +57,36 @@ def test_d4_within_tolerance(dev, fz, oracle, H, W, B):
     assert np.abs(out - ref).max() <= D4_TOL
 
 
+@pytest.mark.parametrize("wavelet", ["haar", "d4"])
+@pytest.mark.parametrize("H,W", [(2, 1 << 20), (1 << 20, 2), (4, (1 << 19) + 6), ((1 << 18) + 2, 6)])
+def test_extreme_aspect_ratios(dev, fz, oracle, wavelet, H, W):
+    """One-row-pair and one-column-pair images a million pixels long (every
+    D4 tap wraps along the short side; strips or tiles by the thousand along
+    the long one), in the default and the tuned launch shapes, forward and
+    adjoint, against the oracle over the whole image."""
+    rng = np.random.default_rng(H + W)
+    pan, ms = int_scene(rng, H, W, 2)
+    say("aspect", wavelet, H, W)
+    p, m = to_dev(pan, dev), to_dev(ms, dev)
+    ref = oracle_out(oracle, wavelet, pan, ms)
+    ctx = fz.context(dev)
+    for tuned in (False, True):
+        ctx.set_tuning(tuned)
+        try:
+            out = fz.fuse(p, m, wavelet).cpu().numpy()
+        finally:
+            ctx.set_tuning(False)
+        if wavelet == "haar":
+            assert np.array_equal(out, ref.astype(np.float32))
+        else:
+            assert np.abs(out - ref).max() <= D4_TOL
+    gy = rng.normal(size=(2, H, W)).astype(np.float32)
+    gp, gm, _ = fz.fuse_backward(p, to_dev(gy, dev), wavelet, need_gain=False)
+    rp, rm, _ = oracle.fuse_backward(wavelet, pan.astype(np.float64), None, gy.astype(np.float64))
+    assert np.abs(gp.cpu().numpy() - rp).max() <= 16e-5 * max(1.0, np.abs(rp).max())
+    assert np.abs(gm.cpu().numpy() - rm).max() <= 16e-5 * max(1.0, np.abs(rm).max())
+
+
 def test_haar_workload_512(dev, fz, oracle):
     from paper_1803_00737_amd import synth
 
