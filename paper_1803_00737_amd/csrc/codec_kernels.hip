@@ -159,6 +159,53 @@ struct CodecCols {
         }
         x[NC + 1] = ld_pair<TI, AL>(row + 2 * pc[NC + 1]);
     }
+    // 8-bit rows: the lane's own 2*NC pixels as packed words, and the two halo
+    // pairs as 16-bit words (low byte first).
+    __device__ __forceinline__ void load_row_raw(const TI *row, uint32_t (&w)[NC / 2], uint32_t &hl,
+                                                 uint32_t &hr) const {
+        if constexpr (AL) {
+            hl = *reinterpret_cast<const uint16_t *>(row + 2 * pc[0]);
+            hr = *reinterpret_cast<const uint16_t *>(row + 2 * pc[NC + 1]);
+        } else {
+            hl = (uint32_t)row[2 * pc[0]] | ((uint32_t)row[2 * pc[0] + 1] << 8);
+            hr = (uint32_t)row[2 * pc[NC + 1]] | ((uint32_t)row[2 * pc[NC + 1] + 1] << 8);
+        }
+        if (AL && full) {
+            if constexpr (NC == 4) {
+                const u2 v = *reinterpret_cast<const u2 *>(row + 2 * s0);
+                w[0] = v.x;
+                w[1] = v.y;
+            } else {
+                const u4 v = *reinterpret_cast<const u4 *>(row + 2 * s0);
+                w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < NC / 2; ++j) {
+                const uint32_t a0 = row[2 * pc[2 * j + 1]], a1 = row[2 * pc[2 * j + 1] + 1];
+                const uint32_t b0 = row[2 * pc[2 * j + 2]], b1 = row[2 * pc[2 * j + 2] + 1];
+                w[j] = a0 | (a1 << 8) | (b0 << 16) | (b1 << 24);
+            }
+        }
+    }
+    // 8-bit MS row: halo coefficient pc[0] in w[0], own NC coefficients packed in w[1..].
+    __device__ __forceinline__ void load_ms_raw(const TI *mrow, uint32_t (&w)[1 + NC / 4]) const {
+        w[0] = mrow[pc[0]];
+        if (AL && full) {
+            if constexpr (NC == 4) {
+                w[1] = *reinterpret_cast<const uint32_t *>(mrow + s0);
+            } else {
+                const u2 v = *reinterpret_cast<const u2 *>(mrow + s0);
+                w[1] = v.x;
+                w[2] = v.y;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < NC / 4; ++j)
+                w[1 + j] = (uint32_t)mrow[pc[4 * j + 1]] | ((uint32_t)mrow[pc[4 * j + 2]] << 8) |
+                           ((uint32_t)mrow[pc[4 * j + 3]] << 16) | ((uint32_t)mrow[pc[4 * j + 4]] << 24);
+        }
+    }
     __device__ __forceinline__ void load_own(const TI *row, f2 (&x)[NC]) const {
         if (AL && full) {
             ld_own_vec<TI, NC>(row + 2 * s0, &x[0]);
@@ -309,6 +356,125 @@ __device__ __forceinline__ void d4_codec_tile(const CodecParams &p, const Filter
     }
 }
 
+// D4, 8-bit in and out, one-shot tile: as d4_codec_tile, with the PAN pixels of
+// the output rows and the MS rows kept as packed bytes (4 per register) and
+// converted where they are used, which lowers the register count enough for
+// one more wavefront per SIMD (the 8-bit path is bound by latency at its
+// occupancy).  Same operations in the same order, so the same results.
+template <typename TI, typename TO, int NC, int KR, bool AL>
+__device__ __forceinline__ void d4_codec_tile_u8(const CodecParams &p, const Filters &f, int strip, int seg, int lane) {
+    static_assert(sizeof(TI) == 1 && sizeof(TO) == 1 && (NC == 4 || NC == 8), "8-bit in and out");
+    const CodecCols<TI, NC, AL> L(strip, lane, p.W >> 1);
+    if (!L.active()) return;
+    const TI *pan = static_cast<const TI *>(p.pan);
+    const TI *ms = static_cast<const TI *>(p.ms);
+    TO *out = static_cast<TO *>(p.out);
+    const int H2 = p.H >> 1;
+    const int rb = seg * KR;
+    const int nr = min(KR, H2 - rb);
+    constexpr int NR = 2 * KR + 4;  // PAN rows 2rb-2 .. 2rb+2KR+1
+    // Rows lie in [-2, H + 2KR - 1] and [-1, H2 + KR - 1].
+    auto wrow = [](int y, int n) { return wrap_row(y, n); };
+    // Every PAN row of the tile, packed: own pixels 4 per word, halo pairs 2 per word.
+    uint32_t rw[NR][NC / 2], hl[NR], hr[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k)
+        L.load_row_raw(pan + (int64_t)wrow(2 * rb - 2 + k, p.H) * p.pan_ld, rw[k], hl[k], hr[k]);
+    uint32_t raw[2 * KR][NC / 2];  // own pixels of the output rows
+#pragma unroll
+    for (int t = 0; t < 2 * KR; ++t)
+#pragma unroll
+        for (int j = 0; j < NC / 2; ++j) raw[t][j] = rw[t + 2][j];
+    int64_t mrow[KR + 1];  // MS row offsets, the same for every band
+#pragma unroll
+    for (int i = 0; i <= KR; ++i) mrow[i] = (int64_t)wrow(rb - 1 + i, H2) * p.ms_ld;
+    constexpr int MW = 1 + NC / 4;
+    auto load_band = [&](int b, uint32_t(&m)[KR + 1][MW]) {
+        const TI *mb = ms + (int64_t)b * p.ms_bs;
+#pragma unroll
+        for (int i = 0; i <= KR; ++i) L.load_ms_raw(mb + mrow[i], m[i]);
+    };
+    const bool unit_kappa = p.kappa == 1.0f;  // kappa * m == m exactly: skip the multiply
+    uint32_t m[KR + 1][MW];
+    load_band(0, m);
+    float A[KR + 1][NC + 1];
+    {
+        float R[NR][NC + 1];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {  // each row converted just before it is filtered
+            f2 x[NC + 2];
+            x[0] = f2{byte_at(hl[k], 0), byte_at(hl[k], 1)};
+#pragma unroll
+            for (int j = 0; j < NC; ++j)
+                x[j + 1] = f2{byte_at(rw[k][j >> 1], 2 * (j & 1)), byte_at(rw[k][j >> 1], 2 * (j & 1) + 1)};
+            x[NC + 1] = f2{byte_at(hr[k], 0), byte_at(hr[k], 1)};
+            rowfilt<NC>(f, x, R[k]);
+        }
+#pragma unroll
+        for (int i = 0; i <= KR; ++i) colfilt<NC>(f, R[2 * i], R[2 * i + 1], R[2 * i + 2], R[2 * i + 3], A[i]);
+    }
+    const float h0 = f.h[0], h1 = f.h[1], h2 = f.h[2], h3 = f.h[3];
+    for (int b = 0; b < p.B; ++b) {
+        uint32_t mn[KR + 1][MW];
+        if (b + 1 < p.B) load_band(b + 1, mn);
+        const float g = p.gain ? p.gain[b] : 1.0f;
+        TO *ob = out + (int64_t)b * p.out_bs;
+        // Coefficient rows rb-1 .. rb+KR-1 of (kappa m - g L PAN), each formed
+        // once; then the synthesis of d4_out_rows, operation for operation.
+        float c[KR + 1][NC + 1];
+#pragma unroll
+        for (int i = 0; i <= KR; ++i)
+#pragma unroll
+            for (int j = 0; j <= NC; ++j) {
+                const float mv = j == 0 ? (float)m[i][0] : byte_at(m[i][1 + ((j - 1) >> 2)], (j - 1) & 3);
+                c[i][j] = fmaf(-g, A[i][j], unit_kappa ? mv : p.kappa * mv);
+            }
+#pragma unroll
+        for (int i = 0; i < KR; ++i) {
+            if (i >= nr) break;
+            float v0[NC + 1], v1[NC + 1];
+#pragma unroll
+            for (int j = 0; j <= NC; ++j) {
+                v0[j] = fmaf(h2, c[i][j], h0 * c[i + 1][j]);
+                v1[j] = fmaf(h3, c[i][j], h1 * c[i + 1][j]);
+            }
+            // The PAN pixels stay packed across the band loop and are converted
+            // again for every band: the empty asm makes the packed words look
+            // changed here, so the compiler does not hoist the conversions out of
+            // the loop and hold the floats (which costs the occupancy).
+            f2 xa[NC + 1], xb[NC + 1];
+#pragma unroll
+            for (int j = 0; j < NC / 2; ++j) {
+                asm volatile("" : "+v"(raw[2 * i][j]));
+                asm volatile("" : "+v"(raw[2 * i + 1][j]));
+            }
+#pragma unroll
+            for (int j = 0; j < NC; ++j) {
+                xa[j + 1] = f2{byte_at(raw[2 * i][j >> 1], 2 * (j & 1)), byte_at(raw[2 * i][j >> 1], 2 * (j & 1) + 1)};
+                xb[j + 1] = f2{byte_at(raw[2 * i + 1][j >> 1], 2 * (j & 1)),
+                               byte_at(raw[2 * i + 1][j >> 1], 2 * (j & 1) + 1)};
+            }
+            f2 q0[NC], q1[NC];
+#pragma unroll
+            for (int k = 0; k < NC; ++k) {
+                q0[k].x = fmaf(g, xa[k + 1].x, fmaf(h2, v0[k], h0 * v0[k + 1]));
+                q0[k].y = fmaf(g, xa[k + 1].y, fmaf(h3, v0[k], h1 * v0[k + 1]));
+                q1[k].x = fmaf(g, xb[k + 1].x, fmaf(h2, v1[k], h0 * v1[k + 1]));
+                q1[k].y = fmaf(g, xb[k + 1].y, fmaf(h3, v1[k], h1 * v1[k + 1]));
+            }
+            TO *o0 = ob + (int64_t)(2 * (rb + i)) * p.out_ld;
+            store_out<TO, NC, AL>(o0, L.s0, L.W2, L.full, q0);
+            store_out<TO, NC, AL>(o0 + p.out_ld, L.s0, L.W2, L.full, q1);
+        }
+        if (b + 1 < p.B) {
+#pragma unroll
+            for (int i = 0; i <= KR; ++i)
+#pragma unroll
+                for (int j = 0; j < MW; ++j) m[i][j] = mn[i][j];
+        }
+    }
+}
+
 // D4, rolling: the wavefront walks p.seg_rows coefficient rows of its strip,
 // keeping two row-filtered PAN rows, the PAN pixels of the current row pair
 // and one row of L PAN in registers, so each PAN row is unpacked and
@@ -452,6 +618,8 @@ __global__ __launch_bounds__(256) void codec_kernel(CodecParams p, Filters f) {
     if constexpr (WAV == 1) {
         if constexpr (KR == 0)
             d4_codec_rolling<TI, TO, NC, AL>(p, f, strip, seg, lane);
+        else if constexpr (sizeof(TI) == 1 && sizeof(TO) == 1)
+            d4_codec_tile_u8<TI, TO, NC, KR, AL>(p, f, strip, seg, lane);
         else
             d4_codec_tile<TI, TO, NC, KR, AL>(p, f, strip, seg, lane);
     } else {
