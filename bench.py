@@ -129,7 +129,7 @@ def run_copy(torch, steps):
     print(json.dumps({"mode": "copy", "bytes_read": 4 * n, "bytes_written": 4 * n, "ms": ms, "GB/s": gbs}))
 
 
-def cpu_baseline(pan_d, ms_d, wavelet, budget_s=8.0, max_passes=6):
+def cpu_baseline(pan_d, ms_d, wavelet, budget_s=12.0, max_passes=8):
     """The FP64 oracle as it stands (plain C, one thread) on the benchmark's own
     inputs: whole passes over the workload until about budget_s seconds have
     run; the rate is total output pixels over total time."""
