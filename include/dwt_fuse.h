@@ -65,8 +65,9 @@ typedef struct dwt_fuse_ctx dwt_fuse_ctx; /* opaque */
  * graphs, the tuning table).  On failure *ctx is set to NULL. */
 dwt_fuse_status dwt_fuse_create(dwt_fuse_ctx **ctx, int device, void *hip_stream);
 
-/* Release a context and everything it owns.  NULL is ignored.  The caller
- * must make sure no work issued through the context is still running. */
+/* Release a context and everything it owns.  NULL is ignored.  Waits for
+ * all work on the context's device first (hipDeviceSynchronize), so work
+ * issued through the context never reads freed memory. */
 void dwt_fuse_destroy(dwt_fuse_ctx *ctx);
 
 /* Make subsequent calls use `hip_stream` (same device).  When the stream

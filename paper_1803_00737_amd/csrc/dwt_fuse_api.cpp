@@ -773,7 +773,9 @@ Tile tile_for_run(dwt_fuse_ctx *c, const RunArgs &a, Path path, bool allow_tune)
 dwt_fuse_status ensure_ws(dwt_fuse_ctx *c, size_t bytes) {
     if (bytes <= c->ws_bytes) return DWT_FUSE_OK;
     if (c->ws) {
-        (void)hipStreamSynchronize(c->stream);
+        // earlier work may still use the buffer; a failed wait leaves it in place
+        const hipError_t e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize before growing the workspace");
         (void)hipFree(c->ws);
         c->ws = nullptr;
         c->ws_bytes = 0;
@@ -803,7 +805,8 @@ dwt_fuse_status ensure_batch_tables(dwt_fuse_ctx *c, size_t n) {
     }
     if (n <= c->scenes_cap) return DWT_FUSE_OK;
     // Growing moves the device table: captured graphs point at the old one.
-    (void)hipStreamSynchronize(c->stream);
+    const hipError_t se = hipStreamSynchronize(c->stream);
+    if (se != hipSuccess) return hip_fail(c, se, "hipStreamSynchronize before growing the scene table");
     clear_graphs(c);
     if (c->d_scenes) (void)hipFree(c->d_scenes);
     if (c->h_scenes) (void)hipHostFree(c->h_scenes);
@@ -1059,6 +1062,9 @@ void dwt_fuse_destroy(dwt_fuse_ctx *ctx) {
         int cur = -1;
         (void)hipGetDevice(&cur);
         (void)hipSetDevice(ctx->device);
+        // Work issued through the context may still read its workspace and
+        // tables; wait for the device (the context's stream may already be gone).
+        (void)hipDeviceSynchronize();
         clear_graphs(ctx);
         if (ctx->ws) (void)hipFree(ctx->ws);
         if (ctx->mp) (void)hipFree(ctx->mp);
@@ -1652,7 +1658,8 @@ dwt_fuse_status dwt_fuse_run_multipass(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavel
         const size_t need = sizeof(float) * 2 * (size_t)H * (size_t)W;
         if (need > ctx->mp_bytes) {
             if (ctx->mp) {
-                (void)hipStreamSynchronize(ctx->stream);
+                const hipError_t e = hipStreamSynchronize(ctx->stream);
+                if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamSynchronize before growing the work arrays");
                 (void)hipFree(ctx->mp);
                 ctx->mp = nullptr;
                 ctx->mp_bytes = 0;
@@ -1871,7 +1878,8 @@ dwt_fuse_status ensure_bwd_tables(dwt_fuse_ctx *c, size_t bytes) {
         }
     }
     if (bytes <= c->bwd_bytes) return DWT_FUSE_OK;
-    (void)hipStreamSynchronize(c->stream);
+    const hipError_t se = hipStreamSynchronize(c->stream);
+    if (se != hipSuccess) return hip_fail(c, se, "hipStreamSynchronize before growing the backward tables");
     if (c->d_bwd) (void)hipFree(c->d_bwd);
     if (c->h_bwd) (void)hipHostFree(c->h_bwd);
     c->d_bwd = nullptr;
