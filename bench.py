@@ -117,7 +117,9 @@ def read_traffic(bytes_per_launch):
         return None
 
 
-def run_copy(torch, steps):
+def copy_rate(torch, steps):
+    """GB/s of a 1 GiB device-to-device copy (torch's copy kernel): what a
+    plain streaming read + write attains on this GPU."""
     n = 1 << 28  # 1 GiB of float32
     a = torch.ones(n, device="cuda")
     b = torch.empty_like(a)
@@ -125,7 +127,13 @@ def run_copy(torch, steps):
         b.copy_(a)
     torch.cuda.synchronize()
     ms = time_loop(torch, lambda: b.copy_(a), steps, 2)
-    gbs = 2 * 4 * n / (ms * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * 4 * n / (ms * 1e-3) / 1e9, ms, n
+
+
+def run_copy(torch, steps):
+    gbs, ms, n = copy_rate(torch, steps)
     print(json.dumps({"mode": "copy", "bytes_read": 4 * n, "bytes_written": 4 * n, "ms": ms, "GB/s": gbs}))
 
 
@@ -149,6 +157,54 @@ def cpu_baseline(pan_d, ms_d, wavelet, budget_s=12.0, max_passes=8):
             "sample": "%d whole passes over the workload (same inputs) of the FP64 oracle, 1 thread, %.1f s"
                       % (passes, total),
             "host": {"cpu": cpu_model(), "logical_cpus": os.cpu_count()}}
+
+
+def cpu_oracle_rates(torch, synth, pan_d, ms_d, wavelet):
+    """Further FP64-oracle rates beside the baseline figure (same oracle, as it
+    stands): the Haar 512x512 scene and a 1/8 row strip of the Landsat-shaped
+    scene (its top 1984 rows as an image of their own) for each wavelet, one
+    thread; and the primary workload with one thread per band (the oracle's
+    C calls release the interpreter lock, so the bands run in parallel)."""
+    import concurrent.futures
+    import numpy as np
+    import oracle
+
+    def rate(fn, px, budget_s):
+        total, passes = 0.0, 0
+        while passes == 0 or (total < budget_s and passes < 20):
+            t0 = time.perf_counter()
+            fn()
+            total += time.perf_counter() - t0
+            passes += 1
+        return px * passes / total / 1e6, passes, total
+
+    out = {}
+    wl = synth.haar_512()
+    pan, ms = wl.make()
+    r, n, t = rate(lambda: oracle.fuse("haar", pan, ms), wl.B * wl.H * wl.W, 1.0)
+    out[wl.name] = {"Mpix/s": r, "threads": 1, "sample": "%d passes, %.2f s" % (n, t)}
+    dev = pan_d.device
+    for w in ("haar", "d4"):
+        wl = synth.landsat(w)
+        p_d, m_d = wl.make(device=dev)
+        rows = 1984
+        pan = p_d[:rows].cpu().numpy().astype(np.float64)
+        ms = m_d[:, : rows // 2].cpu().numpy().astype(np.float64)
+        del p_d, m_d
+        torch.cuda.empty_cache()
+        r, n, t = rate(lambda: oracle.fuse(w, pan, ms), wl.B * rows * wl.W, 2.0)
+        out[wl.name + "_strip1984"] = {"Mpix/s": r, "threads": 1,
+                                       "sample": "rows 0-1983 as an image, %d passes, %.2f s" % (n, t)}
+        del pan, ms
+    pan = pan_d.cpu().numpy().astype(np.float64)
+    ms = ms_d.cpu().numpy().astype(np.float64)
+    B = ms.shape[0]
+    with concurrent.futures.ThreadPoolExecutor(max_workers=B) as ex:
+        def one_pass():
+            list(ex.map(lambda b: oracle.fuse(wavelet, pan, ms[b:b + 1]), range(B)))
+        r, n, t = rate(one_pass, B * pan.shape[0] * pan.shape[1], 4.0)
+    out["primary_one_thread_per_band"] = {"Mpix/s": r, "threads": B, "sample": "%d passes, %.2f s" % (n, t)}
+    return out
 
 
 def cpu_model():
@@ -454,7 +510,8 @@ def main():
         "device": device_info(torch),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": read_traffic(nbytes),
-                     "algorithmic_bytes_per_launch": nbytes},
+                     "algorithmic_bytes_per_launch": nbytes,
+                     "copy_1GiB_GB/s": copy_rate(torch, 20)[0]},
     }
     if args.mode == "full":
         result["workloads"] = extras(torch, api, synth, args.steps, args.warmup)
@@ -464,6 +521,9 @@ def main():
         log("cpu baseline (oracle) ...")
         result["cpu_baseline"] = cpu_baseline(pan, ms, wl.wavelet)
         log("cpu baseline", result["cpu_baseline"])
+        if args.mode == "full":
+            result["cpu_oracle_rates"] = cpu_oracle_rates(torch, synth, pan, ms, wl.wavelet)
+            log("cpu oracle rates", result["cpu_oracle_rates"])
     print(json.dumps(result), flush=True)
 
 
