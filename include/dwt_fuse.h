@@ -186,7 +186,8 @@ dwt_fuse_status dwt_fuse_run_batched(dwt_fuse_ctx *ctx, const dwt_fuse_item *ite
  *             (Haar: the 2x2 block sum of y_b, the transpose of Eq. 11-12)
  *   grad_gain NULL or B floats:              < y_b, PAN - P PAN >
  * where P is the projection of an image onto its LL part.  grad_gain is
- * reduced in a fixed order (bitwise reproducible).  Outputs must not overlap
+ * reduced in a fixed order (bitwise reproducible, whatever the rows per work
+ * unit).  Outputs must not overlap
  * inputs.  Uses context workspace (DWT_FUSE_E_NOMEM if it cannot grow). */
 dwt_fuse_status dwt_fuse_backward(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet,
                                   int64_t H, int64_t W, int64_t B,
@@ -211,16 +212,19 @@ typedef struct {
  * wavelets; the adjoint of a dwt_fuse_run_batched call, for instance) with
  * one adjoint launch per kernel variant present in the batch (scenes of the
  * same variant share a launch, so small scenes fill the GPU together) and
- * one launch for every grad_gain reduction.  Each scene gets the work units
- * dwt_fuse_backward would give it on this context, so its results are
- * bit-identical to that call (the LDS-staged adjoint of forced variant 3 is
- * not used here).  `items` is a HOST array of n descriptors (read during the
- * call only); the pointers inside are device pointers.  Every item is
- * validated as in dwt_fuse_backward (first failure returned, nothing
- * launched); no output of any item may overlap any input or another output
- * of any item.  n == 0 is a no-op.  Uses context workspace for the per-unit
- * gain partials of all scenes and a context-owned scene table, grown on
- * first use of a larger batch (DWT_FUSE_E_NOMEM on failure). */
+ * one launch for every grad_gain reduction.  Each scene gets the kernel
+ * variant dwt_fuse_backward would give it on this context (the LDS-staged
+ * adjoint of forced variant 3 is not used here); scenes on the default
+ * band-unrolled D4 plan (at most 4 bands, no tuned or forced shape) may take
+ * longer work units than alone, since the batch fills the GPU together.  No
+ * gradient depends on the unit length, so every scene's results are
+ * bit-identical to that call's.  `items` is a HOST array of n descriptors
+ * (read during the call only); the pointers inside are device pointers.
+ * Every item is validated as in dwt_fuse_backward (first failure returned,
+ * nothing launched); no output of any item may overlap any input or another
+ * output of any item.  n == 0 is a no-op.  Uses context workspace for the
+ * per-row gain partials of all scenes and a context-owned scene table, grown
+ * on first use of a larger batch (DWT_FUSE_E_NOMEM on failure). */
 dwt_fuse_status dwt_fuse_backward_batched(dwt_fuse_ctx *ctx, const dwt_fuse_bwd_item *items, int64_t n);
 
 /* The paper's own GPU pipeline, kept as a comparator for dwt_fuse_run

@@ -12,9 +12,11 @@
 //     dLoss/d(g_b)   = < y_b, PAN - P PAN >.
 // The kernels walk the same work units as the forward kernels (a strip of
 // 64*NC coefficient columns per wavefront, seg_rows coefficient rows) with
-// rolling rows in registers; the per-band gain products are reduced per
-// lane in LDS, per wavefront with cross-lane adds, written per work unit and
-// summed by gain_reduce_kernel in a fixed order (reproducible bit for bit).
+// rolling rows in registers; the per-band gain products of each coefficient
+// row of a strip are summed across the wavefront and written to their own
+// slot (gain_row), and gain_reduce_kernel sums the slots in a fixed order, so
+// grad_gain has the same bits whatever the unit length, order or variant
+// with two coefficient columns per lane.
 #include "fuse_internal.h"
 
 namespace dwtf {
@@ -56,10 +58,39 @@ __device__ __forceinline__ int xcd_remap(int b, int G) {
     return x * q + (x < rem ? x : rem) + i;
 }
 
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ float lane_value(float x, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
+}
+
+// Sum of v over the wavefront's 64 lanes (all of them must be active), the
+// same value in every lane and the same bits for the same inputs.  Within
+// each row of 16 lanes by data-parallel moves: pairs (quad_perm 1,0,3,2),
+// quads (quad_perm 2,3,0,1), then the row's four quads (rotations by 4 and
+// by 8; float addition commutes, so lane 0 of the row holds a fixed tree);
+// then the four rows' sums, read from lanes 0, 16, 32, 48, in a fixed order.
 __device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
-    return v;
+    v += dpp_move<0xB1>(v);
+    v += dpp_move<0x4E>(v);
+    v += dpp_move<0x124>(v);
+    v += dpp_move<0x128>(v);
+    return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
+}
+
+// Gain partial of coefficient row r of a strip (two output rows, all of the
+// strip's columns) for band b: the lanes' products summed across the
+// wavefront, written to partial[(r * nstrips + strip) * pstride + b].  One
+// entry per (row, strip) whatever unit holds the row, so the reduction over
+// them gives the same bits for any unit length or order.  Every lane of the
+// wavefront must take part (inactive columns contribute 0).
+__device__ __forceinline__ void gain_row(const AdjParams &p, int strip, int r, int b, float dot) {
+    if (!p.partial) return;
+    const float s = wave_sum(dot);
+    if ((threadIdx.x & 63) == 0) p.partial[((int64_t)r * p.nstrips + strip) * p.pstride + b] = s;
 }
 
 // Loads NC+2 column pairs (pc[0..NC+1]) of one row; pairs 1..NC are the
@@ -127,7 +158,7 @@ __device__ __forceinline__ void store_pairs(float *row, int s0, int W2, bool ful
     if constexpr (NC == 2 && AL) {
         if (full)
             *reinterpret_cast<f4 *>(row + 2 * s0) = f4{q[0].x, q[0].y, q[1].x, q[1].y};
-        else
+        else if (s0 < W2)
             st2<AL>(row + 2 * s0, q[0]);
     } else {
 #pragma unroll
@@ -141,7 +172,7 @@ __device__ __forceinline__ void store_ms(float *row, int s0, int W2, bool full, 
     if constexpr (NC == 2 && AL) {
         if (full)
             *reinterpret_cast<f2 *>(row + s0) = f2{v[0], v[1]};
-        else
+        else if (s0 < W2)
             row[s0] = v[0];
     } else {
 #pragma unroll
@@ -153,11 +184,9 @@ __device__ __forceinline__ void store_ms(float *row, int s0, int W2, bool full, 
 // ---- D4 adjoint ----------------------------------------------------------
 
 template <int NC, bool AL>
-__device__ __forceinline__ void d4_adj_unit(const AdjParams &p, const Filters &f, int strip, int seg,
-                                            int lane, float *acc /* this lane's LDS slots */, int acc_stride) {
+__device__ __forceinline__ void d4_adj_unit(const AdjParams &p, const Filters &f, int strip, int seg, int lane) {
     const int W2 = p.W >> 1, H2 = p.H >> 1;
-    const int s0 = (strip * 64 + lane) * NC;
-    if (s0 >= W2) return;
+    const int s0 = (strip * 64 + lane) * NC;  // lanes past W2 load wrapped columns and store nothing
     const bool full = (s0 + NC) <= W2;
     bool valid[NC];
 #pragma unroll
@@ -269,7 +298,7 @@ __device__ __forceinline__ void d4_adj_unit(const AdjParams &p, const Filters &f
                 dot = fmaf(z1[i + 1].x, Db[i].x, dot);
                 dot = fmaf(z1[i + 1].y, Db[i].y, dot);
             }
-            acc[b * acc_stride] += dot;
+            gain_row(p, strip, r, b, dot);
         }
         if (p.grad_pan) {
             f2 sa[NC], sb[NC], q0[NC], q1[NC];
@@ -318,11 +347,9 @@ __device__ __forceinline__ void d4_adj_unit(const AdjParams &p, const Filters &f
 // other D4 adjoints (bit-identical grad_pan / grad_ms).
 
 template <int NC, bool AL, int BG>
-__device__ __forceinline__ void d4_adj_unit_bg(const AdjParams &p, const Filters &f, int strip, int seg, int lane,
-                                               float *acc, int acc_stride) {
+__device__ __forceinline__ void d4_adj_unit_bg(const AdjParams &p, const Filters &f, int strip, int seg, int lane) {
     const int W2 = p.W >> 1, H2 = p.H >> 1;
-    const int s0 = (strip * 64 + lane) * NC;
-    if (s0 >= W2) return;
+    const int s0 = (strip * 64 + lane) * NC;  // lanes past W2 load wrapped columns and store nothing
     const bool full = (s0 + NC) <= W2;
     bool valid[NC];
 #pragma unroll
@@ -449,7 +476,7 @@ __device__ __forceinline__ void d4_adj_unit_bg(const AdjParams &p, const Filters
                 dot = fmaf(o1[bb][i].x, Db[i].x, dot);
                 dot = fmaf(o1[bb][i].y, Db[i].y, dot);
             }
-            acc[bb * acc_stride] += dot;
+            gain_row(p, strip, r, bb, dot);
 #pragma unroll
             for (int j = 0; j <= NC; ++j) {
                 Y0[bb][j] = R2[j];
@@ -494,16 +521,14 @@ __device__ __forceinline__ void d4_adj_unit_bg(const AdjParams &p, const Filters
 // One wavefront covers KR coefficient rows of a strip: it issues all PAN rows
 // 2rb-2 .. 2rb+2KR+1 at once, then, band after band, all of that band's
 // upstream-gradient rows at once (the halo rows are re-read from L2).  The
-// per-pixel values use the shared fma chains above, so grad_pan and grad_ms
-// agree with the rolling units bit for bit; only the gain partial sums
-// differ in rounding (their per-unit split).
+// per-pixel values and the per-row gain products use the shared fma chains
+// and operand order above, so all three gradients agree with the rolling
+// units bit for bit.
 
 template <int NC, bool AL, int KR>
-__device__ __forceinline__ void d4_adj_tile(const AdjParams &p, const Filters &f, int strip, int seg, int lane,
-                                            float *acc, int acc_stride) {
+__device__ __forceinline__ void d4_adj_tile(const AdjParams &p, const Filters &f, int strip, int seg, int lane) {
     const int W2 = p.W >> 1, H2 = p.H >> 1;
-    const int s0 = (strip * 64 + lane) * NC;
-    if (s0 >= W2) return;
+    const int s0 = (strip * 64 + lane) * NC;  // lanes past W2 load wrapped columns and store nothing
     const bool full = (s0 + NC) <= W2;
     bool valid[NC];
 #pragma unroll
@@ -579,21 +604,26 @@ __device__ __forceinline__ void d4_adj_tile(const AdjParams &p, const Filters &f
 #pragma unroll
             for (int j = 0; j <= NC; ++j) LY[i][j] = fmaf(g, Ly[j], LY[i][j]);
         }
-        float dot = 0.f;
 #pragma unroll
-        for (int t = 0; t < 2 * KR; ++t) {
-            if (t >= 2 * nr) break;
+        for (int i = 0; i < KR; ++i) {
+            if (i >= nr) break;
+            // same operand order as the rolling units: per column, row 2r then 2r+1
+            float dot = 0.f;
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 if (!valid[c]) continue;
-                const f2 zz = z[t + 2][c + 1];
-                Y[t][c].x = fmaf(g, zz.x, Y[t][c].x);
-                Y[t][c].y = fmaf(g, zz.y, Y[t][c].y);
-                dot = fmaf(zz.x, D[t][c].x, dot);
-                dot = fmaf(zz.y, D[t][c].y, dot);
+                const f2 z0 = z[2 * i + 2][c + 1], z1 = z[2 * i + 3][c + 1];
+                Y[2 * i][c].x = fmaf(g, z0.x, Y[2 * i][c].x);
+                Y[2 * i][c].y = fmaf(g, z0.y, Y[2 * i][c].y);
+                Y[2 * i + 1][c].x = fmaf(g, z1.x, Y[2 * i + 1][c].x);
+                Y[2 * i + 1][c].y = fmaf(g, z1.y, Y[2 * i + 1][c].y);
+                dot = fmaf(z0.x, D[2 * i][c].x, dot);
+                dot = fmaf(z0.y, D[2 * i][c].y, dot);
+                dot = fmaf(z1.x, D[2 * i + 1][c].x, dot);
+                dot = fmaf(z1.y, D[2 * i + 1][c].y, dot);
             }
+            gain_row(p, strip, rb + i, b, dot);
         }
-        acc[b * acc_stride] += dot;
     }
     if (p.grad_pan) {
 #pragma unroll
@@ -625,15 +655,15 @@ __device__ __forceinline__ void d4_adj_tile(const AdjParams &p, const Filters &f
 // ---- Haar adjoint --------------------------------------------------------
 
 template <int NC, bool AL>
-__device__ __forceinline__ void haar_adj_unit(const AdjParams &p, int strip, int seg, int lane, float *acc,
-                                              int acc_stride) {
+__device__ __forceinline__ void haar_adj_unit(const AdjParams &p, int strip, int seg, int lane) {
     const int W2 = p.W >> 1, H2 = p.H >> 1;
     const int s0 = (strip * 64 + lane) * NC;
-    if (s0 >= W2) return;
     const bool full = (s0 + NC) <= W2;
     int pc[NC];
+    // columns past W2 re-read an inside pair (pair s0, or W2-1 for lanes
+    // wholly past the edge); they store nothing and add nothing
 #pragma unroll
-    for (int i = 0; i < NC; ++i) pc[i] = (s0 + i < W2) ? s0 + i : s0;  // invalid pairs re-read pair s0
+    for (int i = 0; i < NC; ++i) pc[i] = (s0 + i < W2) ? s0 + i : (s0 < W2 ? s0 : W2 - 1);
     bool valid[NC];
 #pragma unroll
     for (int i = 0; i < NC; ++i) valid[i] = (s0 + i) < W2;
@@ -685,7 +715,7 @@ __device__ __forceinline__ void haar_adj_unit(const AdjParams &p, int strip, int
                 dot += z0[i].x * Da[i].x + z0[i].y * Da[i].y + z1[i].x * Dc[i].x + z1[i].y * Dc[i].y;
             }
             if (p.grad_ms) store_ms<NC, AL>(p.grad_ms + (int64_t)b * H2 * W2 + (int64_t)r * W2, s0, W2, full, bs);
-            acc[b * acc_stride] += dot;
+            gain_row(p, strip, r, b, dot);
         }
         if (p.grad_pan) {
             f2 q0[NC], q1[NC];
@@ -721,50 +751,36 @@ __device__ __forceinline__ void unit_strip_seg(const AdjParams &p, int unit, int
     }
 }
 
-// One work unit of each adjoint variant, by one wavefront; `acc` is the
-// lane's slot in a block-wide LDS array of nb * 256 floats.  The unit's
-// per-band gain products go to p.partial[unit * p.pstride + b].
+// One work unit of each adjoint variant, by one wavefront (all 64 lanes).
+// Its gain products go to p.partial, one entry per coefficient row and strip
+// (gain_row).
 //   KIND 0: rolling, any wavelet, p.B <= kAdjMaxBands (X unused)
 //   KIND 1: rolling D4 with the band loop unrolled, p.B == X <= 4
 //   KIND 2: one-shot D4 tile of X = p.seg_rows coefficient rows
 template <int KIND, int NC, bool AL, int X>
-__device__ __forceinline__ void adj_unit(const AdjParams &p, const Filters &f, int unit, int lane, float *acc) {
-    const int nb = KIND == 1 ? X : p.B;
-    for (int b = 0; b < nb; ++b) acc[b * 256] = 0.f;
+__device__ __forceinline__ void adj_unit(const AdjParams &p, const Filters &f, int unit, int lane) {
     int strip, seg;
     unit_strip_seg(p, unit, strip, seg);
     if constexpr (KIND == 0) {
         if (p.wavelet == 1)
-            d4_adj_unit<NC, AL>(p, f, strip, seg, lane, acc, 256);
+            d4_adj_unit<NC, AL>(p, f, strip, seg, lane);
         else
-            haar_adj_unit<NC, AL>(p, strip, seg, lane, acc, 256);
+            haar_adj_unit<NC, AL>(p, strip, seg, lane);
     } else if constexpr (KIND == 1) {
-        d4_adj_unit_bg<NC, AL, X>(p, f, strip, seg, lane, acc, 256);
+        d4_adj_unit_bg<NC, AL, X>(p, f, strip, seg, lane);
     } else {
-        d4_adj_tile<NC, AL, X>(p, f, strip, seg, lane, acc, 256);
+        d4_adj_tile<NC, AL, X>(p, f, strip, seg, lane);
     }
-    if (p.partial) {
-        for (int b = 0; b < nb; ++b) {
-            const float s = wave_sum(acc[b * 256]);
-            if (lane == 0) p.partial[(int64_t)unit * p.pstride + b] = s;
-        }
-    }
-}
-
-template <int KIND>
-constexpr int adj_lds_bands() {
-    return KIND == 1 ? 4 : kAdjMaxBands;
 }
 
 // One scene: one wavefront per work unit.
 template <int KIND, int NC, bool AL, int X>
 __global__ __launch_bounds__(256) void adjoint_kernel(AdjParams p, Filters f) {
-    __shared__ float acc_lds[adj_lds_bands<KIND>() * 256];
     const int wpb = blockDim.x >> 6;
     const int lane = threadIdx.x & 63;
     const int unit = xcd_remap(blockIdx.x, gridDim.x) * wpb + (threadIdx.x >> 6);
     if (unit >= p.units) return;  // whole wavefront leaves together
-    adj_unit<KIND, NC, AL, X>(p, f, unit, lane, acc_lds + threadIdx.x);
+    adj_unit<KIND, NC, AL, X>(p, f, unit, lane);
 }
 
 // Many scenes of one variant: workgroups of 4 wavefronts, wavefront u of the
@@ -784,46 +800,95 @@ __device__ __forceinline__ int find_adj_scene(const AdjScene *sc, int n, int u) 
 template <int KIND, int NC, bool AL, int X>
 __global__ __launch_bounds__(256) void adjoint_batched_kernel(const AdjScene *__restrict__ scenes, int nscenes,
                                                               int total, Filters f) {
-    __shared__ float acc_lds[adj_lds_bands<KIND>() * 256];
     const int lane = threadIdx.x & 63;
     const int u = xcd_remap(blockIdx.x, gridDim.x) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (u >= total) return;  // whole wavefront leaves together
     const int si = find_adj_scene(scenes, nscenes, u);
     const AdjParams p = scenes[si].p;
-    adj_unit<KIND, NC, AL, X>(p, f, u - scenes[si].unit_begin, lane, acc_lds + threadIdx.x);
+    adj_unit<KIND, NC, AL, X>(p, f, u - scenes[si].unit_begin, lane);
 }
 
-// grad_gain[b] = sum over units of partial[unit * pstride + b], in FP64 with
-// a fixed assignment of units to threads and a fixed reduction tree.
-__global__ __launch_bounds__(256) void gain_reduce_kernel(const float *partial, int units, int pstride,
-                                                          float *grad_gain) {
+// ---- grad_gain reduction ----------------------------------------------------
+//
+// grad_gain[b] = sum over slots of partial[slot * pstride + b], in FP64 with
+// a fixed order: chunks of kGainChunk consecutive slots, one workgroup each
+// (thread t adds slots t, t + 256, ... of the chunk in turn, then a fixed
+// tree over the workgroup), then a band's chunk sums (same scheme).  The
+// single-scene and batched launches share both steps, so they agree bit for
+// bit.
+
+__device__ __forceinline__ double block_sum256(double a, double *sh) {
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    return sh[0];
+}
+
+__device__ __forceinline__ double chunk_sum(const float *partial, int pstride, int band, int units, int c,
+                                            double *sh) {
+    constexpr int K = kGainChunk / 256;
+    const int u0 = c * kGainChunk + (int)threadIdx.x;
+    float v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int u = u0 + k * 256;
+        v[k] = u < units ? partial[(int64_t)u * pstride + band] : 0.f;
+    }
+    double a = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) a += (double)v[k];
+    return block_sum256(a, sh);
+}
+
+__device__ __forceinline__ double chunks_total(const double *chunks, int n, double *sh) {
+    double a = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) a += chunks[i];
+    return block_sum256(a, sh);
+}
+
+// Workgroup g: chunk g % nch of band g / nch.
+__global__ __launch_bounds__(256) void gain_chunk_kernel(const float *partial, int units, int B, int nch,
+                                                         double *chunks) {
+    __shared__ double sh[256];
+    const int b = blockIdx.x / nch, c = blockIdx.x - b * nch;
+    const double a = chunk_sum(partial, B, b, units, c, sh);
+    if (threadIdx.x == 0) chunks[(int64_t)b * nch + c] = a;
+}
+
+__global__ __launch_bounds__(256) void gain_total_kernel(const double *chunks, int nch, float *grad_gain) {
     __shared__ double sh[256];
     const int b = blockIdx.x;
-    double a = 0.0;
-    for (int u = threadIdx.x; u < units; u += 256) a += (double)partial[(int64_t)u * pstride + b];
-    sh[threadIdx.x] = a;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) grad_gain[b] = (float)sh[0];
+    const double a = chunks_total(chunks + (int64_t)b * nch, nch, sh);
+    if (threadIdx.x == 0) grad_gain[b] = (float)a;
 }
 
-// One workgroup per (scene, band) job: the same sum, order and rounding as
-// gain_reduce_kernel on that scene alone.
-__global__ __launch_bounds__(256) void gain_reduce_batched_kernel(const GainJob *__restrict__ jobs) {
+// Batched: workgroup g takes chunk g - chunk_begin of the job whose range
+// holds g; then one workgroup per job.
+__global__ __launch_bounds__(256) void gain_chunk_batched_kernel(const GainJob *__restrict__ jobs, int njobs) {
+    __shared__ double sh[256];
+    const int g = blockIdx.x;
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].chunk_begin <= g)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const GainJob j = jobs[lo];
+    const int c = g - j.chunk_begin;
+    const double a = chunk_sum(j.partial, j.pstride, j.band, j.units, c, sh);
+    if (threadIdx.x == 0) j.chunks[c] = a;
+}
+
+__global__ __launch_bounds__(256) void gain_total_batched_kernel(const GainJob *__restrict__ jobs) {
     __shared__ double sh[256];
     const GainJob j = jobs[blockIdx.x];
-    double a = 0.0;
-    for (int u = threadIdx.x; u < j.units; u += 256) a += (double)j.partial[(int64_t)u * j.pstride + j.band];
-    sh[threadIdx.x] = a;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) j.grad_gain[j.band] = (float)sh[0];
+    const double a = chunks_total(j.chunks, (j.units + kGainChunk - 1) / kGainChunk, sh);
+    if (threadIdx.x == 0) j.grad_gain[j.band] = (float)a;
 }
 
 // ---- D4 adjoint, LDS-staged workgroup tile (16-byte rows) -------------------
@@ -835,8 +900,8 @@ __global__ __launch_bounds__(256) void gain_reduce_batched_kernel(const GainJob 
 // (band b+1 is in flight while band b is computed).  Each wavefront keeps
 // Y = sum_b g_b y_b and L Y for its KR rows in registers and writes grad_pan
 // once at the end, so any band count runs in one launch.  The per-band
-// products <y_b, D> are reduced per wavefront, combined over the workgroup's
-// wavefronts in LDS in a fixed order, and written once per work unit.
+// products <y_b, D> go out per coefficient row (gain_row), as in the rolling
+// units.
 
 constexpr int kAdjRow = 264;  // floats per staged row: [2,4) left halo, [4,260) own, [260,262) right halo
 
@@ -882,7 +947,6 @@ __global__ __launch_bounds__(256) void d4_adjoint_staged_kernel(AdjParams p, Fil
     const int rows = 2 * T + 4;
     float *Pl = lds;
     float *Yl[2] = {lds + rows * kAdjRow, lds + 2 * rows * kAdjRow};
-    float *red = lds + 3 * rows * kAdjRow;  // [band][wavefront] partial products
 
     adj_stage_rows(p.pan, p.pan_ld, p.H, p.W, r0, T, sb, Pl, w, wpb, lane);
     adj_stage_rows(p.gy, p.gy_ld, p.H, p.W, r0, T, sb, Yl[0], w, wpb, lane);
@@ -966,29 +1030,30 @@ __global__ __launch_bounds__(256) void d4_adjoint_staged_kernel(AdjParams p, Fil
         for (int i = 0; i <= KR; ++i)
 #pragma unroll
             for (int j = 0; j < 3; ++j) Ly[i][j] = col4(h, R[2 * i][j], R[2 * i + 1][j], R[2 * i + 2][j], R[2 * i + 3][j]);
-        float dot = 0.f;
-        if (active) {
 #pragma unroll
-            for (int t = 0; t < 2 * KR; ++t) {
-                if (t >= 2 * nr) break;
+        for (int i = 0; i < KR; ++i) {
+            if (i >= nr) break;
+            // same operand order as the rolling units: per column, row 2r then 2r+1
+            float dot = 0.f;
 #pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                    if (c == 1 && !full) break;
-                    Y[t][c].x = fmaf(g, yo[t][c].x, Y[t][c].x);
-                    Y[t][c].y = fmaf(g, yo[t][c].y, Y[t][c].y);
-                    dot = fmaf(yo[t][c].x, D[t][c].x, dot);
-                    dot = fmaf(yo[t][c].y, D[t][c].y, dot);
-                }
+            for (int c = 0; c < 2; ++c) {
+                if (!active || (c == 1 && !full)) break;
+                const f2 z0 = yo[2 * i][c], z1 = yo[2 * i + 1][c];
+                Y[2 * i][c].x = fmaf(g, z0.x, Y[2 * i][c].x);
+                Y[2 * i][c].y = fmaf(g, z0.y, Y[2 * i][c].y);
+                Y[2 * i + 1][c].x = fmaf(g, z1.x, Y[2 * i + 1][c].x);
+                Y[2 * i + 1][c].y = fmaf(g, z1.y, Y[2 * i + 1][c].y);
+                dot = fmaf(z0.x, D[2 * i][c].x, dot);
+                dot = fmaf(z0.y, D[2 * i][c].y, dot);
+                dot = fmaf(z1.x, D[2 * i + 1][c].x, dot);
+                dot = fmaf(z1.y, D[2 * i + 1][c].y, dot);
             }
+            gain_row(p, strip, rb + i, b, dot);
         }
 #pragma unroll
         for (int i = 0; i <= KR; ++i)
 #pragma unroll
             for (int j = 0; j < 3; ++j) LY[i][j] = fmaf(g, Ly[i][j], LY[i][j]);
-        if (p.partial) {
-            const float sd = wave_sum(dot);
-            if (lane == 0) red[b * wpb + w] = sd;
-        }
         // Wait for band b+1's rows before this band's stores are issued, so
         // the wait does not include them (the counter also covers stores).
         __builtin_amdgcn_s_waitcnt(0);
@@ -1027,13 +1092,6 @@ __global__ __launch_bounds__(256) void d4_adjoint_staged_kernel(AdjParams p, Fil
             }
         }
     }
-    if (p.partial) {  // fixed-order sum over the wavefronts
-        for (int bb = threadIdx.x; bb < p.B; bb += blockDim.x) {
-            float t = 0.f;
-            for (int k = 0; k < wpb; ++k) t += red[bb * wpb + k];
-            p.partial[(int64_t)unit * p.pstride + bb] = t;
-        }
-    }
 }
 
 // The same tile with the upstream gradients of a group of up to bg_all bands
@@ -1061,7 +1119,6 @@ __global__ __launch_bounds__(256) void d4_adjoint_staged_all_kernel(AdjParams p,
     const int rows = 2 * T + 4;
     float *Pl = lds;
     float *Yl = lds + rows * kAdjRow;                  // bg_all images of `rows` rows
-    float *red = lds + (1 + bg_all) * rows * kAdjRow;  // [band][wavefront] partial products
 
     auto stage_group = [&](int g0, int bg) {
         for (int bi = 0; bi < bg; ++bi)
@@ -1156,29 +1213,30 @@ __global__ __launch_bounds__(256) void d4_adjoint_staged_all_kernel(AdjParams p,
 #pragma unroll
                 for (int j = 0; j < 3; ++j)
                     Ly[i][j] = col4(h, R[2 * i][j], R[2 * i + 1][j], R[2 * i + 2][j], R[2 * i + 3][j]);
-            float dot = 0.f;
-            if (active) {
 #pragma unroll
-                for (int t = 0; t < 2 * KR; ++t) {
-                    if (t >= 2 * nr) break;
+            for (int i = 0; i < KR; ++i) {
+                if (i >= nr) break;
+                // same operand order as the rolling units: per column, row 2r then 2r+1
+                float dot = 0.f;
 #pragma unroll
-                    for (int c = 0; c < 2; ++c) {
-                        if (c == 1 && !full) break;
-                        Y[t][c].x = fmaf(g, yo[t][c].x, Y[t][c].x);
-                        Y[t][c].y = fmaf(g, yo[t][c].y, Y[t][c].y);
-                        dot = fmaf(yo[t][c].x, D[t][c].x, dot);
-                        dot = fmaf(yo[t][c].y, D[t][c].y, dot);
-                    }
+                for (int c = 0; c < 2; ++c) {
+                    if (!active || (c == 1 && !full)) break;
+                    const f2 z0 = yo[2 * i][c], z1 = yo[2 * i + 1][c];
+                    Y[2 * i][c].x = fmaf(g, z0.x, Y[2 * i][c].x);
+                    Y[2 * i][c].y = fmaf(g, z0.y, Y[2 * i][c].y);
+                    Y[2 * i + 1][c].x = fmaf(g, z1.x, Y[2 * i + 1][c].x);
+                    Y[2 * i + 1][c].y = fmaf(g, z1.y, Y[2 * i + 1][c].y);
+                    dot = fmaf(z0.x, D[2 * i][c].x, dot);
+                    dot = fmaf(z0.y, D[2 * i][c].y, dot);
+                    dot = fmaf(z1.x, D[2 * i + 1][c].x, dot);
+                    dot = fmaf(z1.y, D[2 * i + 1][c].y, dot);
                 }
+                gain_row(p, strip, rb + i, b, dot);
             }
 #pragma unroll
             for (int i = 0; i <= KR; ++i)
 #pragma unroll
                 for (int j = 0; j < 3; ++j) LY[i][j] = fmaf(g, Ly[i][j], LY[i][j]);
-            if (p.partial) {
-                const float sd = wave_sum(dot);
-                if (lane == 0) red[b * wpb + w] = sd;
-            }
             if (active && p.grad_ms) {
 #pragma unroll
                 for (int i = 0; i < KR; ++i) {
@@ -1213,14 +1271,6 @@ __global__ __launch_bounds__(256) void d4_adjoint_staged_all_kernel(AdjParams p,
             }
         }
     }
-    if (p.partial) {  // fixed-order sum over the wavefronts
-        __syncthreads();
-        for (int bb = threadIdx.x; bb < p.B; bb += blockDim.x) {
-            float t = 0.f;
-            for (int k = 0; k < wpb; ++k) t += red[bb * wpb + k];
-            p.partial[(int64_t)unit * p.pstride + bb] = t;
-        }
-    }
 }
 
 }  // namespace
@@ -1230,16 +1280,15 @@ __global__ __launch_bounds__(256) void d4_adjoint_staged_all_kernel(AdjParams p,
 // next to its PAN rows in 64 KB of LDS (all-bands form), at most B.
 static int adjoint_staged_group(int T, int B) {
     const int img = (2 * T + 4) * kAdjRow;
-    const int g = (16384 - img - 4 * B) / img;
+    const int g = (16384 - img) / img;
     return g < B ? g : B;
 }
 
 size_t adjoint_staged_lds(int T, int B, bool all) {
     const size_t img = (size_t)(2 * T + 4) * kAdjRow;
-    const size_t red = (size_t)B * 4;  // [band][wavefront <= 4]
-    if (!all) return sizeof(float) * (3 * img + red);
+    if (!all) return sizeof(float) * 3 * img;
     const int g = adjoint_staged_group(T, B);
-    return g < 1 ? (size_t)1 << 30 : sizeof(float) * ((1 + (size_t)g) * img + red);
+    return g < 1 ? (size_t)1 << 30 : sizeof(float) * (1 + (size_t)g) * img;
 }
 
 hipError_t launch_adjoint_staged(const AdjParams &p, const Filters &f, int kr, int wpb, bool all, hipStream_t s) {
@@ -1364,15 +1413,25 @@ hipError_t launch_adjoint_batched(const AdjScene *d_scenes, int nscenes, int tot
     return hipGetLastError();
 }
 
-hipError_t launch_gain_reduce_batched(const GainJob *d_jobs, int njobs, hipStream_t s) {
-    if (njobs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(gain_reduce_batched_kernel, dim3(njobs), dim3(256), 0, s, d_jobs);
+hipError_t launch_gain_reduce_batched(const GainJob *d_jobs, int njobs, int total_chunks, hipStream_t s) {
+    if (njobs <= 0 || total_chunks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gain_chunk_batched_kernel, dim3(total_chunks), dim3(256), 0, s, d_jobs, njobs);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(gain_total_batched_kernel, dim3(njobs), dim3(256), 0, s, d_jobs);
     return hipGetLastError();
 }
 
-hipError_t launch_gain_reduce(const float *partial, int units, int B, float *grad_gain, hipStream_t s) {
-    if (B <= 0) return hipSuccess;
-    hipLaunchKernelGGL(gain_reduce_kernel, dim3(B), dim3(256), 0, s, partial, units, B, grad_gain);
+hipError_t launch_gain_reduce(const float *partial, int units, int B, double *chunks, float *grad_gain,
+                              hipStream_t s) {
+    if (B <= 0 || units <= 0) return hipSuccess;
+    const int64_t nch = gain_chunks(units);
+    if (nch * B > INT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(gain_chunk_kernel, dim3((unsigned)(nch * B)), dim3(256), 0, s, partial, units, B, (int)nch,
+                       chunks);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(gain_total_kernel, dim3(B), dim3(256), 0, s, chunks, (int)nch, grad_gain);
     return hipGetLastError();
 }
 

@@ -1697,7 +1697,19 @@ struct BwdTile {
     Path pp = PATH_SCALAR;
     Decomp d;
     int kind = 0, x = 0;
+    bool auto_seg = false;  // unit length chosen by the default rule below (no tuned or forced one)
 };
+
+// Gain partial slots of an adjoint launch: one per (coefficient row, strip),
+// B floats each, whatever the unit length (see gain_row).
+static int64_t gain_slots(int64_t H, int64_t nstrips) { return (H / 2) * nstrips; }
+
+// Workspace of a single-scene gain reduction: the slots' B floats each, then
+// (256-byte aligned) the B * gain_chunks(slots) chunk sums.
+static size_t gain_ws_chunk_off(int64_t slots, int64_t B) { return ((size_t)(slots * B) * sizeof(float) + 255) / 256 * 256; }
+static size_t gain_ws_bytes(int64_t slots, int64_t B) {
+    return gain_ws_chunk_off(slots, B) + (size_t)(gain_chunks(slots) * B) * sizeof(double);
+}
 
 static bool plan_bwd(const dwt_fuse_ctx *ctx, const BwdArgs &a, Path path, BwdTile *out) {
     const int64_t H = a.H, W = a.W, B = a.B;
@@ -1712,6 +1724,9 @@ static bool plan_bwd(const dwt_fuse_ctx *ctx, const BwdArgs &a, Path path, BwdTi
         t.seg_rows = 32;
         Decomp d0;
         while (t.seg_rows > 4 && decompose(H, W, t, &d0) && d0.units < 2048) t.seg_rows /= 2;
+        out->auto_seg = true;
+    } else {
+        out->auto_seg = false;
     }
     t = apply_forced(ctx, t, path, a.wavelet, path_nc(path));
     // Adjoint kernels: rolling units (mode 0) and, for D4, one-shot tiles of
@@ -1729,6 +1744,7 @@ static bool plan_bwd(const dwt_fuse_ctx *ctx, const BwdArgs &a, Path path, BwdTi
     out->t = t;
     out->pp = path_for_nc(path, t.nc);
     if (!decompose(H, W, t, &out->d)) return false;
+    if (gain_slots(H, out->d.nstrips) > INT32_MAX - kGainChunk) return false;
     // D4 with at most 4 bands: the rolling kernel with the band loop
     // unrolled (unless the dynamic-band rolling kernel is forced).
     if (t.mode != 0) {
@@ -1800,10 +1816,14 @@ dwt_fuse_status dwt_fuse_backward(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet, i
             const int64_t ns = (W / 2 + 127) / 128, ng = (H / 2 + T - 1) / T;
             if (ns * ng > INT32_MAX) return fail(ctx, DWT_FUSE_E_SHAPE, "too many work units");
             const int units = (int)(ns * ng);
+            const int64_t slots = gain_slots(H, ns);
+            if (slots > INT32_MAX - kGainChunk) return fail(ctx, DWT_FUSE_E_SHAPE, "too many gain partial slots");
             float *partial = nullptr;
+            double *chunks = nullptr;
             if (grad_gain) {
-                if ((st = ensure_ws(ctx, sizeof(float) * (size_t)units * (size_t)B))) return st;
+                if ((st = ensure_ws(ctx, gain_ws_bytes(slots, B)))) return st;
                 partial = ctx->ws;
+                chunks = reinterpret_cast<double *>(reinterpret_cast<char *>(ctx->ws) + gain_ws_chunk_off(slots, B));
             }
             AdjParams p{};
             p.pan = pan;
@@ -1830,17 +1850,20 @@ dwt_fuse_status dwt_fuse_backward(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet, i
             hipError_t e = launch_adjoint_staged(p, ctx->filt, kr, wpb, ctx->forced.nc != 1, ctx->stream);
             if (e != hipSuccess) return hip_fail(ctx, e, "staged adjoint launch");
             if (grad_gain) {
-                e = launch_gain_reduce(partial, units, (int)B, grad_gain, ctx->stream);
+                e = launch_gain_reduce(partial, (int)slots, (int)B, chunks, grad_gain, ctx->stream);
                 if (e != hipSuccess) return hip_fail(ctx, e, "gain reduction launch");
             }
             return DWT_FUSE_OK;
         }
         BwdTile bt;
         if (!plan_bwd(ctx, a, path, &bt)) return fail(ctx, DWT_FUSE_E_SHAPE, "too many work units");
+        const int64_t slots = gain_slots(H, bt.d.nstrips);
         float *partial = nullptr;
+        double *chunks = nullptr;
         if (grad_gain) {
-            if ((st = ensure_ws(ctx, sizeof(float) * (size_t)bt.d.units * (size_t)B))) return st;
+            if ((st = ensure_ws(ctx, gain_ws_bytes(slots, B)))) return st;
             partial = ctx->ws;
+            chunks = reinterpret_cast<double *>(reinterpret_cast<char *>(ctx->ws) + gain_ws_chunk_off(slots, B));
         }
         const int maxb = adjoint_max_bands();
         for (int64_t b0 = 0; b0 < B; b0 += maxb) {
@@ -1851,7 +1874,7 @@ dwt_fuse_status dwt_fuse_backward(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet, i
             if (e != hipSuccess) return hip_fail(ctx, e, "adjoint launch");
         }
         if (grad_gain) {
-            const hipError_t e = launch_gain_reduce(partial, bt.d.units, (int)B, grad_gain, ctx->stream);
+            const hipError_t e = launch_gain_reduce(partial, (int)slots, (int)B, chunks, grad_gain, ctx->stream);
             if (e != hipSuccess) return hip_fail(ctx, e, "gain reduction launch");
         }
         return DWT_FUSE_OK;
@@ -1920,21 +1943,71 @@ dwt_fuse_status dwt_fuse_backward_batched(dwt_fuse_ctx *ctx, const dwt_fuse_bwd_
         // then group the launches by kernel variant and band group.
         std::vector<BwdTile> tiles((size_t)n);
         std::vector<int64_t> poff((size_t)n, -1);  // float offset of a scene's partials in ws
-        int64_t pfloats = 0;
+        std::vector<int64_t> doff((size_t)n, -1);  // offset of its chunk sums in the double part
+        int64_t pfloats = 0, pdoubles = 0;
         for (int64_t i = 0; i < n; ++i) {
             const BwdArgs a = bwd_item_args(items[i]);
             if (!a.grad_pan && !a.grad_ms && !a.grad_gain) continue;
             if (!plan_bwd(ctx, a, choose_bwd_path(a), &tiles[(size_t)i]))
                 return fail(ctx, DWT_FUSE_E_SHAPE, "item " + std::to_string(i) + ": too many work units");
             if (a.grad_gain) {
+                const int64_t slots = gain_slots(a.H, tiles[(size_t)i].d.nstrips);
                 poff[(size_t)i] = pfloats;
-                pfloats += (int64_t)tiles[(size_t)i].d.units * a.B;
+                pfloats += slots * a.B;
+                doff[(size_t)i] = pdoubles;
+                pdoubles += gain_chunks(slots) * a.B;
             }
         }
-        if (pfloats > 0 && (st = ensure_ws(ctx, sizeof(float) * (size_t)pfloats))) return st;
+        // workspace: every scene's slot partials, then (256-byte aligned) their chunk sums
+        const size_t dbyte = ((size_t)pfloats * sizeof(float) + 255) / 256 * 256;
+        if (pfloats > 0 && (st = ensure_ws(ctx, dbyte + (size_t)pdoubles * sizeof(double)))) return st;
+        double *dbase = pfloats > 0 ? reinterpret_cast<double *>(reinterpret_cast<char *>(ctx->ws) + dbyte) : nullptr;
+        // Scenes on the default band-unrolled D4 plan run in one launch, so
+        // their units are lengthened together: the longest (<= 32 rows) that
+        // still give >= 2048 units over all of them, never shorter than a
+        // scene would take alone.  Gradients do not depend on the unit length
+        // (the gain products are kept per row), so every scene's results still
+        // equal its single call's bit for bit.
+        {
+            std::vector<int64_t> joint;
+            for (int64_t i = 0; i < n; ++i)
+                if (tiles[(size_t)i].auto_seg && tiles[(size_t)i].kind == 1 && tiles[(size_t)i].t.mode == 0) {
+                    const BwdArgs a = bwd_item_args(items[i]);
+                    if (a.grad_pan || a.grad_ms || a.grad_gain) joint.push_back(i);
+                }
+            if (joint.size() > 1) {
+                int seg = 32;
+                for (; seg > 4; seg /= 2) {
+                    int64_t total = 0;
+                    bool ok = true;
+                    for (const int64_t i : joint) {
+                        Tile t = tiles[(size_t)i].t;
+                        t.seg_rows = seg;
+                        Decomp d;
+                        if (!decompose(items[i].H, items[i].W, t, &d)) {
+                            ok = false;
+                            break;
+                        }
+                        total += d.units;
+                    }
+                    if (ok && total >= 2048) break;
+                }
+                for (const int64_t i : joint) {
+                    BwdTile &bt = tiles[(size_t)i];
+                    if (seg <= bt.t.seg_rows) continue;
+                    Tile t = bt.t;
+                    t.seg_rows = seg;
+                    Decomp d;
+                    if (!decompose(items[i].H, items[i].W, t, &d)) continue;
+                    bt.t = t;
+                    bt.d = d;
+                }
+            }
+        }
         const int maxb = adjoint_max_bands();
         std::map<std::tuple<int, int, int, int>, BwdGroup> groups;  // (chunk, kind, path, x): chunk first
         std::vector<GainJob> jobs;
+        int64_t total_chunks = 0;
         for (int64_t i = 0; i < n; ++i) {
             const BwdArgs a = bwd_item_args(items[i]);
             if (!a.grad_pan && !a.grad_ms && !a.grad_gain) continue;
@@ -1954,10 +2027,17 @@ dwt_fuse_status dwt_fuse_backward_batched(dwt_fuse_ctx *ctx, const dwt_fuse_bwd_
                 if (g.total > INT32_MAX) return fail(ctx, DWT_FUSE_E_SHAPE, "too many work units in batch");
                 g.sc.push_back(sc);
             }
-            if (partial)
-                for (int64_t b = 0; b < a.B; ++b)
-                    jobs.push_back(GainJob{partial, const_cast<float *>(a.grad_gain), bt.d.units, (int32_t)a.B,
-                                           (int32_t)b, 0});
+            if (partial) {
+                const int64_t slots = gain_slots(a.H, bt.d.nstrips), nch = gain_chunks(slots);
+                for (int64_t b = 0; b < a.B; ++b) {
+                    jobs.push_back(GainJob{partial, const_cast<float *>(a.grad_gain),
+                                           dbase + doff[(size_t)i] + b * nch, (int32_t)slots, (int32_t)a.B,
+                                           (int32_t)b, (int32_t)total_chunks});
+                    total_chunks += nch;
+                    if (total_chunks > INT32_MAX)
+                        return fail(ctx, DWT_FUSE_E_SHAPE, "too many gain reduction chunks in batch");
+                }
+            }
         }
         if (groups.empty()) return DWT_FUSE_OK;
         if (jobs.size() > (size_t)INT32_MAX) return fail(ctx, DWT_FUSE_E_SHAPE, "too many gain reductions in batch");
@@ -1996,7 +2076,7 @@ dwt_fuse_status dwt_fuse_backward_batched(dwt_fuse_ctx *ctx, const dwt_fuse_bwd_
         if (!jobs.empty()) {
             e = launch_gain_reduce_batched(
                 reinterpret_cast<const GainJob *>(static_cast<const char *>(ctx->d_bwd) + job_off), (int)jobs.size(),
-                ctx->stream);
+                (int)total_chunks, ctx->stream);
             if (e != hipSuccess) return hip_fail(ctx, e, "batched gain reduction launch");
         }
         return DWT_FUSE_OK;

@@ -71,20 +71,21 @@ struct BatchQueues {
 };
 
 // Adjoint.  grad_ms / grad_pan are contiguous; grad-gain partial sums are
-// written per (work unit, band) into `partial` and reduced in a fixed order.
+// written per (coefficient row r, strip, band b) into
+// partial[(r * nstrips + strip) * pstride + b] and reduced in a fixed order.
 struct AdjParams {
     const float *pan;
     const float *gain;
     const float *gy;  // dL/d(out)
     float *grad_pan;  // may be NULL
     float *grad_ms;   // may be NULL
-    float *partial;   // units * B floats, may be NULL (no grad_gain)
+    float *partial;   // (H/2) * nstrips * pstride floats, may be NULL (no grad_gain)
     int64_t pan_ld, gy_ld, gy_bs;
     int32_t H, W, B;
     int32_t seg_rows, nseg, units;
     int32_t wavelet, path;
     int32_t nstrips, order;  // as in FuseParams
-    int32_t pstride;     // floats between consecutive units' partials
+    int32_t pstride;     // floats between consecutive (row, strip) slots
     int32_t accumulate;  // 1: add into grad_pan instead of overwriting
 };
 
@@ -118,8 +119,14 @@ hipError_t launch_adjoint_bg(const AdjParams &p, const Filters &f, int waves_per
 // same decomposition and band-group rules as launch_adjoint.
 hipError_t launch_adjoint_tile(const AdjParams &p, const Filters &f, int kr, int waves_per_block, hipStream_t s);
 
-// grad_gain[b] = sum_u partial[u * B + b], b < B, fixed order.
-hipError_t launch_gain_reduce(const float *partial, int units, int B, float *grad_gain, hipStream_t s);
+// grad_gain[b] = sum_u partial[u * B + b] over slots u < units, b < B, in
+// FP64 and a fixed order: first per chunk of kGainChunk consecutive slots
+// (one workgroup each; the chunk sums go to `chunks`, B * gain_chunks(units)
+// doubles of device workspace, band-major), then each band's chunk sums.
+constexpr int kGainChunk = 2048;
+inline int64_t gain_chunks(int64_t units) { return (units + kGainChunk - 1) / kGainChunk; }
+hipError_t launch_gain_reduce(const float *partial, int units, int B, double *chunks, float *grad_gain,
+                              hipStream_t s);
 
 // One scene of a batched adjoint launch: its parameters (as for the
 // single-scene launchers) and the first launch-wide unit it owns.
@@ -140,13 +147,18 @@ hipError_t launch_adjoint_batched(const AdjScene *d_scenes, int nscenes, int tot
                                   const Filters &f, hipStream_t s);
 
 // One band of one scene's gain reduction: grad_gain[band] = sum over the
-// scene's units u of partial[u * pstride + band], as launch_gain_reduce.
+// scene's slots u of partial[u * pstride + band], with the chunks, order and
+// rounding of launch_gain_reduce.  `chunks` holds the job's
+// gain_chunks(units) chunk sums; chunk_begin numbers the job's first chunk
+// among all chunks of the launch (jobs in increasing order, total_chunks in
+// all).
 struct GainJob {
     const float *partial;
     float *grad_gain;
-    int32_t units, pstride, band, pad_;
+    double *chunks;
+    int32_t units, pstride, band, chunk_begin;
 };
-hipError_t launch_gain_reduce_batched(const GainJob *d_jobs, int njobs, hipStream_t s);
+hipError_t launch_gain_reduce_batched(const GainJob *d_jobs, int njobs, int total_chunks, hipStream_t s);
 
 // Bands one rolling adjoint launch handles (the host splits larger band counts).
 int adjoint_max_bands();

@@ -4,7 +4,8 @@ differences of an MSE loss on 32x32 crops, and autograd end to end.
 
 Tolerances (float32 sums of at most 16 terms per gradient pixel; gain
 gradients are sums over the whole image, accumulated in float32 per lane
-and per wavefront, then in FP64 across work units):
+and across the wavefront for each coefficient row of a strip, then in FP64
+across those (row, strip) slots):
   grad_pan, grad_ms: max-abs <= 1e-5 * max(1, max|reference|) * 16
   grad_gain:         |err| <= 1e-5 * sum|y_b * D| + 1e-6
 """
@@ -78,7 +79,11 @@ def test_forced_adjoint_shapes(dev, fz, oracle, H, W, B):
     rows per wavefront; upstream gradients staged a group of bands at a time,
     or with 1 column per lane requested, band after band in two buffers).  Every shape must meet the oracle's tolerance; all
     of them form every per-pixel gradient with the same fma chains in the same
-    order, so grad_pan and grad_ms also agree bit for bit."""
+    order, so grad_pan and grad_ms also agree bit for bit.  The gain products
+    are summed per (coefficient row, strip) whatever the unit length, so
+    grad_gain agrees bit for bit between shapes with the same strip width
+    (128 columns: two columns per lane on 16-byte rows and the staged kernel;
+    64 columns: one column per lane)."""
     rng = np.random.default_rng(7 * H + W + B)
     pan, _ = int_scene(rng, H, W, 1)
     gy = rng.normal(size=(B, H, W)).astype(np.float32)
@@ -99,13 +104,59 @@ def test_forced_adjoint_shapes(dev, fz, oracle, H, W, B):
             outs.append((seg, wpb, nc, var, got))
     finally:
         ctx.force_tile(0, 0, 0, 0)
+    def strip_cols(nc, var):
+        v4 = W % 4 == 0
+        return 128 if v4 and (var == 3 or nc != 1) else 64
+
     for seg, wpb, nc, var, o in outs[1:]:
+        ref = next(r for r in outs[1:] if strip_cols(r[2], r[3]) == strip_cols(nc, var))
+        assert np.array_equal(o[2], ref[4][2]), ("grad_gain differs", seg, wpb, nc, var, ref[:4])
         # Above 8 bands the rolling and one-shot kernels sum grad_pan over
         # groups of 8 bands and add the groups; the staged kernel sums all
         # bands in one pass, so only grad_ms is comparable bit for bit there.
         if not (var == 3 and B > 8):
             assert np.array_equal(o[0], outs[0][4][0]), ("grad_pan differs", seg, wpb, nc, var)
         assert np.array_equal(o[1], outs[0][4][1]), ("grad_ms differs", seg, wpb, nc, var)
+
+
+@pytest.mark.parametrize("wavelet", ["haar", "d4"])
+@pytest.mark.parametrize("H,W", [(8, 8), (34, 136), (66, 516), (10, 1292)])
+def test_adjoint_writes_stay_inside(dev, fz, wavelet, H, W):
+    """Lanes past the last coefficient column of a strip (W/2 not a multiple
+    of the strip width) store nothing: grad_pan and grad_ms are views into
+    larger buffers whose other elements hold a sentinel, and every forced
+    adjoint shape must leave the sentinels alone."""
+    import ctypes
+
+    B = 3
+    rng = np.random.default_rng(H * W)
+    pan, _ = int_scene(rng, H, W, 1)
+    gy = rng.normal(size=(B, H, W)).astype(np.float32)
+    p, y = to_dev(pan, dev), to_dev(gy, dev)
+    gain = torch.ones(B, device=dev)
+    npan, nms = H * W, B * (H // 2) * (W // 2)
+    sentinel = 12345.0
+    ctx = fz.context(dev)
+    try:
+        for seg, wpb, nc, var in [(0, 0, 0, 0), (1, 1, 1, 1), (16, 4, 2, 1), (3, 2, 2, 0), (1, 4, 2, 2),
+                                  (2, 2, 2, 2), (1, 4, 2, 3), (2, 2, 1, 3)]:
+            say("adjoint sentinel", wavelet, H, W, seg, wpb, nc, var)
+            ctx.force_tile(seg, wpb, nc, var)
+            gp = torch.full((npan + 4096,), sentinel, device=dev)
+            gm = torch.full((nms + 4096,), sentinel, device=dev)
+            gg = torch.full((B + 64,), sentinel, device=dev)
+            ctx.check(ctx.lib.dwt_fuse_backward(ctx.handle, 0 if wavelet == "haar" else 1, H, W, B,
+                                                ctypes.c_void_p(p.data_ptr()), W, ctypes.c_void_p(gain.data_ptr()),
+                                                ctypes.c_void_p(y.data_ptr()), W, H * W,
+                                                ctypes.c_void_p(gp.data_ptr()), ctypes.c_void_p(gm.data_ptr()),
+                                                ctypes.c_void_p(gg.data_ptr())), "dwt_fuse_backward")
+            torch.cuda.synchronize(dev)
+            assert bool((gp[npan:] == sentinel).all()), ("grad_pan tail written", seg, wpb, nc, var)
+            assert bool((gm[nms:] == sentinel).all()), ("grad_ms tail written", seg, wpb, nc, var)
+            assert bool((gg[B:] == sentinel).all()), ("grad_gain tail written", seg, wpb, nc, var)
+            assert bool(torch.isfinite(gp[:npan]).all()) and bool(torch.isfinite(gm[:nms]).all())
+    finally:
+        ctx.force_tile(0, 0, 0, 0)
 
 
 @pytest.mark.parametrize("wavelet", ["haar", "d4"])
@@ -249,7 +300,7 @@ BWD_BATCH = [("d4", 66, 516, 4, 0, 0, True, (True, True, True)),
 
 def test_backward_batched_matches_single_calls(dev, fz, oracle):
     """One batched call equals a dwt_fuse_backward call per scene bit for bit
-    (same work units per scene, same fma chains, same fixed-order gain sums),
+    (same kernel variant per scene, same fma chains, same fixed-order gain sums),
     and meets the oracle's tolerance."""
     rng = np.random.default_rng(99)
     scenes = [_bwd_scene(rng, dev, *c) for c in BWD_BATCH]
@@ -278,6 +329,19 @@ def test_backward_batched_forced_shapes(dev, fz, seg, wpb, nc, var):
             _same(g, _single(fz, s))
     finally:
         ctx.force_tile(0, 0, 0, 0)
+
+
+def test_backward_batched_joint_unit_length(dev, fz):
+    """Eight 1024^2 D4 scenes with 4 bands: together they fill the GPU with
+    units twice as long as one scene alone takes, and the results still equal
+    the single calls bit for bit (grad_gain included: its products are kept
+    per coefficient row, not per unit)."""
+    rng = np.random.default_rng(17)
+    scenes = [_bwd_scene(rng, dev, "d4", 1024, 1024, 4) for _ in range(8)]
+    say("backward batched joint unit length")
+    got = fz.fuse_backward_batched(scenes)
+    for s, g in zip(scenes, got):
+        _same(g, _single(fz, s))
 
 
 def test_backward_batched_twice_and_empty(dev, fz):
