@@ -187,8 +187,10 @@ dwt_fuse_status dwt_fuse_run_batched(dwt_fuse_ctx *ctx, const dwt_fuse_item *ite
  *   grad_gain NULL or B floats:              < y_b, PAN - P PAN >
  * where P is the projection of an image onto its LL part.  grad_gain is
  * reduced in a fixed order (bitwise reproducible, whatever the rows per work
- * unit).  Outputs must not overlap
- * inputs.  Uses context workspace (DWT_FUSE_E_NOMEM if it cannot grow). */
+ * unit).  D4 with 5 or more bands on 16-byte aligned rows runs the LDS-staged
+ * adjoint (all bands in one launch), other cases the rolling adjoint.
+ * Outputs must not overlap inputs.  Uses context workspace (DWT_FUSE_E_NOMEM
+ * if it cannot grow). */
 dwt_fuse_status dwt_fuse_backward(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet,
                                   int64_t H, int64_t W, int64_t B,
                                   const float *pan, int64_t pan_ld, const float *gain,
@@ -212,9 +214,9 @@ typedef struct {
  * wavelets; the adjoint of a dwt_fuse_run_batched call, for instance) with
  * one adjoint launch per kernel variant present in the batch (scenes of the
  * same variant share a launch, so small scenes fill the GPU together) and
- * one launch for every grad_gain reduction.  Each scene gets the kernel
- * variant dwt_fuse_backward would give it on this context (the LDS-staged
- * adjoint of forced variant 3 is not used here); scenes on the default
+ * two launches for every grad_gain reduction.  Each scene gets the kernel
+ * variant dwt_fuse_backward would give it on this context (a scene on the
+ * LDS-staged adjoint gets a launch of its own); scenes on the default
  * band-unrolled D4 plan (at most 4 bands, no tuned or forced shape) may take
  * longer work units than alone, since the batch fills the GPU together.  No
  * gradient depends on the unit length, so every scene's results are
@@ -301,9 +303,10 @@ dwt_fuse_status dwt_fuse_tune_load(dwt_fuse_ctx *ctx, const char *path);
  * one-shot tiles.  dwt_fuse_backward and dwt_fuse_backward_batched follow the
  * rows, waves and columns fields with the rolling adjoint and variant 2 with
  * one-shot D4 adjoint tiles; variant 3 selects the LDS-staged D4 adjoint
- * (dwt_fuse_backward only, 16-byte aligned rows, 1 or 2 rows per wavefront,
- * up to 4 waves), which is otherwise never used.  DWT_FUSE_E_SHAPE if a field
- * is out of range. */
+ * (16-byte aligned rows, 1 or 2 rows per wavefront, up to 4 waves; columns
+ * 1 stages the upstream gradients band after band), which is otherwise the
+ * untuned default for D4 with 5 or more bands on 16-byte aligned rows.
+ * DWT_FUSE_E_SHAPE if a field is out of range. */
 dwt_fuse_status dwt_fuse_force_tile(dwt_fuse_ctx *ctx, int seg_rows, int waves_per_block, int cols_per_lane,
                                     int variant);
 

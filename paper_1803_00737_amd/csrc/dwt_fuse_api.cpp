@@ -1789,6 +1789,74 @@ static AdjParams bwd_params(const BwdArgs &a, const BwdTile &bt, float *partial,
     return p;
 }
 
+// The LDS-staged D4 adjoint (16-byte rows): workgroups of wpb wavefronts x
+// kr coefficient rows over a 128-column strip; `all` stages the upstream
+// gradients of as many bands as fit at once (else band after band in two
+// buffers).
+struct StagedBwd {
+    int kr = 0, wpb = 0;
+    bool all = true;
+};
+
+// Whether a scene takes the staged adjoint: on request (forced variant 3,
+// with the forced rows and waves), or by default for D4 with 5 or more bands
+// and no tuned or forced shape, where it measured faster than the rolling
+// adjoint (whose band loop is unrolled only up to 4 bands): 2 rows x 4
+// wavefronts, every band staged.
+static bool staged_bwd(const dwt_fuse_ctx *ctx, const BwdArgs &a, Path path, StagedBwd *sb) {
+    if (a.wavelet != DWT_FUSE_D4 || path != PATH_V4) return false;
+    const Forced &fc = ctx->forced;
+    if (fc.variant == 3) {
+        sb->kr = fc.seg_rows == 2 ? 2 : 1;
+        sb->wpb = fc.wpb >= 1 && fc.wpb <= 4 ? fc.wpb : 4;
+        sb->all = fc.nc != 1;
+    } else if (fc.variant == 0 && fc.seg_rows == 0 && fc.wpb == 0 && fc.nc == 0 && a.B >= 5 &&
+               it_bwd_default(ctx, a, path)) {
+        sb->kr = 2;
+        sb->wpb = 4;
+        sb->all = true;
+    } else {
+        return false;
+    }
+    return adjoint_staged_lds(sb->kr * sb->wpb, (int)a.B, sb->all) <= 65536;
+}
+
+static int64_t staged_strips(const BwdArgs &a) { return (a.W / 2 + 127) / 128; }
+
+// Launches the staged adjoint of one scene; gain slots go to `partial` (NULL:
+// no grad_gain).
+static dwt_fuse_status run_staged_bwd(dwt_fuse_ctx *ctx, const BwdArgs &a, Path path, const StagedBwd &sb,
+                                      float *partial) {
+    const int T = sb.kr * sb.wpb;
+    const int64_t ns = staged_strips(a), ng = (a.H / 2 + T - 1) / T;
+    if (ns * ng > INT32_MAX) return fail(ctx, DWT_FUSE_E_SHAPE, "too many work units");
+    AdjParams p{};
+    p.pan = a.pan;
+    p.gain = a.gain;
+    p.gy = a.gy;
+    p.grad_pan = const_cast<float *>(a.grad_pan);
+    p.grad_ms = const_cast<float *>(a.grad_ms);
+    p.partial = partial;
+    p.pan_ld = a.pan_ld;
+    p.gy_ld = a.gy_ld;
+    p.gy_bs = a.gy_bs;
+    p.H = (int32_t)a.H;
+    p.W = (int32_t)a.W;
+    p.B = (int32_t)a.B;
+    p.seg_rows = T;
+    p.nseg = (int32_t)ng;
+    p.units = (int32_t)(ns * ng);
+    p.wavelet = a.wavelet;
+    p.path = path;
+    p.nstrips = (int32_t)ns;
+    p.order = 0;
+    p.pstride = (int32_t)a.B;
+    p.accumulate = 0;
+    const hipError_t e = launch_adjoint_staged(p, ctx->filt, sb.kr, sb.wpb, sb.all, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "staged adjoint launch");
+    return DWT_FUSE_OK;
+}
+
 dwt_fuse_status dwt_fuse_backward(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet, int64_t H, int64_t W, int64_t B,
                                   const float *pan, int64_t pan_ld, const float *gain, const float *grad_out,
                                   int64_t go_ld, int64_t go_band_stride, float *grad_pan, float *grad_ms,
@@ -1803,20 +1871,9 @@ dwt_fuse_status dwt_fuse_backward(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet, i
         if (!grad_pan && !grad_ms && !grad_gain) return DWT_FUSE_OK;
         if ((st = use_device(ctx))) return st;
         const Path path = choose_bwd_path(a);
-        // D4 on 16-byte rows, on request only (forced variant 3): the LDS-staged
-        // adjoint (wpb wavefronts x kr rows, all bands in one launch).  The
-        // rolling adjoint below is faster on every shape measured, so it is the
-        // default.
-        const int skr = ctx->forced.seg_rows == 2 ? 2 : 1;
-        const int swpb = ctx->forced.wpb >= 1 && ctx->forced.wpb <= 4 ? ctx->forced.wpb : 4;
-        const bool staged = a.wavelet == DWT_FUSE_D4 && path == PATH_V4 && ctx->forced.variant == 3 &&
-                            adjoint_staged_lds(skr * swpb, (int)B, ctx->forced.nc != 1) <= 65536;
-        if (staged) {
-            const int kr = skr, wpb = swpb, T = kr * wpb;
-            const int64_t ns = (W / 2 + 127) / 128, ng = (H / 2 + T - 1) / T;
-            if (ns * ng > INT32_MAX) return fail(ctx, DWT_FUSE_E_SHAPE, "too many work units");
-            const int units = (int)(ns * ng);
-            const int64_t slots = gain_slots(H, ns);
+        StagedBwd sb;
+        if (staged_bwd(ctx, a, path, &sb)) {
+            const int64_t slots = gain_slots(H, staged_strips(a));
             if (slots > INT32_MAX - kGainChunk) return fail(ctx, DWT_FUSE_E_SHAPE, "too many gain partial slots");
             float *partial = nullptr;
             double *chunks = nullptr;
@@ -1825,32 +1882,9 @@ dwt_fuse_status dwt_fuse_backward(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet, i
                 partial = ctx->ws;
                 chunks = reinterpret_cast<double *>(reinterpret_cast<char *>(ctx->ws) + gain_ws_chunk_off(slots, B));
             }
-            AdjParams p{};
-            p.pan = pan;
-            p.gain = gain;
-            p.gy = grad_out;
-            p.grad_pan = grad_pan;
-            p.grad_ms = grad_ms;
-            p.partial = partial;
-            p.pan_ld = pan_ld;
-            p.gy_ld = go_ld;
-            p.gy_bs = go_band_stride;
-            p.H = (int32_t)H;
-            p.W = (int32_t)W;
-            p.B = (int32_t)B;
-            p.seg_rows = T;
-            p.nseg = (int32_t)ng;
-            p.units = units;
-            p.wavelet = a.wavelet;
-            p.path = path;
-            p.nstrips = (int32_t)ns;
-            p.order = 0;
-            p.pstride = (int32_t)B;
-            p.accumulate = 0;
-            hipError_t e = launch_adjoint_staged(p, ctx->filt, kr, wpb, ctx->forced.nc != 1, ctx->stream);
-            if (e != hipSuccess) return hip_fail(ctx, e, "staged adjoint launch");
+            if ((st = run_staged_bwd(ctx, a, path, sb, partial))) return st;
             if (grad_gain) {
-                e = launch_gain_reduce(partial, (int)slots, (int)B, chunks, grad_gain, ctx->stream);
+                const hipError_t e = launch_gain_reduce(partial, (int)slots, (int)B, chunks, grad_gain, ctx->stream);
                 if (e != hipSuccess) return hip_fail(ctx, e, "gain reduction launch");
             }
             return DWT_FUSE_OK;
@@ -1939,19 +1973,35 @@ dwt_fuse_status dwt_fuse_backward_batched(dwt_fuse_ctx *ctx, const dwt_fuse_bwd_
         if (st) return fail(ctx, st, err);
         if (n == 0) return DWT_FUSE_OK;
         if ((st = use_device(ctx))) return st;
-        // Plan every scene as dwt_fuse_backward would (without the staged form),
-        // then group the launches by kernel variant and band group.
+        // Plan every scene as dwt_fuse_backward would, then group the rolling
+        // and one-shot launches by kernel variant and band group; scenes on
+        // the LDS-staged adjoint get a launch of their own each.
         std::vector<BwdTile> tiles((size_t)n);
+        std::vector<StagedBwd> stg((size_t)n);
+        std::vector<char> is_staged((size_t)n, 0);
+        std::vector<int64_t> nslots((size_t)n, 0);
         std::vector<int64_t> poff((size_t)n, -1);  // float offset of a scene's partials in ws
         std::vector<int64_t> doff((size_t)n, -1);  // offset of its chunk sums in the double part
         int64_t pfloats = 0, pdoubles = 0;
         for (int64_t i = 0; i < n; ++i) {
             const BwdArgs a = bwd_item_args(items[i]);
             if (!a.grad_pan && !a.grad_ms && !a.grad_gain) continue;
-            if (!plan_bwd(ctx, a, choose_bwd_path(a), &tiles[(size_t)i]))
-                return fail(ctx, DWT_FUSE_E_SHAPE, "item " + std::to_string(i) + ": too many work units");
+            const Path path = choose_bwd_path(a);
+            if (staged_bwd(ctx, a, path, &stg[(size_t)i])) {
+                is_staged[(size_t)i] = 1;
+                nslots[(size_t)i] = gain_slots(a.H, staged_strips(a));
+                const int T = stg[(size_t)i].kr * stg[(size_t)i].wpb;
+                if (staged_strips(a) * ((a.H / 2 + T - 1) / T) > INT32_MAX)
+                    return fail(ctx, DWT_FUSE_E_SHAPE, "item " + std::to_string(i) + ": too many work units");
+                if (nslots[(size_t)i] > INT32_MAX - kGainChunk)
+                    return fail(ctx, DWT_FUSE_E_SHAPE, "item " + std::to_string(i) + ": too many gain partial slots");
+            } else {
+                if (!plan_bwd(ctx, a, path, &tiles[(size_t)i]))
+                    return fail(ctx, DWT_FUSE_E_SHAPE, "item " + std::to_string(i) + ": too many work units");
+                nslots[(size_t)i] = gain_slots(a.H, tiles[(size_t)i].d.nstrips);
+            }
             if (a.grad_gain) {
-                const int64_t slots = gain_slots(a.H, tiles[(size_t)i].d.nstrips);
+                const int64_t slots = nslots[(size_t)i];
                 poff[(size_t)i] = pfloats;
                 pfloats += slots * a.B;
                 doff[(size_t)i] = pdoubles;
@@ -1971,7 +2021,8 @@ dwt_fuse_status dwt_fuse_backward_batched(dwt_fuse_ctx *ctx, const dwt_fuse_bwd_
         {
             std::vector<int64_t> joint;
             for (int64_t i = 0; i < n; ++i)
-                if (tiles[(size_t)i].auto_seg && tiles[(size_t)i].kind == 1 && tiles[(size_t)i].t.mode == 0) {
+                if (!is_staged[(size_t)i] && tiles[(size_t)i].auto_seg && tiles[(size_t)i].kind == 1 &&
+                    tiles[(size_t)i].t.mode == 0) {
                     const BwdArgs a = bwd_item_args(items[i]);
                     if (a.grad_pan || a.grad_ms || a.grad_gain) joint.push_back(i);
                 }
@@ -2013,7 +2064,7 @@ dwt_fuse_status dwt_fuse_backward_batched(dwt_fuse_ctx *ctx, const dwt_fuse_bwd_
             if (!a.grad_pan && !a.grad_ms && !a.grad_gain) continue;
             const BwdTile &bt = tiles[(size_t)i];
             float *partial = poff[(size_t)i] >= 0 ? ctx->ws + poff[(size_t)i] : nullptr;
-            for (int64_t b0 = 0; b0 < a.B; b0 += maxb) {
+            for (int64_t b0 = 0; b0 < a.B && !is_staged[(size_t)i]; b0 += maxb) {
                 const int chunk = (int)(b0 / maxb);
                 BwdGroup &g = groups[std::make_tuple(chunk, bt.kind, (int)bt.pp, bt.x)];
                 g.kind = bt.kind;
@@ -2028,7 +2079,7 @@ dwt_fuse_status dwt_fuse_backward_batched(dwt_fuse_ctx *ctx, const dwt_fuse_bwd_
                 g.sc.push_back(sc);
             }
             if (partial) {
-                const int64_t slots = gain_slots(a.H, bt.d.nstrips), nch = gain_chunks(slots);
+                const int64_t slots = nslots[(size_t)i], nch = gain_chunks(slots);
                 for (int64_t b = 0; b < a.B; ++b) {
                     jobs.push_back(GainJob{partial, const_cast<float *>(a.grad_gain),
                                            dbase + doff[(size_t)i] + b * nch, (int32_t)slots, (int32_t)a.B,
@@ -2039,30 +2090,32 @@ dwt_fuse_status dwt_fuse_backward_batched(dwt_fuse_ctx *ctx, const dwt_fuse_bwd_
                 }
             }
         }
-        if (groups.empty()) return DWT_FUSE_OK;
         if (jobs.size() > (size_t)INT32_MAX) return fail(ctx, DWT_FUSE_E_SHAPE, "too many gain reductions in batch");
         size_t nsc = 0;
         for (const auto &kv : groups) nsc += kv.second.sc.size();
         const size_t sc_bytes = nsc * sizeof(AdjScene);
         const size_t job_off = (sc_bytes + 255) / 256 * 256;
         const size_t bytes = job_off + jobs.size() * sizeof(GainJob);
-        if ((st = ensure_bwd_tables(ctx, bytes))) return st;
-        if (ctx->bwd_pending) {  // the previous upload has left the pinned buffer
-            const hipError_t e = hipEventSynchronize(ctx->bwd_staged);
-            if (e != hipSuccess) return hip_fail(ctx, e, "hipEventSynchronize");
+        hipError_t e = hipSuccess;
+        if (nsc > 0 || !jobs.empty()) {
+            if ((st = ensure_bwd_tables(ctx, bytes))) return st;
+            if (ctx->bwd_pending) {  // the previous upload has left the pinned buffer
+                e = hipEventSynchronize(ctx->bwd_staged);
+                if (e != hipSuccess) return hip_fail(ctx, e, "hipEventSynchronize");
+            }
+            char *h = static_cast<char *>(ctx->h_bwd);
+            size_t off = 0;
+            for (const auto &kv : groups) {
+                std::memcpy(h + off, kv.second.sc.data(), kv.second.sc.size() * sizeof(AdjScene));
+                off += kv.second.sc.size() * sizeof(AdjScene);
+            }
+            if (!jobs.empty()) std::memcpy(h + job_off, jobs.data(), jobs.size() * sizeof(GainJob));
+            e = hipMemcpyAsync(ctx->d_bwd, ctx->h_bwd, bytes, hipMemcpyHostToDevice, ctx->stream);
+            if (e != hipSuccess) return hip_fail(ctx, e, "backward table upload");
+            e = hipEventRecord(ctx->bwd_staged, ctx->stream);
+            if (e != hipSuccess) return hip_fail(ctx, e, "hipEventRecord");
+            ctx->bwd_pending = true;
         }
-        char *h = static_cast<char *>(ctx->h_bwd);
-        size_t off = 0;
-        for (const auto &kv : groups) {
-            std::memcpy(h + off, kv.second.sc.data(), kv.second.sc.size() * sizeof(AdjScene));
-            off += kv.second.sc.size() * sizeof(AdjScene);
-        }
-        if (!jobs.empty()) std::memcpy(h + job_off, jobs.data(), jobs.size() * sizeof(GainJob));
-        hipError_t e = hipMemcpyAsync(ctx->d_bwd, ctx->h_bwd, bytes, hipMemcpyHostToDevice, ctx->stream);
-        if (e != hipSuccess) return hip_fail(ctx, e, "backward table upload");
-        e = hipEventRecord(ctx->bwd_staged, ctx->stream);
-        if (e != hipSuccess) return hip_fail(ctx, e, "hipEventRecord");
-        ctx->bwd_pending = true;
         // Band group 0 of every scene first (the map is ordered by chunk), so
         // later groups, which add into grad_pan, run after it on the stream.
         const AdjScene *d_sc = static_cast<const AdjScene *>(ctx->d_bwd);
@@ -2072,6 +2125,12 @@ dwt_fuse_status dwt_fuse_backward_batched(dwt_fuse_ctx *ctx, const dwt_fuse_bwd_
                                        ctx->stream);
             if (e != hipSuccess) return hip_fail(ctx, e, "batched adjoint launch");
             d_sc += g.sc.size();
+        }
+        for (int64_t i = 0; i < n; ++i) {
+            if (!is_staged[(size_t)i]) continue;
+            const BwdArgs a = bwd_item_args(items[i]);
+            float *partial = poff[(size_t)i] >= 0 ? ctx->ws + poff[(size_t)i] : nullptr;
+            if ((st = run_staged_bwd(ctx, a, choose_bwd_path(a), stg[(size_t)i], partial))) return st;
         }
         if (!jobs.empty()) {
             e = launch_gain_reduce_batched(
