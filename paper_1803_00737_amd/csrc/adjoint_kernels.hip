@@ -16,7 +16,10 @@
 // row of a strip are summed across the wavefront and written to their own
 // slot (gain_row), and gain_reduce_kernel sums the slots in a fixed order, so
 // grad_gain has the same bits whatever the unit length, order or variant
-// with two coefficient columns per lane.
+// with two coefficient columns per lane.  grad_pan and grad_ms are written
+// with non-temporal stores (they are not read again by the kernel, except
+// grad_pan by later band groups, and keeping them out of the caches leaves
+// room for the upstream-gradient halo rows).
 #include "fuse_internal.h"
 
 namespace dwtf {
@@ -45,7 +48,7 @@ __device__ __forceinline__ f2 ld2(const float *p) {
 template <bool AL>
 __device__ __forceinline__ void st2(float *p, f2 v) {
     if constexpr (AL) {
-        *reinterpret_cast<f2 *>(p) = v;
+        __builtin_nontemporal_store(v, reinterpret_cast<f2 *>(p));
     } else {
         p[0] = v.x;
         p[1] = v.y;
@@ -157,7 +160,7 @@ template <int NC, bool AL>
 __device__ __forceinline__ void store_pairs(float *row, int s0, int W2, bool full, const f2 (&q)[NC]) {
     if constexpr (NC == 2 && AL) {
         if (full)
-            *reinterpret_cast<f4 *>(row + 2 * s0) = f4{q[0].x, q[0].y, q[1].x, q[1].y};
+            __builtin_nontemporal_store(f4{q[0].x, q[0].y, q[1].x, q[1].y}, reinterpret_cast<f4 *>(row + 2 * s0));
         else if (s0 < W2)
             st2<AL>(row + 2 * s0, q[0]);
     } else {
@@ -171,7 +174,7 @@ template <int NC, bool AL>
 __device__ __forceinline__ void store_ms(float *row, int s0, int W2, bool full, const float (&v)[NC]) {
     if constexpr (NC == 2 && AL) {
         if (full)
-            *reinterpret_cast<f2 *>(row + s0) = f2{v[0], v[1]};
+            __builtin_nontemporal_store(f2{v[0], v[1]}, reinterpret_cast<f2 *>(row + s0));
         else if (s0 < W2)
             row[s0] = v[0];
     } else {
@@ -1064,7 +1067,7 @@ __global__ __launch_bounds__(256) void d4_adjoint_staged_kernel(AdjParams p, Fil
                 if (i >= nr) break;
                 float *gm = p.grad_ms + (int64_t)b * H2 * W2 + (int64_t)(rb + i) * W2 + s0;
                 if (full)
-                    *reinterpret_cast<f2 *>(gm) = f2{Ly[i + 1][1], Ly[i + 1][2]};
+                    __builtin_nontemporal_store(f2{Ly[i + 1][1], Ly[i + 1][2]}, reinterpret_cast<f2 *>(gm));
                 else
                     gm[0] = Ly[i + 1][1];
             }
@@ -1084,11 +1087,11 @@ __global__ __launch_bounds__(256) void d4_adjoint_staged_kernel(AdjParams p, Fil
             }
             float *g0 = p.grad_pan + (int64_t)(2 * (rb + i)) * p.W + 2 * s0;
             if (full) {
-                *reinterpret_cast<f4 *>(g0) = f4{q0[0].x, q0[0].y, q0[1].x, q0[1].y};
-                *reinterpret_cast<f4 *>(g0 + p.W) = f4{q1[0].x, q1[0].y, q1[1].x, q1[1].y};
+                __builtin_nontemporal_store(f4{q0[0].x, q0[0].y, q0[1].x, q0[1].y}, reinterpret_cast<f4 *>(g0));
+                __builtin_nontemporal_store(f4{q1[0].x, q1[0].y, q1[1].x, q1[1].y}, reinterpret_cast<f4 *>(g0 + p.W));
             } else {
-                *reinterpret_cast<f2 *>(g0) = q0[0];
-                *reinterpret_cast<f2 *>(g0 + p.W) = q1[0];
+                __builtin_nontemporal_store(q0[0], reinterpret_cast<f2 *>(g0));
+                __builtin_nontemporal_store(q1[0], reinterpret_cast<f2 *>(g0 + p.W));
             }
         }
     }
@@ -1243,7 +1246,7 @@ __global__ __launch_bounds__(256) void d4_adjoint_staged_all_kernel(AdjParams p,
                     if (i >= nr) break;
                     float *gm = p.grad_ms + (int64_t)b * H2 * W2 + (int64_t)(rb + i) * W2 + s0;
                     if (full)
-                        *reinterpret_cast<f2 *>(gm) = f2{Ly[i + 1][1], Ly[i + 1][2]};
+                        __builtin_nontemporal_store(f2{Ly[i + 1][1], Ly[i + 1][2]}, reinterpret_cast<f2 *>(gm));
                     else
                         gm[0] = Ly[i + 1][1];
                 }
@@ -1263,11 +1266,11 @@ __global__ __launch_bounds__(256) void d4_adjoint_staged_all_kernel(AdjParams p,
             }
             float *g0p = p.grad_pan + (int64_t)(2 * (rb + i)) * p.W + 2 * s0;
             if (full) {
-                *reinterpret_cast<f4 *>(g0p) = f4{q0[0].x, q0[0].y, q0[1].x, q0[1].y};
-                *reinterpret_cast<f4 *>(g0p + p.W) = f4{q1[0].x, q1[0].y, q1[1].x, q1[1].y};
+                __builtin_nontemporal_store(f4{q0[0].x, q0[0].y, q0[1].x, q0[1].y}, reinterpret_cast<f4 *>(g0p));
+                __builtin_nontemporal_store(f4{q1[0].x, q1[0].y, q1[1].x, q1[1].y}, reinterpret_cast<f4 *>(g0p + p.W));
             } else {
-                *reinterpret_cast<f2 *>(g0p) = q0[0];
-                *reinterpret_cast<f2 *>(g0p + p.W) = q1[0];
+                __builtin_nontemporal_store(q0[0], reinterpret_cast<f2 *>(g0p));
+                __builtin_nontemporal_store(q1[0], reinterpret_cast<f2 *>(g0p + p.W));
             }
         }
     }

@@ -1719,11 +1719,13 @@ static bool plan_bwd(const dwt_fuse_ctx *ctx, const BwdArgs &a, Path path, BwdTi
         if (it != ctx->table.end()) t = it->second;
     }
     if (a.wavelet == DWT_FUSE_D4 && B <= 4 && ctx->forced.seg_rows == 0 && it_bwd_default(ctx, a, path)) {
-        // band-unrolled D4 adjoint: longest units (<= 32 rows) that still
-        // give >= 2048 units (measured best at 2048^2 .. 8192^2)
-        t.seg_rows = 32;
+        // band-unrolled D4 adjoint: longest units (<= 64 rows) that still
+        // give >= 1536 units, i.e. about one round of wavefronts at the
+        // kernel's 2-3 waves per SIMD (measured best at 2048^2 .. 8192^2:
+        // 64 rows at 7680^2 and 8192^2, 16 at 4096^2, 4 at 2048^2)
+        t.seg_rows = 64;
         Decomp d0;
-        while (t.seg_rows > 4 && decompose(H, W, t, &d0) && d0.units < 2048) t.seg_rows /= 2;
+        while (t.seg_rows > 4 && decompose(H, W, t, &d0) && d0.units < 1536) t.seg_rows /= 2;
         out->auto_seg = true;
     } else {
         out->auto_seg = false;
@@ -2013,9 +2015,10 @@ dwt_fuse_status dwt_fuse_backward_batched(dwt_fuse_ctx *ctx, const dwt_fuse_bwd_
         if (pfloats > 0 && (st = ensure_ws(ctx, dbyte + (size_t)pdoubles * sizeof(double)))) return st;
         double *dbase = pfloats > 0 ? reinterpret_cast<double *>(reinterpret_cast<char *>(ctx->ws) + dbyte) : nullptr;
         // Scenes on the default band-unrolled D4 plan run in one launch, so
-        // their units are lengthened together: the longest (<= 32 rows) that
-        // still give >= 2048 units over all of them, never shorter than a
-        // scene would take alone.  Gradients do not depend on the unit length
+        // their units are lengthened together by the single-scene rule
+        // applied to the whole batch: the longest (<= 64 rows) that still
+        // give >= 1536 units over all of them, never shorter than a scene
+        // would take alone.  Gradients do not depend on the unit length
         // (the gain products are kept per row), so every scene's results still
         // equal its single call's bit for bit.
         {
@@ -2027,7 +2030,7 @@ dwt_fuse_status dwt_fuse_backward_batched(dwt_fuse_ctx *ctx, const dwt_fuse_bwd_
                     if (a.grad_pan || a.grad_ms || a.grad_gain) joint.push_back(i);
                 }
             if (joint.size() > 1) {
-                int seg = 32;
+                int seg = 64;
                 for (; seg > 4; seg /= 2) {
                     int64_t total = 0;
                     bool ok = true;
@@ -2041,7 +2044,7 @@ dwt_fuse_status dwt_fuse_backward_batched(dwt_fuse_ctx *ctx, const dwt_fuse_bwd_
                         }
                         total += d.units;
                     }
-                    if (ok && total >= 2048) break;
+                    if (ok && total >= 1536) break;
                 }
                 for (const int64_t i : joint) {
                     BwdTile &bt = tiles[(size_t)i];
