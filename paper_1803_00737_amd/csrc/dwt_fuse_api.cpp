@@ -667,7 +667,6 @@ Path path_for_nc(Path path, int nc) {
     return path;
 }
 
-// Time one forward launch configuration on the caller's buffers (ms, median of 3).
 // Median of 3 timed runs of `launch` on stream s (ms), after one warm-up;
 // 1e30 if any launch or event call fails, so a failing candidate is never
 // chosen.
@@ -691,16 +690,71 @@ float time_median3(hipStream_t s, F launch) {
     return t[1];
 }
 
+// One forward launch of shape t on the caller's buffers.
+hipError_t launch_tile(dwt_fuse_ctx *c, const RunArgs &a, Path path, const Tile &t) {
+    Decomp d;
+    if (!decompose(a.H, a.W, t, &d) || !split_fits(t, d, a.B)) return hipErrorInvalidValue;
+    const FuseParams p = make_params(a, path_for_nc(path, t.nc), t, d);
+    return launch_fuse(p, c->filt, t.wpb, c->stream);
+}
+
+// Time one forward launch configuration on the caller's buffers (ms, median of 3).
 float time_fuse(dwt_fuse_ctx *c, const RunArgs &a, Path path, const Tile &t) {
     Decomp d;
     if (!decompose(a.H, a.W, t, &d) || !split_fits(t, d, a.B)) return 1e30f;
-    const FuseParams p = make_params(a, path_for_nc(path, t.nc), t, d);
-    return time_median3(c->stream, [&] { return launch_fuse(p, c->filt, t.wpb, c->stream); });
+    return time_median3(c->stream, [&] { return launch_tile(c, a, path, t); });
+}
+
+// Second pass over the fastest few shapes of a first pass: 7 timed runs of
+// each, interleaved across the shapes (clock or thermal drift during the
+// pass then affects them alike); the lowest median wins.  A single pass
+// over ~100 shapes with 3 runs each tends to keep whichever shape happened
+// to run fast, 5-10% off the best one on the 8192^2 workload.
+Tile confirm_fuse(dwt_fuse_ctx *c, const RunArgs &a, Path path, std::vector<std::pair<float, Tile>> &cands,
+                  float *best_ms) {
+    std::stable_sort(cands.begin(), cands.end(),
+                     [](const std::pair<float, Tile> &x, const std::pair<float, Tile> &y) { return x.first < y.first; });
+    size_t k = 0;
+    while (k < cands.size() && k < 4 && cands[k].first < 1e29f) ++k;
+    *best_ms = cands[0].first;
+    if (k < 2) return cands[0].second;
+    constexpr int R = 7;
+    std::vector<float> t(k * R, 1e30f);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return cands[0].second;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return cands[0].second;
+    }
+    bool ok = true;
+    for (int r = 0; ok && r < R; ++r)
+        for (size_t i = 0; ok && i < k; ++i)
+            ok = hipEventRecord(e0, c->stream) == hipSuccess && launch_tile(c, a, path, cands[i].second) == hipSuccess &&
+                 hipEventRecord(e1, c->stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+                 hipEventElapsedTime(&t[i * R + r], e0, e1) == hipSuccess;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (!ok) return cands[0].second;
+    size_t best = 0;
+    float bm = 1e30f;
+    for (size_t i = 0; i < k; ++i) {
+        std::sort(t.begin() + i * R, t.begin() + (i + 1) * R);
+        const float m = t[i * R + R / 2];
+        if (m < bm) {
+            bm = m;
+            best = i;
+        }
+    }
+    *best_ms = bm;
+    return cands[best].second;
 }
 
 Tile tune_fuse(dwt_fuse_ctx *c, const RunArgs &a, Path path) {
-    Tile bestt = default_tile(a.wavelet, a.H, a.W, path);
-    float bestms = time_fuse(c, a, path, bestt);
+    std::vector<std::pair<float, Tile>> cands;
+    {
+        const Tile t = default_tile(a.wavelet, a.H, a.W, path);
+        cands.emplace_back(time_fuse(c, a, path, t), t);
+    }
     // Candidates: rolling units of 2..64 rows and one-shot units of 1 or 2
     // rows, each with 1, 2 or 4 waves per workgroup, both unit orders and
     // (on 128- and 64-bit rows) 1 or 2 coefficient columns per lane.
@@ -717,11 +771,7 @@ Tile tune_fuse(dwt_fuse_ctx *c, const RunArgs &a, Path path) {
                     t.seg_rows = rc < 0 ? -rc : rc;
                     t.wpb = wpb;
                     t.order = order;
-                    const float ms = time_fuse(c, a, path, t);
-                    if (ms < bestms) {
-                        bestms = ms;
-                        bestt = t;
-                    }
+                    cands.emplace_back(time_fuse(c, a, path, t), t);
                 }
             }
         }
@@ -739,15 +789,13 @@ Tile tune_fuse(dwt_fuse_ctx *c, const RunArgs &a, Path path) {
                     t.seg_rows = kr;
                     t.wpb = wpb;
                     t.order = order;
-                    const float ms = time_fuse(c, a, path, t);
-                    if (ms < bestms) {
-                        bestms = ms;
-                        bestt = t;
-                    }
+                    cands.emplace_back(time_fuse(c, a, path, t), t);
                 }
             }
         }
     }
+    float bestms = 0.f;
+    const Tile bestt = confirm_fuse(c, a, path, cands, &bestms);
     if (std::getenv("DWT_FUSE_LOG"))
         std::fprintf(stderr, "[dwt_fuse] tuned %s: mode=%d seg_rows=%d wpb=%d nc=%d order=%d split=%d (%.3f ms)\n",
                      tune_key(0, a.wavelet, a.H, a.W, a.B, path).c_str(), bestt.mode, bestt.seg_rows, bestt.wpb,
