@@ -657,7 +657,11 @@ __device__ __forceinline__ void d4_adj_tile(const AdjParams &p, const Filters &f
 
 // ---- Haar adjoint --------------------------------------------------------
 
-template <int NC, bool AL>
+// BG = 0: any band count, in groups of 4 bands; BG = p.B (1..4): the band
+// loop unrolled.  Either way a group's upstream-gradient rows are all loaded
+// before any is used, and both forms take the same fma chains in the same
+// order (bit-identical results).
+template <int NC, bool AL, int BG>
 __device__ __forceinline__ void haar_adj_unit(const AdjParams &p, int strip, int seg, int lane) {
     const int W2 = p.W >> 1, H2 = p.H >> 1;
     const int s0 = (strip * 64 + lane) * NC;
@@ -684,6 +688,28 @@ __device__ __forceinline__ void haar_adj_unit(const AdjParams &p, int strip, int
 #pragma unroll
         for (int i = 0; i < NC; ++i) x[i] = ld2<AL>(row + 2 * pc[i]);
     };
+    // One band's contribution at coefficient row r: grad_ms (the 2x2 block
+    // sums), Y += g y_b, and the gain product <y_b, D> over the lane's pixels.
+    auto band = [&](int b, float g, const f2(&z0)[NC], const f2(&z1)[NC], const f2(&Da)[NC], const f2(&Dc)[NC],
+                    f2(&Ya)[NC], f2(&Yc)[NC], int r) {
+        float bs[NC];
+        float dot = 0.f;
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            bs[i] = (z0[i].x + z0[i].y) + (z1[i].x + z1[i].y);  // transpose of block repeat
+            if (!valid[i]) continue;
+            Ya[i].x = fmaf(g, z0[i].x, Ya[i].x);
+            Ya[i].y = fmaf(g, z0[i].y, Ya[i].y);
+            Yc[i].x = fmaf(g, z1[i].x, Yc[i].x);
+            Yc[i].y = fmaf(g, z1[i].y, Yc[i].y);
+            dot = fmaf(z0[i].x, Da[i].x, dot);
+            dot = fmaf(z0[i].y, Da[i].y, dot);
+            dot = fmaf(z1[i].x, Dc[i].x, dot);
+            dot = fmaf(z1[i].y, Dc[i].y, dot);
+        }
+        if (p.grad_ms) store_ms<NC, AL>(p.grad_ms + (int64_t)b * H2 * W2 + (int64_t)r * W2, s0, W2, full, bs);
+        gain_row(p, strip, r, b, dot);
+    };
     for (int r = rb; r < re; ++r) {
         f2 a[NC], c[NC];
         load_own(p.pan + (int64_t)(2 * r) * p.pan_ld, a);
@@ -701,24 +727,33 @@ __device__ __forceinline__ void haar_adj_unit(const AdjParams &p, int strip, int
             Ya[i] = f2{0.f, 0.f};
             Yc[i] = f2{0.f, 0.f};
         }
-        for (int b = 0; b < p.B; ++b) {
-            const float g = p.gain ? p.gain[b] : 1.0f;
-            const float *yb = p.gy + (int64_t)b * p.gy_bs;
-            f2 z0[NC], z1[NC];
-            load_own(yb + (int64_t)(2 * r) * p.gy_ld, z0);
-            load_own(yb + (int64_t)(2 * r + 1) * p.gy_ld, z1);
-            float bs[NC];
-            float dot = 0.f;
+        if constexpr (BG > 0) {
+            f2 z0[BG][NC], z1[BG][NC];
 #pragma unroll
-            for (int i = 0; i < NC; ++i) {
-                bs[i] = (z0[i].x + z0[i].y) + (z1[i].x + z1[i].y);  // transpose of block repeat
-                if (!valid[i]) continue;
-                Ya[i] += g * z0[i];
-                Yc[i] += g * z1[i];
-                dot += z0[i].x * Da[i].x + z0[i].y * Da[i].y + z1[i].x * Dc[i].x + z1[i].y * Dc[i].y;
+            for (int b = 0; b < BG; ++b) {
+                const float *yb = p.gy + (int64_t)b * p.gy_bs;
+                load_own(yb + (int64_t)(2 * r) * p.gy_ld, z0[b]);
+                load_own(yb + (int64_t)(2 * r + 1) * p.gy_ld, z1[b]);
             }
-            if (p.grad_ms) store_ms<NC, AL>(p.grad_ms + (int64_t)b * H2 * W2 + (int64_t)r * W2, s0, W2, full, bs);
-            gain_row(p, strip, r, b, dot);
+#pragma unroll
+            for (int b = 0; b < BG; ++b) band(b, p.gain ? p.gain[b] : 1.0f, z0[b], z1[b], Da, Dc, Ya, Yc, r);
+        } else {
+            // bands in groups of 4, each group's rows loaded before any is used
+            for (int b0 = 0; b0 < p.B; b0 += 4) {
+                f2 z0[4][NC], z1[4][NC];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if (b0 + k >= p.B) break;
+                    const float *yb = p.gy + (int64_t)(b0 + k) * p.gy_bs;
+                    load_own(yb + (int64_t)(2 * r) * p.gy_ld, z0[k]);
+                    load_own(yb + (int64_t)(2 * r + 1) * p.gy_ld, z1[k]);
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if (b0 + k >= p.B) break;
+                    band(b0 + k, p.gain ? p.gain[b0 + k] : 1.0f, z0[k], z1[k], Da, Dc, Ya, Yc, r);
+                }
+            }
         }
         if (p.grad_pan) {
             f2 q0[NC], q1[NC];
@@ -758,7 +793,7 @@ __device__ __forceinline__ void unit_strip_seg(const AdjParams &p, int unit, int
 // Its gain products go to p.partial, one entry per coefficient row and strip
 // (gain_row).
 //   KIND 0: rolling, any wavelet, p.B <= kAdjMaxBands (X unused)
-//   KIND 1: rolling D4 with the band loop unrolled, p.B == X <= 4
+//   KIND 1: rolling (D4 or Haar) with the band loop unrolled, p.B == X <= 4
 //   KIND 2: one-shot D4 tile of X = p.seg_rows coefficient rows
 template <int KIND, int NC, bool AL, int X>
 __device__ __forceinline__ void adj_unit(const AdjParams &p, const Filters &f, int unit, int lane) {
@@ -768,9 +803,12 @@ __device__ __forceinline__ void adj_unit(const AdjParams &p, const Filters &f, i
         if (p.wavelet == 1)
             d4_adj_unit<NC, AL>(p, f, strip, seg, lane);
         else
-            haar_adj_unit<NC, AL>(p, strip, seg, lane);
+            haar_adj_unit<NC, AL, 0>(p, strip, seg, lane);
     } else if constexpr (KIND == 1) {
-        d4_adj_unit_bg<NC, AL, X>(p, f, strip, seg, lane);
+        if (p.wavelet == 1)
+            d4_adj_unit_bg<NC, AL, X>(p, f, strip, seg, lane);
+        else
+            haar_adj_unit<NC, AL, X>(p, strip, seg, lane);
     } else {
         d4_adj_tile<NC, AL, X>(p, f, strip, seg, lane);
     }
@@ -1339,7 +1377,7 @@ hipError_t launch_adjoint(const AdjParams &p, const Filters &f, int wpb, hipStre
 
 hipError_t launch_adjoint_bg(const AdjParams &p, const Filters &f, int wpb, hipStream_t s) {
     if (p.units <= 0) return hipSuccess;
-    if (p.B < 1 || p.B > 4 || p.wavelet != 1 || p.accumulate || wpb < 1 || wpb > 4 || p.path == PATH_V2W)
+    if (p.B < 1 || p.B > 4 || p.accumulate || wpb < 1 || wpb > 4 || p.path == PATH_V2W)
         return hipErrorInvalidValue;
     const int grid = (p.units + wpb - 1) / wpb;
     const dim3 block(64 * wpb);

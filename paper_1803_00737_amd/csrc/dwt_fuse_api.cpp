@@ -1738,7 +1738,7 @@ static bool it_bwd_default(const dwt_fuse_ctx *ctx, const BwdArgs &a, Path path)
 
 // Work units of the rolling / one-shot adjoint of one scene (everything but
 // the LDS-staged form): tile, launch path, decomposition and kernel variant
-// (kind 0 rolling, 1 rolling D4 with x = B <= 4 bands unrolled, 2 one-shot
+// (kind 0 rolling, 1 rolling with x = B <= 4 bands unrolled, 2 one-shot
 // D4 tiles of x rows).
 struct BwdTile {
     Tile t;
@@ -1795,12 +1795,12 @@ static bool plan_bwd(const dwt_fuse_ctx *ctx, const BwdArgs &a, Path path, BwdTi
     out->pp = path_for_nc(path, t.nc);
     if (!decompose(H, W, t, &out->d)) return false;
     if (gain_slots(H, out->d.nstrips) > INT32_MAX - kGainChunk) return false;
-    // D4 with at most 4 bands: the rolling kernel with the band loop
-    // unrolled (unless the dynamic-band rolling kernel is forced).
+    // At most 4 bands: the rolling kernel with the band loop unrolled
+    // (unless the dynamic-band rolling kernel is forced).
     if (t.mode != 0) {
         out->kind = 2;
         out->x = t.mode;
-    } else if (a.wavelet == DWT_FUSE_D4 && B <= 4 && ctx->forced.variant != 1) {
+    } else if (B <= 4 && ctx->forced.variant != 1) {
         out->kind = 1;
         out->x = (int)B;
     } else {

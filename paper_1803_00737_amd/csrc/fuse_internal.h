@@ -111,8 +111,9 @@ int staged_bg_max(int T);
 
 hipError_t launch_adjoint(const AdjParams &p, const Filters &f, int waves_per_block, hipStream_t s);
 
-// Rolling D4 adjoint with the band loop unrolled for p.B <= 4 bands (whole
-// band set in one launch, no accumulate); same units as launch_adjoint.
+// Rolling adjoint (D4 or Haar) with the band loop unrolled for p.B <= 4
+// bands (whole band set in one launch, no accumulate); same units and
+// results as launch_adjoint.
 hipError_t launch_adjoint_bg(const AdjParams &p, const Filters &f, int waves_per_block, hipStream_t s);
 
 // One-shot D4 adjoint: units of kr (1 or 2) coefficient rows (p.seg_rows == kr),
@@ -139,8 +140,8 @@ struct AdjScene {
 // Adjoint units of many scenes that share one kernel variant, in one launch
 // of 4-wavefront workgroups (scenes sorted by unit_begin, units of scene i
 // are unit_begin[i] .. unit_begin[i] + p.units - 1, total in all).  kind 0:
-// rolling, any wavelet, B <= adjoint_max_bands(); kind 1: rolling D4 with
-// x = B <= 4 bands unrolled (no accumulate); kind 2: one-shot D4 tiles of
+// rolling, any wavelet, B <= adjoint_max_bands(); kind 1: rolling, any
+// wavelet, x = B <= 4 bands unrolled (no accumulate); kind 2: one-shot D4 tiles of
 // x = seg_rows (1 or 2) rows.  path: PATH_V4, PATH_V2 or PATH_SCALAR, the
 // same for every scene.  Results per scene equal the single-scene launch.
 hipError_t launch_adjoint_batched(const AdjScene *d_scenes, int nscenes, int total, int kind, int path, int x,

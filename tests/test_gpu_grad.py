@@ -127,6 +127,42 @@ def test_forced_adjoint_shapes(dev, fz, oracle, H, W, B):
         assert np.array_equal(r[4][1], outs[0][4][1]), ("grad_ms differs", r[:4])
 
 
+@pytest.mark.parametrize("H,W", [(8, 8), (34, 136), (130, 1288), (66, 516), (34, 134), (66, 1030), (2, 2)])
+@pytest.mark.parametrize("B", [1, 3, 4, 6])
+def test_haar_adjoint_band_loop_forms(dev, fz, oracle, H, W, B):
+    """Haar adjoint: the band loop unrolled (default up to 4 bands) and the
+    dynamic band loop in groups of 4 bands (forced variant 1; the default
+    above 4 bands), at several unit lengths, take the same fma chains, so all
+    three gradients agree bit for bit, and meet the oracle's tolerance."""
+    rng = np.random.default_rng(11 * H + W + B)
+    pan, _ = int_scene(rng, H, W, 1)
+    gy = rng.normal(size=(B, H, W)).astype(np.float32)
+    gain = rng.uniform(0.5, 1.5, B).astype(np.float32)
+    p, y, g = to_dev(pan, dev), to_dev(gy, dev), to_dev(gain, dev)
+    ctx = fz.context(dev)
+    outs = []
+    try:
+        for seg, wpb, nc, var in [(0, 0, 0, 0), (1, 1, 1, 1), (7, 2, 2, 1), (32, 4, 2, 1), (3, 4, 2, 0),
+                                  (1, 1, 1, 0), (64, 1, 2, 0)]:
+            say("haar adjoint", H, W, B, seg, wpb, nc, var)
+            ctx.force_tile(seg, wpb, nc, var)
+            got = [t.cpu().numpy() for t in fz.fuse_backward(p, y, "haar", g)]
+            check_grads(oracle, "haar", pan, gy, gain, got)
+            outs.append(((seg, wpb, nc, var), got))
+    finally:
+        ctx.force_tile(0, 0, 0, 0)
+    v4 = W % 4 == 0
+
+    def strip_cols(seg, wpb, nc, var):
+        return 128 if v4 and nc != 1 else 64
+
+    for shape, o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][1][0]), ("grad_pan differs", shape)
+        assert np.array_equal(o[1], outs[0][1][1]), ("grad_ms differs", shape)
+        ref = next(q for q in outs if strip_cols(*q[0]) == strip_cols(*shape))
+        assert np.array_equal(o[2], ref[1][2]), ("grad_gain differs", shape, ref[0])
+
+
 @pytest.mark.parametrize("wavelet", ["haar", "d4"])
 @pytest.mark.parametrize("H,W", [(8, 8), (34, 136), (66, 516), (10, 1292)])
 def test_adjoint_writes_stay_inside(dev, fz, wavelet, H, W):
