@@ -36,18 +36,22 @@ __device__ __forceinline__ int wrap_idx(int q, int n) {
     return q < 0 ? q + n : q;
 }
 
-template <bool AL>
+// AL: the alignment class of a launch path's rows: 2 = 16-byte rows (pairs
+// 8-byte aligned; two-column reads and writes as 16-byte accesses), 1 =
+// 8-byte rows (pairs 8-byte aligned, rows of W/2 coefficients may be odd, so
+// coefficient pairs are written one by one), 0 = 4-byte alignment only.
+template <int AL>
 __device__ __forceinline__ f2 ld2(const float *p) {
-    if constexpr (AL) {
+    if constexpr (AL >= 1) {
         return *reinterpret_cast<const f2 *>(p);
     } else {
         return f2{p[0], p[1]};
     }
 }
 
-template <bool AL>
+template <int AL>
 __device__ __forceinline__ void st2(float *p, f2 v) {
-    if constexpr (AL) {
+    if constexpr (AL >= 1) {
         __builtin_nontemporal_store(v, reinterpret_cast<f2 *>(p));
     } else {
         p[0] = v.x;
@@ -98,11 +102,11 @@ __device__ __forceinline__ void gain_row(const AdjParams &p, int strip, int r, i
 
 // Loads NC+2 column pairs (pc[0..NC+1]) of one row; pairs 1..NC are the
 // lane's own pixels.
-template <int NC, bool AL>
+template <int NC, int AL>
 __device__ __forceinline__ void load_pairs(const float *row, const int (&pc)[NC + 2], int s0, bool full,
                                            f2 (&x)[NC + 2]) {
     x[0] = ld2<AL>(row + 2 * pc[0]);
-    if constexpr (NC == 2 && AL) {
+    if constexpr (NC == 2 && AL == 2) {
         if (full) {
             const f4 v = *reinterpret_cast<const f4 *>(row + 2 * s0);
             x[1] = f2{v.x, v.y};
@@ -156,9 +160,9 @@ __device__ __forceinline__ void synth_rows(const float (&h)[4], const float (&c)
     }
 }
 
-template <int NC, bool AL>
+template <int NC, int AL>
 __device__ __forceinline__ void store_pairs(float *row, int s0, int W2, bool full, const f2 (&q)[NC]) {
-    if constexpr (NC == 2 && AL) {
+    if constexpr (NC == 2 && AL == 2) {
         if (full)
             __builtin_nontemporal_store(f4{q[0].x, q[0].y, q[1].x, q[1].y}, reinterpret_cast<f4 *>(row + 2 * s0));
         else if (s0 < W2)
@@ -170,9 +174,9 @@ __device__ __forceinline__ void store_pairs(float *row, int s0, int W2, bool ful
     }
 }
 
-template <int NC, bool AL>
+template <int NC, int AL>
 __device__ __forceinline__ void store_ms(float *row, int s0, int W2, bool full, const float (&v)[NC]) {
-    if constexpr (NC == 2 && AL) {
+    if constexpr (NC == 2 && AL == 2) {
         if (full)
             __builtin_nontemporal_store(f2{v[0], v[1]}, reinterpret_cast<f2 *>(row + s0));
         else if (s0 < W2)
@@ -186,7 +190,7 @@ __device__ __forceinline__ void store_ms(float *row, int s0, int W2, bool full, 
 
 // ---- D4 adjoint ----------------------------------------------------------
 
-template <int NC, bool AL>
+template <int NC, int AL>
 __device__ __forceinline__ void d4_adj_unit(const AdjParams &p, const Filters &f, int strip, int seg, int lane) {
     const int W2 = p.W >> 1, H2 = p.H >> 1;
     const int s0 = (strip * 64 + lane) * NC;  // lanes past W2 load wrapped columns and store nothing
@@ -349,7 +353,7 @@ __device__ __forceinline__ void d4_adj_unit(const AdjParams &p, const Filters &f
 // next, so every row of y_b is loaded once per unit.  Same fma chains as the
 // other D4 adjoints (bit-identical grad_pan / grad_ms).
 
-template <int NC, bool AL, int BG>
+template <int NC, int AL, int BG>
 __device__ __forceinline__ void d4_adj_unit_bg(const AdjParams &p, const Filters &f, int strip, int seg, int lane) {
     const int W2 = p.W >> 1, H2 = p.H >> 1;
     const int s0 = (strip * 64 + lane) * NC;  // lanes past W2 load wrapped columns and store nothing
@@ -528,7 +532,7 @@ __device__ __forceinline__ void d4_adj_unit_bg(const AdjParams &p, const Filters
 // and operand order above, so all three gradients agree with the rolling
 // units bit for bit.
 
-template <int NC, bool AL, int KR>
+template <int NC, int AL, int KR>
 __device__ __forceinline__ void d4_adj_tile(const AdjParams &p, const Filters &f, int strip, int seg, int lane) {
     const int W2 = p.W >> 1, H2 = p.H >> 1;
     const int s0 = (strip * 64 + lane) * NC;  // lanes past W2 load wrapped columns and store nothing
@@ -661,7 +665,7 @@ __device__ __forceinline__ void d4_adj_tile(const AdjParams &p, const Filters &f
 // loop unrolled.  Either way a group's upstream-gradient rows are all loaded
 // before any is used, and both forms take the same fma chains in the same
 // order (bit-identical results).
-template <int NC, bool AL, int BG>
+template <int NC, int AL, int BG>
 __device__ __forceinline__ void haar_adj_unit(const AdjParams &p, int strip, int seg, int lane) {
     const int W2 = p.W >> 1, H2 = p.H >> 1;
     const int s0 = (strip * 64 + lane) * NC;
@@ -677,7 +681,7 @@ __device__ __forceinline__ void haar_adj_unit(const AdjParams &p, int strip, int
     const int rb = seg * p.seg_rows;
     const int re = min(rb + p.seg_rows, H2);
     auto load_own = [&](const float *row, f2(&x)[NC]) {
-        if constexpr (NC == 2 && AL) {
+        if constexpr (NC == 2 && AL == 2) {
             if (full) {
                 const f4 v = *reinterpret_cast<const f4 *>(row + 2 * s0);
                 x[0] = f2{v.x, v.y};
@@ -795,7 +799,7 @@ __device__ __forceinline__ void unit_strip_seg(const AdjParams &p, int unit, int
 //   KIND 0: rolling, any wavelet, p.B <= kAdjMaxBands (X unused)
 //   KIND 1: rolling (D4 or Haar) with the band loop unrolled, p.B == X <= 4
 //   KIND 2: one-shot D4 tile of X = p.seg_rows coefficient rows
-template <int KIND, int NC, bool AL, int X>
+template <int KIND, int NC, int AL, int X>
 __device__ __forceinline__ void adj_unit(const AdjParams &p, const Filters &f, int unit, int lane) {
     int strip, seg;
     unit_strip_seg(p, unit, strip, seg);
@@ -815,7 +819,7 @@ __device__ __forceinline__ void adj_unit(const AdjParams &p, const Filters &f, i
 }
 
 // One scene: one wavefront per work unit.
-template <int KIND, int NC, bool AL, int X>
+template <int KIND, int NC, int AL, int X>
 __global__ __launch_bounds__(256) void adjoint_kernel(AdjParams p, Filters f) {
     const int wpb = blockDim.x >> 6;
     const int lane = threadIdx.x & 63;
@@ -838,7 +842,7 @@ __device__ __forceinline__ int find_adj_scene(const AdjScene *sc, int n, int u) 
     return lo;
 }
 
-template <int KIND, int NC, bool AL, int X>
+template <int KIND, int NC, int AL, int X>
 __global__ __launch_bounds__(256) void adjoint_batched_kernel(const AdjScene *__restrict__ scenes, int nscenes,
                                                               int total, Filters f) {
     const int lane = threadIdx.x & 63;
@@ -1358,18 +1362,21 @@ hipError_t launch_adjoint_staged(const AdjParams &p, const Filters &f, int kr, i
 
 hipError_t launch_adjoint(const AdjParams &p, const Filters &f, int wpb, hipStream_t s) {
     if (p.units <= 0) return hipSuccess;
-    if (p.B > kAdjMaxBands || p.B < 1 || p.path == PATH_V2W) return hipErrorInvalidValue;
+    if (p.B > kAdjMaxBands || p.B < 1) return hipErrorInvalidValue;
     const int grid = (p.units + wpb - 1) / wpb;
     const dim3 block(64 * wpb);
     switch (p.path) {
         case PATH_V4:
-            hipLaunchKernelGGL((adjoint_kernel<0, 2, true, 0>), dim3(grid), block, 0, s, p, f);
+            hipLaunchKernelGGL((adjoint_kernel<0, 2, 2, 0>), dim3(grid), block, 0, s, p, f);
             break;
         case PATH_V2:
-            hipLaunchKernelGGL((adjoint_kernel<0, 1, true, 0>), dim3(grid), block, 0, s, p, f);
+            hipLaunchKernelGGL((adjoint_kernel<0, 1, 1, 0>), dim3(grid), block, 0, s, p, f);
+            break;
+        case PATH_V2W:
+            hipLaunchKernelGGL((adjoint_kernel<0, 2, 1, 0>), dim3(grid), block, 0, s, p, f);
             break;
         default:
-            hipLaunchKernelGGL((adjoint_kernel<0, 1, false, 0>), dim3(grid), block, 0, s, p, f);
+            hipLaunchKernelGGL((adjoint_kernel<0, 1, 0, 0>), dim3(grid), block, 0, s, p, f);
             break;
     }
     return hipGetLastError();
@@ -1377,16 +1384,16 @@ hipError_t launch_adjoint(const AdjParams &p, const Filters &f, int wpb, hipStre
 
 hipError_t launch_adjoint_bg(const AdjParams &p, const Filters &f, int wpb, hipStream_t s) {
     if (p.units <= 0) return hipSuccess;
-    if (p.B < 1 || p.B > 4 || p.accumulate || wpb < 1 || wpb > 4 || p.path == PATH_V2W)
-        return hipErrorInvalidValue;
+    if (p.B < 1 || p.B > 4 || p.accumulate || wpb < 1 || wpb > 4) return hipErrorInvalidValue;
     const int grid = (p.units + wpb - 1) / wpb;
     const dim3 block(64 * wpb);
 #define ADJ_BG(NC, AL, BG) hipLaunchKernelGGL((adjoint_kernel<1, NC, AL, BG>), dim3(grid), block, 0, s, p, f)
 #define ADJ_BG_PATH(BG)                                   \
     do {                                                  \
-        if (p.path == PATH_V4) ADJ_BG(2, true, BG);       \
-        else if (p.path == PATH_V2) ADJ_BG(1, true, BG);  \
-        else ADJ_BG(1, false, BG);                        \
+        if (p.path == PATH_V4) ADJ_BG(2, 2, BG);          \
+        else if (p.path == PATH_V2W) ADJ_BG(2, 1, BG);    \
+        else if (p.path == PATH_V2) ADJ_BG(1, 1, BG);     \
+        else ADJ_BG(1, 0, BG);                            \
     } while (0)
     switch (p.B) {
         case 1: ADJ_BG_PATH(1); break;
@@ -1401,20 +1408,21 @@ hipError_t launch_adjoint_bg(const AdjParams &p, const Filters &f, int wpb, hipS
 
 hipError_t launch_adjoint_tile(const AdjParams &p, const Filters &f, int kr, int wpb, hipStream_t s) {
     if (p.units <= 0) return hipSuccess;
-    if (p.B > kAdjMaxBands || p.B < 1 || p.wavelet != 1 || p.seg_rows != kr || wpb < 1 || wpb > 4 ||
-        p.path == PATH_V2W)
+    if (p.B > kAdjMaxBands || p.B < 1 || p.wavelet != 1 || p.seg_rows != kr || wpb < 1 || wpb > 4)
         return hipErrorInvalidValue;
     const int grid = (p.units + wpb - 1) / wpb;
     const dim3 block(64 * wpb);
 #define ADJ_TILE(NC, AL, KR) hipLaunchKernelGGL((adjoint_kernel<2, NC, AL, KR>), dim3(grid), block, 0, s, p, f)
     if (kr == 1) {
-        if (p.path == PATH_V4) ADJ_TILE(2, true, 1);
-        else if (p.path == PATH_V2) ADJ_TILE(1, true, 1);
-        else ADJ_TILE(1, false, 1);
+        if (p.path == PATH_V4) ADJ_TILE(2, 2, 1);
+        else if (p.path == PATH_V2W) ADJ_TILE(2, 1, 1);
+        else if (p.path == PATH_V2) ADJ_TILE(1, 1, 1);
+        else ADJ_TILE(1, 0, 1);
     } else if (kr == 2) {
-        if (p.path == PATH_V4) ADJ_TILE(2, true, 2);
-        else if (p.path == PATH_V2) ADJ_TILE(1, true, 2);
-        else ADJ_TILE(1, false, 2);
+        if (p.path == PATH_V4) ADJ_TILE(2, 2, 2);
+        else if (p.path == PATH_V2W) ADJ_TILE(2, 1, 2);
+        else if (p.path == PATH_V2) ADJ_TILE(1, 1, 2);
+        else ADJ_TILE(1, 0, 2);
     } else {
         return hipErrorInvalidValue;
     }
@@ -1425,16 +1433,17 @@ hipError_t launch_adjoint_tile(const AdjParams &p, const Filters &f, int kr, int
 hipError_t launch_adjoint_batched(const AdjScene *d_scenes, int nscenes, int total, int kind, int path, int x,
                                   const Filters &f, hipStream_t s) {
     if (nscenes <= 0 || total <= 0) return hipSuccess;
-    if (path == PATH_V2W || kind < 0 || kind > 2) return hipErrorInvalidValue;
+    if (kind < 0 || kind > 2) return hipErrorInvalidValue;
     if ((kind == 1 && (x < 1 || x > 4)) || (kind == 2 && x != 1 && x != 2)) return hipErrorInvalidValue;
     const dim3 grid((total + 3) / 4), block(256);
 #define ADJ_B(K, NC, AL, X) \
     hipLaunchKernelGGL((adjoint_batched_kernel<K, NC, AL, X>), grid, block, 0, s, d_scenes, nscenes, total, f)
 #define ADJ_B_PATH(K, X)                                  \
     do {                                                  \
-        if (path == PATH_V4) ADJ_B(K, 2, true, X);        \
-        else if (path == PATH_V2) ADJ_B(K, 1, true, X);   \
-        else ADJ_B(K, 1, false, X);                       \
+        if (path == PATH_V4) ADJ_B(K, 2, 2, X);           \
+        else if (path == PATH_V2W) ADJ_B(K, 2, 1, X);     \
+        else if (path == PATH_V2) ADJ_B(K, 1, 1, X);      \
+        else ADJ_B(K, 1, 0, X);                           \
     } while (0)
     if (kind == 0) {
         ADJ_B_PATH(0, 0);

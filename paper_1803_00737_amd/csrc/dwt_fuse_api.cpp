@@ -490,7 +490,7 @@ Tile default_tile(int wavelet, int64_t H, int64_t W, Path path) {
         t.wpb = 4;
         t.order = 0;
     } else {
-        t.nc = fwd_path_nc(path);
+        t.nc = path_nc(path);
         t.mode = 1;
         t.seg_rows = 1;
         t.wpb = wavelet == DWT_FUSE_D4 ? 4 : 1;
@@ -761,7 +761,7 @@ Tile tune_fuse(dwt_fuse_ctx *c, const RunArgs &a, Path path) {
     const int ncs[2] = {2, 1};
     const int rows_cand[8] = {-1, -2, 2, 4, 8, 16, 32, 64};  // negative: one-shot of that many rows
     for (int nc : ncs) {
-        if (nc > fwd_path_nc(path)) continue;
+        if (nc > path_nc(path)) continue;
         for (int rc : rows_cand) {
             for (int wpb : {1, 2, 4}) {
                 for (int order : {1, 0}) {
@@ -815,7 +815,7 @@ Tile tile_for_run(dwt_fuse_ctx *c, const RunArgs &a, Path path, bool allow_tune)
     } else {
         t = default_tile(a.wavelet, a.H, a.W, path);
     }
-    return apply_forced(c, t, path, a.wavelet, fwd_path_nc(path));
+    return apply_forced(c, t, path, a.wavelet, path_nc(path));
 }
 
 dwt_fuse_status ensure_ws(dwt_fuse_ctx *c, size_t bytes) {
@@ -925,7 +925,7 @@ dwt_fuse_status plan_batch(dwt_fuse_ctx *ctx, const dwt_fuse_item *items, int64_
                 t.seg_rows = 2;
                 pl->staged_bands = std::max<int>(pl->staged_bands, (int)a.B);
             } else {
-                t.nc = fwd_path_nc(path);
+                t.nc = path_nc(path);
                 t.mode = 1;
                 t.seg_rows = 1;
             }
@@ -936,7 +936,7 @@ dwt_fuse_status plan_batch(dwt_fuse_ctx *ctx, const dwt_fuse_item *items, int64_
             if (mode > 0) {
                 t.mode = mode;
             } else if (t.mode > 0) {  // one-shot or staged per-image tiles: rolling here
-                t = rolling_tile(a.H, a.W, fwd_path_nc(path));
+                t = rolling_tile(a.H, a.W, path_nc(path));
             }
             if (!decompose(a.H, a.W, t, &d)) return fail(ctx, DWT_FUSE_E_SHAPE, "too many work units");
             items_of_scene = d.units;
@@ -1790,7 +1790,7 @@ static bool plan_bwd(const dwt_fuse_ctx *ctx, const BwdArgs &a, Path path, BwdTi
     }
     if (t.mode == 1 || t.mode == 2) t.seg_rows = t.mode;
     if (t.seg_rows < 1) t.seg_rows = 1;
-    if (t.nc > path_nc(path)) t.nc = path_nc(path);  // the adjoint has no mixed 64/128-bit form
+    if (t.nc > path_nc(path)) t.nc = path_nc(path);
     out->t = t;
     out->pp = path_for_nc(path, t.nc);
     if (!decompose(H, W, t, &out->d)) return false;

@@ -19,11 +19,10 @@ namespace dwtf {
 // (PATH_V2 and PATH_V2W both mean 8-byte rows).
 enum Path : int32_t { PATH_V4 = 0, PATH_V2 = 1, PATH_SCALAR = 2, PATH_V2W = 3 };
 
-// Widest lane layout of a path chosen from the alignment of the arguments
-// (the adjoint kernels: NC = 2 needs the 128-bit path).
-inline int path_nc(Path p) { return p == PATH_V4 ? 2 : 1; }
-// The same for the forward kernels, which also run NC = 2 on 64-bit rows.
-inline int fwd_path_nc(Path p) { return p == PATH_SCALAR ? 1 : 2; }
+// Widest lane layout of a path chosen from the alignment of the arguments:
+// two coefficient columns per lane on 128- and 64-bit rows (the latter as
+// PATH_V2W, see path_for_nc), one on 32-bit rows.
+inline int path_nc(Path p) { return p == PATH_SCALAR ? 1 : 2; }
 
 // One scene as the kernels see it.  A work unit is one wavefront (64 lanes)
 // covering a strip of 64*NC coefficient columns and seg_rows coefficient

@@ -82,8 +82,8 @@ def test_forced_adjoint_shapes(dev, fz, oracle, H, W, B):
     order, so grad_pan and grad_ms also agree bit for bit.  The gain products
     are summed per (coefficient row, strip) whatever the unit length, so
     grad_gain agrees bit for bit between shapes with the same strip width
-    (128 columns: two columns per lane on 16-byte rows and the staged kernel;
-    64 columns: one column per lane)."""
+    (128 columns: two columns per lane, on 16- or 8-byte rows, and the staged
+    kernel; 64 columns: one column per lane)."""
     rng = np.random.default_rng(7 * H + W + B)
     pan, _ = int_scene(rng, H, W, 1)
     gy = rng.normal(size=(B, H, W)).astype(np.float32)
@@ -107,10 +107,10 @@ def test_forced_adjoint_shapes(dev, fz, oracle, H, W, B):
     v4 = W % 4 == 0
 
     def strip_cols(seg, wpb, nc, var):
-        if not v4:
-            return 64
-        if (seg, wpb, nc, var) == (0, 0, 0, 0):  # default: staged from 5 bands, else 2 columns per lane
+        if (seg, wpb, nc, var) == (0, 0, 0, 0):  # default: staged from 5 bands on 16-byte rows, else 2 columns
             return 128
+        # variant 3 is the staged kernel on 16-byte rows; on 8-byte rows it
+        # falls back to rolling units that keep the staged shape's 2 columns
         return 128 if var == 3 or nc != 1 else 64
 
     def staged(seg, wpb, nc, var):
@@ -151,10 +151,8 @@ def test_haar_adjoint_band_loop_forms(dev, fz, oracle, H, W, B):
             outs.append(((seg, wpb, nc, var), got))
     finally:
         ctx.force_tile(0, 0, 0, 0)
-    v4 = W % 4 == 0
-
     def strip_cols(seg, wpb, nc, var):
-        return 128 if v4 and nc != 1 else 64
+        return 128 if nc != 1 else 64
 
     for shape, o in outs[1:]:
         assert np.array_equal(o[0], outs[0][1][0]), ("grad_pan differs", shape)
@@ -164,10 +162,11 @@ def test_haar_adjoint_band_loop_forms(dev, fz, oracle, H, W, B):
 
 
 @pytest.mark.parametrize("wavelet", ["haar", "d4"])
-@pytest.mark.parametrize("H,W", [(8, 8), (34, 136), (66, 516), (10, 1292)])
+@pytest.mark.parametrize("H,W", [(8, 8), (34, 136), (66, 516), (10, 1292), (34, 134), (10, 1290), (6, 6)])
 def test_adjoint_writes_stay_inside(dev, fz, wavelet, H, W):
     """Lanes past the last coefficient column of a strip (W/2 not a multiple
-    of the strip width) store nothing: grad_pan and grad_ms are views into
+    of the strip width; on 8-byte rows W/2 is odd, so one lane holds a valid
+    and an invalid column) store nothing: grad_pan and grad_ms are views into
     larger buffers whose other elements hold a sentinel, and every forced
     adjoint shape must leave the sentinels alone."""
     import ctypes
