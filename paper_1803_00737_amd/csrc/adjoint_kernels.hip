@@ -936,7 +936,7 @@ __global__ __launch_bounds__(256) void gain_total_batched_kernel(const GainJob *
     if (threadIdx.x == 0) j.grad_gain[j.band] = (float)a;
 }
 
-// ---- D4 adjoint, LDS-staged workgroup tile (16-byte rows) -------------------
+// ---- D4 adjoint, LDS-staged workgroup tile (16- or 8-byte rows) -------------
 //
 // A workgroup of wpb wavefronts covers a strip of 128 coefficient columns and
 // T = wpb * KR coefficient rows.  PAN rows 2r0-2 .. 2r0+2T+1 (with 2-column
@@ -957,13 +957,21 @@ __device__ __forceinline__ void lds_load16(const float *g, float *l) {
     __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void *)l, 16, 0, 0);
 }
 
-// Stage rows 2r0-2+k (k < 2T+4) of an H x W image (pitch ld) for strip sb.
+// Stage rows 2r0-2+k (k < 2T+4) of an H x W image (pitch ld) for strip sb:
+// 16 bytes per lane on 16-byte rows (A16), else four 4-byte loads per lane,
+// each column wrapped on its own.
+template <bool A16>
 __device__ __forceinline__ void adj_stage_rows(const float *img, int64_t ld, int H, int W, int r0, int T, int sb,
                                                float *dst, int w, int wpb, int lane) {
     for (int k = w; k < 2 * T + 4; k += wpb) {
         const float *row = img + (int64_t)wrap_idx(2 * r0 - 2 + k, H) * ld;
         float *d = dst + k * kAdjRow;
-        lds_load16(row + wrap_idx(2 * sb + 4 * lane, W), d + 4);
+        if constexpr (A16) {
+            lds_load16(row + wrap_idx(2 * sb + 4 * lane, W), d + 4);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) lds_load4(row + wrap_idx(2 * sb + 64 * q + lane, W), d + 4 + 64 * q);
+        }
         if (lane < 2) {
             lds_load4(row + wrap_idx(2 * sb - 2 + lane, W), d + 2);
             lds_load4(row + wrap_idx(2 * sb + 256 + lane, W), d + 260);
@@ -971,7 +979,40 @@ __device__ __forceinline__ void adj_stage_rows(const float *img, int64_t ld, int
     }
 }
 
-template <int KR>
+// grad_ms of a lane's two coefficients (one if !full): one 8-byte store on
+// 16-byte rows; on 8-byte rows W/2 is odd, so two 4-byte stores.
+template <bool A16>
+__device__ __forceinline__ void staged_store_ms(float *gm, bool full, float v0, float v1) {
+    if (!full) {
+        gm[0] = v0;
+    } else if constexpr (A16) {
+        __builtin_nontemporal_store(f2{v0, v1}, reinterpret_cast<f2 *>(gm));
+    } else {
+        __builtin_nontemporal_store(v0, gm);
+        __builtin_nontemporal_store(v1, gm + 1);
+    }
+}
+
+// grad_pan of a lane's 2x2 (2x1 if !full) pixel pairs in rows g0 and g0 + W.
+template <bool A16>
+__device__ __forceinline__ void staged_store_pan(float *g0, int W, bool full, const f2 (&q0)[2], const f2 (&q1)[2]) {
+    if (full) {
+        if constexpr (A16) {
+            __builtin_nontemporal_store(f4{q0[0].x, q0[0].y, q0[1].x, q0[1].y}, reinterpret_cast<f4 *>(g0));
+            __builtin_nontemporal_store(f4{q1[0].x, q1[0].y, q1[1].x, q1[1].y}, reinterpret_cast<f4 *>(g0 + W));
+        } else {
+            __builtin_nontemporal_store(q0[0], reinterpret_cast<f2 *>(g0));
+            __builtin_nontemporal_store(q0[1], reinterpret_cast<f2 *>(g0 + 2));
+            __builtin_nontemporal_store(q1[0], reinterpret_cast<f2 *>(g0 + W));
+            __builtin_nontemporal_store(q1[1], reinterpret_cast<f2 *>(g0 + W + 2));
+        }
+    } else {
+        __builtin_nontemporal_store(q0[0], reinterpret_cast<f2 *>(g0));
+        __builtin_nontemporal_store(q1[0], reinterpret_cast<f2 *>(g0 + W));
+    }
+}
+
+template <int KR, bool A16>
 __global__ __launch_bounds__(256) void d4_adjoint_staged_kernel(AdjParams p, Filters f) {
     extern __shared__ float lds[];
     const int wpb = blockDim.x >> 6;
@@ -993,8 +1034,8 @@ __global__ __launch_bounds__(256) void d4_adjoint_staged_kernel(AdjParams p, Fil
     float *Pl = lds;
     float *Yl[2] = {lds + rows * kAdjRow, lds + 2 * rows * kAdjRow};
 
-    adj_stage_rows(p.pan, p.pan_ld, p.H, p.W, r0, T, sb, Pl, w, wpb, lane);
-    adj_stage_rows(p.gy, p.gy_ld, p.H, p.W, r0, T, sb, Yl[0], w, wpb, lane);
+    adj_stage_rows<A16>(p.pan, p.pan_ld, p.H, p.W, r0, T, sb, Pl, w, wpb, lane);
+    adj_stage_rows<A16>(p.gy, p.gy_ld, p.H, p.W, r0, T, sb, Yl[0], w, wpb, lane);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
 
@@ -1055,7 +1096,7 @@ __global__ __launch_bounds__(256) void d4_adjoint_staged_kernel(AdjParams p, Fil
     for (int b = 0; b < p.B; ++b) {
         const float *Yb = Yl[b & 1];
         if (b + 1 < p.B)  // next band into the other buffer, in flight during this band
-            adj_stage_rows(p.gy + (int64_t)(b + 1) * p.gy_bs, p.gy_ld, p.H, p.W, r0, T, sb, Yl[(b + 1) & 1], w, wpb,
+            adj_stage_rows<A16>(p.gy + (int64_t)(b + 1) * p.gy_bs, p.gy_ld, p.H, p.W, r0, T, sb, Yl[(b + 1) & 1], w, wpb,
                            lane);
         const float g = p.gain ? p.gain[b] : 1.0f;
         float R[NR][3];
@@ -1108,10 +1149,7 @@ __global__ __launch_bounds__(256) void d4_adjoint_staged_kernel(AdjParams p, Fil
             for (int i = 0; i < KR; ++i) {
                 if (i >= nr) break;
                 float *gm = p.grad_ms + (int64_t)b * H2 * W2 + (int64_t)(rb + i) * W2 + s0;
-                if (full)
-                    __builtin_nontemporal_store(f2{Ly[i + 1][1], Ly[i + 1][2]}, reinterpret_cast<f2 *>(gm));
-                else
-                    gm[0] = Ly[i + 1][1];
+                staged_store_ms<A16>(gm, full, Ly[i + 1][1], Ly[i + 1][2]);
             }
         }
     }
@@ -1128,13 +1166,7 @@ __global__ __launch_bounds__(256) void d4_adjoint_staged_kernel(AdjParams p, Fil
                 q1[c] = Y[2 * i + 1][c] - sb[c];
             }
             float *g0 = p.grad_pan + (int64_t)(2 * (rb + i)) * p.W + 2 * s0;
-            if (full) {
-                __builtin_nontemporal_store(f4{q0[0].x, q0[0].y, q0[1].x, q0[1].y}, reinterpret_cast<f4 *>(g0));
-                __builtin_nontemporal_store(f4{q1[0].x, q1[0].y, q1[1].x, q1[1].y}, reinterpret_cast<f4 *>(g0 + p.W));
-            } else {
-                __builtin_nontemporal_store(q0[0], reinterpret_cast<f2 *>(g0));
-                __builtin_nontemporal_store(q1[0], reinterpret_cast<f2 *>(g0 + p.W));
-            }
+            staged_store_pan<A16>(g0, p.W, full, q0, q1);
         }
     }
 }
@@ -1143,7 +1175,7 @@ __global__ __launch_bounds__(256) void d4_adjoint_staged_kernel(AdjParams p, Fil
 // staged together: PAN and the group's y rows go to LDS at once, one barrier,
 // then every band of the group is computed from LDS without further waits
 // (per-pixel values as in the kernel above, so results are bit-identical).
-template <int KR>
+template <int KR, bool A16>
 __global__ __launch_bounds__(256) void d4_adjoint_staged_all_kernel(AdjParams p, Filters f, int bg_all) {
     extern __shared__ float lds[];
     const int wpb = blockDim.x >> 6;
@@ -1167,10 +1199,10 @@ __global__ __launch_bounds__(256) void d4_adjoint_staged_all_kernel(AdjParams p,
 
     auto stage_group = [&](int g0, int bg) {
         for (int bi = 0; bi < bg; ++bi)
-            adj_stage_rows(p.gy + (int64_t)(g0 + bi) * p.gy_bs, p.gy_ld, p.H, p.W, r0, T, sb, Yl + bi * rows * kAdjRow,
+            adj_stage_rows<A16>(p.gy + (int64_t)(g0 + bi) * p.gy_bs, p.gy_ld, p.H, p.W, r0, T, sb, Yl + bi * rows * kAdjRow,
                            w, wpb, lane);
     };
-    adj_stage_rows(p.pan, p.pan_ld, p.H, p.W, r0, T, sb, Pl, w, wpb, lane);
+    adj_stage_rows<A16>(p.pan, p.pan_ld, p.H, p.W, r0, T, sb, Pl, w, wpb, lane);
     stage_group(0, min(bg_all, p.B));
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
@@ -1287,10 +1319,7 @@ __global__ __launch_bounds__(256) void d4_adjoint_staged_all_kernel(AdjParams p,
                 for (int i = 0; i < KR; ++i) {
                     if (i >= nr) break;
                     float *gm = p.grad_ms + (int64_t)b * H2 * W2 + (int64_t)(rb + i) * W2 + s0;
-                    if (full)
-                        __builtin_nontemporal_store(f2{Ly[i + 1][1], Ly[i + 1][2]}, reinterpret_cast<f2 *>(gm));
-                    else
-                        gm[0] = Ly[i + 1][1];
+                    staged_store_ms<A16>(gm, full, Ly[i + 1][1], Ly[i + 1][2]);
                 }
             }
         }
@@ -1307,13 +1336,7 @@ __global__ __launch_bounds__(256) void d4_adjoint_staged_all_kernel(AdjParams p,
                 q1[c] = Y[2 * i + 1][c] - sb2[c];
             }
             float *g0p = p.grad_pan + (int64_t)(2 * (rb + i)) * p.W + 2 * s0;
-            if (full) {
-                __builtin_nontemporal_store(f4{q0[0].x, q0[0].y, q0[1].x, q0[1].y}, reinterpret_cast<f4 *>(g0p));
-                __builtin_nontemporal_store(f4{q1[0].x, q1[0].y, q1[1].x, q1[1].y}, reinterpret_cast<f4 *>(g0p + p.W));
-            } else {
-                __builtin_nontemporal_store(q0[0], reinterpret_cast<f2 *>(g0p));
-                __builtin_nontemporal_store(q1[0], reinterpret_cast<f2 *>(g0p + p.W));
-            }
+            staged_store_pan<A16>(g0p, p.W, full, q0, q1);
         }
     }
 }
@@ -1338,23 +1361,28 @@ size_t adjoint_staged_lds(int T, int B, bool all) {
 
 hipError_t launch_adjoint_staged(const AdjParams &p, const Filters &f, int kr, int wpb, bool all, hipStream_t s) {
     if (p.units <= 0) return hipSuccess;
-    if (p.wavelet != 1 || p.path != PATH_V4 || p.seg_rows != kr * wpb || p.nstrips != (p.W / 2 + 127) / 128)
+    if (p.wavelet != 1 || p.path == PATH_SCALAR || p.seg_rows != kr * wpb || p.nstrips != (p.W / 2 + 127) / 128)
         return hipErrorInvalidValue;
+    const bool a16 = p.path == PATH_V4;
     const size_t lds = adjoint_staged_lds(p.seg_rows, p.B, all);
     if (lds > 65536) return hipErrorInvalidValue;
     const dim3 grid(p.units), block(64 * wpb);
     if (all) {
         const int g = adjoint_staged_group(p.seg_rows, p.B);
-        switch (kr) {
-            case 1: hipLaunchKernelGGL(d4_adjoint_staged_all_kernel<1>, grid, block, lds, s, p, f, g); break;
-            case 2: hipLaunchKernelGGL(d4_adjoint_staged_all_kernel<2>, grid, block, lds, s, p, f, g); break;
+        switch (kr * 2 + (a16 ? 1 : 0)) {
+            case 2: hipLaunchKernelGGL((d4_adjoint_staged_all_kernel<1, false>), grid, block, lds, s, p, f, g); break;
+            case 3: hipLaunchKernelGGL((d4_adjoint_staged_all_kernel<1, true>), grid, block, lds, s, p, f, g); break;
+            case 4: hipLaunchKernelGGL((d4_adjoint_staged_all_kernel<2, false>), grid, block, lds, s, p, f, g); break;
+            case 5: hipLaunchKernelGGL((d4_adjoint_staged_all_kernel<2, true>), grid, block, lds, s, p, f, g); break;
             default: return hipErrorInvalidValue;
         }
         return hipGetLastError();
     }
-    switch (kr) {
-        case 1: hipLaunchKernelGGL(d4_adjoint_staged_kernel<1>, grid, block, lds, s, p, f); break;
-        case 2: hipLaunchKernelGGL(d4_adjoint_staged_kernel<2>, grid, block, lds, s, p, f); break;
+    switch (kr * 2 + (a16 ? 1 : 0)) {
+        case 2: hipLaunchKernelGGL((d4_adjoint_staged_kernel<1, false>), grid, block, lds, s, p, f); break;
+        case 3: hipLaunchKernelGGL((d4_adjoint_staged_kernel<1, true>), grid, block, lds, s, p, f); break;
+        case 4: hipLaunchKernelGGL((d4_adjoint_staged_kernel<2, false>), grid, block, lds, s, p, f); break;
+        case 5: hipLaunchKernelGGL((d4_adjoint_staged_kernel<2, true>), grid, block, lds, s, p, f); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

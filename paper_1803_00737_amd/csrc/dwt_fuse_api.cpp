@@ -1839,7 +1839,7 @@ static AdjParams bwd_params(const BwdArgs &a, const BwdTile &bt, float *partial,
     return p;
 }
 
-// The LDS-staged D4 adjoint (16-byte rows): workgroups of wpb wavefronts x
+// The LDS-staged D4 adjoint (16- or 8-byte rows): workgroups of wpb wavefronts x
 // kr coefficient rows over a 128-column strip; `all` stages the upstream
 // gradients of as many bands as fit at once (else band after band in two
 // buffers).
@@ -1854,7 +1854,7 @@ struct StagedBwd {
 // adjoint (whose band loop is unrolled only up to 4 bands): 2 rows x 4
 // wavefronts, every band staged.
 static bool staged_bwd(const dwt_fuse_ctx *ctx, const BwdArgs &a, Path path, StagedBwd *sb) {
-    if (a.wavelet != DWT_FUSE_D4 || path != PATH_V4) return false;
+    if (a.wavelet != DWT_FUSE_D4 || path == PATH_SCALAR) return false;
     const Forced &fc = ctx->forced;
     if (fc.variant == 3) {
         sb->kr = fc.seg_rows == 2 ? 2 : 1;

@@ -104,17 +104,14 @@ def test_forced_adjoint_shapes(dev, fz, oracle, H, W, B):
             outs.append((seg, wpb, nc, var, got))
     finally:
         ctx.force_tile(0, 0, 0, 0)
-    v4 = W % 4 == 0
 
     def strip_cols(seg, wpb, nc, var):
         if (seg, wpb, nc, var) == (0, 0, 0, 0):  # default: staged from 5 bands on 16-byte rows, else 2 columns
             return 128
-        # variant 3 is the staged kernel on 16-byte rows; on 8-byte rows it
-        # falls back to rolling units that keep the staged shape's 2 columns
         return 128 if var == 3 or nc != 1 else 64
 
-    def staged(seg, wpb, nc, var):
-        return v4 and (var == 3 or ((seg, wpb, nc, var) == (0, 0, 0, 0) and B >= 5))
+    def staged(seg, wpb, nc, var):  # contiguous rows: 16- or 8-byte aligned, both staged
+        return var == 3 or ((seg, wpb, nc, var) == (0, 0, 0, 0) and B >= 5)
 
     for r in outs:
         ref = next(q for q in outs if strip_cols(*q[:4]) == strip_cols(*r[:4]))
