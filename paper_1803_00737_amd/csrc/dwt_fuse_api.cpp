@@ -1759,6 +1759,35 @@ static size_t gain_ws_bytes(int64_t slots, int64_t B) {
     return gain_ws_chunk_off(slots, B) + (size_t)(gain_chunks(slots) * B) * sizeof(double);
 }
 
+// Rows per unit of the band-unrolled D4 adjoint over scenes (H[i], W[i])
+// that share one launch: 64 if that still gives >= 1536 units (about one
+// round of wavefronts at the kernel's 2-3 waves per SIMD), else the longest
+// of 16, 8, 4 that does (4 at least).  Measured: 64 best at 7680^2 and
+// 8192^2; below 1536 units at 64 rows, 32-row units lost to 16-row ones
+// (6144^2 B = 3: 0.216 vs 0.194 ms; 4096^2 B = 4: 0.113 vs 0.101 ms).
+struct SegScene {
+    int64_t H, W;
+    Tile t;
+};
+static int bwd_auto_seg(const std::vector<SegScene> &sc) {
+    auto units = [&](int seg) {
+        int64_t n = 0;
+        for (const SegScene &s : sc) {
+            Tile t = s.t;
+            t.seg_rows = seg;
+            Decomp d;
+            if (!decompose(s.H, s.W, t, &d)) return (int64_t)-1;
+            n += d.units;
+        }
+        return n;
+    };
+    if (units(64) >= 1536) return 64;
+    for (int seg : {16, 8})
+        if (units(seg) >= 1536) return seg;
+    return 4;
+}
+static int bwd_auto_seg(int64_t H, int64_t W, const Tile &t) { return bwd_auto_seg(std::vector<SegScene>{{H, W, t}}); }
+
 static bool plan_bwd(const dwt_fuse_ctx *ctx, const BwdArgs &a, Path path, BwdTile *out) {
     const int64_t H = a.H, W = a.W, B = a.B;
     Tile t = rolling_tile(H, W, path_nc(path));
@@ -1767,13 +1796,7 @@ static bool plan_bwd(const dwt_fuse_ctx *ctx, const BwdArgs &a, Path path, BwdTi
         if (it != ctx->table.end()) t = it->second;
     }
     if (a.wavelet == DWT_FUSE_D4 && B <= 4 && ctx->forced.seg_rows == 0 && it_bwd_default(ctx, a, path)) {
-        // band-unrolled D4 adjoint: longest units (<= 64 rows) that still
-        // give >= 1536 units, i.e. about one round of wavefronts at the
-        // kernel's 2-3 waves per SIMD (measured best at 2048^2 .. 8192^2:
-        // 64 rows at 7680^2 and 8192^2, 16 at 4096^2, 4 at 2048^2)
-        t.seg_rows = 64;
-        Decomp d0;
-        while (t.seg_rows > 4 && decompose(H, W, t, &d0) && d0.units < 1536) t.seg_rows /= 2;
+        t.seg_rows = bwd_auto_seg(H, W, t);
         out->auto_seg = true;
     } else {
         out->auto_seg = false;
@@ -2063,37 +2086,25 @@ dwt_fuse_status dwt_fuse_backward_batched(dwt_fuse_ctx *ctx, const dwt_fuse_bwd_
         if (pfloats > 0 && (st = ensure_ws(ctx, dbyte + (size_t)pdoubles * sizeof(double)))) return st;
         double *dbase = pfloats > 0 ? reinterpret_cast<double *>(reinterpret_cast<char *>(ctx->ws) + dbyte) : nullptr;
         // Scenes on the default band-unrolled D4 plan run in one launch, so
-        // their units are lengthened together by the single-scene rule
-        // applied to the whole batch: the longest (<= 64 rows) that still
-        // give >= 1536 units over all of them, never shorter than a scene
-        // would take alone.  Gradients do not depend on the unit length
-        // (the gain products are kept per row), so every scene's results still
-        // equal its single call's bit for bit.
+        // their units are lengthened together: the single-scene rule
+        // (bwd_auto_seg) over all of them, never shorter than a scene would
+        // take alone.  Gradients do not depend on the unit length (the gain
+        // products are kept per row), so every scene's results still equal
+        // its single call's bit for bit.
         {
             std::vector<int64_t> joint;
+            std::vector<SegScene> hw;
             for (int64_t i = 0; i < n; ++i)
                 if (!is_staged[(size_t)i] && tiles[(size_t)i].auto_seg && tiles[(size_t)i].kind == 1 &&
                     tiles[(size_t)i].t.mode == 0) {
                     const BwdArgs a = bwd_item_args(items[i]);
-                    if (a.grad_pan || a.grad_ms || a.grad_gain) joint.push_back(i);
+                    if (a.grad_pan || a.grad_ms || a.grad_gain) {
+                        joint.push_back(i);
+                        hw.push_back(SegScene{a.H, a.W, tiles[(size_t)i].t});
+                    }
                 }
             if (joint.size() > 1) {
-                int seg = 64;
-                for (; seg > 4; seg /= 2) {
-                    int64_t total = 0;
-                    bool ok = true;
-                    for (const int64_t i : joint) {
-                        Tile t = tiles[(size_t)i].t;
-                        t.seg_rows = seg;
-                        Decomp d;
-                        if (!decompose(items[i].H, items[i].W, t, &d)) {
-                            ok = false;
-                            break;
-                        }
-                        total += d.units;
-                    }
-                    if (ok && total >= 1536) break;
-                }
+                const int seg = bwd_auto_seg(hw);
                 for (const int64_t i : joint) {
                     BwdTile &bt = tiles[(size_t)i];
                     if (seg <= bt.t.seg_rows) continue;
