@@ -322,9 +322,11 @@ def _same(a, b):
 
 
 # (wavelet, H, W, B, pad, offset, gain, need): every adjoint variant and load
-# path -- D4 with <= 4 bands (band loop unrolled), D4 and Haar with 9 bands
-# (two band groups, the second adding into grad_pan), 16-byte, 8-byte and
-# 4-byte rows, scenes without grad_gain or without any output.
+# path -- D4 and Haar with <= 4 bands (band loop unrolled), D4 from 5 bands on
+# 16- and 8-byte rows (the LDS-staged adjoint, a launch per scene), Haar with
+# 6 and 9 bands (groups of 4; two band groups, the second adding into
+# grad_pan), 16-byte, 8-byte and 4-byte rows, scenes without grad_gain or
+# without any output.
 BWD_BATCH = [("d4", 66, 516, 4, 0, 0, True, (True, True, True)),
              ("d4", 34, 70, 3, 0, 0, True, (True, True, True)),
              ("haar", 130, 258, 2, 0, 0, True, (True, True, True)),
@@ -335,7 +337,10 @@ BWD_BATCH = [("d4", 66, 516, 4, 0, 0, True, (True, True, True)),
              ("haar", 34, 134, 5, 1, 1, True, (True, True, True)),
              ("d4", 8, 8, 2, 0, 0, True, (False, False, False)),
              ("d4", 2, 4, 1, 0, 0, True, (True, True, True)),
-             ("d4", 66, 516, 4, 0, 0, False, (True, True, False))]
+             ("d4", 66, 516, 4, 0, 0, False, (True, True, False)),
+             ("d4", 66, 1030, 6, 0, 0, True, (True, True, True)),
+             ("d4", 34, 134, 9, 0, 0, True, (True, True, True)),
+             ("haar", 66, 1030, 6, 0, 0, True, (True, True, True))]
 
 
 def test_backward_batched_matches_single_calls(dev, fz, oracle):
