@@ -373,7 +373,9 @@ def make_bwd_items(scenes: Sequence[dict]):
 
 def fuse_backward_batched(scenes: Sequence[dict], device=None):
     """``fuse_backward`` of many independent scenes (dicts as in
-    ``make_bwd_items``) with one launch per adjoint kernel variant.  Returns
+    ``make_bwd_items``) with one launch per adjoint kernel variant (scenes on
+    the LDS-staged adjoint, D4 with 5 or more bands, a launch each); results
+    equal per-scene ``fuse_backward`` calls bit for bit.  Returns
     [(grad_pan, grad_ms, grad_gain)] per scene; entries not requested are
     None."""
     if len(scenes) == 0:
