@@ -138,6 +138,44 @@ def test_paths_and_pitches(dev, fz, oracle, wavelet, pad, offset, H, W):
 
 
 @pytest.mark.parametrize("wavelet", ["haar", "d4"])
+@pytest.mark.parametrize("H,W", [(8, 8), (34, 136), (66, 516), (34, 134), (130, 1288), (10, 1290)])
+@pytest.mark.parametrize("pad,off", [(8, 4), (6, 2), (5, 1)])
+def test_forward_writes_stay_inside(dev, fz, wavelet, H, W, pad, off):
+    """Every forward variant writes only its output: the output is a window
+    (rows 1..H, columns off..off+W-1) of a larger buffer whose other elements
+    hold a sentinel, with pitches and offsets that select the 128-bit, 64-bit
+    and scalar paths; the sentinels must survive every forced launch shape,
+    float and 8-bit output alike, and the window must match the plain call."""
+    rng = np.random.default_rng(H * W + pad)
+    B = 3
+    pan, ms = int_scene(rng, H, W, B)
+    p, m = to_dev(pan, dev), to_dev(ms, dev)
+    ref = fz.fuse(p, m, wavelet)
+    ref8 = fz.fuse(p.to(torch.uint8), m.to(torch.uint8), wavelet, out_dtype=torch.uint8)
+    sentinel = 12345.0
+    ctx = fz.context(dev)
+    try:
+        for seg, wpb, nc, var in [(0, 0, 0, 0), (16, 4, 2, 1), (3, 2, 1, 1), (1, 4, 2, 2), (2, 2, 1, 2),
+                                  (2, 4, 2, 3), (1, 2, 2, 3), (4, 1, 2, 3)]:
+            say(wavelet, "sentinel", H, W, pad, off, seg, wpb, nc, var)
+            ctx.force_tile(seg, wpb, nc, var)
+            big = torch.full((B, H + 2, W + pad), sentinel, device=dev)
+            out = big[:, 1:H + 1, off:off + W]
+            fz.fuse(p, m, wavelet, out=out)
+            inside = torch.zeros_like(big, dtype=torch.bool)
+            inside[:, 1:H + 1, off:off + W] = True
+            assert bool((big[~inside] == sentinel).all()), ("float output escaped its window", seg, wpb, nc, var)
+            assert torch.equal(out, ref), ("float window differs", seg, wpb, nc, var)
+            big8 = torch.full((B, H + 2, W + pad), 77, dtype=torch.uint8, device=dev)
+            out8 = big8[:, 1:H + 1, off:off + W]
+            fz.fuse(p.to(torch.uint8), m.to(torch.uint8), wavelet, out=out8, out_dtype=torch.uint8)
+            assert bool((big8[~inside] == 77).all()), ("8-bit output escaped its window", seg, wpb, nc, var)
+            assert torch.equal(out8, ref8), ("8-bit window differs", seg, wpb, nc, var)
+    finally:
+        ctx.force_tile(0, 0, 0, 0)
+
+
+@pytest.mark.parametrize("wavelet", ["haar", "d4"])
 @pytest.mark.parametrize("H,W", [(250, 1034), (250, 1288), (18, 8)])
 def test_tile_shapes_give_identical_results(dev, fz, wavelet, H, W):
     """Every output pixel is evaluated in the same order whatever unit holds
