@@ -141,8 +141,9 @@ struct AdjScene {
 // are unit_begin[i] .. unit_begin[i] + p.units - 1, total in all).  kind 0:
 // rolling, any wavelet, B <= adjoint_max_bands(); kind 1: rolling, any
 // wavelet, x = B <= 4 bands unrolled (no accumulate); kind 2: one-shot D4 tiles of
-// x = seg_rows (1 or 2) rows.  path: PATH_V4, PATH_V2 or PATH_SCALAR, the
-// same for every scene.  Results per scene equal the single-scene launch.
+// x = seg_rows (1 or 2) rows.  path: PATH_V4, PATH_V2W (two columns per lane
+// on 8-byte rows), PATH_V2 or PATH_SCALAR, the same for every scene.  Results
+// per scene equal the single-scene launch.
 hipError_t launch_adjoint_batched(const AdjScene *d_scenes, int nscenes, int total, int kind, int path, int x,
                                   const Filters &f, hipStream_t s);
 
@@ -163,7 +164,8 @@ hipError_t launch_gain_reduce_batched(const GainJob *d_jobs, int njobs, int tota
 // Bands one rolling adjoint launch handles (the host splits larger band counts).
 int adjoint_max_bands();
 
-// LDS-staged D4 adjoint (16-byte rows): units are strips of 128 coefficient
+// LDS-staged D4 adjoint (p.path PATH_V4: 16-byte rows; PATH_V2 or PATH_V2W:
+// 8-byte rows, staged with 4-byte loads): units are strips of 128 coefficient
 // columns x (kr * wpb) coefficient rows, one workgroup each; any band count.
 // all: the upstream gradients of a group of bands are staged together (one
 // barrier per group) instead of band after band into two alternating buffers.
