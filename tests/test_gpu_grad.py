@@ -228,6 +228,72 @@ def test_dot_product(dev, fz, wavelet):
     assert abs(lhs - rhs) <= 1e-5 * (abs(lhs) + abs(rhs)) + 1e-3
 
 
+def _adjoint_identities(fz, pan, ms, y, gain, wavelet, grads):
+    """At any size: <F(pan, ms), y> = <pan, grad_pan> + <ms, grad_ms> (the map
+    is linear in (pan, ms) at fixed gains), and grad_gain_b = <y_b, D_b> with
+    D_b = F(gain 1)_b - F(gain 0)_b = PAN - P PAN.  Sums in FP64.  The bounds
+    scale with the sums of absolute products: float32 rounding of each output
+    and gradient element is unbiased and independent, so the sums drift by
+    about sqrt(n) roundings, some 10^-11 of the scale here; 10^-8 (10^-7 for
+    grad_gain, summed in float32 along rows of 512 products) leaves a margin
+    of over 20x, while a wrong row of gradients would move the sums by an
+    estimated ~10^-6 of the scale."""
+    gp, gm, gg = grads
+    out = fz.fuse(pan, ms, wavelet, gain)
+    prod = out.double() * y.double()
+    lhs = prod.sum().item()
+    scale = prod.abs().sum().item()
+    del prod, out
+    rhs = (pan.double() * gp.double()).sum().item() + (ms.double() * gm.double()).sum().item()
+    assert abs(lhs - rhs) <= 1e-8 * scale + 1e-3, (lhs, rhs, scale)
+    B = y.shape[0]
+    one = torch.ones(B, device=pan.device)
+    d = fz.fuse(pan, ms, wavelet, one) - fz.fuse(pan, ms, wavelet, torch.zeros(B, device=pan.device))
+    for b in range(B):
+        prod = d[b].double() * y[b].double()
+        ref = prod.sum().item()
+        bound = 1e-7 * prod.abs().sum().item() + 1e-3
+        assert abs(float(gg[b]) - ref) <= bound, (b, float(gg[b]), ref, bound)
+    del d
+
+
+@pytest.mark.parametrize("H,W,B", [(8192, 8192, 3), (8192, 8190, 6)])
+def test_full_size_adjoint_identities(dev, fz, H, W, B):
+    """Full-size adjoint in the configuration the benchmark times (D4 8192^2
+    with 3 bands: band-unrolled rolling units; 8-byte rows with 6 bands: the
+    LDS-staged adjoint), checked through identities that hold at any size."""
+    from paper_1803_00737_amd import synth
+
+    say("full-size adjoint identities", H, W, B)
+    pan, ms = synth.make_scene(H, W, B, synth.seed_for(2, 0), device=dev)
+    y = torch.randn((B, H, W), device=dev, generator=torch.Generator(device=dev).manual_seed(5))
+    gain = torch.linspace(0.5, 1.5, B, device=dev)
+    grads = fz.fuse_backward(pan, y, "d4", gain)
+    _adjoint_identities(fz, pan, ms, y, gain, "d4", grads)
+    torch.cuda.empty_cache()
+
+
+def test_full_size_batched_adjoint_identities(dev, fz):
+    """The differentiation workload's adjoint (16 scenes of 2048^2 with 4
+    bands in one batched call, 64-row units) satisfies the same identities
+    scene by scene."""
+    from paper_1803_00737_amd import synth
+
+    H = W = 2048
+    B = 4
+    gain = torch.ones(B, device=dev)
+    scenes, inputs = [], []
+    for s in range(16):
+        pan, ms = synth.make_scene(H, W, B, synth.seed_for(4, s), device=dev)
+        y = torch.randn((B, H, W), device=dev, generator=torch.Generator(device=dev).manual_seed(100 + s))
+        scenes.append(dict(pan=pan, grad_out=y, wavelet="d4", gain=gain))
+        inputs.append((pan, ms, y))
+    say("full-size batched adjoint identities")
+    got = fz.fuse_backward_batched(scenes)
+    for (pan, ms, y), g in zip(inputs, got):
+        _adjoint_identities(fz, pan, ms, y, gain, "d4", g)
+
+
 @pytest.mark.parametrize("wavelet", ["d4", "haar"])
 def test_autograd_vs_fp64_finite_differences(dev, fz, oracle, wavelet):
     """MSE(fused, target) on a 32x32 crop (4 bands, gain initialised to 1):
