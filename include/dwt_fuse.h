@@ -187,8 +187,9 @@ dwt_fuse_status dwt_fuse_run_batched(dwt_fuse_ctx *ctx, const dwt_fuse_item *ite
  *   grad_gain NULL or B floats:              < y_b, PAN - P PAN >
  * where P is the projection of an image onto its LL part.  grad_gain is
  * reduced in a fixed order (bitwise reproducible, whatever the rows per work
- * unit).  D4 with 5 or more bands on 8-byte aligned rows runs the LDS-staged
- * adjoint (all bands in one launch), other cases the rolling adjoint.
+ * unit).  D4 on 8-byte aligned rows runs the LDS-staged adjoint (all bands
+ * in one launch) with 5 or more bands or when the scene is too small to
+ * fill the GPU with 4-row rolling units; other cases the rolling adjoint.
  * Outputs must not overlap inputs.  Uses context workspace (DWT_FUSE_E_NOMEM
  * if it cannot grow). */
 dwt_fuse_status dwt_fuse_backward(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet,
@@ -305,7 +306,9 @@ dwt_fuse_status dwt_fuse_tune_load(dwt_fuse_ctx *ctx, const char *path);
  * one-shot D4 adjoint tiles; variant 3 selects the LDS-staged D4 adjoint
  * (8-byte aligned rows, 1 or 2 rows per wavefront, up to 4 waves; columns 1
  * stages the upstream gradients band after band), which is otherwise the
- * untuned default for D4 with 5 or more bands on 8-byte aligned rows.
+ * untuned default for D4 on 8-byte aligned rows with 5 or more bands, and
+ * in dwt_fuse_backward for scenes too small to fill the GPU with 4-row
+ * rolling units.
  * DWT_FUSE_E_SHAPE if a field is out of range. */
 dwt_fuse_status dwt_fuse_force_tile(dwt_fuse_ctx *ctx, int seg_rows, int waves_per_block, int cols_per_lane,
                                     int variant);

@@ -1871,21 +1871,39 @@ struct StagedBwd {
     bool all = true;
 };
 
+static int64_t staged_strips(const BwdArgs &a) { return (a.W / 2 + 127) / 128; }
+
+// Fewer than 1536 rolling units even at 4 rows per unit (two columns per lane).
+static bool small_for_rolling(const BwdArgs &a, Path path) {
+    Tile t = rolling_tile(a.H, a.W, path_nc(path));
+    t.seg_rows = 4;
+    Decomp d;
+    return decompose(a.H, a.W, t, &d) && d.units < 1536;
+}
+
 // Whether a scene takes the staged adjoint: on request (forced variant 3,
-// with the forced rows and waves), or by default for D4 with 5 or more bands
-// and no tuned or forced shape, where it measured faster than the rolling
-// adjoint (whose band loop is unrolled only up to 4 bands): 2 rows x 4
-// wavefronts, every band staged.
-static bool staged_bwd(const dwt_fuse_ctx *ctx, const BwdArgs &a, Path path, StagedBwd *sb) {
+// with the forced rows and waves), or by default with no tuned or forced
+// shape: for D4 with 5 or more bands, where it measured faster than the
+// rolling adjoint (whose band loop is unrolled only up to 4 bands), 2 rows
+// x 4 wavefronts, every band staged; and, in a call of its own (`single`),
+// for a D4 scene too small to fill the GPU with 4-row rolling units
+// (< 1536 of them), 1 row x 4 wavefronts (1024^2: 10-25% faster).  A batch
+// keeps rolling units for the latter, its scenes filling the GPU together;
+// up to 8 bands both kernels give the same bits.
+static bool staged_bwd(const dwt_fuse_ctx *ctx, const BwdArgs &a, Path path, bool single, StagedBwd *sb) {
     if (a.wavelet != DWT_FUSE_D4 || path == PATH_SCALAR) return false;
     const Forced &fc = ctx->forced;
+    const bool dflt = fc.variant == 0 && fc.seg_rows == 0 && fc.wpb == 0 && fc.nc == 0 && it_bwd_default(ctx, a, path);
     if (fc.variant == 3) {
         sb->kr = fc.seg_rows == 2 ? 2 : 1;
         sb->wpb = fc.wpb >= 1 && fc.wpb <= 4 ? fc.wpb : 4;
         sb->all = fc.nc != 1;
-    } else if (fc.variant == 0 && fc.seg_rows == 0 && fc.wpb == 0 && fc.nc == 0 && a.B >= 5 &&
-               it_bwd_default(ctx, a, path)) {
+    } else if (dflt && a.B >= 5) {
         sb->kr = 2;
+        sb->wpb = 4;
+        sb->all = true;
+    } else if (dflt && single && small_for_rolling(a, path)) {
+        sb->kr = 1;
         sb->wpb = 4;
         sb->all = true;
     } else {
@@ -1893,8 +1911,6 @@ static bool staged_bwd(const dwt_fuse_ctx *ctx, const BwdArgs &a, Path path, Sta
     }
     return adjoint_staged_lds(sb->kr * sb->wpb, (int)a.B, sb->all) <= 65536;
 }
-
-static int64_t staged_strips(const BwdArgs &a) { return (a.W / 2 + 127) / 128; }
 
 // Launches the staged adjoint of one scene; gain slots go to `partial` (NULL:
 // no grad_gain).
@@ -1945,7 +1961,7 @@ dwt_fuse_status dwt_fuse_backward(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet, i
         if ((st = use_device(ctx))) return st;
         const Path path = choose_bwd_path(a);
         StagedBwd sb;
-        if (staged_bwd(ctx, a, path, &sb)) {
+        if (staged_bwd(ctx, a, path, true, &sb)) {
             const int64_t slots = gain_slots(H, staged_strips(a));
             if (slots > INT32_MAX - kGainChunk) return fail(ctx, DWT_FUSE_E_SHAPE, "too many gain partial slots");
             float *partial = nullptr;
@@ -2060,7 +2076,7 @@ dwt_fuse_status dwt_fuse_backward_batched(dwt_fuse_ctx *ctx, const dwt_fuse_bwd_
             const BwdArgs a = bwd_item_args(items[i]);
             if (!a.grad_pan && !a.grad_ms && !a.grad_gain) continue;
             const Path path = choose_bwd_path(a);
-            if (staged_bwd(ctx, a, path, &stg[(size_t)i])) {
+            if (staged_bwd(ctx, a, path, false, &stg[(size_t)i])) {
                 is_staged[(size_t)i] = 1;
                 nslots[(size_t)i] = gain_slots(a.H, staged_strips(a));
                 const int T = stg[(size_t)i].kr * stg[(size_t)i].wpb;
