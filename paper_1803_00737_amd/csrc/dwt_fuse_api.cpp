@@ -707,9 +707,12 @@ float time_fuse(dwt_fuse_ctx *c, const RunArgs &a, Path path, const Tile &t) {
 
 // Second pass over the fastest few shapes of a first pass: 7 timed runs of
 // each, interleaved across the shapes (clock or thermal drift during the
-// pass then affects them alike); the lowest median wins.  A single pass
-// over ~100 shapes with 3 runs each tends to keep whichever shape happened
-// to run fast, 5-10% off the best one on the 8192^2 workload.
+// pass then affects them alike), each run a burst of 4 back-to-back
+// launches (the steady state of repeated calls, where one launch's tail
+// overlaps the next one's start; isolated launches ranked a 1-row staged
+// shape first on the 8192^2 workload, 14% slower back to back than the
+// 2-row one); the lowest median wins.  A single pass over ~100 shapes with 3
+// runs each also tends to keep whichever shape happened to run fast.
 Tile confirm_fuse(dwt_fuse_ctx *c, const RunArgs &a, Path path, std::vector<std::pair<float, Tile>> &cands,
                   float *best_ms) {
     std::stable_sort(cands.begin(), cands.end(),
@@ -726,12 +729,16 @@ Tile confirm_fuse(dwt_fuse_ctx *c, const RunArgs &a, Path path, std::vector<std:
         (void)hipEventDestroy(e0);
         return cands[0].second;
     }
+    constexpr int BURST = 4;
     bool ok = true;
     for (int r = 0; ok && r < R; ++r)
-        for (size_t i = 0; ok && i < k; ++i)
-            ok = hipEventRecord(e0, c->stream) == hipSuccess && launch_tile(c, a, path, cands[i].second) == hipSuccess &&
-                 hipEventRecord(e1, c->stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+        for (size_t i = 0; ok && i < k; ++i) {
+            ok = hipEventRecord(e0, c->stream) == hipSuccess;
+            for (int q = 0; ok && q < BURST; ++q) ok = launch_tile(c, a, path, cands[i].second) == hipSuccess;
+            ok = ok && hipEventRecord(e1, c->stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
                  hipEventElapsedTime(&t[i * R + r], e0, e1) == hipSuccess;
+            t[i * R + r] /= BURST;
+        }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (!ok) return cands[0].second;
