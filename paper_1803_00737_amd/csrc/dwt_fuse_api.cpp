@@ -711,12 +711,13 @@ float time_fuse(dwt_fuse_ctx *c, const RunArgs &a, Path path, const Tile &t) {
 // launches (the steady state of repeated calls, where one launch's tail
 // overlaps the next one's start; isolated launches ranked a 1-row staged
 // shape first on the 8192^2 workload, 14% slower back to back than the
-// 2-row one); the lowest median wins.  A single pass over ~100 shapes with 3
-// runs each also tends to keep whichever shape happened to run fast.
-Tile confirm_fuse(dwt_fuse_ctx *c, const RunArgs &a, Path path, std::vector<std::pair<float, Tile>> &cands,
-                  float *best_ms) {
+// 2-row one); the lowest median wins, near-ties going to the smallest
+// tie_key.  A single pass over ~100 shapes with 3 runs each also tends to
+// keep whichever shape happened to run fast.
+template <class T, class L, class K>
+T confirm_best(hipStream_t stream, std::vector<std::pair<float, T>> &cands, L launch, K tie_key, float *best_ms) {
     std::stable_sort(cands.begin(), cands.end(),
-                     [](const std::pair<float, Tile> &x, const std::pair<float, Tile> &y) { return x.first < y.first; });
+                     [](const std::pair<float, T> &x, const std::pair<float, T> &y) { return x.first < y.first; });
     size_t k = 0;
     while (k < cands.size() && k < 4 && cands[k].first < 1e29f) ++k;
     *best_ms = cands[0].first;
@@ -733,26 +734,29 @@ Tile confirm_fuse(dwt_fuse_ctx *c, const RunArgs &a, Path path, std::vector<std:
     bool ok = true;
     for (int r = 0; ok && r < R; ++r)
         for (size_t i = 0; ok && i < k; ++i) {
-            ok = hipEventRecord(e0, c->stream) == hipSuccess;
-            for (int q = 0; ok && q < BURST; ++q) ok = launch_tile(c, a, path, cands[i].second) == hipSuccess;
-            ok = ok && hipEventRecord(e1, c->stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+            ok = hipEventRecord(e0, stream) == hipSuccess;
+            for (int q = 0; ok && q < BURST; ++q) ok = launch(cands[i].second) == hipSuccess;
+            ok = ok && hipEventRecord(e1, stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
                  hipEventElapsedTime(&t[i * R + r], e0, e1) == hipSuccess;
             t[i * R + r] /= BURST;
         }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (!ok) return cands[0].second;
-    size_t best = 0;
+    std::vector<float> med(k);
     float bm = 1e30f;
     for (size_t i = 0; i < k; ++i) {
         std::sort(t.begin() + i * R, t.begin() + (i + 1) * R);
-        const float m = t[i * R + R / 2];
-        if (m < bm) {
-            bm = m;
-            best = i;
-        }
+        med[i] = t[i * R + R / 2];
+        bm = std::min(bm, med[i]);
     }
-    *best_ms = bm;
+    // Shapes within 1% of the best burst median are taken as equal; of those
+    // the one with the smallest tie_key wins (first-pass order among equal
+    // keys), so that repeated tuning settles on the same shape.
+    size_t best = k;
+    for (size_t i = 0; i < k; ++i)
+        if (med[i] <= 1.01f * bm && (best == k || tie_key(cands[i].second) < tie_key(cands[best].second))) best = i;
+    *best_ms = med[best];
     return cands[best].second;
 }
 
@@ -802,7 +806,14 @@ Tile tune_fuse(dwt_fuse_ctx *c, const RunArgs &a, Path path) {
         }
     }
     float bestms = 0.f;
-    const Tile bestt = confirm_fuse(c, a, path, cands, &bestms);
+    // near-ties: fewest work units (larger tiles re-read fewer halo rows and
+    // stay ahead when launches do not overlap, e.g. one call at a time)
+    auto units = [&](const Tile &t) {
+        Decomp d;
+        return decompose(a.H, a.W, t, &d) ? (int64_t)d.units : INT64_MAX;
+    };
+    const Tile bestt =
+        confirm_best(c->stream, cands, [&](const Tile &t) { return launch_tile(c, a, path, t); }, units, &bestms);
     if (std::getenv("DWT_FUSE_LOG"))
         std::fprintf(stderr, "[dwt_fuse] tuned %s: mode=%d seg_rows=%d wpb=%d nc=%d order=%d split=%d (%.3f ms)\n",
                      tune_key(0, a.wavelet, a.H, a.W, a.B, path).c_str(), bestt.mode, bestt.seg_rows, bestt.wpb,
@@ -1398,7 +1409,8 @@ CodecShape codec_shape(dwt_fuse_ctx *c, const ExArgs &a) {
         t.wpb = it->second.wpb;
         t.order = it->second.order;
     } else if (c->tuning && t.aligned) {
-        float bestms = time_codec(c, a, t);
+        std::vector<std::pair<float, CodecShape>> cands;
+        cands.emplace_back(time_codec(c, a, t), t);
         // one-shot tiles of 1 or 2 rows (rolling D4 units, forced variant 1,
         // measured slower on every 8-bit workload, so they are not candidates)
         const int rows_cand[2] = {-1, -2};  // negative: one-shot of that many rows
@@ -1414,11 +1426,7 @@ CodecShape codec_shape(dwt_fuse_ctx *c, const ExArgs &a) {
                         s.rows = rc < 0 ? -rc : rc;
                         s.wpb = wpb;
                         s.order = order;
-                        const float ms = time_codec(c, a, s);
-                        if (ms < bestms) {
-                            bestms = ms;
-                            t = s;
-                        }
+                        cands.emplace_back(time_codec(c, a, s), s);
                     }
             }
         }
@@ -1434,13 +1442,13 @@ CodecShape codec_shape(dwt_fuse_ctx *c, const ExArgs &a) {
                         s.rows = (kr - 2) * wpb;
                         s.order = order;
                         codec_set_aligned(a, &s);
-                        const float ms = time_codec(c, a, s);
-                        if (ms < bestms) {
-                            bestms = ms;
-                            t = s;
-                        }
+                        cands.emplace_back(time_codec(c, a, s), s);
                     }
         }
+        float bestms = 0.f;
+        t = confirm_best(
+            c->stream, cands, [&](const CodecShape &s) { return launch_codec_shape(c, a, s); },
+            [](const CodecShape &) { return 0; }, &bestms);
         Tile rec;
         rec.nc = t.nc;
         rec.seg_rows = t.rows;
