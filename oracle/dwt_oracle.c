@@ -3,7 +3,7 @@
  * pan-sharpening (Al-Oraiqat et al., section 2, Eq. 1-16).
  *
  * TEST INFRASTRUCTURE ONLY: used by the tests, the smoke check and the
- * benchmark's CPU-baseline leg to judge the GPU path.  It shares no code,
+ * benchmark's CPU-baseline leg, to check and time the GPU path against.  It shares no code,
  * header or constant with the GPU library.
  *
  * Structure: each printed equation is written once, as a "taps" function
