@@ -389,6 +389,33 @@ def extras(torch, api, synth, steps, warmup):
     log("multipass", out["paper_multipass_" + wl.name])
     del pan, ms, o
     torch.cuda.empty_cache()
+    # Adjoint alone at the primary shape (D4 8192^2, 3 bands): gradients
+    # w.r.t. PAN, MS and the 3 gains from one upstream gradient, one
+    # pre-marshalled dwt_fuse_backward call per step; algorithmic bytes
+    # H*W*(8 + 5B) (PAN and B upstream gradients read, grad_pan and B
+    # quarter-size grad_ms written).
+    wl = synth.d4_8192()
+    pan, _ = wl.make(device=dev)
+    H, W, B = wl.H, wl.W, wl.B
+    gy = torch.randn((B, H, W), device=dev, generator=torch.Generator(device=dev).manual_seed(3))
+    gain = torch.ones(B, device=dev)
+    gp = torch.empty((H, W), device=dev)
+    gm = torch.empty((B, H // 2, W // 2), device=dev)
+    gg = torch.empty(B, device=dev)
+    actx = api.context(dev)
+    actx.bind_stream()
+    alib = actx.lib
+    bargs = (actx.handle, 1, H, W, B, ctypes.c_void_p(pan.data_ptr()), W, ctypes.c_void_p(gain.data_ptr()),
+             ctypes.c_void_p(gy.data_ptr()), W, H * W, ctypes.c_void_p(gp.data_ptr()),
+             ctypes.c_void_p(gm.data_ptr()), ctypes.c_void_p(gg.data_ptr()))
+    ms_t = time_loop(torch, lambda: actx.check(alib.dwt_fuse_backward(*bargs), "dwt_fuse_backward"),
+                     max(5, steps // 2), warmup)
+    gbs = H * W * (8 + 5 * B) / (ms_t * 1e-3) / 1e9
+    out["adjoint_d4_8192x8192_b3"] = {"ms": ms_t, "GB/s": gbs, "frac": gbs / HBM_PEAK_GBS}
+    log("adjoint_d4_8192x8192_b3", out["adjoint_d4_8192x8192_b3"])
+    del pan, gy, gp, gm, gg, bargs
+    torch.cuda.empty_cache()
+
     # Differentiation: 16 x 2048^2, 4 bands, D4: fused forward + adjoint
     # (gradients w.r.t. PAN, MS and the 4 gains) of every scene, as
     # pre-marshalled C-ABI calls (the Python autograd wrapper adds host time).
