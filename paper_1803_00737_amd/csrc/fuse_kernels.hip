@@ -458,18 +458,25 @@ __device__ __forceinline__ void d4_staged_tile(const FuseParams &p, const Filter
     float *Ml = lds + (2 * T + 4) * kStagedPanRow;
 
     // PAN rows 2r0-2 .. 2r0+2T+1.  On the 16-byte path column groups of 4
-    // start at multiples of 4 and W % 4 == 0, so a group never straddles the
-    // wrap; the other paths stage single floats, except that on 8-byte rows
+    // start at multiples of 4; a group straddles the wrap only when
+    // W % 4 == 2 (16-byte rows with a pitch padded past an odd W/2), and only
+    // in a strip that reaches the right border, which then stages single
+    // floats (the group holding pixels W-2, W-1 would otherwise take the row
+    // padding where Eq. 5-6 put pixels 0, 1, and its wrapped successors would
+    // start 8 bytes off a 16-byte boundary).  The other paths stage single
+    // floats, except that on 8-byte rows
     // (LAY 3) strips clear of the wrap stage 16-byte groups starting at pixel
     // 2sb (rows 16-byte aligned there) or 2sb-2 (rows 8 bytes off), the
     // latter placed 2 floats further right in LDS (row shift, see pan_shift).
     // 8-byte rows: a strip whose groups of 4 pixels from 2sb-2 to 2sb+257 all
     // lie inside the row.
     const bool fast = LAY == 3 && sb >= 128 && 2 * sb + 258 <= p.W;
+    // 16-byte rows: every group of the strip is 16-byte aligned in the row.
+    const bool groups16 = LAY == 0 && ((p.W & 3) == 0 || 2 * sb + 256 <= p.W);
     for (int k = w; k < 2 * T + 4; k += wpb) {
         const float *row = p.pan + (int64_t)wrap_idx(2 * r0 - 2 + k, p.H) * p.pan_ld;
         float *dst = Pl + k * kStagedPanRow;
-        if constexpr (LAY == 0) {
+        if (LAY == 0 && groups16) {
             lds_load16(row + wrap_idx(2 * sb + 4 * lane, p.W), dst + 4);
         } else if (LAY == 3 && fast && (reinterpret_cast<uintptr_t>(row) & 15) != 0) {
             // groups from pixel 2sb-2: LDS 4 + 4l holds pixels 2sb-2+4l .. +3

@@ -238,6 +238,93 @@ def test_tile_shapes_on_8_byte_rows(dev, fz, oracle, wavelet, H, W, ms_pad, ms_o
         assert np.abs(base - oracle_out(oracle, "d4", pan, ms)).max() <= D4_TOL
 
 
+def padded(a: np.ndarray, dev, pitch: int):
+    """Device view of ``a`` inside a NaN-filled buffer whose rows have
+    ``pitch`` floats (the first row at the start of the allocation).
+    Returns (view, buffer)."""
+    buf = torch.full(a.shape[:-1] + (pitch,), float("nan"), dtype=torch.float32, device=dev)
+    v = buf[..., :a.shape[-1]]
+    v.copy_(torch.from_numpy(np.ascontiguousarray(a)).to(dev))
+    return v, buf
+
+
+W2MOD4_SHAPES = [(2, 2), (34, 70), (66, 1030), (64, 4070)]
+W2MOD4_TILES = [(0, 0, 0, 0), (16, 4, 2, 1), (1, 4, 2, 2), (2, 1, 2, 2), (2, 4, 2, 3), (1, 2, 2, 3),
+                (4, 1, 2, 3), (4, 4, 2, 3)]
+
+
+@pytest.mark.parametrize("wavelet", ["haar", "d4"])
+@pytest.mark.parametrize("H,W", W2MOD4_SHAPES)
+def test_16_byte_rows_with_w_2_mod_4(dev, fz, oracle, wavelet, H, W):
+    """W = 2 (mod 4) with PAN and output rows padded to a multiple of 4
+    floats and MS rows to an even pitch: every row is 16-byte aligned, so the
+    128-bit path runs although W/2 is odd.  The last coefficient column's D4
+    row filter wraps to pixels 0, 1 (Eq. 5-6) where the row padding (NaN
+    here) follows pixel W-1 in memory.  Every forced shape (rolling, one-shot,
+    LDS-staged) must match the oracle, equal the contiguous call bit for bit,
+    and leave the output padding untouched."""
+    B = 3
+    rng = np.random.default_rng(H * 7 + W)
+    pan, ms = int_scene(rng, H, W, B)
+    base = fz.fuse(to_dev(pan, dev), to_dev(ms, dev), wavelet).cpu().numpy()
+    ref = oracle_out(oracle, wavelet, pan, ms)
+    pitch = W + 2
+    pv, _ = padded(pan, dev, pitch)
+    mv, _ = padded(ms, dev, W // 2 + 1)
+    ctx = fz.context(dev)
+    try:
+        for seg, wpb, nc, var in W2MOD4_TILES:
+            say(wavelet, "16-byte rows, W = 2 mod 4", H, W, "tile", seg, wpb, nc, var)
+            ctx.force_tile(seg, wpb, nc, var)
+            ov, obuf = padded(np.zeros((B, H, W), np.float32), dev, pitch)
+            fz.fuse(pv, mv, wavelet, out=ov)
+            got = ov.cpu().numpy()
+            assert bool(torch.isnan(obuf[..., W:]).all()), ("output padding written", seg, wpb, nc, var)
+            if wavelet == "haar":
+                assert np.array_equal(got, ref.astype(np.float32)), (seg, wpb, nc, var)
+            else:
+                assert np.abs(got - ref).max() <= D4_TOL, (seg, wpb, nc, var)
+            assert np.array_equal(got, base), (seg, wpb, nc, var)
+    finally:
+        ctx.force_tile(0, 0, 0, 0)
+
+
+@pytest.mark.parametrize("variant", [0, 3])
+def test_16_byte_rows_with_w_2_mod_4_batched(dev, fz, oracle, variant):
+    """The same padded layouts as one batch (default form and the forced flat
+    grid, whose D4 scenes on 16-byte rows run the LDS-staged tile): each
+    output equals its contiguous per-image call bit for bit and the oracle."""
+    rng = np.random.default_rng(31 + variant)
+    scenes, host, bufs = [], [], []
+    for i, (H, W) in enumerate(W2MOD4_SHAPES * 2):
+        w = "d4" if i < len(W2MOD4_SHAPES) else "haar"
+        B = 3 + i % 3
+        pan, ms = int_scene(rng, H, W, B)
+        pv, _ = padded(pan, dev, W + 2)
+        mv, _ = padded(ms, dev, W // 2 + 1)
+        ov, obuf = padded(np.zeros((B, H, W), np.float32), dev, W + 2)
+        scenes.append(dict(pan=pv, ms=mv, out=ov, wavelet=w))
+        host.append((w, pan, ms))
+        bufs.append(obuf)
+    ctx = fz.context(dev)
+    say("16-byte rows, W = 2 mod 4, batched variant", variant)
+    try:
+        ctx.force_tile(0, 0, 0, variant)
+        outs = fz.fuse_batched(scenes)
+    finally:
+        ctx.force_tile(0, 0, 0, 0)
+    for o, obuf, (w, pan, ms) in zip(outs, bufs, host):
+        W = pan.shape[1]
+        assert bool(torch.isnan(obuf[..., W:]).all())
+        got = o.cpu().numpy()
+        assert np.array_equal(got, fz.fuse(to_dev(pan, dev), to_dev(ms, dev), w).cpu().numpy())
+        ref = oracle_out(oracle, w, pan, ms)
+        if w == "haar":
+            assert np.array_equal(got, ref.astype(np.float32))
+        else:
+            assert np.abs(got - ref).max() <= D4_TOL
+
+
 @pytest.mark.parametrize("wavelet", ["haar", "d4"])
 def test_cyclic_shift_equivariance(dev, fz, wavelet):
     """Shifting PAN by (2r, 2c) and MS by (r, c) shifts the output by (2r, 2c):
