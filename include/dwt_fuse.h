@@ -198,6 +198,33 @@ dwt_fuse_status dwt_fuse_backward(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet,
                                   const float *grad_out, int64_t go_ld, int64_t go_band_stride,
                                   float *grad_pan, float *grad_ms, float *grad_gain);
 
+/* Size of the static device scratch used by dwt_fuse_backward_noalloc, per GPU. */
+#define DWT_FUSE_STATIC_SCRATCH_BYTES (16u * 1024u * 1024u)
+
+/* dwt_fuse_backward for callers that cannot allocate device memory: code
+ * under hipGraph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, validation and kernels as dwt_fuse_backward
+ * on the same context, so the same results bit for bit; it calls no
+ * hipMalloc, hipFree or other allocating routine.  The only scratch it needs,
+ * the grad_gain reduction's partial sums, lives in a static device array of
+ * DWT_FUSE_STATIC_SCRATCH_BYTES that every GPU the library runs on holds
+ * from the library's load until the process ends (its address is looked up
+ * once per device in dwt_fuse_create).  That is
+ *   4 * B * (H/2) * S  bytes (rounded up to 256) + 8 * B * ceil((H/2) * S / 2048)
+ * with S = ceil((W/2) / 128) column strips, or ceil((W/2) / 64) where the
+ * adjoint runs one column per lane (pointers or pitches not 8-byte aligned,
+ * or such a shape forced), e.g. 10.7 MB for 15872 x 14336 with 6 bands; a call needing more returns DWT_FUSE_E_SHAPE before launching
+ * anything.  Without grad_gain no scratch is used.  Every call on one GPU
+ * shares that GPU's array (each call overwrites every slot it reads, so
+ * nothing needs clearing): calls that may overlap in time on one GPU (other
+ * streams, contexts or threads) race on it and must be ordered by the
+ * caller. */
+dwt_fuse_status dwt_fuse_backward_noalloc(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet,
+                                          int64_t H, int64_t W, int64_t B,
+                                          const float *pan, int64_t pan_ld, const float *gain,
+                                          const float *grad_out, int64_t go_ld, int64_t go_band_stride,
+                                          float *grad_pan, float *grad_ms, float *grad_gain);
+
 /* One scene of a batched backward; fields as in dwt_fuse_backward (grad_pan
  * H x W and grad_ms B x H/2 x W/2 contiguous; each output may be NULL). */
 typedef struct {

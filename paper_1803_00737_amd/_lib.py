@@ -23,6 +23,7 @@ EXPORTS = (
     "dwt_fuse_tune_save", "dwt_fuse_tune_load", "dwt_fuse_force_tile", "dwt_fuse_run_multipass",
     "dwt_fuse_run_ex", "dwt_fuse_check_run_ex", "dwt_fuse_quality", "dwt_fuse_check_quality",
     "dwt_fuse_force_band_split", "dwt_fuse_backward_batched", "dwt_fuse_check_backward_batched",
+    "dwt_fuse_backward_noalloc",
 )
 
 HAAR = 0
@@ -109,6 +110,8 @@ def load(require_torch: bool = True):
         bwd_args = [i32, i64, i64, i64, vp, i64, vp, vp, i64, i64, vp, vp, vp]
         lib.dwt_fuse_backward.argtypes = [vp] + bwd_args
         lib.dwt_fuse_backward.restype = st
+        lib.dwt_fuse_backward_noalloc.argtypes = [vp] + bwd_args
+        lib.dwt_fuse_backward_noalloc.restype = st
         lib.dwt_fuse_check_backward.argtypes = bwd_args
         lib.dwt_fuse_check_backward.restype = st
         lib.dwt_fuse_backward_batched.argtypes = [vp, ctypes.POINTER(BwdItem), i64]

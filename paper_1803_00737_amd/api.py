@@ -337,6 +337,44 @@ def fuse_backward(pan: torch.Tensor, grad_out: torch.Tensor, wavelet="d4", gain:
     return gp, gm, gg
 
 
+def fuse_backward_noalloc(pan: torch.Tensor, grad_out: torch.Tensor, grad_pan: Optional[torch.Tensor],
+                          grad_ms: Optional[torch.Tensor], grad_gain: Optional[torch.Tensor], wavelet="d4",
+                          gain: Optional[torch.Tensor] = None):
+    """``fuse_backward`` into caller-provided outputs through
+    dwt_fuse_backward_noalloc: neither this call nor the library allocates
+    device memory (the grad_gain reduction uses the library's static scratch,
+    so calls overlapping on one GPU race).  pan (H, W) and grad_out (B, H, W)
+    need unit stride along rows; grad_pan (H, W), grad_ms (B, H/2, W/2) and
+    grad_gain (B,) must be contiguous float32 on the same GPU, or None."""
+    _require(pan, "pan", 2)
+    _require(grad_out, "grad_out", 3)
+    for t, name in ((pan, "pan"), (grad_out, "grad_out")):
+        if t.stride(-1) != 1 or any(s < 0 for s in t.stride()):
+            raise ValueError("%s needs unit stride along its rows (no copy is made)" % name)
+    H, W = pan.shape
+    B = grad_out.shape[0]
+    if tuple(grad_out.shape[1:]) != (H, W):
+        raise ValueError("grad_out must be (B, H, W)")
+    for t, name, shape in ((grad_pan, "grad_pan", (H, W)), (grad_ms, "grad_ms", (B, H // 2, W // 2)),
+                           (grad_gain, "grad_gain", (B,)), (gain, "gain", (B,))):
+        if t is None:
+            continue
+        _require(t, name, len(shape))
+        if tuple(t.shape) != shape or not t.is_contiguous():
+            raise ValueError("%s must be a contiguous %s tensor" % (name, shape))
+        if t.device != pan.device:
+            raise ValueError("%s must be on the device of pan" % name)
+    if grad_out.device != pan.device:
+        raise ValueError("pan and grad_out must be on the same device")
+    c = context(pan.device)
+    c.bind_stream()
+    st = c.lib.dwt_fuse_backward_noalloc(c.handle, wavelet_id(wavelet), H, W, B, _ptr(pan), _pitch(pan, 0),
+                                         _ptr(gain), _ptr(grad_out), _pitch(grad_out, 1), _pitch(grad_out, 0),
+                                         _ptr(grad_pan), _ptr(grad_ms), _ptr(grad_gain))
+    c.check(st, "dwt_fuse_backward_noalloc")
+    return grad_pan, grad_ms, grad_gain
+
+
 def make_bwd_items(scenes: Sequence[dict]):
     """Prepare dwt_fuse_bwd_item descriptors; each scene is a dict with keys
     pan, grad_out, wavelet and optionally gain, need_pan, need_ms, need_gain

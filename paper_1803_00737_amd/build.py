@@ -20,7 +20,7 @@ BUILD_DIR = os.path.join(ROOT, "_build")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 SOURCES = ["dwt_fuse_api.cpp", "fuse_kernels.hip", "adjoint_kernels.hip", "multipass_kernels.hip", "codec_kernels.hip",
-           "quality_kernels.hip"]
+           "quality_kernels.hip", "static_scratch.hip"]
 HEADERS = [os.path.join(CSRC, "fuse_internal.h"), os.path.join(CSRC, "fuse_math.h"), os.path.join(INCLUDE, "dwt_fuse.h")]
 
 # -packed-fp32-ops: keep the compiler from forming packed FP32 arithmetic.

@@ -27,6 +27,8 @@
 
 using namespace dwtf;
 
+static_assert(DWT_FUSE_STATIC_SCRATCH_BYTES == kStaticScratchBytes, "header and library disagree on the static scratch size");
+
 namespace {
 
 // ---------------------------------------------------------------- validation
@@ -562,6 +564,10 @@ struct dwt_fuse_ctx {
     hipEvent_t bwd_staged = nullptr;  // last upload of h_bwd finished
     bool bwd_pending = false;
     hipEvent_t switched = nullptr;  // recorded on the old stream by dwt_fuse_set_stream
+    // the device's static scratch (dwt_fuse_backward_noalloc); NULL if the
+    // lookup at creation failed (scratch_err says why)
+    void *scratch = nullptr;
+    std::string scratch_err;
 };
 
 namespace {
@@ -1102,6 +1108,12 @@ dwt_fuse_status dwt_fuse_create(dwt_fuse_ctx **ctx, int device, void *hip_stream
         c->filt = make_filters();
         c->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
         c->device_name = prop.gcnArchName;
+        // once per device (cached), with the device current: the static
+        // scratch's device address for the entry points that allocate nothing
+        if (const hipError_t e = static_scratch_address(device, &c->scratch)) {
+            c->scratch = nullptr;
+            c->scratch_err = std::string("hipGetSymbolAddress of the static scratch failed: ") + hipGetErrorString(e);
+        }
         if (const char *f = std::getenv("DWT_FUSE_FORCE_TILE")) {
             int a = 0, b = 0, d = 0, v = 0;
             if (std::sscanf(f, "%d,%d,%d,%d", &a, &b, &d, &v) >= 1 && a >= 0 && a <= 4096 && b >= 0 && b <= 4 &&
@@ -1961,6 +1973,74 @@ static dwt_fuse_status run_staged_bwd(dwt_fuse_ctx *ctx, const BwdArgs &a, Path 
     return DWT_FUSE_OK;
 }
 
+// Gain-reduction workspace of one backward call (slots' partial sums, then
+// the chunk sums): context workspace, grown on demand, or with `noalloc` the
+// device's static scratch, checked against its size (nothing is launched if
+// it does not fit).
+static dwt_fuse_status gain_workspace(dwt_fuse_ctx *ctx, bool noalloc, int64_t slots, int64_t B, float **partial,
+                                      double **chunks) {
+    const size_t bytes = gain_ws_bytes(slots, B);
+    char *base = nullptr;
+    if (noalloc) {
+        if (!ctx->scratch) return fail(ctx, DWT_FUSE_E_DEVICE, ctx->scratch_err);
+        if (bytes > kStaticScratchBytes)
+            return fail(ctx, DWT_FUSE_E_SHAPE,
+                        "grad_gain of this scene needs " + std::to_string(bytes) +
+                            " bytes of scratch, more than the static scratch's " +
+                            std::to_string(kStaticScratchBytes) + " (use dwt_fuse_backward)");
+        base = static_cast<char *>(ctx->scratch);
+    } else {
+        if (const dwt_fuse_status st = ensure_ws(ctx, bytes)) return st;
+        base = reinterpret_cast<char *>(ctx->ws);
+    }
+    *partial = reinterpret_cast<float *>(base);
+    *chunks = reinterpret_cast<double *>(base + gain_ws_chunk_off(slots, B));
+    return DWT_FUSE_OK;
+}
+
+static dwt_fuse_status backward_impl(dwt_fuse_ctx *ctx, const BwdArgs &a, bool noalloc) {
+    const int64_t H = a.H, B = a.B;
+    std::string err;
+    dwt_fuse_status st = check_bwd_args(a, &err);
+    if (st) return fail(ctx, st, err);
+    if (!a.grad_pan && !a.grad_ms && !a.grad_gain) return DWT_FUSE_OK;
+    if ((st = use_device(ctx))) return st;
+    const Path path = choose_bwd_path(a);
+    StagedBwd sb;
+    if (staged_bwd(ctx, a, path, true, &sb)) {
+        const int64_t slots = gain_slots(H, staged_strips(a));
+        if (slots > INT32_MAX - kGainChunk) return fail(ctx, DWT_FUSE_E_SHAPE, "too many gain partial slots");
+        float *partial = nullptr;
+        double *chunks = nullptr;
+        if (a.grad_gain && (st = gain_workspace(ctx, noalloc, slots, B, &partial, &chunks))) return st;
+        if ((st = run_staged_bwd(ctx, a, path, sb, partial))) return st;
+        if (a.grad_gain) {
+            const hipError_t e = launch_gain_reduce(partial, (int)slots, (int)B, chunks, const_cast<float *>(a.grad_gain), ctx->stream);
+            if (e != hipSuccess) return hip_fail(ctx, e, "gain reduction launch");
+        }
+        return DWT_FUSE_OK;
+    }
+    BwdTile bt;
+    if (!plan_bwd(ctx, a, path, &bt)) return fail(ctx, DWT_FUSE_E_SHAPE, "too many work units");
+    const int64_t slots = gain_slots(H, bt.d.nstrips);
+    float *partial = nullptr;
+    double *chunks = nullptr;
+    if (a.grad_gain && (st = gain_workspace(ctx, noalloc, slots, B, &partial, &chunks))) return st;
+    const int maxb = adjoint_max_bands();
+    for (int64_t b0 = 0; b0 < B; b0 += maxb) {
+        const AdjParams p = bwd_params(a, bt, partial, b0);
+        const hipError_t e = bt.kind == 2   ? launch_adjoint_tile(p, ctx->filt, bt.x, bt.t.wpb, ctx->stream)
+                             : bt.kind == 1 ? launch_adjoint_bg(p, ctx->filt, bt.t.wpb, ctx->stream)
+                                            : launch_adjoint(p, ctx->filt, bt.t.wpb, ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "adjoint launch");
+    }
+    if (a.grad_gain) {
+        const hipError_t e = launch_gain_reduce(partial, (int)slots, (int)B, chunks, const_cast<float *>(a.grad_gain), ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "gain reduction launch");
+    }
+    return DWT_FUSE_OK;
+}
+
 dwt_fuse_status dwt_fuse_backward(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet, int64_t H, int64_t W, int64_t B,
                                   const float *pan, int64_t pan_ld, const float *gain, const float *grad_out,
                                   int64_t go_ld, int64_t go_band_stride, float *grad_pan, float *grad_ms,
@@ -1969,53 +2049,23 @@ dwt_fuse_status dwt_fuse_backward(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet, i
     try {
         const BwdArgs a{(int)wavelet, H, W, B, pan, pan_ld, gain, grad_out, go_ld, go_band_stride,
                         grad_pan, grad_ms, grad_gain};
-        std::string err;
-        dwt_fuse_status st = check_bwd_args(a, &err);
-        if (st) return fail(ctx, st, err);
-        if (!grad_pan && !grad_ms && !grad_gain) return DWT_FUSE_OK;
-        if ((st = use_device(ctx))) return st;
-        const Path path = choose_bwd_path(a);
-        StagedBwd sb;
-        if (staged_bwd(ctx, a, path, true, &sb)) {
-            const int64_t slots = gain_slots(H, staged_strips(a));
-            if (slots > INT32_MAX - kGainChunk) return fail(ctx, DWT_FUSE_E_SHAPE, "too many gain partial slots");
-            float *partial = nullptr;
-            double *chunks = nullptr;
-            if (grad_gain) {
-                if ((st = ensure_ws(ctx, gain_ws_bytes(slots, B)))) return st;
-                partial = ctx->ws;
-                chunks = reinterpret_cast<double *>(reinterpret_cast<char *>(ctx->ws) + gain_ws_chunk_off(slots, B));
-            }
-            if ((st = run_staged_bwd(ctx, a, path, sb, partial))) return st;
-            if (grad_gain) {
-                const hipError_t e = launch_gain_reduce(partial, (int)slots, (int)B, chunks, grad_gain, ctx->stream);
-                if (e != hipSuccess) return hip_fail(ctx, e, "gain reduction launch");
-            }
-            return DWT_FUSE_OK;
-        }
-        BwdTile bt;
-        if (!plan_bwd(ctx, a, path, &bt)) return fail(ctx, DWT_FUSE_E_SHAPE, "too many work units");
-        const int64_t slots = gain_slots(H, bt.d.nstrips);
-        float *partial = nullptr;
-        double *chunks = nullptr;
-        if (grad_gain) {
-            if ((st = ensure_ws(ctx, gain_ws_bytes(slots, B)))) return st;
-            partial = ctx->ws;
-            chunks = reinterpret_cast<double *>(reinterpret_cast<char *>(ctx->ws) + gain_ws_chunk_off(slots, B));
-        }
-        const int maxb = adjoint_max_bands();
-        for (int64_t b0 = 0; b0 < B; b0 += maxb) {
-            const AdjParams p = bwd_params(a, bt, partial, b0);
-            const hipError_t e = bt.kind == 2   ? launch_adjoint_tile(p, ctx->filt, bt.x, bt.t.wpb, ctx->stream)
-                                 : bt.kind == 1 ? launch_adjoint_bg(p, ctx->filt, bt.t.wpb, ctx->stream)
-                                                : launch_adjoint(p, ctx->filt, bt.t.wpb, ctx->stream);
-            if (e != hipSuccess) return hip_fail(ctx, e, "adjoint launch");
-        }
-        if (grad_gain) {
-            const hipError_t e = launch_gain_reduce(partial, (int)slots, (int)B, chunks, grad_gain, ctx->stream);
-            if (e != hipSuccess) return hip_fail(ctx, e, "gain reduction launch");
-        }
-        return DWT_FUSE_OK;
+        return backward_impl(ctx, a, false);
+    } catch (const std::bad_alloc &) {
+        return fail(ctx, DWT_FUSE_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(ctx, DWT_FUSE_E_STATE, "unexpected exception");
+    }
+}
+
+dwt_fuse_status dwt_fuse_backward_noalloc(dwt_fuse_ctx *ctx, dwt_fuse_wavelet wavelet, int64_t H, int64_t W,
+                                          int64_t B, const float *pan, int64_t pan_ld, const float *gain,
+                                          const float *grad_out, int64_t go_ld, int64_t go_band_stride,
+                                          float *grad_pan, float *grad_ms, float *grad_gain) {
+    if (!ctx) return DWT_FUSE_E_NULL;
+    try {
+        const BwdArgs a{(int)wavelet, H, W, B, pan, pan_ld, gain, grad_out, go_ld, go_band_stride,
+                        grad_pan, grad_ms, grad_gain};
+        return backward_impl(ctx, a, true);
     } catch (const std::bad_alloc &) {
         return fail(ctx, DWT_FUSE_E_NOMEM, "host allocation failed");
     } catch (...) {

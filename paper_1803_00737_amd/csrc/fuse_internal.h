@@ -211,6 +211,13 @@ constexpr int kQualityMaxBands = 65535;  // grid y limit
 // partial: B * kQualityBlocks * 2 doubles of workspace; out: 2 * B doubles.
 hipError_t launch_quality(const QualityParams &p, double *partial, double *out, hipStream_t s);
 
+// Static device scratch of the entry points that allocate nothing
+// (static_scratch.hip): kStaticScratchBytes per GPU, held from the library's
+// load until the process ends.  static_scratch_address gives its address on
+// `device` (looked up once per device, then cached).
+constexpr size_t kStaticScratchBytes = size_t(16) << 20;
+hipError_t static_scratch_address(int device, void **ptr);
+
 // The paper's multi-pass pipeline (comparator); work and scratch are H x W.
 hipError_t launch_multipass(int wavelet, int H, int W, int B, const float *pan, int64_t pan_ld, const float *ms,
                             int64_t ms_ld, int64_t ms_bs, float *out, int64_t out_ld, int64_t out_bs, float *work,
