@@ -70,6 +70,8 @@ def _load():
         lib.oracle_fuse.restype = ci
         lib.oracle_fuse_kappa.argtypes = [ci, i64, i64, i64, dp, dp, dp, ctypes.c_double, dp]
         lib.oracle_fuse_kappa.restype = ci
+        lib.oracle_fuse_rows.argtypes = [ci, i64, i64, i64, dp, dp, dp, ctypes.c_double, i64, i64, dp]
+        lib.oracle_fuse_rows.restype = ci
         lib.oracle_quantize_u8.argtypes = [i64, dp, ctypes.POINTER(ctypes.c_uint8)]
         lib.oracle_quantize_u8.restype = ci
         lib.oracle_quality.argtypes = [i64, i64, i64, dp, dp, dp, dp]
@@ -186,6 +188,28 @@ def fuse(w, pan, ms, gain=None, kappa=1.0):
     else:
         _check(lib.oracle_fuse_kappa(_wav(w), H, W, B, _ptr(pan), _ptr(ms), _ptr(g), float(kappa), _ptr(out)),
                "fuse_kappa")
+    return out
+
+
+def fuse_rows(w, pan, ms, row0, row1, gain=None, kappa=1.0):
+    """Rows row0 .. row1-1 of ``fuse(w, pan, ms, gain, kappa)``, (B, row1-row0, W)
+    float64, equal to those rows of the whole-image result bit for bit; only
+    the rows they need are transformed."""
+    lib = _load()
+    pan = _f64(pan)
+    ms = _f64(ms)
+    if ms.ndim == 2:
+        ms = ms[None]
+    H, W = pan.shape
+    B = ms.shape[0]
+    if ms.shape[1:] != (H // 2, W // 2):
+        raise ValueError("ms must be (B, H/2, W/2)")
+    if not 0 <= row0 <= row1 <= H:
+        raise ValueError("need 0 <= row0 <= row1 <= H")
+    g = _gain(gain, B)
+    out = np.empty((B, row1 - row0, W), dtype=np.float64)
+    _check(lib.oracle_fuse_rows(_wav(w), H, W, B, _ptr(pan), _ptr(ms), _ptr(g), float(kappa), int(row0), int(row1),
+                                _ptr(out)), "fuse_rows")
     return out
 
 

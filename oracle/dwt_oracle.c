@@ -294,6 +294,92 @@ int oracle_fuse(int w, int64_t H, int64_t W, int64_t B, const double *pan,
     return oracle_fuse_kappa(w, H, W, B, pan, ms, gain, 1.0, out);
 }
 
+/* Rows row0 .. row1-1 of every fused band of oracle_fuse_kappa: the same
+ * steps (forward along rows, then columns; LL replaced, details scaled;
+ * inverse along columns, then rows) evaluated only for the 2D coefficient
+ * rows that the column inverse of those output rows reads (Eq. 11-16), and
+ * only for the PAN rows that the column forward of those coefficient rows
+ * reads (Eq. 1-6).  Every value is formed by the same products and sums in
+ * the same order as in the whole-image oracle, so the rows equal its rows
+ * bit for bit.  out is B x (row1 - row0) x W. */
+int oracle_fuse_rows(int w, int64_t H, int64_t W, int64_t B, const double *pan,
+                     const double *ms, const double *gain, double kappa,
+                     int64_t row0, int64_t row1, double *out)
+{
+    if (!valid_wavelet(w) || !valid_len(H) || !valid_len(W) || B < 0 || row0 < 0 ||
+        row1 > H || row0 > row1)
+        return -1;
+    const int64_t H2 = H / 2, W2 = W / 2, R = row1 - row0;
+    filt_t f;
+    make_filters(&f);
+    double **Z = (double **)calloc((size_t)H, sizeof(double *)); /* row-transformed PAN rows */
+    double **X = (double **)calloc((size_t)H, sizeof(double *)); /* 2D forward coefficient rows */
+    double *Y = (double *)malloc(sizeof(double) * (size_t)W);     /* one column-inverted row */
+    int rc = 0;
+    if (!Z || !X || !Y) {
+        rc = -2;
+        goto done;
+    }
+    int64_t ci[4], pi[4];
+    double cw[4], pw[4];
+    /* Step 1: the forward 2D transform, restricted to the rows needed. */
+    for (int64_t y = row0; y < row1; ++y) {
+        const int nc = inv1_taps(w, H, y, &f, ci, cw);
+        for (int k = 0; k < nc; ++k) {
+            const int64_t i = ci[k];
+            if (X[i]) continue;
+            const int np = fwd1_taps(w, H, i, &f, pi, pw);
+            for (int t = 0; t < np; ++t) {
+                const int64_t r = pi[t];
+                if (Z[r]) continue;
+                Z[r] = (double *)malloc(sizeof(double) * (size_t)W);
+                if (!Z[r]) {
+                    rc = -2;
+                    goto done;
+                }
+                along_rows(fwd1_taps, w, 1, W, &f, pan + r * W, Z[r]);
+            }
+            X[i] = (double *)malloc(sizeof(double) * (size_t)W);
+            if (!X[i]) {
+                rc = -2;
+                goto done;
+            }
+            for (int64_t x = 0; x < W; ++x) {
+                double acc = 0.0;
+                for (int t = 0; t < np; ++t) acc += pw[t] * Z[pi[t]][x];
+                X[i][x] = acc;
+            }
+        }
+    }
+    /* Steps 2-3 per band: replaced coefficients, inverse along columns, then rows. */
+    for (int64_t b = 0; b < B; ++b) {
+        const double gb = gain ? gain[b] : 1.0;
+        const double *m = ms + b * H2 * W2;
+        for (int64_t y = row0; y < row1; ++y) {
+            const int nc = inv1_taps(w, H, y, &f, ci, cw);
+            for (int64_t x = 0; x < W; ++x) {
+                double acc = 0.0;
+                for (int k = 0; k < nc; ++k) {
+                    const int64_t i = ci[k];
+                    const double c = (i < H2 && x < W2) ? kappa * m[i * W2 + x] : gb * X[i][x];
+                    acc += cw[k] * c;
+                }
+                Y[x] = acc;
+            }
+            along_rows(inv1_taps, w, 1, W, &f, Y, out + (b * R + (y - row0)) * W);
+        }
+    }
+done:
+    if (Z)
+        for (int64_t r = 0; r < H; ++r) free(Z[r]);
+    if (X)
+        for (int64_t i = 0; i < H; ++i) free(X[i]);
+    free(Z);
+    free(X);
+    free(Y);
+    return rc;
+}
+
 /* Squared-error and reference sums per band, the inputs of RMSE and of an
  * ERGAS-style score (section 4 names ERGAS without a formula). */
 int oracle_quality(int64_t H, int64_t W, int64_t B, const double *fused,

@@ -82,6 +82,13 @@ int oracle_quantize_u8(int64_t n, const double *v, uint8_t *out);
 int oracle_quality(int64_t H, int64_t W, int64_t B, const double *fused,
                    const double *ref, double *sse, double *sum_ref);
 
+/* Rows row0 .. row1-1 (0 <= row0 <= row1 <= H) of every band of
+ * oracle_fuse_kappa, equal to its rows bit for bit, computed from the
+ * coefficient and PAN rows they need only.  out is B x (row1 - row0) x W. */
+int oracle_fuse_rows(int wavelet, int64_t H, int64_t W, int64_t B, const double *pan,
+                     const double *ms, const double *gain, double kappa,
+                     int64_t row0, int64_t row1, double *out);
+
 /* One output pixel (y, x) of the fusion with one MS band, evaluated from
  * the same 1D equations restricted to the coefficients that pixel needs. */
 double oracle_fuse_point(int wavelet, int64_t H, int64_t W,

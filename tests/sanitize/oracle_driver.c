@@ -58,6 +58,20 @@ int main(void) {
                 expect(fabs(v - out[y * W + W - 1]) < 1e-9, "fuse_point against fuse", w, H, W);
             }
             expect(oracle_fuse_kappa(w, H, W, B, pan, ms, gain, 2.0, out) == 0, "fuse_kappa", w, H, W);
+            {
+                /* rows 1 .. H-1 of every band (the first pair row at H = 2) equal the whole image's */
+                const long r0 = H > 2 ? 1 : 0, r1 = H;
+                double *rows = img(B * (r1 - r0) * W, 0u);
+                expect(oracle_fuse_rows(w, H, W, B, pan, ms, gain, 2.0, r0, r1, rows) == 0, "fuse_rows", w, H, W);
+                for (long b = 0; b < B; ++b)
+                    for (long y = r0; y < r1; ++y)
+                        for (long x = 0; x < W; ++x)
+                            expect(rows[(b * (r1 - r0) + y - r0) * W + x] == out[(b * H + y) * W + x],
+                                   "fuse_rows against fuse_kappa", w, H, W);
+                expect(oracle_fuse_rows(w, H, W, B, pan, ms, NULL, 1.0, H / 2, H / 2, rows) == 0, "fuse_rows empty",
+                       w, H, W);
+                free(rows);
+            }
             expect(oracle_quantize_u8(B * H * W, out, u8) == 0, "quantize_u8", w, H, W);
             expect(oracle_quality(H, W, B, out, out, sse, sref) == 0, "quality", w, H, W);
             for (int b = 0; b < 3; ++b) expect(sse[b] == 0.0, "quality of identical images", w, H, W);

@@ -448,6 +448,41 @@ def test_full_size_landsat(dev, fz, oracle, wavelet):
 
 
 @pytest.mark.parametrize("wavelet", ["haar", "d4"])
+def test_full_width_landsat_rows(dev, fz, oracle, wavelet):
+    """Whole rows of the Landsat-shaped scene (15872 x 14336, 6 bands) in the
+    launch configuration the benchmark times (tuner on): the top and bottom
+    64 rows, whose D4 taps wrap to the opposite border (Eq. 5-6, 13-14), and
+    an interior strip across tile and unit seams, every column of every band
+    element by element against the row-strip oracle."""
+    from paper_1803_00737_amd import synth
+
+    wl = synth.landsat(wavelet)
+    say("full width", wl.name, "generate")
+    pan_d, ms_d = wl.make(device=dev)
+    ctx = fz.context(dev)
+    ctx.set_tuning(True)
+    try:
+        say("full width", wl.name, "fuse (tuned)")
+        out_d = fz.fuse(pan_d, ms_d, wavelet)
+    finally:
+        ctx.set_tuning(False)
+    torch.cuda.synchronize()
+    strips = [(0, 64), (4000, 4064), (wl.H - 64, wl.H)]
+    got = [out_d[:, a:b].cpu().numpy() for a, b in strips]
+    pan = pan_d.cpu().numpy().astype(np.float64)
+    ms = ms_d.cpu().numpy().astype(np.float64)
+    del out_d, pan_d, ms_d
+    torch.cuda.empty_cache()
+    for (a, b), g in zip(strips, got):
+        say("full width", wl.name, "oracle rows", a, b)
+        ref = oracle.fuse_rows(wavelet, pan, ms, a, b)
+        if wavelet == "haar":
+            assert np.array_equal(g, ref.astype(np.float32)), (a, b)
+        else:
+            assert np.abs(g - ref).max() <= D4_TOL, (a, b)
+
+
+@pytest.mark.parametrize("wavelet", ["haar", "d4"])
 def test_output_beyond_2_pow_31_elements(dev, fz, oracle, wavelet):
     """PAN 8192 x 8192 with 33 bands: the output holds 2.2e9 float32 elements
     (8.9 GB), more than a 32-bit index can address, so every band offset must

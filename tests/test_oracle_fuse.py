@@ -146,3 +146,29 @@ def test_point_equals_full(oracle, wavelet, H, W):
     b, y, x = map(np.array, zip(*pts))
     vals = oracle.fuse_points(wavelet, pan, ms, gain, b, y, x)
     assert np.array_equal(vals, out[b, y, x])
+
+
+@pytest.mark.parametrize("wavelet", ["haar", "d4"])
+@pytest.mark.parametrize("H,W", [(2, 2), (2, 8), (6, 4), (16, 10), (34, 22), (40, 64)])
+def test_row_strips_stitch_to_the_whole_image(oracle, wavelet, H, W):
+    """The row-strip entry point evaluates only the coefficient and PAN rows
+    its output rows need, with the same arithmetic: any partition of the rows
+    into strips (odd and even cuts, single rows, strips touching the top and
+    bottom wrap) stitches to the whole-image fusion bit for bit, with gains
+    and kappa; an empty strip is empty and out-of-range strips are rejected."""
+    rng = np.random.default_rng(H * 100 + W)
+    B = 3
+    pan = rng.integers(0, 256, (H, W)).astype(np.float64)
+    ms = rng.integers(0, 256, (B, H // 2, W // 2)).astype(np.float64)
+    gain = np.array([1.0, 0.75, 1.3])
+    for kappa in (1.0, 2.0):
+        full = oracle.fuse(wavelet, pan, ms, gain, kappa)
+        cuts = sorted(set([0, H] + [int(c) for c in rng.integers(0, H + 1, 4)]))
+        for cuts_ in (cuts, list(range(H + 1))):
+            parts = [oracle.fuse_rows(wavelet, pan, ms, a, b, gain, kappa) for a, b in zip(cuts_[:-1], cuts_[1:])]
+            assert np.array_equal(np.concatenate(parts, axis=1), full)
+    assert oracle.fuse_rows(wavelet, pan, ms, 1, 1).shape == (B, 0, W)
+    for a, b in ((-1, 1), (0, H + 1), (2, 1)):
+        with pytest.raises(ValueError):
+            oracle.fuse_rows(wavelet, pan, ms, a, b)
+
