@@ -349,6 +349,17 @@ dwt_fuse_status dwt_fuse_force_tile(dwt_fuse_ctx *ctx, int seg_rows, int waves_p
  * out of range. */
 dwt_fuse_status dwt_fuse_force_band_split(dwt_fuse_ctx *ctx, int bands_per_unit);
 
+/* Force the order in which the work units of forward launches (dwt_fuse_run,
+ * dwt_fuse_run_ex, the flat dwt_fuse_run_batched form) and of the adjoint
+ * are numbered and handed to workgroups: bit 0 set = row bands across the
+ * image width (else column strips down the image), bit 1 set = workgroups
+ * take units in dispatch order, so the whole GPU advances through them as
+ * one front (else each XCD takes a contiguous run); -1 = automatic (the
+ * tuned or default order).  Results are bit-identical for every order.
+ * DWT_FUSE_E_SHAPE if out of range (-1 .. 3).  The environment variable
+ * DWT_FUSE_FORCE_ORDER sets the same at dwt_fuse_create. */
+dwt_fuse_status dwt_fuse_force_order(dwt_fuse_ctx *ctx, int order);
+
 #ifdef __cplusplus
 }
 #endif

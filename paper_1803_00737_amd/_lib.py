@@ -23,7 +23,7 @@ EXPORTS = (
     "dwt_fuse_tune_save", "dwt_fuse_tune_load", "dwt_fuse_force_tile", "dwt_fuse_run_multipass",
     "dwt_fuse_run_ex", "dwt_fuse_check_run_ex", "dwt_fuse_quality", "dwt_fuse_check_quality",
     "dwt_fuse_force_band_split", "dwt_fuse_backward_batched", "dwt_fuse_check_backward_batched",
-    "dwt_fuse_backward_noalloc",
+    "dwt_fuse_backward_noalloc", "dwt_fuse_force_order",
 )
 
 HAAR = 0
@@ -132,6 +132,8 @@ def load(require_torch: bool = True):
         lib.dwt_fuse_force_tile.restype = st
         lib.dwt_fuse_force_band_split.argtypes = [vp, i32]
         lib.dwt_fuse_force_band_split.restype = st
+        lib.dwt_fuse_force_order.argtypes = [vp, i32]
+        lib.dwt_fuse_force_order.restype = st
         lib.dwt_fuse_run_multipass.argtypes = [vp, i32, i64, i64, i64, vp, i64, vp, i64, i64, vp, i64, i64]
         lib.dwt_fuse_run_multipass.restype = st
         ex_args = run_args + [ctypes.POINTER(Opts)]

@@ -61,6 +61,11 @@ class Context:
         """LDS-staged D4: bands per work unit (0 = automatic)."""
         self.check(self.lib.dwt_fuse_force_band_split(self.handle, bands_per_unit), "dwt_fuse_force_band_split")
 
+    def force_order(self, order: int = -1):
+        """Unit order of forward and adjoint launches (-1 = automatic): bit 0
+        row bands (else column strips), bit 1 dispatch order (else per-XCD runs)."""
+        self.check(self.lib.dwt_fuse_force_order(self.handle, order), "dwt_fuse_force_order")
+
     def tune_save(self, path: str):
         self.check(self.lib.dwt_fuse_tune_save(self.handle, path.encode()), "dwt_fuse_tune_save")
 

@@ -65,6 +65,12 @@ __device__ __forceinline__ int xcd_remap(int b, int G) {
     return x * q + (x < rem ? x : rem) + i;
 }
 
+// Workgroup -> logical block: bit 1 of the unit order set takes the dispatch
+// order (one front across the GPU), clear the per-XCD contiguous runs above.
+__device__ __forceinline__ int block_unit(int order) {
+    return (order & 2) ? (int)blockIdx.x : xcd_remap(blockIdx.x, gridDim.x);
+}
+
 template <int CTRL>
 __device__ __forceinline__ float dpp_move(float x) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
@@ -784,7 +790,7 @@ __device__ __forceinline__ void haar_adj_unit(const AdjParams &p, int strip, int
 }
 
 __device__ __forceinline__ void unit_strip_seg(const AdjParams &p, int unit, int &strip, int &seg) {
-    if (p.order) {
+    if (p.order & 1) {
         seg = unit / p.nstrips;
         strip = unit - seg * p.nstrips;
     } else {
@@ -823,7 +829,7 @@ template <int KIND, int NC, int AL, int X>
 __global__ __launch_bounds__(256) void adjoint_kernel(AdjParams p, Filters f) {
     const int wpb = blockDim.x >> 6;
     const int lane = threadIdx.x & 63;
-    const int unit = xcd_remap(blockIdx.x, gridDim.x) * wpb + (threadIdx.x >> 6);
+    const int unit = block_unit(p.order) * wpb + (threadIdx.x >> 6);
     if (unit >= p.units) return;  // whole wavefront leaves together
     adj_unit<KIND, NC, AL, X>(p, f, unit, lane);
 }
@@ -1018,10 +1024,10 @@ __global__ __launch_bounds__(256) void d4_adjoint_staged_kernel(AdjParams p, Fil
     const int wpb = blockDim.x >> 6;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int T = wpb * KR;
-    const int unit = xcd_remap(blockIdx.x, gridDim.x);
+    const int unit = block_unit(p.order);
     if (unit >= p.units) return;  // whole workgroup
     int strip, trow;
-    if (p.order) {
+    if (p.order & 1) {
         trow = unit / p.nstrips;
         strip = unit - trow * p.nstrips;
     } else {
@@ -1181,10 +1187,10 @@ __global__ __launch_bounds__(256) void d4_adjoint_staged_all_kernel(AdjParams p,
     const int wpb = blockDim.x >> 6;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int T = wpb * KR;
-    const int unit = xcd_remap(blockIdx.x, gridDim.x);
+    const int unit = block_unit(p.order);
     if (unit >= p.units) return;  // whole workgroup
     int strip, trow;
-    if (p.order) {
+    if (p.order & 1) {
         trow = unit / p.nstrips;
         strip = unit - trow * p.nstrips;
     } else {

@@ -605,10 +605,10 @@ __global__ __launch_bounds__(256) void codec_kernel(CodecParams p, Filters f) {
     // The wavefront's index is the same on all its lanes; saying so keeps the
     // unit's row and column bookkeeping in scalar registers.
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int unit = xcd_remap(blockIdx.x, gridDim.x) * wpb + wave;
+    const int unit = block_unit(p.order) * wpb + wave;
     if (unit >= p.units) return;  // whole wavefront; no barriers in this kernel
     int strip, seg;
-    if (p.order) {
+    if (p.order & 1) {
         seg = unit / p.nstrips;
         strip = unit - seg * p.nstrips;
     } else {
@@ -647,11 +647,11 @@ __global__ __launch_bounds__(256) void d4_codec_staged_kernel(CodecParams p, Fil
     extern __shared__ float lds[];
     const int wpb = blockDim.x >> 6;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const int unit = xcd_remap(blockIdx.x, gridDim.x);
+    const int unit = block_unit(p.order);
     if (unit >= p.units) return;  // whole workgroup
     const int T = wpb * KR;
     int strip, trow;
-    if (p.order) {
+    if (p.order & 1) {
         trow = unit / p.nstrips;
         strip = unit - trow * p.nstrips;
     } else {

@@ -430,7 +430,7 @@ Path choose_bwd_path(const BwdArgs &a) {
 // each (D4, 128-bit path only).  seg_rows is ignored unless mode == 0.
 struct Tile {
     int seg_rows = 0, wpb = 0, nc = 0;
-    int order = 1;  // 1 row-band-major, 0 strip-major
+    int order = 1;  // bit 0: row-band-major (else strip-major); bit 1: dispatch order (else per-XCD runs)
     int mode = 0;
     int split = 0;  // LDS-staged: bands per unit (0 = all)
     int rows() const { return mode >= 3 ? wpb * (mode - 2) : (mode > 0 ? mode : seg_rows); }
@@ -441,6 +441,7 @@ struct Tile {
 // LDS-staged unit.
 struct Forced {
     int seg_rows = 0, wpb = 0, nc = 0, variant = 0, split = 0;
+    int order = -1;  // unit order of forward launches (-1 = the shape's own)
 };
 
 struct Decomp {
@@ -478,11 +479,17 @@ Tile rolling_tile(int64_t H, int64_t W, int nc) {
 }
 
 // Default forward shape (what the tuner picks on the large workloads):
-// D4 -> LDS-staged workgroups of 4 wavefronts x 2 coefficient rows, strip-major
-// units, except on 8-byte rows below 2^25 pixels, where one-shot single-row
-// wavefronts with 2 coefficient columns per lane measured faster (the staged
-// tile then stages half of its rows in 16-byte groups shifted by 2 floats);
-// Haar -> one-shot single-row wavefronts, row-band-major units.
+// D4 -> LDS-staged workgroups of 4 wavefronts x 2 coefficient rows, except on
+// 8-byte rows below 2^25 pixels, where one-shot single-row wavefronts with 2
+// coefficient columns per lane measured faster (the staged tile then stages
+// half of its rows in 16-byte groups shifted by 2 floats); Haar -> one-shot
+// single-row wavefronts.  Units row-band-major in dispatch order (order 3):
+// the whole GPU writes one narrow band of rows of every output band at a
+// time, which HBM absorbs faster than the same stores spread over per-XCD
+// runs or down column strips (Landsat-shaped D4, 6 bands: 1.36 against
+// 1.56 ms strip-major with per-XCD runs; Haar 1.35 against 1.42 ms).  The
+// small-image one-shot D4 shape keeps per-XCD runs (order 1), whose halo
+// rows then stay in one L2.
 Tile default_tile(int wavelet, int64_t H, int64_t W, Path path) {
     Tile t;
     if (wavelet == DWT_FUSE_D4 && !(path == PATH_V2 && H * W < ((int64_t)1 << 25))) {
@@ -490,13 +497,13 @@ Tile default_tile(int wavelet, int64_t H, int64_t W, Path path) {
         t.mode = 4;
         t.seg_rows = 2;
         t.wpb = 4;
-        t.order = 0;
+        t.order = 3;
     } else {
         t.nc = path_nc(path);
         t.mode = 1;
         t.seg_rows = 1;
         t.wpb = wavelet == DWT_FUSE_D4 ? 4 : 1;
-        t.order = 1;
+        t.order = wavelet == DWT_FUSE_D4 ? 1 : 3;
     }
     return t;
 }
@@ -662,6 +669,7 @@ Tile apply_forced(const dwt_fuse_ctx *c, Tile t, Path path, int wavelet, int max
     if (t.mode == 0 && t.seg_rows < 1) t.seg_rows = 1;
     if (fo.split > 0) t.split = fo.split;
     if (t.mode < 3) t.split = 0;
+    if (fo.order >= 0) t.order = fo.order;
     return t;
 }
 
@@ -773,7 +781,9 @@ Tile tune_fuse(dwt_fuse_ctx *c, const RunArgs &a, Path path) {
         cands.emplace_back(time_fuse(c, a, path, t), t);
     }
     // Candidates: rolling units of 2..64 rows and one-shot units of 1 or 2
-    // rows, each with 1, 2 or 4 waves per workgroup, both unit orders and
+    // rows, each with 1, 2 or 4 waves per workgroup, three unit orders
+    // (strip-major and row-band-major in per-XCD runs, row-band-major in
+    // dispatch order) and
     // (on 128- and 64-bit rows) 1 or 2 coefficient columns per lane.
     const int ncs[2] = {2, 1};
     const int rows_cand[8] = {-1, -2, 2, 4, 8, 16, 32, 64};  // negative: one-shot of that many rows
@@ -781,7 +791,7 @@ Tile tune_fuse(dwt_fuse_ctx *c, const RunArgs &a, Path path) {
         if (nc > path_nc(path)) continue;
         for (int rc : rows_cand) {
             for (int wpb : {1, 2, 4}) {
-                for (int order : {1, 0}) {
+                for (int order : {1, 0, 3}) {
                     Tile t;
                     t.nc = nc;
                     t.mode = rc < 0 ? -rc : 0;
@@ -799,7 +809,7 @@ Tile tune_fuse(dwt_fuse_ctx *c, const RunArgs &a, Path path) {
     if (staged_allowed(a.wavelet, path, 2)) {
         for (int kr : {1, 2, 4}) {
             for (int wpb : {1, 2, 4}) {
-                for (int order : {1, 0}) {
+                for (int order : {1, 0, 3}) {
                     Tile t;
                     t.nc = 2;
                     t.mode = 2 + kr;
@@ -916,6 +926,7 @@ struct BatchPlan {
     int mode = 0;
     int total = 0;          // work items (flat) or wavefront units (persistent)
     int staged_bands = 0;   // flat: largest band count among staged scenes
+    int flat_order = 1;     // flat: unit order of the items (bit 0 row-band-major, bit 1 no XCD remap)
     std::string sig;  // batch signature (graph cache key), includes the variant and grid
 };
 
@@ -925,6 +936,7 @@ struct BatchPlan {
 dwt_fuse_status plan_batch(dwt_fuse_ctx *ctx, const dwt_fuse_item *items, int64_t n, int mode, BatchPlan *pl) {
     pl->sc.assign((size_t)n, BatchScene{});
     pl->mode = mode;
+    pl->flat_order = ctx->forced.order >= 0 ? ctx->forced.order : 3;
     pl->staged_bands = 0;
     pl->sig.clear();
     pl->sig.reserve((size_t)n * 48);
@@ -937,7 +949,7 @@ dwt_fuse_status plan_batch(dwt_fuse_ctx *ctx, const dwt_fuse_item *items, int64_
         int items_of_scene = 0;
         Decomp d;
         if (mode == kFlatBatch) {
-            t.order = 1;
+            t.order = pl->flat_order & 1;
             t.wpb = 4;
             // Every D4 scene staged, also on 8-byte rows where one-shot
             // wavefronts win per image: the launch reserves the staged
@@ -984,7 +996,7 @@ dwt_fuse_status plan_batch(dwt_fuse_ctx *ctx, const dwt_fuse_item *items, int64_
     if (mode == kFlatBatch) {
         pl->grid = (int)total;
         char gb[64];
-        std::snprintf(gb, sizeof(gb), "#flat#%d", pl->staged_bands);
+        std::snprintf(gb, sizeof(gb), "#flat#%d#o%d", pl->staged_bands, pl->flat_order);
         pl->sig += gb;
         return DWT_FUSE_OK;
     }
@@ -1036,7 +1048,8 @@ dwt_fuse_status stage_batch(dwt_fuse_ctx *ctx, const BatchPlan &pl) {
 
 hipError_t launch_plan(dwt_fuse_ctx *ctx, const BatchPlan &pl, hipStream_t s) {
     const int n = (int)pl.sc.size();
-    if (pl.mode == kFlatBatch) return launch_fuse_batched_flat(ctx->d_scenes, n, pl.total, pl.staged_bands, ctx->filt, s);
+    if (pl.mode == kFlatBatch)
+        return launch_fuse_batched_flat(ctx->d_scenes, n, pl.total, pl.staged_bands, pl.flat_order, ctx->filt, s);
     return launch_fuse_batched(ctx->d_scenes, n, pl.q, ctx->d_counters, pl.grid, pl.mode, ctx->filt, s);
 }
 
@@ -1123,6 +1136,10 @@ dwt_fuse_status dwt_fuse_create(dwt_fuse_ctx **ctx, int device, void *hip_stream
                 c->forced.nc = d;
                 c->forced.variant = v;
             }
+        }
+        if (const char *f = std::getenv("DWT_FUSE_FORCE_ORDER")) {
+            const int o = std::atoi(f);
+            if (o >= 0 && o <= 3) c->forced.order = o;
         }
         if (const char *f = std::getenv("DWT_FUSE_TUNE_CACHE")) dwt_fuse_tune_load(c, f);
         *ctx = c;
@@ -1214,6 +1231,13 @@ dwt_fuse_status dwt_fuse_force_band_split(dwt_fuse_ctx *ctx, int bands_per_unit)
     return DWT_FUSE_OK;
 }
 
+dwt_fuse_status dwt_fuse_force_order(dwt_fuse_ctx *ctx, int order) {
+    if (!ctx) return DWT_FUSE_E_NULL;
+    if (order < -1 || order > 3) return fail(ctx, DWT_FUSE_E_SHAPE, "unit order out of range (-1 .. 3)");
+    ctx->forced.order = order;
+    return DWT_FUSE_OK;
+}
+
 dwt_fuse_status dwt_fuse_tune_save(const dwt_fuse_ctx *ctx, const char *path) {
     if (!ctx || !path) return DWT_FUSE_E_NULL;
     FILE *f = std::fopen(path, "w");
@@ -1250,7 +1274,7 @@ dwt_fuse_status dwt_fuse_tune_load(dwt_fuse_ctx *ctx, const char *path) {
                                               (t.mode < 3 || t.nc == 2))
                                     : (t.nc >= 1 && t.nc <= 2 && t.mode >= 0 && t.mode <= 6 && t.mode != 5);
         if (r != 7 || t.split < 0 || t.split > 8 || (key[0] != 'f' && key[0] != 'b' && !codec) || t.seg_rows < 1 || t.seg_rows > 4096 ||
-            t.wpb < 1 || t.wpb > 4 || t.order < 0 || t.order > 1 || !shape_ok) {
+            t.wpb < 1 || t.wpb > 4 || t.order < 0 || t.order > 3 || !shape_ok) {
             ok = false;
             break;
         }
@@ -1305,7 +1329,7 @@ namespace {
 // ------------------------------------------------------------ format variants
 
 struct CodecShape {
-    int nc = 4, kr = 1, wpb = 4, order = 1;
+    int nc = 4, kr = 1, wpb = 4, order = 3;
     // coefficient rows per unit: kr for one-shot tiles (kr 1, 2), seg_rows when
     // rolling (kr 0), (kr - 2) * wpb for LDS-staged tiles (kr 3, 4: D4, 8-bit
     // input, nc 2)
@@ -1409,7 +1433,16 @@ float time_codec(dwt_fuse_ctx *c, const ExArgs &a, const CodecShape &t) {
     return time_median3(c->stream, [&] { return launch_codec_shape(c, a, t); });
 }
 
+CodecShape codec_shape_of(dwt_fuse_ctx *c, const ExArgs &a);
+
+// The launch shape of a format call, with a forced unit order applied.
 CodecShape codec_shape(dwt_fuse_ctx *c, const ExArgs &a) {
+    CodecShape t = codec_shape_of(c, a);
+    if (c->forced.order >= 0) t.order = c->forced.order;
+    return t;
+}
+
+CodecShape codec_shape_of(dwt_fuse_ctx *c, const ExArgs &a) {
     CodecShape t = codec_default(a);
     const bool u8 = a.in_format == DWT_FUSE_U8;
     const std::string key = codec_key(a, t.aligned);
@@ -1431,7 +1464,7 @@ CodecShape codec_shape(dwt_fuse_ctx *c, const ExArgs &a) {
             for (int rc : rows_cand) {
                 if (rc > 0 && a.wavelet != DWT_FUSE_D4) continue;
                 for (int wpb : {1, 2, 4})
-                    for (int order : {1, 0}) {
+                    for (int order : {1, 0, 3}) {
                         CodecShape s = t;
                         s.nc = nc;
                         s.kr = rc < 0 ? -rc : 0;
@@ -1446,7 +1479,7 @@ CodecShape codec_shape(dwt_fuse_ctx *c, const ExArgs &a) {
         if (u8 && a.wavelet == DWT_FUSE_D4) {
             for (int kr : {3, 4})
                 for (int wpb : {2, 4})
-                    for (int order : {0, 1}) {
+                    for (int order : {0, 1, 3}) {
                         CodecShape s = t;
                         s.nc = 2;
                         s.kr = kr;
@@ -1965,7 +1998,7 @@ static dwt_fuse_status run_staged_bwd(dwt_fuse_ctx *ctx, const BwdArgs &a, Path 
     p.wavelet = a.wavelet;
     p.path = path;
     p.nstrips = (int32_t)ns;
-    p.order = 0;
+    p.order = ctx->forced.order >= 0 ? ctx->forced.order : 0;
     p.pstride = (int32_t)a.B;
     p.accumulate = 0;
     const hipError_t e = launch_adjoint_staged(p, ctx->filt, sb.kr, sb.wpb, sb.all, ctx->stream);

@@ -40,7 +40,8 @@ struct FuseParams {
     int32_t wavelet;   // 0 Haar, 1 D4
     int32_t path;      // Path
     int32_t nstrips;   // ceil((W/2) / (64*NC))
-    int32_t order;     // unit numbering: 0 strip-major, 1 row-band-major
+    int32_t order;     // unit numbering, bit 0: row-band-major (else strip-major); bit 1:
+                       // workgroups in dispatch order (else each XCD a contiguous run)
     int32_t mode;      // 0 rolling over seg_rows rows; 1, 2 one-shot tile of that many rows
     float kappa;       // LL <- kappa * MS band (1 = as printed)
     int32_t bsplit;    // LDS-staged D4: bands per unit (0 = every band in one unit); units
@@ -102,7 +103,7 @@ int batched_blocks_per_cu(int mode);
 // tiles of 8 coefficient rows (4 wavefronts x 2 rows, band groups of at most
 // `staged_bands`); all others are one-shot single-row wavefront units, 4 per
 // item.
-hipError_t launch_fuse_batched_flat(const BatchScene *d_scenes, int nscenes, int total, int staged_bands,
+hipError_t launch_fuse_batched_flat(const BatchScene *d_scenes, int nscenes, int total, int staged_bands, int order,
                                     const Filters &f, hipStream_t s);
 
 // Largest band group a staged tile of T coefficient rows can hold in 64 KB of LDS.
@@ -188,7 +189,7 @@ struct CodecParams {
     int32_t seg_rows;  // coefficient rows per unit (= kr for one-shot tiles)
     int32_t nseg;      // ceil((H/2) / seg_rows)
     int32_t units;     // nstrips * nseg
-    int32_t order;     // 0 strip-major, 1 row-band-major
+    int32_t order;     // as in FuseParams
     int32_t wavelet;   // 0 Haar, 1 D4
 };
 

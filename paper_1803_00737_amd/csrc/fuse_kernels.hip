@@ -394,12 +394,12 @@ __device__ __forceinline__ void haar_tile(const FuseParams &p, int strip, int se
     }
 }
 
-// Unit numbering.  Row-band-major (order 1) puts horizontally adjacent
+// Unit numbering.  Row-band-major (order bit 0 set) puts horizontally adjacent
 // strips of the same rows next to each other, so with the XCD remap one
 // XCD works on a band of rows across the whole width at a time and the
 // 1-column halos of neighbouring strips are read while still in its L2.
 __device__ __forceinline__ void unit_coords(int unit, int nstrips, int nseg, int order, int &strip, int &seg) {
-    if (order) {
+    if (order & 1) {
         seg = unit / nstrips;
         strip = unit - seg * nstrips;
     } else {
@@ -636,7 +636,7 @@ __device__ __forceinline__ void d4_staged_tile(const FuseParams &p, const Filter
 template <int KR, int LAY>
 __global__ __launch_bounds__(256) void d4_staged_kernel(FuseParams p, Filters f, int bg_max) {
     extern __shared__ float lds[];
-    const int unit = xcd_remap(blockIdx.x, gridDim.x);
+    const int unit = block_unit(p.order);
     if (unit >= p.units) return;  // whole workgroup
     if (p.bsplit > 0) {  // unit = tile * ngroups + group
         const int ng = (p.B + p.bsplit - 1) / p.bsplit;
@@ -692,7 +692,7 @@ template <int WAV, int NC, int AL, int KR>
 __global__ __launch_bounds__(256) void fuse_kernel(FuseParams p, Filters f) {
     const int wpb = blockDim.x >> 6;
     const int lane = threadIdx.x & 63;
-    const int unit = xcd_remap(blockIdx.x, gridDim.x) * wpb + (threadIdx.x >> 6);
+    const int unit = block_unit(p.order) * wpb + (threadIdx.x >> 6);
     if (unit >= p.units) return;
     run_unit<NC, AL, KR, WAV>(p, f, unit, lane);
 }
@@ -867,9 +867,9 @@ hipError_t launch_fuse_batched(const BatchScene *d_scenes, int nscenes, const Ba
 // queue on this GPU.
 
 __global__ __launch_bounds__(256) void fuse_batched_flat_kernel(const BatchScene *__restrict__ scenes, int nscenes,
-                                                                int total, int bg_max, Filters f) {
+                                                                int total, int bg_max, int order, Filters f) {
     extern __shared__ float lds[];
-    const int u = xcd_remap(blockIdx.x, gridDim.x);
+    const int u = block_unit(order);
     if (u >= total) return;
     const int si = find_scene(scenes, nscenes, u);
     const FuseParams p = scenes[si].p;
@@ -902,14 +902,14 @@ __global__ __launch_bounds__(256) void fuse_batched_flat_kernel(const BatchScene
     }
 }
 
-hipError_t launch_fuse_batched_flat(const BatchScene *d_scenes, int nscenes, int total, int staged_bands,
+hipError_t launch_fuse_batched_flat(const BatchScene *d_scenes, int nscenes, int total, int staged_bands, int order,
                                     const Filters &f, hipStream_t s) {
     if (nscenes <= 0 || total <= 0) return hipSuccess;
     const int bgm = staged_bg_max(8);
     const int bg = staged_bands < bgm ? staged_bands : bgm;
     const size_t lds = bg > 0 ? sizeof(float) * staged_lds_floats(8, bg) : 0;
     hipLaunchKernelGGL(fuse_batched_flat_kernel, dim3(total), dim3(256), lds, s, d_scenes, nscenes, total,
-                       bg > 0 ? bg : 1, f);
+                       bg > 0 ? bg : 1, order, f);
     return hipGetLastError();
 }
 

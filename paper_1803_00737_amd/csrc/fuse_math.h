@@ -26,6 +26,14 @@ __device__ __forceinline__ int xcd_remap(int b, int G) {
     return x * q + (x < rem ? x : rem) + i;
 }
 
+// Workgroup -> logical block.  Bit 1 of a launch's unit order clear:
+// remapped so that each XCD takes a contiguous run of blocks; set: dispatch
+// order (the hardware deals consecutive workgroups round-robin to the XCDs,
+// so the whole GPU then advances through the units as one front).
+__device__ __forceinline__ int block_unit(int order) {
+    return (order & 2) ? (int)blockIdx.x : xcd_remap(blockIdx.x, gridDim.x);
+}
+
 // Row low-pass at coefficient columns pc[0..NC]: sum_l h_l PAN(y, 2s+l).
 template <int NC>
 __device__ __forceinline__ void rowfilt(const Filters &f, const f2 (&x)[NC + 2], float (&R)[NC + 1]) {

@@ -68,6 +68,32 @@ def test_adjoint_matches_oracle(dev, fz, oracle, wavelet, H, W, B):
     check_grads(oracle, wavelet, pan, gy, gain, [t.cpu().numpy() for t in got])
 
 
+@pytest.mark.parametrize("H,W,B", [(130, 1030, 3), (66, 516, 6)])
+def test_adjoint_unit_orders(dev, fz, H, W, B):
+    """Every unit order of the rolling, one-shot and LDS-staged adjoints gives
+    the gradients of the default order bit for bit."""
+    rng = np.random.default_rng(H + W + B)
+    pan, _ = int_scene(rng, H, W, 1)
+    gy = rng.normal(size=(B, H, W)).astype(np.float32)
+    gain = rng.uniform(0.5, 1.5, B).astype(np.float32)
+    p, y, g = to_dev(pan, dev), to_dev(gy, dev), to_dev(gain, dev)
+    ctx = fz.context(dev)
+    try:
+        for seg, wpb, nc, var in [(0, 0, 0, 0), (16, 4, 2, 0), (4, 2, 2, 1), (2, 4, 2, 2), (2, 4, 2, 3)]:
+            ctx.force_tile(seg, wpb, nc, var)
+            ctx.force_order(-1)
+            ref = [t.cpu().numpy() for t in fz.fuse_backward(p, y, "d4", g)]
+            for order in (0, 1, 2, 3):
+                say("adjoint order", order, H, W, B, seg, wpb, nc, var)
+                ctx.force_order(order)
+                got = [t.cpu().numpy() for t in fz.fuse_backward(p, y, "d4", g)]
+                for r, q in zip(ref, got):
+                    assert np.array_equal(r, q), (order, seg, wpb, nc, var)
+    finally:
+        ctx.force_tile(0, 0, 0, 0)
+        ctx.force_order(-1)
+
+
 @pytest.mark.parametrize("H,W", [(8, 8), (34, 136), (130, 1288), (66, 516), (2, 4), (66, 1030)])
 @pytest.mark.parametrize("B", [1, 4, 6, 10])
 def test_forced_adjoint_shapes(dev, fz, oracle, H, W, B):

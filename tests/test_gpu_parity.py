@@ -206,6 +206,40 @@ def test_tile_shapes_give_identical_results(dev, fz, wavelet, H, W):
 
 
 @pytest.mark.parametrize("wavelet", ["haar", "d4"])
+@pytest.mark.parametrize("H,W", [(250, 1288), (66, 1030), (18, 8)])
+def test_unit_orders_give_identical_results(dev, fz, oracle, wavelet, H, W):
+    """Every unit order (column strips or row bands, per-XCD runs or dispatch
+    order) of every variant gives the same output bit for bit, and the
+    oracle's; 8-bit output too."""
+    rng = np.random.default_rng(17)
+    pan, ms = int_scene(rng, H, W, 3)
+    p, m = to_dev(pan, dev), to_dev(ms, dev)
+    ref = oracle_out(oracle, wavelet, pan, ms)
+    ctx = fz.context(dev)
+    base = None
+    try:
+        for order in (0, 1, 2, 3):
+            ctx.force_order(order)
+            for seg, wpb, nc, var in [(0, 0, 0, 0), (16, 4, 2, 1), (1, 2, 1, 2), (2, 4, 2, 2), (2, 4, 2, 3),
+                                      (1, 4, 2, 3)]:
+                say(wavelet, "order", order, H, W, "tile", seg, wpb, nc, var)
+                ctx.force_tile(seg, wpb, nc, var)
+                out = fz.fuse(p, m, wavelet).cpu().numpy()
+                out8 = fz.fuse(p.to(torch.uint8), m.to(torch.uint8), wavelet, out_dtype=torch.uint8).cpu().numpy()
+                if base is None:
+                    base = (out, out8)
+                    if wavelet == "haar":
+                        assert np.array_equal(out, ref.astype(np.float32))
+                    else:
+                        assert np.abs(out - ref).max() <= D4_TOL
+                assert np.array_equal(out, base[0]), (order, seg, wpb, nc, var)
+                assert np.array_equal(out8, base[1]), (order, seg, wpb, nc, var)
+    finally:
+        ctx.force_tile(0, 0, 0, 0)
+        ctx.force_order(-1)
+
+
+@pytest.mark.parametrize("wavelet", ["haar", "d4"])
 @pytest.mark.parametrize("H,W", [(66, 1032), (34, 70), (10, 516)])
 @pytest.mark.parametrize("ms_pad,ms_off", [(0, 0), (1, 1), (2, 2)])
 def test_tile_shapes_on_8_byte_rows(dev, fz, oracle, wavelet, H, W, ms_pad, ms_off):
