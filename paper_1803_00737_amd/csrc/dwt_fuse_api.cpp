@@ -410,6 +410,15 @@ Path choose_path(const RunArgs &a) {
     return PATH_SCALAR;
 }
 
+// Forward launches store in overlapped strips (strip_origin) when some
+// output row does not start on a 64-byte boundary; never on 4-byte rows
+// (their pixel pairs are not 8-byte aligned).
+bool overlap_strips(const RunArgs &a, Path path, int forced = -1) {
+    if (path == PATH_SCALAR) return false;
+    if (forced >= 0) return forced == 1;
+    return !(aligned(a.out, 64) && a.out_ld % 16 == 0 && (a.B == 1 || a.out_bs % 16 == 0));
+}
+
 Path choose_bwd_path(const BwdArgs &a) {
     const bool b1 = a.B == 1;
     const bool gp = !a.grad_pan || aligned(a.grad_pan, 16);
@@ -442,18 +451,20 @@ struct Tile {
 struct Forced {
     int seg_rows = 0, wpb = 0, nc = 0, variant = 0, split = 0;
     int order = -1;  // unit order of forward launches (-1 = the shape's own)
+    int ovl = -1;    // overlapped strips (-1 = by the output's alignment)
 };
 
 struct Decomp {
     int32_t nstrips = 0, nseg = 0, units = 0;
+    int32_t ovl = 0;  // overlapped strips (strip_origin)
 };
 
-bool decompose(int64_t H, int64_t W, const Tile &t, Decomp *d) {
-    const int64_t W2 = W / 2, H2 = H / 2;
-    const int64_t cols = 64 * t.nc;
+bool decompose(int64_t H, int64_t W, const Tile &t, Decomp *d, bool ovl = false) {
+    const int64_t H2 = H / 2;
     const int seg_rows = t.rows();
-    if (seg_rows < 1) return false;
-    const int64_t ns = (W2 + cols - 1) / cols;
+    if (seg_rows < 1 || t.nc < 1 || t.nc > 2) return false;
+    const int64_t ns = strip_count(W, t.nc, ovl ? 1 : 0);
+    d->ovl = ovl ? 1 : 0;
     const int64_t ng = (H2 + seg_rows - 1) / seg_rows;
     if (ns * ng > INT32_MAX) return false;
     d->nstrips = (int32_t)ns;
@@ -537,6 +548,15 @@ Filters make_filters() {
 
 // ---------------------------------------------------------------- context
 
+// Form of a batched forward launch: persistent queues (mode 0 rolling, 1-2
+// one-shot rows) or the flat grid (mode 3) with its unit order and the band
+// group size of its LDS-staged tiles (0 = every band of the batch at once).
+struct BatchChoice {
+    int mode = 3;
+    int order = 3;
+    int bg = 0;
+};
+
 struct dwt_fuse_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -548,7 +568,7 @@ struct dwt_fuse_ctx {
     bool tuning = false;
     Forced forced;
     std::map<std::string, Tile> table;
-    std::map<std::string, int> batch_modes;  // tuned variant per batch signature
+    std::map<std::string, BatchChoice> batch_modes;  // tuned form per batch signature
     // backward workspace
     float *ws = nullptr;
     size_t ws_bytes = 0;
@@ -627,6 +647,7 @@ FuseParams make_params(const RunArgs &a, Path path, const Tile &t, const Decomp 
     p.order = t.order;
     p.mode = t.mode;
     p.kappa = 1.0f;
+    p.ovl = d.ovl;
     if (t.mode >= 3 && t.split > 0 && t.split < a.B) {  // (tile, band group) units
         p.bsplit = t.split;
         p.units = d.units * (int32_t)((a.B + t.split - 1) / t.split);  // bounded by split_fits
@@ -707,7 +728,7 @@ float time_median3(hipStream_t s, F launch) {
 // One forward launch of shape t on the caller's buffers.
 hipError_t launch_tile(dwt_fuse_ctx *c, const RunArgs &a, Path path, const Tile &t) {
     Decomp d;
-    if (!decompose(a.H, a.W, t, &d) || !split_fits(t, d, a.B)) return hipErrorInvalidValue;
+    if (!decompose(a.H, a.W, t, &d, overlap_strips(a, path, c->forced.ovl)) || !split_fits(t, d, a.B)) return hipErrorInvalidValue;
     const FuseParams p = make_params(a, path_for_nc(path, t.nc), t, d);
     return launch_fuse(p, c->filt, t.wpb, c->stream);
 }
@@ -715,7 +736,7 @@ hipError_t launch_tile(dwt_fuse_ctx *c, const RunArgs &a, Path path, const Tile 
 // Time one forward launch configuration on the caller's buffers (ms, median of 3).
 float time_fuse(dwt_fuse_ctx *c, const RunArgs &a, Path path, const Tile &t) {
     Decomp d;
-    if (!decompose(a.H, a.W, t, &d) || !split_fits(t, d, a.B)) return 1e30f;
+    if (!decompose(a.H, a.W, t, &d, overlap_strips(a, path, c->forced.ovl)) || !split_fits(t, d, a.B)) return 1e30f;
     return time_median3(c->stream, [&] { return launch_tile(c, a, path, t); });
 }
 
@@ -826,7 +847,7 @@ Tile tune_fuse(dwt_fuse_ctx *c, const RunArgs &a, Path path) {
     // stay ahead when launches do not overlap, e.g. one call at a time)
     auto units = [&](const Tile &t) {
         Decomp d;
-        return decompose(a.H, a.W, t, &d) ? (int64_t)d.units : INT64_MAX;
+        return decompose(a.H, a.W, t, &d, overlap_strips(a, path, c->forced.ovl)) ? (int64_t)d.units : INT64_MAX;
     };
     const Tile bestt =
         confirm_best(c->stream, cands, [&](const Tile &t) { return launch_tile(c, a, path, t); }, units, &bestms);
@@ -917,7 +938,6 @@ dwt_fuse_status ensure_batch_tables(dwt_fuse_ctx *c, size_t n) {
 // one-shot (1 or 2 rows) wavefront units; 3 = flat grid, one workgroup per
 // work item (LDS-staged D4 tiles, one-shot wavefronts otherwise).
 constexpr int kFlatBatch = 3;
-constexpr int kDefaultBatchMode = kFlatBatch;
 
 struct BatchPlan {
     std::vector<BatchScene> sc;
@@ -926,17 +946,21 @@ struct BatchPlan {
     int mode = 0;
     int total = 0;          // work items (flat) or wavefront units (persistent)
     int staged_bands = 0;   // flat: largest band count among staged scenes
-    int flat_order = 1;     // flat: unit order of the items (bit 0 row-band-major, bit 1 no XCD remap)
+    int flat_order = 3;     // flat: unit order of the items (bit 0 row-band-major, bit 1 dispatch order)
+    int flat_bg = 0;        // flat: bands staged at once by an LDS-staged tile (0 = all)
     std::string sig;  // batch signature (graph cache key), includes the variant and grid
 };
 
 // Per-scene tiles (tuned per size class with the per-image kernel when tuning
 // is on), forced to the batch's variant `mode`, then 8 contiguous queues of
 // about equal bytes.
-dwt_fuse_status plan_batch(dwt_fuse_ctx *ctx, const dwt_fuse_item *items, int64_t n, int mode, BatchPlan *pl) {
+dwt_fuse_status plan_batch(dwt_fuse_ctx *ctx, const dwt_fuse_item *items, int64_t n, const BatchChoice &ch,
+                           BatchPlan *pl) {
+    const int mode = ch.mode;
     pl->sc.assign((size_t)n, BatchScene{});
     pl->mode = mode;
-    pl->flat_order = ctx->forced.order >= 0 ? ctx->forced.order : 3;
+    pl->flat_order = ctx->forced.order >= 0 ? ctx->forced.order : ch.order;
+    pl->flat_bg = ch.bg;
     pl->staged_bands = 0;
     pl->sig.clear();
     pl->sig.reserve((size_t)n * 48);
@@ -965,7 +989,8 @@ dwt_fuse_status plan_batch(dwt_fuse_ctx *ctx, const dwt_fuse_item *items, int64_
                 t.mode = 1;
                 t.seg_rows = 1;
             }
-            if (!decompose(a.H, a.W, t, &d)) return fail(ctx, DWT_FUSE_E_SHAPE, "too many work units");
+            if (!decompose(a.H, a.W, t, &d, overlap_strips(a, path, ctx->forced.ovl)))
+                return fail(ctx, DWT_FUSE_E_SHAPE, "too many work units");
             items_of_scene = t.mode >= 3 ? d.units : (d.units + 3) / 4;
         } else {
             t = tile_for_run(ctx, a, path, true);
@@ -974,7 +999,8 @@ dwt_fuse_status plan_batch(dwt_fuse_ctx *ctx, const dwt_fuse_item *items, int64_
             } else if (t.mode > 0) {  // one-shot or staged per-image tiles: rolling here
                 t = rolling_tile(a.H, a.W, path_nc(path));
             }
-            if (!decompose(a.H, a.W, t, &d)) return fail(ctx, DWT_FUSE_E_SHAPE, "too many work units");
+            if (!decompose(a.H, a.W, t, &d, overlap_strips(a, path, ctx->forced.ovl)))
+                return fail(ctx, DWT_FUSE_E_SHAPE, "too many work units");
             items_of_scene = d.units;
         }
         BatchScene &b = pl->sc[(size_t)i];
@@ -996,7 +1022,7 @@ dwt_fuse_status plan_batch(dwt_fuse_ctx *ctx, const dwt_fuse_item *items, int64_
     if (mode == kFlatBatch) {
         pl->grid = (int)total;
         char gb[64];
-        std::snprintf(gb, sizeof(gb), "#flat#%d#o%d", pl->staged_bands, pl->flat_order);
+        std::snprintf(gb, sizeof(gb), "#flat#%d#o%d#g%d", pl->staged_bands, pl->flat_order, pl->flat_bg);
         pl->sig += gb;
         return DWT_FUSE_OK;
     }
@@ -1049,7 +1075,9 @@ dwt_fuse_status stage_batch(dwt_fuse_ctx *ctx, const BatchPlan &pl) {
 hipError_t launch_plan(dwt_fuse_ctx *ctx, const BatchPlan &pl, hipStream_t s) {
     const int n = (int)pl.sc.size();
     if (pl.mode == kFlatBatch)
-        return launch_fuse_batched_flat(ctx->d_scenes, n, pl.total, pl.staged_bands, pl.flat_order, ctx->filt, s);
+        return launch_fuse_batched_flat(ctx->d_scenes, n, pl.total,
+                                        pl.flat_bg > 0 ? std::min(pl.flat_bg, pl.staged_bands) : pl.staged_bands,
+                                        pl.flat_order, ctx->filt, s);
     return launch_fuse_batched(ctx->d_scenes, n, pl.q, ctx->d_counters, pl.grid, pl.mode, ctx->filt, s);
 }
 
@@ -1136,6 +1164,10 @@ dwt_fuse_status dwt_fuse_create(dwt_fuse_ctx **ctx, int device, void *hip_stream
                 c->forced.nc = d;
                 c->forced.variant = v;
             }
+        }
+        if (const char *f = std::getenv("DWT_FUSE_FORCE_OVERLAP")) {
+            const int o = std::atoi(f);
+            if (o >= 0 && o <= 1) c->forced.ovl = o;
         }
         if (const char *f = std::getenv("DWT_FUSE_FORCE_ORDER")) {
             const int o = std::atoi(f);
@@ -1298,7 +1330,7 @@ dwt_fuse_status run_float(dwt_fuse_ctx *ctx, const RunArgs &a, float kappa) {
         const Path path = choose_path(a);
         const Tile t = tile_for_run(ctx, a, path, true);
         Decomp d;
-        if (!decompose(a.H, a.W, t, &d) || !split_fits(t, d, a.B))
+        if (!decompose(a.H, a.W, t, &d, overlap_strips(a, path, ctx->forced.ovl)) || !split_fits(t, d, a.B))
             return fail(ctx, DWT_FUSE_E_SHAPE, "too many work units");
         FuseParams p = make_params(a, path_for_nc(path, t.nc), t, d);
         p.kappa = kappa;
@@ -1671,40 +1703,49 @@ dwt_fuse_status dwt_fuse_run_batched(dwt_fuse_ctx *ctx, const dwt_fuse_item *ite
         if ((st = ensure_batch_tables(ctx, (size_t)n))) return st;
 
         BatchPlan plan;
-        int mode = 0;
+        BatchChoice ch;
         if (ctx->forced.variant == 1) {
-            mode = 0;
+            ch.mode = 0;
         } else if (ctx->forced.variant == 2) {
-            mode = std::min(2, std::max(1, ctx->forced.seg_rows > 0 ? ctx->forced.seg_rows : 2));
+            ch.mode = std::min(2, std::max(1, ctx->forced.seg_rows > 0 ? ctx->forced.seg_rows : 2));
         } else if (ctx->forced.variant == 3) {
-            mode = kFlatBatch;
+            ch.mode = kFlatBatch;
         } else {
-            // The variant is chosen per batch signature (sizes, bands, wavelets,
-            // pitches); with tuning on, each variant is timed once on the batch.
-            if ((st = plan_batch(ctx, items, n, kDefaultBatchMode, &plan))) return st;
+            // The form is chosen per batch signature (sizes, bands, wavelets,
+            // pitches); with tuning on, each candidate is timed once on the
+            // batch: the flat grid in dispatch order or per-XCD runs, with
+            // its staged tiles holding every band, 3 or 2 bands at once (less
+            // LDS per workgroup: more of the batch's one-shot Haar items
+            // resident per CU), and the persistent queue kernels.
+            if ((st = plan_batch(ctx, items, n, BatchChoice{}, &plan))) return st;
             auto it = ctx->batch_modes.find(plan.sig);
             if (it != ctx->batch_modes.end()) {
-                mode = it->second;
+                ch = it->second;
             } else if (ctx->tuning) {
+                std::vector<BatchChoice> cands;
+                for (int order : {3, 1})
+                    for (int bg : {0, 3, 2}) cands.push_back(BatchChoice{kFlatBatch, order, bg});
+                for (int m : {0, 1, 2}) cands.push_back(BatchChoice{m, 1, 0});
                 float best = 1e30f;
-                for (int m : {kFlatBatch, 0, 1, 2}) {
+                for (const BatchChoice &c : cands) {
                     BatchPlan pm;
-                    if ((st = plan_batch(ctx, items, n, m, &pm))) return st;
+                    if ((st = plan_batch(ctx, items, n, c, &pm))) return st;
                     const float ms = time_batch(ctx, pm);
+                    if (std::getenv("DWT_FUSE_LOG"))
+                        std::fprintf(stderr, "[dwt_fuse]   batch candidate mode=%d order=%d bg=%d: %.3f ms\n", c.mode,
+                                     c.order, c.bg, ms);
                     if (ms < best) {
                         best = ms;
-                        mode = m;
+                        ch = c;
                     }
                 }
-                ctx->batch_modes[plan.sig] = mode;
+                ctx->batch_modes[plan.sig] = ch;
                 if (std::getenv("DWT_FUSE_LOG"))
-                    std::fprintf(stderr, "[dwt_fuse] tuned batch of %lld scenes: mode=%d (%.3f ms)\n", (long long)n,
-                                 mode, best);
-            } else {
-                mode = kDefaultBatchMode;
+                    std::fprintf(stderr, "[dwt_fuse] tuned batch of %lld scenes: mode=%d order=%d bg=%d (%.3f ms)\n",
+                                 (long long)n, ch.mode, ch.order, ch.bg, best);
             }
         }
-        if ((st = plan_batch(ctx, items, n, mode, &plan))) return st;
+        if ((st = plan_batch(ctx, items, n, ch, &plan))) return st;
         if ((st = stage_batch(ctx, plan))) return st;
 
         hipError_t e;

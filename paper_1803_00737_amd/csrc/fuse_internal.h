@@ -46,8 +46,31 @@ struct FuseParams {
     float kappa;       // LL <- kappa * MS band (1 = as printed)
     int32_t bsplit;    // LDS-staged D4: bands per unit (0 = every band in one unit); units
                        // are then (tile, band group) with the groups of a tile adjacent
-    int32_t pad_;
+    int32_t ovl;       // 1: overlapped strips (see strip_origin); 0: strips side by side
 };
+
+// Column strips of a launch.  Side by side (ovl 0), strip k's wavefront
+// computes and stores coefficient columns [64 NC k, 64 NC (k+1)).  With output
+// rows that do not start on a 64-byte boundary, such strips split a 64-byte
+// line of every row between two wavefronts that write their parts at
+// different times, which HBM absorbs as slower partial writes.  Overlapped
+// strips (ovl 1) advance by S = 64 NC - 8 coefficient columns (2S = 128 NC -
+// 16 output pixels, a multiple of 64 bytes); strip k computes the 64 NC
+// columns from k S - 8 on, and stores, of every output row, the pixels
+// [2 S k - phi, 2 S (k+1) - phi) inside the image, where phi (< 16, even on
+// 8-byte aligned rows) is the row's start address in floats modulo 16, so
+// every stored run starts on a 64-byte boundary and covers whole lines.  The
+// overlap recomputes 16 pixels per strip; the results do not change (each
+// pixel is evaluated by the same arithmetic wherever it is computed).
+__host__ __device__ inline int strip_stride_cols(int nc, int ovl) { return ovl ? 64 * nc - 8 : 64 * nc; }
+// First coefficient column computed by strip k.
+__host__ __device__ inline int strip_origin(int k, int nc, int ovl) {
+    return ovl ? k * (64 * nc - 8) - 8 : k * 64 * nc;
+}
+// Number of strips for W output columns.
+__host__ __device__ inline int64_t strip_count(int64_t W, int nc, int ovl) {
+    return ovl ? (W + 14 + 2 * (64 * nc - 8) - 1) / (2 * (64 * nc - 8)) : (W / 2 + 64 * nc - 1) / (64 * nc);
+}
 
 // Daubechies-4 low-pass taps (Eq. 7-8), rounded once from double.
 struct Filters {

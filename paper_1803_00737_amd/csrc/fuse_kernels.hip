@@ -77,19 +77,32 @@ __device__ __forceinline__ void st4(float *p, f4 v) {
 // on the MS rows that are 8-byte aligned.  2*s0 is a multiple of 4 when
 // NC = 2, so the alignment of a lane's group is that of its row (the same
 // for the whole wavefront).
+// Pixels [a, e) of the output row starting at orow that a strip stores: the
+// strip's run [lo, lo + span) in a row starting on a 64-byte boundary,
+// shifted left by the row's misalignment with overlapped strips (see
+// strip_origin), and clipped to the image.
+__device__ __forceinline__ void stored_span(const float *orow, int lo, int span, int W, int ovl, int &a, int &e) {
+    const int phi = ovl ? (int)((reinterpret_cast<uintptr_t>(orow) >> 2) & 15) : 0;
+    a = max(lo - phi, 0);
+    e = min(lo - phi + span, W);
+}
+
 template <int NC, int AL>
 struct LaneCols {
     int s0, W2;
     bool full;  // all NC own columns inside the image (vector access allowed)
+    int ovl;    // overlapped strips
+    int lo;     // first pixel of the strip's stored run in a row starting on a 64-byte boundary
     int pc[NC + 2];
 
-    __device__ __forceinline__ LaneCols(int strip, int lane, int W2_) : W2(W2_) {
-        s0 = (strip * 64 + lane) * NC;
-        full = (s0 + NC) <= W2;
+    __device__ __forceinline__ LaneCols(int strip, int lane, int W2_, int ovl_) : W2(W2_), ovl(ovl_) {
+        s0 = strip_origin(strip, NC, ovl_) + NC * lane;
+        lo = 2 * strip * strip_stride_cols(NC, ovl_);
+        full = s0 >= 0 && (s0 + NC) <= W2;
 #pragma unroll
         for (int k = 0; k < NC + 2; ++k) pc[k] = wrap_idx(s0 - 1 + k, W2);
     }
-    __device__ __forceinline__ bool active() const { return s0 < W2; }
+    __device__ __forceinline__ bool active() const { return s0 < W2 && s0 + NC > 0; }
 
     static __device__ __forceinline__ bool wide(const float *row) {
         return AL == 1 || (AL == 2 && (reinterpret_cast<uintptr_t>(row) & 15) == 0);
@@ -156,20 +169,24 @@ struct LaneCols {
 #pragma unroll
         for (int i = 0; i < NC; ++i) m[i] = mrow[pc[i + 1]];
     }
+    // orow: the start of the output row.
     __device__ __forceinline__ void store_row(float *orow, const f2 (&q)[NC]) const {
+        int a, e;
+        stored_span(orow, lo, 2 * strip_stride_cols(NC, ovl), 2 * W2, ovl, a, e);
+        bool in[NC];
+#pragma unroll
+        for (int i = 0; i < NC; ++i) in[i] = 2 * (s0 + i) >= a && 2 * (s0 + i) < e;
         if constexpr (NC == 2 && AL) {
-            if (!full) {
-                st2<AL>(orow + 2 * s0, q[0]);  // s0 + 1 == W2: one pair left
-            } else if (wide(orow)) {
+            if (in[0] && in[1] && wide(orow)) {
                 st4(orow + 2 * s0, f4{q[0].x, q[0].y, q[1].x, q[1].y});
             } else {
-                st2<AL>(orow + 2 * s0, q[0]);
-                st2<AL>(orow + 2 * s0 + 2, q[1]);
+                if (in[0]) st2<AL>(orow + 2 * s0, q[0]);
+                if (in[1]) st2<AL>(orow + 2 * s0 + 2, q[1]);
             }
         } else {
 #pragma unroll
             for (int i = 0; i < NC; ++i)
-                if (s0 + i < W2) st2<AL>(orow + 2 * (s0 + i), q[i]);
+                if (in[i]) st2<AL>(orow + 2 * (s0 + i), q[i]);
         }
     }
 };
@@ -178,7 +195,7 @@ struct LaneCols {
 
 template <int NC, int AL>
 __device__ __forceinline__ void d4_rolling(const FuseParams &p, const Filters &f, int strip, int seg, int lane) {
-    const LaneCols<NC, AL> L(strip, lane, p.W >> 1);
+    const LaneCols<NC, AL> L(strip, lane, p.W >> 1, p.ovl);
     if (!L.active()) return;
     const int H2 = p.H >> 1;
     const int rb = seg * p.seg_rows;
@@ -241,7 +258,7 @@ __device__ __forceinline__ void d4_rolling(const FuseParams &p, const Filters &f
 
 template <int NC, int AL, int KR>
 __device__ __forceinline__ void d4_tile(const FuseParams &p, const Filters &f, int strip, int seg, int lane) {
-    const LaneCols<NC, AL> L(strip, lane, p.W >> 1);
+    const LaneCols<NC, AL> L(strip, lane, p.W >> 1, p.ovl);
     if (!L.active()) return;
     const int H2 = p.H >> 1;
     const int rb = seg * KR;
@@ -295,7 +312,7 @@ __device__ __forceinline__ void d4_tile(const FuseParams &p, const Filters &f, i
 
 template <int NC, int AL>
 __device__ __forceinline__ void haar_rolling(const FuseParams &p, int strip, int seg, int lane) {
-    const LaneCols<NC, AL> L(strip, lane, p.W >> 1);
+    const LaneCols<NC, AL> L(strip, lane, p.W >> 1, p.ovl);
     if (!L.active()) return;
     const int H2 = p.H >> 1;
     const int rb = seg * p.seg_rows;
@@ -321,7 +338,7 @@ __device__ __forceinline__ void haar_rolling(const FuseParams &p, int strip, int
 
 template <int NC, int AL, int KR>
 __device__ __forceinline__ void haar_tile(const FuseParams &p, int strip, int seg, int lane) {
-    const LaneCols<NC, AL> L(strip, lane, p.W >> 1);
+    const LaneCols<NC, AL> L(strip, lane, p.W >> 1, p.ovl);
     if (!L.active()) return;
     const int H2 = p.H >> 1;
     const int rb = seg * KR;
@@ -433,6 +450,23 @@ __host__ __device__ constexpr int staged_lds_floats(int T, int bg) {
     return (2 * T + 4) * kStagedPanRow + bg * (T + 1) * kStagedMsRow;
 }
 
+// The two pixel pairs of coefficient columns s0, s0+1 of the output row
+// starting at orow, as far as this strip stores them (stored_span).
+template <int LAY>
+__device__ __forceinline__ void staged_store(float *orow, int s0, int lo, int span, int W, int ovl, const f2 (&q)[2]) {
+    int a, e;
+    stored_span(orow, lo, span, W, ovl, a, e);
+    const int x = 2 * s0;
+    const bool i0 = x >= a && x < e, i1 = x + 2 >= a && x + 2 < e;
+    float *o = orow + x;
+    if (i0 && i1 && (LAY == 0 || (reinterpret_cast<uintptr_t>(o) & 15) == 0)) {
+        st4(o, f4{q[0].x, q[0].y, q[1].x, q[1].y});
+    } else {
+        if (i0) st2<true>(o, q[0]);
+        if (i1) st2<true>(o + 2, q[1]);
+    }
+}
+
 // One staged tile (`unit` of p) by the whole workgroup; every wavefront must
 // call it (it contains barriers).  LAY follows the row alignment: 0 = 16-byte
 // rows (PAN staged with 16-byte loads; a lane owns 2 adjacent coefficient
@@ -452,7 +486,8 @@ __device__ __forceinline__ void d4_staged_tile(const FuseParams &p, const Filter
     int strip, trow;
     unit_coords(unit, p.nstrips, p.nseg, p.order, strip, trow);
     const int W2 = p.W >> 1, H2 = p.H >> 1;
-    const int sb = strip * 128;  // first coefficient column of the strip
+    const int sb = strip_origin(strip, 2, p.ovl);  // first coefficient column of the strip
+    const int lo = 2 * strip * strip_stride_cols(2, p.ovl), span = 2 * strip_stride_cols(2, p.ovl);
     const int r0 = trow * T;
     float *Pl = lds;
     float *Ml = lds + (2 * T + 4) * kStagedPanRow;
@@ -472,7 +507,7 @@ __device__ __forceinline__ void d4_staged_tile(const FuseParams &p, const Filter
     // lie inside the row.
     const bool fast = LAY == 3 && sb >= 128 && 2 * sb + 258 <= p.W;
     // 16-byte rows: every group of the strip is 16-byte aligned in the row.
-    const bool groups16 = LAY == 0 && ((p.W & 3) == 0 || 2 * sb + 256 <= p.W);
+    const bool groups16 = LAY == 0 && ((p.W & 3) == 0 || (sb >= 0 && 2 * sb + 256 <= p.W));
     for (int k = w; k < 2 * T + 4; k += wpb) {
         const float *row = p.pan + (int64_t)wrap_idx(2 * r0 - 2 + k, p.H) * p.pan_ld;
         float *dst = Pl + k * kStagedPanRow;
@@ -574,7 +609,7 @@ __device__ __forceinline__ void d4_staged_tile(const FuseParams &p, const Filter
             float *ob = p.out + (int64_t)b * p.out_bs;
 #pragma unroll
             for (int h = 0; h < NH; ++h) {
-                if (s0[h] >= W2) continue;
+                if (s0[h] >= W2 || s0[h] + NC <= 0) continue;
                 float m[KR + 1][NC + 1];
 #pragma unroll
                 for (int i = 0; i <= KR; ++i) {
@@ -594,36 +629,15 @@ __device__ __forceinline__ void d4_staged_tile(const FuseParams &p, const Filter
                     }
                     f2 q0[NC], q1[NC];
                     d4_out_rows<NC>(f, g, p.kappa, m[i + 1], m[i], A[h][i + 1], A[h][i], xa, xb, q0, q1);
-                    float *o0 = ob + (int64_t)(2 * (rb + i)) * p.out_ld + 2 * s0[h];
-                    if constexpr (LAY == 0) {
-                        if (s0[h] + 2 <= W2) {
-                            st4(o0, f4{q0[0].x, q0[0].y, q0[1].x, q0[1].y});
-                            st4(o0 + p.out_ld, f4{q1[0].x, q1[0].y, q1[1].x, q1[1].y});
-                        } else {
-                            st2<true>(o0, q0[0]);
-                            st2<true>(o0 + p.out_ld, q1[0]);
-                        }
-                    } else if constexpr (LAY == 3) {
-                        // 8-byte rows: 16-byte stores on rows that are 16-byte aligned here
-                        float *o1 = o0 + p.out_ld;
-                        if (s0[h] + 2 <= W2) {
-                            if ((reinterpret_cast<uintptr_t>(o0) & 15) == 0) {
-                                st4(o0, f4{q0[0].x, q0[0].y, q0[1].x, q0[1].y});
-                            } else {
-                                st2<true>(o0, q0[0]);
-                                st2<true>(o0 + 2, q0[1]);
-                            }
-                            if ((reinterpret_cast<uintptr_t>(o1) & 15) == 0) {
-                                st4(o1, f4{q1[0].x, q1[0].y, q1[1].x, q1[1].y});
-                            } else {
-                                st2<true>(o1, q1[0]);
-                                st2<true>(o1 + 2, q1[1]);
-                            }
-                        } else {
-                            st2<true>(o0, q0[0]);
-                            st2<true>(o1, q1[0]);
-                        }
+                    float *r0 = ob + (int64_t)(2 * (rb + i)) * p.out_ld;  // output rows 2(rb+i), +1
+                    if constexpr (LAY == 0 || LAY == 3) {
+                        // 16-byte stores where both pairs are stored and the
+                        // address is 16-byte aligned (every row on 16-byte rows,
+                        // every other one on 8-byte rows), 8-byte ones elsewhere
+                        staged_store<LAY>(r0, s0[h], lo, span, p.W, p.ovl, q0);
+                        staged_store<LAY>(r0 + p.out_ld, s0[h], lo, span, p.W, p.ovl, q1);
                     } else {
+                        float *o0 = r0 + 2 * s0[h];
                         st2<false>(o0, q0[0]);  // 4-byte rows
                         st2<false>(o0 + p.out_ld, q1[0]);
                     }
@@ -735,7 +749,8 @@ hipError_t launch_fuse(const FuseParams &p, const Filters &f, int wpb, hipStream
     if (p.units <= 0) return hipSuccess;
     if (p.mode >= 3) {  // LDS-staged: one workgroup per unit, KR = mode - 2 rows per wavefront
         const int kr = p.mode - 2;
-        if (p.wavelet != 1 || p.seg_rows != wpb * kr || p.nstrips != (p.W / 2 + 127) / 128)
+        if (p.wavelet != 1 || p.seg_rows != wpb * kr || p.nstrips != strip_count(p.W, 2, p.ovl) ||
+            (p.ovl && p.path == PATH_SCALAR))
             return hipErrorInvalidValue;
         const int bgm = staged_bg_max(p.seg_rows);
         if (bgm < 1 || p.bsplit < 0) return hipErrorInvalidValue;
