@@ -554,7 +554,9 @@ Filters make_filters() {
 struct BatchChoice {
     int mode = 3;
     int order = 3;
-    int bg = 0;
+    int bg = 2;
+    int staged = 1;  // flat: D4 scenes as LDS-staged tiles (else one-shot single-row wavefronts)
+    int kr = 2;      // flat: coefficient rows per wavefront of a staged tile (1 or 2; 4 wavefronts)
 };
 
 struct dwt_fuse_ctx {
@@ -948,6 +950,7 @@ struct BatchPlan {
     int staged_bands = 0;   // flat: largest band count among staged scenes
     int flat_order = 3;     // flat: unit order of the items (bit 0 row-band-major, bit 1 dispatch order)
     int flat_bg = 0;        // flat: bands staged at once by an LDS-staged tile (0 = all)
+    int flat_kr = 2;        // flat: coefficient rows per wavefront of a staged tile
     std::string sig;  // batch signature (graph cache key), includes the variant and grid
 };
 
@@ -961,6 +964,7 @@ dwt_fuse_status plan_batch(dwt_fuse_ctx *ctx, const dwt_fuse_item *items, int64_
     pl->mode = mode;
     pl->flat_order = ctx->forced.order >= 0 ? ctx->forced.order : ch.order;
     pl->flat_bg = ch.bg;
+    pl->flat_kr = ch.kr == 1 ? 1 : 2;
     pl->staged_bands = 0;
     pl->sig.clear();
     pl->sig.reserve((size_t)n * 48);
@@ -979,10 +983,10 @@ dwt_fuse_status plan_batch(dwt_fuse_ctx *ctx, const dwt_fuse_item *items, int64_
             // wavefronts win per image: the launch reserves the staged
             // tiles' LDS for every workgroup, and one-shot items at that
             // occupancy measured slower than staged ones.
-            if (staged_allowed(a.wavelet, path, 2)) {
+            if (ch.staged && staged_allowed(a.wavelet, path, 2)) {
                 t.nc = 2;
-                t.mode = 4;  // staged, 2 rows per wavefront, 4 wavefronts
-                t.seg_rows = 2;
+                t.mode = 2 + pl->flat_kr;  // staged, 1 or 2 rows per wavefront, 4 wavefronts
+                t.seg_rows = pl->flat_kr;
                 pl->staged_bands = std::max<int>(pl->staged_bands, (int)a.B);
             } else {
                 t.nc = path_nc(path);
@@ -1022,7 +1026,8 @@ dwt_fuse_status plan_batch(dwt_fuse_ctx *ctx, const dwt_fuse_item *items, int64_
     if (mode == kFlatBatch) {
         pl->grid = (int)total;
         char gb[64];
-        std::snprintf(gb, sizeof(gb), "#flat#%d#o%d#g%d", pl->staged_bands, pl->flat_order, pl->flat_bg);
+        std::snprintf(gb, sizeof(gb), "#flat#%d#o%d#g%d#s%d#k%d", pl->staged_bands, pl->flat_order, pl->flat_bg,
+                      ch.staged, pl->flat_kr);
         pl->sig += gb;
         return DWT_FUSE_OK;
     }
@@ -1077,7 +1082,7 @@ hipError_t launch_plan(dwt_fuse_ctx *ctx, const BatchPlan &pl, hipStream_t s) {
     if (pl.mode == kFlatBatch)
         return launch_fuse_batched_flat(ctx->d_scenes, n, pl.total,
                                         pl.flat_bg > 0 ? std::min(pl.flat_bg, pl.staged_bands) : pl.staged_bands,
-                                        pl.flat_order, ctx->filt, s);
+                                        pl.flat_kr, pl.flat_order, ctx->filt, s);
     return launch_fuse_batched(ctx->d_scenes, n, pl.q, ctx->d_counters, pl.grid, pl.mode, ctx->filt, s);
 }
 
@@ -1709,7 +1714,11 @@ dwt_fuse_status dwt_fuse_run_batched(dwt_fuse_ctx *ctx, const dwt_fuse_item *ite
         } else if (ctx->forced.variant == 2) {
             ch.mode = std::min(2, std::max(1, ctx->forced.seg_rows > 0 ? ctx->forced.seg_rows : 2));
         } else if (ctx->forced.variant == 3) {
+            // forced flat grid: seg_rows = rows per wavefront of its staged
+            // tiles (1 or 2), band split = bands they stage at once (0 = all)
             ch.mode = kFlatBatch;
+            ch.kr = ctx->forced.seg_rows == 1 ? 1 : 2;
+            ch.bg = ctx->forced.split;
         } else {
             // The form is chosen per batch signature (sizes, bands, wavelets,
             // pitches); with tuning on, each candidate is timed once on the
@@ -1723,17 +1732,20 @@ dwt_fuse_status dwt_fuse_run_batched(dwt_fuse_ctx *ctx, const dwt_fuse_item *ite
                 ch = it->second;
             } else if (ctx->tuning) {
                 std::vector<BatchChoice> cands;
-                for (int order : {3, 1})
-                    for (int bg : {0, 3, 2}) cands.push_back(BatchChoice{kFlatBatch, order, bg});
-                for (int m : {0, 1, 2}) cands.push_back(BatchChoice{m, 1, 0});
+                for (int kr : {2, 1})
+                    for (int bg : {2, 0, 3, 1}) cands.push_back(BatchChoice{kFlatBatch, 3, bg, 1, kr});
+                cands.push_back(BatchChoice{kFlatBatch, 1, 2, 1, 2});
+                cands.push_back(BatchChoice{kFlatBatch, 3, 0, 0, 2});
+                for (int m : {0, 1, 2}) cands.push_back(BatchChoice{m, 1, 0, 1, 2});
                 float best = 1e30f;
                 for (const BatchChoice &c : cands) {
                     BatchPlan pm;
                     if ((st = plan_batch(ctx, items, n, c, &pm))) return st;
                     const float ms = time_batch(ctx, pm);
                     if (std::getenv("DWT_FUSE_LOG"))
-                        std::fprintf(stderr, "[dwt_fuse]   batch candidate mode=%d order=%d bg=%d: %.3f ms\n", c.mode,
-                                     c.order, c.bg, ms);
+                        std::fprintf(stderr,
+                                     "[dwt_fuse]   batch candidate mode=%d order=%d bg=%d staged=%d kr=%d: %.3f ms\n",
+                                     c.mode, c.order, c.bg, c.staged, c.kr, ms);
                     if (ms < best) {
                         best = ms;
                         ch = c;

@@ -126,8 +126,8 @@ int batched_blocks_per_cu(int mode);
 // tiles of 8 coefficient rows (4 wavefronts x 2 rows, band groups of at most
 // `staged_bands`); all others are one-shot single-row wavefront units, 4 per
 // item.
-hipError_t launch_fuse_batched_flat(const BatchScene *d_scenes, int nscenes, int total, int staged_bands, int order,
-                                    const Filters &f, hipStream_t s);
+hipError_t launch_fuse_batched_flat(const BatchScene *d_scenes, int nscenes, int total, int staged_bands,
+                                    int staged_rows, int order, const Filters &f, hipStream_t s);
 
 // Largest band group a staged tile of T coefficient rows can hold in 64 KB of LDS.
 int staged_bg_max(int T);

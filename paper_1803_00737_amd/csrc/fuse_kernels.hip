@@ -87,6 +87,31 @@ __device__ __forceinline__ void stored_span(const float *orow, int lo, int span,
     e = min(lo - phi + span, W);
 }
 
+// Lane l receives lane l+1's value (lane 63 gets 0): DPP wave shift left.
+__device__ __forceinline__ float from_next_lane(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, false));
+}
+
+// The pixel pairs q[0] (pixels x0, x0+1) and q[1] (x0+2, x0+3) of each lane
+// (x0 = 2 s0, a multiple of 4 apart from lane to lane) on an output row that
+// starts 8 bytes past a 16-byte boundary, as far as the strip stores them
+// ([a, e)): each lane writes its second pair and its right neighbour's first
+// pair with one 16-byte store (aligned there); a first pair that its left
+// neighbour does not write that way is written alone.  Every active lane of
+// the wavefront must call it (cross-lane move).
+__device__ __forceinline__ void store_pairs_shifted(float *orow, int x0, int a, int e, int lane, const f2 (&q)[2]) {
+    const float nx = from_next_lane(q[0].x), ny = from_next_lane(q[0].y);
+    const bool in0 = x0 >= a && x0 < e, in1 = x0 + 2 >= a && x0 + 2 < e;
+    const bool in2 = lane < 63 && x0 + 4 >= a && x0 + 4 < e;   // the right neighbour's first pair
+    const bool left = lane > 0 && x0 - 2 >= a && x0 - 2 < e;    // the left neighbour writes pair x0
+    if (in1 && in2) {
+        st4(orow + x0 + 2, f4{q[1].x, q[1].y, nx, ny});
+    } else if (in1) {
+        st2<true>(orow + x0 + 2, q[1]);
+    }
+    if (in0 && !left) st2<true>(orow + x0, q[0]);
+}
+
 template <int NC, int AL>
 struct LaneCols {
     int s0, W2;
@@ -169,10 +194,18 @@ struct LaneCols {
 #pragma unroll
         for (int i = 0; i < NC; ++i) m[i] = mrow[pc[i + 1]];
     }
-    // orow: the start of the output row.
-    __device__ __forceinline__ void store_row(float *orow, const f2 (&q)[NC]) const {
+    // orow: the start of the output row.  lane: the lane's index (AL 2:
+    // rows 8 bytes off a 16-byte boundary are written with 16-byte stores
+    // of pairs shifted by one, store_pairs_shifted).
+    __device__ __forceinline__ void store_row(float *orow, const f2 (&q)[NC], int lane) const {
         int a, e;
         stored_span(orow, lo, 2 * strip_stride_cols(NC, ovl), 2 * W2, ovl, a, e);
+        if constexpr (NC == 2 && AL == 2) {
+            if (!wide(orow)) {
+                store_pairs_shifted(orow, 2 * s0, a, e, lane, q);
+                return;
+            }
+        }
         bool in[NC];
 #pragma unroll
         for (int i = 0; i < NC; ++i) in[i] = 2 * (s0 + i) >= a && 2 * (s0 + i) < e;
@@ -237,8 +270,8 @@ __device__ __forceinline__ void d4_rolling(const FuseParams &p, const Filters &f
             f2 q0[NC], q1[NC];
             d4_out_rows<NC>(f, g, p.kappa, mc, mp, A, Ap, xa, xb, q0, q1);
             float *o0 = p.out + (int64_t)b * p.out_bs + (int64_t)(2 * r) * p.out_ld;
-            L.store_row(o0, q0);
-            L.store_row(o0 + p.out_ld, q1);
+            L.store_row(o0, q0, lane);
+            L.store_row(o0 + p.out_ld, q1, lane);
         }
 #pragma unroll
         for (int j = 0; j <= NC; ++j) {
@@ -296,8 +329,8 @@ __device__ __forceinline__ void d4_tile(const FuseParams &p, const Filters &f, i
             f2 q0[NC], q1[NC];
             d4_out_rows<NC>(f, g, p.kappa, m[i + 1], m[i], A[i + 1], A[i], x[2 * i + 2], x[2 * i + 3], q0, q1);
             float *o0 = ob + (int64_t)(2 * (rb + i)) * p.out_ld;
-            L.store_row(o0, q0);
-            L.store_row(o0 + p.out_ld, q1);
+            L.store_row(o0, q0, lane);
+            L.store_row(o0 + p.out_ld, q1, lane);
         }
         if (b + 1 < p.B) {
 #pragma unroll
@@ -330,8 +363,8 @@ __device__ __forceinline__ void haar_rolling(const FuseParams &p, int strip, int
             f2 q0[NC], q1[NC];
             haar_out_rows<NC>(g, p.kappa, m, da, dc, q0, q1);
             float *o0 = p.out + (int64_t)b * p.out_bs + (int64_t)(2 * r) * p.out_ld;
-            L.store_row(o0, q0);
-            L.store_row(o0 + p.out_ld, q1);
+            L.store_row(o0, q0, lane);
+            L.store_row(o0 + p.out_ld, q1, lane);
         }
     }
 }
@@ -378,8 +411,8 @@ __device__ __forceinline__ void haar_tile(const FuseParams &p, int strip, int se
                 f2 q0[NC], q1[NC];
                 haar_out_rows<NC>(g, p.kappa, mall[b][i], da[i], dc[i], q0, q1);
                 float *o0 = ob + (int64_t)(2 * (rb + i)) * p.out_ld;
-                L.store_row(o0, q0);
-                L.store_row(o0 + p.out_ld, q1);
+                L.store_row(o0, q0, lane);
+                L.store_row(o0 + p.out_ld, q1, lane);
             }
         }
         return;
@@ -399,8 +432,8 @@ __device__ __forceinline__ void haar_tile(const FuseParams &p, int strip, int se
             f2 q0[NC], q1[NC];
             haar_out_rows<NC>(g, p.kappa, m[i], da[i], dc[i], q0, q1);
             float *o0 = ob + (int64_t)(2 * (rb + i)) * p.out_ld;
-            L.store_row(o0, q0);
-            L.store_row(o0 + p.out_ld, q1);
+            L.store_row(o0, q0, lane);
+            L.store_row(o0 + p.out_ld, q1, lane);
         }
         if (b + 1 < p.B) {
 #pragma unroll
@@ -453,10 +486,15 @@ __host__ __device__ constexpr int staged_lds_floats(int T, int bg) {
 // The two pixel pairs of coefficient columns s0, s0+1 of the output row
 // starting at orow, as far as this strip stores them (stored_span).
 template <int LAY>
-__device__ __forceinline__ void staged_store(float *orow, int s0, int lo, int span, int W, int ovl, const f2 (&q)[2]) {
+__device__ __forceinline__ void staged_store(float *orow, int s0, int lo, int span, int W, int ovl, int lane,
+                                             const f2 (&q)[2]) {
     int a, e;
     stored_span(orow, lo, span, W, ovl, a, e);
     const int x = 2 * s0;
+    if (LAY == 3 && (reinterpret_cast<uintptr_t>(orow) & 15) != 0) {  // 8-byte rows, this one 8 bytes off
+        store_pairs_shifted(orow, x, a, e, lane, q);
+        return;
+    }
     const bool i0 = x >= a && x < e, i1 = x + 2 >= a && x + 2 < e;
     float *o = orow + x;
     if (i0 && i1 && (LAY == 0 || (reinterpret_cast<uintptr_t>(o) & 15) == 0)) {
@@ -634,8 +672,8 @@ __device__ __forceinline__ void d4_staged_tile(const FuseParams &p, const Filter
                         // 16-byte stores where both pairs are stored and the
                         // address is 16-byte aligned (every row on 16-byte rows,
                         // every other one on 8-byte rows), 8-byte ones elsewhere
-                        staged_store<LAY>(r0, s0[h], lo, span, p.W, p.ovl, q0);
-                        staged_store<LAY>(r0 + p.out_ld, s0[h], lo, span, p.W, p.ovl, q1);
+                        staged_store<LAY>(r0, s0[h], lo, span, p.W, p.ovl, lane, q0);
+                        staged_store<LAY>(r0 + p.out_ld, s0[h], lo, span, p.W, p.ovl, lane, q1);
                     } else {
                         float *o0 = r0 + 2 * s0[h];
                         st2<false>(o0, q0[0]);  // 4-byte rows
@@ -889,13 +927,22 @@ __global__ __launch_bounds__(256) void fuse_batched_flat_kernel(const BatchScene
     const int si = find_scene(scenes, nscenes, u);
     const FuseParams p = scenes[si].p;
     const int item = u - scenes[si].unit_begin;
-    if (p.mode >= 3) {
+    if (p.mode == 4) {  // staged, 4 wavefronts x 2 rows
         if (p.path == PATH_V4)
             d4_staged_tile<2, 0>(p, f, bg_max, item, lds, 4, 0, p.B);
         else if (p.path == PATH_V2 || p.path == PATH_V2W)
             d4_staged_tile<2, 3>(p, f, bg_max, item, lds, 4, 0, p.B);
         else
             d4_staged_tile<2, 2>(p, f, bg_max, item, lds, 4, 0, p.B);
+        return;
+    }
+    if (p.mode == 3) {  // staged, 4 wavefronts x 1 row
+        if (p.path == PATH_V4)
+            d4_staged_tile<1, 0>(p, f, bg_max, item, lds, 4, 0, p.B);
+        else if (p.path == PATH_V2 || p.path == PATH_V2W)
+            d4_staged_tile<1, 3>(p, f, bg_max, item, lds, 4, 0, p.B);
+        else
+            d4_staged_tile<1, 2>(p, f, bg_max, item, lds, 4, 0, p.B);
         return;
     }
     const int unit = item * 4 + (threadIdx.x >> 6);
@@ -917,12 +964,14 @@ __global__ __launch_bounds__(256) void fuse_batched_flat_kernel(const BatchScene
     }
 }
 
-hipError_t launch_fuse_batched_flat(const BatchScene *d_scenes, int nscenes, int total, int staged_bands, int order,
-                                    const Filters &f, hipStream_t s) {
+hipError_t launch_fuse_batched_flat(const BatchScene *d_scenes, int nscenes, int total, int staged_bands,
+                                    int staged_rows, int order, const Filters &f, hipStream_t s) {
     if (nscenes <= 0 || total <= 0) return hipSuccess;
-    const int bgm = staged_bg_max(8);
+    if (staged_rows != 1 && staged_rows != 2) return hipErrorInvalidValue;
+    const int T = 4 * staged_rows;
+    const int bgm = staged_bg_max(T);
     const int bg = staged_bands < bgm ? staged_bands : bgm;
-    const size_t lds = bg > 0 ? sizeof(float) * staged_lds_floats(8, bg) : 0;
+    const size_t lds = bg > 0 ? sizeof(float) * staged_lds_floats(T, bg) : 0;
     hipLaunchKernelGGL(fuse_batched_flat_kernel, dim3(total), dim3(256), lds, s, d_scenes, nscenes, total,
                        bg > 0 ? bg : 1, order, f);
     return hipGetLastError();

@@ -82,6 +82,37 @@ def test_batch_variants_match_per_image(dev, fz, variant, graph):
         assert torch.equal(o2, ref)
 
 
+@pytest.mark.parametrize("rows,bands_at_once,order", [(2, 0, 3), (2, 2, 3), (1, 1, 3), (1, 3, 1), (2, 2, 0)])
+def test_flat_batch_forms_match_per_image(dev, fz, rows, bands_at_once, order):
+    """The flat grid with staged tiles of 1 or 2 rows per wavefront, staging
+    every band or 1-3 bands at a time, in each unit order, over scenes with
+    16-byte, 8-byte and misaligned rows and band counts above the group size:
+    every output equals its per-image call bit for bit."""
+    rng = np.random.default_rng(700 + rows * 10 + bands_at_once)
+    scenes = []
+    for i, (H, W, B, w, pad) in enumerate([(64, 1288, 3, "d4", 0), (34, 1030, 6, "d4", 0), (66, 262, 5, "d4", 2),
+                                           (130, 516, 5, "haar", 0), (18, 4070, 2, "d4", 4), (2, 8, 1, "d4", 0),
+                                           (256, 254, 6, "haar", 6), (40, 132, 4, "d4", 1)]):
+        pan, ms = int_scene(rng, H, W, B)
+        if pad:
+            scenes.append(dict(pan=strided_view(pan, dev, pad, 0), ms=strided_view(ms, dev, pad, 0), wavelet=w))
+        else:
+            scenes.append(dict(pan=to_dev(pan, dev), ms=to_dev(ms, dev), wavelet=w))
+    ctx = fz.context(dev)
+    say("flat batch form", rows, bands_at_once, order)
+    try:
+        ctx.force_tile(rows, 0, 0, 3)
+        ctx.force_band_split(bands_at_once)
+        ctx.force_order(order)
+        outs = fz.fuse_batched(scenes)
+    finally:
+        ctx.force_tile(0, 0, 0, 0)
+        ctx.force_band_split(0)
+        ctx.force_order(-1)
+    for s, o in zip(scenes, outs):
+        assert torch.equal(o, fz.fuse(s["pan"], s["ms"], s["wavelet"]))
+
+
 def test_batch_with_pitches_and_misalignment(dev, fz):
     rng = np.random.default_rng(9)
     scenes = []
