@@ -442,6 +442,7 @@ struct Tile {
     int order = 1;  // bit 0: row-band-major (else strip-major); bit 1: dispatch order (else per-XCD runs)
     int mode = 0;
     int split = 0;  // LDS-staged: bands per unit (0 = all)
+    int bg = 0;     // LDS-staged: bands staged at once (0 = as many as fit)
     int rows() const { return mode >= 3 ? wpb * (mode - 2) : (mode > 0 ? mode : seg_rows); }
 };
 
@@ -452,6 +453,7 @@ struct Forced {
     int seg_rows = 0, wpb = 0, nc = 0, variant = 0, split = 0;
     int order = -1;  // unit order of forward launches (-1 = the shape's own)
     int ovl = -1;    // overlapped strips (-1 = by the output's alignment)
+    int bg = 0;      // LDS-staged: bands staged at once (0 = the shape's own)
 };
 
 struct Decomp {
@@ -509,6 +511,7 @@ Tile default_tile(int wavelet, int64_t H, int64_t W, Path path) {
         t.seg_rows = 2;
         t.wpb = 4;
         t.order = 3;
+        t.bg = 2;
     } else {
         t.nc = path_nc(path);
         t.mode = 1;
@@ -650,6 +653,7 @@ FuseParams make_params(const RunArgs &a, Path path, const Tile &t, const Decomp 
     p.mode = t.mode;
     p.kappa = 1.0f;
     p.ovl = d.ovl;
+    p.bg = t.mode >= 3 ? t.bg : 0;
     if (t.mode >= 3 && t.split > 0 && t.split < a.B) {  // (tile, band group) units
         p.bsplit = t.split;
         p.units = d.units * (int32_t)((a.B + t.split - 1) / t.split);  // bounded by split_fits
@@ -693,6 +697,7 @@ Tile apply_forced(const dwt_fuse_ctx *c, Tile t, Path path, int wavelet, int max
     if (fo.split > 0) t.split = fo.split;
     if (t.mode < 3) t.split = 0;
     if (fo.order >= 0) t.order = fo.order;
+    if (fo.bg > 0) t.bg = fo.bg;
     return t;
 }
 
@@ -828,18 +833,23 @@ Tile tune_fuse(dwt_fuse_ctx *c, const RunArgs &a, Path path) {
     }
     // LDS-staged workgroups (D4): KR rows per wavefront, all bands of a tile
     // per unit (units split into band groups, dwt_fuse_force_band_split,
-    // measured slower on every workload, so they are not candidates).
+    // measured slower on every workload, so they are not candidates), the
+    // MS rows of every band or of 2 bands at a time in LDS.
     if (staged_allowed(a.wavelet, path, 2)) {
         for (int kr : {1, 2, 4}) {
             for (int wpb : {1, 2, 4}) {
                 for (int order : {1, 0, 3}) {
-                    Tile t;
-                    t.nc = 2;
-                    t.mode = 2 + kr;
-                    t.seg_rows = kr;
-                    t.wpb = wpb;
-                    t.order = order;
-                    cands.emplace_back(time_fuse(c, a, path, t), t);
+                    for (int bg : {0, 2}) {  // bands staged at once: as many as fit, or 2 (less LDS)
+                        if (bg > 0 && bg >= a.B) continue;
+                        Tile t;
+                        t.nc = 2;
+                        t.mode = 2 + kr;
+                        t.seg_rows = kr;
+                        t.wpb = wpb;
+                        t.order = order;
+                        t.bg = bg;
+                        cands.emplace_back(time_fuse(c, a, path, t), t);
+                    }
                 }
             }
         }
@@ -854,9 +864,9 @@ Tile tune_fuse(dwt_fuse_ctx *c, const RunArgs &a, Path path) {
     const Tile bestt =
         confirm_best(c->stream, cands, [&](const Tile &t) { return launch_tile(c, a, path, t); }, units, &bestms);
     if (std::getenv("DWT_FUSE_LOG"))
-        std::fprintf(stderr, "[dwt_fuse] tuned %s: mode=%d seg_rows=%d wpb=%d nc=%d order=%d split=%d (%.3f ms)\n",
+        std::fprintf(stderr, "[dwt_fuse] tuned %s: mode=%d seg_rows=%d wpb=%d nc=%d order=%d split=%d bg=%d (%.3f ms)\n",
                      tune_key(0, a.wavelet, a.H, a.W, a.B, path).c_str(), bestt.mode, bestt.seg_rows, bestt.wpb,
-                     bestt.nc, bestt.order, bestt.split, bestms);
+                     bestt.nc, bestt.order, bestt.split, bestt.bg, bestms);
     return bestt;
 }
 
@@ -1170,6 +1180,10 @@ dwt_fuse_status dwt_fuse_create(dwt_fuse_ctx **ctx, int device, void *hip_stream
                 c->forced.variant = v;
             }
         }
+        if (const char *f = std::getenv("DWT_FUSE_FORCE_BG")) {
+            const int o = std::atoi(f);
+            if (o >= 0 && o <= 8) c->forced.bg = o;
+        }
         if (const char *f = std::getenv("DWT_FUSE_FORCE_OVERLAP")) {
             const int o = std::atoi(f);
             if (o >= 0 && o <= 1) c->forced.ovl = o;
@@ -1279,10 +1293,10 @@ dwt_fuse_status dwt_fuse_tune_save(const dwt_fuse_ctx *ctx, const char *path) {
     if (!ctx || !path) return DWT_FUSE_E_NULL;
     FILE *f = std::fopen(path, "w");
     if (!f) return DWT_FUSE_E_STATE;
-    std::fprintf(f, "dwt_fuse_tune 4 %s %s\n", DWT_FUSE_BUILD_ID, ctx->device_name.c_str());
+    std::fprintf(f, "dwt_fuse_tune 5 %s %s\n", DWT_FUSE_BUILD_ID, ctx->device_name.c_str());
     for (const auto &kv : ctx->table)
-        std::fprintf(f, "%s %d %d %d %d %d %d\n", kv.first.c_str(), kv.second.seg_rows, kv.second.wpb, kv.second.nc,
-                     kv.second.order, kv.second.mode, kv.second.split);
+        std::fprintf(f, "%s %d %d %d %d %d %d %d\n", kv.first.c_str(), kv.second.seg_rows, kv.second.wpb, kv.second.nc,
+                     kv.second.order, kv.second.mode, kv.second.split, kv.second.bg);
     std::fclose(f);
     return DWT_FUSE_OK;
 }
@@ -1295,13 +1309,13 @@ dwt_fuse_status dwt_fuse_tune_load(dwt_fuse_ctx *ctx, const char *path) {
     int ver = 0;
     std::map<std::string, Tile> tab;
     bool ok = std::fscanf(f, "%31s %d %127s %127s", magic, &ver, build, dev) == 4 &&
-              std::strcmp(magic, "dwt_fuse_tune") == 0 && ver == 4 && std::strcmp(build, DWT_FUSE_BUILD_ID) == 0 &&
+              std::strcmp(magic, "dwt_fuse_tune") == 0 && ver == 5 && std::strcmp(build, DWT_FUSE_BUILD_ID) == 0 &&
               ctx->device_name == dev;
     while (ok) {
         char key[96] = {0};
         Tile t;
-        const int r = std::fscanf(f, "%95s %d %d %d %d %d %d", key, &t.seg_rows, &t.wpb, &t.nc, &t.order, &t.mode,
-                                  &t.split);
+        const int r = std::fscanf(f, "%95s %d %d %d %d %d %d %d", key, &t.seg_rows, &t.wpb, &t.nc, &t.order, &t.mode,
+                                  &t.split, &t.bg);
         if (r == EOF) break;
         // 'f' / 'b': float-path tiles (mode 0 rolling, 1-2 one-shot, 3/4/6
         // LDS-staged); 'c': format-variant shapes (nc 2/4/8, mode = rows of a
@@ -1310,7 +1324,7 @@ dwt_fuse_status dwt_fuse_tune_load(dwt_fuse_ctx *ctx, const char *path) {
         const bool shape_ok = codec ? ((t.nc == 2 || t.nc == 4 || t.nc == 8) && t.mode >= 0 && t.mode <= 4 &&
                                               (t.mode < 3 || t.nc == 2))
                                     : (t.nc >= 1 && t.nc <= 2 && t.mode >= 0 && t.mode <= 6 && t.mode != 5);
-        if (r != 7 || t.split < 0 || t.split > 8 || (key[0] != 'f' && key[0] != 'b' && !codec) || t.seg_rows < 1 || t.seg_rows > 4096 ||
+        if (r != 8 || t.split < 0 || t.split > 8 || t.bg < 0 || t.bg > 8 || (key[0] != 'f' && key[0] != 'b' && !codec) || t.seg_rows < 1 || t.seg_rows > 4096 ||
             t.wpb < 1 || t.wpb > 4 || t.order < 0 || t.order > 3 || !shape_ok) {
             ok = false;
             break;

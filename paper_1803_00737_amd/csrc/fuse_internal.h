@@ -47,6 +47,8 @@ struct FuseParams {
     int32_t bsplit;    // LDS-staged D4: bands per unit (0 = every band in one unit); units
                        // are then (tile, band group) with the groups of a tile adjacent
     int32_t ovl;       // 1: overlapped strips (see strip_origin); 0: strips side by side
+    int32_t bg;        // LDS-staged D4: bands staged at once (0 = as many as fit in 64 KB)
+    int32_t pad_;
 };
 
 // Column strips of a launch.  Side by side (ovl 0), strip k's wavefront

@@ -790,7 +790,7 @@ hipError_t launch_fuse(const FuseParams &p, const Filters &f, int wpb, hipStream
         if (p.wavelet != 1 || p.seg_rows != wpb * kr || p.nstrips != strip_count(p.W, 2, p.ovl) ||
             (p.ovl && p.path == PATH_SCALAR))
             return hipErrorInvalidValue;
-        const int bgm = staged_bg_max(p.seg_rows);
+        const int bgm = p.bg > 0 && p.bg < staged_bg_max(p.seg_rows) ? p.bg : staged_bg_max(p.seg_rows);
         if (bgm < 1 || p.bsplit < 0) return hipErrorInvalidValue;
         const int per_unit = p.bsplit > 0 && p.bsplit < p.B ? p.bsplit : p.B;  // bands one unit handles
         const size_t lds = sizeof(float) * staged_lds_floats(p.seg_rows, per_unit < bgm ? per_unit : bgm);

@@ -53,7 +53,7 @@ def test_tuning_table_round_trip(dev, fz, tmp_path):
     path = str(tmp_path / "tune.txt")
     a.tune_save(path)
     text = open(path).read().splitlines()
-    assert text[0].startswith("dwt_fuse_tune 4 ")
+    assert text[0].startswith("dwt_fuse_tune 5 ")
     keys = [line.split()[0] for line in text[1:]]
     assert any(k.startswith("f1_") for k in keys) and any(k.startswith("c111_") for k in keys)
     b = fz.Context(dev.index or 0)
@@ -65,7 +65,7 @@ def test_tuning_table_round_trip(dev, fz, tmp_path):
     # a table from another build (or a corrupt one) is refused as a whole
     bad = str(tmp_path / "bad.txt")
     with open(bad, "w") as f:
-        f.write(text[0].replace("dwt_fuse_tune 4 ", "dwt_fuse_tune 4 x") + "\n" + "\n".join(text[1:]) + "\n")
+        f.write(text[0].replace("dwt_fuse_tune 5 ", "dwt_fuse_tune 5 x") + "\n" + "\n".join(text[1:]) + "\n")
     c = fz.Context(dev.index or 0)
     c.bind_stream()
     with pytest.raises(_lib.DwtFuseError) as e:
