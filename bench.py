@@ -119,15 +119,34 @@ def time_loop(torch, fn, steps, warmup):
     return e0.elapsed_time(e1) / steps  # ms per step
 
 
-def read_traffic(bytes_per_launch):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel build."""
+def primary_tile(ctx, wl):
+    """The launch shape the context holds for the primary workload (the
+    tuning table's entry for its key, as the library saves it), or None."""
+    import math
+    import tempfile
+
+    key = "f%d_h%d_w%d_b%d_" % (1 if wl.wavelet == "d4" else 0, math.ceil(math.log2(wl.H)), math.ceil(math.log2(wl.W)),
+                                min(wl.B, 8))
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "table.txt")
+        ctx.tune_save(path)
+        with open(path) as f:
+            for line in f.read().splitlines()[1:]:
+                if line.startswith(key):
+                    return " ".join(line.split()[1:])
+    return None
+
+
+def read_traffic(tile):
+    """HBM bytes per launch from the committed rocprofv3 counter runs, if they
+    were taken on the current kernel build with the launch shape this run
+    uses (`tile`, from primary_tile)."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
         from paper_1803_00737_amd.build import build_id
 
-        if t.get("build_id") != build_id():
+        if t.get("build_id") != build_id() or t.get("tile") != tile:
             return None
         return float(t["traffic_bytes_per_launch"])
     except Exception:
@@ -556,6 +575,7 @@ def main():
     if args.tune_cache and not loaded and not args.no_tune:
         ctx.tune_save(args.tune_cache)
     ms_step = time_loop(torch, call, args.steps, args.warmup)
+    tile = primary_tile(ctx, wl)
     nbytes = algo_bytes(wl.H, wl.W, wl.B)
     achieved = nbytes / (ms_step * 1e-3) / 1e9
     value = wl.B * wl.H * wl.W / ms_step / 1e3
@@ -578,7 +598,8 @@ def main():
                    "stands_in_for": "the paper's largest Landsat-7 PAN scene, 16280 x 14960 (section 4, Table 1)"},
         "device": device_info(torch),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": read_traffic(nbytes),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": read_traffic(tile),
+                     "launch_shape": tile,
                      "algorithmic_bytes_per_launch": nbytes,
                      "torch_copy_1GiB_GB/s": copy_rate(torch, 20)[0]},
         "paper_context": PAPER_CONTEXT,
