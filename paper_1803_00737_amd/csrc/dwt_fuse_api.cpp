@@ -1996,6 +1996,7 @@ static AdjParams bwd_params(const BwdArgs &a, const BwdTile &bt, float *partial,
 struct StagedBwd {
     int kr = 0, wpb = 0;
     bool all = true;
+    int order = 0;
 };
 
 static int64_t staged_strips(const BwdArgs &a) { return (a.W / 2 + 127) / 128; }
@@ -2020,11 +2021,19 @@ static bool small_for_rolling(const BwdArgs &a, Path path) {
 static bool staged_bwd(const dwt_fuse_ctx *ctx, const BwdArgs &a, Path path, bool single, StagedBwd *sb) {
     if (a.wavelet != DWT_FUSE_D4 || path == PATH_SCALAR) return false;
     const Forced &fc = ctx->forced;
-    const bool dflt = fc.variant == 0 && fc.seg_rows == 0 && fc.wpb == 0 && fc.nc == 0 && it_bwd_default(ctx, a, path);
+    const bool unforced = fc.variant == 0 && fc.seg_rows == 0 && fc.wpb == 0 && fc.nc == 0;
+    const bool dflt = unforced && it_bwd_default(ctx, a, path);
+    auto it = ctx->table.find(tune_key(1, a.wavelet, a.H, a.W, a.B, path));
     if (fc.variant == 3) {
         sb->kr = fc.seg_rows == 2 ? 2 : 1;
         sb->wpb = fc.wpb >= 1 && fc.wpb <= 4 ? fc.wpb : 4;
         sb->all = fc.nc != 1;
+    } else if (unforced && it != ctx->table.end()) {  // tuned (or loaded) shape
+        if (it->second.mode < 3) return false;
+        sb->kr = it->second.mode - 2;
+        sb->wpb = it->second.wpb;
+        sb->all = true;
+        sb->order = it->second.order;
     } else if (dflt && a.B >= 5) {
         sb->kr = 2;
         sb->wpb = 4;
@@ -2065,7 +2074,7 @@ static dwt_fuse_status run_staged_bwd(dwt_fuse_ctx *ctx, const BwdArgs &a, Path 
     p.wavelet = a.wavelet;
     p.path = path;
     p.nstrips = (int32_t)ns;
-    p.order = ctx->forced.order >= 0 ? ctx->forced.order : 0;
+    p.order = ctx->forced.order >= 0 ? ctx->forced.order : sb.order;
     p.pstride = (int32_t)a.B;
     p.accumulate = 0;
     const hipError_t e = launch_adjoint_staged(p, ctx->filt, sb.kr, sb.wpb, sb.all, ctx->stream);
@@ -2098,6 +2107,97 @@ static dwt_fuse_status gain_workspace(dwt_fuse_ctx *ctx, bool noalloc, int64_t s
     return DWT_FUSE_OK;
 }
 
+// The adjoint kernels of one call with launch shape t (rolling mode 0,
+// one-shot D4 mode 1-2, LDS-staged D4 mode >= 3), gain slots to `partial`
+// (NULL: none); no gain reduction.
+static hipError_t launch_bwd_shape(dwt_fuse_ctx *ctx, const BwdArgs &a, Path path, const Tile &t, float *partial) {
+    if (t.mode >= 3) {
+        StagedBwd sb;
+        sb.kr = t.mode - 2;
+        sb.wpb = t.wpb;
+        sb.all = true;
+        sb.order = t.order;
+        if (adjoint_staged_lds(sb.kr * sb.wpb, (int)a.B, true) > 65536) return hipErrorInvalidValue;
+        return run_staged_bwd(ctx, a, path, sb, partial) == DWT_FUSE_OK ? hipSuccess : hipErrorLaunchFailure;
+    }
+    BwdTile bt;
+    bt.t = t;
+    bt.pp = path_for_nc(path, t.nc);
+    if (!decompose(a.H, a.W, t, &bt.d)) return hipErrorInvalidValue;
+    if (t.mode != 0) {
+        bt.kind = 2;
+        bt.x = t.mode;
+    } else {
+        bt.kind = a.B <= 4 ? 1 : 0;
+        bt.x = a.B <= 4 ? (int)a.B : 0;
+    }
+    const int maxb = adjoint_max_bands();
+    for (int64_t b0 = 0; b0 < a.B; b0 += maxb) {
+        const AdjParams p = bwd_params(a, bt, partial, b0);
+        const hipError_t e = bt.kind == 2   ? launch_adjoint_tile(p, ctx->filt, bt.x, t.wpb, ctx->stream)
+                             : bt.kind == 1 ? launch_adjoint_bg(p, ctx->filt, t.wpb, ctx->stream)
+                                            : launch_adjoint(p, ctx->filt, t.wpb, ctx->stream);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// Adjoint tuner (first call of a (wavelet, size class, bands, path) key with
+// tuning on): times, on the call's own buffers, rolling units of 4 .. 64
+// rows in three unit orders, one-shot D4 tiles of 1 or 2 rows and LDS-staged
+// D4 tiles of 1 or 2 rows x 4 wavefronts, every one with the path's widest
+// lane layout (so grad_gain keeps the same partial-slot layout and bits),
+// then confirms the fastest few as the forward tuner does.
+static Tile tune_bwd(dwt_fuse_ctx *ctx, const BwdArgs &a, Path path, float *partial) {
+    std::vector<std::pair<float, Tile>> cands;
+    const int nc = path_nc(path);
+    auto timed = [&](const Tile &t) {
+        return time_median3(ctx->stream, [&] { return launch_bwd_shape(ctx, a, path, t, partial); });
+    };
+    for (int seg : {64, 32, 16, 8, 4})
+        for (int order : {1, 0, 3}) {
+            Tile t;
+            t.mode = 0;
+            t.seg_rows = seg;
+            t.wpb = 4;
+            t.nc = nc;
+            t.order = order;
+            cands.emplace_back(timed(t), t);
+        }
+    if (a.wavelet == DWT_FUSE_D4) {
+        for (int kr : {1, 2})
+            for (int order : {1, 3}) {
+                Tile t;
+                t.mode = kr;
+                t.seg_rows = kr;
+                t.wpb = 4;
+                t.nc = nc;
+                t.order = order;
+                cands.emplace_back(timed(t), t);
+            }
+        if (path != PATH_SCALAR)
+            for (int kr : {1, 2})
+                for (int order : {0, 3}) {
+                    Tile t;
+                    t.mode = 2 + kr;
+                    t.seg_rows = kr;
+                    t.wpb = 4;
+                    t.nc = 2;
+                    t.order = order;
+                    cands.emplace_back(timed(t), t);
+                }
+    }
+    float bestms = 0.f;
+    const Tile best = confirm_best(
+        ctx->stream, cands, [&](const Tile &t) { return launch_bwd_shape(ctx, a, path, t, partial); },
+        [](const Tile &t) { return t.mode >= 3 ? 0 : t.mode > 0 ? 1 : 2 + 64 / std::max(1, t.seg_rows); }, &bestms);
+    if (std::getenv("DWT_FUSE_LOG"))
+        std::fprintf(stderr, "[dwt_fuse] tuned %s: mode=%d seg_rows=%d wpb=%d nc=%d order=%d (%.3f ms)\n",
+                     tune_key(1, a.wavelet, a.H, a.W, a.B, path).c_str(), best.mode, best.seg_rows, best.wpb, best.nc,
+                     best.order, bestms);
+    return best;
+}
+
 static dwt_fuse_status backward_impl(dwt_fuse_ctx *ctx, const BwdArgs &a, bool noalloc) {
     const int64_t H = a.H, B = a.B;
     std::string err;
@@ -2106,6 +2206,20 @@ static dwt_fuse_status backward_impl(dwt_fuse_ctx *ctx, const BwdArgs &a, bool n
     if (!a.grad_pan && !a.grad_ms && !a.grad_gain) return DWT_FUSE_OK;
     if ((st = use_device(ctx))) return st;
     const Path path = choose_bwd_path(a);
+    {
+        const Forced &fc = ctx->forced;
+        if (ctx->tuning && !noalloc && fc.variant == 0 && fc.seg_rows == 0 && fc.wpb == 0 && fc.nc == 0 &&
+            it_bwd_default(ctx, a, path)) {
+            // gain slots for the widest strip layout a candidate uses (128 columns)
+            float *partial = nullptr;
+            double *chunks = nullptr;
+            const int64_t slots = gain_slots(H, (a.W / 2 + 63) / 64);
+            if (a.grad_gain && slots <= INT32_MAX - kGainChunk &&
+                (st = gain_workspace(ctx, false, slots, B, &partial, &chunks)))
+                return st;
+            ctx->table[tune_key(1, a.wavelet, a.H, a.W, a.B, path)] = tune_bwd(ctx, a, path, partial);
+        }
+    }
     StagedBwd sb;
     if (staged_bwd(ctx, a, path, true, &sb)) {
         const int64_t slots = gain_slots(H, staged_strips(a));
