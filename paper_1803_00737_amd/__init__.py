@@ -12,7 +12,8 @@ from ._lib import D4, HAAR, DwtFuseError, LIB_PATH  # noqa: F401
 
 def __getattr__(name):
     # Lazy: the torch-facing API is imported on first use.
-    if name in ("fuse", "fuse_batched", "fuse_backward", "fuse_backward_batched", "fuse_multipass", "quality",
+    if name in ("fuse", "fuse_batched", "fuse_backward", "fuse_backward_noalloc", "fuse_backward_batched",
+                "fuse_multipass", "quality",
                 "DwtFuseFn", "Context", "context", "make_items", "make_bwd_items"):
         from . import api
 
