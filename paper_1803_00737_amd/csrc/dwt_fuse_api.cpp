@@ -1424,8 +1424,9 @@ std::string codec_key(const ExArgs &a, bool aligned) {
 
 // Untuned shape: one coefficient row per wavefront, 16-byte 8-bit rows for
 // Haar, 8-byte ones for D4; D4 with 8-bit input and output: 16-byte rows, 2
-// coefficient rows per wavefront, one wavefront per workgroup (the fastest
-// measured on both 8-bit D4 workloads).
+// coefficient rows per wavefront, one wavefront per workgroup, row bands in
+// per-XCD runs (unit order 1; among the fastest measured on both 8-bit D4
+// workloads).
 CodecShape codec_default(const ExArgs &a) {
     CodecShape t;
     const bool u8 = a.in_format == DWT_FUSE_U8;
@@ -1433,7 +1434,10 @@ CodecShape codec_default(const ExArgs &a) {
     t.nc = u8 ? (a.wavelet == DWT_FUSE_D4 && !u8io ? 4 : 8) : 2;
     t.kr = u8io ? 2 : 1;
     t.rows = t.kr;
-    if (u8io) t.wpb = 1;
+    if (u8io) {
+        t.wpb = 1;
+        t.order = 1;
+    }
     if (!codec_aligned(a, t.nc) && u8) t.nc = 4;
     t.aligned = codec_aligned(a, t.nc);
     if (!t.aligned) {
