@@ -149,6 +149,15 @@ dwt_fuse_status dwt_fuse_quality(dwt_fuse_ctx *ctx, int64_t H, int64_t W, int64_
                                  const float *ref, int64_t ref_ld, int64_t ref_band_stride,
                                  double *out);
 
+/* As dwt_fuse_quality, with the scores formed on the device in FP64 (bands
+ * in order, reproducible bit for bit): out is a device array of 4*B + 1
+ * doubles, out[0 .. 2B) the sums above, out[2B + b] = RMSE_b, out[3B + b] =
+ * mean_b, out[4B] = the ERGAS-style score (+inf if some mean_b is 0). */
+dwt_fuse_status dwt_fuse_quality_scores(dwt_fuse_ctx *ctx, int64_t H, int64_t W, int64_t B,
+                                        const float *fused, int64_t fused_ld, int64_t fused_band_stride,
+                                        const float *ref, int64_t ref_ld, int64_t ref_band_stride,
+                                        double *out);
+
 /* One independent scene of a batch; fields as in dwt_fuse_run. */
 typedef struct {
     int32_t wavelet; /* dwt_fuse_wavelet */

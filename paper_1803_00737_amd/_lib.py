@@ -23,7 +23,7 @@ EXPORTS = (
     "dwt_fuse_tune_save", "dwt_fuse_tune_load", "dwt_fuse_force_tile", "dwt_fuse_run_multipass",
     "dwt_fuse_run_ex", "dwt_fuse_check_run_ex", "dwt_fuse_quality", "dwt_fuse_check_quality",
     "dwt_fuse_force_band_split", "dwt_fuse_backward_batched", "dwt_fuse_check_backward_batched",
-    "dwt_fuse_backward_noalloc", "dwt_fuse_force_order",
+    "dwt_fuse_backward_noalloc", "dwt_fuse_force_order", "dwt_fuse_quality_scores",
 )
 
 HAAR = 0
@@ -144,6 +144,8 @@ def load(require_torch: bool = True):
         q_args = [i64, i64, i64, vp, i64, i64, vp, i64, i64, vp]
         lib.dwt_fuse_quality.argtypes = [vp] + q_args
         lib.dwt_fuse_quality.restype = st
+        lib.dwt_fuse_quality_scores.argtypes = [vp] + q_args
+        lib.dwt_fuse_quality_scores.restype = st
         lib.dwt_fuse_check_quality.argtypes = q_args
         lib.dwt_fuse_check_quality.restype = st
         _lib = lib

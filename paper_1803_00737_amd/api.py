@@ -198,7 +198,8 @@ def quality(fused: torch.Tensor, ref: torch.Tensor) -> dict:
     shape (e.g. a synthetic full-resolution truth), float32 on the GPU.
 
     The per-band sums (squared error, reference) are reduced on the GPU in
-    FP64; returns dict with ``sse``, ``sum_ref`` (float64 tensors of B, on the
+    FP64 and the scores formed from them there (dwt_fuse_quality_scores);
+    returns dict with ``sse``, ``sum_ref`` (float64 tensors of B, on the
     device), ``rmse`` and ``mean`` (lists), and ``ergas`` =
     100 * (1/2) * sqrt(mean_b (rmse_b / mean_b)^2) for the 1:2 PAN:MS pixel
     size of section 2."""
@@ -213,19 +214,15 @@ def quality(fused: torch.Tensor, ref: torch.Tensor) -> dict:
                          % (tuple(fused.shape), tuple(ref.shape)))
     fused, ref = _rows_unit(fused), _rows_unit(ref)
     B, H, W = fused.shape
-    out = torch.empty(2 * B, dtype=torch.float64, device=fused.device)
+    out = torch.empty(4 * B + 1, dtype=torch.float64, device=fused.device)
     c = context(fused.device)
     c.bind_stream()
-    st = c.lib.dwt_fuse_quality(c.handle, H, W, B, _ptr(fused), _pitch(fused, 1), _pitch(fused, 0),
-                                _ptr(ref), _pitch(ref, 1), _pitch(ref, 0), _ptr(out))
-    c.check(st, "dwt_fuse_quality")
+    st = c.lib.dwt_fuse_quality_scores(c.handle, H, W, B, _ptr(fused), _pitch(fused, 1), _pitch(fused, 0),
+                                       _ptr(ref), _pitch(ref, 1), _pitch(ref, 0), _ptr(out))
+    c.check(st, "dwt_fuse_quality_scores")
     host = out.cpu().tolist()
-    n = float(H * W)
-    rmse = [(host[b] / n) ** 0.5 for b in range(B)]
-    mean = [host[B + b] / n for b in range(B)]
-    rel = [(r / m) ** 2 if m != 0 else float("inf") for r, m in zip(rmse, mean)]
-    return {"sse": out[:B], "sum_ref": out[B:], "rmse": rmse, "mean": mean,
-            "ergas": 100.0 * 0.5 * (sum(rel) / B) ** 0.5}
+    return {"sse": out[:B], "sum_ref": out[B:2 * B], "rmse": host[2 * B:3 * B], "mean": host[3 * B:4 * B],
+            "ergas": host[4 * B]}
 
 
 def fuse_multipass(pan: torch.Tensor, ms: torch.Tensor, wavelet="d4", out: Optional[torch.Tensor] = None):

@@ -1650,7 +1650,7 @@ namespace {
 
 dwt_fuse_status check_quality_args(int64_t H, int64_t W, int64_t B, const float *fused, int64_t f_ld, int64_t f_bs,
                                    const float *ref, int64_t r_ld, int64_t r_bs, const double *out,
-                                   std::string *err) {
+                                   std::string *err, bool scores = false) {
     if (!fused || !ref || !out) {
         if (err) *err = "fused, ref and out must not be NULL";
         return DWT_FUSE_E_NULL;
@@ -1663,11 +1663,12 @@ dwt_fuse_status check_quality_args(int64_t H, int64_t W, int64_t B, const float 
     dwt_fuse_status st;
     if ((st = check_strided("fused", B, H, W, f_ld, f_bs, fused, &fs, err))) return st;
     if ((st = check_strided("ref", B, H, W, r_ld, r_bs, ref, &rs, err))) return st;
-    if (!fits_address_space(out, 2 * B, sizeof(double))) {
+    const int64_t nout = scores ? 4 * B + 1 : 2 * B;
+    if (!fits_address_space(out, nout, sizeof(double))) {
         if (err) *err = "out: extent overflows";
         return DWT_FUSE_E_SHAPE;
     }
-    const Span os = span_of(out, 2 * B, sizeof(double));
+    const Span os = span_of(out, nout, sizeof(double));
     if (os.overlaps(fs) || os.overlaps(rs)) {
         if (err) *err = "out overlaps an input";
         return DWT_FUSE_E_ALIAS;
@@ -1677,14 +1678,16 @@ dwt_fuse_status check_quality_args(int64_t H, int64_t W, int64_t B, const float 
 
 }  // namespace
 
-dwt_fuse_status dwt_fuse_quality(dwt_fuse_ctx *ctx, int64_t H, int64_t W, int64_t B, const float *fused,
-                                 int64_t fused_ld, int64_t fused_band_stride, const float *ref, int64_t ref_ld,
-                                 int64_t ref_band_stride, double *out) {
+namespace {
+
+dwt_fuse_status quality_impl(dwt_fuse_ctx *ctx, int64_t H, int64_t W, int64_t B, const float *fused,
+                             int64_t fused_ld, int64_t fused_band_stride, const float *ref, int64_t ref_ld,
+                             int64_t ref_band_stride, double *out, bool scores) {
     if (!ctx) return DWT_FUSE_E_NULL;
     try {
         std::string err;
         dwt_fuse_status st = check_quality_args(H, W, B, fused, fused_ld, fused_band_stride, ref, ref_ld,
-                                                ref_band_stride, out, &err);
+                                                ref_band_stride, out, &err, scores);
         if (st) return fail(ctx, st, err);
         if ((st = use_device(ctx))) return st;
         if ((st = ensure_ws(ctx, sizeof(double) * 2 * (size_t)kQualityBlocks * (size_t)B))) return st;
@@ -1698,7 +1701,9 @@ dwt_fuse_status dwt_fuse_quality(dwt_fuse_ctx *ctx, int64_t H, int64_t W, int64_
         p.H = (int32_t)H;
         p.W = (int32_t)W;
         p.B = (int32_t)B;
-        const hipError_t e = launch_quality(p, reinterpret_cast<double *>(ctx->ws), out, ctx->stream);
+        double *partial = reinterpret_cast<double *>(ctx->ws);
+        const hipError_t e = scores ? launch_quality_scores(p, partial, out, ctx->stream)
+                                    : launch_quality(p, partial, out, ctx->stream);
         if (e != hipSuccess) return hip_fail(ctx, e, "quality launch");
         return DWT_FUSE_OK;
     } catch (const std::bad_alloc &) {
@@ -1706,6 +1711,20 @@ dwt_fuse_status dwt_fuse_quality(dwt_fuse_ctx *ctx, int64_t H, int64_t W, int64_
     } catch (...) {
         return fail(ctx, DWT_FUSE_E_STATE, "unexpected exception");
     }
+}
+
+}  // namespace
+
+dwt_fuse_status dwt_fuse_quality(dwt_fuse_ctx *ctx, int64_t H, int64_t W, int64_t B, const float *fused,
+                                 int64_t fused_ld, int64_t fused_band_stride, const float *ref, int64_t ref_ld,
+                                 int64_t ref_band_stride, double *out) {
+    return quality_impl(ctx, H, W, B, fused, fused_ld, fused_band_stride, ref, ref_ld, ref_band_stride, out, false);
+}
+
+dwt_fuse_status dwt_fuse_quality_scores(dwt_fuse_ctx *ctx, int64_t H, int64_t W, int64_t B, const float *fused,
+                                        int64_t fused_ld, int64_t fused_band_stride, const float *ref,
+                                        int64_t ref_ld, int64_t ref_band_stride, double *out) {
+    return quality_impl(ctx, H, W, B, fused, fused_ld, fused_band_stride, ref, ref_ld, ref_band_stride, out, true);
 }
 
 dwt_fuse_status dwt_fuse_check_quality(int64_t H, int64_t W, int64_t B, const float *fused, int64_t fused_ld,

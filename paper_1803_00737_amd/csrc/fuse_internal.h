@@ -236,6 +236,9 @@ constexpr int kQualityBlocks = 256;       // blocks per band
 constexpr int kQualityMaxBands = 65535;  // grid y limit
 // partial: B * kQualityBlocks * 2 doubles of workspace; out: 2 * B doubles.
 hipError_t launch_quality(const QualityParams &p, double *partial, double *out, hipStream_t s);
+// The same sums followed by RMSE, mean and the ERGAS-style score: out holds
+// 4*B + 1 doubles (sse, sum_ref, rmse, mean per band, then the score).
+hipError_t launch_quality_scores(const QualityParams &p, double *partial, double *out, hipStream_t s);
 
 // Static device scratch of the entry points that allocate nothing
 // (static_scratch.hip): kStaticScratchBytes per GPU, held from the library's

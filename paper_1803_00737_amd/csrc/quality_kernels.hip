@@ -4,7 +4,8 @@
 //
 // The paper reports no quality metric it defines (section 4 names ERGAS and
 // QNR without formulas); these two sums are what RMSE, the relative error and
-// an ERGAS-style score need, and the host turns them into those numbers.
+// an ERGAS-style score need, and a one-wavefront kernel turns them into those
+// numbers (in FP64, bands in order).
 //
 // Every pixel goes to a fixed thread of a fixed block (rows round-robin over
 // the blocks of a band, columns strided over the threads, 4 adjacent pixels
@@ -89,7 +90,31 @@ __global__ __launch_bounds__(256) void quality_final_kernel(const double *__rest
     }
 }
 
+// RMSE_b = sqrt(sse_b / n), mean_b = sum_b / n, and the ERGAS-style score
+// 100 * (1/2) * sqrt(mean over b of (RMSE_b / mean_b)^2) (1:2 PAN:MS pixel
+// size, section 2); a band with mean 0 makes the score +inf.  One thread,
+// bands in order: the score is reproducible bit for bit.
+__global__ __launch_bounds__(64) void quality_scores_kernel(double *__restrict__ out, int B, double n) {
+    if (threadIdx.x != 0) return;
+    double acc = 0.0;
+    for (int b = 0; b < B; ++b) {
+        const double rmse = sqrt(out[b] / n), mean = out[B + b] / n;
+        out[2 * B + b] = rmse;
+        out[3 * B + b] = mean;
+        const double rel = rmse / mean;
+        acc += mean != 0.0 ? rel * rel : __builtin_inf();
+    }
+    out[4 * B] = 100.0 * 0.5 * sqrt(acc / B);
+}
+
 }  // namespace
+
+hipError_t launch_quality_scores(const QualityParams &p, double *partial, double *out, hipStream_t s) {
+    hipError_t e = launch_quality(p, partial, out, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(quality_scores_kernel, dim3(1), dim3(64), 0, s, out, p.B, (double)p.H * (double)p.W);
+    return hipGetLastError();
+}
 
 hipError_t launch_quality(const QualityParams &p, double *partial, double *out, hipStream_t s) {
     if (p.B < 1 || p.B > kQualityMaxBands || p.H < 1 || p.W < 1) return hipErrorInvalidValue;

@@ -231,6 +231,7 @@ def test_null_context_entry_points(lib):
     assert lib.dwt_fuse_force_tile(None, 1, 1, 1, 0) == E_NULL
     assert lib.dwt_fuse_force_band_split(None, 1) == E_NULL
     assert lib.dwt_fuse_force_order(None, 3) == E_NULL
+    assert lib.dwt_fuse_quality_scores(None, 8, 8, 1, P, 8, 64, P + 10**6, 8, 64, P + 2 * 10**6) == E_NULL
     assert lib.dwt_fuse_backward_noalloc(None, 1, 8, 8, 1, P, 8, None, P, 8, 64, None, None, None) == E_NULL
     assert lib.dwt_fuse_run_multipass(None, 1, 8, 8, 1, P, 8, P + 10**6, 4, 16, P + 2 * 10**6, 8, 64) == E_NULL
     lib.dwt_fuse_destroy(None)  # NULL-safe

@@ -4,7 +4,8 @@ box average of a known full-resolution truth (plus noise), kappa = 2 brings
 D4's fused bands back to the truth's mean level while kappa = 1 halves it.
 
 Bars: sse and sum_ref within 1e-12 relative of the oracle's FP64 sums
-(different summation order over float32 inputs converted exactly); the
+(different summation order over float32 inputs converted exactly), the
+GPU-formed RMSE and means likewise and the ERGAS-style score within 1e-9; the
 fused-vs-truth RMSE of each kernel path within 1e-4 relative of the oracle's
 (the fused values themselves differ by at most 1e-3)."""
 import numpy as np
@@ -39,10 +40,26 @@ def test_sums_match_oracle(dev, fz, oracle, B, H, W):
     got_sr = q["sum_ref"].cpu().numpy()
     assert np.allclose(got_sse, ref["sse"], rtol=1e-12, atol=0)
     assert np.allclose(got_sr, ref["sum_ref"], rtol=1e-12, atol=1e-9)
+    # the scores are formed on the GPU (dwt_fuse_quality_scores) from its sums
+    assert np.allclose(q["rmse"], ref["rmse"], rtol=1e-12, atol=0)
+    assert np.allclose(q["mean"], ref["mean"], rtol=1e-12, atol=1e-12)
     assert abs(q["ergas"] - ref["ergas"]) <= 1e-9 * ref["ergas"]
     # fixed order: a second call gives the same bits
     q2 = fz.quality(to_dev(f, dev), to_dev(r, dev))
     assert torch.equal(q["sse"], q2["sse"]) and torch.equal(q["sum_ref"], q2["sum_ref"])
+
+
+def test_score_zero_mean_band(dev, fz, oracle):
+    """A reference band with mean 0 makes the ERGAS-style score +inf on the
+    GPU as in the oracle; the other bands' RMSE and means stay finite."""
+    rng = np.random.default_rng(5)
+    f = rng.normal(10, 3, (2, 16, 24)).astype(np.float32)
+    r = np.stack([rng.normal(10, 3, (16, 24)), np.zeros((16, 24))]).astype(np.float32)
+    say("quality zero mean")
+    q = fz.quality(to_dev(f, dev), to_dev(r, dev))
+    ref = oracle.quality(f.astype(np.float64), r.astype(np.float64))
+    assert q["ergas"] == float("inf") and ref["ergas"] == float("inf")
+    assert np.allclose(q["rmse"], ref["rmse"], rtol=1e-12) and q["mean"][1] == 0.0
 
 
 @pytest.mark.parametrize("cols", [(5, 55, 1, 51), (4, 68, 8, 72)])
