@@ -224,6 +224,23 @@ struct CodecCols {
             for (int k = 1; k <= NC; ++k) m[k] = (float)mrow[pc[k]];
         }
     }
+    // 8-bit MS row: the lane's own NC coefficients packed 4 per word.
+    __device__ __forceinline__ void load_ms_own_raw(const TI *mrow, uint32_t (&w)[NC / 4]) const {
+        if (AL && full) {
+            if constexpr (NC == 4) {
+                w[0] = *reinterpret_cast<const uint32_t *>(mrow + s0);
+            } else {
+                const u2 v = *reinterpret_cast<const u2 *>(mrow + s0);
+                w[0] = v.x;
+                w[1] = v.y;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < NC / 4; ++j)
+                w[j] = (uint32_t)mrow[pc[4 * j + 1]] | ((uint32_t)mrow[pc[4 * j + 2]] << 8) |
+                       ((uint32_t)mrow[pc[4 * j + 3]] << 16) | ((uint32_t)mrow[pc[4 * j + 4]] << 24);
+        }
+    }
     __device__ __forceinline__ void load_ms_own(const TI *mrow, float (&m)[NC]) const {
         if (AL && full) {
             ld_ms_vec<TI, NC>(mrow + s0, &m[0]);
@@ -621,6 +638,41 @@ __device__ __forceinline__ void haar_codec_tile(const CodecParams &p, int strip,
 #pragma unroll
         for (int i = 0; i < KR; ++i) L.load_ms_own(mb + (int64_t)(rb + (i < nr ? i : 0)) * p.ms_ld, m[i]);
     };
+    if constexpr (sizeof(TI) == 1 && (NC == 4 || NC == 8)) {
+        // 8-bit MS, up to 8 bands: every band's rows of the tile are loaded up
+        // front as packed bytes (NC / 4 registers a row) and converted where
+        // they are used, so no band waits for its own loads.
+        constexpr int MB = 8;
+        if (p.B <= MB) {
+            uint32_t mall[MB][KR][NC / 4];
+#pragma unroll
+            for (int b = 0; b < MB; ++b) {
+                if (b >= p.B) break;
+                const TI *mb = ms + (int64_t)b * p.ms_bs;
+#pragma unroll
+                for (int i = 0; i < KR; ++i) L.load_ms_own_raw(mb + (int64_t)(rb + (i < nr ? i : 0)) * p.ms_ld, mall[b][i]);
+            }
+#pragma unroll
+            for (int b = 0; b < MB; ++b) {
+                if (b >= p.B) break;
+                const float g = p.gain ? p.gain[b] : 1.0f;
+                TO *ob = out + (int64_t)b * p.out_bs;
+#pragma unroll
+                for (int i = 0; i < KR; ++i) {
+                    if (i >= nr) break;
+                    float mv[NC];
+#pragma unroll
+                    for (int j = 0; j < NC; ++j) mv[j] = byte_at(mall[b][i][j >> 2], j & 3);
+                    f2 q0[NC], q1[NC];
+                    haar_out_rows<NC>(g, p.kappa, mv, da[i], dc[i], q0, q1);
+                    TO *o0 = ob + (int64_t)(2 * (rb + i)) * p.out_ld;
+                    store_out<TO, NC, AL>(o0, L.s0, L.W2, L.full, q0);
+                    store_out<TO, NC, AL>(o0 + p.out_ld, L.s0, L.W2, L.full, q1);
+                }
+            }
+            return;
+        }
+    }
     float m[KR][NC];
     load_band(0, m);
     for (int b = 0; b < p.B; ++b) {
