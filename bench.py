@@ -290,234 +290,250 @@ def launch_stats(torch, fn, n, flush=None):
     return {"median_ms": t[len(t) // 2], "min_ms": t[0], "max_ms": t[-1], "launches": n}
 
 
-def extras(torch, api, synth, steps, warmup, primary_call):
+def extras(torch, api, synth, steps, warmup, primary_call, only=None):
+    """Every workload after the primary one (or those named in `only`)."""
     out = {}
+
+    def want(name):
+        return only is None or name in only
+
     dev = torch.device("cuda:0")
-    # Primary workload launch by launch: back to back, and with every input
-    # and output evicted from the caches before each launch.
-    flush = torch.ones(1 << 27, device=dev)  # 512 MiB
-    n = max(10, steps // 2)
-    out["primary_per_launch"] = {"back_to_back": launch_stats(torch, primary_call, n),
-                                 "cache_flushed": launch_stats(torch, primary_call, n, flush)}
-    log("primary per launch", out["primary_per_launch"])
-    del flush
-    torch.cuda.empty_cache()
-    # D4 8192 x 8192, 3 bands.
-    wl = synth.d4_8192()
-    pan, ms = wl.make(device=dev)
-    o = torch.empty((wl.B, wl.H, wl.W), device=dev)
-    call = Prepared(api, pan, ms, wl.wavelet, o)
-    call()  # tunes the launch shape for this size class unless tuning is off
-    ms_t = time_loop(torch, call, steps, warmup)
-    gbs = algo_bytes(wl.H, wl.W, wl.B) / (ms_t * 1e-3) / 1e9
-    out[wl.name] = {"Mpix/s": wl.B * wl.H * wl.W / ms_t / 1e3, "ms": ms_t, "GB/s": gbs, "frac": gbs / HBM_PEAK_GBS,
-                    "per_launch": launch_stats(torch, call, max(10, steps // 2))}
-    log(wl.name, out[wl.name])
-    del pan, ms, o, call
-    torch.cuda.empty_cache()
-    # Haar 512x512, 1 band: launch-latency bound (fits in cache); Mpix/s only.
-    wl = synth.haar_512()
-    pan, ms = wl.make(device=dev)
-    o = torch.empty((wl.B, wl.H, wl.W), device=dev)
-    ms_t = time_loop(torch, Prepared(api, pan, ms, wl.wavelet, o), steps, warmup)
-    out[wl.name] = {"Mpix/s": wl.B * wl.H * wl.W / ms_t / 1e3, "ms": ms_t}
-    log(wl.name, out[wl.name])
-    # Haar on the Landsat-shaped scene (PAN detail computed once for 6 bands).
-    wl = synth.landsat("haar")
-    pan, ms = wl.make(device=dev)
-    o = torch.empty((wl.B, wl.H, wl.W), device=dev)
-    call = Prepared(api, pan, ms, wl.wavelet, o)
-    call()
-    ms_t = time_loop(torch, call, max(5, steps // 2), warmup)
-    gbs = algo_bytes(wl.H, wl.W, wl.B) / (ms_t * 1e-3) / 1e9
-    out[wl.name] = {"Mpix/s": wl.B * wl.H * wl.W / ms_t / 1e3, "ms": ms_t, "GB/s": gbs, "frac": gbs / HBM_PEAK_GBS}
-    log(wl.name, out[wl.name])
-    del pan, ms, o, call
-    torch.cuda.empty_cache()
-    # 8-bit images in and out (the paper's 8-bit-per-pixel representation):
-    # Landsat-shaped scene and the 8192^2 D4 scene.
-    for wl in (synth.landsat("haar"), synth.landsat("d4"), synth.d4_8192()):
-        pan, ms = wl.make(device=dev)
-        p8, m8 = pan.to(torch.uint8), ms.to(torch.uint8)
-        del pan, ms
-        o8 = torch.empty((wl.B, wl.H, wl.W), dtype=torch.uint8, device=dev)
-        call = PreparedEx(api, p8, m8, wl.wavelet, o8)
-        call()  # tunes the launch shape for this size class unless tuning is off
-        ms_t = time_loop(torch, call, max(5, steps // 2), warmup)
-        gbs = u8_bytes(wl.H, wl.W, wl.B) / (ms_t * 1e-3) / 1e9
-        out[wl.name + "_u8"] = {"Mpix/s": wl.B * wl.H * wl.W / ms_t / 1e3, "ms": ms_t, "GB/s": gbs,
-                                "frac": gbs / HBM_PEAK_GBS, "bytes_per_output_pixel": u8_bytes(wl.H, wl.W, wl.B) /
-                                (wl.B * wl.H * wl.W)}
-        log(wl.name + "_u8", out[wl.name + "_u8"])
-        del p8, m8, o8, call
+    if want("per_launch"):
+        # Primary workload launch by launch: back to back, and with every input
+        # and output evicted from the caches before each launch.
+        flush = torch.ones(1 << 27, device=dev)  # 512 MiB
+        n = max(10, steps // 2)
+        out["primary_per_launch"] = {"back_to_back": launch_stats(torch, primary_call, n),
+                                     "cache_flushed": launch_stats(torch, primary_call, n, flush)}
+        log("primary per launch", out["primary_per_launch"])
+        del flush
         torch.cuda.empty_cache()
-    # DC-matched D4 (kappa = 2) and the quality diagnostics against the
-    # scene's synthetic full-resolution truth, on the 8192^2 D4 scene.
-    wl = synth.d4_8192()
-    pan, ms = wl.make(device=dev)
-    truth = wl.truth(pan)
-    o = torch.empty((wl.B, wl.H, wl.W), device=dev)
-    qual = {}
-    for name, w, kappa in (("d4_kappa1", "d4", 1.0), ("d4_kappa2", "d4", 2.0), ("haar", "haar", 1.0)):
-        api.fuse(pan, ms, w, out=o, kappa=kappa)
-        q = api.quality(o, truth)
-        qual[name] = {"rmse": q["rmse"], "ergas": q["ergas"]}
-    call = PreparedEx(api, pan, ms, "d4", o, kappa=2.0)
-    t_k2 = time_loop(torch, call, steps, warmup)
-    t_q = time_loop(torch, lambda: api.quality(o, truth), max(3, steps // 10), 1)
-    qual["fused_kappa2_ms"] = t_k2
-    qual["fused_kappa2_Mpix/s"] = wl.B * wl.H * wl.W / t_k2 / 1e3
-    qual["fused_kappa2_frac"] = algo_bytes(wl.H, wl.W, wl.B) / (t_k2 * 1e-3) / 1e9 / HBM_PEAK_GBS
-    qual["quality_call_ms"] = t_q
-    out["dc_matched_quality_" + wl.name] = qual
-    log("dc matched / quality", qual)
-    del pan, ms, truth, o, call
-    torch.cuda.empty_cache()
-    # Batched: 96 uneven scenes, mixed wavelets, one persistent launch vs 96 launches.
-    layout = synth.uneven_batch()
-    scenes, preps = [], []
-    px = 0
-    nbytes = 0
-    for sc in layout:
-        pan, ms = synth.make_scene(sc.H, sc.W, sc.B, sc.seed, device=dev)
-        o = torch.empty((sc.B, sc.H, sc.W), device=dev)
-        scenes.append(dict(pan=pan, ms=ms, wavelet=sc.wavelet, out=o))
-        preps.append(Prepared(api, pan, ms, sc.wavelet, o))
-        px += sc.B * sc.H * sc.W
-        nbytes += algo_bytes(sc.H, sc.W, sc.B)
-    arr, _, keep = api.make_items(scenes)
-    ctx = api.context(dev)
-    ctx.bind_stream()
-    lib = ctx.lib
+    if want("d4_8192"):
+        # D4 8192 x 8192, 3 bands.
+        wl = synth.d4_8192()
+        pan, ms = wl.make(device=dev)
+        o = torch.empty((wl.B, wl.H, wl.W), device=dev)
+        call = Prepared(api, pan, ms, wl.wavelet, o)
+        call()  # tunes the launch shape for this size class unless tuning is off
+        ms_t = time_loop(torch, call, steps, warmup)
+        gbs = algo_bytes(wl.H, wl.W, wl.B) / (ms_t * 1e-3) / 1e9
+        out[wl.name] = {"Mpix/s": wl.B * wl.H * wl.W / ms_t / 1e3, "ms": ms_t, "GB/s": gbs, "frac": gbs / HBM_PEAK_GBS,
+                        "per_launch": launch_stats(torch, call, max(10, steps // 2))}
+        log(wl.name, out[wl.name])
+        del pan, ms, o, call
+        torch.cuda.empty_cache()
+    if want("haar_512"):
+        # Haar 512x512, 1 band: launch-latency bound (fits in cache); Mpix/s only.
+        wl = synth.haar_512()
+        pan, ms = wl.make(device=dev)
+        o = torch.empty((wl.B, wl.H, wl.W), device=dev)
+        ms_t = time_loop(torch, Prepared(api, pan, ms, wl.wavelet, o), steps, warmup)
+        out[wl.name] = {"Mpix/s": wl.B * wl.H * wl.W / ms_t / 1e3, "ms": ms_t}
+        log(wl.name, out[wl.name])
+    if want("haar_landsat"):
+        # Haar on the Landsat-shaped scene (PAN detail computed once for 6 bands).
+        wl = synth.landsat("haar")
+        pan, ms = wl.make(device=dev)
+        o = torch.empty((wl.B, wl.H, wl.W), device=dev)
+        call = Prepared(api, pan, ms, wl.wavelet, o)
+        call()
+        ms_t = time_loop(torch, call, max(5, steps // 2), warmup)
+        gbs = algo_bytes(wl.H, wl.W, wl.B) / (ms_t * 1e-3) / 1e9
+        out[wl.name] = {"Mpix/s": wl.B * wl.H * wl.W / ms_t / 1e3, "ms": ms_t, "GB/s": gbs, "frac": gbs / HBM_PEAK_GBS}
+        log(wl.name, out[wl.name])
+        del pan, ms, o, call
+        torch.cuda.empty_cache()
+    if want("u8"):
+        # 8-bit images in and out (the paper's 8-bit-per-pixel representation):
+        # Landsat-shaped scene and the 8192^2 D4 scene.
+        for wl in (synth.landsat("haar"), synth.landsat("d4"), synth.d4_8192()):
+            pan, ms = wl.make(device=dev)
+            p8, m8 = pan.to(torch.uint8), ms.to(torch.uint8)
+            del pan, ms
+            o8 = torch.empty((wl.B, wl.H, wl.W), dtype=torch.uint8, device=dev)
+            call = PreparedEx(api, p8, m8, wl.wavelet, o8)
+            call()  # tunes the launch shape for this size class unless tuning is off
+            ms_t = time_loop(torch, call, max(5, steps // 2), warmup)
+            gbs = u8_bytes(wl.H, wl.W, wl.B) / (ms_t * 1e-3) / 1e9
+            out[wl.name + "_u8"] = {"Mpix/s": wl.B * wl.H * wl.W / ms_t / 1e3, "ms": ms_t, "GB/s": gbs,
+                                    "frac": gbs / HBM_PEAK_GBS, "bytes_per_output_pixel": u8_bytes(wl.H, wl.W, wl.B) /
+                                    (wl.B * wl.H * wl.W)}
+            log(wl.name + "_u8", out[wl.name + "_u8"])
+            del p8, m8, o8, call
+            torch.cuda.empty_cache()
+    if want("quality"):
+        # DC-matched D4 (kappa = 2) and the quality diagnostics against the
+        # scene's synthetic full-resolution truth, on the 8192^2 D4 scene.
+        wl = synth.d4_8192()
+        pan, ms = wl.make(device=dev)
+        truth = wl.truth(pan)
+        o = torch.empty((wl.B, wl.H, wl.W), device=dev)
+        qual = {}
+        for name, w, kappa in (("d4_kappa1", "d4", 1.0), ("d4_kappa2", "d4", 2.0), ("haar", "haar", 1.0)):
+            api.fuse(pan, ms, w, out=o, kappa=kappa)
+            q = api.quality(o, truth)
+            qual[name] = {"rmse": q["rmse"], "ergas": q["ergas"]}
+        call = PreparedEx(api, pan, ms, "d4", o, kappa=2.0)
+        t_k2 = time_loop(torch, call, steps, warmup)
+        t_q = time_loop(torch, lambda: api.quality(o, truth), max(3, steps // 10), 1)
+        qual["fused_kappa2_ms"] = t_k2
+        qual["fused_kappa2_Mpix/s"] = wl.B * wl.H * wl.W / t_k2 / 1e3
+        qual["fused_kappa2_frac"] = algo_bytes(wl.H, wl.W, wl.B) / (t_k2 * 1e-3) / 1e9 / HBM_PEAK_GBS
+        qual["quality_call_ms"] = t_q
+        out["dc_matched_quality_" + wl.name] = qual
+        log("dc matched / quality", qual)
+        del pan, ms, truth, o, call
+        torch.cuda.empty_cache()
+    if want("batched"):
+        # Batched: 96 uneven scenes, mixed wavelets, one persistent launch vs 96 launches.
+        layout = synth.uneven_batch()
+        scenes, preps = [], []
+        px = 0
+        nbytes = 0
+        for sc in layout:
+            pan, ms = synth.make_scene(sc.H, sc.W, sc.B, sc.seed, device=dev)
+            o = torch.empty((sc.B, sc.H, sc.W), device=dev)
+            scenes.append(dict(pan=pan, ms=ms, wavelet=sc.wavelet, out=o))
+            preps.append(Prepared(api, pan, ms, sc.wavelet, o))
+            px += sc.B * sc.H * sc.W
+            nbytes += algo_bytes(sc.H, sc.W, sc.B)
+        arr, _, keep = api.make_items(scenes)
+        ctx = api.context(dev)
+        ctx.bind_stream()
+        lib = ctx.lib
 
-    def per_image():
-        for p in preps:
-            p()
+        def per_image():
+            for p in preps:
+                p()
 
-    def batched(flags):
-        def f():
-            st = lib.dwt_fuse_run_batched(ctx.handle, arr, len(scenes), flags)
-            if st != 0:
-                ctx.check(st, "dwt_fuse_run_batched")
-        return f
+        def batched(flags):
+            def f():
+                st = lib.dwt_fuse_run_batched(ctx.handle, arr, len(scenes), flags)
+                if st != 0:
+                    ctx.check(st, "dwt_fuse_run_batched")
+            return f
 
-    bsteps = max(5, steps // 2)
-    t_per = time_loop(torch, per_image, bsteps, warmup)
-    t_bat = time_loop(torch, batched(0), bsteps, warmup)
-    t_gra = time_loop(torch, batched(1), bsteps, warmup)
-    out["uneven_96_batched"] = {
-        "scenes": len(layout), "output_Mpix": px / 1e6,
-        "per_image_ms": t_per, "batched_ms": t_bat, "batched_graph_ms": t_gra,
-        "per_image_Mpix/s": px / t_per / 1e3, "batched_graph_Mpix/s": px / t_gra / 1e3,
-        "batched_graph_GB/s": nbytes / (t_gra * 1e-3) / 1e9,
-        "speedup_graph_vs_per_image": t_per / t_gra,
-    }
-    log("uneven_96", out["uneven_96_batched"])
-    del scenes, preps, arr, keep
-    torch.cuda.empty_cache()
-    # The paper's own multi-pass pipeline (section 3) on the primary workload, as a comparator.
-    wl = synth.d4_8192()
-    pan, ms = wl.make(device=dev)
-    o = torch.empty((wl.B, wl.H, wl.W), device=dev)
-    t_mp = time_loop(torch, lambda: api.fuse_multipass(pan, ms, wl.wavelet, out=o), max(3, steps // 10), 1)
-    t_fu = time_loop(torch, Prepared(api, pan, ms, wl.wavelet, o), steps, warmup)
-    out["paper_multipass_" + wl.name] = {"multipass_ms": t_mp, "fused_ms": t_fu, "fused_speedup": t_mp / t_fu,
-                                         "multipass_Mpix/s": wl.B * wl.H * wl.W / t_mp / 1e3}
-    log("multipass", out["paper_multipass_" + wl.name])
-    del pan, ms, o
-    torch.cuda.empty_cache()
-    # Adjoint alone at the primary shape (D4 8192^2, 3 bands): gradients
-    # w.r.t. PAN, MS and the 3 gains from one upstream gradient, one
-    # pre-marshalled dwt_fuse_backward call per step; algorithmic bytes
-    # H*W*(8 + 5B) (PAN and B upstream gradients read, grad_pan and B
-    # quarter-size grad_ms written).
-    wl = synth.d4_8192()
-    pan, _ = wl.make(device=dev)
-    H, W, B = wl.H, wl.W, wl.B
-    gy = torch.randn((B, H, W), device=dev, generator=torch.Generator(device=dev).manual_seed(3))
-    gain = torch.ones(B, device=dev)
-    gp = torch.empty((H, W), device=dev)
-    gm = torch.empty((B, H // 2, W // 2), device=dev)
-    gg = torch.empty(B, device=dev)
-    actx = api.context(dev)
-    actx.bind_stream()
-    alib = actx.lib
-    bargs = (actx.handle, 1, H, W, B, ctypes.c_void_p(pan.data_ptr()), W, ctypes.c_void_p(gain.data_ptr()),
-             ctypes.c_void_p(gy.data_ptr()), W, H * W, ctypes.c_void_p(gp.data_ptr()),
-             ctypes.c_void_p(gm.data_ptr()), ctypes.c_void_p(gg.data_ptr()))
-    ms_t = time_loop(torch, lambda: actx.check(alib.dwt_fuse_backward(*bargs), "dwt_fuse_backward"),
-                     max(5, steps // 2), warmup)
-    gbs = H * W * (8 + 5 * B) / (ms_t * 1e-3) / 1e9
-    out["adjoint_d4_8192x8192_b3"] = {"ms": ms_t, "GB/s": gbs, "frac": gbs / HBM_PEAK_GBS}
-    log("adjoint_d4_8192x8192_b3", out["adjoint_d4_8192x8192_b3"])
-    del pan, gy, gp, gm, gg, bargs
-    torch.cuda.empty_cache()
-
-    # Differentiation: 16 x 2048^2, 4 bands, D4: fused forward + adjoint
-    # (gradients w.r.t. PAN, MS and the 4 gains) of every scene, as
-    # pre-marshalled C-ABI calls (the Python autograd wrapper adds host time).
-    # Two ways: one batched forward call and one batched adjoint call over the
-    # 16 scenes; and per-scene calls issued round-robin on 4 streams, one
-    # library context each, so one scene's kernels fill the ramp-up and tail
-    # of another's (a 2048^2 launch is short).
-    H = W = 2048
-    B = 4
-    NS = 4
-    gain = torch.ones(B, device=dev)
-    fwd_sc, bwd_sc = [], []
-    for s in range(16):
-        pan, ms = synth.make_scene(H, W, B, synth.seed_for(4, s), device=dev)
-        gy = torch.randn((B, H, W), device=dev) * 1e-3
-        o = torch.empty((B, H, W), device=dev)
-        fwd_sc.append(dict(pan=pan, ms=ms, wavelet="d4", gain=gain, out=o))
-        bwd_sc.append(dict(pan=pan, grad_out=gy, wavelet="d4", gain=gain))
-    farr, _, fkeep = api.make_items(fwd_sc)
-    barr, bouts, bkeep = api.make_bwd_items(bwd_sc)
-    ctx = api.context(dev)
-    ctx.bind_stream()
-
-    def fwd_bwd_batched():
-        ctx.check(lib.dwt_fuse_run_batched(ctx.handle, farr, 16, 0), "dwt_fuse_run_batched")
-        ctx.check(lib.dwt_fuse_backward_batched(ctx.handle, barr, 16), "dwt_fuse_backward_batched")
-
-    streams = [torch.cuda.Stream() for _ in range(NS)]
-    sctx = [api.Context(dev.index if dev.index is not None else 0) for _ in range(NS)]
-    for c, st in zip(sctx, streams):
-        c.bind_stream(st)
-    calls = []
-    for s, (f, b, (gp, gm, gg)) in enumerate(zip(fwd_sc, bwd_sc, bouts)):
-        c = sctx[s % NS]
-        fargs = (c.handle, 1, H, W, B, ctypes.c_void_p(f["pan"].data_ptr()), W, ctypes.c_void_p(f["ms"].data_ptr()),
-                 W // 2, (H // 2) * (W // 2), ctypes.c_void_p(gain.data_ptr()), ctypes.c_void_p(f["out"].data_ptr()),
-                 W, H * W)
-        bargs = (c.handle, 1, H, W, B, ctypes.c_void_p(b["pan"].data_ptr()), W, ctypes.c_void_p(gain.data_ptr()),
-                 ctypes.c_void_p(b["grad_out"].data_ptr()), W, H * W, ctypes.c_void_p(gp.data_ptr()),
+        bsteps = max(5, steps // 2)
+        t_per = time_loop(torch, per_image, bsteps, warmup)
+        t_bat = time_loop(torch, batched(0), bsteps, warmup)
+        t_gra = time_loop(torch, batched(1), bsteps, warmup)
+        out["uneven_96_batched"] = {
+            "scenes": len(layout), "output_Mpix": px / 1e6,
+            "per_image_ms": t_per, "batched_ms": t_bat, "batched_graph_ms": t_gra,
+            "per_image_Mpix/s": px / t_per / 1e3, "batched_graph_Mpix/s": px / t_gra / 1e3,
+            "batched_graph_GB/s": nbytes / (t_gra * 1e-3) / 1e9,
+            "speedup_graph_vs_per_image": t_per / t_gra,
+        }
+        log("uneven_96", out["uneven_96_batched"])
+        del scenes, preps, arr, keep
+        torch.cuda.empty_cache()
+    if want("multipass"):
+        # The paper's own multi-pass pipeline (section 3) on the primary workload, as a comparator.
+        wl = synth.d4_8192()
+        pan, ms = wl.make(device=dev)
+        o = torch.empty((wl.B, wl.H, wl.W), device=dev)
+        t_mp = time_loop(torch, lambda: api.fuse_multipass(pan, ms, wl.wavelet, out=o), max(3, steps // 10), 1)
+        t_fu = time_loop(torch, Prepared(api, pan, ms, wl.wavelet, o), steps, warmup)
+        out["paper_multipass_" + wl.name] = {"multipass_ms": t_mp, "fused_ms": t_fu, "fused_speedup": t_mp / t_fu,
+                                             "multipass_Mpix/s": wl.B * wl.H * wl.W / t_mp / 1e3}
+        log("multipass", out["paper_multipass_" + wl.name])
+        del pan, ms, o
+        torch.cuda.empty_cache()
+    if want("adjoint"):
+        # Adjoint alone at the primary shape (D4 8192^2, 3 bands): gradients
+        # w.r.t. PAN, MS and the 3 gains from one upstream gradient, one
+        # pre-marshalled dwt_fuse_backward call per step; algorithmic bytes
+        # H*W*(8 + 5B) (PAN and B upstream gradients read, grad_pan and B
+        # quarter-size grad_ms written).
+        wl = synth.d4_8192()
+        pan, _ = wl.make(device=dev)
+        H, W, B = wl.H, wl.W, wl.B
+        gy = torch.randn((B, H, W), device=dev, generator=torch.Generator(device=dev).manual_seed(3))
+        gain = torch.ones(B, device=dev)
+        gp = torch.empty((H, W), device=dev)
+        gm = torch.empty((B, H // 2, W // 2), device=dev)
+        gg = torch.empty(B, device=dev)
+        actx = api.context(dev)
+        actx.bind_stream()
+        alib = actx.lib
+        bargs = (actx.handle, 1, H, W, B, ctypes.c_void_p(pan.data_ptr()), W, ctypes.c_void_p(gain.data_ptr()),
+                 ctypes.c_void_p(gy.data_ptr()), W, H * W, ctypes.c_void_p(gp.data_ptr()),
                  ctypes.c_void_p(gm.data_ptr()), ctypes.c_void_p(gg.data_ptr()))
-        calls.append(lambda a=fargs, c=c: c.check(lib.dwt_fuse_run(*a), "dwt_fuse_run"))
-        calls.append(lambda a=bargs, c=c: c.check(lib.dwt_fuse_backward(*a), "dwt_fuse_backward"))
+        ms_t = time_loop(torch, lambda: actx.check(alib.dwt_fuse_backward(*bargs), "dwt_fuse_backward"),
+                         max(5, steps // 2), warmup)
+        gbs = H * W * (8 + 5 * B) / (ms_t * 1e-3) / 1e9
+        out["adjoint_d4_8192x8192_b3"] = {"ms": ms_t, "GB/s": gbs, "frac": gbs / HBM_PEAK_GBS}
+        log("adjoint_d4_8192x8192_b3", out["adjoint_d4_8192x8192_b3"])
+        del pan, gy, gp, gm, gg, bargs
+        torch.cuda.empty_cache()
 
-    def fwd_bwd_streams():
-        cur = torch.cuda.current_stream()
-        for st in streams:
-            st.wait_stream(cur)
-        for c in calls:
-            c()
-        for st in streams:
-            cur.wait_stream(st)
+    if want("differentiation"):
+        # Differentiation: 16 x 2048^2, 4 bands, D4: fused forward + adjoint
+        # (gradients w.r.t. PAN, MS and the 4 gains) of every scene, as
+        # pre-marshalled C-ABI calls (the Python autograd wrapper adds host time).
+        # Two ways: one batched forward call and one batched adjoint call over the
+        # 16 scenes; and per-scene calls issued round-robin on 4 streams, one
+        # library context each, so one scene's kernels fill the ramp-up and tail
+        # of another's (a 2048^2 launch is short).
+        H = W = 2048
+        B = 4
+        NS = 4
+        gain = torch.ones(B, device=dev)
+        fwd_sc, bwd_sc = [], []
+        for s in range(16):
+            pan, ms = synth.make_scene(H, W, B, synth.seed_for(4, s), device=dev)
+            gy = torch.randn((B, H, W), device=dev) * 1e-3
+            o = torch.empty((B, H, W), device=dev)
+            fwd_sc.append(dict(pan=pan, ms=ms, wavelet="d4", gain=gain, out=o))
+            bwd_sc.append(dict(pan=pan, grad_out=gy, wavelet="d4", gain=gain))
+        farr, _, fkeep = api.make_items(fwd_sc)
+        barr, bouts, bkeep = api.make_bwd_items(bwd_sc)
+        ctx = api.context(dev)
+        ctx.bind_stream()
+        lib = ctx.lib
 
-    n = max(5, steps // 5)
-    t_b = time_loop(torch, fwd_bwd_batched, n, 2)
-    t_s = time_loop(torch, fwd_bwd_streams, n, 2)
-    fb_bytes = 16 * (algo_bytes(H, W, B) + H * W * (8 + 5 * B))
-    out["differentiation_16x2048_b4"] = {"fwd_bwd_ms": t_b, "scenes/s": 16 / (t_b * 1e-3),
-                                         "GB/s": fb_bytes / (t_b * 1e-3) / 1e9,
-                                         "frac": fb_bytes / (t_b * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                                         "how": "one batched forward call + one batched adjoint call",
-                                         "per_scene_calls_on_%d_streams_ms" % NS: t_s}
-    log("differentiation", out["differentiation_16x2048_b4"])
-    torch.cuda.synchronize()
-    del calls, sctx, fkeep, bkeep, bouts, farr, barr, fwd_sc, bwd_sc
-    torch.cuda.empty_cache()
+        def fwd_bwd_batched():
+            ctx.check(lib.dwt_fuse_run_batched(ctx.handle, farr, 16, 0), "dwt_fuse_run_batched")
+            ctx.check(lib.dwt_fuse_backward_batched(ctx.handle, barr, 16), "dwt_fuse_backward_batched")
+
+        streams = [torch.cuda.Stream() for _ in range(NS)]
+        sctx = [api.Context(dev.index if dev.index is not None else 0) for _ in range(NS)]
+        for c, st in zip(sctx, streams):
+            c.bind_stream(st)
+        calls = []
+        for s, (f, b, (gp, gm, gg)) in enumerate(zip(fwd_sc, bwd_sc, bouts)):
+            c = sctx[s % NS]
+            fargs = (c.handle, 1, H, W, B, ctypes.c_void_p(f["pan"].data_ptr()), W, ctypes.c_void_p(f["ms"].data_ptr()),
+                     W // 2, (H // 2) * (W // 2), ctypes.c_void_p(gain.data_ptr()), ctypes.c_void_p(f["out"].data_ptr()),
+                     W, H * W)
+            bargs = (c.handle, 1, H, W, B, ctypes.c_void_p(b["pan"].data_ptr()), W, ctypes.c_void_p(gain.data_ptr()),
+                     ctypes.c_void_p(b["grad_out"].data_ptr()), W, H * W, ctypes.c_void_p(gp.data_ptr()),
+                     ctypes.c_void_p(gm.data_ptr()), ctypes.c_void_p(gg.data_ptr()))
+            calls.append(lambda a=fargs, c=c: c.check(lib.dwt_fuse_run(*a), "dwt_fuse_run"))
+            calls.append(lambda a=bargs, c=c: c.check(lib.dwt_fuse_backward(*a), "dwt_fuse_backward"))
+
+        def fwd_bwd_streams():
+            cur = torch.cuda.current_stream()
+            for st in streams:
+                st.wait_stream(cur)
+            for c in calls:
+                c()
+            for st in streams:
+                cur.wait_stream(st)
+
+        n = max(5, steps // 5)
+        t_b = time_loop(torch, fwd_bwd_batched, n, 2)
+        t_s = time_loop(torch, fwd_bwd_streams, n, 2)
+        fb_bytes = 16 * (algo_bytes(H, W, B) + H * W * (8 + 5 * B))
+        out["differentiation_16x2048_b4"] = {"fwd_bwd_ms": t_b, "scenes/s": 16 / (t_b * 1e-3),
+                                             "GB/s": fb_bytes / (t_b * 1e-3) / 1e9,
+                                             "frac": fb_bytes / (t_b * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                             "how": "one batched forward call + one batched adjoint call",
+                                             "per_scene_calls_on_%d_streams_ms" % NS: t_s}
+        log("differentiation", out["differentiation_16x2048_b4"])
+        torch.cuda.synchronize()
+        del calls, sctx, fkeep, bkeep, bouts, farr, barr, fwd_sc, bwd_sc
+        torch.cuda.empty_cache()
     return out
 
 
@@ -534,6 +550,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--mode", choices=["full", "primary", "copy"], default="full")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", default=None,
+                    help="comma-separated subset of the extra workloads (per_launch, d4_8192, haar_512, "
+                         "haar_landsat, u8, quality, batched, multipass, adjoint, differentiation)")
     ap.add_argument("--no-tune", action="store_true", help="use the default tile instead of the autotuner")
     ap.add_argument("--tune-cache", default=None,
                     help="tuning table file: loaded if it exists (no tuning), else written after tuning "
@@ -605,7 +624,8 @@ def main():
         "paper_context": PAPER_CONTEXT,
     }
     if args.mode == "full":
-        result["workloads"] = extras(torch, api, synth, args.steps, args.warmup, call)
+        only = set(args.only.split(",")) if args.only else None
+        result["workloads"] = extras(torch, api, synth, args.steps, args.warmup, call, only)
         if args.tune_cache and not loaded and not args.no_tune:
             ctx.tune_save(args.tune_cache)  # now with the shapes of every workload
     if not args.no_cpu_baseline:
