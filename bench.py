@@ -179,7 +179,7 @@ def _strip_rows(H, nstrips, rows):
     return [(2 * ((H // 2) * k // nstrips), 2 * ((H // 2) * k // nstrips) + rows) for k in range(nstrips)]
 
 
-def cpu_baseline(pan, ms, wavelet, budget_s=12.0, max_passes=8):
+def cpu_baseline(pan, ms, wavelet, budget_s=12.0, max_passes=16):
     """The FP64 oracle as it stands (plain C, one thread) on a bounded sample of
     the primary workload: 8 strips of 248 output rows (1984 of the scene's rows,
     every column and band) at evenly spaced offsets, each computed by the
