@@ -363,10 +363,14 @@ dwt_fuse_status dwt_fuse_force_band_split(dwt_fuse_ctx *ctx, int bands_per_unit)
  * are numbered and handed to workgroups: bit 0 set = row bands across the
  * image width (else column strips down the image), bit 1 set = workgroups
  * take units in dispatch order, so the whole GPU advances through them as
- * one front (else each XCD takes a contiguous run); -1 = automatic (the
- * tuned or default order).  Results are bit-identical for every order.
- * DWT_FUSE_E_SHAPE if out of range (-1 .. 3).  The environment variable
- * DWT_FUSE_FORCE_ORDER sets the same at dwt_fuse_create. */
+ * one front (else each XCD takes a contiguous run); bit 2 set (LDS-staged D4
+ * tiles of dwt_fuse_run without a band split; other launches ignore it) =
+ * XCD slabs: row bands across the GPU, each of the 8 XCDs taking a
+ * contiguous chunk of every band's strips, so neighbouring tiles share an
+ * L2; -1 = automatic (the tuned or default order).  Results are
+ * bit-identical for every order.  DWT_FUSE_E_SHAPE if out of range
+ * (-1 .. 7).  The environment variable DWT_FUSE_FORCE_ORDER sets the same at
+ * dwt_fuse_create. */
 dwt_fuse_status dwt_fuse_force_order(dwt_fuse_ctx *ctx, int order);
 
 #ifdef __cplusplus

@@ -41,7 +41,9 @@ struct FuseParams {
     int32_t path;      // Path
     int32_t nstrips;   // ceil((W/2) / (64*NC))
     int32_t order;     // unit numbering, bit 0: row-band-major (else strip-major); bit 1:
-                       // workgroups in dispatch order (else each XCD a contiguous run)
+                       // workgroups in dispatch order (else each XCD a contiguous run);
+                       // bit 2 (LDS-staged D4 tiles without band split, with bit 0): XCD
+                       // slabs, each XCD walking its own chunk of every row band's strips
     int32_t mode;      // 0 rolling over seg_rows rows; 1, 2 one-shot tile of that many rows
     float kappa;       // LL <- kappa * MS band (1 = as printed)
     int32_t bsplit;    // LDS-staged D4: bands per unit (0 = every band in one unit); units

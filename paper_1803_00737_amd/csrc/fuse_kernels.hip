@@ -685,10 +685,31 @@ __device__ __forceinline__ void d4_staged_tile(const FuseParams &p, const Filter
     }
 }
 
+// Bit 2 of the unit order: XCD slabs.  The strips of every row band are cut
+// into 8 contiguous chunks, chunk x for XCD x (workgroups are dealt
+// round-robin to the 8 XCDs); XCD x walks its chunk row band after row band,
+// so horizontally and vertically adjacent tiles share an L2 and the GPU still
+// advances down the image together.  The grid is 8 * cmax * nseg workgroups
+// (cmax = the largest chunk); those past their XCD's chunk leave at once.
+__device__ __forceinline__ bool slab_unit(int b, int nstrips, int nseg, int &unit) {
+    const int x = b & 7, i = b >> 3;
+    const int q = nstrips >> 3, r = nstrips & 7;
+    const int c = q + (x < r ? 1 : 0);
+    if (c == 0 || i >= c * nseg) return false;
+    const int trow = i / c;
+    unit = trow * nstrips + x * q + min(x, r) + (i - trow * c);  // row-band-major numbering
+    return true;
+}
+
 template <int KR, int LAY>
 __global__ __launch_bounds__(256) void d4_staged_kernel(FuseParams p, Filters f, int bg_max) {
     extern __shared__ float lds[];
-    const int unit = block_unit(p.order);
+    int unit = 0;
+    if (p.order & 4) {
+        if (!slab_unit(blockIdx.x, p.nstrips, p.nseg, unit)) return;  // whole workgroup
+    } else {
+        unit = block_unit(p.order);
+    }
     if (unit >= p.units) return;  // whole workgroup
     if (p.bsplit > 0) {  // unit = tile * ngroups + group
         const int ng = (p.B + p.bsplit - 1) / p.bsplit;
@@ -702,16 +723,17 @@ __global__ __launch_bounds__(256) void d4_staged_kernel(FuseParams p, Filters f,
 
 template <int KR>
 static void launch_staged(const FuseParams &p, const Filters &f, int wpb, size_t lds, int bgm, hipStream_t s) {
+    const int grid = (p.order & 4) ? 8 * ((p.nstrips + 7) / 8) * p.nseg : p.units;
     switch (p.path) {
         case PATH_V4:
-            hipLaunchKernelGGL((d4_staged_kernel<KR, 0>), dim3(p.units), dim3(64 * wpb), lds, s, p, f, bgm);
+            hipLaunchKernelGGL((d4_staged_kernel<KR, 0>), dim3(grid), dim3(64 * wpb), lds, s, p, f, bgm);
             break;
         case PATH_V2:
         case PATH_V2W:
-            hipLaunchKernelGGL((d4_staged_kernel<KR, 3>), dim3(p.units), dim3(64 * wpb), lds, s, p, f, bgm);
+            hipLaunchKernelGGL((d4_staged_kernel<KR, 3>), dim3(grid), dim3(64 * wpb), lds, s, p, f, bgm);
             break;
         default:
-            hipLaunchKernelGGL((d4_staged_kernel<KR, 2>), dim3(p.units), dim3(64 * wpb), lds, s, p, f, bgm);
+            hipLaunchKernelGGL((d4_staged_kernel<KR, 2>), dim3(grid), dim3(64 * wpb), lds, s, p, f, bgm);
             break;
     }
 }
@@ -792,6 +814,8 @@ hipError_t launch_fuse(const FuseParams &p, const Filters &f, int wpb, hipStream
             return hipErrorInvalidValue;
         const int bgm = p.bg > 0 && p.bg < staged_bg_max(p.seg_rows) ? p.bg : staged_bg_max(p.seg_rows);
         if (bgm < 1 || p.bsplit < 0) return hipErrorInvalidValue;
+        if ((p.order & 4) && (p.bsplit > 0 || (p.order & 1) == 0 || (int64_t)8 * ((p.nstrips + 7) / 8) * p.nseg > INT32_MAX))
+            return hipErrorInvalidValue;  // slabs: whole tiles, row-band-major numbering
         const int per_unit = p.bsplit > 0 && p.bsplit < p.B ? p.bsplit : p.B;  // bands one unit handles
         const size_t lds = sizeof(float) * staged_lds_floats(p.seg_rows, per_unit < bgm ? per_unit : bgm);
         switch (kr) {

@@ -77,6 +77,14 @@ def test_tuning_table_round_trip(dev, fz, tmp_path):
         c.tune_load(bad)
     with pytest.raises(_lib.DwtFuseError):
         c.tune_load(str(tmp_path / "missing.txt"))
+    with open(bad, "w") as f:  # unit order out of range (bits 0-2 only)
+        f.write(text[0] + "\nf1_h10_w10_b3_p0 2 4 2 8 4 0 0\n")
+    with pytest.raises(_lib.DwtFuseError):
+        c.tune_load(bad)
+    for order in (-2, 8):
+        with pytest.raises(_lib.DwtFuseError) as e:
+            c.force_order(order)
+        assert e.value.status == _lib.E_SHAPE
     got = run(c)
     assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
 

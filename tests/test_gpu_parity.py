@@ -206,11 +206,13 @@ def test_tile_shapes_give_identical_results(dev, fz, wavelet, H, W):
 
 
 @pytest.mark.parametrize("wavelet", ["haar", "d4"])
-@pytest.mark.parametrize("H,W", [(250, 1288), (66, 1030), (18, 8)])
+@pytest.mark.parametrize("H,W", [(250, 1288), (66, 1030), (18, 8), (130, 2824), (34, 4104)])
 def test_unit_orders_give_identical_results(dev, fz, oracle, wavelet, H, W):
     """Every unit order (column strips or row bands, per-XCD runs or dispatch
-    order) of every variant gives the same output bit for bit, and the
-    oracle's; 8-bit output too."""
+    order, XCD slabs for the LDS-staged tiles: 1, 5, 6, 12 and 17 strips of
+    128 coefficient columns, so some XCDs' chunks are empty or shorter) of
+    every variant gives the same output bit for bit, and the oracle's; 8-bit
+    output too."""
     rng = np.random.default_rng(17)
     pan, ms = int_scene(rng, H, W, 3)
     p, m = to_dev(pan, dev), to_dev(ms, dev)
@@ -218,10 +220,10 @@ def test_unit_orders_give_identical_results(dev, fz, oracle, wavelet, H, W):
     ctx = fz.context(dev)
     base = None
     try:
-        for order in (0, 1, 2, 3):
+        for order in (0, 1, 2, 3, 4, 5, 6, 7):
             ctx.force_order(order)
             for seg, wpb, nc, var in [(0, 0, 0, 0), (16, 4, 2, 1), (1, 2, 1, 2), (2, 4, 2, 2), (2, 4, 2, 3),
-                                      (1, 4, 2, 3)]:
+                                      (1, 4, 2, 3), (4, 2, 2, 3)]:
                 say(wavelet, "order", order, H, W, "tile", seg, wpb, nc, var)
                 ctx.force_tile(seg, wpb, nc, var)
                 out = fz.fuse(p, m, wavelet).cpu().numpy()
