@@ -1553,9 +1553,13 @@ CodecShape codec_shape_of(dwt_fuse_ctx *c, const ExArgs &a) {
                     }
         }
         float bestms = 0.f;
+        // near-ties: D4 one-shot tiles in per-XCD runs of row bands (order 1),
+        // whose vertically adjacent tiles share an L2 and so fetch each halo
+        // row once (1.0 x the algorithmic reads against up to 2.1 x otherwise)
+        const bool d4 = a.wavelet == DWT_FUSE_D4;
         t = confirm_best(
             c->stream, cands, [&](const CodecShape &s) { return launch_codec_shape(c, a, s); },
-            [](const CodecShape &) { return 0; }, &bestms);
+            [d4](const CodecShape &s) { return d4 && s.kr > 0 && s.kr < 3 && s.order != 1 ? 1 : 0; }, &bestms);
         Tile rec;
         rec.nc = t.nc;
         rec.seg_rows = t.rows;
