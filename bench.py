@@ -140,17 +140,37 @@ def primary_tile(ctx, wl):
 def read_traffic(tile):
     """HBM bytes per launch from the committed rocprofv3 counter runs, if they
     were taken on the current kernel build with the launch shape this run
-    uses (`tile`, from primary_tile)."""
+    uses (`tile`, from primary_tile; counters are kept for the shapes the
+    tuner picks most often)."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
         from paper_1803_00737_amd.build import build_id
 
-        if t.get("build_id") != build_id() or t.get("tile") != tile:
+        if t.get("build_id") != build_id() or tile not in t.get("tiles", {}):
             return None
-        return float(t["traffic_bytes_per_launch"])
+        return float(t["tiles"][tile]["traffic_bytes_per_launch"])
     except Exception:
         return None
+
+
+def force_primary_tile(ctx, wl, tile):
+    """Load a one-entry tuning table that gives the primary workload the
+    launch shape `tile` ("seg_rows wpb nc order mode split bg", as the table
+    stores it), so a profiler run can take counters for that shape."""
+    import math
+    import tempfile
+
+    key = "f%d_h%d_w%d_b%d_p0" % (1 if wl.wavelet == "d4" else 0, math.ceil(math.log2(wl.H)),
+                                 math.ceil(math.log2(wl.W)), min(wl.B, 8))
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "table.txt")
+        ctx.tune_save(path)  # for the header line: this build and device
+        with open(path) as f:
+            header = f.read().splitlines()[0]
+        with open(path, "w") as f:
+            f.write(header + "\n" + key + " " + tile + "\n")
+        ctx.tune_load(path)
 
 
 def copy_rate(torch, steps):
@@ -554,6 +574,9 @@ def main():
                     help="comma-separated subset of the extra workloads (per_launch, d4_8192, haar_512, "
                          "haar_landsat, u8, quality, batched, multipass, adjoint, differentiation)")
     ap.add_argument("--no-tune", action="store_true", help="use the default tile instead of the autotuner")
+    ap.add_argument("--tile", default=None,
+                    help='primary workload only: its launch shape, "seg_rows wpb nc order mode split bg" '
+                         "(as in a tuning table), instead of tuning")
     ap.add_argument("--tune-cache", default=None,
                     help="tuning table file: loaded if it exists (no tuning), else written after tuning "
                          "(after the primary workload, and again at the end with every workload's shapes)")
@@ -581,7 +604,11 @@ def main():
     out = torch.empty((wl.B, wl.H, wl.W), device=dev)
     ctx = api.context(dev)
     loaded = False
-    if args.tune_cache and os.path.exists(args.tune_cache):
+    if args.tile:
+        force_primary_tile(ctx, wl, args.tile)
+        loaded = True
+        log("primary launch shape forced:", args.tile)
+    elif args.tune_cache and os.path.exists(args.tune_cache):
         ctx.tune_load(args.tune_cache)
         loaded = True
         log("tuning table loaded from", args.tune_cache)
