@@ -225,9 +225,10 @@ def cpu_baseline(pan, ms, wavelet, budget_s=12.0, max_passes=16):
             "host": {"cpu": cpu_model(), "logical_cpus": os.cpu_count()}}
 
 
-def cpu_oracle_rates(synth, pan, ms, wavelet):
+def cpu_oracle_rates(synth, pan, ms, wavelet, torch=None):
     """Further FP64-oracle rates beside the baseline figure (same oracle, as it
-    stands, on the host cores): the Haar 512x512 scene (one thread); the
+    stands, on the host cores): the Haar 512x512 scene (one thread); a
+    row-strip sample of the D4 8192x8192 3-band scene (one thread); the
     baseline's sample of the primary scene with the other wavelet (one
     thread); and the baseline's sample on all host cores (at most 16, the host
     share of one GPU): its 8 strips cut into as many row strips as threads,
@@ -250,6 +251,25 @@ def cpu_oracle_rates(synth, pan, ms, wavelet):
     p5, m5 = wl.make()
     r, n, t = rate(lambda: oracle.fuse("haar", p5, m5), wl.B * wl.H * wl.W, 1.0)
     out[wl.name] = {"Mpix/s": r, "threads": 1, "sample": "whole scene, %d passes, %.2f s" % (n, t)}
+    # D4 8192 x 8192, 3 bands: the same kind of row-strip sample as the baseline's
+    import numpy as np
+
+    wl = synth.d4_8192()
+    if torch is not None:  # generated on the GPU (numpy takes about a minute here), timed on the host
+        pd, md = wl.make(device="cuda")
+        p8, m8 = pd.cpu().numpy().astype(np.float64), md.cpu().numpy().astype(np.float64)
+        del pd, md
+        torch.cuda.empty_cache()
+    else:
+        p8, m8 = wl.make()
+        p8, m8 = p8.astype(np.float64), m8.astype(np.float64)
+    strips8 = _strip_rows(wl.H, 8, 248)
+    px8 = wl.B * wl.W * sum(b - a for a, b in strips8)
+    r, n, t = rate(lambda: [oracle.fuse_rows(wl.wavelet, p8, m8, a, b) for a, b in strips8], px8, 2.0)
+    out[wl.name + "_sample"] = {"Mpix/s": r, "threads": 1,
+                                "sample": "8 strips of 248 rows (1984 of %d rows, all columns and %d bands), "
+                                          "%d passes, %.2f s" % (wl.H, wl.B, n, t)}
+    del p8, m8
     H, W = pan.shape
     B = ms.shape[0]
     strips = _strip_rows(H, 8, 248)
@@ -666,7 +686,7 @@ def main():
         result["cpu_baseline"] = cpu_baseline(pan_h, ms_h, wl.wavelet)
         log("cpu baseline", result["cpu_baseline"])
         if args.mode == "full":
-            result["cpu_oracle_rates"] = cpu_oracle_rates(synth, pan_h, ms_h, wl.wavelet)
+            result["cpu_oracle_rates"] = cpu_oracle_rates(synth, pan_h, ms_h, wl.wavelet, torch)
             log("cpu oracle rates", result["cpu_oracle_rates"])
     print(json.dumps(result), flush=True)
 
