@@ -359,6 +359,9 @@ def extras(torch, api, synth, steps, warmup, primary_call, only=None):
         gbs = algo_bytes(wl.H, wl.W, wl.B) / (ms_t * 1e-3) / 1e9
         out[wl.name] = {"Mpix/s": wl.B * wl.H * wl.W / ms_t / 1e3, "ms": ms_t, "GB/s": gbs, "frac": gbs / HBM_PEAK_GBS,
                         "per_launch": launch_stats(torch, call, max(10, steps // 2))}
+        flush = torch.ones(1 << 27, device=dev)  # 512 MiB: inputs evicted before each launch
+        out[wl.name]["per_launch_cache_flushed"] = launch_stats(torch, call, max(10, steps // 2), flush)
+        del flush
         log(wl.name, out[wl.name])
         del pan, ms, o, call
         torch.cuda.empty_cache()
