@@ -171,16 +171,25 @@ typedef struct {
 enum { DWT_FUSE_GRAPH = 1 /* capture into / replay from a cached hipGraph */ };
 
 /* Fuse n independent scenes of any sizes, band counts and wavelets in ONE
- * persistent kernel launch whose workgroups take (scene, tile) work units
- * from a device queue.  `items` is a HOST array of n descriptors (read
- * during the call only); the pointers inside are device pointers.  Every
- * item is validated as in dwt_fuse_run (first failure returned, nothing
- * launched); outputs must not overlap any item's inputs or each other.
- * With DWT_FUSE_GRAPH the launch is captured once per batch signature
- * (sizes, bands, wavelets, pitches) and replayed afterwards; scene pointers
- * live in a device table refreshed before each replay, so new tensors of
- * the same signature replay safely.  n == 0 is a no-op.  The context grows
- * its descriptor tables on first use of a larger batch (DWT_FUSE_E_NOMEM on
+ * kernel launch.  The launch is either a flat grid, one workgroup per
+ * (scene, tile) work item (LDS-staged D4 tiles, one-shot Haar wavefronts),
+ * or a persistent kernel whose workgroups take work units from per-XCD
+ * device queues; with tuning on, the form (grid or queue, unit order, rows
+ * per wavefront, bands staged at once) is timed on the batch itself and
+ * kept per batch signature, else the flat grid with 2-row staged tiles
+ * runs.  The environment variable DWT_FUSE_FORCE_BATCH = "mode,order,bg,
+ * staged,kr" read at dwt_fuse_create fixes the form (mode 3 = flat grid;
+ * staged 2 = each D4 scene with its own per-image tuned rows per
+ * wavefront).  `items` is a HOST array of n descriptors (read during the
+ * call only); the pointers inside are device pointers.  Every item is
+ * validated as in dwt_fuse_run (first failure returned, nothing launched);
+ * outputs must not overlap any item's inputs or each other.  Results are
+ * bit-identical to one dwt_fuse_run call per scene, in every form.  With
+ * DWT_FUSE_GRAPH the launch is captured once per batch signature (sizes,
+ * bands, wavelets, pitches) and replayed afterwards; scene pointers live in
+ * a device table refreshed before each replay, so new tensors of the same
+ * signature replay safely.  n == 0 is a no-op.  The context grows its
+ * descriptor tables on first use of a larger batch (DWT_FUSE_E_NOMEM on
  * failure). */
 dwt_fuse_status dwt_fuse_run_batched(dwt_fuse_ctx *ctx, const dwt_fuse_item *items,
                                      int64_t n, uint32_t flags);

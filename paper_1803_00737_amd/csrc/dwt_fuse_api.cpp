@@ -563,7 +563,8 @@ struct BatchChoice {
     int mode = 3;
     int order = 3;
     int bg = 2;
-    int staged = 1;  // flat: D4 scenes as LDS-staged tiles (else one-shot single-row wavefronts)
+    int staged = 1;  // flat: D4 scenes as LDS-staged tiles of kr rows per wavefront (1), one-shot single-row
+                     // wavefronts (0), or staged with each scene's own (per-image tuned) rows per wavefront (2)
     int kr = 2;      // flat: coefficient rows per wavefront of a staged tile (1 or 2; 4 wavefronts)
 };
 
@@ -577,6 +578,8 @@ struct dwt_fuse_ctx {
     // tiling
     bool tuning = false;
     Forced forced;
+    bool force_batch = false;  // DWT_FUSE_FORCE_BATCH: every batch takes forced_batch
+    BatchChoice forced_batch;
     std::map<std::string, Tile> table;
     std::map<std::string, BatchChoice> batch_modes;  // tuned form per batch signature
     // backward workspace
@@ -982,6 +985,7 @@ dwt_fuse_status plan_batch(dwt_fuse_ctx *ctx, const dwt_fuse_item *items, int64_
     pl->flat_order = ctx->forced.order >= 0 ? ctx->forced.order : ch.order;
     pl->flat_bg = ch.bg;
     pl->flat_kr = ch.kr == 1 ? 1 : 2;
+    int max_kr = 0;  // per-scene shapes: the largest staged rows per wavefront (sizes the launch's LDS)
     pl->staged_bands = 0;
     pl->sig.clear();
     pl->sig.reserve((size_t)n * 48);
@@ -1000,11 +1004,18 @@ dwt_fuse_status plan_batch(dwt_fuse_ctx *ctx, const dwt_fuse_item *items, int64_
             // wavefronts win per image: the launch reserves the staged
             // tiles' LDS for every workgroup, and one-shot items at that
             // occupancy measured slower than staged ones.
-            if (ch.staged && staged_allowed(a.wavelet, path, 2)) {
+            // Per-scene shapes: every D4 scene staged, with the rows per
+            // wavefront of its per-image tile (tuned for its size class when
+            // tuning is on): 1 where that tile is staged with 1 row, else 2.
+            int kr = pl->flat_kr;
+            const bool stage = ch.staged >= 1 && staged_allowed(a.wavelet, path, 2);
+            if (ch.staged == 2 && stage) kr = tile_for_run(ctx, a, path, true).mode == 3 ? 1 : 2;
+            if (stage) {
                 t.nc = 2;
-                t.mode = 2 + pl->flat_kr;  // staged, 1 or 2 rows per wavefront, 4 wavefronts
-                t.seg_rows = pl->flat_kr;
+                t.mode = 2 + kr;  // staged, 1 or 2 rows per wavefront, 4 wavefronts
+                t.seg_rows = kr;
                 pl->staged_bands = std::max<int>(pl->staged_bands, (int)a.B);
+                max_kr = std::max(max_kr, kr);
             } else {
                 t.nc = path_nc(path);
                 t.mode = 1;
@@ -1041,6 +1052,7 @@ dwt_fuse_status plan_batch(dwt_fuse_ctx *ctx, const dwt_fuse_item *items, int64_
     }
     pl->total = (int)total;
     if (mode == kFlatBatch) {
+        if (ch.staged == 2 && max_kr > 0) pl->flat_kr = max_kr;  // LDS for the largest staged tile
         pl->grid = (int)total;
         char gb[64];
         std::snprintf(gb, sizeof(gb), "#flat#%d#o%d#g%d#s%d#k%d", pl->staged_bands, pl->flat_order, pl->flat_bg,
@@ -1194,6 +1206,15 @@ dwt_fuse_status dwt_fuse_create(dwt_fuse_ctx **ctx, int device, void *hip_stream
         if (const char *f = std::getenv("DWT_FUSE_FORCE_OVERLAP")) {
             const int o = std::atoi(f);
             if (o >= 0 && o <= 1) c->forced.ovl = o;
+        }
+        if (const char *f = std::getenv("DWT_FUSE_FORCE_BATCH")) {  // "mode,order,bg,staged,kr"
+            BatchChoice b;
+            if (std::sscanf(f, "%d,%d,%d,%d,%d", &b.mode, &b.order, &b.bg, &b.staged, &b.kr) == 5 && b.mode >= 0 &&
+                b.mode <= kFlatBatch && b.order >= 0 && b.order <= 3 && b.bg >= 0 && b.bg <= 8 && b.staged >= 0 &&
+                b.staged <= 2 && (b.kr == 1 || b.kr == 2)) {
+                c->force_batch = true;
+                c->forced_batch = b;
+            }
         }
         if (const char *f = std::getenv("DWT_FUSE_FORCE_ORDER")) {
             const int o = std::atoi(f);
@@ -1757,7 +1778,9 @@ dwt_fuse_status dwt_fuse_run_batched(dwt_fuse_ctx *ctx, const dwt_fuse_item *ite
 
         BatchPlan plan;
         BatchChoice ch;
-        if (ctx->forced.variant == 1) {
+        if (ctx->force_batch) {
+            ch = ctx->forced_batch;
+        } else if (ctx->forced.variant == 1) {
             ch.mode = 0;
         } else if (ctx->forced.variant == 2) {
             ch.mode = std::min(2, std::max(1, ctx->forced.seg_rows > 0 ? ctx->forced.seg_rows : 2));
@@ -1773,7 +1796,12 @@ dwt_fuse_status dwt_fuse_run_batched(dwt_fuse_ctx *ctx, const dwt_fuse_item *ite
             // batch: the flat grid in dispatch order or per-XCD runs, with
             // its staged tiles holding every band, 3 or 2 bands at once (less
             // LDS per workgroup: more of the batch's one-shot Haar items
-            // resident per CU), and the persistent queue kernels.
+            // resident per CU), with 1 or 2 rows per wavefront for every
+            // scene or each scene's own (per-image tuned) rows, and the
+            // persistent queue kernels.  (Taking each D4 scene's whole
+            // per-image shape, one-shot wavefronts where those won alone,
+            // measured 1.43 against 1.09 ms on the 96-scene batch: the launch
+            // reserves the staged tiles' LDS for every workgroup.)
             if ((st = plan_batch(ctx, items, n, BatchChoice{}, &plan))) return st;
             auto it = ctx->batch_modes.find(plan.sig);
             if (it != ctx->batch_modes.end()) {
@@ -1784,6 +1812,7 @@ dwt_fuse_status dwt_fuse_run_batched(dwt_fuse_ctx *ctx, const dwt_fuse_item *ite
                     for (int bg : {2, 0, 3, 1}) cands.push_back(BatchChoice{kFlatBatch, 3, bg, 1, kr});
                 cands.push_back(BatchChoice{kFlatBatch, 1, 2, 1, 2});
                 cands.push_back(BatchChoice{kFlatBatch, 3, 0, 0, 2});
+                cands.push_back(BatchChoice{kFlatBatch, 3, 2, 2, 2});  // per-scene rows per wavefront
                 for (int m : {0, 1, 2}) cands.push_back(BatchChoice{m, 1, 0, 1, 2});
                 float best = 1e30f;
                 for (const BatchChoice &c : cands) {

@@ -82,6 +82,34 @@ def test_batch_variants_match_per_image(dev, fz, variant, graph):
         assert torch.equal(o2, ref)
 
 
+@pytest.mark.parametrize("bands_at_once,tuning", [(2, True), (0, False)])
+def test_flat_batch_per_scene_shapes(dev, fz, monkeypatch, bands_at_once, tuning):
+    """The flat form with per-scene shapes (each D4 scene staged with 1 or 2
+    rows per wavefront, or as one-shot wavefronts, as its own per-image tile
+    says; with tuning on, the scenes' size classes are tuned first): every
+    output equals its per-image call bit for bit."""
+    monkeypatch.setenv("DWT_FUSE_FORCE_BATCH", "3,3,%d,2,2" % bands_at_once)
+    rng = np.random.default_rng(910 + bands_at_once)
+    scenes = []
+    for H, W, B, w, pad in [(64, 1288, 3, "d4", 0), (34, 1030, 6, "d4", 0), (66, 262, 5, "d4", 2),
+                            (130, 516, 5, "haar", 0), (18, 4070, 2, "d4", 4), (2, 8, 1, "d4", 0),
+                            (1026, 2050, 3, "d4", 0), (40, 132, 4, "d4", 1)]:
+        pan, ms = int_scene(rng, H, W, B)
+        if pad:
+            scenes.append(dict(pan=strided_view(pan, dev, pad, 0), ms=strided_view(ms, dev, pad, 0), wavelet=w))
+        else:
+            scenes.append(dict(pan=to_dev(pan, dev), ms=to_dev(ms, dev), wavelet=w))
+    ctx = fz.Context(dev.index or 0)  # created after the variable is set
+    ctx.bind_stream()
+    ctx.set_tuning(tuning)
+    arr, outs, keep = fz.make_items(scenes)
+    say("flat batch per-scene shapes", bands_at_once, tuning)
+    ctx.check(ctx.lib.dwt_fuse_run_batched(ctx.handle, arr, len(scenes), 0), "dwt_fuse_run_batched")
+    torch.cuda.synchronize()
+    for s, o in zip(scenes, outs):
+        assert torch.equal(o, fz.fuse(s["pan"], s["ms"], s["wavelet"]))
+
+
 @pytest.mark.parametrize("rows,bands_at_once,order", [(2, 0, 3), (2, 2, 3), (1, 1, 3), (1, 3, 1), (2, 2, 0)])
 def test_flat_batch_forms_match_per_image(dev, fz, rows, bands_at_once, order):
     """The flat grid with staged tiles of 1 or 2 rows per wavefront, staging
