@@ -689,16 +689,35 @@ __device__ __forceinline__ void d4_staged_tile(const FuseParams &p, const Filter
 // into 8 contiguous chunks, chunk x for XCD x (workgroups are dealt
 // round-robin to the 8 XCDs); XCD x walks its chunk row band after row band,
 // so horizontally and vertically adjacent tiles share an L2 and the GPU still
-// advances down the image together.  The grid is 8 * cmax * nseg workgroups
-// (cmax = the largest chunk); those past their XCD's chunk leave at once.
+// advances down the image together.  With nstrips = 8q + r, the r chunks of
+// q + 1 strips go in row band t to XCDs t, t+1, .., t+r-1 (mod 8), so over
+// any 8 consecutive row bands every XCD takes 8q + r tiles (fixed chunks would
+// leave the XCDs holding the larger ones up to (q+1)/(q+r/8) times as much
+// work).  The grid is 8 * slab_slots workgroups; those past their XCD's tiles
+// leave at once.
+__host__ __device__ inline int64_t slab_slots(int nstrips, int nseg) {
+    return (int64_t)(nstrips >> 3) * nseg + (int64_t)(nstrips & 7) * ((nseg + 7) / 8);
+}
+
 __device__ __forceinline__ bool slab_unit(int b, int nstrips, int nseg, int &unit) {
     const int x = b & 7, i = b >> 3;
     const int q = nstrips >> 3, r = nstrips & 7;
-    const int c = q + (x < r ? 1 : 0);
-    if (c == 0 || i >= c * nseg) return false;
-    const int trow = i / c;
-    unit = trow * nstrips + x * q + min(x, r) + (i - trow * c);  // row-band-major numbering
-    return true;
+    const int per = 8 * q + r;  // tiles of one XCD in 8 consecutive row bands
+    const int P = i / per;
+    int j = i - P * per;
+    for (int k = 0; k < 8; ++k) {
+        const int t = 8 * P + k;
+        if (t >= nseg) return false;
+        const int c = q + (((x - t) & 7) < r ? 1 : 0);  // XCD x's chunk in row band t
+        if (j < c) {
+            int below = 0;  // XCDs below x holding a larger chunk in row band t
+            for (int m = 0; m < r; ++m) below += ((t + m) & 7) < x ? 1 : 0;
+            unit = t * nstrips + x * q + below + j;  // row-band-major numbering
+            return true;
+        }
+        j -= c;
+    }
+    return false;
 }
 
 template <int KR, int LAY>
@@ -723,7 +742,7 @@ __global__ __launch_bounds__(256) void d4_staged_kernel(FuseParams p, Filters f,
 
 template <int KR>
 static void launch_staged(const FuseParams &p, const Filters &f, int wpb, size_t lds, int bgm, hipStream_t s) {
-    const int grid = (p.order & 4) ? 8 * ((p.nstrips + 7) / 8) * p.nseg : p.units;
+    const int grid = (p.order & 4) ? (int)(8 * slab_slots(p.nstrips, p.nseg)) : p.units;
     switch (p.path) {
         case PATH_V4:
             hipLaunchKernelGGL((d4_staged_kernel<KR, 0>), dim3(grid), dim3(64 * wpb), lds, s, p, f, bgm);
@@ -814,7 +833,7 @@ hipError_t launch_fuse(const FuseParams &p, const Filters &f, int wpb, hipStream
             return hipErrorInvalidValue;
         const int bgm = p.bg > 0 && p.bg < staged_bg_max(p.seg_rows) ? p.bg : staged_bg_max(p.seg_rows);
         if (bgm < 1 || p.bsplit < 0) return hipErrorInvalidValue;
-        if ((p.order & 4) && (p.bsplit > 0 || (p.order & 1) == 0 || (int64_t)8 * ((p.nstrips + 7) / 8) * p.nseg > INT32_MAX))
+        if ((p.order & 4) && (p.bsplit > 0 || (p.order & 1) == 0 || 8 * slab_slots(p.nstrips, p.nseg) > INT32_MAX))
             return hipErrorInvalidValue;  // slabs: whole tiles, row-band-major numbering
         const int per_unit = p.bsplit > 0 && p.bsplit < p.B ? p.bsplit : p.B;  // bands one unit handles
         const size_t lds = sizeof(float) * staged_lds_floats(p.seg_rows, per_unit < bgm ? per_unit : bgm);

@@ -206,19 +206,22 @@ def test_tile_shapes_give_identical_results(dev, fz, wavelet, H, W):
 
 
 @pytest.mark.parametrize("wavelet", ["haar", "d4"])
-@pytest.mark.parametrize("H,W", [(250, 1288), (66, 1030), (18, 8), (130, 2824), (34, 4104)])
+@pytest.mark.parametrize("H,W", [(250, 1288), (66, 1030), (18, 8), (130, 2824), (34, 4104), (300, 3320)])
 def test_unit_orders_give_identical_results(dev, fz, oracle, wavelet, H, W):
     """Every unit order (column strips or row bands, per-XCD runs or dispatch
-    order, XCD slabs for the LDS-staged tiles: 1, 5, 6, 12 and 17 strips of
-    128 coefficient columns, so some XCDs' chunks are empty or shorter) of
+    order, XCD slabs for the LDS-staged tiles: 1, 5, 6, 12, 14 and 18 overlapped
+    strips of 128 coefficient columns over 2-38 row bands, so some XCDs' chunks are
+    empty or shorter and rotate from band to band) of
     every variant gives the same output bit for bit, and the oracle's; 8-bit
-    output too."""
+    output too.  Outputs start as NaN (8-bit: alternately 0 and 255), so a
+    unit that an order skips shows."""
     rng = np.random.default_rng(17)
     pan, ms = int_scene(rng, H, W, 3)
     p, m = to_dev(pan, dev), to_dev(ms, dev)
     ref = oracle_out(oracle, wavelet, pan, ms)
     ctx = fz.context(dev)
     base = None
+    fill8 = 0
     try:
         for order in (0, 1, 2, 3, 4, 5, 6, 7):
             ctx.force_order(order)
@@ -226,8 +229,11 @@ def test_unit_orders_give_identical_results(dev, fz, oracle, wavelet, H, W):
                                       (1, 4, 2, 3), (4, 2, 2, 3)]:
                 say(wavelet, "order", order, H, W, "tile", seg, wpb, nc, var)
                 ctx.force_tile(seg, wpb, nc, var)
-                out = fz.fuse(p, m, wavelet).cpu().numpy()
-                out8 = fz.fuse(p.to(torch.uint8), m.to(torch.uint8), wavelet, out_dtype=torch.uint8).cpu().numpy()
+                o = torch.full((3, H, W), float("nan"), device=dev)
+                o8 = torch.full((3, H, W), fill8, dtype=torch.uint8, device=dev)
+                fill8 = 255 - fill8
+                out = fz.fuse(p, m, wavelet, out=o).cpu().numpy()
+                out8 = fz.fuse(p.to(torch.uint8), m.to(torch.uint8), wavelet, out=o8).cpu().numpy()
                 if base is None:
                     base = (out, out8)
                     if wavelet == "haar":
