@@ -126,6 +126,9 @@ def test_flat_batch_forms_match_per_image(dev, fz, rows, bands_at_once, order):
             scenes.append(dict(pan=strided_view(pan, dev, pad, 0), ms=strided_view(ms, dev, pad, 0), wavelet=w))
         else:
             scenes.append(dict(pan=to_dev(pan, dev), ms=to_dev(ms, dev), wavelet=w))
+    for s in scenes:  # outputs start as NaN, so an item that a form skips shows
+        B, H, W = s["ms"].shape[0], s["pan"].shape[0], s["pan"].shape[1]
+        s["out"] = torch.full((B, H, W), float("nan"), device=dev)
     ctx = fz.context(dev)
     say("flat batch form", rows, bands_at_once, order)
     try:
