@@ -252,3 +252,40 @@ def test_full_size_landsat_u8(dev, fz, oracle, wavelet):
     torch.cuda.empty_cache()
     ref = oracle.fuse_points(wavelet, pan, ms, None, b, y, x)
     check_u8(oracle, got, ref, exact=(wavelet == "haar"))
+
+
+@pytest.mark.parametrize("wavelet", ["haar", "d4"])
+def test_u8_beyond_2_31_bytes(dev, fz, oracle, wavelet):
+    """8-bit in and out, 8192 x 8192 with 33 bands: the output holds 2.2e9
+    bytes, more than a 32-bit index can address, so every band offset of the
+    8-bit kernels must be formed in 64-bit arithmetic.  Sampled pixels of the
+    first and last bands against the single-pixel oracle, in the tuned launch
+    shape."""
+    H = W = 8192
+    B = 33
+    rng = np.random.default_rng(34)
+    say("u8 beyond 2^31", wavelet, "generate")
+    p8 = torch.randint(0, 256, (H, W), device=dev, dtype=torch.uint8)
+    ms1 = torch.randint(0, 256, (1, H // 2, W // 2), device=dev, dtype=torch.uint8)
+    m8 = ms1.expand(B, H // 2, W // 2).contiguous()
+    m8[B - 1] = torch.flip(ms1[0], dims=[1])  # a last band that differs from the others
+    ctx = fz.context(dev)
+    ctx.set_tuning(True)
+    try:
+        say("u8 beyond 2^31", wavelet, "fuse")
+        q = fz.fuse(p8, m8, wavelet, out_dtype=torch.uint8)
+    finally:
+        ctx.set_tuning(False)
+    torch.cuda.synchronize()
+    assert q.numel() > 2 ** 31
+    pts = [(b, int(y), int(x)) for b in (0, 1, B - 2, B - 1) for y, x in
+           zip(rng.integers(0, H, 24), rng.integers(0, W, 24))] + [(B - 1, H - 1, W - 1), (B - 1, 0, 0)]
+    b, y, x = map(np.array, zip(*pts))
+    got = q[torch.from_numpy(b).to(dev), torch.from_numpy(y).to(dev), torch.from_numpy(x).to(dev)].cpu().numpy()
+    pan = p8.cpu().numpy().astype(np.float64)
+    ms_small = np.stack([m8[k].cpu().numpy() for k in (0, B - 1)]).astype(np.float64)
+    del q, m8, p8
+    torch.cuda.empty_cache()
+    bi = np.where(b == B - 1, 1, 0)
+    ref = oracle.fuse_points(wavelet, pan, ms_small, None, bi, y, x)
+    check_u8(oracle, got, ref, exact=(wavelet == "haar"))

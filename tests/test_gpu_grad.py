@@ -670,3 +670,46 @@ def test_differentiation_workload_batched(dev, fz, oracle):
         if i == 0:
             check_grads(oracle, "d4", b["pan"].cpu().numpy(), b["grad_out"].cpu().numpy(), np.ones(4, np.float32),
                         [t.cpu().numpy() for t in g])
+
+
+def test_adjoint_beyond_2_31_elements(dev, fz):
+    """D4 adjoint of 8192 x 8192 with 33 bands: the upstream gradient holds
+    2.2e9 elements (8.9 GB), more than a 32-bit index can address, so band
+    offsets must be formed in 64-bit arithmetic (the bands run in groups
+    that accumulate into grad_pan).  Checked through the identities of
+    _adjoint_identities, summed band by band in FP64: <F, y> = <PAN,
+    grad_pan> + <MS, grad_ms>, and grad_gain_b = <y_b, PAN - P PAN>."""
+    H = W = 8192
+    B = 33
+    say("adjoint beyond 2^31", "generate")
+    g = torch.Generator(device=dev).manual_seed(33)
+    pan = torch.randint(0, 256, (H, W), device=dev, generator=g).float()
+    ms = torch.randint(0, 256, (B, H // 2, W // 2), device=dev, generator=g).float()
+    y = torch.randn((B, H, W), device=dev, generator=g)
+    assert y.numel() > 2 ** 31
+    gain = torch.linspace(0.5, 1.5, B, device=dev)
+    say("adjoint beyond 2^31", "backward")
+    gp, gm, gg = fz.fuse_backward(pan, y, "d4", gain)
+    say("adjoint beyond 2^31", "forward and sums")
+    out = fz.fuse(pan, ms, "d4", gain)
+    lhs = scale = 0.0
+    rhs = float((pan.double() * gp.double()).sum())
+    rscale = float((pan.double() * gp.double()).abs().sum())
+    for b in range(B):
+        prod = out[b].double() * y[b].double()
+        lhs += float(prod.sum())
+        scale += float(prod.abs().sum())
+        mprod = ms[b].double() * gm[b].double()
+        rhs += float(mprod.sum())
+        rscale += float(mprod.abs().sum())
+    assert abs(lhs - rhs) <= 1e-8 * max(scale, rscale), (lhs, rhs, scale)
+    del out
+    one, zero = torch.ones(1, device=dev), torch.zeros(1, device=dev)
+    d = (fz.fuse(pan, ms[:1], "d4", one) - fz.fuse(pan, ms[:1], "d4", zero))[0].double()  # PAN - P PAN
+    for b in range(B):
+        prod = y[b].double() * d
+        ref = float(prod.sum())
+        bound = 1e-7 * float(prod.abs().sum()) + 1e-3
+        assert abs(float(gg[b]) - ref) <= bound, (b, float(gg[b]), ref, bound)
+    del y, gp, gm, d
+    torch.cuda.empty_cache()
