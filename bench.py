@@ -165,7 +165,7 @@ def force_primary_tile(ctx, wl, tile):
                                  math.ceil(math.log2(wl.W)), min(wl.B, 8))
     with tempfile.TemporaryDirectory() as d:
         path = os.path.join(d, "table.txt")
-        ctx.tune_save(path)  # for the header line: this build and device
+        ctx.tune_save(path)  # for the header line: the library build id and the device
         with open(path) as f:
             header = f.read().splitlines()[0]
         with open(path, "w") as f:
