@@ -1022,7 +1022,7 @@ template <int KR, bool A16>
 __global__ __launch_bounds__(256) void d4_adjoint_staged_kernel(AdjParams p, Filters f) {
     extern __shared__ float lds[];
     const int wpb = blockDim.x >> 6;
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int T = wpb * KR;
     const int unit = block_unit(p.order);
     if (unit >= p.units) return;  // whole workgroup

@@ -519,7 +519,10 @@ template <int KR, int LAY>
 __device__ __forceinline__ void d4_staged_tile(const FuseParams &p, const Filters &f, int bg_max, int unit,
                                                float *lds, int wpb, int b_lo, int b_hi) {
     static_assert(LAY == 0 || LAY == 2 || LAY == 3, "row layouts: 16-, 4- or 8-byte rows");
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // The wavefront index is the same on all its lanes; saying so keeps the
+    // tile's row bookkeeping on the scalar unit (about a quarter fewer vector
+    // instructions in the kernel).
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int T = wpb * KR;
     int strip, trow;
     unit_coords(unit, p.nstrips, p.nseg, p.order, strip, trow);
