@@ -148,6 +148,14 @@ struct CodecCols {
         }
     }
     __device__ __forceinline__ bool active() const { return s0 < W2; }
+    // Byte offsets of the lane's 8-bit accesses within a row, as opaque 32-bit
+    // values: added to a wavefront-uniform row address they make loads and
+    // stores of the scalar-base, vector-offset form (no 64-bit vector address
+    // arithmetic per access).
+    __device__ __forceinline__ static unsigned opaque(unsigned v) {
+        asm volatile("" : "+v"(v));
+        return v;
+    }
 
     __device__ __forceinline__ void load_row(const TI *row, f2 (&x)[NC + 2]) const {
         x[0] = ld_pair<TI, AL>(row + 2 * pc[0]);
@@ -164,19 +172,19 @@ struct CodecCols {
     __device__ __forceinline__ void load_row_raw(const TI *row, uint32_t (&w)[NC / 2], uint32_t &hl,
                                                  uint32_t &hr) const {
         if constexpr (AL) {
-            hl = *reinterpret_cast<const uint16_t *>(row + 2 * pc[0]);
-            hr = *reinterpret_cast<const uint16_t *>(row + 2 * pc[NC + 1]);
+            hl = *reinterpret_cast<const uint16_t *>(row + opaque(2u * pc[0]));
+            hr = *reinterpret_cast<const uint16_t *>(row + opaque(2u * pc[NC + 1]));
         } else {
             hl = (uint32_t)row[2 * pc[0]] | ((uint32_t)row[2 * pc[0] + 1] << 8);
             hr = (uint32_t)row[2 * pc[NC + 1]] | ((uint32_t)row[2 * pc[NC + 1] + 1] << 8);
         }
         if (AL && full) {
             if constexpr (NC == 4) {
-                const u2 v = *reinterpret_cast<const u2 *>(row + 2 * s0);
+                const u2 v = *reinterpret_cast<const u2 *>(row + opaque(2u * s0));
                 w[0] = v.x;
                 w[1] = v.y;
             } else {
-                const u4 v = *reinterpret_cast<const u4 *>(row + 2 * s0);
+                const u4 v = *reinterpret_cast<const u4 *>(row + opaque(2u * s0));
                 w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
             }
         } else {
@@ -190,12 +198,12 @@ struct CodecCols {
     }
     // 8-bit MS row: halo coefficient pc[0] in w[0], own NC coefficients packed in w[1..].
     __device__ __forceinline__ void load_ms_raw(const TI *mrow, uint32_t (&w)[1 + NC / 4]) const {
-        w[0] = mrow[pc[0]];
+        w[0] = mrow[opaque(pc[0])];
         if (AL && full) {
             if constexpr (NC == 4) {
-                w[1] = *reinterpret_cast<const uint32_t *>(mrow + s0);
+                w[1] = *reinterpret_cast<const uint32_t *>(mrow + opaque(s0));
             } else {
-                const u2 v = *reinterpret_cast<const u2 *>(mrow + s0);
+                const u2 v = *reinterpret_cast<const u2 *>(mrow + opaque(s0));
                 w[1] = v.x;
                 w[2] = v.y;
             }
@@ -259,12 +267,14 @@ __device__ __forceinline__ void store_out(TO *orow, int s0, int W2, bool full, c
             uint32_t w[NC / 2];
 #pragma unroll
             for (int k = 0; k < NC / 2; ++k) w[k] = pack4(q[2 * k].x, q[2 * k].y, q[2 * k + 1].x, q[2 * k + 1].y);
+            unsigned off = 2u * s0;  // opaque 32-bit offset: scalar-base store (see CodecCols::opaque)
+            asm volatile("" : "+v"(off));
             if constexpr (NC == 2) {
-                __builtin_nontemporal_store(w[0], reinterpret_cast<uint32_t *>(orow + 2 * s0));
+                __builtin_nontemporal_store(w[0], reinterpret_cast<uint32_t *>(orow + off));
             } else if constexpr (NC == 4) {
-                __builtin_nontemporal_store(u2{w[0], w[1]}, reinterpret_cast<u2 *>(orow + 2 * s0));
+                __builtin_nontemporal_store(u2{w[0], w[1]}, reinterpret_cast<u2 *>(orow + off));
             } else {
-                __builtin_nontemporal_store(u4{w[0], w[1], w[2], w[3]}, reinterpret_cast<u4 *>(orow + 2 * s0));
+                __builtin_nontemporal_store(u4{w[0], w[1], w[2], w[3]}, reinterpret_cast<u4 *>(orow + off));
             }
         } else {
 #pragma unroll
