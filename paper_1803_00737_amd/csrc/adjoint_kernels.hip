@@ -10,13 +10,14 @@
 //     dLoss/d(m_b)   = S^T y_b            (D4: L y_b;  Haar: 2x2 block sum)
 //     dLoss/d(PAN)   = Y - P Y,  Y = sum_b g_b y_b
 //     dLoss/d(g_b)   = < y_b, PAN - P PAN >.
-// The kernels walk the same work units as the forward kernels (a strip of
-// 64*NC coefficient columns per wavefront, seg_rows coefficient rows) with
-// rolling rows in registers; the per-band gain products of each coefficient
-// row of a strip are summed across the wavefront and written to their own
-// slot (gain_row), and gain_reduce_kernel sums the slots in a fixed order, so
-// grad_gain has the same bits whatever the unit length, order or variant
-// with two coefficient columns per lane.  grad_pan and grad_ms are written
+// The kernels walk the same work units as the forward kernels: rolling
+// wavefronts (a strip of 64*NC coefficient columns, seg_rows coefficient rows,
+// rows rolling in registers), one-shot wavefront tiles, and LDS-staged
+// workgroup tiles.  The per-band gain products of each coefficient row of a
+// strip are summed across the wavefront and written to their own slot
+// (gain_row), and gain_chunk_kernel / gain_total_kernel add the slots in FP64
+// in a fixed order, so grad_gain has the same bits whatever the unit length,
+// order or variant with two coefficient columns per lane.  grad_pan and grad_ms are written
 // with non-temporal stores (they are not read again by the kernel, except
 // grad_pan by later band groups, and keeping them out of the caches leaves
 // room for the upstream-gradient halo rows).

@@ -17,8 +17,12 @@
 // 8-bit PAN, 16 bytes of float PAN) and a run of coefficient rows of every
 // band.  One-shot tiles (KR = 1, 2 rows) issue all their PAN rows (with the
 // D4 halo rows and columns, Eq. 5-6 wrap) and the first band's MS rows before
-// computing, and load band b+1 while band b is computed and stored; D4 also
-// has rolling units (KR = 0: seg_rows rows, each PAN row filtered once).
+// computing; the float-output tiles load band b+1's MS rows while band b is
+// computed and stored, the 8-bit D4 tiles two bands ahead (three rotating
+// register sets), the 8-bit Haar tiles every band's rows (up to 8) up front.
+// D4 also has rolling units (KR = 0: seg_rows rows, each PAN row filtered
+// once) and an LDS-staged form (a workgroup converts its strip's PAN and MS
+// rows to float32 in LDS once).
 #include "fuse_internal.h"
 #include "fuse_math.h"
 

@@ -26,7 +26,9 @@ inline int path_nc(Path p) { return p == PATH_SCALAR ? 1 : 2; }
 
 // One scene as the kernels see it.  A work unit is one wavefront (64 lanes)
 // covering a strip of 64*NC coefficient columns and seg_rows coefficient
-// rows (2*seg_rows output rows) of every band.
+// rows (2*seg_rows output rows) of every band; for the LDS-staged D4 tiles
+// (mode >= 3) it is one workgroup covering 128 coefficient columns and
+// seg_rows = wavefronts x rows per wavefront coefficient rows.
 struct FuseParams {
     const float *pan;
     const float *ms;

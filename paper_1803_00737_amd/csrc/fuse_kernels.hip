@@ -23,23 +23,31 @@
 //     2^10, so this is exact in float32 (and with g = 1 equals the printed
 //     method bit for bit).
 //
-// Work decomposition: one wavefront handles a strip of 64*NC coefficient
-// columns (each lane NC columns = 2*NC output columns, 128-bit rows for
-// NC = 2) and a run of coefficient rows of every band.  Two variants:
-//   * rolling (KR = 0): the wavefront walks seg_rows coefficient rows,
-//     keeping two row-filtered PAN rows and one row of L PAN in registers,
-//     so each PAN row is read once per strip plus a 2-row halo per unit;
-//   * one-shot (KR = 1 or 2): the wavefront covers KR coefficient rows, issues
+// Work decomposition: a strip of coefficient columns by a run of coefficient
+// rows, every band.  Three variants:
+//   * rolling (KR = 0): one wavefront walks seg_rows coefficient rows of a
+//     strip of 64*NC columns (each lane NC columns = 2*NC output columns,
+//     128-bit rows for NC = 2), keeping two row-filtered PAN rows and one row
+//     of L PAN in registers, so each PAN row is read once per strip plus a
+//     2-row halo per unit;
+//   * one-shot (KR = 1 or 2): one wavefront covers KR coefficient rows, issues
 //     all its PAN rows (with the 2-row halos) and band 0's MS rows at once,
-//     and loads band b+1's MS rows while computing and storing band b.  Many
-//     short-lived wavefronts keep far more bytes in flight per CU; the halo
-//     rows are re-read from L2.
-// Both evaluate every output pixel with the same fixed fma chains, so they
+//     and loads band b+1's MS rows while computing and storing band b; the
+//     halo rows are re-read from L2;
+//   * LDS-staged D4 tiles (d4_staged_tile): a workgroup of wpb wavefronts
+//     copies the PAN rows of its wpb*KR coefficient rows (with the 2-row and
+//     2-column halos) and a band group's MS rows straight into LDS, then each
+//     wavefront computes its KR rows of every band from there, so the halos
+//     are shared instead of re-read.
+// All evaluate every output pixel with the same fixed fma chains, so they
 // agree bit for bit whatever the tiling.  The PAN-dependent part (L PAN and
 // the PAN pixels) is computed once and reused for all B bands.  Outputs go out
-// with non-temporal stores.  Workgroups are remapped so that each XCD (one
-// L2) takes a contiguous run of units (by default a band of rows across the
-// whole width), whose halo rows and columns then hit that L2.
+// with non-temporal stores.  Units are numbered down column strips or across
+// row bands and handed to workgroups in dispatch order (the whole GPU as one
+// front) or as one contiguous run per XCD; the LDS-staged tiles also have XCD
+// slabs (slab_unit).  Output rows that do not start on a 64-byte boundary are
+// covered by overlapped strips (strip_origin), so every stored run is 64-byte
+// aligned.
 #include "fuse_internal.h"
 #include "fuse_math.h"
 
